@@ -1,0 +1,101 @@
+"""Preconditioned conjugate gradients, plainly (oracle; tests and CPU baseline only).
+
+Alg. 2 of the paper is unpreconditioned CG on G mu = b with x0 given and the stopping rule
+||r|| <= eps ||r0||; the paper notes that preconditioning can be added (Section 3.2, remarks after
+Alg. 2).  This is that algorithm with a left preconditioner Minv inserted in the standard way
+(z = Minv r, rho = <r, z>, p = z + beta p), which reduces to Alg. 2 when Minv = I.
+
+Readings of Alg. 2 used here: the operator is Q + B^T C B and the right-hand side B^T C y (as in
+eq. (Axb)); the first search direction is the initial (preconditioned) residual; the stopping test
+uses the Euclidean norm of the unpreconditioned residual.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+from . import operator as op
+
+
+def block_jacobi(prob, G=None, kind: str = "block"):
+    """Preconditioner blocks taken from the assembled matrix G.
+
+    'block'  : per pixel p, the k x k block G[(i, p), (j, p)] (prior diagonal + mixing), inverted.
+    'jacobi' : 1 / diag(G).
+    'none'   : identity.
+    Returns a function r[k, n_pix] -> z[k, n_pix] and, for 'block', the [n_pix, k, k] inverses.
+    """
+    k, n_pix = prob.k, prob.n_pix
+    if kind == "none":
+        return (lambda r: np.array(r, dtype=np.float64, copy=True)), None
+    if G is None:
+        G = op.posterior_precision(prob)
+    G = sp.csr_matrix(G)
+    if kind == "jacobi":
+        d = G.diagonal().reshape(k, n_pix)
+        return (lambda r: np.asarray(r) / d), None
+    if kind != "block":
+        raise ValueError(kind)
+    blocks = np.zeros((n_pix, k, k))
+    pix = np.arange(n_pix)
+    for i in range(k):
+        for j in range(k):
+            blocks[:, i, j] = np.asarray(G[i * n_pix + pix, j * n_pix + pix]).ravel()
+    inv = np.linalg.inv(blocks)
+
+    def apply_inv(r):
+        rr = np.asarray(r, dtype=np.float64).reshape(k, n_pix).T[..., None]   # [n_pix, k, 1]
+        return (inv @ rr)[..., 0].T.copy()
+
+    return apply_inv, inv
+
+
+def pcg(prob, b=None, x0=None, tol=1e-12, max_iter=10000, precond="block", G=None,
+        record=False):
+    """Solve G x = b.  Returns dict(x, iters, relres_rec, relres_true, history[, iterates])."""
+    if G is None:
+        G = op.posterior_precision(prob)
+    if b is None:
+        b = op.rhs(prob)
+    k, n_pix = prob.k, prob.n_pix
+    Minv, _ = block_jacobi(prob, G, precond)
+    bv = np.asarray(b, dtype=np.float64).reshape(k, n_pix)
+    x = np.zeros((k, n_pix)) if x0 is None else np.array(x0, dtype=np.float64).reshape(k, n_pix)
+
+    def Gv(v):
+        return (G @ v.ravel()).reshape(k, n_pix)
+
+    r = bv - Gv(x)
+    z = Minv(r)
+    p = z.copy()
+    rho = float(np.vdot(r, z))
+    r0 = float(np.linalg.norm(r))
+    hist = [r0]
+    iterates = [x.copy()] if record else None
+    it = 0
+    rn = r0
+    while rn > tol * r0 and it < max_iter:
+        q = Gv(p)
+        pq = float(np.vdot(p, q))
+        if not pq > 0:
+            break
+        alpha = rho / pq
+        x = x + alpha * p
+        r = r - alpha * q
+        z = Minv(r)
+        rho_new = float(np.vdot(r, z))
+        beta = rho_new / rho
+        rho = rho_new
+        p = z + beta * p
+        it += 1
+        rn = float(np.linalg.norm(r))
+        hist.append(rn)
+        if record:
+            iterates.append(x.copy())
+    bn = float(np.linalg.norm(bv))
+    true = float(np.linalg.norm(bv - Gv(x)) / bn) if bn > 0 else 0.0
+    out = dict(x=x, iters=it, relres_rec=rn / r0 if r0 > 0 else 0.0, relres_true=true,
+               history=np.array(hist))
+    if record:
+        out["iterates"] = iterates
+    return out
