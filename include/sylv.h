@@ -1,0 +1,178 @@
+/*
+ * sylv.h -- C ABI of the MI355X (gfx950) solver for the posterior mean of the CMB
+ * source-separation model: matrix-free preconditioned conjugate gradients on
+ *
+ *     G(X) = sum_j Q_j X E_jj + sum_f D_f X a_f a_f^T  =  B_rhs,
+ *     Q_j  = tau_j (kappa_j^2 I - Lap)^T (kappa_j^2 I - Lap),   D_f = diag(W[f, :]),
+ *     B_rhs[j, p] = sum_f W[f, p] Y[f, p] A[f, j],
+ *
+ * i.e. the system (Q + B^T C B) mu = B^T C Y of Section 3, eq. (Axb), with the paper's prior
+ * phi_l D^2 generalised to the SPDE prior (kappa_j^2 - Lap)^2 (kappa_j = 0, tau_j = phi_l is the
+ * paper's case; Section 3 and App. C), its separable noise precision T (x) N generalised to
+ * per-map, per-pixel weights W[f, p], and Lap the 5-point Laplacian of a periodic grid (the
+ * paper's D on a grid whose pixels each have four edge neighbours).  The solver is Alg. 2
+ * (conjugate gradients) with a block-Jacobi preconditioner, run in float64 or with float32
+ * operator applies inside float64 iterative refinement.
+ *
+ * Conventions shared by every entry point:
+ *  - Every array argument is a DEVICE pointer (hipMalloc / torch CUDA memory) on the current
+ *    device, including the small parameter arrays kappa, tau and A.  Structs are host memory.
+ *  - Maps are component-major: X[j * n_pix + p], with pixel p = iy * nx + ix (row-major grid).
+ *    W and Y are stacked by map: W[f * n_pix + p] (Section 2.1).  A is row-major f x k:
+ *    A[f * k + j], row f is a_f.
+ *  - The caller owns all memory.  The library allocates nothing on the device: scratch space
+ *    comes from the caller's workspace `ws` of `ws_bytes` bytes (256-byte aligned), sized by
+ *    sylv_workspace_bytes().  The workspace must not be shared by calls that overlap in time.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  sylv_apply, sylv_precond,
+ *    sylv_prepare, sylv_rhs and sylv_po_perturb only enqueue work.  sylv_pcg_solve and
+ *    sylv_pcg_backward enqueue work and synchronise `stream` a few times to test convergence;
+ *    they return when the solve has finished.
+ *  - Return value: 0 on success, a negative SYLV_E_* code when the arguments are rejected before
+ *    any work is enqueued (then sylv_last_error() describes why), or SYLV_E_HIP when a HIP call
+ *    failed.  Numerical outcomes of a solve (converged, not converged, breakdown, non-finite
+ *    values) are reported per solve in sylv_pcg_stats.status, not as the return value.
+ *  - Limits: 1 <= k <= 8, 1 <= f <= 16, ny, nx >= 1, ny * nx < 2^31.
+ */
+#ifndef SYLV_H
+#define SYLV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return and status codes ------------------------------------------------------------- */
+#define SYLV_OK              0  /* converged (stats) / success (return value)                  */
+#define SYLV_NOT_CONVERGED   1  /* max_iter (or refine_max) reached; X holds the last iterate   */
+#define SYLV_BREAKDOWN       2  /* <p, G p> <= 0 or <r, z> <= 0: operator or preconditioner not
+                                   positive definite (e.g. negative tau, or kappa = 0 with no
+                                   data weight at all)                                          */
+#define SYLV_NONFINITE       3  /* a NaN or Inf appeared in a residual or inner product         */
+#define SYLV_STAGNATED       4  /* mixed precision: an outer refinement step did not reduce the
+                                   float64 residual                                             */
+#define SYLV_E_INVALID     (-1) /* bad argument (null pointer, size out of range, bad option)   */
+#define SYLV_E_WORKSPACE   (-2) /* ws_bytes smaller than sylv_workspace_bytes()                  */
+#define SYLV_E_HIP         (-3) /* a HIP runtime call failed                                     */
+
+/* ---- element types, precisions, preconditioners ------------------------------------------ */
+#define SYLV_F64 0
+#define SYLV_F32 1
+
+#define SYLV_PREC_F64   0       /* every vector and every apply in float64                       */
+#define SYLV_PREC_MIXED 1       /* float32 vectors and applies inside float64 refinement         */
+
+#define SYLV_PC_NONE   0        /* z = r (plain Alg. 2)                                           */
+#define SYLV_PC_JACOBI 1        /* z = r / diag(G)                                                */
+#define SYLV_PC_BLOCK  2        /* z_p = (G_pp)^-1 r_p, G_pp the k x k block of pixel p           */
+
+/* One posterior-mean system (Section 2, Section 3).  Host struct of device pointers. */
+typedef struct sylv_problem {
+    int64_t ny, nx;        /* periodic grid, n_pix = ny * nx                                     */
+    int32_t k;             /* components (the paper's m: sources)                                */
+    int32_t f;             /* maps (the paper's n: frequencies)                                  */
+    const double *kappa;   /* [k]  kappa_j >= 0   (prior range parameter)                        */
+    const double *tau;     /* [k]  tau_j > 0      (prior precision scale; the paper's phi_l)     */
+    const double *A;       /* [f * k] mixing matrix, row-major                                   */
+    const double *W;       /* [f * n_pix] noise precision per map and pixel, >= 0 (0 = masked)   */
+} sylv_problem;
+
+typedef struct sylv_pcg_opts {
+    double  tol;           /* stop when ||b - G x||_2 <= tol * ||b - G x0||_2 (Alg. 2 test)       */
+    int32_t max_iter;      /* iteration cap of each (inner) conjugate-gradient run               */
+    int32_t precision;     /* SYLV_PREC_F64 or SYLV_PREC_MIXED                                   */
+    double  inner_tol;     /* mixed: smallest relative reduction asked of one float32 inner run
+                              (0 = 1e-5)                                                          */
+    int32_t refine_max;    /* mixed: maximum number of float64 refinement steps (0 = 8)          */
+    int32_t precond;       /* SYLV_PC_NONE, SYLV_PC_JACOBI or SYLV_PC_BLOCK                       */
+    int32_t check_every;   /* iterations enqueued between host convergence checks (0 = 16)       */
+    int32_t reserved;
+} sylv_pcg_opts;
+
+/* Per-solve result, written by the device into caller memory (DEVICE pointer). */
+typedef struct sylv_pcg_stats {
+    int32_t status;        /* SYLV_OK, SYLV_NOT_CONVERGED, SYLV_BREAKDOWN, SYLV_NONFINITE, ... */
+    int32_t iters;         /* total conjugate-gradient iterations (all inner runs)              */
+    int32_t outer;         /* refinement steps (mixed) or 1 (float64)                           */
+    int32_t reserved;
+    double  relres_rec;    /* last recursive residual norm / initial residual norm              */
+    double  relres_true;   /* ||b - G x||_2 / ||b||_2 recomputed in float64 at the end          */
+} sylv_pcg_stats;
+
+/* Bytes of workspace needed.  probs[nprob] are the problems of a batch, each solved for nrhs
+ * right-hand sides.  opts == NULL: enough for sylv_prepare / sylv_apply / sylv_precond with
+ * nprob = 1 and up to nrhs right-hand sides.  Returns 0 for invalid arguments. */
+size_t sylv_workspace_bytes(const sylv_problem *probs, int32_t nprob, int32_t nrhs,
+                            const sylv_pcg_opts *opts);
+
+/* Operator set-up for one problem: stencil coefficients of every Q_j (13-point expansion of
+ * tau_j (kappa_j^2 - Lap)^2, Section 3.1), the per-pixel mixing blocks
+ * M_p = sum_f W[f,p] a_f a_f^T (the block map of Section 3.1 in per-pixel form) and the
+ * preconditioner blocks, in float64 and float32.  Written into ws; later calls with
+ * prepared = 1 reuse them. */
+int sylv_prepare(const sylv_problem *prob, int32_t precond, void *ws, size_t ws_bytes,
+                 void *stream);
+
+/* Y = G(X) for nrhs maps (Section 3.1: the matrix-free product x -> (Q + B^T C B) x).
+ * X, Y: [nrhs][k][n_pix] of dtype SYLV_F64 or SYLV_F32 (not overlapping).  prepared = 0 runs
+ * sylv_prepare first. */
+int sylv_apply(const sylv_problem *prob, int32_t dtype, const void *X, void *Y, int32_t nrhs,
+               int32_t prepared, void *ws, size_t ws_bytes, void *stream);
+
+/* Z = Minv R with the chosen preconditioner (Section 3.2 remarks on preconditioning).
+ * R, Z: [nrhs][k][n_pix] of dtype.  precond must match the sylv_prepare call when prepared. */
+int sylv_precond(const sylv_problem *prob, int32_t dtype, int32_t precond, const void *R,
+                 void *Z, int32_t nrhs, int32_t prepared, void *ws, size_t ws_bytes,
+                 void *stream);
+
+/* Right-hand side B_rhs = B^T C Y (eq. (mu*)): Bout[j*n_pix+p] = sum_f W[f,p] Y[f,p] A[f,j].
+ * Y: [f][n_pix] float64, Bout: [k][n_pix] float64. */
+int sylv_rhs(const sylv_problem *prob, const double *Y, double *Bout, void *stream);
+
+/* Perturbation for posterior sampling (perturbation optimisation):
+ * eta_j = sqrt(tau_j) L_j^T xi_j + sum_f A[f,j] sqrt(W[f,:]) zeta_f, L_j = kappa_j^2 - Lap,
+ * so that Cov(eta) = G and G^-1 (B_rhs + eta) is a draw from the posterior of Section 2.2.
+ * xi: [nrhs][k][n_pix], zeta: [nrhs][f][n_pix], eta: [nrhs][k][n_pix], all float64. */
+int sylv_po_perturb(const sylv_problem *prob, const double *xi, const double *zeta, double *eta,
+                    int32_t nrhs, void *stream);
+
+/* Solve G x = b for nprob problems times nrhs right-hand sides each, by preconditioned CG
+ * (Alg. 2 plus preconditioner), in float64 or mixed precision.
+ *   b = B^T C Y (if Y != NULL) + Bextra (if Bextra != NULL); at least one must be given.
+ *   Y:      concatenation over problems of [f_g][n_pix_g] float64 (shared by the g's rhs)
+ *   Bextra: concatenation over problems of [nrhs][k][n_pix_g] float64
+ *   X:      concatenation over problems of [nrhs][k][n_pix_g] float64: initial guess on entry
+ *           (zeros for the paper's x0 = 0), solution on return
+ *   stats:  [nprob * nrhs] device structs, problem-major.
+ * All problems of one call must share k. */
+int sylv_pcg_solve(const sylv_problem *probs, int32_t nprob, int32_t nrhs, const double *Y,
+                   const double *Bextra, double *X, const sylv_pcg_opts *opts,
+                   sylv_pcg_stats *stats, void *ws, size_t ws_bytes, void *stream);
+
+/* Adjoint of the solve.  Given x* = G^-1 B_rhs (Xstar, [k][n_pix]) and Gbar = dL/dx*, solves
+ * G lambda = Gbar (G is symmetric, so this is a second PCG run; Lambda is the initial guess on
+ * entry and lambda on return) and forms the gradient of <Gbar, x*> with respect to the
+ * parameters, writing (device pointers, each may be NULL to skip):
+ *   dkappa[k]  = -4 kappa_j tau_j <lambda_j, L_j x*_j>
+ *   dtau[k]    = -<L_j lambda_j, L_j x*_j>
+ *   dA[f*k]    = sum_p W[f,p] (r_f(p) lambda_p - (a_f . lambda_p) x*_p),  r_f = Y_f - a_f . x*
+ *   dW[f*n_pix]= (a_f . lambda_p) r_f(p)
+ *   dY[f*n_pix]= W[f,p] (a_f . lambda_p)
+ * Y: [f][n_pix] float64 (the observed maps used for x*). */
+int sylv_pcg_backward(const sylv_problem *prob, const double *Y, const double *Xstar,
+                      const double *Gbar, double *Lambda, double *dkappa, double *dtau,
+                      double *dA, double *dW, double *dY, const sylv_pcg_opts *opts,
+                      sylv_pcg_stats *stats, void *ws, size_t ws_bytes, void *stream);
+
+/* Human-readable name of a status or return code (static string). */
+const char *sylv_status_string(int code);
+
+/* Description of the last argument error of the calling thread (static per-thread buffer). */
+const char *sylv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SYLV_H */

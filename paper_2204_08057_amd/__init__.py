@@ -1,0 +1,32 @@
+"""MI355X (gfx950) solver for the posterior mean of the CMB source-separation model.
+
+Python binding of libsylv (C ABI declared in include/sylv.h).  Argument marshalling only: every
+numerical step runs in the library's HIP kernels; torch supplies device memory and the current
+stream.  Importing works without a GPU; calling any solver function requires the built library
+and a GPU, and raises otherwise (there is no CPU fallback).
+"""
+from .binding import (  # noqa: F401
+    SYLV_F32,
+    SYLV_F64,
+    SYLV_PC_BLOCK,
+    SYLV_PC_JACOBI,
+    SYLV_PC_NONE,
+    SYLV_PREC_F64,
+    SYLV_PREC_MIXED,
+    STATUS_NAMES,
+    DeviceProblem,
+    SolveOptions,
+    SylvError,
+    SylvSolve,
+    apply,
+    declared_symbols,
+    lib,
+    library_path,
+    pcg_backward,
+    pcg_solve,
+    po_perturb,
+    precond,
+    rhs,
+    status_string,
+    workspace_bytes,
+)

@@ -1,0 +1,480 @@
+// Host side of libsylv: argument validation, workspace layout, and the driver loops of the
+// preconditioned CG solve (Alg. 2 plus preconditioner; float64 or mixed precision with float64
+// iterative refinement) and of its adjoint.  Everything numerical runs in the kernels of
+// sylv_kernels.hip; the host only enqueues launches and, every `check_every` iterations, reads
+// one integer (how many runs are still going) to decide whether to enqueue more.
+
+#include "sylv.h"
+#include "sylv_internal.h"
+
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+using namespace sylv;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+void set_err(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int apply_rows_setting() {
+    static int rows = -1;
+    if (rows < 0) {
+        const char *e = getenv("SYLV_APPLY_ROWS");
+        int v = e ? atoi(e) : 4;
+        rows = apply_rows_valid(v) ? v : 4;
+    }
+    return rows;
+}
+
+int tiles_for(int ny, int nx, int rows) {
+    const int tx = (nx + kTileX - 1) / kTileX;
+    const int ty = (ny + kWavesY * rows - 1) / (kWavesY * rows);
+    return tx * ty;
+}
+int chunks_for(int n_pix) { return (n_pix + kChunk - 1) / kChunk; }
+
+struct ProbLayout {
+    size_t coef, M64, M32, P64, P32;
+};
+struct InstLayout {
+    size_t st, partial, b, r, z, p, p2, q, r32, z32, p32, p32b, q32, d32;
+    int nred;
+};
+struct Layout {
+    std::vector<ProbLayout> prob;
+    std::vector<InstLayout> inst;
+    size_t table = 0, tprefix = 0, cprefix = 0, count = 0, gpartial = 0, gticket = 0;
+    size_t total = 0;
+};
+
+bool check_problem(const sylv_problem *p, int idx) {
+    if (!p) { set_err("problem %d: null pointer", idx); return false; }
+    if (p->k < 1 || p->k > kMaxK) { set_err("problem %d: k=%d outside [1, %d]", idx, p->k, kMaxK); return false; }
+    if (p->f < 1 || p->f > kMaxF) { set_err("problem %d: f=%d outside [1, %d]", idx, p->f, kMaxF); return false; }
+    if (p->ny < 1 || p->nx < 1) { set_err("problem %d: grid %lld x %lld", idx, (long long)p->ny, (long long)p->nx); return false; }
+    if (p->ny * p->nx >= (int64_t)1 << 30) { set_err("problem %d: n_pix too large", idx); return false; }
+    if (!p->kappa || !p->tau || !p->A || !p->W) { set_err("problem %d: null parameter pointer", idx); return false; }
+    return true;
+}
+
+// Workspace: per-problem operator regions first (so that the layout of the operator of a single
+// problem does not depend on the call), then the instance table and prefixes, the run states,
+// reduction partials, solver vectors and the gradient partials.
+bool make_layout(const sylv_problem *probs, int nprob, int nrhs, bool solve, Layout &L) {
+    size_t off = 0;
+    L.prob.resize(nprob);
+    for (int g = 0; g < nprob; ++g) {
+        const size_t n = (size_t)probs[g].ny * probs[g].nx;
+        const size_t mk = (size_t)packed_size(probs[g].k);
+        ProbLayout &P = L.prob[g];
+        P.coef = off; off = align_up(off + sizeof(double) * kCoefStride * kMaxK);
+        P.M64 = off;  off = align_up(off + sizeof(double) * mk * n);
+        P.M32 = off;  off = align_up(off + sizeof(float) * mk * n);
+        P.P64 = off;  off = align_up(off + sizeof(double) * mk * n);
+        P.P32 = off;  off = align_up(off + sizeof(float) * mk * n);
+    }
+    const int ninst = solve ? nprob * nrhs : 1;
+    L.table = off;   off = align_up(off + sizeof(Inst) * ninst);
+    L.tprefix = off; off = align_up(off + sizeof(int) * (ninst + 1));
+    L.cprefix = off; off = align_up(off + sizeof(int) * (ninst + 1));
+    L.count = off;   off = align_up(off + sizeof(int) * 4);
+    if (solve) {
+        L.inst.resize(ninst);
+        for (int g = 0; g < nprob; ++g) {
+            const int ny = (int)probs[g].ny, nx = (int)probs[g].nx, k = probs[g].k;
+            const size_t n = (size_t)ny * nx;
+            const size_t vk = (size_t)k * n;
+            for (int r = 0; r < nrhs; ++r) {
+                InstLayout &I = L.inst[(size_t)g * nrhs + r];
+                I.nred = std::max(tiles_for(ny, nx, 2), chunks_for((int)n));
+                I.st = off;      off = align_up(off + 2 * sizeof(DevState));
+                I.partial = off; off = align_up(off + sizeof(double) * 4 * I.nred);
+                I.b = off;   off = align_up(off + sizeof(double) * vk);
+                I.r = off;   off = align_up(off + sizeof(double) * vk);
+                I.z = off;   off = align_up(off + sizeof(double) * vk);
+                I.p = off;   off = align_up(off + sizeof(double) * vk);
+                I.p2 = off;  off = align_up(off + sizeof(double) * vk);
+                I.q = off;   off = align_up(off + sizeof(double) * vk);
+                I.r32 = off; off = align_up(off + sizeof(float) * vk);
+                I.z32 = off; off = align_up(off + sizeof(float) * vk);
+                I.p32 = off; off = align_up(off + sizeof(float) * vk);
+                I.p32b = off; off = align_up(off + sizeof(float) * vk);
+                I.q32 = off; off = align_up(off + sizeof(float) * vk);
+                I.d32 = off; off = align_up(off + sizeof(float) * vk);
+            }
+        }
+        if (nprob == 1 && nrhs == 1) {
+            const int n_pix = (int)(probs[0].ny * probs[0].nx);
+            L.gpartial = off;
+            off = align_up(off + sizeof(double) * grad_nv(probs[0].k, probs[0].f) *
+                                     grad_blocks(n_pix));
+            L.gticket = off;
+            off = align_up(off + sizeof(uint32_t) * 4);
+        }
+    }
+    L.total = off;
+    return true;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            set_err("%s failed: %s", #expr, hipGetErrorString(e_));                     \
+            return SYLV_E_HIP;                                                          \
+        }                                                                               \
+    } while (0)
+
+Inst operator_inst(const sylv_problem &p, const ProbLayout &P, char *base, int pc) {
+    Inst I;
+    memset(&I, 0, sizeof(I));
+    I.ny = (int)p.ny;
+    I.nx = (int)p.nx;
+    I.n_pix = (int)(p.ny * p.nx);
+    I.tiles_x = (I.nx + kTileX - 1) / kTileX;
+    I.pc = pc;
+    I.f = p.f;
+    I.coef = reinterpret_cast<const double *>(base + P.coef);
+    I.A = p.A;
+    I.W = p.W;
+    I.M64 = reinterpret_cast<const double *>(base + P.M64);
+    I.M32 = reinterpret_cast<const float *>(base + P.M32);
+    I.P64 = reinterpret_cast<const double *>(base + P.P64);
+    I.P32 = reinterpret_cast<const float *>(base + P.P32);
+    return I;
+}
+
+int prepare_operator(const sylv_problem &p, const ProbLayout &P, char *base, int pc,
+                     hipStream_t s) {
+    double *coef = reinterpret_cast<double *>(base + P.coef);
+    HIP_TRY(launch_coef(p.kappa, p.tau, p.k, (int)p.ny, (int)p.nx, coef, s));
+    HIP_TRY(launch_setup(p.W, p.A, p.f, (int)(p.ny * p.nx), coef, pc,
+                         reinterpret_cast<double *>(base + P.M64),
+                         reinterpret_cast<float *>(base + P.M32),
+                         reinterpret_cast<double *>(base + P.P64),
+                         reinterpret_cast<float *>(base + P.P32), p.k, s));
+    return SYLV_OK;
+}
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+int check_ws(void *ws, size_t ws_bytes, size_t need) {
+    if (!ws) { set_err("null workspace"); return SYLV_E_INVALID; }
+    if (((uintptr_t)ws & (kAlign - 1)) != 0) { set_err("workspace not 256-byte aligned"); return SYLV_E_INVALID; }
+    if (ws_bytes < need) {
+        set_err("workspace of %zu bytes, %zu needed", ws_bytes, need);
+        return SYLV_E_WORKSPACE;
+    }
+    return SYLV_OK;
+}
+
+int check_opts(const sylv_pcg_opts *o) {
+    if (!o) { set_err("null opts"); return SYLV_E_INVALID; }
+    if (!(o->tol > 0.0) || !(o->tol < 1.0)) { set_err("tol must be in (0, 1)"); return SYLV_E_INVALID; }
+    if (o->max_iter < 1) { set_err("max_iter must be >= 1"); return SYLV_E_INVALID; }
+    if (o->precision != SYLV_PREC_F64 && o->precision != SYLV_PREC_MIXED) { set_err("bad precision"); return SYLV_E_INVALID; }
+    if (o->precond < SYLV_PC_NONE || o->precond > SYLV_PC_BLOCK) { set_err("bad precond"); return SYLV_E_INVALID; }
+    if (o->inner_tol < 0.0 || o->inner_tol >= 1.0) { set_err("inner_tol must be in [0, 1)"); return SYLV_E_INVALID; }
+    if (o->refine_max < 0 || o->check_every < 0) { set_err("negative refine_max/check_every"); return SYLV_E_INVALID; }
+    return SYLV_OK;
+}
+
+// Enqueue `chunk`-iteration batches until no run is going; one 4-byte readback per batch.
+int run_cg_loop(const InstSet &set, int k, int mixed, int rows, int chunk, int max_iter,
+                int *dcount, hipStream_t s) {
+    int done_iters = 0;
+    for (;;) {
+        for (int c = 0; c < chunk; ++c) {
+            HIP_TRY(launch_cg_apply(set, k, mixed, rows, s));
+            HIP_TRY(launch_cg_update(set, k, mixed, s));
+        }
+        done_iters += chunk;
+        HIP_TRY(launch_count_running(set, mixed, dcount, s));
+        int h = 0;
+        HIP_TRY(hipMemcpyAsync(&h, dcount, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (h == 0 || done_iters >= max_iter) break;
+    }
+    return SYLV_OK;
+}
+
+int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
+               const double *Bextra, double *X, const sylv_pcg_opts *opts,
+               sylv_pcg_stats *stats, void *ws, size_t ws_bytes, hipStream_t s, Layout &L) {
+    if (nprob < 1 || nrhs < 1) { set_err("nprob and nrhs must be >= 1"); return SYLV_E_INVALID; }
+    for (int g = 0; g < nprob; ++g)
+        if (!check_problem(&probs[g], g)) return SYLV_E_INVALID;
+    const int k = probs[0].k;
+    for (int g = 1; g < nprob; ++g)
+        if (probs[g].k != k) { set_err("all problems of a call must share k"); return SYLV_E_INVALID; }
+    int rc = check_opts(opts);
+    if (rc) return rc;
+    if (!X || !stats) { set_err("null X or stats"); return SYLV_E_INVALID; }
+    if (!Y && !Bextra) { set_err("need Y or Bextra"); return SYLV_E_INVALID; }
+    make_layout(probs, nprob, nrhs, true, L);
+    rc = check_ws(ws, ws_bytes, L.total);
+    if (rc) return rc;
+    char *base = reinterpret_cast<char *>(ws);
+    const int mixed = opts->precision == SYLV_PREC_MIXED;
+    const int rows = apply_rows_setting();
+    const int pc = opts->precond;
+
+    // instance table
+    const int ninst = nprob * nrhs;
+    std::vector<Inst> tab(ninst);
+    std::vector<int> tpre(ninst + 1), cpre(ninst + 1);
+    size_t xoff = 0, yoff = 0;
+    tpre[0] = cpre[0] = 0;
+    for (int g = 0; g < nprob; ++g) {
+        const sylv_problem &p = probs[g];
+        const size_t n = (size_t)p.ny * p.nx;
+        for (int r = 0; r < nrhs; ++r) {
+            const int i = g * nrhs + r;
+            const InstLayout &IL = L.inst[i];
+            Inst I = operator_inst(p, L.prob[g], base, pc);
+            I.ntiles = tiles_for(I.ny, I.nx, rows);
+            I.nchunks = chunks_for(I.n_pix);
+            I.nred = IL.nred;
+            I.Y = Y ? Y + yoff : nullptr;
+            I.bext = Bextra ? Bextra + xoff + (size_t)r * k * n : nullptr;
+            I.b = reinterpret_cast<double *>(base + IL.b);
+            I.x = X + xoff + (size_t)r * k * n;
+            I.r = reinterpret_cast<double *>(base + IL.r);
+            I.z = reinterpret_cast<double *>(base + IL.z);
+            I.p[0] = reinterpret_cast<double *>(base + IL.p);
+            I.p[1] = reinterpret_cast<double *>(base + IL.p2);
+            I.q = reinterpret_cast<double *>(base + IL.q);
+            I.r32 = reinterpret_cast<float *>(base + IL.r32);
+            I.z32 = reinterpret_cast<float *>(base + IL.z32);
+            I.p32[0] = reinterpret_cast<float *>(base + IL.p32);
+            I.p32[1] = reinterpret_cast<float *>(base + IL.p32b);
+            I.q32 = reinterpret_cast<float *>(base + IL.q32);
+            I.d32 = reinterpret_cast<float *>(base + IL.d32);
+            I.st = reinterpret_cast<DevState *>(base + IL.st);
+            I.st_in = I.st + 1;
+            I.partial = reinterpret_cast<double *>(base + IL.partial);
+            I.vec4 = (I.n_pix % 4 == 0) && aligned16(I.x) ? 1 : 0;
+            tab[i] = I;
+            tpre[i + 1] = tpre[i] + I.ntiles;
+            cpre[i + 1] = cpre[i] + I.nchunks;
+        }
+        xoff += (size_t)nrhs * k * n;
+        yoff += (size_t)p.f * n;
+    }
+    HIP_TRY(hipMemcpyAsync(base + L.table, tab.data(), sizeof(Inst) * ninst,
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(base + L.tprefix, tpre.data(), sizeof(int) * (ninst + 1),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(base + L.cprefix, cpre.data(), sizeof(int) * (ninst + 1),
+                           hipMemcpyHostToDevice, s));
+    InstSet set;
+    set.table = reinterpret_cast<const Inst *>(base + L.table);
+    set.tprefix = reinterpret_cast<const int *>(base + L.tprefix);
+    set.cprefix = reinterpret_cast<const int *>(base + L.cprefix);
+    set.ninst = ninst;
+    set.total_tiles = tpre[ninst];
+    set.total_chunks = cpre[ninst];
+    int *dcount = reinterpret_cast<int *>(base + L.count);
+
+    // operator set-up and right-hand sides
+    for (int g = 0; g < nprob; ++g) {
+        rc = prepare_operator(probs[g], L.prob[g], base, pc, s);
+        if (rc) return rc;
+    }
+    HIP_TRY(launch_state_init(set, opts->tol, opts->max_iter, s));
+    for (int i = 0; i < ninst; ++i) {
+        const Inst &I = tab[i];
+        HIP_TRY(launch_rhs(I.W, I.Y, I.A, I.f, I.n_pix, I.bext, I.b, k, s));
+    }
+    const int chunk = opts->check_every > 0 ? opts->check_every : 16;
+    HIP_TRY(launch_resid(set, k, rows, 0, s));   // r0 = b - G x0, ||b||, ||r0||
+    if (!mixed) {
+        HIP_TRY(launch_pinit(set, k, 0, 0.0, opts->max_iter, s));
+        rc = run_cg_loop(set, k, 0, rows, chunk, opts->max_iter, dcount, s);
+        if (rc) return rc;
+        HIP_TRY(launch_resid(set, k, rows, 1, s));   // true residual of the result
+    } else {
+        const double inner_tol = opts->inner_tol > 0.0 ? opts->inner_tol : 1e-5;
+        const int refine_max = opts->refine_max > 0 ? opts->refine_max : 8;
+        for (int o = 0; o < refine_max; ++o) {
+            HIP_TRY(launch_pinit(set, k, 1, inner_tol, opts->max_iter, s));
+            rc = run_cg_loop(set, k, 1, rows, chunk, opts->max_iter, dcount, s);
+            if (rc) return rc;
+            HIP_TRY(launch_refine_axpy(set, k, s));
+            HIP_TRY(launch_resid(set, k, rows, 2, s));   // float64 residual of the new x
+            HIP_TRY(launch_count_running(set, 0, dcount, s));
+            int h = 0;
+            HIP_TRY(hipMemcpyAsync(&h, dcount, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (h == 0) break;
+        }
+    }
+    HIP_TRY(launch_stats(set, stats, mixed, s));
+    return SYLV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sylv_workspace_bytes(const sylv_problem *probs, int32_t nprob, int32_t nrhs,
+                            const sylv_pcg_opts *opts) {
+    if (!probs || nprob < 1 || nrhs < 1) return 0;
+    for (int g = 0; g < nprob; ++g)
+        if (!check_problem(&probs[g], g)) return 0;
+    Layout L;
+    if (!opts) {
+        if (nprob != 1) return 0;
+        make_layout(probs, 1, 1, false, L);
+    } else {
+        make_layout(probs, nprob, nrhs, true, L);
+    }
+    return L.total;
+}
+
+int sylv_prepare(const sylv_problem *prob, int32_t precond, void *ws, size_t ws_bytes,
+                 void *stream) {
+    if (!check_problem(prob, 0)) return SYLV_E_INVALID;
+    if (precond < SYLV_PC_NONE || precond > SYLV_PC_BLOCK) { set_err("bad precond"); return SYLV_E_INVALID; }
+    Layout L;
+    make_layout(prob, 1, 1, false, L);
+    int rc = check_ws(ws, ws_bytes, L.total);
+    if (rc) return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char *base = reinterpret_cast<char *>(ws);
+    rc = prepare_operator(*prob, L.prob[0], base, precond, s);
+    if (rc) return rc;
+    Inst I = operator_inst(*prob, L.prob[0], base, precond);
+    I.ntiles = 0;
+    I.nchunks = chunks_for(I.n_pix);
+    HIP_TRY(hipMemcpyAsync(base + L.table, &I, sizeof(Inst), hipMemcpyHostToDevice, s));
+    // pageable source: make sure the copy has consumed it before `I` goes out of scope
+    HIP_TRY(hipStreamSynchronize(s));
+    return SYLV_OK;
+}
+
+int sylv_apply(const sylv_problem *prob, int32_t dtype, const void *X, void *Y, int32_t nrhs,
+               int32_t prepared, void *ws, size_t ws_bytes, void *stream) {
+    if (!check_problem(prob, 0)) return SYLV_E_INVALID;
+    if (dtype != SYLV_F64 && dtype != SYLV_F32) { set_err("bad dtype"); return SYLV_E_INVALID; }
+    if (!X || !Y || nrhs < 1) { set_err("null X/Y or nrhs < 1"); return SYLV_E_INVALID; }
+    if (X == Y) { set_err("X and Y must not overlap"); return SYLV_E_INVALID; }
+    Layout L;
+    make_layout(prob, 1, 1, false, L);
+    int rc = check_ws(ws, ws_bytes, L.total);
+    if (rc) return rc;
+    if (!prepared) {
+        rc = sylv_prepare(prob, SYLV_PC_NONE, ws, ws_bytes, stream);
+        if (rc) return rc;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char *base = reinterpret_cast<char *>(ws);
+    HIP_TRY(launch_apply_plain(reinterpret_cast<const Inst *>(base + L.table), prob->k, dtype,
+                               apply_rows_setting(), (int)prob->ny, (int)prob->nx, nrhs, X, Y,
+                               s));
+    return SYLV_OK;
+}
+
+int sylv_precond(const sylv_problem *prob, int32_t dtype, int32_t precond, const void *R,
+                 void *Z, int32_t nrhs, int32_t prepared, void *ws, size_t ws_bytes,
+                 void *stream) {
+    if (!check_problem(prob, 0)) return SYLV_E_INVALID;
+    if (dtype != SYLV_F64 && dtype != SYLV_F32) { set_err("bad dtype"); return SYLV_E_INVALID; }
+    if (precond < SYLV_PC_NONE || precond > SYLV_PC_BLOCK) { set_err("bad precond"); return SYLV_E_INVALID; }
+    if (!R || !Z || nrhs < 1) { set_err("null R/Z or nrhs < 1"); return SYLV_E_INVALID; }
+    Layout L;
+    make_layout(prob, 1, 1, false, L);
+    int rc = check_ws(ws, ws_bytes, L.total);
+    if (rc) return rc;
+    if (!prepared) {
+        rc = sylv_prepare(prob, precond, ws, ws_bytes, stream);
+        if (rc) return rc;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char *base = reinterpret_cast<char *>(ws);
+    HIP_TRY(launch_precond_plain(reinterpret_cast<const Inst *>(base + L.table), prob->k, dtype,
+                                 (int)(prob->ny * prob->nx), nrhs, R, Z, s));
+    return SYLV_OK;
+}
+
+int sylv_rhs(const sylv_problem *prob, const double *Y, double *Bout, void *stream) {
+    if (!check_problem(prob, 0)) return SYLV_E_INVALID;
+    if (!Y || !Bout) { set_err("null Y or Bout"); return SYLV_E_INVALID; }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIP_TRY(launch_rhs(prob->W, Y, prob->A, prob->f, (int)(prob->ny * prob->nx), nullptr, Bout,
+                       prob->k, s));
+    return SYLV_OK;
+}
+
+int sylv_po_perturb(const sylv_problem *prob, const double *xi, const double *zeta, double *eta,
+                    int32_t nrhs, void *stream) {
+    if (!check_problem(prob, 0)) return SYLV_E_INVALID;
+    if (!xi || !zeta || !eta || nrhs < 1) { set_err("null xi/zeta/eta or nrhs < 1"); return SYLV_E_INVALID; }
+    if (nrhs > 65535) { set_err("nrhs > 65535"); return SYLV_E_INVALID; }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIP_TRY(launch_po(prob->kappa, prob->tau, prob->A, prob->W, xi, zeta, eta, prob->k, prob->f,
+                      (int)prob->ny, (int)prob->nx, nrhs, s));
+    return SYLV_OK;
+}
+
+int sylv_pcg_solve(const sylv_problem *probs, int32_t nprob, int32_t nrhs, const double *Y,
+                   const double *Bextra, double *X, const sylv_pcg_opts *opts,
+                   sylv_pcg_stats *stats, void *ws, size_t ws_bytes, void *stream) {
+    if (!probs) { set_err("null problems"); return SYLV_E_INVALID; }
+    Layout L;
+    return solve_impl(probs, nprob, nrhs, Y, Bextra, X, opts, stats, ws, ws_bytes,
+                      reinterpret_cast<hipStream_t>(stream), L);
+}
+
+int sylv_pcg_backward(const sylv_problem *prob, const double *Y, const double *Xstar,
+                      const double *Gbar, double *Lambda, double *dkappa, double *dtau,
+                      double *dA, double *dW, double *dY, const sylv_pcg_opts *opts,
+                      sylv_pcg_stats *stats, void *ws, size_t ws_bytes, void *stream) {
+    if (!check_problem(prob, 0)) return SYLV_E_INVALID;
+    if (!Y || !Xstar || !Gbar || !Lambda) { set_err("null Y/Xstar/Gbar/Lambda"); return SYLV_E_INVALID; }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Layout L;
+    int rc = solve_impl(prob, 1, 1, nullptr, Gbar, Lambda, opts, stats, ws, ws_bytes, s, L);
+    if (rc) return rc;
+    char *base = reinterpret_cast<char *>(ws);
+    uint32_t *ticket = reinterpret_cast<uint32_t *>(base + L.gticket);
+    HIP_TRY(hipMemsetAsync(ticket, 0, sizeof(uint32_t), s));
+    HIP_TRY(launch_grad(reinterpret_cast<const double *>(base + L.prob[0].coef), prob->A,
+                        prob->W, Y, Xstar, Lambda, prob->k, prob->f, (int)prob->ny,
+                        (int)prob->nx, dkappa, dtau, dA, dW, dY,
+                        reinterpret_cast<double *>(base + L.gpartial), ticket, s));
+    return SYLV_OK;
+}
+
+const char *sylv_status_string(int code) {
+    switch (code) {
+        case SYLV_OK: return "ok";
+        case SYLV_NOT_CONVERGED: return "not converged";
+        case SYLV_BREAKDOWN: return "breakdown (operator or preconditioner not positive definite)";
+        case SYLV_NONFINITE: return "non-finite value";
+        case SYLV_STAGNATED: return "refinement stagnated";
+        case SYLV_E_INVALID: return "invalid argument";
+        case SYLV_E_WORKSPACE: return "workspace too small";
+        case SYLV_E_HIP: return "HIP runtime error";
+        default: return "unknown code";
+    }
+}
+
+const char *sylv_last_error(void) { return g_err; }
+
+}  // extern "C"

@@ -1,0 +1,127 @@
+// Internal declarations shared by the HIP kernels (sylv_kernels.hip) and the host driver
+// (sylv_api.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sylv {
+
+constexpr int kMaxK = 8;
+constexpr int kMaxF = 16;
+constexpr int kCoefStride = 8;   // per component: c0, c1, cd, c2, diag, kappa, tau, unused
+constexpr int kBlock = 256;      // threads per workgroup (4 wavefronts of 64)
+constexpr int kTileX = 64;       // apply tile width = one wavefront across x
+constexpr int kWavesY = 4;       // wavefronts stacked in y inside an apply tile
+constexpr int kChunk = 1024;     // pixels per workgroup in streaming kernels (4 per thread)
+constexpr int kNumTickets = 8;
+
+enum Ticket { T_APPLY = 0, T_UPDATE = 1, T_INIT = 2, T_RESID = 3, T_GRAD = 4 };
+
+// Solver state of one conjugate-gradient run, in device memory.  All scalars of the
+// recurrence (Alg. 2: alpha, beta, <r, z>, ||r||) live here in float64 and are produced by the
+// last workgroup of each reduction, so the host never has to read them inside the loop.
+struct DevState {
+    double rho;      // <r, z> of the current residual
+    double alpha;    // step length of the current iteration
+    double beta;     // direction update coefficient
+    double pq;       // <p, G p>
+    double rr;       // ||r||^2 (recursive residual)
+    double rr0;      // ||r_0||^2
+    double bb;       // ||b||^2
+    double thresh;   // stop when rr <= thresh
+    double tol;      // relative tolerance of this run
+    double rel_true; // ||b - G x|| / ||b|| from the last float64 residual pass
+    double rr_prev;  // previous refinement residual (stagnation test of the mixed path)
+    int32_t iter;    // iterations done by this run
+    int32_t max_iter;
+    int32_t status;  // SYLV_OK / SYLV_NOT_CONVERGED / SYLV_BREAKDOWN / SYLV_NONFINITE / ...
+    int32_t done;    // 1 once the run stopped; every kernel of the loop returns early then
+    int32_t first;   // 1 before the first direction: p = z instead of z + beta p
+    int32_t total_iter;  // accumulated over inner runs (mixed precision)
+    int32_t outer;   // refinement steps
+    int32_t pad;
+    uint32_t ticket[kNumTickets];  // arrival counters of the last-workgroup reductions
+};
+
+// One solve instance = one (problem, right-hand side) pair.  Pointers are into the caller's
+// buffers or into the workspace.
+struct Inst {
+    int32_t ny, nx, n_pix;
+    int32_t tiles_x;     // apply tiles across x
+    int32_t ntiles;      // apply tiles in this instance
+    int32_t nchunks;     // streaming chunks in this instance
+    int32_t nred;        // stride between reduction quantities in `partial`
+    int32_t pc;          // preconditioner kind (SYLV_PC_*)
+    int32_t vec4;        // 1 if n_pix % 4 == 0 and every plane is 16-byte aligned
+    int32_t f;           // maps of the problem
+    const double *coef;  // [K * kCoefStride]
+    const double *A;     // [f * K]
+    const double *W;     // [f * n_pix]
+    const double *Y;     // [f * n_pix] or null
+    const double *bext;  // [K * n_pix] extra right-hand side or null
+    const double *M64;   // packed mixing blocks [K(K+1)/2][n_pix]
+    const float *M32;
+    const double *P64;   // packed preconditioner blocks
+    const float *P32;
+    // float64 vectors.  The search direction is double-buffered: the apply of iteration i reads
+    // the previous direction from p[i & 1] (including stencil halos owned by other workgroups)
+    // and writes the new one to p[(i + 1) & 1], so no workgroup overwrites a value another one
+    // may still read.
+    double *b, *x, *r, *z, *p[2], *q;
+    // float32 vectors of the inner runs of the mixed path; d = inner solution
+    float *r32, *z32, *p32[2], *q32, *d32;
+    DevState *st;        // float64 run (or outer refinement state)
+    DevState *st_in;     // float32 inner run
+    double *partial;     // [nslots][nred]
+};
+
+// Launch-time view of the instances: a device table plus prefix sums that map a flat
+// workgroup id to (instance, tile) for apply kernels or (instance, chunk) for streaming ones.
+struct InstSet {
+    const Inst *table;   // device array [ninst]
+    const int *tprefix;  // device [ninst + 1] prefix sums of apply tiles
+    const int *cprefix;  // device [ninst + 1] prefix sums of streaming chunks
+    int ninst;
+    int total_tiles;
+    int total_chunks;
+};
+
+inline int packed_size(int k) { return k * (k + 1) / 2; }
+
+// ---- launchers (sylv_kernels.hip) -------------------------------------------------------
+// Every launcher returns the hipError_t of its launch.
+int apply_rows_valid(int rows);
+hipError_t launch_coef(const double *kappa, const double *tau, int k, int ny, int nx,
+                       double *coef, hipStream_t s);
+hipError_t launch_setup(const double *W, const double *A, int f, int n_pix, const double *coef,
+                        int pc, double *M64, float *M32, double *P64, float *P32, int k,
+                        hipStream_t s);
+hipError_t launch_rhs(const double *W, const double *Y, const double *A, int f, int n_pix,
+                      const double *bext, double *b, int k, hipStream_t s);
+hipError_t launch_apply_plain(const Inst *table0, int k, int dtype, int rows, int ny, int nx,
+                              int nrhs, const void *in, void *out, hipStream_t s);
+hipError_t launch_precond_plain(const Inst *table0, int k, int dtype, int n_pix, int nrhs,
+                                const void *in, void *out, hipStream_t s);
+// residual r = b - G x (float64); phase 0: initial (sets ||b||, ||r0||, threshold),
+// 1: final true residual only, 2: refinement step of the mixed path
+hipError_t launch_resid(const InstSet &set, int k, int rows, int phase, hipStream_t s);
+hipError_t launch_pinit(const InstSet &set, int k, int mixed, double inner_tol, int max_iter,
+                        hipStream_t s);
+hipError_t launch_cg_apply(const InstSet &set, int k, int mixed, int rows, hipStream_t s);
+hipError_t launch_cg_update(const InstSet &set, int k, int mixed, hipStream_t s);
+hipError_t launch_refine_axpy(const InstSet &set, int k, hipStream_t s);
+hipError_t launch_state_init(const InstSet &set, double tol, int max_iter, hipStream_t s);
+hipError_t launch_count_running(const InstSet &set, int inner, int *out, hipStream_t s);
+hipError_t launch_stats(const InstSet &set, void *stats, int mixed, hipStream_t s);
+hipError_t launch_po(const double *kappa, const double *tau, const double *A, const double *W,
+                     const double *xi, const double *zeta, double *eta, int k, int f, int ny,
+                     int nx, int nrhs, hipStream_t s);
+hipError_t launch_grad(const double *coef, const double *A, const double *W, const double *Y,
+                       const double *X, const double *Lm, int k, int f, int ny, int nx,
+                       double *dkappa, double *dtau, double *dA, double *dW, double *dY,
+                       double *partial, uint32_t *ticket, hipStream_t s);
+int grad_blocks(int n_pix);
+int grad_nv(int k, int f);
+
+}  // namespace sylv

@@ -1,0 +1,1193 @@
+// HIP kernels (gfx950) of the matrix-free preconditioned CG solve for the posterior mean of the
+// CMB source-separation model (Section 3: eq. (Axb); Section 3.1 matrix-free products;
+// Alg. 2 conjugate gradients).
+//
+// Data layout: every map is a plane of n_pix = ny * nx values, pixel p = iy * nx + ix, and a
+// k-component field is k consecutive planes (component-major, the paper's stacking by map).
+// Per-pixel k x k symmetric blocks (mixing M_p, preconditioner) are stored as k(k+1)/2 planes,
+// upper triangle row by row.
+//
+// Work decomposition:
+//  * operator apply: a workgroup owns a 64 x (4R) tile; each wavefront covers 64 consecutive
+//    pixels of a row (coalesced 256/512-byte accesses) and each lane walks R rows of one column,
+//    keeping a register window of the 13-point stencil, so every interior value is fetched
+//    from memory about 7 times per R=4 outputs instead of 13 (the rest come from the wave's
+//    neighbouring lanes through L1).  The k x k mixing is done on VALU from the packed block.
+//  * streaming kernels: 4 consecutive pixels per lane, 16-byte vector accesses.
+//  * reductions: shuffle tree in the wavefront, fixed-order sum of the 4 wavefronts, one
+//    partial per workgroup, and the last workgroup to arrive (atomic ticket) sums the partials
+//    in fixed order and advances the CG scalars on the device.  Results are bitwise
+//    reproducible run to run.
+//  * workgroup -> tile mapping is XCD-aware: consecutive workgroup ids are dealt round-robin to
+//    the 8 XCDs, so ids are remapped to give every XCD a contiguous band of tiles, which keeps
+//    stencil halos and the shared per-pixel blocks in that XCD's L2.
+
+#include "sylv_internal.h"
+#include "sylv.h"
+
+#include <math.h>
+
+namespace sylv {
+namespace {
+
+constexpr int kXcd = 8;
+
+__device__ __forceinline__ int wrapi(int v, int n) {
+    while (v < 0) v += n;
+    while (v >= n) v -= n;
+    return v;
+}
+
+// Give XCD x (which receives workgroups x, x+8, x+16, ...) a contiguous range of logical ids.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    const int q = nb / kXcd, rem = nb % kXcd;
+    const int x = b % kXcd, slot = b / kXcd;
+    return x * q + min(x, rem) + slot;
+}
+
+__device__ __forceinline__ int find_inst(const int *__restrict__ prefix, int ninst, int L) {
+    int lo = 0, hi = ninst;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= L) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+template <int K>
+__host__ __device__ constexpr int pidx(int i, int j) {
+    return (i <= j) ? (i * K - (i * (i - 1)) / 2 + (j - i)) : (j * K - (j * (j - 1)) / 2 + (i - j));
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Block-reduce NV values (fixed order) and store one partial per quantity for this workgroup.
+template <int NV>
+__device__ __forceinline__ void block_partials(double (&v)[NV], double *__restrict__ partial,
+                                               int nred, int slot) {
+    __shared__ double sm[NV][kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) sm[i][wid] = v[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+            partial[(size_t)i * nred + slot] = (sm[i][0] + sm[i][1]) + (sm[i][2] + sm[i][3]);
+    }
+}
+
+// Returns true in the last workgroup (of nblocks) to pass this point.  Thread 0 has written
+// the workgroup's partials before the call.
+__device__ __forceinline__ bool arrive_last(uint32_t *ticket, int nblocks) {
+    __shared__ int last;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t t = atomicAdd(ticket, 1u);
+        last = (t == (uint32_t)(nblocks - 1));
+    }
+    __syncthreads();
+    if (last) __threadfence();
+    return last != 0;
+}
+
+// Fixed-order sum of NV quantities over nblocks partials, result valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void final_sums(const double *__restrict__ partial, int nred,
+                                           int nblocks, double (&out)[NV]) {
+    __shared__ double sm[NV][kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += kBlock) s += partial[(size_t)i * nred + b];
+        s = wave_sum(s);
+        if (lane == 0) sm[i][wid] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) out[i] = (sm[i][0] + sm[i][1]) + (sm[i][2] + sm[i][3]);
+}
+
+__device__ __forceinline__ bool finite_d(double v) { return isfinite(v); }
+
+// ---- vector access helpers ----------------------------------------------------------------
+__device__ __forceinline__ void ld4(const double *__restrict__ p, double (&v)[4]) {
+    const double2 a = reinterpret_cast<const double2 *>(p)[0];
+    const double2 b = reinterpret_cast<const double2 *>(p)[1];
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+__device__ __forceinline__ void ld4(const float *__restrict__ p, float (&v)[4]) {
+    const float4 a = reinterpret_cast<const float4 *>(p)[0];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+}
+__device__ __forceinline__ void st4(double *__restrict__ p, const double (&v)[4]) {
+    reinterpret_cast<double2 *>(p)[0] = make_double2(v[0], v[1]);
+    reinterpret_cast<double2 *>(p)[1] = make_double2(v[2], v[3]);
+}
+__device__ __forceinline__ void st4(float *__restrict__ p, const float (&v)[4]) {
+    reinterpret_cast<float4 *>(p)[0] = make_float4(v[0], v[1], v[2], v[3]);
+}
+
+// Field selectors by precision.
+template <typename T> struct Sel;
+template <> struct Sel<double> {
+    static __device__ __forceinline__ const double *M(const Inst &I) { return I.M64; }
+    static __device__ __forceinline__ const double *P(const Inst &I) { return I.P64; }
+    static __device__ __forceinline__ double *x(const Inst &I) { return I.x; }
+    static __device__ __forceinline__ double *r(const Inst &I) { return I.r; }
+    static __device__ __forceinline__ double *z(const Inst &I) { return I.z; }
+    static __device__ __forceinline__ double *p(const Inst &I, int i) { return I.p[i & 1]; }
+    static __device__ __forceinline__ double *q(const Inst &I) { return I.q; }
+    static __device__ __forceinline__ DevState *st(const Inst &I) { return I.st; }
+};
+template <> struct Sel<float> {
+    static __device__ __forceinline__ const float *M(const Inst &I) { return I.M32; }
+    static __device__ __forceinline__ const float *P(const Inst &I) { return I.P32; }
+    static __device__ __forceinline__ float *x(const Inst &I) { return I.d32; }
+    static __device__ __forceinline__ float *r(const Inst &I) { return I.r32; }
+    static __device__ __forceinline__ float *z(const Inst &I) { return I.z32; }
+    static __device__ __forceinline__ float *p(const Inst &I, int i) { return I.p32[i & 1]; }
+    static __device__ __forceinline__ float *q(const Inst &I) { return I.q32; }
+    static __device__ __forceinline__ DevState *st(const Inst &I) { return I.st_in; }
+};
+
+// z = Pinv r at one pixel for the three preconditioner kinds; P planes are read at `pix`.
+template <typename T, int K>
+__device__ __forceinline__ void precond_pixel(int pc, const T *__restrict__ P, int n_pix, int pix,
+                                              const T (&r)[K], T (&z)[K]) {
+    if (pc == SYLV_PC_BLOCK) {
+        constexpr int MK = K * (K + 1) / 2;
+        T pm[MK];
+#pragma unroll
+        for (int e = 0; e < MK; ++e) pm[e] = P[(size_t)e * n_pix + pix];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            T s = 0;
+#pragma unroll
+            for (int i = 0; i < K; ++i) s += pm[pidx<K>(j, i)] * r[i];
+            z[j] = s;
+        }
+    } else if (pc == SYLV_PC_JACOBI) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) z[j] = P[(size_t)j * n_pix + pix] * r[j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < K; ++j) z[j] = r[j];
+    }
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void precond_vec4(int pc, const T *__restrict__ P, int n_pix, int p0,
+                                             const T (&r)[K][4], T (&z)[K][4]) {
+    if (pc == SYLV_PC_BLOCK) {
+        constexpr int MK = K * (K + 1) / 2;
+        T pm[MK][4];
+#pragma unroll
+        for (int e = 0; e < MK; ++e) ld4(P + (size_t)e * n_pix + p0, pm[e]);
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                T s = 0;
+#pragma unroll
+                for (int i = 0; i < K; ++i) s += pm[pidx<K>(j, i)][e] * r[i][e];
+                z[j][e] = s;
+            }
+    } else if (pc == SYLV_PC_JACOBI) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            T d[4];
+            ld4(P + (size_t)j * n_pix + p0, d);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) z[j][e] = d[e] * r[j][e];
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) z[j][e] = r[j][e];
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Stencil coefficients of Q_j = tau (kappa^2 - Lap)^2 on the periodic 5-point Laplacian.
+// Expanding the square with N4 = sum of the 4 edge neighbours (Lap = N4 - 4):
+//   (kappa^2 + 4 - N4)^2 = (kappa^2+4)^2 - 2 (kappa^2+4) N4 + N4^2,
+//   N4^2 = 4 (centre) + 2 (each of the 4 diagonal neighbours) + 1 (each of the 4 pixels at
+//   distance 2 along an axis),
+// so c0 = tau((kappa^2+4)^2 + 4), c1 = -2 tau (kappa^2+4), cd = 2 tau, c2 = tau.  Since the
+// shift operators commute, the expansion is exact on every periodic grid; on grids with a side
+// <= 2 several offsets land on the same pixel and their coefficients simply add, which is what
+// the apply does with wrapped indices.  `diag` is the true diagonal of Q_j including those
+// coincidences (used by the preconditioner).
+__global__ void k_coef(const double *__restrict__ kappa, const double *__restrict__ tau, int k,
+                       int ny, int nx, double *__restrict__ coef) {
+    const int j = threadIdx.x;
+    if (j >= k) return;
+    const double kp = kappa[j], t = tau[j];
+    const double s = kp * kp + 4.0;
+    const double c0 = t * (s * s + 4.0), c1 = -2.0 * t * s, cd = 2.0 * t, c2 = t;
+    double dg = c0;
+    dg += 2.0 * c1 * ((nx == 1 ? 1.0 : 0.0) + (ny == 1 ? 1.0 : 0.0));
+    dg += 4.0 * cd * ((nx == 1 && ny == 1) ? 1.0 : 0.0);
+    dg += 2.0 * c2 * ((nx <= 2 ? 1.0 : 0.0) + (ny <= 2 ? 1.0 : 0.0));
+    double *c = coef + j * kCoefStride;
+    c[0] = c0; c[1] = c1; c[2] = cd; c[3] = c2; c[4] = dg; c[5] = kp; c[6] = t; c[7] = 0.0;
+}
+
+// Per-pixel mixing block M_p = sum_f W[f,p] a_f a_f^T (the block map N (M A^T) T A of
+// Section 3.1 done pixel by pixel) and the preconditioner: block-Jacobi inverts
+// diag_j(Q_j diagonal) + M_p by a k x k Cholesky factorisation in float64.
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_setup(const double *__restrict__ W,
+                                                  const double *__restrict__ A, int f, int n_pix,
+                                                  const double *__restrict__ coef, int pc,
+                                                  double *__restrict__ M64, float *__restrict__ M32,
+                                                  double *__restrict__ P64, float *__restrict__ P32) {
+    constexpr int MK = K * (K + 1) / 2;
+    const int pix = blockIdx.x * kBlock + threadIdx.x;
+    if (pix >= n_pix) return;
+    double m[MK];
+#pragma unroll
+    for (int e = 0; e < MK; ++e) m[e] = 0.0;
+    for (int fi = 0; fi < f; ++fi) {
+        const double w = W[(size_t)fi * n_pix + pix];
+        double a[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) a[j] = A[fi * K + j];
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+#pragma unroll
+            for (int j = i; j < K; ++j) m[pidx<K>(i, j)] += w * a[i] * a[j];
+    }
+#pragma unroll
+    for (int e = 0; e < MK; ++e) {
+        M64[(size_t)e * n_pix + pix] = m[e];
+        M32[(size_t)e * n_pix + pix] = (float)m[e];
+    }
+    if (pc == SYLV_PC_JACOBI) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const double d = 1.0 / (coef[j * kCoefStride + 4] + m[pidx<K>(j, j)]);
+            P64[(size_t)j * n_pix + pix] = d;
+            P32[(size_t)j * n_pix + pix] = (float)d;
+        }
+    } else if (pc == SYLV_PC_BLOCK) {
+        double a[K][K], l[K][K];
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                a[i][j] = m[pidx<K>(i, j)] + (i == j ? coef[i * kCoefStride + 4] : 0.0);
+                l[i][j] = 0.0;
+            }
+        bool ok = true;
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            double s = a[c][c];
+#pragma unroll
+            for (int t = 0; t < c; ++t) s -= l[c][t] * l[c][t];
+            ok = ok && (s > 0.0);
+            const double d = sqrt(s > 0.0 ? s : 1.0);
+            l[c][c] = d;
+            const double inv = 1.0 / d;
+#pragma unroll
+            for (int r = c + 1; r < K; ++r) {
+                double v = a[r][c];
+#pragma unroll
+                for (int t = 0; t < c; ++t) v -= l[r][t] * l[c][t];
+                l[r][c] = v * inv;
+            }
+        }
+        // inverse = L^-T L^-1, column by column
+        double inv[K][K];
+#pragma unroll
+        for (int col = 0; col < K; ++col) {
+            double y[K];
+#pragma unroll
+            for (int r = 0; r < K; ++r) {
+                double v = (r == col) ? 1.0 : 0.0;
+#pragma unroll
+                for (int t = 0; t < r; ++t) v -= l[r][t] * y[t];
+                y[r] = v / l[r][r];
+            }
+#pragma unroll
+            for (int r = K - 1; r >= 0; --r) {
+                double v = y[r];
+#pragma unroll
+                for (int t = r + 1; t < K; ++t) v -= l[t][r] * inv[t][col];
+                inv[r][col] = v / l[r][r];
+            }
+        }
+        const double bad = ok ? 0.0 : __builtin_nan("");
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+#pragma unroll
+            for (int j = i; j < K; ++j) {
+                const double v = 0.5 * (inv[i][j] + inv[j][i]) + bad;
+                P64[(size_t)pidx<K>(i, j) * n_pix + pix] = v;
+                P32[(size_t)pidx<K>(i, j) * n_pix + pix] = (float)v;
+            }
+    }
+}
+
+// Right-hand side b = B^T C Y (+ extra): b[j,p] = sum_f W[f,p] Y[f,p] A[f,j] (eq. (mu*)).
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_rhs(const double *__restrict__ W,
+                                                const double *__restrict__ Y,
+                                                const double *__restrict__ A, int f, int n_pix,
+                                                const double *__restrict__ bext,
+                                                double *__restrict__ b) {
+    const int pix = blockIdx.x * kBlock + threadIdx.x;
+    if (pix >= n_pix) return;
+    double acc[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) acc[j] = bext ? bext[(size_t)j * n_pix + pix] : 0.0;
+    if (Y) {
+        for (int fi = 0; fi < f; ++fi) {
+            const double wy = W[(size_t)fi * n_pix + pix] * Y[(size_t)fi * n_pix + pix];
+#pragma unroll
+            for (int j = 0; j < K; ++j) acc[j] += wy * A[fi * K + j];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) b[(size_t)j * n_pix + pix] = acc[j];
+}
+
+// ---------------------------------------------------------------------------------------------
+// Operator apply G(u) = sum_j Q_j u_j + M_p u_p, fused variants:
+//   AM_PLAIN : out = G(in)                                       (stand-alone apply)
+//   AM_CG    : u = z + beta p (u = z at the first iteration), p <- u, q = G(u),
+//              <u, q> -> alpha = rho / <p, q>                   (Alg. 2: q = G p, alpha)
+//   AM_RESID : r = b - G(x), ||r||^2, ||b||^2                    (initial / true residual)
+enum ApplyMode { AM_PLAIN = 0, AM_CG = 1, AM_RESID = 2 };
+
+template <typename T, int K, int R, int MODE>
+__global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
+                                                  const int *__restrict__ tprefix, int ninst,
+                                                  int nb, int phase,
+                                                  const T *__restrict__ ext_in,
+                                                  T *__restrict__ ext_out) {
+    constexpr int MK = K * (K + 1) / 2;
+    const int L = xcd_remap(blockIdx.x, nb);
+    const int ii = (MODE == AM_PLAIN) ? 0 : find_inst(tprefix, ninst, L);
+    const Inst &I = tab[ii];
+    const int tile = (MODE == AM_PLAIN) ? L : L - tprefix[ii];
+    DevState *st = (MODE == AM_CG) ? Sel<T>::st(I) : I.st;
+    if (MODE == AM_CG) {
+        if (st->done) return;
+    }
+    const int nx = I.nx, ny = I.ny, n_pix = I.n_pix;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int tile_x = tile % I.tiles_x, tile_y = tile / I.tiles_x;
+    const int ix = tile_x * kTileX + tx;
+    const int iy0 = (tile_y * kWavesY + ty) * R;
+    const bool active = (ix < nx) && (iy0 < ny);
+
+    const T *u0;           // field (or previous direction when fusing)
+    const T *u1 = nullptr; // preconditioned residual z when fusing
+    T beta = 0;
+    if constexpr (MODE == AM_PLAIN) {
+        u0 = ext_in + (size_t)blockIdx.y * K * n_pix;
+    } else if constexpr (MODE == AM_CG) {
+        u1 = Sel<T>::z(I);
+        // first direction: p = z; alias p_old to z with beta = 0 so that no uninitialised
+        // value is ever read.
+        const bool first = st->first != 0;
+        u0 = first ? u1 : Sel<T>::p(I, st->iter);
+        beta = first ? (T)0 : (T)st->beta;
+    } else {
+        u0 = reinterpret_cast<const T *>(I.x);
+    }
+
+    T acc[K][R];
+    T ctr[K][R];
+    int rowoff[R + 4];
+    double d0 = 0.0, d1 = 0.0;
+    if (active) {
+#pragma unroll
+        for (int t = 0; t < R + 4; ++t) rowoff[t] = wrapi(iy0 - 2 + t, ny) * nx;
+        const int xm2 = wrapi(ix - 2, nx), xm1 = wrapi(ix - 1, nx);
+        const int xp1 = wrapi(ix + 1, nx), xp2 = wrapi(ix + 2, nx);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const double *cj = I.coef + j * kCoefStride;
+            const T c0 = (T)cj[0], c1 = (T)cj[1], cd = (T)cj[2], c2 = (T)cj[3];
+            const T *a = u0 + (size_t)j * n_pix;
+            const T *zz = (MODE == AM_CG) ? (u1 + (size_t)j * n_pix) : nullptr;
+            auto ld = [&](int off) -> T {
+                if constexpr (MODE == AM_CG) return zz[off] + beta * a[off];
+                else return a[off];
+            };
+            T cc[R + 4], l1[R + 2], r1[R + 2], l2[R], r2[R];
+#pragma unroll
+            for (int t = 0; t < R + 4; ++t) cc[t] = ld(rowoff[t] + ix);
+#pragma unroll
+            for (int t = 0; t < R + 2; ++t) {
+                l1[t] = ld(rowoff[t + 1] + xm1);
+                r1[t] = ld(rowoff[t + 1] + xp1);
+            }
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                l2[t] = ld(rowoff[t + 2] + xm2);
+                r2[t] = ld(rowoff[t + 2] + xp2);
+            }
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                const T n4 = (cc[t + 1] + cc[t + 3]) + (l1[t + 1] + r1[t + 1]);
+                const T d4 = (l1[t] + r1[t]) + (l1[t + 2] + r1[t + 2]);
+                const T f4 = (cc[t] + cc[t + 4]) + (l2[t] + r2[t]);
+                acc[j][t] = c0 * cc[t + 2] + c1 * n4 + cd * d4 + c2 * f4;
+                ctr[j][t] = cc[t + 2];
+            }
+        }
+        const T *M = Sel<T>::M(I);
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            if (iy0 + t < ny) {
+                const int pix = rowoff[t + 2] + ix;
+                T m[MK];
+#pragma unroll
+                for (int e = 0; e < MK; ++e) m[e] = M[(size_t)e * n_pix + pix];
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    T s = acc[j][t];
+#pragma unroll
+                    for (int i = 0; i < K; ++i) s += m[pidx<K>(j, i)] * ctr[i][t];
+                    acc[j][t] = s;
+                }
+                if constexpr (MODE == AM_PLAIN) {
+                    T *o = ext_out + (size_t)blockIdx.y * K * n_pix;
+#pragma unroll
+                    for (int j = 0; j < K; ++j) o[(size_t)j * n_pix + pix] = acc[j][t];
+                } else if constexpr (MODE == AM_CG) {
+                    T *pp = Sel<T>::p(I, st->iter + 1);
+                    T *qq = Sel<T>::q(I);
+#pragma unroll
+                    for (int j = 0; j < K; ++j) {
+                        pp[(size_t)j * n_pix + pix] = ctr[j][t];
+                        qq[(size_t)j * n_pix + pix] = acc[j][t];
+                        d0 += (double)ctr[j][t] * (double)acc[j][t];
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < K; ++j) {
+                        const double bv = I.b[(size_t)j * n_pix + pix];
+                        const double rv = bv - (double)acc[j][t];
+                        I.r[(size_t)j * n_pix + pix] = rv;
+                        d0 += rv * rv;
+                        d1 += bv * bv;
+                    }
+                }
+            }
+        }
+    }
+    if constexpr (MODE == AM_CG) {
+        double v[1] = {d0};
+        block_partials<1>(v, I.partial, I.nred, tile);
+        if (arrive_last(&st->ticket[T_APPLY], I.ntiles)) {
+            double s[1];
+            final_sums<1>(I.partial, I.nred, I.ntiles, s);
+            if (threadIdx.x == 0) {
+                const double pq = s[0];
+                st->pq = pq;
+                if (!finite_d(pq)) {
+                    st->status = SYLV_NONFINITE; st->done = 1;
+                } else if (!(pq > 0.0)) {
+                    st->status = SYLV_BREAKDOWN; st->done = 1;
+                } else {
+                    st->alpha = st->rho / pq;
+                }
+                st->ticket[T_APPLY] = 0u;
+            }
+        }
+    } else if constexpr (MODE == AM_RESID) {
+        double v[2] = {d0, d1};
+        block_partials<2>(v, I.partial, I.nred, tile);
+        if (arrive_last(&st->ticket[T_RESID], I.ntiles)) {
+            double s[2];
+            final_sums<2>(I.partial, I.nred, I.ntiles, s);
+            if (threadIdx.x == 0) {
+                const double rr = s[0];
+                if (phase == 0) {
+                    st->bb = s[1];
+                    st->rr0 = rr;
+                    st->rr = rr;
+                    st->rr_prev = rr;
+                    st->thresh = st->tol * st->tol * rr;
+                    if (!finite_d(rr)) { st->status = SYLV_NONFINITE; st->done = 1; }
+                    else if (rr == 0.0) { st->status = SYLV_OK; st->done = 1; }
+                } else if (phase == 2) {
+                    // refinement step of the mixed path: converged / stagnated / not finite
+                    st->rr = rr;
+                    st->outer += 1;
+                    if (!finite_d(rr)) {
+                        st->status = SYLV_NONFINITE; st->done = 1;
+                    } else if (rr <= st->thresh) {
+                        st->status = SYLV_OK; st->done = 1;
+                    } else if (rr > 0.25 * st->rr_prev) {
+                        st->status = SYLV_STAGNATED; st->done = 1;
+                    }
+                    st->rr_prev = rr;
+                }
+                const double bb = st->bb;
+                st->rel_true = (bb > 0.0) ? sqrt(rr / bb) : sqrt(rr);
+                st->ticket[T_RESID] = 0u;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// CG vector update of Alg. 2 with the preconditioner fused in:
+//   x += alpha p, r -= alpha q, z = Pinv r, <r, z>, ||r||^2  -> beta, stopping test.
+// T = double: the float64 run (x = solution).  T = float: an inner run of the mixed path
+// (x = d32, the correction).
+template <typename T, int K>
+__global__ __launch_bounds__(kBlock) void k_update(const Inst *__restrict__ tab,
+                                                   const int *__restrict__ cprefix, int ninst,
+                                                   int nb) {
+    const int L = xcd_remap(blockIdx.x, nb);
+    const int ii = find_inst(cprefix, ninst, L);
+    const Inst &I = tab[ii];
+    const int chunk = L - cprefix[ii];
+    DevState *st = Sel<T>::st(I);
+    if (st->done) return;
+    const int n_pix = I.n_pix;
+    const T alpha = (T)st->alpha;
+    T *x = Sel<T>::x(I);
+    T *r = Sel<T>::r(I);
+    T *z = Sel<T>::z(I);
+    const T *p = Sel<T>::p(I, st->iter + 1);   // direction written by this iteration's apply
+    const T *q = Sel<T>::q(I);
+    const T *P = Sel<T>::P(I);
+    const int pc = I.pc;
+    const int p0 = chunk * kChunk + threadIdx.x * 4;
+    double rz = 0.0, rr = 0.0;
+    if (p0 < n_pix) {
+        if (I.vec4 && p0 + 4 <= n_pix) {
+            T rv[K][4], zv[K][4];
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const size_t o = (size_t)j * n_pix + p0;
+                T xv[4], pv[4], qv[4];
+                ld4(x + o, xv); ld4(p + o, pv); ld4(r + o, rv[j]); ld4(q + o, qv);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    xv[e] += alpha * pv[e];
+                    rv[j][e] -= alpha * qv[e];
+                }
+                st4(x + o, xv);
+                st4(r + o, rv[j]);
+            }
+            precond_vec4<T, K>(pc, P, n_pix, p0, rv, zv);
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                st4(z + (size_t)j * n_pix + p0, zv[j]);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    rz += (double)rv[j][e] * (double)zv[j][e];
+                    rr += (double)rv[j][e] * (double)rv[j][e];
+                }
+            }
+        } else {
+            for (int e = 0; e < 4 && p0 + e < n_pix; ++e) {
+                const int pix = p0 + e;
+                T rv[K], zv[K];
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    const size_t o = (size_t)j * n_pix + pix;
+                    x[o] += alpha * p[o];
+                    rv[j] = r[o] - alpha * q[o];
+                    r[o] = rv[j];
+                }
+                precond_pixel<T, K>(pc, P, n_pix, pix, rv, zv);
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    z[(size_t)j * n_pix + pix] = zv[j];
+                    rz += (double)rv[j] * (double)zv[j];
+                    rr += (double)rv[j] * (double)rv[j];
+                }
+            }
+        }
+    }
+    double v[2] = {rz, rr};
+    block_partials<2>(v, I.partial, I.nred, chunk);
+    if (arrive_last(&st->ticket[T_UPDATE], I.nchunks)) {
+        double s[2];
+        final_sums<2>(I.partial, I.nred, I.nchunks, s);
+        if (threadIdx.x == 0) {
+            const double rho_new = s[0], rrn = s[1];
+            st->rr = rrn;
+            st->iter += 1;
+            st->total_iter += 1;
+            st->first = 0;
+            if (!finite_d(rho_new) || !finite_d(rrn)) {
+                st->status = SYLV_NONFINITE; st->done = 1;
+            } else if (rrn <= st->thresh) {
+                st->status = SYLV_OK; st->done = 1;
+            } else if (!(rho_new > 0.0)) {
+                st->status = SYLV_BREAKDOWN; st->done = 1;
+            } else if (st->iter >= st->max_iter) {
+                st->status = SYLV_NOT_CONVERGED; st->done = 1;
+            }
+            st->beta = rho_new / st->rho;
+            st->rho = rho_new;
+            st->ticket[T_UPDATE] = 0u;
+        }
+    }
+}
+
+// Start of a CG run: z0 = Pinv r0, rho0 = <r0, z0>, ||r0||^2.
+// T = double: r is the float64 residual of the float64 run.
+// T = float : start of an inner run of the mixed path; the float64 outer residual I.r is
+//             rounded to float32 (r32), the correction d32 is zeroed, and the inner stopping
+//             threshold asks for the reduction that brings the outer residual to tolerance
+//             (with a safety factor), but never less than `inner_tol`.
+template <typename T, int K>
+__global__ __launch_bounds__(kBlock) void k_pinit(const Inst *__restrict__ tab,
+                                                  const int *__restrict__ cprefix, int ninst,
+                                                  int nb, double inner_tol, int max_iter) {
+    const int L = xcd_remap(blockIdx.x, nb);
+    const int ii = find_inst(cprefix, ninst, L);
+    const Inst &I = tab[ii];
+    const int chunk = L - cprefix[ii];
+    DevState *st = Sel<T>::st(I);
+    if constexpr (sizeof(T) == 4) {
+        if (I.st->done) {   // outer refinement already finished for this instance
+            if (chunk == 0 && threadIdx.x == 0) { st->done = 1; st->status = SYLV_OK; }
+            return;
+        }
+    }
+    const int n_pix = I.n_pix;
+    const double *r64 = I.r;
+    T *rr_out = Sel<T>::r(I);
+    T *z = Sel<T>::z(I);
+    const T *P = Sel<T>::P(I);
+    const int pc = I.pc;
+    const int p0 = chunk * kChunk + threadIdx.x * 4;
+    double rz = 0.0, rr = 0.0;
+    for (int e = 0; e < 4 && p0 + e < n_pix; ++e) {
+        const int pix = p0 + e;
+        T rv[K], zv[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const size_t o = (size_t)j * n_pix + pix;
+            rv[j] = (T)r64[o];
+            if constexpr (sizeof(T) == 4) {
+                rr_out[o] = rv[j];
+                I.d32[o] = 0.0f;
+            }
+        }
+        precond_pixel<T, K>(pc, P, n_pix, pix, rv, zv);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            z[(size_t)j * n_pix + pix] = zv[j];
+            rz += (double)rv[j] * (double)zv[j];
+            rr += (double)rv[j] * (double)rv[j];
+        }
+    }
+    double v[2] = {rz, rr};
+    block_partials<2>(v, I.partial, I.nred, chunk);
+    if (arrive_last(&st->ticket[T_INIT], I.nchunks)) {
+        double s[2];
+        final_sums<2>(I.partial, I.nred, I.nchunks, s);
+        if (threadIdx.x == 0) {
+            st->rho = s[0];
+            st->rr0 = s[1];
+            st->rr = s[1];
+            st->beta = 0.0;
+            st->iter = 0;
+            st->first = 1;
+            st->max_iter = max_iter;
+            st->status = SYLV_OK;
+            st->done = 0;
+            double tol = st->tol;
+            if constexpr (sizeof(T) == 4) {
+                // relative reduction needed by the outer residual, with a factor 0.3 margin
+                const double need = 0.3 * sqrt(I.st->thresh / fmax(I.st->rr, 1e-300));
+                tol = fmin(0.1, fmax(inner_tol, need));
+                st->tol = tol;
+            }
+            st->thresh = tol * tol * s[1];
+            if (!finite_d(s[0]) || !finite_d(s[1])) {
+                st->status = SYLV_NONFINITE; st->done = 1;
+            } else if (s[1] <= st->thresh || s[1] == 0.0) {
+                st->done = 1;
+            } else if (!(s[0] > 0.0)) {
+                st->status = SYLV_BREAKDOWN; st->done = 1;
+            }
+            if constexpr (sizeof(T) == 8) {
+                // the float64 run's initial-residual state also carries the final result
+                if (st->status != SYLV_OK) I.st->done = 1;
+            } else {
+                if (st->status != SYLV_OK) {
+                    I.st->status = st->status;
+                    I.st->done = 1;
+                }
+            }
+            st->ticket[T_INIT] = 0u;
+        }
+    }
+}
+
+// Mixed path: x += d (float32 correction promoted to float64), for instances still refining.
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_refine_axpy(const Inst *__restrict__ tab,
+                                                        const int *__restrict__ cprefix,
+                                                        int ninst, int nb) {
+    const int L = xcd_remap(blockIdx.x, nb);
+    const int ii = find_inst(cprefix, ninst, L);
+    const Inst &I = tab[ii];
+    if (I.st->done) return;
+    const int chunk = L - cprefix[ii];
+    const int n_pix = I.n_pix;
+    const int p0 = chunk * kChunk + threadIdx.x * 4;
+    if (I.st_in->status == SYLV_NONFINITE || I.st_in->status == SYLV_BREAKDOWN) return;
+    for (int e = 0; e < 4 && p0 + e < n_pix; ++e) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const size_t o = (size_t)j * n_pix + p0 + e;
+            I.x[o] += (double)I.d32[o];
+        }
+    }
+}
+
+// Stand-alone preconditioner apply: out = Pinv in.
+template <typename T, int K>
+__global__ __launch_bounds__(kBlock) void k_precond_plain(const Inst *__restrict__ tab,
+                                                          const T *__restrict__ in,
+                                                          T *__restrict__ out) {
+    const Inst &I = tab[0];
+    const int n_pix = I.n_pix;
+    const int pix = blockIdx.x * kBlock + threadIdx.x;
+    if (pix >= n_pix) return;
+    const T *src = in + (size_t)blockIdx.y * K * n_pix;
+    T *dst = out + (size_t)blockIdx.y * K * n_pix;
+    T rv[K], zv[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) rv[j] = src[(size_t)j * n_pix + pix];
+    precond_pixel<T, K>(I.pc, Sel<T>::P(I), n_pix, pix, rv, zv);
+#pragma unroll
+    for (int j = 0; j < K; ++j) dst[(size_t)j * n_pix + pix] = zv[j];
+}
+
+// Reset the run states of every instance before a solve.
+__global__ void k_state_init(const Inst *__restrict__ tab, int ninst, double tol, int max_iter) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ninst) return;
+    DevState *ss[2] = {tab[i].st, tab[i].st_in};
+    for (int s = 0; s < 2; ++s) {
+        DevState *st = ss[s];
+        st->rho = 0.0; st->alpha = 0.0; st->beta = 0.0; st->pq = 0.0; st->rr = 0.0;
+        st->rr0 = 0.0; st->bb = 0.0; st->thresh = 0.0; st->tol = tol; st->rel_true = 0.0;
+        st->iter = 0; st->max_iter = max_iter; st->status = SYLV_OK; st->done = 0;
+        st->first = 1; st->total_iter = 0; st->outer = 0; st->pad = 0;
+        for (int t = 0; t < kNumTickets; ++t) st->ticket[t] = 0u;
+    }
+}
+
+// Number of instances whose run (outer or inner) has not finished.
+__global__ void k_count_running(const Inst *__restrict__ tab, int ninst, int inner,
+                                int *__restrict__ out) {
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < ninst; i += blockDim.x) {
+        const DevState *st = inner ? tab[i].st_in : tab[i].st;
+        if (!st->done) atomicAdd(&cnt, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = cnt;
+}
+
+__global__ void k_stats(const Inst *__restrict__ tab, int ninst, sylv_pcg_stats *__restrict__ out,
+                        int mixed) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ninst) return;
+    const DevState *st = tab[i].st;
+    const DevState *si = tab[i].st_in;
+    sylv_pcg_stats s;
+    if (mixed) {
+        s.status = st->status;
+        if (st->status == SYLV_OK && !st->done) s.status = SYLV_NOT_CONVERGED;
+        s.iters = si->total_iter;
+        s.outer = st->outer;
+        s.relres_rec = (st->rr0 > 0.0) ? sqrt(st->rr / st->rr0) : 0.0;
+    } else {
+        s.status = st->status;
+        if (st->status == SYLV_OK && !st->done) s.status = SYLV_NOT_CONVERGED;
+        s.iters = st->iter;
+        s.outer = 1;
+        s.relres_rec = (st->rr0 > 0.0) ? sqrt(st->rr / st->rr0) : 0.0;
+    }
+    s.reserved = 0;
+    s.relres_true = st->rel_true;
+    out[i] = s;
+}
+
+// Perturbation for posterior sampling:
+// eta_j = sqrt(tau_j) L_j xi_j + sum_f A[f,j] sqrt(W[f]) zeta_f, L_j = (kappa_j^2 + 4) - N4
+// (L_j is symmetric, so L_j^T xi = L_j xi).
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_po(const double *__restrict__ kappa,
+                                               const double *__restrict__ tau,
+                                               const double *__restrict__ A,
+                                               const double *__restrict__ W,
+                                               const double *__restrict__ xi,
+                                               const double *__restrict__ zeta,
+                                               double *__restrict__ eta, int f, int ny, int nx) {
+    const int n_pix = ny * nx;
+    const int pix = blockIdx.x * kBlock + threadIdx.x;
+    if (pix >= n_pix) return;
+    const int rhs = blockIdx.y;
+    const double *xr = xi + (size_t)rhs * K * n_pix;
+    const double *zr = zeta + (size_t)rhs * f * n_pix;
+    double *er = eta + (size_t)rhs * K * n_pix;
+    const int iy = pix / nx, ix = pix - iy * nx;
+    const int n = wrapi(iy - 1, ny) * nx + ix, s = wrapi(iy + 1, ny) * nx + ix;
+    const int w = iy * nx + wrapi(ix - 1, nx), e = iy * nx + wrapi(ix + 1, nx);
+    double acc[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const double *u = xr + (size_t)j * n_pix;
+        const double kp = kappa[j], t = tau[j];
+        const double lu = (kp * kp + 4.0) * u[pix] - ((u[n] + u[s]) + (u[w] + u[e]));
+        acc[j] = sqrt(t) * lu;
+    }
+    for (int fi = 0; fi < f; ++fi) {
+        const double v = sqrt(W[(size_t)fi * n_pix + pix]) * zr[(size_t)fi * n_pix + pix];
+#pragma unroll
+        for (int j = 0; j < K; ++j) acc[j] += A[fi * K + j] * v;
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) er[(size_t)j * n_pix + pix] = acc[j];
+}
+
+// Gradient reductions of the adjoint (backward) pass; see sylv.h for the formulas.  One pixel
+// per thread; L_j x*_j and L_j lambda_j come from 5-point stencils on the fly.
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_grad(const double *__restrict__ coef,
+                                                 const double *__restrict__ A,
+                                                 const double *__restrict__ W,
+                                                 const double *__restrict__ Y,
+                                                 const double *__restrict__ X,
+                                                 const double *__restrict__ Lm, int f, int ny,
+                                                 int nx, double *__restrict__ dkappa,
+                                                 double *__restrict__ dtau,
+                                                 double *__restrict__ dA,
+                                                 double *__restrict__ dW,
+                                                 double *__restrict__ dY,
+                                                 double *__restrict__ partial,
+                                                 uint32_t *__restrict__ ticket) {
+    const int n_pix = ny * nx;
+    const int nblk = gridDim.x;
+    const int nv = 2 * K + f * K;
+    __shared__ double sm[2 * kMaxK + kMaxF * kMaxK][kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int pix = blockIdx.x * kBlock + threadIdx.x;
+    const bool active = pix < n_pix;
+    double xs[K], lm[K], tx[K], tl[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) { xs[j] = lm[j] = tx[j] = tl[j] = 0.0; }
+    if (active) {
+        const int iy = pix / nx, ix = pix - iy * nx;
+        const int n = wrapi(iy - 1, ny) * nx + ix, s = wrapi(iy + 1, ny) * nx + ix;
+        const int w = iy * nx + wrapi(ix - 1, nx), e = iy * nx + wrapi(ix + 1, nx);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const double kp = coef[j * kCoefStride + 5];
+            const double d = kp * kp + 4.0;
+            const double *u = X + (size_t)j * n_pix;
+            const double *v = Lm + (size_t)j * n_pix;
+            xs[j] = u[pix];
+            lm[j] = v[pix];
+            tx[j] = d * xs[j] - ((u[n] + u[s]) + (u[w] + u[e]));
+            tl[j] = d * lm[j] - ((v[n] + v[s]) + (v[w] + v[e]));
+        }
+    }
+    // dtau_j = -<L lambda, L x>, dkappa_j = -4 kappa tau <lambda, L x>
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const double kp = coef[j * kCoefStride + 5], t = coef[j * kCoefStride + 6];
+        const double a = wave_sum(-tl[j] * tx[j]);
+        const double b = wave_sum(-4.0 * kp * t * lm[j] * tx[j]);
+        if (lane == 0) { sm[j][wid] = a; sm[K + j][wid] = b; }
+    }
+    for (int fi = 0; fi < f; ++fi) {
+        double a[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) a[j] = A[fi * K + j];
+        double al = 0.0, ax = 0.0;
+#pragma unroll
+        for (int j = 0; j < K; ++j) { al += a[j] * lm[j]; ax += a[j] * xs[j]; }
+        double wv = 0.0, yv = 0.0;
+        if (active) {
+            wv = W[(size_t)fi * n_pix + pix];
+            yv = Y[(size_t)fi * n_pix + pix];
+        }
+        const double rf = yv - ax;
+        if (active) {
+            if (dW) dW[(size_t)fi * n_pix + pix] = al * rf;
+            if (dY) dY[(size_t)fi * n_pix + pix] = wv * al;
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const double g = wave_sum(wv * (rf * lm[j] - al * xs[j]));
+            if (lane == 0) sm[2 * K + fi * K + j][wid] = g;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nv; i += kBlock)
+        partial[(size_t)i * nblk + blockIdx.x] = (sm[i][0] + sm[i][1]) + (sm[i][2] + sm[i][3]);
+    __syncthreads();
+    __shared__ int last;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t t = atomicAdd(ticket, 1u);
+        last = (t == (uint32_t)(nblk - 1));
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    for (int i = threadIdx.x; i < nv; i += kBlock) {
+        double s = 0.0;
+        for (int b = 0; b < nblk; ++b) s += partial[(size_t)i * nblk + b];
+        if (i < K) {
+            if (dtau) dtau[i] = s;
+        } else if (i < 2 * K) {
+            if (dkappa) dkappa[i - K] = s;
+        } else {
+            if (dA) dA[i - 2 * K] = s;
+        }
+    }
+    if (threadIdx.x == 0) ticket[0] = 0u;
+}
+
+template <int K>
+struct KTag {
+    static constexpr int value = K;
+};
+
+template <typename F>
+hipError_t dispatch_k(int k, F &&fn) {
+    switch (k) {
+        case 1: return fn(KTag<1>{});
+        case 2: return fn(KTag<2>{});
+        case 3: return fn(KTag<3>{});
+        case 4: return fn(KTag<4>{});
+        case 5: return fn(KTag<5>{});
+        case 6: return fn(KTag<6>{});
+        case 7: return fn(KTag<7>{});
+        case 8: return fn(KTag<8>{});
+        default: return hipErrorInvalidValue;
+    }
+}
+
+inline unsigned blocks_for(long n, int per) { return (unsigned)((n + per - 1) / per); }
+
+template <typename T, int K, int MODE>
+hipError_t launch_apply_rows(int rows, dim3 grid, hipStream_t s, const Inst *table,
+                             const int *tprefix, int ninst, int phase, const void *in,
+                             void *out) {
+    const T *i = reinterpret_cast<const T *>(in);
+    T *o = reinterpret_cast<T *>(out);
+    const int nb = (int)grid.x;
+    switch (rows) {
+        case 2:
+            hipLaunchKernelGGL((k_apply<T, K, 2, MODE>), grid, dim3(kBlock), 0, s, table,
+                               tprefix, ninst, nb, phase, i, o);
+            break;
+        case 8:
+            hipLaunchKernelGGL((k_apply<T, K, 8, MODE>), grid, dim3(kBlock), 0, s, table,
+                               tprefix, ninst, nb, phase, i, o);
+            break;
+        default:
+            hipLaunchKernelGGL((k_apply<T, K, 4, MODE>), grid, dim3(kBlock), 0, s, table,
+                               tprefix, ninst, nb, phase, i, o);
+            break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// ---- launchers -------------------------------------------------------------------------------
+
+int apply_rows_valid(int rows) { return rows == 2 || rows == 4 || rows == 8; }
+
+int grad_blocks(int n_pix) { return (int)blocks_for(n_pix, kBlock); }
+int grad_nv(int k, int f) { return 2 * k + f * k; }
+
+hipError_t launch_coef(const double *kappa, const double *tau, int k, int ny, int nx,
+                       double *coef, hipStream_t s) {
+    hipLaunchKernelGGL(k_coef, dim3(1), dim3(64), 0, s, kappa, tau, k, ny, nx, coef);
+    return hipGetLastError();
+}
+
+hipError_t launch_setup(const double *W, const double *A, int f, int n_pix, const double *coef,
+                        int pc, double *M64, float *M32, double *P64, float *P32, int k,
+                        hipStream_t s) {
+    return dispatch_k(k, [&](auto tag) {
+        constexpr int K = decltype(tag)::value;
+        hipLaunchKernelGGL((k_setup<K>), dim3(blocks_for(n_pix, kBlock)), dim3(kBlock), 0, s, W,
+                           A, f, n_pix, coef, pc, M64, M32, P64, P32);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_rhs(const double *W, const double *Y, const double *A, int f, int n_pix,
+                      const double *bext, double *b, int k, hipStream_t s) {
+    return dispatch_k(k, [&](auto tag) {
+        constexpr int K = decltype(tag)::value;
+        hipLaunchKernelGGL((k_rhs<K>), dim3(blocks_for(n_pix, kBlock)), dim3(kBlock), 0, s, W,
+                           Y, A, f, n_pix, bext, b);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_apply_plain(const Inst *table0, int k, int dtype, int rows, int ny, int nx,
+                              int nrhs, const void *in, void *out, hipStream_t s) {
+    const unsigned tx = blocks_for(nx, kTileX);
+    const unsigned ty = blocks_for(ny, kWavesY * rows);
+    const dim3 grid(tx * ty, nrhs);
+    return dispatch_k(k, [&](auto tag) {
+        constexpr int K = decltype(tag)::value;
+        if (dtype == SYLV_F64)
+            return launch_apply_rows<double, K, AM_PLAIN>(rows, grid, s, table0, nullptr, 1, 0,
+                                                          in, out);
+        return launch_apply_rows<float, K, AM_PLAIN>(rows, grid, s, table0, nullptr, 1, 0, in,
+                                                     out);
+    });
+}
+
+hipError_t launch_precond_plain(const Inst *table0, int k, int dtype, int n_pix, int nrhs,
+                                const void *in, void *out, hipStream_t s) {
+    const dim3 grid(blocks_for(n_pix, kBlock), nrhs);
+    return dispatch_k(k, [&](auto tag) {
+        constexpr int K = decltype(tag)::value;
+        if (dtype == SYLV_F64)
+            hipLaunchKernelGGL((k_precond_plain<double, K>), grid, dim3(kBlock), 0, s, table0,
+                               reinterpret_cast<const double *>(in),
+                               reinterpret_cast<double *>(out));
+        else
+            hipLaunchKernelGGL((k_precond_plain<float, K>), grid, dim3(kBlock), 0, s, table0,
+                               reinterpret_cast<const float *>(in),
+                               reinterpret_cast<float *>(out));
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_resid(const InstSet &set, int k, int rows, int phase, hipStream_t s) {
+    return dispatch_k(k, [&](auto tag) {
+        constexpr int K = decltype(tag)::value;
+        return launch_apply_rows<double, K, AM_RESID>(rows, dim3(set.total_tiles), s, set.table,
+                                                      set.tprefix, set.ninst, phase, nullptr,
+                                                      nullptr);
+    });
+}
+
+hipError_t launch_cg_apply(const InstSet &set, int k, int mixed, int rows, hipStream_t s) {
+    return dispatch_k(k, [&](auto tag) {
+        constexpr int K = decltype(tag)::value;
+        if (mixed)
+            return launch_apply_rows<float, K, AM_CG>(rows, dim3(set.total_tiles), s, set.table,
+                                                      set.tprefix, set.ninst, 0, nullptr,
+                                                      nullptr);
+        return launch_apply_rows<double, K, AM_CG>(rows, dim3(set.total_tiles), s, set.table,
+                                                   set.tprefix, set.ninst, 0, nullptr, nullptr);
+    });
+}
+
+hipError_t launch_cg_update(const InstSet &set, int k, int mixed, hipStream_t s) {
+    return dispatch_k(k, [&](auto tag) {
+        constexpr int K = decltype(tag)::value;
+        const dim3 grid(set.total_chunks);
+        if (mixed)
+            hipLaunchKernelGGL((k_update<float, K>), grid, dim3(kBlock), 0, s, set.table,
+                               set.cprefix, set.ninst, (int)grid.x);
+        else
+            hipLaunchKernelGGL((k_update<double, K>), grid, dim3(kBlock), 0, s, set.table,
+                               set.cprefix, set.ninst, (int)grid.x);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_pinit(const InstSet &set, int k, int mixed, double inner_tol, int max_iter,
+                        hipStream_t s) {
+    return dispatch_k(k, [&](auto tag) {
+        constexpr int K = decltype(tag)::value;
+        const dim3 grid(set.total_chunks);
+        if (mixed)
+            hipLaunchKernelGGL((k_pinit<float, K>), grid, dim3(kBlock), 0, s, set.table,
+                               set.cprefix, set.ninst, (int)grid.x, inner_tol, max_iter);
+        else
+            hipLaunchKernelGGL((k_pinit<double, K>), grid, dim3(kBlock), 0, s, set.table,
+                               set.cprefix, set.ninst, (int)grid.x, inner_tol, max_iter);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_refine_axpy(const InstSet &set, int k, hipStream_t s) {
+    return dispatch_k(k, [&](auto tag) {
+        constexpr int K = decltype(tag)::value;
+        const dim3 grid(set.total_chunks);
+        hipLaunchKernelGGL((k_refine_axpy<K>), grid, dim3(kBlock), 0, s, set.table, set.cprefix,
+                           set.ninst, (int)grid.x);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_state_init(const InstSet &set, double tol, int max_iter, hipStream_t s) {
+    hipLaunchKernelGGL(k_state_init, dim3(blocks_for(set.ninst, 64)), dim3(64), 0, s, set.table,
+                       set.ninst, tol, max_iter);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_running(const InstSet &set, int inner, int *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_count_running, dim3(1), dim3(256), 0, s, set.table, set.ninst, inner,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats(const InstSet &set, void *stats, int mixed, hipStream_t s) {
+    hipLaunchKernelGGL(k_stats, dim3(blocks_for(set.ninst, 64)), dim3(64), 0, s, set.table,
+                       set.ninst, reinterpret_cast<sylv_pcg_stats *>(stats), mixed);
+    return hipGetLastError();
+}
+
+hipError_t launch_po(const double *kappa, const double *tau, const double *A, const double *W,
+                     const double *xi, const double *zeta, double *eta, int k, int f, int ny,
+                     int nx, int nrhs, hipStream_t s) {
+    return dispatch_k(k, [&](auto tag) {
+        constexpr int K = decltype(tag)::value;
+        const dim3 grid(blocks_for((long)ny * nx, kBlock), nrhs);
+        hipLaunchKernelGGL((k_po<K>), grid, dim3(kBlock), 0, s, kappa, tau, A, W, xi, zeta, eta,
+                           f, ny, nx);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_grad(const double *coef, const double *A, const double *W, const double *Y,
+                       const double *X, const double *Lm, int k, int f, int ny, int nx,
+                       double *dkappa, double *dtau, double *dA, double *dW, double *dY,
+                       double *partial, uint32_t *ticket, hipStream_t s) {
+    return dispatch_k(k, [&](auto tag) {
+        constexpr int K = decltype(tag)::value;
+        const dim3 grid(grad_blocks(ny * nx));
+        hipLaunchKernelGGL((k_grad<K>), grid, dim3(kBlock), 0, s, coef, A, W, Y, X, Lm, f, ny,
+                           nx, dkappa, dtau, dA, dW, dY, partial, ticket);
+        return hipGetLastError();
+    });
+}
+
+}  // namespace sylv

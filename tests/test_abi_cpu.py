@@ -1,0 +1,124 @@
+"""C-ABI library checks that need no GPU: it loads, exports every declared entry point, and its
+host-side logic (workspace sizing, argument validation, status strings) behaves."""
+import ctypes
+import os
+import subprocess
+
+import pytest
+
+import paper_2204_08057_amd as sy
+from paper_2204_08057_amd import binding as bd
+
+pytestmark = pytest.mark.skipif(not os.path.exists(bd.library_path()),
+                                reason="libsylv.so not built")
+
+FAKE = 0x100000  # never dereferenced: every call below fails validation before any HIP call
+
+
+def fake_problem(ny=32, nx=32, k=3, f=6):
+    return bd._Problem(ny, nx, k, f, FAKE, FAKE, FAKE, FAKE)
+
+
+def test_every_declared_symbol_is_exported():
+    names = sy.declared_symbols()
+    assert {"sylv_apply", "sylv_precond", "sylv_pcg_solve", "sylv_pcg_backward",
+            "sylv_workspace_bytes", "sylv_status_string"} <= set(names)
+    L = sy.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", bd.library_path()],
+                         capture_output=True, text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    assert set(names) <= exported
+
+
+def test_header_struct_sizes_match_binding():
+    # int64 x2 + int32 x2 + 4 pointers; double, int32 x2, double, int32 x4; int32 x4 + double x2
+    assert ctypes.sizeof(bd._Problem) == 56
+    assert ctypes.sizeof(bd._Opts) == 40
+    assert ctypes.sizeof(bd._Stats) == 32
+
+
+def test_workspace_bytes_grows_with_problem():
+    L = sy.lib()
+    small = L.sylv_workspace_bytes(ctypes.byref(fake_problem(32, 32)), 1, 1, None)
+    big = L.sylv_workspace_bytes(ctypes.byref(fake_problem(64, 64)), 1, 1, None)
+    assert 0 < small < big
+    o = bd._Opts(1e-8, 100, 0, 0.0, 0, 2, 0, 0)
+    solve = L.sylv_workspace_bytes(ctypes.byref(fake_problem(64, 64)), 1, 1, ctypes.byref(o))
+    assert solve > big
+    two = L.sylv_workspace_bytes(ctypes.byref(fake_problem(64, 64)), 1, 2, ctypes.byref(o))
+    assert two > solve
+    arr = (bd._Problem * 2)(fake_problem(16, 16), fake_problem(24, 40))
+    assert L.sylv_workspace_bytes(arr, 2, 3, ctypes.byref(o)) > 0
+    # per pixel and component: >= 5 float64 + 5 float32 solver vectors
+    assert solve >= 64 * 64 * 3 * (5 * 8 + 5 * 4)
+
+
+@pytest.mark.parametrize("bad", [dict(k=0), dict(k=9), dict(f=0), dict(f=17), dict(ny=0),
+                                 dict(nx=-3)])
+def test_invalid_problems_rejected(bad):
+    L = sy.lib()
+    args = dict(ny=8, nx=8, k=3, f=4)
+    args.update(bad)
+    p = fake_problem(**args)
+    assert L.sylv_workspace_bytes(ctypes.byref(p), 1, 1, None) == 0
+    rc = L.sylv_apply(ctypes.byref(p), 0, FAKE, FAKE * 2, 1, 1, FAKE, 1 << 30, None)
+    assert rc == bd.SYLV_E_INVALID
+    assert len(L.sylv_last_error()) > 0
+
+
+def test_null_pointers_and_bad_options_rejected():
+    L = sy.lib()
+    p = fake_problem()
+    p.W = None
+    assert L.sylv_apply(ctypes.byref(p), 0, FAKE, FAKE * 2, 1, 1, FAKE, 1 << 30, None) == -1
+    p = fake_problem()
+    st = FAKE
+    for opts in [bd._Opts(0.0, 10, 0, 0.0, 0, 2, 0, 0), bd._Opts(1e-8, 0, 0, 0.0, 0, 2, 0, 0),
+                 bd._Opts(1e-8, 10, 7, 0.0, 0, 2, 0, 0), bd._Opts(1e-8, 10, 0, 0.0, 0, 9, 0, 0),
+                 bd._Opts(1e-8, 10, 1, 2.0, 0, 2, 0, 0)]:
+        rc = L.sylv_pcg_solve(ctypes.byref(p), 1, 1, FAKE, None, FAKE, ctypes.byref(opts), st,
+                              FAKE, 1 << 40, None)
+        assert rc == bd.SYLV_E_INVALID, L.sylv_last_error()
+    ok = bd._Opts(1e-8, 10, 0, 0.0, 0, 2, 0, 0)
+    # neither Y nor Bextra
+    assert L.sylv_pcg_solve(ctypes.byref(p), 1, 1, None, None, FAKE, ctypes.byref(ok), st, FAKE,
+                            1 << 40, None) == bd.SYLV_E_INVALID
+    # mixed k across a batch
+    arr = (bd._Problem * 2)(fake_problem(k=3), fake_problem(k=4))
+    assert L.sylv_pcg_solve(arr, 2, 1, FAKE, None, FAKE, ctypes.byref(ok), st, FAKE, 1 << 40,
+                            None) == bd.SYLV_E_INVALID
+
+
+def test_workspace_too_small_and_misaligned():
+    L = sy.lib()
+    p = fake_problem()
+    need = L.sylv_workspace_bytes(ctypes.byref(p), 1, 1, None)
+    rc = L.sylv_apply(ctypes.byref(p), 0, FAKE, FAKE * 2, 1, 1, FAKE, need - 1, None)
+    assert rc == bd.SYLV_E_WORKSPACE
+    rc = L.sylv_apply(ctypes.byref(p), 0, FAKE, FAKE * 2, 1, 1, FAKE + 8, need, None)
+    assert rc == bd.SYLV_E_INVALID
+    ok = bd._Opts(1e-8, 10, 0, 0.0, 0, 2, 0, 0)
+    need = L.sylv_workspace_bytes(ctypes.byref(p), 1, 1, ctypes.byref(ok))
+    rc = L.sylv_pcg_solve(ctypes.byref(p), 1, 1, FAKE, None, FAKE, ctypes.byref(ok), FAKE, FAKE,
+                          need - 256, None)
+    assert rc == bd.SYLV_E_WORKSPACE
+
+
+def test_status_strings():
+    for code in (0, 1, 2, 3, 4, -1, -2, -3):
+        assert sy.status_string(code) != "unknown code"
+    assert sy.status_string(12345) == "unknown code"
+
+
+def test_binding_refuses_host_tensors():
+    torch = pytest.importorskip("torch")
+    import numpy as np
+    from workloads import make_problem
+    prob = make_problem(4, 4, 2, 3, seed=1)
+    dp = bd.DeviceProblem(4, 4, torch.tensor(prob.kappa), torch.tensor(prob.tau),
+                          torch.tensor(prob.A), torch.tensor(prob.W))
+    with pytest.raises(ValueError):
+        dp.c_struct()
+    del np

@@ -1,0 +1,327 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the same seeded inputs.
+
+Tolerances (relative, float64 unless stated):
+  operator apply / preconditioner / right-hand side / perturbation: 1e-13 of the output norm
+    (the same sums in a different order; each output is a 13-term stencil plus a k-term mixing
+    sum, so rounding differences stay at a few ulps of the largest term);
+  float32 apply: 2e-6 of the output norm (float32 unit roundoff 6e-8 times the stencil's
+    coefficient sum ~80 tau relative to the operator's size);
+  solves: ||x - x*|| / ||x*|| <= 1e-8 (float64 PCG) and <= 1e-7 (mixed precision), run with a
+    residual tolerance small enough that cond(G) * tol stays below those bounds;
+  gradients: 1e-7 relative per quantity.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_2204_08057_amd as sy  # noqa: E402
+from oracle import grad as og  # noqa: E402
+from oracle import operator as op  # noqa: E402
+from oracle import pcg as opcg  # noqa: E402
+from oracle import po as opo  # noqa: E402
+from oracle import solve as osv  # noqa: E402
+from workloads import make_problem, po_draws, random_maps, workload  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def say(*a):
+    print("[gpu]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+SHAPES = [
+    (1, 1, 1, 1), (1, 5, 2, 3), (2, 2, 3, 4), (3, 7, 3, 5), (5, 5, 4, 9), (4, 64, 2, 2),
+    (17, 70, 3, 6), (64, 64, 3, 6), (33, 129, 8, 16), (130, 67, 5, 7), (16, 16, 6, 9),
+    (9, 11, 7, 3),
+]
+
+
+@pytest.mark.parametrize("ny,nx,k,f", SHAPES)
+def test_apply_f64(ny, nx, k, f):
+    say("apply f64", ny, nx, k, f)
+    prob = make_problem(ny, nx, k, f, seed=100 + ny * 7 + nx, noise="hetero", mask_frac=0.1)
+    X = random_maps(prob, 5)
+    dp = sy.DeviceProblem.from_numpy(prob)
+    Y = host(sy.apply(dp, dev(X)))
+    ref = op.apply(prob, X)
+    assert rel(Y, ref) < 1e-13
+
+
+@pytest.mark.parametrize("ny,nx,k,f", [(5, 5, 4, 9), (64, 64, 3, 6), (33, 129, 8, 16)])
+def test_apply_f32(ny, nx, k, f):
+    say("apply f32", ny, nx, k, f)
+    prob = make_problem(ny, nx, k, f, seed=200 + ny, noise="hetero")
+    X = random_maps(prob, 6)
+    dp = sy.DeviceProblem.from_numpy(prob)
+    Y = host(sy.apply(dp, dev(X, torch.float32)))
+    ref = op.apply(prob, X.astype(np.float32).astype(np.float64))
+    assert rel(Y, ref) < 2e-6
+
+
+def test_apply_several_rhs_prepared():
+    say("apply nrhs=3 prepared")
+    prob = make_problem(40, 72, 3, 6, seed=300)
+    X = random_maps(prob, 7, nrhs=3)
+    dp = sy.DeviceProblem.from_numpy(prob)
+    ws = sy.binding.prepare(dp, sy.SYLV_PC_NONE)
+    Y1 = host(sy.apply(dp, dev(X), ws=ws, prepared=True))
+    Y2 = host(sy.apply(dp, dev(X), ws=ws, prepared=True))
+    assert np.array_equal(Y1, Y2)
+    for r in range(3):
+        assert rel(Y1[r], op.apply(prob, X[r])) < 1e-13
+
+
+@pytest.mark.parametrize("kind", [sy.SYLV_PC_BLOCK, sy.SYLV_PC_JACOBI, sy.SYLV_PC_NONE])
+@pytest.mark.parametrize("ny,nx,k,f", [(1, 1, 3, 4), (2, 3, 2, 3), (24, 20, 4, 9),
+                                       (13, 9, 8, 5)])
+def test_precond(kind, ny, nx, k, f):
+    say("precond", kind, ny, nx, k, f)
+    prob = make_problem(ny, nx, k, f, seed=400 + ny, noise="hetero", mask_frac=0.2)
+    R = random_maps(prob, 8)
+    dp = sy.DeviceProblem.from_numpy(prob)
+    Z = host(sy.precond(dp, dev(R), kind))
+    name = {sy.SYLV_PC_BLOCK: "block", sy.SYLV_PC_JACOBI: "jacobi", sy.SYLV_PC_NONE: "none"}
+    Minv, _ = opcg.block_jacobi(prob, kind=name[kind])
+    assert rel(Z, Minv(R)) < 1e-13
+
+
+@pytest.mark.parametrize("ny,nx,k,f", [(1, 3, 2, 2), (31, 45, 4, 9), (64, 64, 8, 16)])
+def test_rhs(ny, nx, k, f):
+    say("rhs", ny, nx, k, f)
+    prob = make_problem(ny, nx, k, f, seed=500 + nx, noise="hetero", mask_frac=0.1)
+    dp = sy.DeviceProblem.from_numpy(prob)
+    B = host(sy.rhs(dp, dev(prob.Y)))
+    assert rel(B, op.rhs(prob)) < 1e-14
+
+
+@pytest.mark.parametrize("ny,nx,k,f,nrhs", [(4, 5, 3, 4, 2), (37, 26, 3, 6, 3), (1, 2, 2, 2, 1)])
+def test_po_perturbation(ny, nx, k, f, nrhs):
+    say("po", ny, nx, k, f, nrhs)
+    prob = make_problem(ny, nx, k, f, seed=600 + ny, noise="hetero", mask_frac=0.1)
+    xi, zeta = po_draws(prob, nrhs, seed=601)
+    dp = sy.DeviceProblem.from_numpy(prob)
+    eta = host(sy.po_perturb(dp, dev(xi), dev(zeta)))
+    assert rel(eta, opo.perturbation(prob, xi, zeta)) < 1e-13
+
+
+# --------------------------------------------------------------------------------------- solves
+
+def _solve(prob, precision, tol, precond=sy.SYLV_PC_BLOCK, X0=None, max_iter=5000,
+           check_every=0):
+    dp = sy.DeviceProblem.from_numpy(prob)
+    opts = sy.SolveOptions(tol=tol, max_iter=max_iter, precision=precision, precond=precond,
+                           check_every=check_every)
+    X, st = sy.pcg_solve(dp, Y=dev(prob.Y), X0=None if X0 is None else dev(X0), opts=opts)
+    return host(X), st[0]
+
+
+@pytest.mark.parametrize("precision,bound", [(sy.SYLV_PREC_F64, 1e-8), (sy.SYLV_PREC_MIXED, 1e-7)])
+@pytest.mark.parametrize("ny,nx,k,f,noise,mask", [
+    (16, 16, 3, 6, "hetero", 0.0), (24, 20, 4, 9, "hetero", 0.1), (13, 29, 2, 3, "homo", 0.0),
+    (1, 1, 3, 4, "hetero", 0.0), (2, 3, 3, 5, "hetero", 0.0), (8, 70, 5, 7, "separable", 0.2),
+])
+def test_solve_dense(precision, bound, ny, nx, k, f, noise, mask):
+    say("solve dense", precision, ny, nx, k, f, noise, mask)
+    prob = make_problem(ny, nx, k, f, seed=700 + ny + nx, noise=noise, mask_frac=mask)
+    x, st = _solve(prob, precision, tol=1e-12 if precision == sy.SYLV_PREC_F64 else 1e-11)
+    assert st["status"] == 0, st
+    xs = osv.solve_dense(prob)
+    assert rel(x, xs) < bound
+    assert st["relres_true"] <= (1e-12 if precision == sy.SYLV_PREC_F64 else 1e-11) * 1.01
+    # independent check of the reported residual
+    b = op.rhs(prob)
+    assert rel(op.apply(prob, x), b) == pytest.approx(st["relres_true"], rel=1e-3, abs=1e-15)
+
+
+@pytest.mark.parametrize("precision,bound", [(sy.SYLV_PREC_F64, 1e-8), (sy.SYLV_PREC_MIXED, 1e-7)])
+def test_solve_tiny_workload_fft(precision, bound):
+    """64 x 64, k = 3, f = 6, homoscedastic: exact Fourier solution."""
+    prob = workload("tiny_64")[0]
+    say("solve tiny_64", precision)
+    x, st = _solve(prob, precision, tol=1e-12 if precision == sy.SYLV_PREC_F64 else 1e-11)
+    assert st["status"] == 0, st
+    assert rel(x, osv.solve_fft(prob)) < bound
+
+
+@pytest.mark.parametrize("precision,bound,tol", [(sy.SYLV_PREC_F64, 1e-8, 1e-11),
+                                                 (sy.SYLV_PREC_MIXED, 1e-7, 1e-10)])
+def test_solve_full_size_homoscedastic_fft(precision, bound, tol):
+    """1024 x 1024, k = 3, f = 9 with homoscedastic noise: the Fourier solve is exact at this
+    size, so the whole solution is compared."""
+    prob = make_problem(1024, 1024, 3, 9, seed=1001, noise="homo")
+    say("solve 1024^2 homo", precision)
+    x, st = _solve(prob, precision, tol=tol)
+    assert st["status"] == 0, st
+    assert rel(x, osv.solve_fft(prob)) < bound
+
+
+@pytest.mark.parametrize("precision", [sy.SYLV_PREC_F64, sy.SYLV_PREC_MIXED])
+def test_solve_full_size_heteroscedastic(precision):
+    """The 1024^2 heteroscedastic workload at its timing tolerance 1e-8: the oracle recomputes
+    the true residual of the GPU result with its own assembled operator, and single outputs of
+    the operator at sampled pixels are compared one by one."""
+    prob = workload("het_1024")[0]
+    say("solve het_1024", precision)
+    x, st = _solve(prob, precision, tol=1e-8)
+    assert st["status"] == 0, st
+    b = op.rhs(prob)
+    G = op.posterior_precision(prob)
+    res = rel(op.apply(prob, x, G=G), b)
+    assert res <= 1e-8 * 1.001
+    assert res == pytest.approx(st["relres_true"], rel=1e-3)
+    pix = np.random.default_rng(9).choice(prob.n_pix, 64, replace=False)
+    dp = sy.DeviceProblem.from_numpy(prob)
+    Yg = host(sy.apply(dp, dev(x)))
+    assert rel(Yg[:, pix], op.apply_at(prob, x, pix)) < 1e-13
+
+
+def test_solve_warm_start_and_zero_rhs():
+    prob = make_problem(20, 24, 3, 5, seed=800)
+    xs = osv.solve_dense(prob)
+    say("warm start")
+    x, st = _solve(prob, sy.SYLV_PREC_F64, 1e-12, X0=xs + 1e-3 * random_maps(prob, 1))
+    assert st["status"] == 0 and rel(x, xs) < 1e-8
+    say("zero rhs")
+    prob0 = make_problem(20, 24, 3, 5, seed=801)
+    prob0.Y[:] = 0.0
+    x0, st0 = _solve(prob0, sy.SYLV_PREC_F64, 1e-10)
+    assert st0["status"] == 0 and st0["iters"] == 0 and np.all(x0 == 0)
+
+
+def test_solve_fully_masked_uses_prior_only():
+    prob = make_problem(12, 12, 2, 3, seed=802, mask_frac=0.0)
+    prob.W[:] = 0.0
+    say("fully masked")
+    dp = sy.DeviceProblem.from_numpy(prob)
+    Bx = random_maps(prob, 3)
+    opts = sy.SolveOptions(tol=1e-12)
+    X, st = sy.pcg_solve(dp, Bextra=dev(Bx), opts=opts)
+    assert st[0]["status"] == 0
+    assert rel(host(X), osv.solve_dense(prob, b=Bx)) < 1e-8
+
+
+def test_solve_not_converged_reported():
+    prob = make_problem(32, 32, 3, 6, seed=803)
+    say("max_iter=2")
+    x, st = _solve(prob, sy.SYLV_PREC_F64, 1e-12, max_iter=2, check_every=1)
+    assert st["status"] == sy.binding.SYLV_NOT_CONVERGED
+    assert st["iters"] == 2
+
+
+def test_solve_nonfinite_reported():
+    prob = make_problem(16, 16, 3, 6, seed=804)
+    prob.W[2, 17] = np.nan
+    say("nan weight")
+    x, st = _solve(prob, sy.SYLV_PREC_F64, 1e-10)
+    assert st["status"] == sy.binding.SYLV_NONFINITE
+
+
+def test_solve_negative_tau_reported():
+    prob = make_problem(16, 16, 3, 6, seed=805, tau=np.array([1.0, -3.0, 1.0]))
+    say("negative tau")
+    x, st = _solve(prob, sy.SYLV_PREC_F64, 1e-10, precond=sy.SYLV_PC_NONE)
+    assert st["status"] in (sy.binding.SYLV_BREAKDOWN, sy.binding.SYLV_NONFINITE,
+                            sy.binding.SYLV_NOT_CONVERGED)
+
+
+def test_solve_repeatable_bitwise():
+    prob = make_problem(48, 40, 3, 6, seed=806)
+    say("repeatability")
+    x1, s1 = _solve(prob, sy.SYLV_PREC_F64, 1e-10)
+    x2, s2 = _solve(prob, sy.SYLV_PREC_F64, 1e-10)
+    assert np.array_equal(x1, x2) and s1 == s2
+    m1, _ = _solve(prob, sy.SYLV_PREC_MIXED, 1e-10)
+    m2, _ = _solve(prob, sy.SYLV_PREC_MIXED, 1e-10)
+    assert np.array_equal(m1, m2)
+
+
+@pytest.mark.parametrize("precision", [sy.SYLV_PREC_F64, sy.SYLV_PREC_MIXED])
+def test_batched_uneven_grids_with_po_rhs(precision):
+    """Several uneven grids x several perturbed right-hand sides in one call; each equals the
+    oracle's solve of its own right-hand side."""
+    probs = [make_problem(s0, s1, 3, 4, seed=900 + i, noise="hetero")
+             for i, (s0, s1) in enumerate([(16, 16), (24, 20), (9, 33)])]
+    nrhs = 3
+    say("batched", precision)
+    Ycat, Bcat, etas = [], [], []
+    for i, p in enumerate(probs):
+        xi, zeta = po_draws(p, nrhs, seed=950 + i)
+        eta = opo.perturbation(p, xi, zeta)
+        etas.append(eta)
+        Ycat.append(p.Y.ravel())
+        Bcat.append(eta.ravel())
+    dps = [sy.DeviceProblem.from_numpy(p) for p in probs]
+    opts = sy.SolveOptions(tol=1e-12 if precision == sy.SYLV_PREC_F64 else 1e-11,
+                           precision=precision)
+    X, st = sy.pcg_solve(dps, Y=dev(np.concatenate(Ycat)), Bextra=dev(np.concatenate(Bcat)),
+                         opts=opts, nrhs=nrhs)
+    X = host(X)
+    off = 0
+    bound = 1e-8 if precision == sy.SYLV_PREC_F64 else 1e-7
+    for i, p in enumerate(probs):
+        blk = X[off:off + nrhs * p.k * p.n_pix].reshape(nrhs, p.k, p.n_pix)
+        off += nrhs * p.k * p.n_pix
+        b = op.rhs(p)
+        for r in range(nrhs):
+            assert st[i * nrhs + r]["status"] == 0, st[i * nrhs + r]
+            xs = osv.solve_dense(p, b=b + etas[i][r])
+            assert rel(blk[r], xs) < bound
+
+
+# ------------------------------------------------------------------------------------- gradients
+
+@pytest.mark.parametrize("ny,nx,k,f", [(12, 10, 3, 4), (7, 5, 2, 9), (16, 16, 4, 9)])
+def test_backward_matches_oracle(ny, nx, k, f):
+    prob = make_problem(ny, nx, k, f, seed=1100 + ny, noise="hetero", mask_frac=0.1)
+    gbar = random_maps(prob, 1101)
+    say("backward", ny, nx, k, f)
+    g_ref, xs, lam_ref = og.adjoint_solution_grads(prob, gbar, return_solution=True)
+    dp = sy.DeviceProblem.from_numpy(prob)
+    lam, g, st = sy.pcg_backward(dp, dev(prob.Y), dev(xs), dev(gbar),
+                                 sy.SolveOptions(tol=1e-13))
+    assert st["status"] == 0, st
+    assert rel(host(lam), lam_ref) < 1e-9
+    for name in ("kappa", "tau", "A", "W", "Y"):
+        assert rel(host(g[name]), g_ref[name]) < 1e-8, name
+
+
+def test_autograd_function_loss_gradient():
+    """The differentiable-solve loss at 16 x 16 (k = 4, f = 9): torch autograd through
+    SylvSolve equals the oracle's total gradient."""
+    prob = make_problem(16, 16, 4, 9, seed=1200, noise="hetero")
+    xt = random_maps(prob, 1201)
+    say("autograd")
+    g_ref, _, _ = og.loss_grads(prob, xt)
+    kappa = dev(prob.kappa).requires_grad_(True)
+    tau = dev(prob.tau).requires_grad_(True)
+    A = dev(prob.A).requires_grad_(True)
+    W = dev(prob.W).requires_grad_(True)
+    Y = dev(prob.Y).requires_grad_(True)
+    X = sy.SylvSolve.apply(kappa, tau, A, W, Y, prob.ny, prob.nx, sy.SolveOptions(tol=1e-13))
+    resid = Y - A @ X
+    loss = ((X - dev(xt)) ** 2).sum() + 0.5 * (W * resid * resid).sum()
+    loss.backward()
+    for name, t in (("kappa", kappa), ("tau", tau), ("A", A), ("W", W), ("Y", Y)):
+        assert rel(host(t.grad), g_ref[name]) < 1e-7, name
