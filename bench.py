@@ -1,0 +1,237 @@
+"""Benchmark: time to a 1e-8 relative residual on the 1024 x 1024 heteroscedastic workload
+(k = 3 components, f = 9 maps), float64 PCG vs mixed precision, plus operator-apply bandwidth.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+
+One step = one complete mixed-precision solve through the C ABI: operator set-up (stencil
+coefficients, per-pixel mixing and block-Jacobi blocks), right-hand side B^T C Y, initial
+residual, float32 inner PCG runs inside float64 refinement until ||b - G x|| <= 1e-8 ||b||, and
+the statistics.  Inputs (kappa, tau, A, W, Y) are resident in HBM before timing starts.  The same
+K steps are then timed for the float64 solver.  The roofline object reports the stand-alone
+operator apply (float32, the precision of the inner runs), timed with HIP events on the stream it
+runs on.  Prints one JSON line.
+
+--mode pmc runs only a device copy of known size and the applies, for hardware-counter runs
+(rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE) that calibrate the HBM-traffic figure.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import resource
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-1e-8 rel. residual @1024² k=3 (FP64 vs mixed); operator-apply HBM GB/s"
+PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_apply_f32_het_1024.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2204_08057_amd", "csrc", "sylv_kernels.hip")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def apply_bytes_per_pixel(k: int, elem: int) -> int:
+    """Algorithmic bytes of one operator apply per pixel: read the k input maps and the
+    k(k+1)/2 packed mixing-block planes once, write the k output maps (stencil halos are reuse,
+    not extra traffic)."""
+    return (2 * k + k * (k + 1) // 2) * elem
+
+
+def timed_applies(sy, torch, dp, X, ws, reps):
+    stream = torch.cuda.current_stream()
+    Y = torch.empty_like(X)
+    for _ in range(5):
+        sy.apply(dp, X, ws=ws, prepared=True, out=Y)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        sy.apply(dp, X, ws=ws, prepared=True, out=Y)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps   # ms per launch
+
+
+def traffic_from_counters(kernel_hash: str):
+    """HBM bytes per launch of the float32 apply from the committed counter summary, if it was
+    taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+    except Exception:
+        return None
+    if d.get("kernel_source_sha") != kernel_hash:
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline(prob, tol):
+    """The oracle (plain float64 CPU PCG with the same block-Jacobi preconditioner and stopping
+    rule, including assembly of the operator) on the full workload, timed on this host."""
+    from oracle import operator as op
+    from oracle import pcg as opcg
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    t0 = time.perf_counter()
+    G = op.posterior_precision(prob)
+    b = op.rhs(prob)
+    res = opcg.pcg(prob, b=b, G=G, tol=tol, max_iter=2000, precond="block")
+    wall = time.perf_counter() - t0
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    cores = max(1, int(round(cpu / wall)))
+    return dict(value=round(wall * 1e3, 1), unit="ms", cores=cores, kind="oracle",
+                sample=f"complete oracle solve of the 1024x1024 workload to {tol:g} "
+                       f"(assembly + block-Jacobi PCG, {res['iters']} iterations, "
+                       f"relres {res['relres_true']:.2e}); host reports {os.cpu_count()} CPUs")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--apply-reps", type=int, default=200)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--mode", default="bench", choices=["bench", "pmc"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2204_08057_amd as sy
+    from workloads import WORKLOADS, workload
+
+    torch.cuda.set_device(0)
+    name = "het_1024"
+    cfg = WORKLOADS[name]
+    prob = workload(name)[0]
+    k, f, n_pix = prob.k, prob.f, prob.n_pix
+    dp = sy.DeviceProblem.from_numpy(prob)
+    Y = torch.as_tensor(prob.Y, device="cuda")
+    tol = cfg["tol"]
+    rng = np.random.default_rng(3)
+    X64 = torch.as_tensor(rng.standard_normal((k, n_pix)), device="cuda")
+    X32 = X64.to(torch.float32)
+    ws_app = sy.binding.prepare(dp, sy.SYLV_PC_NONE)
+
+    if args.mode == "pmc":
+        nbytes = 256 << 20
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").uniform_()
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        for _ in range(3):
+            sy.apply(dp, X32, ws=ws_app, prepared=True)
+            sy.apply(dp, X64, ws=ws_app, prepared=True)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "pmc", "copy_bytes": nbytes,
+                          "apply_f32_bytes": apply_bytes_per_pixel(k, 4) * n_pix,
+                          "apply_f64_bytes": apply_bytes_per_pixel(k, 8) * n_pix,
+                          "kernel_source_sha": kernel_source_hash()}))
+        return
+
+    opts = {
+        "mixed": sy.SolveOptions(tol=tol, precision=sy.SYLV_PREC_MIXED, precond=sy.SYLV_PC_BLOCK),
+        "f64": sy.SolveOptions(tol=tol, precision=sy.SYLV_PREC_F64, precond=sy.SYLV_PC_BLOCK),
+    }
+    ws_bytes = max(sy.workspace_bytes([dp], 1, o) for o in opts.values())
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    results = {}
+    for label in ("mixed", "f64"):
+        o = opts[label]
+        for _ in range(args.warmup):
+            sy.pcg_solve(dp, Y=Y, opts=o, ws=ws, return_stats=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            X, stats_t = sy.pcg_solve(dp, Y=Y, opts=o, ws=ws, return_stats=False)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / args.steps * 1e3
+        st = sy.binding._stats_list(stats_t, 1)[0]
+        results[label] = dict(ms=ms, stats=st, X=X)
+        log(f"{label}: {ms:.3f} ms/solve  {st}")
+
+    xm = results["mixed"]["X"]
+    xd = results["f64"]["X"]
+    err = float(torch.linalg.norm(xm - xd) / torch.linalg.norm(xd))
+
+    t32 = timed_applies(sy, torch, dp, X32, ws_app, args.apply_reps)
+    t64 = timed_applies(sy, torch, dp, X64, ws_app, args.apply_reps)
+    b32 = apply_bytes_per_pixel(k, 4) * n_pix
+    b64 = apply_bytes_per_pixel(k, 8) * n_pix
+    gbs32 = b32 / (t32 * 1e-3) / 1e9
+    gbs64 = b64 / (t64 * 1e-3) / 1e9
+    log(f"apply f32 {t32 * 1e3:.2f} us {gbs32:.0f} GB/s; f64 {t64 * 1e3:.2f} us {gbs64:.0f} GB/s")
+
+    khash = kernel_source_hash()
+    traffic = traffic_from_counters(khash)
+
+    mixed_ms = results["mixed"]["ms"]
+    line = {
+        "metric": METRIC,
+        "value": round(mixed_ms, 4),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(mixed_ms, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 apply + f64 refinement",
+        "data": "synthetic",
+        "config": {"workload": name, "ny": prob.ny, "nx": prob.nx, "k": k, "f": f,
+                   "noise": "heteroscedastic, W = sigma_f^-2 * lognormal(0, 0.5)",
+                   "tol": tol, "precond": "block-Jacobi", "x0": "zeros"},
+        "fp64_ms": round(results["f64"]["ms"], 4),
+        "speedup_mixed_vs_fp64": round(results["f64"]["ms"] / mixed_ms, 3),
+        "iters_fp64": results["f64"]["stats"]["iters"],
+        "iters_mixed_inner": results["mixed"]["stats"]["iters"],
+        "outer_mixed": results["mixed"]["stats"]["outer"],
+        "relres_true_fp64": results["f64"]["stats"]["relres_true"],
+        "relres_true_mixed": results["mixed"]["stats"]["relres_true"],
+        "rel_err_mixed_vs_fp64": err,
+        "apply_f32_us": round(t32 * 1e3, 3),
+        "apply_f64_us": round(t64 * 1e3, 3),
+        "apply_f32_gbs": round(gbs32, 1),
+        "apply_f64_gbs": round(gbs64, 1),
+        "roofline": {
+            "kernel": "operator apply, float32 (k_apply<float,3,4,plain>)",
+            "bound": "hbm",
+            "achieved": round(gbs32, 1),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(gbs32 / PEAK_HBM_GBS, 4),
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": b32,
+        },
+        "kernel_source_sha": khash,
+    }
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        line["cpu_baseline"] = cpu_baseline(prob, tol)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

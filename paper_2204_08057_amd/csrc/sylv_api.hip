@@ -58,7 +58,7 @@ struct InstLayout {
 struct Layout {
     std::vector<ProbLayout> prob;
     std::vector<InstLayout> inst;
-    size_t table = 0, tprefix = 0, cprefix = 0, count = 0, gpartial = 0, gticket = 0;
+    size_t table = 0, tprefix = 0, cprefix = 0, count = 0, gpartial = 0;
     size_t total = 0;
 };
 
@@ -103,7 +103,7 @@ bool make_layout(const sylv_problem *probs, int nprob, int nrhs, bool solve, Lay
                 InstLayout &I = L.inst[(size_t)g * nrhs + r];
                 I.nred = std::max(tiles_for(ny, nx, 2), chunks_for((int)n));
                 I.st = off;      off = align_up(off + 2 * sizeof(DevState));
-                I.partial = off; off = align_up(off + sizeof(double) * 4 * I.nred);
+                I.partial = off; off = align_up(off + sizeof(double) * kNumSlots * I.nred);
                 I.b = off;   off = align_up(off + sizeof(double) * vk);
                 I.r = off;   off = align_up(off + sizeof(double) * vk);
                 I.z = off;   off = align_up(off + sizeof(double) * vk);
@@ -123,8 +123,6 @@ bool make_layout(const sylv_problem *probs, int nprob, int nrhs, bool solve, Lay
             L.gpartial = off;
             off = align_up(off + sizeof(double) * grad_nv(probs[0].k, probs[0].f) *
                                      grad_blocks(n_pix));
-            L.gticket = off;
-            off = align_up(off + sizeof(uint32_t) * 4);
         }
     }
     L.total = off;
@@ -195,20 +193,22 @@ int check_opts(const sylv_pcg_opts *o) {
 }
 
 // Enqueue `chunk`-iteration batches until no run is going; one 4-byte readback per batch.
+// Iteration `it` is apply(it) (stopping test on the residual of update(it-1), new direction,
+// q = G p) followed by update(it); a run that stops makes every later kernel of the loop a
+// no-op, and apply(max_iter) always stops it, so the loop ends.
 int run_cg_loop(const InstSet &set, int k, int mixed, int rows, int chunk, int max_iter,
                 int *dcount, hipStream_t s) {
-    int done_iters = 0;
+    int it = 0;
     for (;;) {
-        for (int c = 0; c < chunk; ++c) {
-            HIP_TRY(launch_cg_apply(set, k, mixed, rows, s));
-            HIP_TRY(launch_cg_update(set, k, mixed, s));
+        for (int c = 0; c < chunk && it <= max_iter; ++c, ++it) {
+            HIP_TRY(launch_cg_apply(set, k, mixed, rows, it, s));
+            HIP_TRY(launch_cg_update(set, k, mixed, it, s));
         }
-        done_iters += chunk;
         HIP_TRY(launch_count_running(set, mixed, dcount, s));
         int h = 0;
         HIP_TRY(hipMemcpyAsync(&h, dcount, sizeof(int), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        if (h == 0 || done_iters >= max_iter) break;
+        if (h == 0 || it > max_iter) break;
     }
     return SYLV_OK;
 }
@@ -231,7 +231,7 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
     if (rc) return rc;
     char *base = reinterpret_cast<char *>(ws);
     const int mixed = opts->precision == SYLV_PREC_MIXED;
-    const int rows = apply_rows_setting();
+    const int rows = apply_rows_for(k, apply_rows_setting());
     const int pc = opts->precond;
 
     // instance table
@@ -303,11 +303,13 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
     }
     const int chunk = opts->check_every > 0 ? opts->check_every : 16;
     HIP_TRY(launch_resid(set, k, rows, 0, s));   // r0 = b - G x0, ||b||, ||r0||
+    HIP_TRY(launch_resid_fin(set, 0, s));
     if (!mixed) {
         HIP_TRY(launch_pinit(set, k, 0, 0.0, opts->max_iter, s));
         rc = run_cg_loop(set, k, 0, rows, chunk, opts->max_iter, dcount, s);
         if (rc) return rc;
         HIP_TRY(launch_resid(set, k, rows, 1, s));   // true residual of the result
+        HIP_TRY(launch_resid_fin(set, 1, s));
     } else {
         const double inner_tol = opts->inner_tol > 0.0 ? opts->inner_tol : 1e-5;
         const int refine_max = opts->refine_max > 0 ? opts->refine_max : 8;
@@ -317,6 +319,7 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
             if (rc) return rc;
             HIP_TRY(launch_refine_axpy(set, k, s));
             HIP_TRY(launch_resid(set, k, rows, 2, s));   // float64 residual of the new x
+            HIP_TRY(launch_resid_fin(set, 2, s));
             HIP_TRY(launch_count_running(set, 0, dcount, s));
             int h = 0;
             HIP_TRY(hipMemcpyAsync(&h, dcount, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -385,8 +388,8 @@ int sylv_apply(const sylv_problem *prob, int32_t dtype, const void *X, void *Y, 
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     char *base = reinterpret_cast<char *>(ws);
     HIP_TRY(launch_apply_plain(reinterpret_cast<const Inst *>(base + L.table), prob->k, dtype,
-                               apply_rows_setting(), (int)prob->ny, (int)prob->nx, nrhs, X, Y,
-                               s));
+                               apply_rows_for(prob->k, apply_rows_setting()), (int)prob->ny,
+                               (int)prob->nx, nrhs, X, Y, s));
     return SYLV_OK;
 }
 
@@ -452,12 +455,10 @@ int sylv_pcg_backward(const sylv_problem *prob, const double *Y, const double *X
     int rc = solve_impl(prob, 1, 1, nullptr, Gbar, Lambda, opts, stats, ws, ws_bytes, s, L);
     if (rc) return rc;
     char *base = reinterpret_cast<char *>(ws);
-    uint32_t *ticket = reinterpret_cast<uint32_t *>(base + L.gticket);
-    HIP_TRY(hipMemsetAsync(ticket, 0, sizeof(uint32_t), s));
     HIP_TRY(launch_grad(reinterpret_cast<const double *>(base + L.prob[0].coef), prob->A,
                         prob->W, Y, Xstar, Lambda, prob->k, prob->f, (int)prob->ny,
                         (int)prob->nx, dkappa, dtau, dA, dW, dY,
-                        reinterpret_cast<double *>(base + L.gpartial), ticket, s));
+                        reinterpret_cast<double *>(base + L.gpartial), s));
     return SYLV_OK;
 }
 

@@ -14,19 +14,21 @@ constexpr int kBlock = 256;      // threads per workgroup (4 wavefronts of 64)
 constexpr int kTileX = 64;       // apply tile width = one wavefront across x
 constexpr int kWavesY = 4;       // wavefronts stacked in y inside an apply tile
 constexpr int kChunk = 1024;     // pixels per workgroup in streaming kernels (4 per thread)
-constexpr int kNumTickets = 8;
 
-enum Ticket { T_APPLY = 0, T_UPDATE = 1, T_INIT = 2, T_RESID = 3, T_GRAD = 4 };
+// Reduction quantities in an instance's `partial` array (kNumSlots planes of `nred` doubles,
+// one value per producing workgroup).  A kernel that needs a reduced value re-reduces the
+// producer's partials itself, in a fixed order, at its start: kernel boundaries make them
+// visible without any device-wide fence, and every workgroup obtains bitwise the same scalar.
+enum Slot { SLOT_PQ = 0, SLOT_RZ = 1, SLOT_RR = 2, SLOT_RES_RR = 3, SLOT_RES_BB = 4 };
+constexpr int kNumSlots = 5;
 
-// Solver state of one conjugate-gradient run, in device memory.  All scalars of the
-// recurrence (Alg. 2: alpha, beta, <r, z>, ||r||) live here in float64 and are produced by the
-// last workgroup of each reduction, so the host never has to read them inside the loop.
+// Solver state of one conjugate-gradient run, in device memory.  The scalars of the recurrence
+// (Alg. 2: alpha, beta, <r, z>, ||r||) are formed on the device; the host only reads `done`.
+// Fields written during the loop are written by one workgroup of a kernel and read by later
+// kernels only (rho is double-buffered by iteration parity for that reason).
 struct DevState {
-    double rho;      // <r, z> of the current residual
-    double alpha;    // step length of the current iteration
-    double beta;     // direction update coefficient
-    double pq;       // <p, G p>
-    double rr;       // ||r||^2 (recursive residual)
+    double rho[2];   // <r, z> of iterations with even / odd index
+    double rr;       // ||r||^2 at the last test
     double rr0;      // ||r_0||^2
     double bb;       // ||b||^2
     double thresh;   // stop when rr <= thresh
@@ -37,11 +39,9 @@ struct DevState {
     int32_t max_iter;
     int32_t status;  // SYLV_OK / SYLV_NOT_CONVERGED / SYLV_BREAKDOWN / SYLV_NONFINITE / ...
     int32_t done;    // 1 once the run stopped; every kernel of the loop returns early then
-    int32_t first;   // 1 before the first direction: p = z instead of z + beta p
     int32_t total_iter;  // accumulated over inner runs (mixed precision)
     int32_t outer;   // refinement steps
-    int32_t pad;
-    uint32_t ticket[kNumTickets];  // arrival counters of the last-workgroup reductions
+    int32_t pad[2];
 };
 
 // One solve instance = one (problem, right-hand side) pair.  Pointers are into the caller's
@@ -73,7 +73,7 @@ struct Inst {
     float *r32, *z32, *p32[2], *q32, *d32;
     DevState *st;        // float64 run (or outer refinement state)
     DevState *st_in;     // float32 inner run
-    double *partial;     // [nslots][nred]
+    double *partial;     // [kNumSlots][nred]
 };
 
 // Launch-time view of the instances: a device table plus prefix sums that map a flat
@@ -92,6 +92,7 @@ inline int packed_size(int k) { return k * (k + 1) / 2; }
 // ---- launchers (sylv_kernels.hip) -------------------------------------------------------
 // Every launcher returns the hipError_t of its launch.
 int apply_rows_valid(int rows);
+int apply_rows_for(int k, int rows);   // rows per lane the apply kernels use for this k
 hipError_t launch_coef(const double *kappa, const double *tau, int k, int ny, int nx,
                        double *coef, hipStream_t s);
 hipError_t launch_setup(const double *W, const double *A, int f, int n_pix, const double *coef,
@@ -106,10 +107,11 @@ hipError_t launch_precond_plain(const Inst *table0, int k, int dtype, int n_pix,
 // residual r = b - G x (float64); phase 0: initial (sets ||b||, ||r0||, threshold),
 // 1: final true residual only, 2: refinement step of the mixed path
 hipError_t launch_resid(const InstSet &set, int k, int rows, int phase, hipStream_t s);
+hipError_t launch_resid_fin(const InstSet &set, int phase, hipStream_t s);
 hipError_t launch_pinit(const InstSet &set, int k, int mixed, double inner_tol, int max_iter,
                         hipStream_t s);
-hipError_t launch_cg_apply(const InstSet &set, int k, int mixed, int rows, hipStream_t s);
-hipError_t launch_cg_update(const InstSet &set, int k, int mixed, hipStream_t s);
+hipError_t launch_cg_apply(const InstSet &set, int k, int mixed, int rows, int it, hipStream_t s);
+hipError_t launch_cg_update(const InstSet &set, int k, int mixed, int it, hipStream_t s);
 hipError_t launch_refine_axpy(const InstSet &set, int k, hipStream_t s);
 hipError_t launch_state_init(const InstSet &set, double tol, int max_iter, hipStream_t s);
 hipError_t launch_count_running(const InstSet &set, int inner, int *out, hipStream_t s);
@@ -120,7 +122,7 @@ hipError_t launch_po(const double *kappa, const double *tau, const double *A, co
 hipError_t launch_grad(const double *coef, const double *A, const double *W, const double *Y,
                        const double *X, const double *Lm, int k, int f, int ny, int nx,
                        double *dkappa, double *dtau, double *dA, double *dW, double *dY,
-                       double *partial, uint32_t *ticket, hipStream_t s);
+                       double *partial, hipStream_t s);
 int grad_blocks(int n_pix);
 int grad_nv(int k, int f);
 

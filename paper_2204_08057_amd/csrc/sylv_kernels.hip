@@ -9,28 +9,38 @@
 //
 // Work decomposition:
 //  * operator apply: a workgroup owns a 64 x (4R) tile; each wavefront covers 64 consecutive
-//    pixels of a row (coalesced 256/512-byte accesses) and each lane walks R rows of one column,
-//    keeping a register window of the 13-point stencil, so every interior value is fetched
-//    from memory about 7 times per R=4 outputs instead of 13 (the rest come from the wave's
-//    neighbouring lanes through L1).  The k x k mixing is done on VALU from the packed block.
+//    pixels of a row (coalesced accesses) and each lane walks R rows of one column, keeping a
+//    register window of the 13-point stencil, so an interior value is fetched about 7 times per
+//    R=4 outputs instead of 13 (the x-neighbours hit in L1).  The k x k mixing runs on VALU from
+//    the packed block.
 //  * streaming kernels: 4 consecutive pixels per lane, 16-byte vector accesses.
 //  * reductions: shuffle tree in the wavefront, fixed-order sum of the 4 wavefronts, one
-//    partial per workgroup, and the last workgroup to arrive (atomic ticket) sums the partials
-//    in fixed order and advances the CG scalars on the device.  Results are bitwise
-//    reproducible run to run.
+//    partial per workgroup.  No device-scope fence or atomic is used (on this multi-XCD part an
+//    agent-scope release/acquire writes back and invalidates the XCD's L2): the kernel that
+//    needs the reduced value re-reduces the partials in a fixed order at its start, after the
+//    kernel boundary has made them visible.  Results are bitwise reproducible run to run.
 //  * workgroup -> tile mapping is XCD-aware: consecutive workgroup ids are dealt round-robin to
 //    the 8 XCDs, so ids are remapped to give every XCD a contiguous band of tiles, which keeps
-//    stencil halos and the shared per-pixel blocks in that XCD's L2.
+//    stencil halos and shared per-pixel blocks in that XCD's L2.
+//  * pointers read from the instance table are cast to the global address space so that
+//    memory accesses compile to global_* rather than flat_* instructions.
 
 #include "sylv_internal.h"
 #include "sylv.h"
 
 #include <math.h>
 
+#define GAS __attribute__((address_space(1)))
+
 namespace sylv {
 namespace {
 
 constexpr int kXcd = 8;
+
+template <typename T>
+__device__ __forceinline__ GAS T *gp(T *p) { return (GAS T *)p; }
+template <typename T>
+__device__ __forceinline__ const GAS T *gp(const T *p) { return (const GAS T *)p; }
 
 __device__ __forceinline__ int wrapi(int v, int n) {
     while (v < 0) v += n;
@@ -65,10 +75,11 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Block-reduce NV values (fixed order) and store one partial per quantity for this workgroup.
+// Block-reduce NV values (fixed order) and store this workgroup's partial of quantity i at
+// partial[(slot0 + i) * nred + blk].
 template <int NV>
-__device__ __forceinline__ void block_partials(double (&v)[NV], double *__restrict__ partial,
-                                               int nred, int slot) {
+__device__ __forceinline__ void block_partials(double (&v)[NV], double *partial, int nred,
+                                               int slot0, int blk) {
     __shared__ double sm[NV][kBlock / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -79,36 +90,25 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], double *__restri
     }
     __syncthreads();
     if (threadIdx.x == 0) {
+        GAS double *pp = gp(partial);
 #pragma unroll
         for (int i = 0; i < NV; ++i)
-            partial[(size_t)i * nred + slot] = (sm[i][0] + sm[i][1]) + (sm[i][2] + sm[i][3]);
+            pp[(size_t)(slot0 + i) * nred + blk] = (sm[i][0] + sm[i][1]) + (sm[i][2] + sm[i][3]);
     }
 }
 
-// Returns true in the last workgroup (of nblocks) to pass this point.  Thread 0 has written
-// the workgroup's partials before the call.
-__device__ __forceinline__ bool arrive_last(uint32_t *ticket, int nblocks) {
-    __shared__ int last;
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t t = atomicAdd(ticket, 1u);
-        last = (t == (uint32_t)(nblocks - 1));
-    }
-    __syncthreads();
-    if (last) __threadfence();
-    return last != 0;
-}
-
-// Fixed-order sum of NV quantities over nblocks partials, result valid in thread 0.
+// Fixed-order sum over nblocks partials of quantities slot0..slot0+NV-1; every thread of the
+// workgroup receives the result.
 template <int NV>
-__device__ __forceinline__ void final_sums(const double *__restrict__ partial, int nred,
-                                           int nblocks, double (&out)[NV]) {
+__device__ __forceinline__ void consume(const double *partial, int nred, int slot0, int nblocks,
+                                        double (&out)[NV]) {
     __shared__ double sm[NV][kBlock / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const GAS double *pp = gp(partial);
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
         double s = 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += kBlock) s += partial[(size_t)i * nred + b];
+        for (int b = threadIdx.x; b < nblocks; b += kBlock) s += pp[(size_t)(slot0 + i) * nred + b];
         s = wave_sum(s);
         if (lane == 0) sm[i][wid] = s;
     }
@@ -119,50 +119,57 @@ __device__ __forceinline__ void final_sums(const double *__restrict__ partial, i
 
 __device__ __forceinline__ bool finite_d(double v) { return isfinite(v); }
 
-// ---- vector access helpers ----------------------------------------------------------------
-__device__ __forceinline__ void ld4(const double *__restrict__ p, double (&v)[4]) {
-    const double2 a = reinterpret_cast<const double2 *>(p)[0];
-    const double2 b = reinterpret_cast<const double2 *>(p)[1];
+// ---- vector access helpers (clang vector types: usable in the global address space) --------
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void ld4(const GAS double *p, double (&v)[4]) {
+    const dvec2 a = reinterpret_cast<const GAS dvec2 *>(p)[0];
+    const dvec2 b = reinterpret_cast<const GAS dvec2 *>(p)[1];
     v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
 }
-__device__ __forceinline__ void ld4(const float *__restrict__ p, float (&v)[4]) {
-    const float4 a = reinterpret_cast<const float4 *>(p)[0];
+__device__ __forceinline__ void ld4(const GAS float *p, float (&v)[4]) {
+    const fvec4 a = reinterpret_cast<const GAS fvec4 *>(p)[0];
     v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
 }
-__device__ __forceinline__ void st4(double *__restrict__ p, const double (&v)[4]) {
-    reinterpret_cast<double2 *>(p)[0] = make_double2(v[0], v[1]);
-    reinterpret_cast<double2 *>(p)[1] = make_double2(v[2], v[3]);
+__device__ __forceinline__ void st4(GAS double *p, const double (&v)[4]) {
+    dvec2 a, b;
+    a.x = v[0]; a.y = v[1]; b.x = v[2]; b.y = v[3];
+    reinterpret_cast<GAS dvec2 *>(p)[0] = a;
+    reinterpret_cast<GAS dvec2 *>(p)[1] = b;
 }
-__device__ __forceinline__ void st4(float *__restrict__ p, const float (&v)[4]) {
-    reinterpret_cast<float4 *>(p)[0] = make_float4(v[0], v[1], v[2], v[3]);
+__device__ __forceinline__ void st4(GAS float *p, const float (&v)[4]) {
+    fvec4 a;
+    a.x = v[0]; a.y = v[1]; a.z = v[2]; a.w = v[3];
+    reinterpret_cast<GAS fvec4 *>(p)[0] = a;
 }
 
-// Field selectors by precision.
+// Field selectors by precision (all return global-address-space pointers).
 template <typename T> struct Sel;
 template <> struct Sel<double> {
-    static __device__ __forceinline__ const double *M(const Inst &I) { return I.M64; }
-    static __device__ __forceinline__ const double *P(const Inst &I) { return I.P64; }
-    static __device__ __forceinline__ double *x(const Inst &I) { return I.x; }
-    static __device__ __forceinline__ double *r(const Inst &I) { return I.r; }
-    static __device__ __forceinline__ double *z(const Inst &I) { return I.z; }
-    static __device__ __forceinline__ double *p(const Inst &I, int i) { return I.p[i & 1]; }
-    static __device__ __forceinline__ double *q(const Inst &I) { return I.q; }
+    static __device__ __forceinline__ const GAS double *M(const Inst &I) { return gp(I.M64); }
+    static __device__ __forceinline__ const GAS double *P(const Inst &I) { return gp(I.P64); }
+    static __device__ __forceinline__ GAS double *x(const Inst &I) { return gp(I.x); }
+    static __device__ __forceinline__ GAS double *r(const Inst &I) { return gp(I.r); }
+    static __device__ __forceinline__ GAS double *z(const Inst &I) { return gp(I.z); }
+    static __device__ __forceinline__ GAS double *p(const Inst &I, int i) { return gp(I.p[i & 1]); }
+    static __device__ __forceinline__ GAS double *q(const Inst &I) { return gp(I.q); }
     static __device__ __forceinline__ DevState *st(const Inst &I) { return I.st; }
 };
 template <> struct Sel<float> {
-    static __device__ __forceinline__ const float *M(const Inst &I) { return I.M32; }
-    static __device__ __forceinline__ const float *P(const Inst &I) { return I.P32; }
-    static __device__ __forceinline__ float *x(const Inst &I) { return I.d32; }
-    static __device__ __forceinline__ float *r(const Inst &I) { return I.r32; }
-    static __device__ __forceinline__ float *z(const Inst &I) { return I.z32; }
-    static __device__ __forceinline__ float *p(const Inst &I, int i) { return I.p32[i & 1]; }
-    static __device__ __forceinline__ float *q(const Inst &I) { return I.q32; }
+    static __device__ __forceinline__ const GAS float *M(const Inst &I) { return gp(I.M32); }
+    static __device__ __forceinline__ const GAS float *P(const Inst &I) { return gp(I.P32); }
+    static __device__ __forceinline__ GAS float *x(const Inst &I) { return gp(I.d32); }
+    static __device__ __forceinline__ GAS float *r(const Inst &I) { return gp(I.r32); }
+    static __device__ __forceinline__ GAS float *z(const Inst &I) { return gp(I.z32); }
+    static __device__ __forceinline__ GAS float *p(const Inst &I, int i) { return gp(I.p32[i & 1]); }
+    static __device__ __forceinline__ GAS float *q(const Inst &I) { return gp(I.q32); }
     static __device__ __forceinline__ DevState *st(const Inst &I) { return I.st_in; }
 };
 
 // z = Pinv r at one pixel for the three preconditioner kinds; P planes are read at `pix`.
 template <typename T, int K>
-__device__ __forceinline__ void precond_pixel(int pc, const T *__restrict__ P, int n_pix, int pix,
+__device__ __forceinline__ void precond_pixel(int pc, const GAS T *P, int n_pix, int pix,
                                               const T (&r)[K], T (&z)[K]) {
     if (pc == SYLV_PC_BLOCK) {
         constexpr int MK = K * (K + 1) / 2;
@@ -186,7 +193,7 @@ __device__ __forceinline__ void precond_pixel(int pc, const T *__restrict__ P, i
 }
 
 template <typename T, int K>
-__device__ __forceinline__ void precond_vec4(int pc, const T *__restrict__ P, int n_pix, int p0,
+__device__ __forceinline__ void precond_vec4(int pc, const GAS T *P, int n_pix, int p0,
                                              const T (&r)[K][4], T (&z)[K][4]) {
     if (pc == SYLV_PC_BLOCK) {
         constexpr int MK = K * (K + 1) / 2;
@@ -246,7 +253,8 @@ __global__ void k_coef(const double *__restrict__ kappa, const double *__restric
 
 // Per-pixel mixing block M_p = sum_f W[f,p] a_f a_f^T (the block map N (M A^T) T A of
 // Section 3.1 done pixel by pixel) and the preconditioner: block-Jacobi inverts
-// diag_j(Q_j diagonal) + M_p by a k x k Cholesky factorisation in float64.
+// diag_j(Q_j diagonal) + M_p by a k x k Cholesky factorisation in float64.  A block that is not
+// positive definite (negative tau, say) gets NaN entries so the solve reports it.
 template <int K>
 __global__ __launch_bounds__(kBlock) void k_setup(const double *__restrict__ W,
                                                   const double *__restrict__ A, int f, int n_pix,
@@ -366,15 +374,17 @@ __global__ __launch_bounds__(kBlock) void k_rhs(const double *__restrict__ W,
 // ---------------------------------------------------------------------------------------------
 // Operator apply G(u) = sum_j Q_j u_j + M_p u_p, fused variants:
 //   AM_PLAIN : out = G(in)                                       (stand-alone apply)
-//   AM_CG    : u = z + beta p (u = z at the first iteration), p <- u, q = G(u),
-//              <u, q> -> alpha = rho / <p, q>                   (Alg. 2: q = G p, alpha)
-//   AM_RESID : r = b - G(x), ||r||^2, ||b||^2                    (initial / true residual)
+//   AM_CG    : iteration `it` of Alg. 2 with preconditioner.  First the stopping test on the
+//              residual left by the previous update (its <r,z> and ||r||^2 partials), then
+//              beta = rho_it / rho_(it-1), u = z + beta p_old (u = z at it = 0), p_new <- u,
+//              q = G(u) and the <p, q> partials.
+//   AM_RESID : r = b - G(x) and the ||r||^2, ||b||^2 partials   (initial / true residual)
 enum ApplyMode { AM_PLAIN = 0, AM_CG = 1, AM_RESID = 2 };
 
 template <typename T, int K, int R, int MODE>
 __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
                                                   const int *__restrict__ tprefix, int ninst,
-                                                  int nb, int phase,
+                                                  int nb, int it,
                                                   const T *__restrict__ ext_in,
                                                   T *__restrict__ ext_out) {
     constexpr int MK = K * (K + 1) / 2;
@@ -382,32 +392,57 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
     const int ii = (MODE == AM_PLAIN) ? 0 : find_inst(tprefix, ninst, L);
     const Inst &I = tab[ii];
     const int tile = (MODE == AM_PLAIN) ? L : L - tprefix[ii];
-    DevState *st = (MODE == AM_CG) ? Sel<T>::st(I) : I.st;
-    if (MODE == AM_CG) {
-        if (st->done) return;
-    }
     const int nx = I.nx, ny = I.ny, n_pix = I.n_pix;
+
+    const GAS T *u0;            // field (or previous direction when fusing)
+    const GAS T *u1 = nullptr;  // preconditioned residual z when fusing
+    T beta = 0;
+    if constexpr (MODE == AM_PLAIN) {
+        u0 = gp(ext_in) + (size_t)blockIdx.y * K * n_pix;
+    } else if constexpr (MODE == AM_CG) {
+        DevState *st = Sel<T>::st(I);
+        if (st->done) return;
+        double s[2];
+        consume<2>(I.partial, I.nred, SLOT_RZ, I.nchunks, s);
+        const double rz = s[0], rr = s[1];
+        double thresh;
+        if (it == 0) thresh = st->tol * st->tol * rr;
+        else thresh = st->thresh;
+        int status = -1;
+        if (!finite_d(rz) || !finite_d(rr)) status = SYLV_NONFINITE;
+        else if (rr <= thresh) status = SYLV_OK;
+        else if (!(rz > 0.0)) status = SYLV_BREAKDOWN;
+        else if (it >= st->max_iter) status = SYLV_NOT_CONVERGED;
+        if (tile == 0 && threadIdx.x == 0) {
+            st->iter = it;
+            st->rr = rr;
+            st->rho[it & 1] = rz;
+            if (it == 0) { st->rr0 = rr; st->thresh = thresh; }
+            if (status >= 0) {
+                st->status = status;
+                st->done = 1;
+                st->total_iter += it;
+            }
+        }
+        if (status >= 0) return;
+        u1 = Sel<T>::z(I);
+        if (it == 0) {
+            // first direction: p = z; alias p_old to z with beta = 0 so that no uninitialised
+            // value is ever read.
+            u0 = u1;
+        } else {
+            u0 = Sel<T>::p(I, it);
+            beta = (T)(rz / st->rho[(it - 1) & 1]);
+        }
+    } else {
+        u0 = (const GAS T *)gp(I.x);
+    }
+
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const int tile_x = tile % I.tiles_x, tile_y = tile / I.tiles_x;
     const int ix = tile_x * kTileX + tx;
     const int iy0 = (tile_y * kWavesY + ty) * R;
     const bool active = (ix < nx) && (iy0 < ny);
-
-    const T *u0;           // field (or previous direction when fusing)
-    const T *u1 = nullptr; // preconditioned residual z when fusing
-    T beta = 0;
-    if constexpr (MODE == AM_PLAIN) {
-        u0 = ext_in + (size_t)blockIdx.y * K * n_pix;
-    } else if constexpr (MODE == AM_CG) {
-        u1 = Sel<T>::z(I);
-        // first direction: p = z; alias p_old to z with beta = 0 so that no uninitialised
-        // value is ever read.
-        const bool first = st->first != 0;
-        u0 = first ? u1 : Sel<T>::p(I, st->iter);
-        beta = first ? (T)0 : (T)st->beta;
-    } else {
-        u0 = reinterpret_cast<const T *>(I.x);
-    }
 
     T acc[K][R];
     T ctr[K][R];
@@ -422,8 +457,8 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
         for (int j = 0; j < K; ++j) {
             const double *cj = I.coef + j * kCoefStride;
             const T c0 = (T)cj[0], c1 = (T)cj[1], cd = (T)cj[2], c2 = (T)cj[3];
-            const T *a = u0 + (size_t)j * n_pix;
-            const T *zz = (MODE == AM_CG) ? (u1 + (size_t)j * n_pix) : nullptr;
+            const GAS T *a = u0 + (size_t)j * n_pix;
+            const GAS T *zz = (MODE == AM_CG) ? (u1 + (size_t)j * n_pix) : nullptr;
             auto ld = [&](int off) -> T {
                 if constexpr (MODE == AM_CG) return zz[off] + beta * a[off];
                 else return a[off];
@@ -450,7 +485,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
                 ctr[j][t] = cc[t + 2];
             }
         }
-        const T *M = Sel<T>::M(I);
+        const GAS T *M = Sel<T>::M(I);
 #pragma unroll
         for (int t = 0; t < R; ++t) {
             if (iy0 + t < ny) {
@@ -466,12 +501,12 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
                     acc[j][t] = s;
                 }
                 if constexpr (MODE == AM_PLAIN) {
-                    T *o = ext_out + (size_t)blockIdx.y * K * n_pix;
+                    GAS T *o = gp(ext_out) + (size_t)blockIdx.y * K * n_pix;
 #pragma unroll
                     for (int j = 0; j < K; ++j) o[(size_t)j * n_pix + pix] = acc[j][t];
                 } else if constexpr (MODE == AM_CG) {
-                    T *pp = Sel<T>::p(I, st->iter + 1);
-                    T *qq = Sel<T>::q(I);
+                    GAS T *pp = Sel<T>::p(I, it + 1);
+                    GAS T *qq = Sel<T>::q(I);
 #pragma unroll
                     for (int j = 0; j < K; ++j) {
                         pp[(size_t)j * n_pix + pix] = ctr[j][t];
@@ -479,11 +514,13 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
                         d0 += (double)ctr[j][t] * (double)acc[j][t];
                     }
                 } else {
+                    const GAS double *bb = gp(I.b);
+                    GAS double *rr = gp(I.r);
 #pragma unroll
                     for (int j = 0; j < K; ++j) {
-                        const double bv = I.b[(size_t)j * n_pix + pix];
+                        const double bv = bb[(size_t)j * n_pix + pix];
                         const double rv = bv - (double)acc[j][t];
-                        I.r[(size_t)j * n_pix + pix] = rv;
+                        rr[(size_t)j * n_pix + pix] = rv;
                         d0 += rv * rv;
                         d1 += bv * bv;
                     }
@@ -493,69 +530,62 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
     }
     if constexpr (MODE == AM_CG) {
         double v[1] = {d0};
-        block_partials<1>(v, I.partial, I.nred, tile);
-        if (arrive_last(&st->ticket[T_APPLY], I.ntiles)) {
-            double s[1];
-            final_sums<1>(I.partial, I.nred, I.ntiles, s);
-            if (threadIdx.x == 0) {
-                const double pq = s[0];
-                st->pq = pq;
-                if (!finite_d(pq)) {
-                    st->status = SYLV_NONFINITE; st->done = 1;
-                } else if (!(pq > 0.0)) {
-                    st->status = SYLV_BREAKDOWN; st->done = 1;
-                } else {
-                    st->alpha = st->rho / pq;
-                }
-                st->ticket[T_APPLY] = 0u;
-            }
-        }
+        block_partials<1>(v, I.partial, I.nred, SLOT_PQ, tile);
     } else if constexpr (MODE == AM_RESID) {
         double v[2] = {d0, d1};
-        block_partials<2>(v, I.partial, I.nred, tile);
-        if (arrive_last(&st->ticket[T_RESID], I.ntiles)) {
-            double s[2];
-            final_sums<2>(I.partial, I.nred, I.ntiles, s);
-            if (threadIdx.x == 0) {
-                const double rr = s[0];
-                if (phase == 0) {
-                    st->bb = s[1];
-                    st->rr0 = rr;
-                    st->rr = rr;
-                    st->rr_prev = rr;
-                    st->thresh = st->tol * st->tol * rr;
-                    if (!finite_d(rr)) { st->status = SYLV_NONFINITE; st->done = 1; }
-                    else if (rr == 0.0) { st->status = SYLV_OK; st->done = 1; }
-                } else if (phase == 2) {
-                    // refinement step of the mixed path: converged / stagnated / not finite
-                    st->rr = rr;
-                    st->outer += 1;
-                    if (!finite_d(rr)) {
-                        st->status = SYLV_NONFINITE; st->done = 1;
-                    } else if (rr <= st->thresh) {
-                        st->status = SYLV_OK; st->done = 1;
-                    } else if (rr > 0.25 * st->rr_prev) {
-                        st->status = SYLV_STAGNATED; st->done = 1;
-                    }
-                    st->rr_prev = rr;
-                }
-                const double bb = st->bb;
-                st->rel_true = (bb > 0.0) ? sqrt(rr / bb) : sqrt(rr);
-                st->ticket[T_RESID] = 0u;
-            }
-        }
+        block_partials<2>(v, I.partial, I.nred, SLOT_RES_RR, tile);
     }
 }
 
+// Reduction of the residual pass (one workgroup per instance).
+//   phase 0: initial residual: ||b||^2, ||r0||^2, threshold tol^2 ||r0||^2
+//   phase 1: true residual of the result (relres_true only)
+//   phase 2: refinement step of the mixed path: converged / stagnated / failed inner run
+__global__ __launch_bounds__(kBlock) void k_resid_fin(const Inst *__restrict__ tab, int phase) {
+    const Inst &I = tab[blockIdx.x];
+    DevState *st = I.st;
+    if (phase == 2 && st->done) return;
+    double s[2];
+    consume<2>(I.partial, I.nred, SLOT_RES_RR, I.ntiles, s);
+    if (threadIdx.x != 0) return;
+    const double rr = s[0];
+    if (phase == 0) {
+        st->bb = s[1];
+        st->rr0 = rr;
+        st->rr = rr;
+        st->rr_prev = rr;
+        st->thresh = st->tol * st->tol * rr;
+        if (!finite_d(rr) || !finite_d(s[1])) { st->status = SYLV_NONFINITE; st->done = 1; }
+        else if (rr == 0.0) { st->status = SYLV_OK; st->done = 1; }
+    } else if (phase == 2) {
+        const int inner = I.st_in->status;
+        st->rr = rr;
+        st->outer += 1;
+        if (!finite_d(rr)) {
+            st->status = SYLV_NONFINITE; st->done = 1;
+        } else if (rr <= st->thresh) {
+            st->status = SYLV_OK; st->done = 1;
+        } else if (inner == SYLV_NONFINITE || inner == SYLV_BREAKDOWN) {
+            st->status = inner; st->done = 1;
+        } else if (rr > 0.25 * st->rr_prev) {
+            st->status = SYLV_STAGNATED; st->done = 1;
+        }
+        st->rr_prev = rr;
+    }
+    const double bb = st->bb;
+    st->rel_true = (bb > 0.0) ? sqrt(rr / bb) : sqrt(rr);
+}
+
 // ---------------------------------------------------------------------------------------------
-// CG vector update of Alg. 2 with the preconditioner fused in:
-//   x += alpha p, r -= alpha q, z = Pinv r, <r, z>, ||r||^2  -> beta, stopping test.
+// CG vector update of Alg. 2 (iteration `it`) with the preconditioner fused in:
+//   alpha = rho / <p, q> (from the apply's partials), x += alpha p, r -= alpha q, z = Pinv r,
+//   and the <r, z>, ||r||^2 partials for the next stopping test and beta.
 // T = double: the float64 run (x = solution).  T = float: an inner run of the mixed path
 // (x = d32, the correction).
 template <typename T, int K>
 __global__ __launch_bounds__(kBlock) void k_update(const Inst *__restrict__ tab,
                                                    const int *__restrict__ cprefix, int ninst,
-                                                   int nb) {
+                                                   int nb, int it) {
     const int L = xcd_remap(blockIdx.x, nb);
     const int ii = find_inst(cprefix, ninst, L);
     const Inst &I = tab[ii];
@@ -563,15 +593,29 @@ __global__ __launch_bounds__(kBlock) void k_update(const Inst *__restrict__ tab,
     DevState *st = Sel<T>::st(I);
     if (st->done) return;
     const int n_pix = I.n_pix;
-    const T alpha = (T)st->alpha;
-    T *x = Sel<T>::x(I);
-    T *r = Sel<T>::r(I);
-    T *z = Sel<T>::z(I);
-    const T *p = Sel<T>::p(I, st->iter + 1);   // direction written by this iteration's apply
-    const T *q = Sel<T>::q(I);
-    const T *P = Sel<T>::P(I);
+    GAS T *x = Sel<T>::x(I);
+    GAS T *r = Sel<T>::r(I);
+    GAS T *z = Sel<T>::z(I);
+    const GAS T *p = Sel<T>::p(I, it + 1);   // direction written by this iteration's apply
+    const GAS T *q = Sel<T>::q(I);
+    const GAS T *P = Sel<T>::P(I);
     const int pc = I.pc;
     const int p0 = chunk * kChunk + threadIdx.x * 4;
+    double s[1];
+    consume<1>(I.partial, I.nred, SLOT_PQ, I.ntiles, s);
+    const double pq = s[0];
+    int status = -1;
+    if (!finite_d(pq)) status = SYLV_NONFINITE;
+    else if (!(pq > 0.0)) status = SYLV_BREAKDOWN;
+    if (status >= 0) {
+        if (chunk == 0 && threadIdx.x == 0) {
+            st->status = status;
+            st->done = 1;
+            st->total_iter += it;
+        }
+        return;
+    }
+    const T alpha = (T)(st->rho[it & 1] / pq);
     double rz = 0.0, rr = 0.0;
     if (p0 < n_pix) {
         if (I.vec4 && p0 + 4 <= n_pix) {
@@ -621,38 +665,16 @@ __global__ __launch_bounds__(kBlock) void k_update(const Inst *__restrict__ tab,
         }
     }
     double v[2] = {rz, rr};
-    block_partials<2>(v, I.partial, I.nred, chunk);
-    if (arrive_last(&st->ticket[T_UPDATE], I.nchunks)) {
-        double s[2];
-        final_sums<2>(I.partial, I.nred, I.nchunks, s);
-        if (threadIdx.x == 0) {
-            const double rho_new = s[0], rrn = s[1];
-            st->rr = rrn;
-            st->iter += 1;
-            st->total_iter += 1;
-            st->first = 0;
-            if (!finite_d(rho_new) || !finite_d(rrn)) {
-                st->status = SYLV_NONFINITE; st->done = 1;
-            } else if (rrn <= st->thresh) {
-                st->status = SYLV_OK; st->done = 1;
-            } else if (!(rho_new > 0.0)) {
-                st->status = SYLV_BREAKDOWN; st->done = 1;
-            } else if (st->iter >= st->max_iter) {
-                st->status = SYLV_NOT_CONVERGED; st->done = 1;
-            }
-            st->beta = rho_new / st->rho;
-            st->rho = rho_new;
-            st->ticket[T_UPDATE] = 0u;
-        }
-    }
+    block_partials<2>(v, I.partial, I.nred, SLOT_RZ, chunk);
 }
 
-// Start of a CG run: z0 = Pinv r0, rho0 = <r0, z0>, ||r0||^2.
+// Start of a CG run: z0 = Pinv r0 and the <r0, z0>, ||r0||^2 partials (the stopping test and
+// threshold are taken by the first apply).
 // T = double: r is the float64 residual of the float64 run.
-// T = float : start of an inner run of the mixed path; the float64 outer residual I.r is
-//             rounded to float32 (r32), the correction d32 is zeroed, and the inner stopping
-//             threshold asks for the reduction that brings the outer residual to tolerance
-//             (with a safety factor), but never less than `inner_tol`.
+// T = float : start of an inner run of the mixed path: the float64 outer residual I.r is
+//             rounded to float32 (r32), the correction d32 is zeroed, and the inner tolerance
+//             asks for the reduction that brings the outer residual to tolerance (with a 0.3
+//             safety factor), but never less than `inner_tol` nor more than 0.1.
 template <typename T, int K>
 __global__ __launch_bounds__(kBlock) void k_pinit(const Inst *__restrict__ tab,
                                                   const int *__restrict__ cprefix, int ninst,
@@ -662,17 +684,28 @@ __global__ __launch_bounds__(kBlock) void k_pinit(const Inst *__restrict__ tab,
     const Inst &I = tab[ii];
     const int chunk = L - cprefix[ii];
     DevState *st = Sel<T>::st(I);
-    if constexpr (sizeof(T) == 4) {
-        if (I.st->done) {   // outer refinement already finished for this instance
+    const DevState *outer = I.st;
+    if (outer->done) {
+        if constexpr (sizeof(T) == 4) {
             if (chunk == 0 && threadIdx.x == 0) { st->done = 1; st->status = SYLV_OK; }
-            return;
+        }
+        return;
+    }
+    if (chunk == 0 && threadIdx.x == 0) {
+        st->iter = 0;
+        st->max_iter = max_iter;
+        if constexpr (sizeof(T) == 4) {
+            st->done = 0;
+            st->status = SYLV_OK;
+            const double need = 0.3 * sqrt(outer->thresh / fmax(outer->rr, 1e-300));
+            st->tol = fmin(0.1, fmax(inner_tol, need));
         }
     }
     const int n_pix = I.n_pix;
-    const double *r64 = I.r;
-    T *rr_out = Sel<T>::r(I);
-    T *z = Sel<T>::z(I);
-    const T *P = Sel<T>::P(I);
+    const GAS double *r64 = gp(I.r);
+    GAS T *rr_out = Sel<T>::r(I);
+    GAS T *z = Sel<T>::z(I);
+    const GAS T *P = Sel<T>::P(I);
     const int pc = I.pc;
     const int p0 = chunk * kChunk + threadIdx.x * 4;
     double rz = 0.0, rr = 0.0;
@@ -685,7 +718,7 @@ __global__ __launch_bounds__(kBlock) void k_pinit(const Inst *__restrict__ tab,
             rv[j] = (T)r64[o];
             if constexpr (sizeof(T) == 4) {
                 rr_out[o] = rv[j];
-                I.d32[o] = 0.0f;
+                gp(I.d32)[o] = 0.0f;
             }
         }
         precond_pixel<T, K>(pc, P, n_pix, pix, rv, zv);
@@ -697,47 +730,7 @@ __global__ __launch_bounds__(kBlock) void k_pinit(const Inst *__restrict__ tab,
         }
     }
     double v[2] = {rz, rr};
-    block_partials<2>(v, I.partial, I.nred, chunk);
-    if (arrive_last(&st->ticket[T_INIT], I.nchunks)) {
-        double s[2];
-        final_sums<2>(I.partial, I.nred, I.nchunks, s);
-        if (threadIdx.x == 0) {
-            st->rho = s[0];
-            st->rr0 = s[1];
-            st->rr = s[1];
-            st->beta = 0.0;
-            st->iter = 0;
-            st->first = 1;
-            st->max_iter = max_iter;
-            st->status = SYLV_OK;
-            st->done = 0;
-            double tol = st->tol;
-            if constexpr (sizeof(T) == 4) {
-                // relative reduction needed by the outer residual, with a factor 0.3 margin
-                const double need = 0.3 * sqrt(I.st->thresh / fmax(I.st->rr, 1e-300));
-                tol = fmin(0.1, fmax(inner_tol, need));
-                st->tol = tol;
-            }
-            st->thresh = tol * tol * s[1];
-            if (!finite_d(s[0]) || !finite_d(s[1])) {
-                st->status = SYLV_NONFINITE; st->done = 1;
-            } else if (s[1] <= st->thresh || s[1] == 0.0) {
-                st->done = 1;
-            } else if (!(s[0] > 0.0)) {
-                st->status = SYLV_BREAKDOWN; st->done = 1;
-            }
-            if constexpr (sizeof(T) == 8) {
-                // the float64 run's initial-residual state also carries the final result
-                if (st->status != SYLV_OK) I.st->done = 1;
-            } else {
-                if (st->status != SYLV_OK) {
-                    I.st->status = st->status;
-                    I.st->done = 1;
-                }
-            }
-            st->ticket[T_INIT] = 0u;
-        }
-    }
+    block_partials<2>(v, I.partial, I.nred, SLOT_RZ, chunk);
 }
 
 // Mixed path: x += d (float32 correction promoted to float64), for instances still refining.
@@ -749,15 +742,18 @@ __global__ __launch_bounds__(kBlock) void k_refine_axpy(const Inst *__restrict__
     const int ii = find_inst(cprefix, ninst, L);
     const Inst &I = tab[ii];
     if (I.st->done) return;
+    const int st_in = I.st_in->status;
+    if (st_in == SYLV_NONFINITE || st_in == SYLV_BREAKDOWN) return;
     const int chunk = L - cprefix[ii];
     const int n_pix = I.n_pix;
     const int p0 = chunk * kChunk + threadIdx.x * 4;
-    if (I.st_in->status == SYLV_NONFINITE || I.st_in->status == SYLV_BREAKDOWN) return;
+    GAS double *x = gp(I.x);
+    const GAS float *d = gp(I.d32);
     for (int e = 0; e < 4 && p0 + e < n_pix; ++e) {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const size_t o = (size_t)j * n_pix + p0 + e;
-            I.x[o] += (double)I.d32[o];
+            x[o] += (double)d[o];
         }
     }
 }
@@ -788,11 +784,10 @@ __global__ void k_state_init(const Inst *__restrict__ tab, int ninst, double tol
     DevState *ss[2] = {tab[i].st, tab[i].st_in};
     for (int s = 0; s < 2; ++s) {
         DevState *st = ss[s];
-        st->rho = 0.0; st->alpha = 0.0; st->beta = 0.0; st->pq = 0.0; st->rr = 0.0;
-        st->rr0 = 0.0; st->bb = 0.0; st->thresh = 0.0; st->tol = tol; st->rel_true = 0.0;
+        st->rho[0] = 0.0; st->rho[1] = 0.0; st->rr = 0.0; st->rr0 = 0.0; st->bb = 0.0;
+        st->thresh = 0.0; st->tol = tol; st->rel_true = 0.0; st->rr_prev = 0.0;
         st->iter = 0; st->max_iter = max_iter; st->status = SYLV_OK; st->done = 0;
-        st->first = 1; st->total_iter = 0; st->outer = 0; st->pad = 0;
-        for (int t = 0; t < kNumTickets; ++t) st->ticket[t] = 0u;
+        st->total_iter = 0; st->outer = 0; st->pad[0] = 0; st->pad[1] = 0;
     }
 }
 
@@ -817,19 +812,16 @@ __global__ void k_stats(const Inst *__restrict__ tab, int ninst, sylv_pcg_stats 
     const DevState *st = tab[i].st;
     const DevState *si = tab[i].st_in;
     sylv_pcg_stats s;
+    s.status = st->status;
+    if (st->status == SYLV_OK && !st->done) s.status = SYLV_NOT_CONVERGED;
     if (mixed) {
-        s.status = st->status;
-        if (st->status == SYLV_OK && !st->done) s.status = SYLV_NOT_CONVERGED;
         s.iters = si->total_iter;
         s.outer = st->outer;
-        s.relres_rec = (st->rr0 > 0.0) ? sqrt(st->rr / st->rr0) : 0.0;
     } else {
-        s.status = st->status;
-        if (st->status == SYLV_OK && !st->done) s.status = SYLV_NOT_CONVERGED;
         s.iters = st->iter;
         s.outer = 1;
-        s.relres_rec = (st->rr0 > 0.0) ? sqrt(st->rr / st->rr0) : 0.0;
     }
+    s.relres_rec = (st->rr0 > 0.0) ? sqrt(st->rr / st->rr0) : 0.0;
     s.reserved = 0;
     s.relres_true = st->rel_true;
     out[i] = s;
@@ -873,8 +865,11 @@ __global__ __launch_bounds__(kBlock) void k_po(const double *__restrict__ kappa,
     for (int j = 0; j < K; ++j) er[(size_t)j * n_pix + pix] = acc[j];
 }
 
-// Gradient reductions of the adjoint (backward) pass; see sylv.h for the formulas.  One pixel
-// per thread; L_j x*_j and L_j lambda_j come from 5-point stencils on the fly.
+// Gradient reductions of the adjoint (backward) pass: per-workgroup partials of
+//   dtau_j = -<L lambda_j, L x*_j>, dkappa_j = -4 kappa_j tau_j <lambda_j, L x*_j>,
+//   dA[f,j] = sum_p W[f,p] (r_f(p) lambda_j(p) - (a_f . lambda_p) x*_j(p)),
+// and the pointwise dW = (a_f . lambda) r_f, dY = W (a_f . lambda), r_f = Y_f - a_f . x*.
+// One pixel per thread; L x*_j and L lambda_j come from 5-point stencils on the fly.
 template <int K>
 __global__ __launch_bounds__(kBlock) void k_grad(const double *__restrict__ coef,
                                                  const double *__restrict__ A,
@@ -882,13 +877,9 @@ __global__ __launch_bounds__(kBlock) void k_grad(const double *__restrict__ coef
                                                  const double *__restrict__ Y,
                                                  const double *__restrict__ X,
                                                  const double *__restrict__ Lm, int f, int ny,
-                                                 int nx, double *__restrict__ dkappa,
-                                                 double *__restrict__ dtau,
-                                                 double *__restrict__ dA,
-                                                 double *__restrict__ dW,
+                                                 int nx, double *__restrict__ dW,
                                                  double *__restrict__ dY,
-                                                 double *__restrict__ partial,
-                                                 uint32_t *__restrict__ ticket) {
+                                                 double *__restrict__ partial) {
     const int n_pix = ny * nx;
     const int nblk = gridDim.x;
     const int nv = 2 * K + f * K;
@@ -915,7 +906,6 @@ __global__ __launch_bounds__(kBlock) void k_grad(const double *__restrict__ coef
             tl[j] = d * lm[j] - ((v[n] + v[s]) + (v[w] + v[e]));
         }
     }
-    // dtau_j = -<L lambda, L x>, dkappa_j = -4 kappa tau <lambda, L x>
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         const double kp = coef[j * kCoefStride + 5], t = coef[j * kCoefStride + 6];
@@ -949,28 +939,23 @@ __global__ __launch_bounds__(kBlock) void k_grad(const double *__restrict__ coef
     __syncthreads();
     for (int i = threadIdx.x; i < nv; i += kBlock)
         partial[(size_t)i * nblk + blockIdx.x] = (sm[i][0] + sm[i][1]) + (sm[i][2] + sm[i][3]);
-    __syncthreads();
-    __shared__ int last;
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t t = atomicAdd(ticket, 1u);
-        last = (t == (uint32_t)(nblk - 1));
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    for (int i = threadIdx.x; i < nv; i += kBlock) {
+}
+
+// Sum the gradient partials (one thread per quantity, fixed order over workgroups).
+__global__ void k_grad_fin(const double *__restrict__ partial, int nv, int nblk, int k,
+                           double *__restrict__ dkappa, double *__restrict__ dtau,
+                           double *__restrict__ dA) {
+    for (int i = threadIdx.x; i < nv; i += blockDim.x) {
         double s = 0.0;
         for (int b = 0; b < nblk; ++b) s += partial[(size_t)i * nblk + b];
-        if (i < K) {
+        if (i < k) {
             if (dtau) dtau[i] = s;
-        } else if (i < 2 * K) {
-            if (dkappa) dkappa[i - K] = s;
+        } else if (i < 2 * k) {
+            if (dkappa) dkappa[i - k] = s;
         } else {
-            if (dA) dA[i - 2 * K] = s;
+            if (dA) dA[i - 2 * k] = s;
         }
     }
-    if (threadIdx.x == 0) ticket[0] = 0u;
 }
 
 template <int K>
@@ -997,23 +982,22 @@ inline unsigned blocks_for(long n, int per) { return (unsigned)((n + per - 1) / 
 
 template <typename T, int K, int MODE>
 hipError_t launch_apply_rows(int rows, dim3 grid, hipStream_t s, const Inst *table,
-                             const int *tprefix, int ninst, int phase, const void *in,
-                             void *out) {
+                             const int *tprefix, int ninst, int it, const void *in, void *out) {
     const T *i = reinterpret_cast<const T *>(in);
     T *o = reinterpret_cast<T *>(out);
     const int nb = (int)grid.x;
     switch (rows) {
         case 2:
             hipLaunchKernelGGL((k_apply<T, K, 2, MODE>), grid, dim3(kBlock), 0, s, table,
-                               tprefix, ninst, nb, phase, i, o);
+                               tprefix, ninst, nb, it, i, o);
             break;
         case 8:
             hipLaunchKernelGGL((k_apply<T, K, 8, MODE>), grid, dim3(kBlock), 0, s, table,
-                               tprefix, ninst, nb, phase, i, o);
+                               tprefix, ninst, nb, it, i, o);
             break;
         default:
             hipLaunchKernelGGL((k_apply<T, K, 4, MODE>), grid, dim3(kBlock), 0, s, table,
-                               tprefix, ninst, nb, phase, i, o);
+                               tprefix, ninst, nb, it, i, o);
             break;
     }
     return hipGetLastError();
@@ -1024,6 +1008,13 @@ hipError_t launch_apply_rows(int rows, dim3 grid, hipStream_t s, const Inst *tab
 // ---- launchers -------------------------------------------------------------------------------
 
 int apply_rows_valid(int rows) { return rows == 2 || rows == 4 || rows == 8; }
+
+// Rows per lane actually used: long register windows spill for large k, so they are capped.
+int apply_rows_for(int k, int rows) {
+    if (rows == 8 && k > 3) rows = 4;
+    if (rows == 4 && k > 6) rows = 2;
+    return rows;
+}
 
 int grad_blocks(int n_pix) { return (int)blocks_for(n_pix, kBlock); }
 int grad_nv(int k, int f) { return 2 * k + f * k; }
@@ -1088,36 +1079,43 @@ hipError_t launch_precond_plain(const Inst *table0, int k, int dtype, int n_pix,
 }
 
 hipError_t launch_resid(const InstSet &set, int k, int rows, int phase, hipStream_t s) {
+    (void)phase;
     return dispatch_k(k, [&](auto tag) {
         constexpr int K = decltype(tag)::value;
         return launch_apply_rows<double, K, AM_RESID>(rows, dim3(set.total_tiles), s, set.table,
-                                                      set.tprefix, set.ninst, phase, nullptr,
+                                                      set.tprefix, set.ninst, 0, nullptr,
                                                       nullptr);
     });
 }
 
-hipError_t launch_cg_apply(const InstSet &set, int k, int mixed, int rows, hipStream_t s) {
+hipError_t launch_resid_fin(const InstSet &set, int phase, hipStream_t s) {
+    hipLaunchKernelGGL(k_resid_fin, dim3(set.ninst), dim3(kBlock), 0, s, set.table, phase);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_apply(const InstSet &set, int k, int mixed, int rows, int it,
+                           hipStream_t s) {
     return dispatch_k(k, [&](auto tag) {
         constexpr int K = decltype(tag)::value;
         if (mixed)
             return launch_apply_rows<float, K, AM_CG>(rows, dim3(set.total_tiles), s, set.table,
-                                                      set.tprefix, set.ninst, 0, nullptr,
+                                                      set.tprefix, set.ninst, it, nullptr,
                                                       nullptr);
         return launch_apply_rows<double, K, AM_CG>(rows, dim3(set.total_tiles), s, set.table,
-                                                   set.tprefix, set.ninst, 0, nullptr, nullptr);
+                                                   set.tprefix, set.ninst, it, nullptr, nullptr);
     });
 }
 
-hipError_t launch_cg_update(const InstSet &set, int k, int mixed, hipStream_t s) {
+hipError_t launch_cg_update(const InstSet &set, int k, int mixed, int it, hipStream_t s) {
     return dispatch_k(k, [&](auto tag) {
         constexpr int K = decltype(tag)::value;
         const dim3 grid(set.total_chunks);
         if (mixed)
             hipLaunchKernelGGL((k_update<float, K>), grid, dim3(kBlock), 0, s, set.table,
-                               set.cprefix, set.ninst, (int)grid.x);
+                               set.cprefix, set.ninst, (int)grid.x, it);
         else
             hipLaunchKernelGGL((k_update<double, K>), grid, dim3(kBlock), 0, s, set.table,
-                               set.cprefix, set.ninst, (int)grid.x);
+                               set.cprefix, set.ninst, (int)grid.x, it);
         return hipGetLastError();
     });
 }
@@ -1180,14 +1178,18 @@ hipError_t launch_po(const double *kappa, const double *tau, const double *A, co
 hipError_t launch_grad(const double *coef, const double *A, const double *W, const double *Y,
                        const double *X, const double *Lm, int k, int f, int ny, int nx,
                        double *dkappa, double *dtau, double *dA, double *dW, double *dY,
-                       double *partial, uint32_t *ticket, hipStream_t s) {
-    return dispatch_k(k, [&](auto tag) {
+                       double *partial, hipStream_t s) {
+    const int nblk = grad_blocks(ny * nx);
+    hipError_t e = dispatch_k(k, [&](auto tag) {
         constexpr int K = decltype(tag)::value;
-        const dim3 grid(grad_blocks(ny * nx));
-        hipLaunchKernelGGL((k_grad<K>), grid, dim3(kBlock), 0, s, coef, A, W, Y, X, Lm, f, ny,
-                           nx, dkappa, dtau, dA, dW, dY, partial, ticket);
+        hipLaunchKernelGGL((k_grad<K>), dim3(nblk), dim3(kBlock), 0, s, coef, A, W, Y, X, Lm, f,
+                           ny, nx, dW, dY, partial);
         return hipGetLastError();
     });
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_grad_fin, dim3(1), dim3(kBlock), 0, s, partial, grad_nv(k, f), nblk, k,
+                       dkappa, dtau, dA);
+    return hipGetLastError();
 }
 
 }  // namespace sylv
