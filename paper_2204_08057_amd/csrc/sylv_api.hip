@@ -31,12 +31,13 @@ void set_err(const char *fmt, ...) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-int apply_rows_setting() {
+// Optional override of the apply kernels' rows per lane (2, 4 or 8) for tuning experiments.
+int apply_rows_request() {
     static int rows = -1;
     if (rows < 0) {
         const char *e = getenv("SYLV_APPLY_ROWS");
-        int v = e ? atoi(e) : 4;
-        rows = apply_rows_valid(v) ? v : 4;
+        const int v = e ? atoi(e) : 0;
+        rows = apply_rows_valid(v) ? v : 0;
     }
     return rows;
 }
@@ -58,7 +59,7 @@ struct InstLayout {
 struct Layout {
     std::vector<ProbLayout> prob;
     std::vector<InstLayout> inst;
-    size_t table = 0, tprefix = 0, cprefix = 0, count = 0, gpartial = 0;
+    size_t table = 0, tprefix = 0, count = 0, gpartial = 0;
     size_t total = 0;
 };
 
@@ -90,8 +91,7 @@ bool make_layout(const sylv_problem *probs, int nprob, int nrhs, bool solve, Lay
     }
     const int ninst = solve ? nprob * nrhs : 1;
     L.table = off;   off = align_up(off + sizeof(Inst) * ninst);
-    L.tprefix = off; off = align_up(off + sizeof(int) * (ninst + 1));
-    L.cprefix = off; off = align_up(off + sizeof(int) * (ninst + 1));
+    L.tprefix = off; off = align_up(off + sizeof(int) * 3 * (ninst + 1));
     L.count = off;   off = align_up(off + sizeof(int) * 4);
     if (solve) {
         L.inst.resize(ninst);
@@ -196,12 +196,12 @@ int check_opts(const sylv_pcg_opts *o) {
 // Iteration `it` is apply(it) (stopping test on the residual of update(it-1), new direction,
 // q = G p) followed by update(it); a run that stops makes every later kernel of the loop a
 // no-op, and apply(max_iter) always stops it, so the loop ends.
-int run_cg_loop(const InstSet &set, int k, int mixed, int rows, int chunk, int max_iter,
+int run_cg_loop(const InstSet &set, int k, int mixed, int chunk, int max_iter,
                 int *dcount, hipStream_t s) {
     int it = 0;
     for (;;) {
         for (int c = 0; c < chunk && it <= max_iter; ++c, ++it) {
-            HIP_TRY(launch_cg_apply(set, k, mixed, rows, it, s));
+            HIP_TRY(launch_cg_apply(set, k, mixed, it, s));
             HIP_TRY(launch_cg_update(set, k, mixed, it, s));
         }
         HIP_TRY(launch_count_running(set, mixed, dcount, s));
@@ -231,15 +231,17 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
     if (rc) return rc;
     char *base = reinterpret_cast<char *>(ws);
     const int mixed = opts->precision == SYLV_PREC_MIXED;
-    const int rows = apply_rows_for(k, apply_rows_setting());
+    const int rows64 = apply_rows_for(k, SYLV_F64, apply_rows_request());
+    const int rows32 = apply_rows_for(k, SYLV_F32, apply_rows_request());
     const int pc = opts->precond;
 
     // instance table
     const int ninst = nprob * nrhs;
     std::vector<Inst> tab(ninst);
-    std::vector<int> tpre(ninst + 1), cpre(ninst + 1);
+    std::vector<int> pre(3 * (ninst + 1));
+    int *tpre = pre.data(), *tpre32 = tpre + (ninst + 1), *cpre = tpre32 + (ninst + 1);
     size_t xoff = 0, yoff = 0;
-    tpre[0] = cpre[0] = 0;
+    tpre[0] = tpre32[0] = cpre[0] = 0;
     for (int g = 0; g < nprob; ++g) {
         const sylv_problem &p = probs[g];
         const size_t n = (size_t)p.ny * p.nx;
@@ -247,7 +249,8 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
             const int i = g * nrhs + r;
             const InstLayout &IL = L.inst[i];
             Inst I = operator_inst(p, L.prob[g], base, pc);
-            I.ntiles = tiles_for(I.ny, I.nx, rows);
+            I.ntiles = tiles_for(I.ny, I.nx, rows64);
+            I.ntiles32 = tiles_for(I.ny, I.nx, rows32);
             I.nchunks = chunks_for(I.n_pix);
             I.nred = IL.nred;
             I.Y = Y ? Y + yoff : nullptr;
@@ -271,6 +274,7 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
             I.vec4 = (I.n_pix % 4 == 0) && aligned16(I.x) ? 1 : 0;
             tab[i] = I;
             tpre[i + 1] = tpre[i] + I.ntiles;
+            tpre32[i + 1] = tpre32[i] + I.ntiles32;
             cpre[i + 1] = cpre[i] + I.nchunks;
         }
         xoff += (size_t)nrhs * k * n;
@@ -278,17 +282,19 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
     }
     HIP_TRY(hipMemcpyAsync(base + L.table, tab.data(), sizeof(Inst) * ninst,
                            hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(base + L.tprefix, tpre.data(), sizeof(int) * (ninst + 1),
-                           hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(base + L.cprefix, cpre.data(), sizeof(int) * (ninst + 1),
+    HIP_TRY(hipMemcpyAsync(base + L.tprefix, pre.data(), sizeof(int) * 3 * (ninst + 1),
                            hipMemcpyHostToDevice, s));
     InstSet set;
     set.table = reinterpret_cast<const Inst *>(base + L.table);
     set.tprefix = reinterpret_cast<const int *>(base + L.tprefix);
-    set.cprefix = reinterpret_cast<const int *>(base + L.cprefix);
+    set.tprefix32 = set.tprefix + (ninst + 1);
+    set.cprefix = set.tprefix32 + (ninst + 1);
     set.ninst = ninst;
     set.total_tiles = tpre[ninst];
+    set.total_tiles32 = tpre32[ninst];
     set.total_chunks = cpre[ninst];
+    set.rows64 = rows64;
+    set.rows32 = rows32;
     int *dcount = reinterpret_cast<int *>(base + L.count);
 
     // operator set-up and right-hand sides
@@ -302,23 +308,23 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
         HIP_TRY(launch_rhs(I.W, I.Y, I.A, I.f, I.n_pix, I.bext, I.b, k, s));
     }
     const int chunk = opts->check_every > 0 ? opts->check_every : 16;
-    HIP_TRY(launch_resid(set, k, rows, 0, s));   // r0 = b - G x0, ||b||, ||r0||
+    HIP_TRY(launch_resid(set, k, 0, s));   // r0 = b - G x0, ||b||, ||r0||
     HIP_TRY(launch_resid_fin(set, 0, s));
     if (!mixed) {
         HIP_TRY(launch_pinit(set, k, 0, 0.0, opts->max_iter, s));
-        rc = run_cg_loop(set, k, 0, rows, chunk, opts->max_iter, dcount, s);
+        rc = run_cg_loop(set, k, 0, chunk, opts->max_iter, dcount, s);
         if (rc) return rc;
-        HIP_TRY(launch_resid(set, k, rows, 1, s));   // true residual of the result
+        HIP_TRY(launch_resid(set, k, 1, s));   // true residual of the result
         HIP_TRY(launch_resid_fin(set, 1, s));
     } else {
         const double inner_tol = opts->inner_tol > 0.0 ? opts->inner_tol : 1e-5;
         const int refine_max = opts->refine_max > 0 ? opts->refine_max : 8;
         for (int o = 0; o < refine_max; ++o) {
             HIP_TRY(launch_pinit(set, k, 1, inner_tol, opts->max_iter, s));
-            rc = run_cg_loop(set, k, 1, rows, chunk, opts->max_iter, dcount, s);
+            rc = run_cg_loop(set, k, 1, chunk, opts->max_iter, dcount, s);
             if (rc) return rc;
             HIP_TRY(launch_refine_axpy(set, k, s));
-            HIP_TRY(launch_resid(set, k, rows, 2, s));   // float64 residual of the new x
+            HIP_TRY(launch_resid(set, k, 2, s));   // float64 residual of the new x
             HIP_TRY(launch_resid_fin(set, 2, s));
             HIP_TRY(launch_count_running(set, 0, dcount, s));
             int h = 0;
@@ -388,7 +394,7 @@ int sylv_apply(const sylv_problem *prob, int32_t dtype, const void *X, void *Y, 
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     char *base = reinterpret_cast<char *>(ws);
     HIP_TRY(launch_apply_plain(reinterpret_cast<const Inst *>(base + L.table), prob->k, dtype,
-                               apply_rows_for(prob->k, apply_rows_setting()), (int)prob->ny,
+                               apply_rows_for(prob->k, dtype, apply_rows_request()), (int)prob->ny,
                                (int)prob->nx, nrhs, X, Y, s));
     return SYLV_OK;
 }

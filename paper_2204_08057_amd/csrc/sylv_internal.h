@@ -49,7 +49,8 @@ struct DevState {
 struct Inst {
     int32_t ny, nx, n_pix;
     int32_t tiles_x;     // apply tiles across x
-    int32_t ntiles;      // apply tiles in this instance
+    int32_t ntiles;      // float64 apply tiles in this instance
+    int32_t ntiles32;    // float32 apply tiles (rows per lane may differ by precision)
     int32_t nchunks;     // streaming chunks in this instance
     int32_t nred;        // stride between reduction quantities in `partial`
     int32_t pc;          // preconditioner kind (SYLV_PC_*)
@@ -79,12 +80,15 @@ struct Inst {
 // Launch-time view of the instances: a device table plus prefix sums that map a flat
 // workgroup id to (instance, tile) for apply kernels or (instance, chunk) for streaming ones.
 struct InstSet {
-    const Inst *table;   // device array [ninst]
-    const int *tprefix;  // device [ninst + 1] prefix sums of apply tiles
-    const int *cprefix;  // device [ninst + 1] prefix sums of streaming chunks
+    const Inst *table;    // device array [ninst]
+    const int *tprefix;   // device [ninst + 1] prefix sums of float64 apply tiles
+    const int *tprefix32; // device [ninst + 1] prefix sums of float32 apply tiles
+    const int *cprefix;   // device [ninst + 1] prefix sums of streaming chunks
     int ninst;
     int total_tiles;
+    int total_tiles32;
     int total_chunks;
+    int rows64, rows32;   // rows per lane of the float64 / float32 apply kernels
 };
 
 inline int packed_size(int k) { return k * (k + 1) / 2; }
@@ -92,7 +96,9 @@ inline int packed_size(int k) { return k * (k + 1) / 2; }
 // ---- launchers (sylv_kernels.hip) -------------------------------------------------------
 // Every launcher returns the hipError_t of its launch.
 int apply_rows_valid(int rows);
-int apply_rows_for(int k, int rows);   // rows per lane the apply kernels use for this k
+// Rows per lane of the apply kernels for k components and element type dtype; `request` (2, 4
+// or 8; 0 = default) is capped where the register window would overflow.
+int apply_rows_for(int k, int dtype, int request);
 hipError_t launch_coef(const double *kappa, const double *tau, int k, int ny, int nx,
                        double *coef, hipStream_t s);
 hipError_t launch_setup(const double *W, const double *A, int f, int n_pix, const double *coef,
@@ -106,11 +112,11 @@ hipError_t launch_precond_plain(const Inst *table0, int k, int dtype, int n_pix,
                                 const void *in, void *out, hipStream_t s);
 // residual r = b - G x (float64); phase 0: initial (sets ||b||, ||r0||, threshold),
 // 1: final true residual only, 2: refinement step of the mixed path
-hipError_t launch_resid(const InstSet &set, int k, int rows, int phase, hipStream_t s);
+hipError_t launch_resid(const InstSet &set, int k, int phase, hipStream_t s);
 hipError_t launch_resid_fin(const InstSet &set, int phase, hipStream_t s);
 hipError_t launch_pinit(const InstSet &set, int k, int mixed, double inner_tol, int max_iter,
                         hipStream_t s);
-hipError_t launch_cg_apply(const InstSet &set, int k, int mixed, int rows, int it, hipStream_t s);
+hipError_t launch_cg_apply(const InstSet &set, int k, int mixed, int it, hipStream_t s);
 hipError_t launch_cg_update(const InstSet &set, int k, int mixed, int it, hipStream_t s);
 hipError_t launch_refine_axpy(const InstSet &set, int k, hipStream_t s);
 hipError_t launch_state_init(const InstSet &set, double tol, int max_iter, hipStream_t s);

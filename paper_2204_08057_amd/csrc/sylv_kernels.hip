@@ -388,26 +388,92 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
                                                   const T *__restrict__ ext_in,
                                                   T *__restrict__ ext_out) {
     constexpr int MK = K * (K + 1) / 2;
+    constexpr int LH = kWavesY * R + 4;   // staged rows: tile + 2-row halo above and below
+    constexpr int LW = kTileX + 4;        // staged columns: tile + 2-column halo left and right
+    constexpr int RPW = LH / kWavesY;     // staged rows per wavefront
     const int L = xcd_remap(blockIdx.x, nb);
     const int ii = (MODE == AM_PLAIN) ? 0 : find_inst(tprefix, ninst, L);
     const Inst &I = tab[ii];
     const int tile = (MODE == AM_PLAIN) ? L : L - tprefix[ii];
     const int nx = I.nx, ny = I.ny, n_pix = I.n_pix;
+    DevState *st = (MODE == AM_CG) ? Sel<T>::st(I) : nullptr;
+    if constexpr (MODE == AM_CG) {
+        if (st->done) return;
+    }
 
-    const GAS T *u0;            // field (or previous direction when fusing)
-    const GAS T *u1 = nullptr;  // preconditioned residual z when fusing
-    T beta = 0;
+    // u = field to apply: the input (plain), x (residual), or z + beta p_old (CG; z alone at
+    // it = 0, where p_old is aliased to z so that no uninitialised value is ever read).
+    const GAS T *u0;
+    const GAS T *u1 = nullptr;
     if constexpr (MODE == AM_PLAIN) {
         u0 = gp(ext_in) + (size_t)blockIdx.y * K * n_pix;
     } else if constexpr (MODE == AM_CG) {
-        DevState *st = Sel<T>::st(I);
-        if (st->done) return;
+        u1 = Sel<T>::z(I);
+        u0 = (it == 0) ? u1 : (const GAS T *)Sel<T>::p(I, it);
+    } else {
+        u0 = (const GAS T *)gp(I.x);
+    }
+
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int tile_x = tile % I.tiles_x, tile_y = tile / I.tiles_x;
+    const int x0 = tile_x * kTileX, y0 = tile_y * kWavesY * R;
+    const int ix = x0 + tx;
+    const int iy0 = y0 + ty * R;
+    const bool active = (ix < nx) && (iy0 < ny);
+
+    // ---- issue every global load of the tile before any barrier ---------------------------
+    // Staging: rows by whole wavefronts (coalesced), the 4 halo columns of all rows by one lane
+    // each.  Every staged column is the periodic wrap of x0 - 2 + c, so ragged tiles see true
+    // neighbours.
+    const int cmain = wrapi(x0 + tx, nx);
+    const int hitem = ty * 64 + tx;                     // halo item: (row, one of 4 columns)
+    const int hr = hitem >> 2, hc = hitem & 3;
+    const int hcol = (hc < 2) ? hc : (kTileX + hc);     // staged columns 0, 1, 66, 67
+    const bool hvalid = hitem < 4 * LH;
+    const int hoff = hvalid ? wrapi(y0 - 2 + hr, ny) * nx + wrapi(x0 - 2 + hcol, nx) : 0;
+    int soff[RPW];
+#pragma unroll
+    for (int rr = 0; rr < RPW; ++rr) soff[rr] = wrapi(y0 - 2 + rr * kWavesY + ty, ny) * nx + cmain;
+    T sa[K][RPW], sb[K][RPW], ha[K], hb[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const GAS T *a = u0 + (size_t)j * n_pix;
+#pragma unroll
+        for (int rr = 0; rr < RPW; ++rr) sa[j][rr] = a[soff[rr]];
+        ha[j] = hvalid ? a[hoff] : (T)0;
+        if constexpr (MODE == AM_CG) {
+            const GAS T *zz = u1 + (size_t)j * n_pix;
+#pragma unroll
+            for (int rr = 0; rr < RPW; ++rr) sb[j][rr] = zz[soff[rr]];
+            hb[j] = hvalid ? zz[hoff] : (T)0;
+        }
+    }
+    // per-pixel mixing blocks (and, for the residual, b) of this lane's R output pixels
+    T m[R][MK];
+    double bpre[R][K];
+    {
+        const GAS T *M = Sel<T>::M(I);
+        const int ixc = ix < nx ? ix : 0;
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const int pix = (iy0 + t < ny ? iy0 + t : 0) * nx + ixc;
+#pragma unroll
+            for (int e = 0; e < MK; ++e) m[t][e] = M[(size_t)e * n_pix + pix];
+            if constexpr (MODE == AM_RESID) {
+                const GAS double *bb = gp(I.b);
+#pragma unroll
+                for (int j = 0; j < K; ++j) bpre[t][j] = bb[(size_t)j * n_pix + pix];
+            }
+        }
+    }
+
+    // ---- CG: stopping test on the last update's residual, then beta -----------------------
+    T beta = 0;
+    if constexpr (MODE == AM_CG) {
         double s[2];
         consume<2>(I.partial, I.nred, SLOT_RZ, I.nchunks, s);
         const double rz = s[0], rr = s[1];
-        double thresh;
-        if (it == 0) thresh = st->tol * st->tol * rr;
-        else thresh = st->thresh;
+        const double thresh = (it == 0) ? st->tol * st->tol * rr : st->thresh;
         int status = -1;
         if (!finite_d(rz) || !finite_d(rr)) status = SYLV_NONFINITE;
         else if (rr <= thresh) status = SYLV_OK;
@@ -425,56 +491,49 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
             }
         }
         if (status >= 0) return;
-        u1 = Sel<T>::z(I);
-        if (it == 0) {
-            // first direction: p = z; alias p_old to z with beta = 0 so that no uninitialised
-            // value is ever read.
-            u0 = u1;
-        } else {
-            u0 = Sel<T>::p(I, it);
-            beta = (T)(rz / st->rho[(it - 1) & 1]);
-        }
-    } else {
-        u0 = (const GAS T *)gp(I.x);
+        if (it > 0) beta = (T)(rz / st->rho[(it - 1) & 1]);
     }
 
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    const int tile_x = tile % I.tiles_x, tile_y = tile / I.tiles_x;
-    const int ix = tile_x * kTileX + tx;
-    const int iy0 = (tile_y * kWavesY + ty) * R;
-    const bool active = (ix < nx) && (iy0 < ny);
+    // ---- stage u in LDS ---------------------------------------------------------------------
+    __shared__ T lds[K][LH][LW];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+#pragma unroll
+        for (int rr = 0; rr < RPW; ++rr) {
+            T v = sa[j][rr];
+            if constexpr (MODE == AM_CG) v = sb[j][rr] + beta * v;
+            lds[j][rr * kWavesY + ty][tx + 2] = v;
+        }
+        if (hvalid) {
+            T v = ha[j];
+            if constexpr (MODE == AM_CG) v = hb[j] + beta * v;
+            lds[j][hr][hcol] = v;
+        }
+    }
+    __syncthreads();
 
-    T acc[K][R];
-    T ctr[K][R];
-    int rowoff[R + 4];
+    // ---- 13-point stencil from LDS, k x k mixing, stores and dot partials --------------------
     double d0 = 0.0, d1 = 0.0;
     if (active) {
-#pragma unroll
-        for (int t = 0; t < R + 4; ++t) rowoff[t] = wrapi(iy0 - 2 + t, ny) * nx;
-        const int xm2 = wrapi(ix - 2, nx), xm1 = wrapi(ix - 1, nx);
-        const int xp1 = wrapi(ix + 1, nx), xp2 = wrapi(ix + 2, nx);
+        const int lr = ty * R;   // first staged row of this wavefront's window
+        T acc[K][R];
+        T ctr[K][R];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const double *cj = I.coef + j * kCoefStride;
             const T c0 = (T)cj[0], c1 = (T)cj[1], cd = (T)cj[2], c2 = (T)cj[3];
-            const GAS T *a = u0 + (size_t)j * n_pix;
-            const GAS T *zz = (MODE == AM_CG) ? (u1 + (size_t)j * n_pix) : nullptr;
-            auto ld = [&](int off) -> T {
-                if constexpr (MODE == AM_CG) return zz[off] + beta * a[off];
-                else return a[off];
-            };
             T cc[R + 4], l1[R + 2], r1[R + 2], l2[R], r2[R];
 #pragma unroll
-            for (int t = 0; t < R + 4; ++t) cc[t] = ld(rowoff[t] + ix);
+            for (int t = 0; t < R + 4; ++t) cc[t] = lds[j][lr + t][tx + 2];
 #pragma unroll
             for (int t = 0; t < R + 2; ++t) {
-                l1[t] = ld(rowoff[t + 1] + xm1);
-                r1[t] = ld(rowoff[t + 1] + xp1);
+                l1[t] = lds[j][lr + t + 1][tx + 1];
+                r1[t] = lds[j][lr + t + 1][tx + 3];
             }
 #pragma unroll
             for (int t = 0; t < R; ++t) {
-                l2[t] = ld(rowoff[t + 2] + xm2);
-                r2[t] = ld(rowoff[t + 2] + xp2);
+                l2[t] = lds[j][lr + t + 2][tx];
+                r2[t] = lds[j][lr + t + 2][tx + 4];
             }
 #pragma unroll
             for (int t = 0; t < R; ++t) {
@@ -485,20 +544,16 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
                 ctr[j][t] = cc[t + 2];
             }
         }
-        const GAS T *M = Sel<T>::M(I);
 #pragma unroll
         for (int t = 0; t < R; ++t) {
             if (iy0 + t < ny) {
-                const int pix = rowoff[t + 2] + ix;
-                T m[MK];
-#pragma unroll
-                for (int e = 0; e < MK; ++e) m[e] = M[(size_t)e * n_pix + pix];
+                const int pix = (iy0 + t) * nx + ix;
 #pragma unroll
                 for (int j = 0; j < K; ++j) {
-                    T s = acc[j][t];
+                    T sum = acc[j][t];
 #pragma unroll
-                    for (int i = 0; i < K; ++i) s += m[pidx<K>(j, i)] * ctr[i][t];
-                    acc[j][t] = s;
+                    for (int i = 0; i < K; ++i) sum += m[t][pidx<K>(j, i)] * ctr[i][t];
+                    acc[j][t] = sum;
                 }
                 if constexpr (MODE == AM_PLAIN) {
                     GAS T *o = gp(ext_out) + (size_t)blockIdx.y * K * n_pix;
@@ -514,14 +569,13 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
                         d0 += (double)ctr[j][t] * (double)acc[j][t];
                     }
                 } else {
-                    const GAS double *bb = gp(I.b);
-                    GAS double *rr = gp(I.r);
+                    GAS double *rv = gp(I.r);
 #pragma unroll
                     for (int j = 0; j < K; ++j) {
-                        const double bv = bb[(size_t)j * n_pix + pix];
-                        const double rv = bv - (double)acc[j][t];
-                        rr[(size_t)j * n_pix + pix] = rv;
-                        d0 += rv * rv;
+                        const double bv = bpre[t][j];
+                        const double res = bv - (double)acc[j][t];
+                        rv[(size_t)j * n_pix + pix] = res;
+                        d0 += res * res;
                         d1 += bv * bv;
                     }
                 }
@@ -602,7 +656,7 @@ __global__ __launch_bounds__(kBlock) void k_update(const Inst *__restrict__ tab,
     const int pc = I.pc;
     const int p0 = chunk * kChunk + threadIdx.x * 4;
     double s[1];
-    consume<1>(I.partial, I.nred, SLOT_PQ, I.ntiles, s);
+    consume<1>(I.partial, I.nred, SLOT_PQ, sizeof(T) == 4 ? I.ntiles32 : I.ntiles, s);
     const double pq = s[0];
     int status = -1;
     if (!finite_d(pq)) status = SYLV_NONFINITE;
@@ -1009,11 +1063,12 @@ hipError_t launch_apply_rows(int rows, dim3 grid, hipStream_t s, const Inst *tab
 
 int apply_rows_valid(int rows) { return rows == 2 || rows == 4 || rows == 8; }
 
-// Rows per lane actually used: long register windows spill for large k, so they are capped.
-int apply_rows_for(int k, int rows) {
-    if (rows == 8 && k > 3) rows = 4;
-    if (rows == 4 && k > 6) rows = 2;
-    return rows;
+int apply_rows_for(int k, int dtype, int request) {
+    // default: 4 rows where the register window leaves >= 2 waves per SIMD, else 2
+    int rows = request;
+    if (!apply_rows_valid(rows)) rows = (dtype == SYLV_F64) ? (k <= 3 ? 4 : 2) : (k <= 4 ? 4 : 2);
+    const int cap = (dtype == SYLV_F64) ? (k <= 2 ? 8 : k <= 3 ? 4 : 2) : (k <= 2 ? 8 : k <= 5 ? 4 : 2);
+    return rows < cap ? rows : cap;
 }
 
 int grad_blocks(int n_pix) { return (int)blocks_for(n_pix, kBlock); }
@@ -1078,13 +1133,13 @@ hipError_t launch_precond_plain(const Inst *table0, int k, int dtype, int n_pix,
     });
 }
 
-hipError_t launch_resid(const InstSet &set, int k, int rows, int phase, hipStream_t s) {
+hipError_t launch_resid(const InstSet &set, int k, int phase, hipStream_t s) {
     (void)phase;
     return dispatch_k(k, [&](auto tag) {
         constexpr int K = decltype(tag)::value;
-        return launch_apply_rows<double, K, AM_RESID>(rows, dim3(set.total_tiles), s, set.table,
-                                                      set.tprefix, set.ninst, 0, nullptr,
-                                                      nullptr);
+        return launch_apply_rows<double, K, AM_RESID>(set.rows64, dim3(set.total_tiles), s,
+                                                      set.table, set.tprefix, set.ninst, 0,
+                                                      nullptr, nullptr);
     });
 }
 
@@ -1093,16 +1148,16 @@ hipError_t launch_resid_fin(const InstSet &set, int phase, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_cg_apply(const InstSet &set, int k, int mixed, int rows, int it,
-                           hipStream_t s) {
+hipError_t launch_cg_apply(const InstSet &set, int k, int mixed, int it, hipStream_t s) {
     return dispatch_k(k, [&](auto tag) {
         constexpr int K = decltype(tag)::value;
         if (mixed)
-            return launch_apply_rows<float, K, AM_CG>(rows, dim3(set.total_tiles), s, set.table,
-                                                      set.tprefix, set.ninst, it, nullptr,
-                                                      nullptr);
-        return launch_apply_rows<double, K, AM_CG>(rows, dim3(set.total_tiles), s, set.table,
-                                                   set.tprefix, set.ninst, it, nullptr, nullptr);
+            return launch_apply_rows<float, K, AM_CG>(set.rows32, dim3(set.total_tiles32), s,
+                                                      set.table, set.tprefix32, set.ninst, it,
+                                                      nullptr, nullptr);
+        return launch_apply_rows<double, K, AM_CG>(set.rows64, dim3(set.total_tiles), s,
+                                                   set.table, set.tprefix, set.ninst, it,
+                                                   nullptr, nullptr);
     });
 }
 
