@@ -192,23 +192,73 @@ int check_opts(const sylv_pcg_opts *o) {
     return SYLV_OK;
 }
 
-// Enqueue `chunk`-iteration batches until no run is going; one 4-byte readback per batch.
-// Iteration `it` is apply(it) (stopping test on the residual of update(it-1), new direction,
-// q = G p) followed by update(it); a run that stops makes every later kernel of the loop a
-// no-op, and apply(max_iter) always stops it, so the loop ends.
-int run_cg_loop(const InstSet &set, int k, int mixed, int chunk, int max_iter,
-                int *dcount, hipStream_t s) {
-    int it = 0;
-    for (;;) {
+// Host-side completion flags: the count kernel writes the number of unfinished runs straight
+// into pinned host memory and an event marks when it is valid.  One small pinned block and a few
+// events per host thread, created on first use and kept for the life of the thread.
+struct HostFlags {
+    static constexpr int kSlots = 4;
+    int *pinned = nullptr;
+    hipEvent_t ev[kSlots] = {};
+    bool ready = false;
+    ~HostFlags() {
+        if (!ready) return;
+        for (int i = 0; i < kSlots; ++i) (void)hipEventDestroy(ev[i]);
+        (void)hipHostFree(pinned);
+    }
+};
+thread_local HostFlags g_flags;
+
+int host_flags(HostFlags *&out) {
+    HostFlags &f = g_flags;
+    if (!f.ready) {
+        HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&f.pinned),
+                              sizeof(int) * HostFlags::kSlots, hipHostMallocDefault));
+        for (int i = 0; i < HostFlags::kSlots; ++i)
+            HIP_TRY(hipEventCreateWithFlags(&f.ev[i], hipEventDisableTiming));
+        f.ready = true;
+    }
+    out = &f;
+    return SYLV_OK;
+}
+
+// Enqueue "how many runs are unfinished" into slot `slot` (inner = 1: the float32 inner runs).
+int post_count(const InstSet &set, int inner, HostFlags *f, int slot, hipStream_t s) {
+    HIP_TRY(launch_count_running(set, inner, f->pinned + slot, s));
+    HIP_TRY(hipEventRecord(f->ev[slot], s));
+    return SYLV_OK;
+}
+
+int wait_count(HostFlags *f, int slot, int &value) {
+    HIP_TRY(hipEventSynchronize(f->ev[slot]));
+    value = *reinterpret_cast<volatile int *>(f->pinned + slot);
+    return SYLV_OK;
+}
+
+// Conjugate-gradient iterations in batches of `chunk`, with one batch always queued ahead of the
+// completion check so that the GPU never waits for the host.  Iteration `it` is apply(it)
+// (stopping test on the residual of update(it-1), new direction, q = G p) followed by
+// update(it); a run that has stopped turns every later kernel of the loop into a no-op, and
+// apply(max_iter) always stops it, so the loop ends.
+int run_cg_loop(const InstSet &set, int k, int mixed, int chunk, int max_iter, HostFlags *f,
+                hipStream_t s) {
+    int it = 0, rc;
+    auto enqueue_batch = [&](int slot) -> int {
         for (int c = 0; c < chunk && it <= max_iter; ++c, ++it) {
             HIP_TRY(launch_cg_apply(set, k, mixed, it, s));
             HIP_TRY(launch_cg_update(set, k, mixed, it, s));
         }
-        HIP_TRY(launch_count_running(set, mixed, dcount, s));
-        int h = 0;
-        HIP_TRY(hipMemcpyAsync(&h, dcount, sizeof(int), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (h == 0 || it > max_iter) break;
+        return post_count(set, mixed, f, slot, s);
+    };
+    if ((rc = enqueue_batch(0))) return rc;
+    for (int cur = 0;; cur ^= 1) {
+        const bool more = it <= max_iter;
+        if (more && (rc = enqueue_batch(cur ^ 1))) return rc;
+        int running = 0;
+        if ((rc = wait_count(f, cur, running))) return rc;
+        if (running == 0 || !more) {
+            if (more && (rc = wait_count(f, cur ^ 1, running))) return rc;   // drain the lookahead
+            break;
+        }
     }
     return SYLV_OK;
 }
@@ -295,7 +345,6 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
     set.total_chunks = cpre[ninst];
     set.rows64 = rows64;
     set.rows32 = rows32;
-    int *dcount = reinterpret_cast<int *>(base + L.count);
 
     // operator set-up and right-hand sides
     for (int g = 0; g < nprob; ++g) {
@@ -307,30 +356,35 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
         const Inst &I = tab[i];
         HIP_TRY(launch_rhs(I.W, I.Y, I.A, I.f, I.n_pix, I.bext, I.b, k, s));
     }
-    const int chunk = opts->check_every > 0 ? opts->check_every : 16;
+    const int chunk = opts->check_every > 0 ? opts->check_every : 8;
+    HostFlags *flags = nullptr;
+    if ((rc = host_flags(flags))) return rc;
     HIP_TRY(launch_resid(set, k, 0, s));   // r0 = b - G x0, ||b||, ||r0||
     HIP_TRY(launch_resid_fin(set, 0, s));
     if (!mixed) {
         HIP_TRY(launch_pinit(set, k, 0, 0.0, opts->max_iter, s));
-        rc = run_cg_loop(set, k, 0, chunk, opts->max_iter, dcount, s);
+        rc = run_cg_loop(set, k, 0, chunk, opts->max_iter, flags, s);
         if (rc) return rc;
         HIP_TRY(launch_resid(set, k, 1, s));   // true residual of the result
         HIP_TRY(launch_resid_fin(set, 1, s));
     } else {
         const double inner_tol = opts->inner_tol > 0.0 ? opts->inner_tol : 1e-5;
         const int refine_max = opts->refine_max > 0 ? opts->refine_max : 8;
+        // One refinement step: float32 inner PCG on the current float64 residual, x += d, new
+        // float64 residual.  Steps of finished instances are no-ops on the device, so the next
+        // step is queued before the host learns whether this one finished.
+        HIP_TRY(launch_pinit(set, k, 1, inner_tol, opts->max_iter, s));
         for (int o = 0; o < refine_max; ++o) {
-            HIP_TRY(launch_pinit(set, k, 1, inner_tol, opts->max_iter, s));
-            rc = run_cg_loop(set, k, 1, chunk, opts->max_iter, dcount, s);
+            rc = run_cg_loop(set, k, 1, chunk, opts->max_iter, flags, s);
             if (rc) return rc;
             HIP_TRY(launch_refine_axpy(set, k, s));
             HIP_TRY(launch_resid(set, k, 2, s));   // float64 residual of the new x
             HIP_TRY(launch_resid_fin(set, 2, s));
-            HIP_TRY(launch_count_running(set, 0, dcount, s));
-            int h = 0;
-            HIP_TRY(hipMemcpyAsync(&h, dcount, sizeof(int), hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
-            if (h == 0) break;
+            if ((rc = post_count(set, 0, flags, 2, s))) return rc;
+            if (o + 1 < refine_max) HIP_TRY(launch_pinit(set, k, 1, inner_tol, opts->max_iter, s));
+            int running = 0;
+            if ((rc = wait_count(flags, 2, running))) return rc;
+            if (running == 0) break;
         }
     }
     HIP_TRY(launch_stats(set, stats, mixed, s));
