@@ -86,8 +86,11 @@ typedef struct sylv_pcg_opts {
                               (0 = 1e-5)                                                          */
     int32_t refine_max;    /* mixed: maximum number of float64 refinement steps (0 = 8)          */
     int32_t precond;       /* SYLV_PC_NONE, SYLV_PC_JACOBI or SYLV_PC_BLOCK                       */
-    int32_t check_every;   /* iterations enqueued between host convergence checks (0 = 16)       */
-    int32_t reserved;
+    int32_t check_every;   /* iterations enqueued between host convergence checks (0 = 8)        */
+    int32_t block;         /* 1: block CG over the nrhs right-hand sides of each problem
+                              (nrhs must be 2, 4 or 8): s x s Gram matrices in float64, alpha and
+                              beta from s x s Cholesky solves, converged columns deflated;
+                              0: independent CG per right-hand side                              */
 } sylv_pcg_opts;
 
 /* Per-solve result, written by the device into caller memory (DEVICE pointer). */

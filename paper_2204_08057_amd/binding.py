@@ -55,7 +55,7 @@ class _Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("inner_tol", ctypes.c_double),
                 ("refine_max", ctypes.c_int32), ("precond", ctypes.c_int32),
-                ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("block", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -190,10 +190,11 @@ class SolveOptions:
     refine_max: int = 0
     precond: int = SYLV_PC_BLOCK
     check_every: int = 0
+    block: int = 0
 
     def c_struct(self) -> _Opts:
         return _Opts(self.tol, self.max_iter, self.precision, self.inner_tol, self.refine_max,
-                     self.precond, self.check_every, 0)
+                     self.precond, self.check_every, self.block)
 
 
 def workspace_bytes(problems: Sequence[DeviceProblem], nrhs: int = 1,

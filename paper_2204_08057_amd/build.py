@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsylv.so")
-SOURCES = ["sylv_kernels.hip", "sylv_api.hip"]
+SOURCES = ["sylv_kernels.hip", "sylv_block.hip", "sylv_api.hip"]
 ARCH = os.environ.get("SYLV_OFFLOAD_ARCH", "gfx950")
 
 
@@ -38,7 +38,7 @@ def flags():
     ]
 
 
-def build(verbose: bool = True, jobs: int = 2) -> str:
+def build(verbose: bool = True, jobs: int = 3) -> str:
     """Compile every source to an object in a temp dir, then link the shared library."""
     cc = hipcc()
     tmp = tempfile.mkdtemp(prefix="sylv_build_")

@@ -49,6 +49,10 @@ int tiles_for(int ny, int nx, int rows) {
 }
 int chunks_for(int n_pix) { return (n_pix + kChunk - 1) / kChunk; }
 
+// The block apply keeps every column's direction at its output pixels in registers, so it runs
+// with 2 rows per lane.
+constexpr int kBlockRows = 2;
+
 struct ProbLayout {
     size_t coef, M64, M32, P64, P32;
 };
@@ -59,6 +63,9 @@ struct InstLayout {
 struct Layout {
     std::vector<ProbLayout> prob;
     std::vector<InstLayout> inst;
+    std::vector<size_t> gstate, gpart;   // block CG: per-group state and partials
+    std::vector<int> gnred;
+    size_t groups = 0, gprefix = 0;
     size_t table = 0, tprefix = 0, count = 0, gpartial = 0;
     size_t total = 0;
 };
@@ -116,6 +123,21 @@ bool make_layout(const sylv_problem *probs, int nprob, int nrhs, bool solve, Lay
                 I.p32b = off; off = align_up(off + sizeof(float) * vk);
                 I.q32 = off; off = align_up(off + sizeof(float) * vk);
                 I.d32 = off; off = align_up(off + sizeof(float) * vk);
+            }
+        }
+        // block CG tables (sized whenever a call could use them)
+        L.groups = off; off = align_up(off + sizeof(Group) * nprob);
+        L.gprefix = off; off = align_up(off + sizeof(int) * 3 * (nprob + 1));
+        L.gstate.resize(nprob);
+        L.gpart.resize(nprob);
+        L.gnred.resize(nprob);
+        if (block_rhs_supported(nrhs)) {
+            for (int g = 0; g < nprob; ++g) {
+                const int ny = (int)probs[g].ny, nx = (int)probs[g].nx;
+                const int n = ny * nx;
+                L.gnred[g] = std::max(tiles_for(ny, nx, 2), (n + kBlockPix - 1) / kBlockPix);
+                L.gstate[g] = off; off = align_up(off + sizeof(GroupState));
+                L.gpart[g] = off;  off = align_up(off + sizeof(double) * kBlockQ * L.gnred[g]);
             }
         }
         if (nprob == 1 && nrhs == 1) {
@@ -263,6 +285,35 @@ int run_cg_loop(const InstSet &set, int k, int mixed, int chunk, int max_iter, H
     return SYLV_OK;
 }
 
+// Block-CG iterations: P = Z + P beta (from the second iteration), Q = G P with the P^T Q
+// Gram, alpha, the block update with the R^T Z Gram, beta and the per-column stopping test.
+int run_block_loop(const GroupSet &gset, const InstSet &set, int k, int mixed, int chunk,
+                   int max_iter, HostFlags *f, hipStream_t s) {
+    int it = 0, rc;
+    auto enqueue_batch = [&](int slot) -> int {
+        for (int c = 0; c < chunk && it <= max_iter; ++c, ++it) {
+            if (it > 0) HIP_TRY(launch_bdir(gset, k, mixed, it, s));
+            HIP_TRY(launch_bapply(gset, k, mixed, it, s));
+            HIP_TRY(launch_bgram(gset, 1, mixed, 0.0, max_iter, s));
+            HIP_TRY(launch_bupdate(gset, k, mixed, it, s));
+            HIP_TRY(launch_bgram(gset, 2, mixed, 0.0, max_iter, s));
+        }
+        return post_count(set, mixed, f, slot, s);
+    };
+    if ((rc = enqueue_batch(0))) return rc;
+    for (int cur = 0;; cur ^= 1) {
+        const bool more = it <= max_iter;
+        if (more && (rc = enqueue_batch(cur ^ 1))) return rc;
+        int running = 0;
+        if ((rc = wait_count(f, cur, running))) return rc;
+        if (running == 0 || !more) {
+            if (more && (rc = wait_count(f, cur ^ 1, running))) return rc;
+            break;
+        }
+    }
+    return SYLV_OK;
+}
+
 int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
                const double *Bextra, double *X, const sylv_pcg_opts *opts,
                sylv_pcg_stats *stats, void *ws, size_t ws_bytes, hipStream_t s, Layout &L) {
@@ -346,6 +397,53 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
     set.rows64 = rows64;
     set.rows32 = rows32;
 
+    // block CG groups: one per problem, its nrhs instances in order
+    const bool block = opts->block != 0;
+    if (block && !block_rhs_supported(nrhs)) {
+        set_err("block CG needs nrhs in {2, 4, 8} (got %d)", nrhs);
+        return SYLV_E_INVALID;
+    }
+    GroupSet gset;
+    memset(&gset, 0, sizeof(gset));
+    if (block) {
+        std::vector<Group> grp(nprob);
+        std::vector<int> gpre(3 * (nprob + 1));
+        int *gt = gpre.data(), *gt32 = gt + (nprob + 1), *gc = gt32 + (nprob + 1);
+        gt[0] = gt32[0] = gc[0] = 0;
+        for (int g = 0; g < nprob; ++g) {
+            const int ny = (int)probs[g].ny, nx = (int)probs[g].nx;
+            Group G;
+            memset(&G, 0, sizeof(G));
+            G.inst0 = g * nrhs;
+            G.ntiles = tiles_for(ny, nx, kBlockRows);
+            G.ntiles32 = tiles_for(ny, nx, kBlockRows);
+            G.nchunks = (ny * nx + kBlockPix - 1) / kBlockPix;
+            G.nred = L.gnred[g];
+            G.gs = reinterpret_cast<GroupState *>(base + L.gstate[g]);
+            G.partial = reinterpret_cast<double *>(base + L.gpart[g]);
+            grp[g] = G;
+            gt[g + 1] = gt[g] + G.ntiles;
+            gt32[g + 1] = gt32[g] + G.ntiles32;
+            gc[g + 1] = gc[g] + G.nchunks;
+        }
+        HIP_TRY(hipMemcpyAsync(base + L.groups, grp.data(), sizeof(Group) * nprob,
+                               hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(base + L.gprefix, gpre.data(), sizeof(int) * 3 * (nprob + 1),
+                               hipMemcpyHostToDevice, s));
+        gset.table = set.table;
+        gset.groups = reinterpret_cast<const Group *>(base + L.groups);
+        gset.gtprefix = reinterpret_cast<const int *>(base + L.gprefix);
+        gset.gtprefix32 = gset.gtprefix + (nprob + 1);
+        gset.gcprefix = gset.gtprefix32 + (nprob + 1);
+        gset.ngroup = nprob;
+        gset.s = nrhs;
+        gset.total_tiles = gt[nprob];
+        gset.total_tiles32 = gt32[nprob];
+        gset.total_chunks = gc[nprob];
+        gset.rows64 = kBlockRows;
+        gset.rows32 = kBlockRows;
+    }
+
     // operator set-up and right-hand sides
     for (int g = 0; g < nprob; ++g) {
         rc = prepare_operator(probs[g], L.prob[g], base, pc, s);
@@ -361,27 +459,38 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
     if ((rc = host_flags(flags))) return rc;
     HIP_TRY(launch_resid(set, k, 0, s));   // r0 = b - G x0, ||b||, ||r0||
     HIP_TRY(launch_resid_fin(set, 0, s));
+    const double inner_tol = opts->inner_tol > 0.0 ? opts->inner_tol : 1e-5;
+    auto start_run = [&]() -> int {
+        if (block) {
+            HIP_TRY(launch_bpinit(gset, k, mixed, s));
+            HIP_TRY(launch_bgram(gset, 0, mixed, inner_tol, opts->max_iter, s));
+        } else {
+            HIP_TRY(launch_pinit(set, k, mixed, inner_tol, opts->max_iter, s));
+        }
+        return SYLV_OK;
+    };
+    auto loop = [&]() -> int {
+        return block ? run_block_loop(gset, set, k, mixed, chunk, opts->max_iter, flags, s)
+                     : run_cg_loop(set, k, mixed, chunk, opts->max_iter, flags, s);
+    };
     if (!mixed) {
-        HIP_TRY(launch_pinit(set, k, 0, 0.0, opts->max_iter, s));
-        rc = run_cg_loop(set, k, 0, chunk, opts->max_iter, flags, s);
-        if (rc) return rc;
+        if ((rc = start_run())) return rc;
+        if ((rc = loop())) return rc;
         HIP_TRY(launch_resid(set, k, 1, s));   // true residual of the result
         HIP_TRY(launch_resid_fin(set, 1, s));
     } else {
-        const double inner_tol = opts->inner_tol > 0.0 ? opts->inner_tol : 1e-5;
         const int refine_max = opts->refine_max > 0 ? opts->refine_max : 8;
         // One refinement step: float32 inner PCG on the current float64 residual, x += d, new
         // float64 residual.  Steps of finished instances are no-ops on the device, so the next
         // step is queued before the host learns whether this one finished.
-        HIP_TRY(launch_pinit(set, k, 1, inner_tol, opts->max_iter, s));
+        if ((rc = start_run())) return rc;
         for (int o = 0; o < refine_max; ++o) {
-            rc = run_cg_loop(set, k, 1, chunk, opts->max_iter, flags, s);
-            if (rc) return rc;
+            if ((rc = loop())) return rc;
             HIP_TRY(launch_refine_axpy(set, k, s));
             HIP_TRY(launch_resid(set, k, 2, s));   // float64 residual of the new x
             HIP_TRY(launch_resid_fin(set, 2, s));
             if ((rc = post_count(set, 0, flags, 2, s))) return rc;
-            if (o + 1 < refine_max) HIP_TRY(launch_pinit(set, k, 1, inner_tol, opts->max_iter, s));
+            if (o + 1 < refine_max && (rc = start_run())) return rc;
             int running = 0;
             if ((rc = wait_count(flags, 2, running))) return rc;
             if (running == 0) break;

@@ -1,0 +1,737 @@
+// Block conjugate gradients over the s right-hand sides of one grid (O'Leary's block CG, the
+// block analogue of Alg. 2 with the same per-pixel block-Jacobi preconditioner), for batches of
+// perturbation-optimisation right-hand sides.  Per iteration:
+//   P = Z + P beta                 (k_bdir; P = Z at the start)
+//   Q = G P,  P^T Q                (k_bapply: the s applies share every read of the per-pixel
+//                                   mixing block; Gram partials in float64)
+//   alpha = (P^T Q)^-1 (R^T Z)     (k_bgram, phase 1)
+//   X += P alpha, R -= Q alpha, Z = Minv R, R^T Z, ||r_c||^2   (k_bupdate)
+//   beta = (R^T Z)_old^-1 (R^T Z)_new, per-column stopping test (k_bgram, phase 2)
+// s x s systems are solved by Cholesky in float64 on the active columns only: a column that has
+// converged leaves the block (deflation).  If a Gram matrix is not numerically positive
+// definite the group switches to independent CG for every column (diagonal alpha and beta,
+// after one restart with beta = 0).
+//
+// Reductions follow the same fence-free scheme as the single-vector kernels: every workgroup
+// writes fixed-order partials and the one-workgroup Gram kernel reduces them in fixed order.
+
+#include "sylv_device.h"
+
+namespace sylv {
+namespace {
+using namespace dev;
+
+template <int S>
+constexpr int gram_n() { return S * (S + 1) / 2; }
+
+// Accumulate one quantity into the workgroup's per-wavefront slot (lane 0 of each wavefront
+// owns its slot, so no two threads write the same LDS word).
+__device__ __forceinline__ void wave_accum(double v, double *slot) {
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) *slot += v;
+}
+
+// Write NQ per-workgroup partials from the [4 wavefronts][NQ] LDS accumulators.
+template <int NQ>
+__device__ __forceinline__ void flush_partials(const double (&acc)[kBlock / 64][NQ],
+                                               double *partial, int nred, int blk) {
+    __syncthreads();
+    GAS double *pp = gp(partial);
+    for (int i = threadIdx.x; i < NQ; i += kBlock)
+        pp[(size_t)i * nred + blk] = (acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]);
+}
+
+template <int NQ>
+__device__ __forceinline__ void zero_acc(double (&acc)[kBlock / 64][NQ]) {
+    for (int i = threadIdx.x; i < (kBlock / 64) * NQ; i += kBlock) (&acc[0][0])[i] = 0.0;
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------------------------
+// Start of a block run: per column r, r_r = rounded residual (float32 inner run) or the float64
+// residual, z_r = Minv r_r, P_0 = Z_0, and the partials of R^T Z and ||r_r||^2.
+template <typename T, int K, int S>
+__global__ __launch_bounds__(kBlock) void k_bpinit(const Inst *__restrict__ tab,
+                                                   const Group *__restrict__ groups,
+                                                   const int *__restrict__ gcprefix, int ngroup,
+                                                   int nb) {
+    constexpr int NQ = gram_n<S>() + S;
+    const int L = xcd_remap(blockIdx.x, nb);
+    const int g = find_inst(gcprefix, ngroup, L);
+    const Group &G = groups[g];
+    const int chunk = L - gcprefix[g];
+    const Inst &I0 = tab[G.inst0];
+    const int n_pix = I0.n_pix;
+    const int pix = chunk * kBlockPix + threadIdx.x;
+    const bool valid = pix < n_pix;
+    __shared__ double acc[kBlock / 64][NQ];
+    zero_acc<NQ>(acc);
+    T rv[S][K], zv[S][K];
+#pragma unroll
+    for (int r = 0; r < S; ++r) {
+        const Inst &I = tab[G.inst0 + r];
+        const bool use = valid && !I.st->done;   // outer run finished / initial residual zero
+#pragma unroll
+        for (int j = 0; j < K; ++j) rv[r][j] = 0;
+        if (use) {
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const size_t o = (size_t)j * n_pix + pix;
+                rv[r][j] = (T)gp(I.r)[o];
+                if constexpr (sizeof(T) == 4) {
+                    gp(I.r32)[o] = rv[r][j];
+                    gp(I.d32)[o] = 0.0f;
+                }
+            }
+        }
+        precond_pixel<T, K>(I0.pc, Sel<T>::P(I0), n_pix, valid ? pix : 0, rv[r], zv[r]);
+        if (use) {
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const size_t o = (size_t)j * n_pix + pix;
+                Sel<T>::z(I)[o] = zv[r][j];
+                Sel<T>::p(I, 0)[o] = zv[r][j];
+            }
+        }
+    }
+    const int wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int a = 0; a < S; ++a) {
+#pragma unroll
+        for (int b = a; b < S; ++b) {
+            double v = 0.0;
+#pragma unroll
+            for (int j = 0; j < K; ++j) v += (double)rv[a][j] * (double)zv[b][j];
+            wave_accum(v, &acc[wid][pidx<S>(a, b)]);
+        }
+        double v = 0.0;
+#pragma unroll
+        for (int j = 0; j < K; ++j) v += (double)rv[a][j] * (double)rv[a][j];
+        wave_accum(v, &acc[wid][gram_n<S>() + a]);
+    }
+    flush_partials<NQ>(acc, G.partial, G.nred, chunk);
+}
+
+// P_it = Z + P_(it-1) beta on the active columns (it >= 1).
+template <typename T, int K, int S>
+__global__ __launch_bounds__(kBlock) void k_bdir(const Inst *__restrict__ tab,
+                                                 const Group *__restrict__ groups,
+                                                 const int *__restrict__ gcprefix, int ngroup,
+                                                 int nb, int it) {
+    const int L = xcd_remap(blockIdx.x, nb);
+    const int g = find_inst(gcprefix, ngroup, L);
+    const Group &G = groups[g];
+    const GroupState *gs = G.gs;
+    if (gs->done) return;
+    const int chunk = L - gcprefix[g];
+    const Inst &I0 = tab[G.inst0];
+    const int n_pix = I0.n_pix;
+    const int pix = chunk * kBlockPix + threadIdx.x;
+    if (pix >= n_pix) return;
+    int act[S];
+#pragma unroll
+    for (int r = 0; r < S; ++r) act[r] = gs->active[r];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const size_t o = (size_t)j * n_pix + pix;
+        T po[S];
+#pragma unroll
+        for (int c = 0; c < S; ++c) po[c] = act[c] ? Sel<T>::p(tab[G.inst0 + c], it - 1)[o] : (T)0;
+#pragma unroll
+        for (int r = 0; r < S; ++r) {
+            if (!act[r]) continue;
+            const Inst &I = tab[G.inst0 + r];
+            T v = Sel<T>::z(I)[o];
+#pragma unroll
+            for (int c = 0; c < S; ++c)
+                if (act[c]) v += (T)gs->beta[c][r] * po[c];
+            Sel<T>::p(I, it)[o] = v;
+        }
+    }
+}
+
+// Q = G P for the active columns of a group, sharing the per-pixel mixing blocks, and the
+// partials of P^T Q.  Same tiling and LDS staging as the single-vector apply.
+template <typename T, int K, int R, int S>
+__global__ __launch_bounds__(kBlock) void k_bapply(const Inst *__restrict__ tab,
+                                                   const Group *__restrict__ groups,
+                                                   const int *__restrict__ gtprefix, int ngroup,
+                                                   int nb, int it) {
+    constexpr int MK = K * (K + 1) / 2;
+    constexpr int LH = kWavesY * R + 4;
+    constexpr int LW = kTileX + 4;
+    constexpr int RPW = LH / kWavesY;
+    constexpr int NQ = gram_n<S>();
+    const int L = xcd_remap(blockIdx.x, nb);
+    const int g = find_inst(gtprefix, ngroup, L);
+    const Group &G = groups[g];
+    const GroupState *gs = G.gs;
+    if (gs->done) return;
+    const int tile = L - gtprefix[g];
+    const Inst &I0 = tab[G.inst0];
+    const int nx = I0.nx, ny = I0.ny, n_pix = I0.n_pix;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int tile_x = tile % I0.tiles_x, tile_y = tile / I0.tiles_x;
+    const int x0 = tile_x * kTileX, y0 = tile_y * kWavesY * R;
+    const int ix = x0 + tx;
+    const int iy0 = y0 + ty * R;
+    const bool active = (ix < nx) && (iy0 < ny);
+
+    __shared__ double acc[kBlock / 64][NQ];
+    __shared__ T lds[K][LH][LW];
+    zero_acc<NQ>(acc);
+
+    const int cmain = wrapi(x0 + tx, nx);
+    const int hitem = ty * 64 + tx;
+    const int hr = hitem >> 2, hc = hitem & 3;
+    const int hcol = (hc < 2) ? hc : (kTileX + hc);
+    const bool hvalid = hitem < 4 * LH;
+    const int hoff = hvalid ? wrapi(y0 - 2 + hr, ny) * nx + wrapi(x0 - 2 + hcol, nx) : 0;
+    int soff[RPW];
+#pragma unroll
+    for (int rr = 0; rr < RPW; ++rr) soff[rr] = wrapi(y0 - 2 + rr * kWavesY + ty, ny) * nx + cmain;
+
+    T m[R][MK];
+    {
+        const GAS T *M = Sel<T>::M(I0);
+        const int ixc = ix < nx ? ix : 0;
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const int pix = (iy0 + t < ny ? iy0 + t : 0) * nx + ixc;
+#pragma unroll
+            for (int e = 0; e < MK; ++e) m[t][e] = M[(size_t)e * n_pix + pix];
+        }
+    }
+    T pc[S][K][R];   // centres of every column's direction at this lane's output pixels
+    const int wid = ty;
+#pragma unroll
+    for (int b = 0; b < S; ++b) {
+        if (!gs->active[b]) continue;
+        const Inst &Ib = tab[G.inst0 + b];
+        const GAS T *u = Sel<T>::p(Ib, it);
+        T sa[K][RPW], ha[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+#pragma unroll
+            for (int rr = 0; rr < RPW; ++rr) sa[j][rr] = u[(size_t)j * n_pix + soff[rr]];
+            ha[j] = hvalid ? u[(size_t)j * n_pix + hoff] : (T)0;
+        }
+        __syncthreads();   // previous column's stencil reads are done
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+#pragma unroll
+            for (int rr = 0; rr < RPW; ++rr) lds[j][rr * kWavesY + ty][tx + 2] = sa[j][rr];
+            if (hvalid) lds[j][hr][hcol] = ha[j];
+        }
+        __syncthreads();
+        T q[K][R];
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+#pragma unroll
+            for (int t = 0; t < R; ++t) q[j][t] = 0;
+        if (active) {
+            const int lr = ty * R;
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const double *cj = I0.coef + j * kCoefStride;
+                const T c0 = (T)cj[0], c1 = (T)cj[1], cd = (T)cj[2], c2 = (T)cj[3];
+                T cc[R + 4], l1[R + 2], r1[R + 2], l2[R], r2[R];
+#pragma unroll
+                for (int t = 0; t < R + 4; ++t) cc[t] = lds[j][lr + t][tx + 2];
+#pragma unroll
+                for (int t = 0; t < R + 2; ++t) {
+                    l1[t] = lds[j][lr + t + 1][tx + 1];
+                    r1[t] = lds[j][lr + t + 1][tx + 3];
+                }
+#pragma unroll
+                for (int t = 0; t < R; ++t) {
+                    l2[t] = lds[j][lr + t + 2][tx];
+                    r2[t] = lds[j][lr + t + 2][tx + 4];
+                }
+#pragma unroll
+                for (int t = 0; t < R; ++t) {
+                    const T n4 = (cc[t + 1] + cc[t + 3]) + (l1[t + 1] + r1[t + 1]);
+                    const T d4 = (l1[t] + r1[t]) + (l1[t + 2] + r1[t + 2]);
+                    const T f4 = (cc[t] + cc[t + 4]) + (l2[t] + r2[t]);
+                    q[j][t] = c0 * cc[t + 2] + c1 * n4 + cd * d4 + c2 * f4;
+                    pc[b][j][t] = (iy0 + t < ny) ? cc[t + 2] : (T)0;
+                }
+            }
+            GAS T *qq = Sel<T>::q(Ib);
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                if (iy0 + t < ny) {
+                    const int pix = (iy0 + t) * nx + ix;
+                    T tmp[K];
+#pragma unroll
+                    for (int j = 0; j < K; ++j) {
+                        T sum = q[j][t];
+#pragma unroll
+                        for (int i = 0; i < K; ++i) sum += m[t][pidx<K>(j, i)] * pc[b][i][t];
+                        tmp[j] = sum;
+                    }
+#pragma unroll
+                    for (int j = 0; j < K; ++j) {
+                        q[j][t] = tmp[j];
+                        qq[(size_t)j * n_pix + pix] = tmp[j];
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < K; ++j) q[j][t] = 0;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+#pragma unroll
+                for (int t = 0; t < R; ++t) pc[b][j][t] = 0;
+        }
+        // Gram entries (a, b), a <= b, with this column's q
+#pragma unroll
+        for (int a = 0; a <= b; ++a) {
+            if (!gs->active[a]) continue;
+            double v = 0.0;
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+#pragma unroll
+                for (int t = 0; t < R; ++t) v += (double)pc[a][j][t] * (double)q[j][t];
+            wave_accum(v, &acc[wid][pidx<S>(a, b)]);
+        }
+    }
+    flush_partials<NQ>(acc, G.partial, G.nred, tile);
+}
+
+// X += P alpha, R -= Q alpha, Z = Minv R on the active columns; partials of R^T Z, ||r_c||^2.
+template <typename T, int K, int S>
+__global__ __launch_bounds__(kBlock) void k_bupdate(const Inst *__restrict__ tab,
+                                                    const Group *__restrict__ groups,
+                                                    const int *__restrict__ gcprefix, int ngroup,
+                                                    int nb, int it) {
+    constexpr int NQ = gram_n<S>() + S;
+    const int L = xcd_remap(blockIdx.x, nb);
+    const int g = find_inst(gcprefix, ngroup, L);
+    const Group &G = groups[g];
+    const GroupState *gs = G.gs;
+    if (gs->done) return;
+    const int chunk = L - gcprefix[g];
+    const Inst &I0 = tab[G.inst0];
+    const int n_pix = I0.n_pix;
+    const int pix = chunk * kBlockPix + threadIdx.x;
+    const bool valid = pix < n_pix;
+    __shared__ double acc[kBlock / 64][NQ];
+    zero_acc<NQ>(acc);
+    int act[S];
+#pragma unroll
+    for (int r = 0; r < S; ++r) act[r] = gs->active[r];
+    T rv[S][K], zv[S][K];
+#pragma unroll
+    for (int r = 0; r < S; ++r)
+#pragma unroll
+        for (int j = 0; j < K; ++j) rv[r][j] = zv[r][j] = 0;
+    if (valid) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const size_t o = (size_t)j * n_pix + pix;
+            T pj[S], qj[S];
+#pragma unroll
+            for (int c = 0; c < S; ++c) {
+                pj[c] = act[c] ? Sel<T>::p(tab[G.inst0 + c], it)[o] : (T)0;
+                qj[c] = act[c] ? Sel<T>::q(tab[G.inst0 + c])[o] : (T)0;
+            }
+#pragma unroll
+            for (int r = 0; r < S; ++r) {
+                if (!act[r]) continue;
+                const Inst &I = tab[G.inst0 + r];
+                T xv = Sel<T>::x(I)[o];
+                T rr = Sel<T>::r(I)[o];
+#pragma unroll
+                for (int c = 0; c < S; ++c) {
+                    if (!act[c]) continue;
+                    const T a = (T)gs->alpha[c][r];
+                    xv += a * pj[c];
+                    rr -= a * qj[c];
+                }
+                Sel<T>::x(I)[o] = xv;
+                Sel<T>::r(I)[o] = rr;
+                rv[r][j] = rr;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < S; ++r) {
+            if (!act[r]) continue;
+            const Inst &I = tab[G.inst0 + r];
+            precond_pixel<T, K>(I0.pc, Sel<T>::P(I0), n_pix, pix, rv[r], zv[r]);
+#pragma unroll
+            for (int j = 0; j < K; ++j) Sel<T>::z(I)[(size_t)j * n_pix + pix] = zv[r][j];
+        }
+    }
+    const int wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int a = 0; a < S; ++a) {
+        if (!act[a]) continue;
+#pragma unroll
+        for (int b = a; b < S; ++b) {
+            if (!act[b]) continue;
+            double v = 0.0;
+#pragma unroll
+            for (int j = 0; j < K; ++j) v += (double)rv[a][j] * (double)zv[b][j];
+            wave_accum(v, &acc[wid][pidx<S>(a, b)]);
+        }
+        double v = 0.0;
+#pragma unroll
+        for (int j = 0; j < K; ++j) v += (double)rv[a][j] * (double)rv[a][j];
+        wave_accum(v, &acc[wid][gram_n<S>() + a]);
+    }
+    flush_partials<NQ>(acc, G.partial, G.nred, chunk);
+}
+
+// ---- small dense float64 algebra (one thread) -----------------------------------------------
+// Cholesky of the n x n leading block of a (row stride kMaxS), in place (lower triangle).
+// Fails when a pivot is not positive or falls below 1e-13 of the largest diagonal entry.
+__device__ bool chol_small(double (&a)[kMaxS][kMaxS], int n) {
+    double dmax = 0.0;
+    for (int i = 0; i < n; ++i) dmax = fmax(dmax, fabs(a[i][i]));
+    for (int c = 0; c < n; ++c) {
+        double s = a[c][c];
+        for (int t = 0; t < c; ++t) s -= a[c][t] * a[c][t];
+        if (!(s > 1e-13 * dmax) || !isfinite(s)) return false;
+        const double d = sqrt(s);
+        a[c][c] = d;
+        for (int r = c + 1; r < n; ++r) {
+            double v = a[r][c];
+            for (int t = 0; t < c; ++t) v -= a[r][t] * a[c][t];
+            a[r][c] = v / d;
+        }
+    }
+    return true;
+}
+
+// Solve (L L^T) X = B for n x n B in place (columns independently).
+__device__ void chol_solve_small(const double (&l)[kMaxS][kMaxS], double (&b)[kMaxS][kMaxS],
+                                 int n) {
+    for (int col = 0; col < n; ++col) {
+        for (int r = 0; r < n; ++r) {
+            double v = b[r][col];
+            for (int t = 0; t < r; ++t) v -= l[r][t] * b[t][col];
+            b[r][col] = v / l[r][r];
+        }
+        for (int r = n - 1; r >= 0; --r) {
+            double v = b[r][col];
+            for (int t = r + 1; t < n; ++t) v -= l[t][r] * b[t][col];
+            b[r][col] = v / l[r][r];
+        }
+    }
+}
+
+// Group-level reductions and the s x s recurrences (one workgroup per group).
+//  phase 0: start of a run (after k_bpinit): R^T Z, per-column thresholds and active set
+//  phase 1: alpha = (P^T Q)^-1 R^T Z on the active set (after k_bapply)
+//  phase 2: per-column stopping test, beta = (R^T Z)_old^-1 (R^T Z)_new (after k_bupdate)
+// Column states are mirrored into each instance's DevState (float64 run, or the inner run of
+// the mixed path), which the completion count and the statistics read.
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_bgram(const Inst *__restrict__ tab,
+                                                  const Group *__restrict__ groups, int phase,
+                                                  int mixed, double inner_tol, int max_iter) {
+    constexpr int NG = gram_n<S>();
+    constexpr int NQ = NG + S;
+    const Group &G = groups[blockIdx.x];
+    GroupState *gs = G.gs;
+    if (phase != 0 && gs->done) return;
+    const int nsum = (phase == 1) ? (mixed ? G.ntiles32 : G.ntiles) : G.nchunks;
+    const int nq = (phase == 1) ? NG : NQ;
+    __shared__ double q[NQ];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const GAS double *pp = gp(G.partial);
+    for (int i = wid; i < nq; i += kBlock / 64) {
+        double s = 0.0;
+        for (int b = lane; b < nsum; b += 64) s += pp[(size_t)i * G.nred + b];
+        s = wave_sum(s);
+        if (lane == 0) q[i] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+
+    auto state = [&](int r) -> DevState * {
+        const Inst &I = tab[G.inst0 + r];
+        return mixed ? I.st_in : I.st;
+    };
+    auto finish = [&](int r, int status) {
+        DevState *st = state(r);
+        st->status = status;
+        st->done = 1;
+        st->iter = gs->iter;
+        st->total_iter += gs->iter;
+        gs->active[r] = 0;
+    };
+
+    if (phase == 0) {
+        int nact = 0;
+        for (int r = 0; r < S; ++r) {
+            const Inst &I = tab[G.inst0 + r];
+            DevState *st = state(r);
+            const double rz = q[pidx<S>(r, r)], rr = q[NG + r];
+            double tol = st->tol;
+            bool act;
+            if (mixed) {
+                act = !I.st->done;
+                if (act) {
+                    const double need = 0.3 * sqrt(I.st->thresh / fmax(I.st->rr, 1e-300));
+                    tol = fmin(0.1, fmax(inner_tol, need));
+                }
+                st->tol = tol;
+                st->max_iter = max_iter;
+            } else {
+                act = !st->done;
+            }
+            const double thresh = tol * tol * rr;
+            gs->rr0[r] = rr;
+            gs->rr[r] = rr;
+            gs->thresh[r] = thresh;
+            st->rr0 = rr;
+            st->rr = rr;
+            st->thresh = thresh;
+            st->iter = 0;
+            st->status = SYLV_OK;
+            st->done = act ? 0 : 1;
+            gs->active[r] = act ? 1 : 0;
+            if (act) {
+                if (!isfinite(rr) || !isfinite(rz)) { st->status = SYLV_NONFINITE; st->done = 1; gs->active[r] = 0; }
+                else if (rr <= thresh) { st->done = 1; gs->active[r] = 0; }
+                else if (!(rz > 0.0)) { st->status = SYLV_BREAKDOWN; st->done = 1; gs->active[r] = 0; }
+            }
+            nact += gs->active[r];
+        }
+        for (int a = 0; a < S; ++a)
+            for (int b = 0; b < S; ++b) {
+                gs->rz[a][b] = q[pidx<S>(a, b)];
+                gs->alpha[a][b] = 0.0;
+                gs->beta[a][b] = 0.0;
+            }
+        gs->mode = BM_BLOCK;
+        gs->restart = 0;
+        gs->iter = 0;
+        gs->done = nact == 0;
+        return;
+    }
+
+    int A[kMaxS], n = 0;
+    for (int r = 0; r < S; ++r)
+        if (gs->active[r]) A[n++] = r;
+
+    if (phase == 1) {
+        double alpha[kMaxS][kMaxS];
+        for (int a = 0; a < kMaxS; ++a)
+            for (int b = 0; b < kMaxS; ++b) alpha[a][b] = 0.0;
+        bool ok = false;
+        if (gs->mode == BM_BLOCK) {
+            double l[kMaxS][kMaxS], x[kMaxS][kMaxS];
+            for (int a = 0; a < n; ++a)
+                for (int b = 0; b < n; ++b) {
+                    l[a][b] = q[pidx<S>(A[a], A[b])];
+                    x[a][b] = gs->rz[A[a]][A[b]];
+                }
+            ok = chol_small(l, n);
+            if (ok) {
+                chol_solve_small(l, x, n);
+                for (int a = 0; a < n; ++a)
+                    for (int b = 0; b < n; ++b) {
+                        if (!isfinite(x[a][b])) ok = false;
+                        alpha[A[a]][A[b]] = x[a][b];
+                    }
+            }
+            if (!ok) {
+                gs->mode = BM_DIAG;
+                gs->restart = 1;
+                for (int a = 0; a < kMaxS; ++a)
+                    for (int b = 0; b < kMaxS; ++b) alpha[a][b] = 0.0;
+            }
+        }
+        if (gs->mode == BM_DIAG) {
+            for (int a = 0; a < n; ++a) {
+                const int r = A[a];
+                const double pq = q[pidx<S>(r, r)];
+                if (!isfinite(pq)) finish(r, SYLV_NONFINITE);
+                else if (!(pq > 0.0)) finish(r, SYLV_BREAKDOWN);
+                else alpha[r][r] = gs->rz[r][r] / pq;
+            }
+        }
+        for (int a = 0; a < S; ++a)
+            for (int b = 0; b < S; ++b) gs->alpha[a][b] = alpha[a][b];
+        int left = 0;
+        for (int r = 0; r < S; ++r) left += gs->active[r];
+        gs->done = left == 0;
+        return;
+    }
+
+    // phase 2
+    gs->iter += 1;
+    for (int a = 0; a < n; ++a) {
+        const int r = A[a];
+        const double rr = q[NG + r];
+        gs->rr[r] = rr;
+        DevState *st = state(r);
+        st->rr = rr;
+        st->iter = gs->iter;
+        if (!isfinite(rr) || !isfinite(q[pidx<S>(r, r)])) finish(r, SYLV_NONFINITE);
+        else if (rr <= gs->thresh[r]) finish(r, SYLV_OK);
+        else if (gs->iter >= max_iter) finish(r, SYLV_NOT_CONVERGED);
+    }
+    int B[kMaxS], m = 0;
+    for (int r = 0; r < S; ++r)
+        if (gs->active[r]) B[m++] = r;
+    double beta[kMaxS][kMaxS];
+    for (int a = 0; a < kMaxS; ++a)
+        for (int b = 0; b < kMaxS; ++b) beta[a][b] = 0.0;
+    if (gs->restart) {
+        gs->restart = 0;
+    } else if (gs->mode == BM_BLOCK && m > 0) {
+        double l[kMaxS][kMaxS], x[kMaxS][kMaxS];
+        for (int a = 0; a < m; ++a)
+            for (int b = 0; b < m; ++b) {
+                l[a][b] = gs->rz[B[a]][B[b]];
+                x[a][b] = q[pidx<S>(B[a], B[b])];
+            }
+        bool ok = chol_small(l, m);
+        if (ok) {
+            chol_solve_small(l, x, m);
+            for (int a = 0; a < m; ++a)
+                for (int b = 0; b < m; ++b) {
+                    if (!isfinite(x[a][b])) ok = false;
+                    beta[B[a]][B[b]] = x[a][b];
+                }
+        }
+        if (!ok) {   // restart as independent CG
+            gs->mode = BM_DIAG;
+            for (int a = 0; a < kMaxS; ++a)
+                for (int b = 0; b < kMaxS; ++b) beta[a][b] = 0.0;
+        }
+    } else if (gs->mode == BM_DIAG) {
+        for (int a = 0; a < m; ++a) {
+            const int r = B[a];
+            const double rzn = q[pidx<S>(r, r)], rzo = gs->rz[r][r];
+            if (!(rzn > 0.0)) finish(r, SYLV_BREAKDOWN);
+            else beta[r][r] = rzn / rzo;
+        }
+    }
+    for (int a = 0; a < S; ++a)
+        for (int b = 0; b < S; ++b) {
+            gs->rz[a][b] = q[pidx<S>(a, b)];
+            gs->beta[a][b] = beta[a][b];
+        }
+    int left = 0;
+    for (int r = 0; r < S; ++r) left += gs->active[r];
+    gs->done = left == 0;
+}
+
+template <int S>
+struct STag {
+    static constexpr int value = S;
+};
+
+template <typename F>
+hipError_t dispatch_s(int s, F &&fn) {
+    switch (s) {
+        case 2: return fn(STag<2>{});
+        case 4: return fn(STag<4>{});
+        case 8: return fn(STag<8>{});
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, int K, int S>
+hipError_t launch_bapply_t(const GroupSet &gset, int rows, int total, const int *prefix, int it,
+                           hipStream_t st) {
+    const dim3 grid(total);
+    switch (rows) {
+        case 4:
+            hipLaunchKernelGGL((k_bapply<T, K, 4, S>), grid, dim3(kBlock), 0, st, gset.table,
+                               gset.groups, prefix, gset.ngroup, (int)grid.x, it);
+            break;
+        default:
+            hipLaunchKernelGGL((k_bapply<T, K, 2, S>), grid, dim3(kBlock), 0, st, gset.table,
+                               gset.groups, prefix, gset.ngroup, (int)grid.x, it);
+            break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int block_rhs_supported(int s) { return s == 2 || s == 4 || s == 8; }
+
+hipError_t launch_bpinit(const GroupSet &g, int k, int mixed, hipStream_t st) {
+    return dispatch_s(g.s, [&](auto stag) {
+        constexpr int S = decltype(stag)::value;
+        return dispatch_k(k, [&](auto tag) {
+            constexpr int K = decltype(tag)::value;
+            const dim3 grid(g.total_chunks);
+            if (mixed)
+                hipLaunchKernelGGL((k_bpinit<float, K, S>), grid, dim3(kBlock), 0, st, g.table,
+                                   g.groups, g.gcprefix, g.ngroup, (int)grid.x);
+            else
+                hipLaunchKernelGGL((k_bpinit<double, K, S>), grid, dim3(kBlock), 0, st, g.table,
+                                   g.groups, g.gcprefix, g.ngroup, (int)grid.x);
+            return hipGetLastError();
+        });
+    });
+}
+
+hipError_t launch_bgram(const GroupSet &g, int phase, int mixed, double inner_tol, int max_iter,
+                        hipStream_t st) {
+    return dispatch_s(g.s, [&](auto stag) {
+        constexpr int S = decltype(stag)::value;
+        hipLaunchKernelGGL((k_bgram<S>), dim3(g.ngroup), dim3(kBlock), 0, st, g.table, g.groups,
+                           phase, mixed, inner_tol, max_iter);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_bdir(const GroupSet &g, int k, int mixed, int it, hipStream_t st) {
+    return dispatch_s(g.s, [&](auto stag) {
+        constexpr int S = decltype(stag)::value;
+        return dispatch_k(k, [&](auto tag) {
+            constexpr int K = decltype(tag)::value;
+            const dim3 grid(g.total_chunks);
+            if (mixed)
+                hipLaunchKernelGGL((k_bdir<float, K, S>), grid, dim3(kBlock), 0, st, g.table,
+                                   g.groups, g.gcprefix, g.ngroup, (int)grid.x, it);
+            else
+                hipLaunchKernelGGL((k_bdir<double, K, S>), grid, dim3(kBlock), 0, st, g.table,
+                                   g.groups, g.gcprefix, g.ngroup, (int)grid.x, it);
+            return hipGetLastError();
+        });
+    });
+}
+
+hipError_t launch_bapply(const GroupSet &g, int k, int mixed, int it, hipStream_t st) {
+    return dispatch_s(g.s, [&](auto stag) {
+        constexpr int S = decltype(stag)::value;
+        return dispatch_k(k, [&](auto tag) {
+            constexpr int K = decltype(tag)::value;
+            if (mixed)
+                return launch_bapply_t<float, K, S>(g, g.rows32, g.total_tiles32, g.gtprefix32,
+                                                    it, st);
+            return launch_bapply_t<double, K, S>(g, g.rows64, g.total_tiles, g.gtprefix, it, st);
+        });
+    });
+}
+
+hipError_t launch_bupdate(const GroupSet &g, int k, int mixed, int it, hipStream_t st) {
+    return dispatch_s(g.s, [&](auto stag) {
+        constexpr int S = decltype(stag)::value;
+        return dispatch_k(k, [&](auto tag) {
+            constexpr int K = decltype(tag)::value;
+            const dim3 grid(g.total_chunks);
+            if (mixed)
+                hipLaunchKernelGGL((k_bupdate<float, K, S>), grid, dim3(kBlock), 0, st, g.table,
+                                   g.groups, g.gcprefix, g.ngroup, (int)grid.x, it);
+            else
+                hipLaunchKernelGGL((k_bupdate<double, K, S>), grid, dim3(kBlock), 0, st, g.table,
+                                   g.groups, g.gcprefix, g.ngroup, (int)grid.x, it);
+            return hipGetLastError();
+        });
+    });
+}
+
+}  // namespace sylv

@@ -93,6 +93,46 @@ struct InstSet {
 
 inline int packed_size(int k) { return k * (k + 1) / 2; }
 
+// ---- block conjugate gradients over the s right-hand sides of one grid ----------------------
+constexpr int kMaxS = 8;                           // right-hand sides per group
+constexpr int kGramQ = kMaxS * (kMaxS + 1) / 2;    // packed s x s Gram entries
+constexpr int kBlockQ = kGramQ + kMaxS;            // + per-column ||r||^2
+constexpr int kBlockPix = 256;                     // pixels per workgroup, streaming block kernels
+enum BlockMode { BM_BLOCK = 0, BM_DIAG = 1 };
+
+// State of one block-CG run of a group (device memory, written only by the Gram kernel).
+struct GroupState {
+    double rz[kMaxS][kMaxS];     // R^T Z of the current residual block
+    double alpha[kMaxS][kMaxS];  // X += P alpha, R -= Q alpha (row: direction, column: rhs)
+    double beta[kMaxS][kMaxS];   // P <- Z + P beta
+    double rr[kMaxS], rr0[kMaxS], thresh[kMaxS];
+    int32_t active[kMaxS];       // 1 while column r iterates (deflated once converged)
+    int32_t mode;                // BM_BLOCK, or BM_DIAG (independent CG) after a Gram breakdown
+    int32_t restart;             // next direction update restarts (beta = 0)
+    int32_t iter, done;
+};
+
+struct Group {
+    int32_t inst0;               // instance of right-hand side 0 (the group's s instances follow)
+    int32_t ntiles, ntiles32;    // apply tiles (float64 / float32 rows per lane)
+    int32_t nchunks;             // kBlockPix-pixel chunks
+    int32_t nred;                // partial stride
+    int32_t pad;
+    GroupState *gs;
+    double *partial;             // [kBlockQ][nred]
+};
+
+struct GroupSet {
+    const Inst *table;
+    const Group *groups;         // device [ngroup]
+    const int *gtprefix;         // device [ngroup + 1] float64 apply tiles
+    const int *gtprefix32;       // device [ngroup + 1] float32 apply tiles
+    const int *gcprefix;         // device [ngroup + 1] chunks
+    int ngroup, s;
+    int total_tiles, total_tiles32, total_chunks;
+    int rows64, rows32;
+};
+
 // ---- launchers (sylv_kernels.hip) -------------------------------------------------------
 // Every launcher returns the hipError_t of its launch.
 int apply_rows_valid(int rows);
@@ -131,5 +171,14 @@ hipError_t launch_grad(const double *coef, const double *A, const double *W, con
                        double *partial, hipStream_t s);
 int grad_blocks(int n_pix);
 int grad_nv(int k, int f);
+
+// block CG (sylv_block.hip); s in {2, 4, 8}
+int block_rhs_supported(int s);
+hipError_t launch_bpinit(const GroupSet &g, int k, int mixed, hipStream_t st);
+hipError_t launch_bgram(const GroupSet &g, int phase, int mixed, double inner_tol, int max_iter,
+                        hipStream_t st);
+hipError_t launch_bdir(const GroupSet &g, int k, int mixed, int it, hipStream_t st);
+hipError_t launch_bapply(const GroupSet &g, int k, int mixed, int it, hipStream_t st);
+hipError_t launch_bupdate(const GroupSet &g, int k, int mixed, int it, hipStream_t st);
 
 }  // namespace sylv

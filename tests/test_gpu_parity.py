@@ -325,3 +325,94 @@ def test_autograd_function_loss_gradient():
     loss.backward()
     for name, t in (("kappa", kappa), ("tau", tau), ("A", A), ("W", W), ("Y", Y)):
         assert rel(host(t.grad), g_ref[name]) < 1e-7, name
+
+
+# ------------------------------------------------------------------------------------ block CG
+
+def _batched_inputs(probs, nrhs, seed0):
+    Ycat, Bcat, etas = [], [], []
+    for i, p in enumerate(probs):
+        xi, zeta = po_draws(p, nrhs, seed=seed0 + i)
+        eta = opo.perturbation(p, xi, zeta)
+        etas.append(eta)
+        Ycat.append(p.Y.ravel())
+        Bcat.append(eta.ravel())
+    return np.concatenate(Ycat), np.concatenate(Bcat), etas
+
+
+def _check_batched(probs, X, st, nrhs, bextra_list, bound, use_y=True):
+    off = 0
+    for i, p in enumerate(probs):
+        blk = X[off:off + nrhs * p.k * p.n_pix].reshape(nrhs, p.k, p.n_pix)
+        off += nrhs * p.k * p.n_pix
+        b = op.rhs(p) if use_y else 0.0
+        for r in range(nrhs):
+            s = st[i * nrhs + r]
+            assert s["status"] == 0, (i, r, s)
+            xs = osv.solve_dense(p, b=b + bextra_list[i][r])
+            assert rel(blk[r], xs) < bound, (i, r, rel(blk[r], xs))
+
+
+@pytest.mark.parametrize("precision,bound", [(sy.SYLV_PREC_F64, 1e-8), (sy.SYLV_PREC_MIXED, 1e-7)])
+@pytest.mark.parametrize("nrhs", [2, 4, 8])
+def test_block_cg_uneven_grids(precision, bound, nrhs):
+    probs = [make_problem(s0, s1, 3, 5, seed=1300 + i, noise="hetero", mask_frac=0.05)
+             for i, (s0, s1) in enumerate([(16, 16), (20, 28), (9, 33)])]
+    say("block cg", precision, nrhs)
+    Y, B, etas = _batched_inputs(probs, nrhs, 1350)
+    dps = [sy.DeviceProblem.from_numpy(p) for p in probs]
+    opts = sy.SolveOptions(tol=1e-12 if precision == sy.SYLV_PREC_F64 else 1e-11,
+                           precision=precision, block=1)
+    X, st = sy.pcg_solve(dps, Y=dev(Y), Bextra=dev(B), opts=opts, nrhs=nrhs)
+    _check_batched(probs, host(X), st, nrhs, etas, bound)
+
+
+@pytest.mark.parametrize("precision,bound", [(sy.SYLV_PREC_F64, 1e-8), (sy.SYLV_PREC_MIXED, 1e-7)])
+def test_block_cg_degenerate_columns(precision, bound):
+    """A zero right-hand side (converged at once, deflated) and two identical columns (singular
+    Gram matrices: the group falls back to independent CG) must still solve every column."""
+    p = make_problem(18, 22, 3, 4, seed=1400, noise="hetero")
+    nrhs = 4
+    rng = np.random.default_rng(1401)
+    Bx = rng.standard_normal((nrhs, p.k, p.n_pix))
+    Bx[1] = 0.0
+    Bx[3] = Bx[2]
+    say("block cg degenerate", precision)
+    dp = sy.DeviceProblem.from_numpy(p)
+    opts = sy.SolveOptions(tol=1e-12 if precision == sy.SYLV_PREC_F64 else 1e-11,
+                           precision=precision, block=1)
+    X, st = sy.pcg_solve([dp], Bextra=dev(Bx.ravel()), opts=opts, nrhs=nrhs)
+    X = host(X).reshape(nrhs, p.k, p.n_pix)
+    for r in range(nrhs):
+        assert st[r]["status"] == 0, (r, st[r])
+        xs = osv.solve_dense(p, b=Bx[r])
+        if r == 1:
+            assert np.all(X[r] == 0.0)
+        else:
+            assert rel(X[r], xs) < bound, (r, rel(X[r], xs))
+
+
+def test_block_cg_needs_fewer_iterations():
+    """Block CG over 8 right-hand sides searches an 8-times larger Krylov space per iteration:
+    it must not need more iterations than independent CG on the same columns."""
+    p = make_problem(48, 48, 3, 6, seed=1500, noise="hetero")
+    nrhs = 8
+    xi, zeta = po_draws(p, nrhs, seed=1501)
+    eta = opo.perturbation(p, xi, zeta)
+    dp = sy.DeviceProblem.from_numpy(p)
+    say("block vs independent iterations")
+    its = {}
+    for block in (0, 1):
+        opts = sy.SolveOptions(tol=1e-10, block=block)
+        X, st = sy.pcg_solve([dp], Y=dev(p.Y), Bextra=dev(eta.ravel()), opts=opts, nrhs=nrhs)
+        assert all(s["status"] == 0 for s in st)
+        its[block] = max(s["iters"] for s in st)
+    assert its[1] <= its[0]
+
+
+def test_block_cg_rejects_unsupported_block_size():
+    p = make_problem(8, 8, 2, 3, seed=1600)
+    dp = sy.DeviceProblem.from_numpy(p)
+    with pytest.raises(sy.SylvError):
+        sy.pcg_solve([dp], Bextra=dev(np.ones(3 * 2 * 64)), opts=sy.SolveOptions(block=1),
+                     nrhs=3)
