@@ -98,6 +98,97 @@ def cpu_baseline(prob, tol):
                        f"relres {res['relres_true']:.2e}); host reports {os.cpu_count()} CPUs")
 
 
+def time_solves(sy, torch, probs, Y, B, opts, nrhs, steps, warmup):
+    """Median-free mean time of `steps` solves after `warmup`, with the last stats."""
+    plist = probs if isinstance(probs, list) else [probs]
+    ws = torch.empty(sy.workspace_bytes(plist, nrhs, opts), dtype=torch.uint8, device="cuda")
+    for _ in range(warmup):
+        sy.pcg_solve(probs, Y=Y, Bextra=B, opts=opts, nrhs=nrhs, ws=ws, return_stats=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        X, stt = sy.pcg_solve(probs, Y=Y, Bextra=B, opts=opts, nrhs=nrhs, ws=ws,
+                              return_stats=False)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    n = len(plist) * nrhs
+    st = sy.binding._stats_list(stt, n)
+    return ms, st, X
+
+
+def summarize(ms, st):
+    return {"ms": round(ms, 3),
+            "iters_max": max(s["iters"] for s in st),
+            "outer_max": max(s["outer"] for s in st),
+            "relres_true_max": max(s["relres_true"] for s in st),
+            "all_ok": all(s["status"] == 0 for s in st)}
+
+
+def bench_other_workloads(sy, torch, steps, warmup):
+    """The other workloads of the solver, timed the same way (not the headline value)."""
+    from workloads import WORKLOADS, workload
+    out = {}
+    # 2048^2, k = 4, f = 9, 10% masked pixels: mixed precision vs float64
+    prob = workload("masked_2048")[0]
+    dp = sy.DeviceProblem.from_numpy(prob)
+    Y = torch.as_tensor(prob.Y, device="cuda")
+    res = {}
+    for label, prec in (("mixed", sy.SYLV_PREC_MIXED), ("f64", sy.SYLV_PREC_F64)):
+        o = sy.SolveOptions(tol=1e-8, precision=prec)
+        ms, st, _ = time_solves(sy, torch, dp, Y, None, o, 1, steps, warmup)
+        res[label] = summarize(ms, st)
+        log(f"masked_2048 {label}: {res[label]}")
+    out["masked_2048"] = res
+    del dp, Y
+    # 8 uneven grids x 8 perturbation-optimisation right-hand sides (64 posterior samples)
+    probs = workload("batched_8grids")
+    nrhs = WORKLOADS["batched_8grids"]["nrhs"]
+    dps = [sy.DeviceProblem.from_numpy(p) for p in probs]
+    Y = torch.cat([torch.as_tensor(p.Y.ravel(), device="cuda") for p in probs])
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1003)
+    etas = []
+    for p, d in zip(probs, dps):
+        xi = torch.randn((nrhs, p.k, p.n_pix), generator=gen, dtype=torch.float64, device="cuda")
+        zeta = torch.randn((nrhs, p.f, p.n_pix), generator=gen, dtype=torch.float64,
+                           device="cuda")
+        etas.append(sy.po_perturb(d, xi, zeta).reshape(-1))
+    B = torch.cat(etas)
+    res = {}
+    for label, prec, blk in (("block_mixed", sy.SYLV_PREC_MIXED, 1),
+                             ("independent_mixed", sy.SYLV_PREC_MIXED, 0),
+                             ("block_f64", sy.SYLV_PREC_F64, 1),
+                             ("independent_f64", sy.SYLV_PREC_F64, 0)):
+        o = sy.SolveOptions(tol=1e-8, precision=prec, block=blk)
+        ms, st, _ = time_solves(sy, torch, dps, Y, B, o, nrhs, steps, warmup)
+        res[label] = summarize(ms, st)
+        log(f"batched_8grids {label}: {res[label]}")
+    res["right_hand_sides"] = len(probs) * nrhs
+    res["pixels"] = sum(p.n_pix for p in probs)
+    out["batched_8grids"] = res
+    del dps, Y, B
+    # 512^2, k = 4, f = 9: forward solve + adjoint (gradients w.r.t. kappa, tau, A, W, Y)
+    prob = workload("grad_512")[0]
+    dp = sy.DeviceProblem.from_numpy(prob)
+    Y = torch.as_tensor(prob.Y, device="cuda")
+    o = sy.SolveOptions(tol=WORKLOADS["grad_512"]["tol"], precision=sy.SYLV_PREC_F64)
+    ms_f, st, X = time_solves(sy, torch, dp, Y, None, o, 1, steps, warmup)
+    gbar = torch.randn_like(X)
+    ws = torch.empty(sy.workspace_bytes([dp], 1, o), dtype=torch.uint8, device="cuda")
+    for _ in range(warmup):
+        sy.pcg_backward(dp, Y, X, gbar, o, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, g, stb = sy.pcg_backward(dp, Y, X, gbar, o, ws=ws)
+    torch.cuda.synchronize()
+    ms_b = (time.perf_counter() - t0) / steps * 1e3
+    out["grad_512"] = {"forward": summarize(ms_f, st), "backward_ms": round(ms_b, 3),
+                       "backward_iters": stb["iters"], "backward_ok": stb["status"] == 0}
+    log(f"grad_512: {out['grad_512']}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +196,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--apply-reps", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 2048^2, batched and differentiable workloads")
     ap.add_argument("--mode", default="bench", choices=["bench", "pmc"])
     args = ap.parse_args()
     if args.gpus != 1:
@@ -225,6 +318,9 @@ def main():
         },
         "kernel_source_sha": khash,
     }
+    if not args.no_extra:
+        line["other_workloads"] = bench_other_workloads(sy, torch, max(2, args.steps // 2),
+                                                        max(1, args.warmup))
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(prob, tol)
