@@ -474,10 +474,18 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
                      : run_cg_loop(set, k, mixed, chunk, opts->max_iter, flags, s);
     };
     if (!mixed) {
-        if ((rc = start_run())) return rc;
-        if ((rc = loop())) return rc;
-        HIP_TRY(launch_resid(set, k, 1, s));   // true residual of the result
-        HIP_TRY(launch_resid_fin(set, 1, s));
+        // CG, then the recomputed residual; runs whose recomputed residual misses the threshold
+        // are restarted from their current x (residual replacement, at most kMaxRestarts times)
+        for (int run = 0; run <= kMaxRestarts; ++run) {
+            if ((rc = start_run())) return rc;
+            if ((rc = loop())) return rc;
+            HIP_TRY(launch_resid(set, k, 1, s));   // true residual of the result
+            HIP_TRY(launch_resid_fin(set, 1, s));
+            if ((rc = post_count(set, 0, flags, 2, s))) return rc;
+            int reopened = 0;
+            if ((rc = wait_count(flags, 2, reopened))) return rc;
+            if (reopened == 0) break;
+        }
     } else {
         const int refine_max = opts->refine_max > 0 ? opts->refine_max : 8;
         // One refinement step: float32 inner PCG on the current float64 residual, x += d, new

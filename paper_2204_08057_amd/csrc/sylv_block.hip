@@ -84,7 +84,7 @@ __global__ __launch_bounds__(kBlock) void k_bpinit(const Inst *__restrict__ tab,
                 }
             }
         }
-        precond_pixel<T, K>(I0.pc, Sel<T>::P(I0), n_pix, valid ? pix : 0, rv[r], zv[r]);
+        precond_pixel<T, K>(I0.pc, Pcg(I0), n_pix, valid ? pix : 0, rv[r], zv[r]);
         if (use) {
 #pragma unroll
             for (int j = 0; j < K; ++j) {
@@ -360,7 +360,7 @@ __global__ __launch_bounds__(kBlock) void k_bupdate(const Inst *__restrict__ tab
         for (int r = 0; r < S; ++r) {
             if (!act[r]) continue;
             const Inst &I = tab[G.inst0 + r];
-            precond_pixel<T, K>(I0.pc, Sel<T>::P(I0), n_pix, pix, rv[r], zv[r]);
+            precond_pixel<T, K>(I0.pc, Pcg(I0), n_pix, pix, rv[r], zv[r]);
 #pragma unroll
             for (int j = 0; j < K; ++j) Sel<T>::z(I)[(size_t)j * n_pix + pix] = zv[r][j];
         }
@@ -484,13 +484,17 @@ __global__ __launch_bounds__(kBlock) void k_bgram(const Inst *__restrict__ tab,
             } else {
                 act = !st->done;
             }
-            const double thresh = tol * tol * rr;
+            // float64 runs stop against ||b - G x0|| (threshold of the initial residual pass,
+            // kept across restarts); inner runs against their own starting residual
+            const double thresh = mixed ? tol * tol * rr : st->thresh;
             gs->rr0[r] = rr;
             gs->rr[r] = rr;
             gs->thresh[r] = thresh;
-            st->rr0 = rr;
+            if (mixed) {
+                st->rr0 = rr;
+                st->thresh = thresh;
+            }
             st->rr = rr;
-            st->thresh = thresh;
             st->iter = 0;
             st->status = SYLV_OK;
             st->done = act ? 0 : 1;

@@ -132,6 +132,11 @@ template <> struct Sel<double> {
     static __device__ __forceinline__ GAS double *q(const Inst &I) { return gp(I.q); }
     static __device__ __forceinline__ DevState *st(const Inst &I) { return I.st; }
 };
+
+// Preconditioner blocks used inside CG runs: float32 for both precisions.  The preconditioner
+// only has to be fixed and positive definite, so rounding its entries does not change what the
+// solve converges to, and it halves their traffic in float64 runs.
+__device__ __forceinline__ const GAS float *Pcg(const Inst &I) { return gp(I.P32); }
 template <> struct Sel<float> {
     static __device__ __forceinline__ const GAS float *M(const Inst &I) { return gp(I.M32); }
     static __device__ __forceinline__ const GAS float *P(const Inst &I) { return gp(I.P32); }
@@ -143,15 +148,16 @@ template <> struct Sel<float> {
     static __device__ __forceinline__ DevState *st(const Inst &I) { return I.st_in; }
 };
 
-// z = Pinv r at one pixel for the three preconditioner kinds; P planes are read at `pix`.
-template <typename T, int K>
-__device__ __forceinline__ void precond_pixel(int pc, const GAS T *P, int n_pix, int pix,
+// z = Pinv r at one pixel for the three preconditioner kinds; P planes (element type PT) are
+// read at `pix` and the product is formed in T.
+template <typename T, int K, typename PT>
+__device__ __forceinline__ void precond_pixel(int pc, const GAS PT *P, int n_pix, int pix,
                                               const T (&r)[K], T (&z)[K]) {
     if (pc == SYLV_PC_BLOCK) {
         constexpr int MK = K * (K + 1) / 2;
         T pm[MK];
 #pragma unroll
-        for (int e = 0; e < MK; ++e) pm[e] = P[(size_t)e * n_pix + pix];
+        for (int e = 0; e < MK; ++e) pm[e] = (T)P[(size_t)e * n_pix + pix];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             T s = 0;
@@ -161,21 +167,26 @@ __device__ __forceinline__ void precond_pixel(int pc, const GAS T *P, int n_pix,
         }
     } else if (pc == SYLV_PC_JACOBI) {
 #pragma unroll
-        for (int j = 0; j < K; ++j) z[j] = P[(size_t)j * n_pix + pix] * r[j];
+        for (int j = 0; j < K; ++j) z[j] = (T)P[(size_t)j * n_pix + pix] * r[j];
     } else {
 #pragma unroll
         for (int j = 0; j < K; ++j) z[j] = r[j];
     }
 }
 
-template <typename T, int K>
-__device__ __forceinline__ void precond_vec4(int pc, const GAS T *P, int n_pix, int p0,
+template <typename T, int K, typename PT>
+__device__ __forceinline__ void precond_vec4(int pc, const GAS PT *P, int n_pix, int p0,
                                              const T (&r)[K][4], T (&z)[K][4]) {
     if (pc == SYLV_PC_BLOCK) {
         constexpr int MK = K * (K + 1) / 2;
         T pm[MK][4];
 #pragma unroll
-        for (int e = 0; e < MK; ++e) ld4(P + (size_t)e * n_pix + p0, pm[e]);
+        for (int e = 0; e < MK; ++e) {
+            PT tmp[4];
+            ld4(P + (size_t)e * n_pix + p0, tmp);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pm[e][q] = (T)tmp[q];
+        }
 #pragma unroll
         for (int j = 0; j < K; ++j)
 #pragma unroll
@@ -188,10 +199,10 @@ __device__ __forceinline__ void precond_vec4(int pc, const GAS T *P, int n_pix, 
     } else if (pc == SYLV_PC_JACOBI) {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            T d[4];
+            PT d[4];
             ld4(P + (size_t)j * n_pix + p0, d);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) z[j][e] = d[e] * r[j][e];
+            for (int e = 0; e < 4; ++e) z[j][e] = (T)d[e] * r[j][e];
         }
     } else {
 #pragma unroll

@@ -21,6 +21,7 @@ constexpr int kChunk = 1024;     // pixels per workgroup in streaming kernels (4
 // visible without any device-wide fence, and every workgroup obtains bitwise the same scalar.
 enum Slot { SLOT_PQ = 0, SLOT_RZ = 1, SLOT_RR = 2, SLOT_RES_RR = 3, SLOT_RES_BB = 4 };
 constexpr int kNumSlots = 5;
+constexpr int kMaxRestarts = 3;   // residual replacements of a float64 run
 
 // Solver state of one conjugate-gradient run, in device memory.  The scalars of the recurrence
 // (Alg. 2: alpha, beta, <r, z>, ||r||) are formed on the device; the host only reads `done`.
@@ -28,6 +29,8 @@ constexpr int kNumSlots = 5;
 // kernels only (rho is double-buffered by iteration parity for that reason).
 struct DevState {
     double rho[2];   // <r, z> of iterations with even / odd index
+    double alpha[2]; // step lengths of iterations with even / odd index (x is advanced by the
+                     // next iteration's apply, which already reads that direction)
     double rr;       // ||r||^2 at the last test
     double rr0;      // ||r_0||^2
     double bb;       // ||b||^2
@@ -41,7 +44,10 @@ struct DevState {
     int32_t done;    // 1 once the run stopped; every kernel of the loop returns early then
     int32_t total_iter;  // accumulated over inner runs (mixed precision)
     int32_t outer;   // refinement steps
-    int32_t pad[2];
+    int32_t pend;    // stopping decision of the last apply (-1: continue); the apply's own
+                     // workgroups must all finish it (x update), so `done` is only set by the
+                     // following update kernel
+    int32_t pad;
 };
 
 // One solve instance = one (problem, right-hand side) pair.  Pointers are into the caller's

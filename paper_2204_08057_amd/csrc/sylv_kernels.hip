@@ -253,6 +253,23 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
             hb[j] = hvalid ? zz[hoff] : (T)0;
         }
     }
+    // CG (it >= 1): x += alpha_(it-1) p_(it-1) on the staged interior values (each pixel of the
+    // grid is interior to exactly one tile); prefetch x there.
+    T xs[K][RPW];
+    bool xin[RPW];
+    if constexpr (MODE == AM_CG) {
+#pragma unroll
+        for (int rr = 0; rr < RPW; ++rr) {
+            const int r = rr * kWavesY + ty;
+            xin[rr] = it > 0 && r >= 2 && r < LH - 2 && (y0 + r - 2) < ny && (x0 + tx) < nx;
+        }
+        const GAS T *xx = Sel<T>::x(I);
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+#pragma unroll
+            for (int rr = 0; rr < RPW; ++rr)
+                xs[j][rr] = xin[rr] ? xx[(size_t)j * n_pix + soff[rr]] : (T)0;
+    }
     // per-pixel mixing blocks (and, for the residual, b) of this lane's R output pixels
     T m[R][MK];
     double bpre[R][K];
@@ -278,7 +295,9 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
         double s[2];
         consume<2>(I.partial, I.nred, SLOT_RZ, I.nchunks, s);
         const double rz = s[0], rr = s[1];
-        const double thresh = (it == 0) ? st->tol * st->tol * rr : st->thresh;
+        // float64 runs stop against ||b - G x0|| (threshold set by the initial residual pass,
+        // also across restarts); a float32 inner run against its own starting residual
+        const double thresh = (it == 0 && sizeof(T) == 4) ? st->tol * st->tol * rr : st->thresh;
         int status = -1;
         if (!finite_d(rz) || !finite_d(rr)) status = SYLV_NONFINITE;
         else if (rr <= thresh) status = SYLV_OK;
@@ -288,12 +307,17 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
             st->iter = it;
             st->rr = rr;
             st->rho[it & 1] = rz;
-            if (it == 0) { st->rr0 = rr; st->thresh = thresh; }
-            if (status >= 0) {
-                st->status = status;
-                st->done = 1;
-                st->total_iter += it;
-            }
+            st->pend = status;
+            if (it == 0 && sizeof(T) == 4) { st->rr0 = rr; st->thresh = thresh; }
+        }
+        if (it > 0) {   // x_it = x_(it-1) + alpha_(it-1) p_(it-1), also when the run stops here
+            const T a = (T)st->alpha[(it - 1) & 1];
+            GAS T *xx = Sel<T>::x(I);
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+#pragma unroll
+                for (int rr2 = 0; rr2 < RPW; ++rr2)
+                    if (xin[rr2]) xx[(size_t)j * n_pix + soff[rr2]] = xs[j][rr2] + a * sa[j][rr2];
         }
         if (status >= 0) return;
         if (it > 0) beta = (T)(rz / st->rho[(it - 1) & 1]);
@@ -431,16 +455,25 @@ __global__ __launch_bounds__(kBlock) void k_resid_fin(const Inst *__restrict__ t
         }
         st->rr_prev = rr;
     }
+    if (phase == 1) {
+        // residual replacement: a float64 run whose recursive residual met the threshold but
+        // whose recomputed residual did not (rounding drift of the recurrence) is reopened and
+        // restarted from its current x by the host
+        st->outer += 1;
+        if (st->status == SYLV_OK && st->done && finite_d(rr) && rr > st->thresh &&
+            st->outer <= kMaxRestarts)
+            st->done = 0;
+    }
     const double bb = st->bb;
     st->rel_true = (bb > 0.0) ? sqrt(rr / bb) : sqrt(rr);
 }
 
 // ---------------------------------------------------------------------------------------------
 // CG vector update of Alg. 2 (iteration `it`) with the preconditioner fused in:
-//   alpha = rho / <p, q> (from the apply's partials), x += alpha p, r -= alpha q, z = Pinv r,
-//   and the <r, z>, ||r||^2 partials for the next stopping test and beta.
-// T = double: the float64 run (x = solution).  T = float: an inner run of the mixed path
-// (x = d32, the correction).
+//   alpha = rho / <p, q> (from the apply's partials), r -= alpha q, z = Pinv r, and the
+//   <r, z>, ||r||^2 partials for the next stopping test and beta.  The matching x += alpha p is
+//   done by the next iteration's apply, which reads p anyway (alpha is kept in the state).
+// T = double: the float64 run.  T = float: an inner run of the mixed path.
 template <typename T, int K>
 __global__ __launch_bounds__(kBlock) void k_update(const Inst *__restrict__ tab,
                                                    const int *__restrict__ cprefix, int ninst,
@@ -451,46 +484,60 @@ __global__ __launch_bounds__(kBlock) void k_update(const Inst *__restrict__ tab,
     const int chunk = L - cprefix[ii];
     DevState *st = Sel<T>::st(I);
     if (st->done) return;
+    const int pend = st->pend;
+    if (pend >= 0) {   // this iteration's apply stopped the run
+        if (chunk == 0 && threadIdx.x == 0) {
+            st->status = pend;
+            st->done = 1;
+            st->total_iter += it;
+        }
+        return;
+    }
     const int n_pix = I.n_pix;
-    GAS T *x = Sel<T>::x(I);
     GAS T *r = Sel<T>::r(I);
     GAS T *z = Sel<T>::z(I);
-    const GAS T *p = Sel<T>::p(I, it + 1);   // direction written by this iteration's apply
     const GAS T *q = Sel<T>::q(I);
-    const GAS T *P = Sel<T>::P(I);
+    const GAS float *P = Pcg(I);
     const int pc = I.pc;
     const int p0 = chunk * kChunk + threadIdx.x * 4;
+    const bool vec = I.vec4 && p0 + 4 <= n_pix;
+    // issue the vector loads before the reduction of the apply's partials
+    T rv[K][4], qv[K][4];
+    if (vec) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const size_t o = (size_t)j * n_pix + p0;
+            ld4(r + o, rv[j]);
+            ld4(q + o, qv[j]);
+        }
+    }
     double s[1];
     consume<1>(I.partial, I.nred, SLOT_PQ, sizeof(T) == 4 ? I.ntiles32 : I.ntiles, s);
     const double pq = s[0];
     int status = -1;
     if (!finite_d(pq)) status = SYLV_NONFINITE;
     else if (!(pq > 0.0)) status = SYLV_BREAKDOWN;
-    if (status >= 0) {
-        if (chunk == 0 && threadIdx.x == 0) {
+    const double alpha_d = st->rho[it & 1] / pq;
+    if (chunk == 0 && threadIdx.x == 0) {
+        if (status >= 0) {
             st->status = status;
             st->done = 1;
             st->total_iter += it;
+        } else {
+            st->alpha[it & 1] = alpha_d;
         }
-        return;
     }
-    const T alpha = (T)(st->rho[it & 1] / pq);
+    if (status >= 0) return;
+    const T alpha = (T)alpha_d;
     double rz = 0.0, rr = 0.0;
     if (p0 < n_pix) {
-        if (I.vec4 && p0 + 4 <= n_pix) {
-            T rv[K][4], zv[K][4];
+        if (vec) {
+            T zv[K][4];
 #pragma unroll
             for (int j = 0; j < K; ++j) {
-                const size_t o = (size_t)j * n_pix + p0;
-                T xv[4], pv[4], qv[4];
-                ld4(x + o, xv); ld4(p + o, pv); ld4(r + o, rv[j]); ld4(q + o, qv);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    xv[e] += alpha * pv[e];
-                    rv[j][e] -= alpha * qv[e];
-                }
-                st4(x + o, xv);
-                st4(r + o, rv[j]);
+                for (int e = 0; e < 4; ++e) rv[j][e] -= alpha * qv[j][e];
+                st4(r + (size_t)j * n_pix + p0, rv[j]);
             }
             precond_vec4<T, K>(pc, P, n_pix, p0, rv, zv);
 #pragma unroll
@@ -505,20 +552,19 @@ __global__ __launch_bounds__(kBlock) void k_update(const Inst *__restrict__ tab,
         } else {
             for (int e = 0; e < 4 && p0 + e < n_pix; ++e) {
                 const int pix = p0 + e;
-                T rv[K], zv[K];
+                T rs[K], zs[K];
 #pragma unroll
                 for (int j = 0; j < K; ++j) {
                     const size_t o = (size_t)j * n_pix + pix;
-                    x[o] += alpha * p[o];
-                    rv[j] = r[o] - alpha * q[o];
-                    r[o] = rv[j];
+                    rs[j] = r[o] - alpha * q[o];
+                    r[o] = rs[j];
                 }
-                precond_pixel<T, K>(pc, P, n_pix, pix, rv, zv);
+                precond_pixel<T, K>(pc, P, n_pix, pix, rs, zs);
 #pragma unroll
                 for (int j = 0; j < K; ++j) {
-                    z[(size_t)j * n_pix + pix] = zv[j];
-                    rz += (double)rv[j] * (double)zv[j];
-                    rr += (double)rv[j] * (double)rv[j];
+                    z[(size_t)j * n_pix + pix] = zs[j];
+                    rz += (double)rs[j] * (double)zs[j];
+                    rr += (double)rs[j] * (double)rs[j];
                 }
             }
         }
@@ -552,6 +598,7 @@ __global__ __launch_bounds__(kBlock) void k_pinit(const Inst *__restrict__ tab,
     }
     if (chunk == 0 && threadIdx.x == 0) {
         st->iter = 0;
+        st->pend = -1;
         st->max_iter = max_iter;
         if constexpr (sizeof(T) == 4) {
             st->done = 0;
@@ -564,7 +611,7 @@ __global__ __launch_bounds__(kBlock) void k_pinit(const Inst *__restrict__ tab,
     const GAS double *r64 = gp(I.r);
     GAS T *rr_out = Sel<T>::r(I);
     GAS T *z = Sel<T>::z(I);
-    const GAS T *P = Sel<T>::P(I);
+    const GAS float *P = Pcg(I);
     const int pc = I.pc;
     const int p0 = chunk * kChunk + threadIdx.x * 4;
     double rz = 0.0, rr = 0.0;
@@ -646,7 +693,7 @@ __global__ void k_state_init(const Inst *__restrict__ tab, int ninst, double tol
         st->rho[0] = 0.0; st->rho[1] = 0.0; st->rr = 0.0; st->rr0 = 0.0; st->bb = 0.0;
         st->thresh = 0.0; st->tol = tol; st->rel_true = 0.0; st->rr_prev = 0.0;
         st->iter = 0; st->max_iter = max_iter; st->status = SYLV_OK; st->done = 0;
-        st->total_iter = 0; st->outer = 0; st->pad[0] = 0; st->pad[1] = 0;
+        st->total_iter = 0; st->outer = 0; st->pend = -1; st->pad = 0;
     }
 }
 
@@ -677,8 +724,8 @@ __global__ void k_stats(const Inst *__restrict__ tab, int ninst, sylv_pcg_stats 
         s.iters = si->total_iter;
         s.outer = st->outer;
     } else {
-        s.iters = st->iter;
-        s.outer = 1;
+        s.iters = st->total_iter;
+        s.outer = st->outer;
     }
     s.relres_rec = (st->rr0 > 0.0) ? sqrt(st->rr / st->rr0) : 0.0;
     s.reserved = 0;
