@@ -11,8 +11,9 @@ K steps are then timed for the float64 solver.  The roofline object reports the 
 operator apply (float32, the precision of the inner runs), timed with HIP events on the stream it
 runs on.  Prints one JSON line.
 
---mode pmc runs only a device copy of known size and the applies, for hardware-counter runs
-(rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE) that calibrate the HBM-traffic figure.
+--mode pmc runs only a device copy of known size, the applies and one solve of each precision,
+for hardware-counter runs (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE) that calibrate the
+HBM-traffic figure.
 """
 from __future__ import annotations
 
@@ -21,6 +22,7 @@ import hashlib
 import json
 import os
 import resource
+import statistics
 import sys
 import time
 
@@ -41,11 +43,12 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def apply_bytes_per_pixel(k: int, elem: int) -> int:
-    """Algorithmic bytes of one operator apply per pixel: read the k input maps and the
-    k(k+1)/2 packed mixing-block planes once, write the k output maps (stencil halos are reuse,
-    not extra traffic)."""
-    return (2 * k + k * (k + 1) // 2) * elem
+def apply_bytes_per_pixel(k: int, elem: int, f: int = None) -> int:
+    """Algorithmic bytes of one operator apply per pixel: read the k input maps and the per-pixel
+    weights once (the k(k+1)/2 packed mixing-block planes, or the f weight maps where those are
+    fewer), write the k output maps (stencil halos are reuse, not extra traffic)."""
+    wt = k * (k + 1) // 2 if f is None else min(f, k * (k + 1) // 2)
+    return (2 * k + wt) * elem
 
 
 def timed_applies(sy, torch, dp, X, ws, reps):
@@ -99,18 +102,20 @@ def cpu_baseline(prob, tol):
 
 
 def time_solves(sy, torch, probs, Y, B, opts, nrhs, steps, warmup):
-    """Median-free mean time of `steps` solves after `warmup`, with the last stats."""
+    """Median time of `steps` solves after `warmup`, with the last stats."""
     plist = probs if isinstance(probs, list) else [probs]
     ws = torch.empty(sy.workspace_bytes(plist, nrhs, opts), dtype=torch.uint8, device="cuda")
     for _ in range(warmup):
         sy.pcg_solve(probs, Y=Y, Bextra=B, opts=opts, nrhs=nrhs, ws=ws, return_stats=False)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    times = []
     for _ in range(steps):
+        t0 = time.perf_counter()
         X, stt = sy.pcg_solve(probs, Y=Y, Bextra=B, opts=opts, nrhs=nrhs, ws=ws,
                               return_stats=False)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) / steps * 1e3
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+    ms = statistics.median(times)
     n = len(plist) * nrhs
     st = sy.binding._stats_list(stt, n)
     return ms, st, X
@@ -138,8 +143,19 @@ def bench_other_workloads(sy, torch, steps, warmup):
         ms, st, _ = time_solves(sy, torch, dp, Y, None, o, 1, steps, warmup)
         res[label] = summarize(ms, st)
         log(f"masked_2048 {label}: {res[label]}")
+    # stand-alone applies at a size far beyond the 256 MB last-level cache: the HBM figure
+    ws_app = sy.binding.prepare(dp, sy.SYLV_PC_NONE)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+    X64 = torch.randn((prob.k, prob.n_pix), generator=gen, dtype=torch.float64, device="cuda")
+    for label, X, e in (("apply_f32", X64.float(), 4), ("apply_f64", X64, 8)):
+        t = timed_applies(sy, torch, dp, X, ws_app, 50)
+        nb = apply_bytes_per_pixel(prob.k, e, prob.f) * prob.n_pix
+        res[label] = {"us": round(t * 1e3, 2), "algorithmic_bytes": nb,
+                      "gbs": round(nb / (t * 1e-3) / 1e9, 1)}
+        log(f"masked_2048 {label}: {res[label]}")
     out["masked_2048"] = res
-    del dp, Y
+    del dp, Y, ws_app, X64
     # 8 uneven grids x 8 perturbation-optimisation right-hand sides (64 posterior samples)
     probs = workload("batched_8grids")
     nrhs = WORKLOADS["batched_8grids"]["nrhs"]
@@ -234,10 +250,13 @@ def main():
         for _ in range(3):
             sy.apply(dp, X32, ws=ws_app, prepared=True)
             sy.apply(dp, X64, ws=ws_app, prepared=True)
+        # one solve of each precision, so that the counters also cover the CG kernels
+        for prec in (sy.SYLV_PREC_MIXED, sy.SYLV_PREC_F64):
+            sy.pcg_solve(dp, Y=Y, opts=sy.SolveOptions(tol=tol, precision=prec))
         torch.cuda.synchronize()
         print(json.dumps({"mode": "pmc", "copy_bytes": nbytes,
-                          "apply_f32_bytes": apply_bytes_per_pixel(k, 4) * n_pix,
-                          "apply_f64_bytes": apply_bytes_per_pixel(k, 8) * n_pix,
+                          "apply_f32_bytes": apply_bytes_per_pixel(k, 4, f) * n_pix,
+                          "apply_f64_bytes": apply_bytes_per_pixel(k, 8, f) * n_pix,
                           "kernel_source_sha": kernel_source_hash()}))
         return
 
@@ -253,23 +272,30 @@ def main():
         for _ in range(args.warmup):
             sy.pcg_solve(dp, Y=Y, opts=o, ws=ws, return_stats=False)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        times = []
+        t_all = time.perf_counter()
         for _ in range(args.steps):
+            t0 = time.perf_counter()
             X, stats_t = sy.pcg_solve(dp, Y=Y, opts=o, ws=ws, return_stats=False)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) / args.steps * 1e3
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+        ms_mean = (time.perf_counter() - t_all) / args.steps * 1e3
+        ms = statistics.median(times)
         st = sy.binding._stats_list(stats_t, 1)[0]
-        results[label] = dict(ms=ms, stats=st, X=X)
-        log(f"{label}: {ms:.3f} ms/solve  {st}")
+        results[label] = dict(ms=ms, ms_mean=ms_mean, stats=st, X=X)
+        log(f"{label}: median {ms:.3f} ms/solve (mean {ms_mean:.3f})  {st}")
 
-    xm = results["mixed"]["X"]
-    xd = results["f64"]["X"]
-    err = float(torch.linalg.norm(xm - xd) / torch.linalg.norm(xd))
+    # reference solution: float64 PCG to a 1e-12 relative residual (not timed)
+    xref, st_ref = sy.pcg_solve(dp, Y=Y, ws=ws, opts=sy.SolveOptions(
+        tol=1e-12, precision=sy.SYLV_PREC_F64, precond=sy.SYLV_PC_BLOCK))
+    nref = torch.linalg.norm(xref)
+    err = {lb: float(torch.linalg.norm(results[lb]["X"] - xref) / nref) for lb in results}
+    log(f"error vs float64 tol 1e-12 reference (relres {st_ref[0]['relres_true']:.2e}): {err}")
 
     t32 = timed_applies(sy, torch, dp, X32, ws_app, args.apply_reps)
     t64 = timed_applies(sy, torch, dp, X64, ws_app, args.apply_reps)
-    b32 = apply_bytes_per_pixel(k, 4) * n_pix
-    b64 = apply_bytes_per_pixel(k, 8) * n_pix
+    b32 = apply_bytes_per_pixel(k, 4, f) * n_pix
+    b64 = apply_bytes_per_pixel(k, 8, f) * n_pix
     gbs32 = b32 / (t32 * 1e-3) / 1e9
     gbs64 = b64 / (t64 * 1e-3) / 1e9
     log(f"apply f32 {t32 * 1e3:.2f} us {gbs32:.0f} GB/s; f64 {t64 * 1e3:.2f} us {gbs64:.0f} GB/s")
@@ -301,7 +327,10 @@ def main():
         "outer_mixed": results["mixed"]["stats"]["outer"],
         "relres_true_fp64": results["f64"]["stats"]["relres_true"],
         "relres_true_mixed": results["mixed"]["stats"]["relres_true"],
-        "rel_err_mixed_vs_fp64": err,
+        "rel_err_vs_ref": {"mixed": err["mixed"], "fp64": err["f64"],
+                           "reference": "float64 PCG to relres 1e-12 on the GPU"},
+        "ms_mean": {"mixed": round(results["mixed"]["ms_mean"], 4),
+                    "fp64": round(results["f64"]["ms_mean"], 4)},
         "apply_f32_us": round(t32 * 1e3, 3),
         "apply_f64_us": round(t64 * 1e3, 3),
         "apply_f32_gbs": round(gbs32, 1),

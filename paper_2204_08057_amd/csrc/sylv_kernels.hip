@@ -615,24 +615,51 @@ __global__ __launch_bounds__(kBlock) void k_pinit(const Inst *__restrict__ tab,
     const int pc = I.pc;
     const int p0 = chunk * kChunk + threadIdx.x * 4;
     double rz = 0.0, rr = 0.0;
-    for (int e = 0; e < 4 && p0 + e < n_pix; ++e) {
-        const int pix = p0 + e;
-        T rv[K], zv[K];
+    if (I.vec4 && p0 + 4 <= n_pix) {
+        T rv[K][4], zv[K][4];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            const size_t o = (size_t)j * n_pix + pix;
-            rv[j] = (T)r64[o];
+            const size_t o = (size_t)j * n_pix + p0;
+            double r4[4];
+            ld4(r64 + o, r4);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) rv[j][e] = (T)r4[e];
             if constexpr (sizeof(T) == 4) {
-                rr_out[o] = rv[j];
-                gp(I.d32)[o] = 0.0f;
+                st4(rr_out + o, rv[j]);
+                const float zero4[4] = {0.f, 0.f, 0.f, 0.f};
+                st4(gp(I.d32) + o, zero4);
             }
         }
-        precond_pixel<T, K>(pc, P, n_pix, pix, rv, zv);
+        precond_vec4<T, K>(pc, P, n_pix, p0, rv, zv);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            z[(size_t)j * n_pix + pix] = zv[j];
-            rz += (double)rv[j] * (double)zv[j];
-            rr += (double)rv[j] * (double)rv[j];
+            st4(z + (size_t)j * n_pix + p0, zv[j]);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                rz += (double)rv[j][e] * (double)zv[j][e];
+                rr += (double)rv[j][e] * (double)rv[j][e];
+            }
+        }
+    } else {
+        for (int e = 0; e < 4 && p0 + e < n_pix; ++e) {
+            const int pix = p0 + e;
+            T rv[K], zv[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const size_t o = (size_t)j * n_pix + pix;
+                rv[j] = (T)r64[o];
+                if constexpr (sizeof(T) == 4) {
+                    rr_out[o] = rv[j];
+                    gp(I.d32)[o] = 0.0f;
+                }
+            }
+            precond_pixel<T, K>(pc, P, n_pix, pix, rv, zv);
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                z[(size_t)j * n_pix + pix] = zv[j];
+                rz += (double)rv[j] * (double)zv[j];
+                rr += (double)rv[j] * (double)rv[j];
+            }
         }
     }
     double v[2] = {rz, rr};
@@ -655,6 +682,22 @@ __global__ __launch_bounds__(kBlock) void k_refine_axpy(const Inst *__restrict__
     const int p0 = chunk * kChunk + threadIdx.x * 4;
     GAS double *x = gp(I.x);
     const GAS float *d = gp(I.d32);
+    if (I.vec4 && p0 + 4 <= n_pix) {
+        double xv[K][4];
+        float dv[K][4];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            ld4(x + (size_t)j * n_pix + p0, xv[j]);
+            ld4(d + (size_t)j * n_pix + p0, dv[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) xv[j][e] += (double)dv[j][e];
+            st4(x + (size_t)j * n_pix + p0, xv[j]);
+        }
+        return;
+    }
     for (int e = 0; e < 4 && p0 + e < n_pix; ++e) {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
