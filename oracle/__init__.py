@@ -15,9 +15,12 @@ spatial source separation of the CMB):
   grad.py      gradients of a loss of the solution through the adjoint method, written with
                explicitly assembled derivative matrices, and central finite differences.
   po.py        perturbation-optimisation right-hand sides (a sample of N(x*, G^-1) after a solve).
+  lanczos.py   the Lanczos-Sylvester solver: block Lanczos in the N inner product (Alg. 4) inside
+               the symmetric sparse Sylvester solver with its residual estimate (Alg. 5), for the
+               separable equal-kappa case (Sections 3.3.2-3.3.4).
 
 Only the test-suite, the smoke check of the package entry point and the CPU-baseline leg of the
 benchmark may import anything from here.  The GPU library and its Python binding never import,
 link or call this package, and this package never imports them.
 """
-from . import operator, solve, pcg, grad, po  # noqa: F401
+from . import operator, solve, pcg, grad, po, lanczos  # noqa: F401

@@ -130,7 +130,8 @@ def make_problem(
     elif noise == "hetero":
         W = base[:, None] * rng.lognormal(0.0, 0.5, size=(f, n_pix))
     elif noise == "separable":
-        W = base[:, None] * rng.lognormal(0.0, 0.5, size=(1, n_pix))
+        nsep = rng.lognormal(0.0, 0.5, size=(1, n_pix))
+        W = base[:, None] * nsep
     else:
         raise ValueError(f"unknown noise law {noise!r}")
     W = np.ascontiguousarray(W, dtype=np.float64)
@@ -149,8 +150,12 @@ def make_problem(
         sd = np.where(W > 0, 1.0 / np.sqrt(np.where(W > 0, W, 1.0)), 0.0)
     Y = Am @ S + sd * eps
     Y[W == 0] = 0.0
-    return Problem(ny, nx, k, f, kap, ta, Am, W, np.ascontiguousarray(Y), name=name,
-                   meta={"seed": seed, "noise": noise, "mask_frac": mask_frac, "sources": sources})
+    meta = {"seed": seed, "noise": noise, "mask_frac": mask_frac, "sources": sources}
+    if noise == "separable" and mask_frac == 0.0:
+        # the factors of W[f, p] = t_f n_p (W holds exactly their rounded products)
+        meta["t"] = base.copy()
+        meta["n"] = nsep[0].copy()
+    return Problem(ny, nx, k, f, kap, ta, Am, W, np.ascontiguousarray(Y), name=name, meta=meta)
 
 
 # Named workloads.  Sizes follow the paper's per-patch pixel counts (N = 4^h, App. A) and its
