@@ -52,6 +52,7 @@ extern "C" {
 #define SYLV_NONFINITE       3  /* a NaN or Inf appeared in a residual or inner product         */
 #define SYLV_STAGNATED       4  /* mixed precision: an outer refinement step did not reduce the
                                    float64 residual                                             */
+#define SYLV_BAD_INPUT       5  /* Lanczos-Sylvester: some n_p is not a positive finite number  */
 #define SYLV_E_INVALID     (-1) /* bad argument (null pointer, size out of range, bad option)   */
 #define SYLV_E_WORKSPACE   (-2) /* ws_bytes smaller than sylv_workspace_bytes()                  */
 #define SYLV_E_HIP         (-3) /* a HIP runtime call failed                                     */
@@ -167,6 +168,63 @@ int sylv_pcg_backward(const sylv_problem *prob, const double *Y, const double *X
                       const double *Gbar, double *Lambda, double *dkappa, double *dtau,
                       double *dA, double *dW, double *dY, const sylv_pcg_opts *opts,
                       sylv_pcg_stats *stats, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- Lanczos-Sylvester solver (Section 3.3, Alg. 4 and Alg. 5) ---------------------------------
+ *
+ * The case the paper solves in Sylvester form: every component shares one kappa and the noise
+ * precision is separable, W[f, p] = t_f n_p (C = T (x) N with T = diag(t), N = diag(n)).  With
+ * P = diag(tau) and D2 = (kappa^2 I - Lap)^2 the system G(X) = B_rhs is then the Sylvester
+ * equation (eq. (Axb-Sylv))
+ *
+ *     N^-1 D2 M + M Lhat = Yhat,   Lhat = A^T T A P^-1,   Yhat = Y^T T A P^-1,
+ *
+ * M the n_pix x k matrix whose column j is map j (X[j * n_pix + p] = M[p, j]).  The solver runs
+ * the symmetric block Lanczos process for N^-1 D2 in the N inner product (Alg. 4) from Yhat,
+ * projects the equation on the block Krylov space (eq. (Sylv-small)) and stops on Alg. 5's
+ * residual estimate sqrt(gamma) <= tol ||B_0||_F; the Galerkin approximation is then assembled
+ * from the Lanczos blocks, which stay in the workspace (the paper's second Lanczos pass is not
+ * needed).  All arithmetic is float64.
+ */
+
+/* Host struct of device pointers. */
+typedef struct sylv_sep_problem {
+    int64_t ny, nx;        /* periodic grid, n_pix = ny * nx                                     */
+    int32_t k;             /* components (the paper's m), 1..8                                   */
+    int32_t f;             /* maps (the paper's n), 1..16                                        */
+    double  kappa;         /* common kappa >= 0 (host value; 0 = the paper's D^2 prior)          */
+    const double *tau;     /* [k]  tau_j > 0 (the paper's phi: P = diag(tau))                    */
+    const double *A;       /* [f * k] mixing matrix, row-major, full column rank                 */
+    const double *t;       /* [f]  t_f > 0 (per-map noise precision, T)                          */
+    const double *n;       /* [n_pix] n_p > 0 (per-pixel noise precision, N; no masked pixels)   */
+} sylv_sep_problem;
+
+typedef struct sylv_lanczos_opts {
+    double  tol;           /* stop when sqrt(gamma) <= tol * ||B_0||_F (Alg. 5)                  */
+    int32_t max_iter;      /* Lanczos steps at most; the workspace keeps max_iter basis blocks
+                              of k * n_pix doubles each                                          */
+    int32_t check_every;   /* steps enqueued between host convergence checks (0 = 8)             */
+} sylv_lanczos_opts;
+
+/* Result of a Lanczos-Sylvester solve (HOST struct, filled before the call returns). */
+typedef struct sylv_lanczos_stats {
+    int32_t status;        /* SYLV_OK, SYLV_NOT_CONVERGED, SYLV_BREAKDOWN (N-Gram matrix of a new
+                              block not positive definite), SYLV_NONFINITE, SYLV_BAD_INPUT       */
+    int32_t iters;         /* Lanczos steps whose blocks make up the solution                     */
+    double  relres_est;    /* sqrt(gamma) / ||B_0||_F after the last step (Alg. 5)                */
+    double  relres_true;   /* ||b - G x||_2 / ||b||_2 of eq. (Axb), recomputed in float64         */
+} sylv_lanczos_stats;
+
+/* Bytes of workspace for sylv_lanczos_solve (0 for invalid arguments). */
+size_t sylv_lanczos_workspace_bytes(const sylv_sep_problem *prob, const sylv_lanczos_opts *opts);
+
+/* Solve eq. (Axb-Sylv) by Alg. 5 with Alg. 4 inside.
+ *   Y: [f][n_pix] float64 observed maps;  X: [k][n_pix] float64, the solution on return.
+ * The call copies tau, A and t to the host (the k x k eigenproblem of Lemma 2 is solved there),
+ * synchronises `stream` every check_every steps and at the end, and returns when X and *stats
+ * are final.  Rejected (SYLV_E_INVALID) when A^T T A is not positive definite. */
+int sylv_lanczos_solve(const sylv_sep_problem *prob, const double *Y, double *X,
+                       const sylv_lanczos_opts *opts, sylv_lanczos_stats *stats, void *ws,
+                       size_t ws_bytes, void *stream);
 
 /* Human-readable name of a status or return code (static string). */
 const char *sylv_status_string(int code);

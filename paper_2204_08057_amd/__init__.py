@@ -15,11 +15,15 @@ from .binding import (  # noqa: F401
     SYLV_PREC_MIXED,
     STATUS_NAMES,
     DeviceProblem,
+    LanczosOptions,
+    SepProblem,
     SolveOptions,
     SylvError,
     SylvSolve,
     apply,
     declared_symbols,
+    lanczos_solve,
+    lanczos_workspace_bytes,
     lib,
     library_path,
     pcg_backward,

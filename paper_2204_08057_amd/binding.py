@@ -22,6 +22,7 @@ SYLV_NOT_CONVERGED = 1
 SYLV_BREAKDOWN = 2
 SYLV_NONFINITE = 3
 SYLV_STAGNATED = 4
+SYLV_BAD_INPUT = 5
 SYLV_E_INVALID = -1
 SYLV_E_WORKSPACE = -2
 SYLV_E_HIP = -3
@@ -35,7 +36,7 @@ SYLV_PC_BLOCK = 2
 
 STATUS_NAMES = {
     SYLV_OK: "ok", SYLV_NOT_CONVERGED: "not converged", SYLV_BREAKDOWN: "breakdown",
-    SYLV_NONFINITE: "non-finite", SYLV_STAGNATED: "stagnated",
+    SYLV_NONFINITE: "non-finite", SYLV_STAGNATED: "stagnated", SYLV_BAD_INPUT: "bad input",
 }
 
 
@@ -66,6 +67,22 @@ class _Stats(ctypes.Structure):
 
 STATS_BYTES = ctypes.sizeof(_Stats)
 
+
+class _SepProblem(ctypes.Structure):
+    _fields_ = [("ny", ctypes.c_int64), ("nx", ctypes.c_int64), ("k", ctypes.c_int32),
+                ("f", ctypes.c_int32), ("kappa", ctypes.c_double), ("tau", ctypes.c_void_p),
+                ("A", ctypes.c_void_p), ("t", ctypes.c_void_p), ("n", ctypes.c_void_p)]
+
+
+class _LzOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("check_every", ctypes.c_int32)]
+
+
+class _LzStats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("relres_est", ctypes.c_double), ("relres_true", ctypes.c_double)]
+
 _LIB = None
 
 
@@ -94,8 +111,13 @@ def lib():
         L.sylv_po_perturb.argtypes = [P, vp, vp, vp, i32, vp]
         L.sylv_pcg_solve.argtypes = [P, i32, i32, vp, vp, vp, O, vp, vp, sz, vp]
         L.sylv_pcg_backward.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, vp, O, vp, vp, sz, vp]
+        SP = ctypes.POINTER(_SepProblem)
+        LO = ctypes.POINTER(_LzOpts)
+        L.sylv_lanczos_workspace_bytes.argtypes = [SP, LO]
+        L.sylv_lanczos_workspace_bytes.restype = sz
+        L.sylv_lanczos_solve.argtypes = [SP, vp, vp, LO, ctypes.POINTER(_LzStats), vp, sz, vp]
         for name in ("sylv_prepare", "sylv_apply", "sylv_precond", "sylv_rhs", "sylv_po_perturb",
-                     "sylv_pcg_solve", "sylv_pcg_backward"):
+                     "sylv_pcg_solve", "sylv_pcg_backward", "sylv_lanczos_solve"):
             getattr(L, name).restype = ctypes.c_int
         L.sylv_status_string.argtypes = [ctypes.c_int]
         L.sylv_status_string.restype = ctypes.c_char_p
@@ -395,3 +417,84 @@ def _make_function():
             return g["kappa"], g["tau"], g["A"], g["W"], g["Y"], None, None, None
 
     return _SylvSolveFn
+
+
+# ---- Lanczos-Sylvester solver (Section 3.3, Alg. 4 and Alg. 5) ----------------------------------
+
+@dataclass
+class SepProblem:
+    """The separable, equal-kappa case: W[f, p] = t_f n_p, one kappa for every component.
+    tau[k], A[f, k], t[f], n[n_pix] are float64 CUDA tensors; kappa is a number."""
+
+    ny: int
+    nx: int
+    kappa: float
+    tau: "object"
+    A: "object"
+    t: "object"
+    n: "object"
+
+    @property
+    def k(self) -> int:
+        return int(self.tau.numel())
+
+    @property
+    def f(self) -> int:
+        return int(self.A.shape[0])
+
+    @property
+    def n_pix(self) -> int:
+        return self.ny * self.nx
+
+    def c_struct(self) -> _SepProblem:
+        torch = _torch()
+        for name in ("tau", "A", "t", "n"):
+            if getattr(self, name).dtype != torch.float64:
+                raise ValueError(f"{name} must be float64")
+        return _SepProblem(self.ny, self.nx, self.k, self.f, float(self.kappa), _ptr(self.tau),
+                           _ptr(self.A), _ptr(self.t), _ptr(self.n))
+
+    @staticmethod
+    def from_numpy(ny, nx, kappa, tau, A, t, n, device="cuda"):
+        torch = _torch()
+        c = lambda a: torch.as_tensor(a, dtype=torch.float64, device=device).contiguous()  # noqa
+        return SepProblem(ny, nx, float(kappa), c(tau), c(A), c(t), c(n))
+
+
+@dataclass
+class LanczosOptions:
+    tol: float = 1e-8
+    max_iter: int = 500
+    check_every: int = 0
+
+    def c_struct(self) -> _LzOpts:
+        return _LzOpts(self.tol, self.max_iter, self.check_every)
+
+
+def lanczos_workspace_bytes(problem: SepProblem, opts: Optional[LanczosOptions] = None) -> int:
+    opts = opts or LanczosOptions()
+    ps, os_ = problem.c_struct(), opts.c_struct()
+    n = lib().sylv_lanczos_workspace_bytes(ctypes.byref(ps), ctypes.byref(os_))
+    if n == 0:
+        _check(SYLV_E_INVALID)
+    return int(n)
+
+
+def lanczos_solve(problem: SepProblem, Y, opts: Optional[LanczosOptions] = None, ws=None,
+                  out=None):
+    """X = solution of eq. (Axb-Sylv) as [k, n_pix] float64, and the statistics dict."""
+    torch = _torch()
+    opts = opts or LanczosOptions()
+    if Y.dtype != torch.float64:
+        raise ValueError("Y must be float64")
+    nb = lanczos_workspace_bytes(problem, opts)
+    if ws is None:
+        ws = _workspace(nb, Y.device)
+    X = out if out is not None else torch.empty((problem.k, problem.n_pix), dtype=torch.float64,
+                                                device=Y.device)
+    st = _LzStats()
+    ps, os_ = problem.c_struct(), opts.c_struct()
+    _check(lib().sylv_lanczos_solve(ctypes.byref(ps), _ptr(Y), _ptr(X), ctypes.byref(os_),
+                                    ctypes.byref(st), _ptr(ws), ws.numel(), _stream()))
+    return X, {"status": st.status, "status_name": STATUS_NAMES.get(st.status, str(st.status)),
+               "iters": st.iters, "relres_est": st.relres_est, "relres_true": st.relres_true}

@@ -7,6 +7,7 @@
 #include "sylv.h"
 #include "sylv_internal.h"
 
+#include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -508,6 +509,343 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
     return SYLV_OK;
 }
 
+
+// ---- Lanczos-Sylvester (Section 3.3, Alg. 4 and Alg. 5) ---------------------------------------
+
+struct LzLayout {
+    size_t cst, state, H, B, Binv, hist, G, partial, Yh, Wn, Wa, basis, total;
+    int nred;
+};
+
+bool check_sep(const sylv_sep_problem *p) {
+    if (!p) { set_err("null problem"); return false; }
+    if (p->k < 1 || p->k > kMaxK) { set_err("k=%d outside [1, %d]", p->k, kMaxK); return false; }
+    if (p->f < 1 || p->f > kMaxF) { set_err("f=%d outside [1, %d]", p->f, kMaxF); return false; }
+    if (p->ny < 1 || p->nx < 1) { set_err("grid %lld x %lld", (long long)p->ny, (long long)p->nx); return false; }
+    if (p->ny * p->nx >= (int64_t)1 << 30) { set_err("n_pix too large"); return false; }
+    if (!(p->kappa >= 0.0) || !isfinite(p->kappa)) { set_err("kappa must be finite and >= 0"); return false; }
+    if (!p->tau || !p->A || !p->t || !p->n) { set_err("null parameter pointer"); return false; }
+    return true;
+}
+
+bool check_lz_opts(const sylv_lanczos_opts *o) {
+    if (!o) { set_err("null opts"); return false; }
+    if (!(o->tol > 0.0) || !(o->tol < 1.0)) { set_err("tol must be in (0, 1)"); return false; }
+    if (o->max_iter < 1 || o->max_iter > 100000) { set_err("max_iter must be in [1, 100000]"); return false; }
+    if (o->check_every < 0) { set_err("negative check_every"); return false; }
+    return true;
+}
+
+bool make_lz_layout(const sylv_sep_problem *p, const sylv_lanczos_opts *o, LzLayout &L) {
+    const size_t n = (size_t)p->ny * p->nx, k = (size_t)p->k, mi = (size_t)o->max_iter;
+    const int nt = lz_tiles((int)p->ny, (int)p->nx), nc = chunks_for((int)n);
+    L.nred = std::max(nt, nc);
+    const size_t vb = sizeof(double) * k * n;
+    if (vb && mi > ((size_t)1 << 62) / vb) { set_err("basis size overflows"); return false; }
+    size_t off = 0;
+    L.cst = off;     off = align_up(off + sizeof(LzConst));
+    L.state = off;   off = align_up(off + sizeof(LzState));
+    L.H = off;       off = align_up(off + sizeof(double) * kLzStride * mi);
+    L.B = off;       off = align_up(off + sizeof(double) * kLzStride * (mi + 1));
+    L.Binv = off;    off = align_up(off + sizeof(double) * kLzStride * (mi + 1));
+    L.hist = off;    off = align_up(off + sizeof(double) * mi);
+    L.G = off;       off = align_up(off + sizeof(double) * kLzStride * mi);
+    L.partial = off; off = align_up(off + sizeof(double) * kLzSlots * L.nred);
+    L.Yh = off;      off = align_up(off + vb);
+    L.Wn = off;      off = align_up(off + vb);
+    L.Wa = off;      off = align_up(off + vb);
+    L.basis = off;   off = align_up(off + vb * mi);
+    L.total = off;
+    return true;
+}
+
+// Eigenvalues and orthonormal eigenvectors of a symmetric m x m matrix (cyclic Jacobi
+// rotations), ascending.  a is overwritten; v[i][j] is component i of eigenvector j.
+void sym_eig(int m, double a[kMaxK][kMaxK], double w[kMaxK], double v[kMaxK][kMaxK]) {
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) v[i][j] = (i == j) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) {
+                tot += a[i][j] * a[i][j];
+                if (i != j) off += a[i][j] * a[i][j];
+            }
+        if (off <= 1e-32 * tot) break;
+        for (int p = 0; p < m; ++p)
+            for (int q = p + 1; q < m; ++q) {
+                if (a[p][q] == 0.0) continue;
+                const double th = (a[q][q] - a[p][p]) / (2.0 * a[p][q]);
+                const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+                for (int r = 0; r < m; ++r) {   // columns p, q
+                    const double arp = a[r][p], arq = a[r][q];
+                    a[r][p] = c * arp - sn * arq;
+                    a[r][q] = sn * arp + c * arq;
+                }
+                for (int r = 0; r < m; ++r) {   // rows p, q
+                    const double apr = a[p][r], aqr = a[q][r];
+                    a[p][r] = c * apr - sn * aqr;
+                    a[q][r] = sn * apr + c * aqr;
+                }
+                for (int r = 0; r < m; ++r) {
+                    const double vrp = v[r][p], vrq = v[r][q];
+                    v[r][p] = c * vrp - sn * vrq;
+                    v[r][q] = sn * vrp + c * vrq;
+                }
+            }
+    }
+    int idx[kMaxK];
+    for (int i = 0; i < m; ++i) { idx[i] = i; w[i] = a[i][i]; }
+    std::sort(idx, idx + m, [&](int x, int y) { return w[x] < w[y]; });
+    double ws[kMaxK], vs[kMaxK][kMaxK];
+    for (int j = 0; j < m; ++j) {
+        ws[j] = w[idx[j]];
+        for (int i = 0; i < m; ++i) vs[i][j] = v[i][idx[j]];
+    }
+    for (int j = 0; j < m; ++j) {
+        w[j] = ws[j];
+        for (int i = 0; i < m; ++i) v[i][j] = vs[i][j];
+    }
+}
+
+// Small dense SPD helpers for the projected equation (host, m <= 8, row-major ld kMaxK).
+bool host_chol(int m, const double *a, double *r) {   // a = r^T r, r upper
+    for (int i = 0; i < m * kMaxK; ++i) r[i] = 0.0;
+    for (int i = 0; i < m; ++i) {
+        double d = a[i * kMaxK + i];
+        for (int q = 0; q < i; ++q) d -= r[q * kMaxK + i] * r[q * kMaxK + i];
+        if (!(d > 0.0)) return false;
+        r[i * kMaxK + i] = sqrt(d);
+        for (int j = i + 1; j < m; ++j) {
+            double v = a[i * kMaxK + j];
+            for (int q = 0; q < i; ++q) v -= r[q * kMaxK + i] * r[q * kMaxK + j];
+            r[i * kMaxK + j] = v / r[i * kMaxK + i];
+        }
+    }
+    return true;
+}
+void host_chol_solve(int m, const double *r, const double *b, double *x) {
+    double y[kMaxK];
+    for (int i = 0; i < m; ++i) {
+        double v = b[i];
+        for (int q = 0; q < i; ++q) v -= r[q * kMaxK + i] * y[q];
+        y[i] = v / r[i * kMaxK + i];
+    }
+    for (int i = m - 1; i >= 0; --i) {
+        double v = y[i];
+        for (int q = i + 1; q < m; ++q) v -= r[i * kMaxK + q] * x[q];
+        x[i] = v / r[i * kMaxK + i];
+    }
+}
+
+// Coefficients of the Galerkin approximation M = sum_j V_j G_j after `it` steps: the solution Z
+// of the projected equation T Z + Z Lhat = E_1 B_0 (eq. (Sylv-small)).  With Lhat = U R U^-1 the
+// columns decouple, Z U = [(T + rho_l I)^-1 E_1 B_0 U e_l]_l (eq. (soln-constr) without forming
+// the eigenvectors of T), each a block tridiagonal SPD solve (block elimination, then back
+// substitution); Z = (Z U) U^T P^-1.  Returns false if an elimination pivot is not positive.
+bool lz_coefficients(int m, int it, const std::vector<double> &H, const std::vector<double> &B,
+                     const double U[kMaxK][kMaxK], const double *rho, const double *tau,
+                     std::vector<double> &G) {
+    const int S = kLzStride;
+    std::vector<double> ZU((size_t)it * kMaxK * kMaxK, 0.0);   // [block j][row r][column l]
+    std::vector<double> Sc((size_t)it * S), Rc((size_t)it * S), g((size_t)it * kMaxK);
+    for (int l = 0; l < m; ++l) {
+        // forward elimination: S_1 = H_1 + rho I, g_1 = B_0 U e_l; S_j = H_j + rho I - B_j S_(j-1)^-1 B_j^T,
+        // g_j = -B_j S_(j-1)^-1 g_(j-1)
+        for (int j = 0; j < it; ++j) {
+            double *Sj = &Sc[(size_t)j * S];
+            for (int r = 0; r < m; ++r)
+                for (int q = 0; q < m; ++q) Sj[r * kMaxK + q] = H[(size_t)j * S + r * kMaxK + q] + (r == q ? rho[l] : 0.0);
+            double *gj = &g[(size_t)j * kMaxK];
+            if (j == 0) {
+                for (int r = 0; r < m; ++r) {
+                    double v = 0.0;
+                    for (int q = 0; q < m; ++q) v += B[r * kMaxK + q] * U[q][l];
+                    gj[r] = v;
+                }
+            } else {
+                const double *Bj = &B[(size_t)j * S];          // B_(j+1) in 1-based names
+                const double *Rp = &Rc[(size_t)(j - 1) * S];
+                double X[kMaxK][kMaxK];
+                for (int q = 0; q < m; ++q) {
+                    double bcol[kMaxK], xcol[kMaxK];
+                    for (int r = 0; r < m; ++r) bcol[r] = Bj[q * kMaxK + r];
+                    host_chol_solve(m, Rp, bcol, xcol);
+                    for (int r = 0; r < m; ++r) X[r][q] = xcol[r];
+                }
+                for (int r = 0; r < m; ++r)
+                    for (int q = 0; q < m; ++q) {
+                        double v = Sj[r * kMaxK + q];
+                        for (int a = 0; a < m; ++a) v -= Bj[r * kMaxK + a] * X[a][q];
+                        Sj[r * kMaxK + q] = v;
+                    }
+                for (int r = 0; r < m; ++r)
+                    for (int q = r + 1; q < m; ++q) {
+                        const double v = 0.5 * (Sj[r * kMaxK + q] + Sj[q * kMaxK + r]);
+                        Sj[r * kMaxK + q] = v;
+                        Sj[q * kMaxK + r] = v;
+                    }
+                double z[kMaxK];
+                host_chol_solve(m, Rp, &g[(size_t)(j - 1) * kMaxK], z);
+                for (int r = 0; r < m; ++r) {
+                    double v = 0.0;
+                    for (int q = 0; q < m; ++q) v -= Bj[r * kMaxK + q] * z[q];
+                    gj[r] = v;
+                }
+            }
+            if (!host_chol(m, Sj, &Rc[(size_t)j * S])) return false;
+        }
+        // back substitution: x_it = S_it^-1 g_it, x_j = S_j^-1 (g_j - B_(j+1)^T x_(j+1))
+        std::vector<double> x((size_t)it * kMaxK);
+        for (int j = it - 1; j >= 0; --j) {
+            double rhs[kMaxK];
+            for (int r = 0; r < m; ++r) rhs[r] = g[(size_t)j * kMaxK + r];
+            if (j + 1 < it) {
+                const double *Bn = &B[(size_t)(j + 1) * S];
+                for (int r = 0; r < m; ++r)
+                    for (int q = 0; q < m; ++q) rhs[r] -= Bn[q * kMaxK + r] * x[(size_t)(j + 1) * kMaxK + q];
+            }
+            host_chol_solve(m, &Rc[(size_t)j * S], rhs, &x[(size_t)j * kMaxK]);
+        }
+        for (int j = 0; j < it; ++j)
+            for (int r = 0; r < m; ++r) ZU[((size_t)j * kMaxK + r) * kMaxK + l] = x[(size_t)j * kMaxK + r];
+    }
+    // Z = (Z U) U^T P^-1
+    G.assign((size_t)it * S, 0.0);
+    for (int j = 0; j < it; ++j)
+        for (int r = 0; r < m; ++r)
+            for (int c = 0; c < m; ++c) {
+                double v = 0.0;
+                for (int l = 0; l < m; ++l) v += ZU[((size_t)j * kMaxK + r) * kMaxK + l] * U[c][l];
+                G[(size_t)j * S + r * kMaxK + c] = v / tau[c];
+            }
+    return true;
+}
+
+int lanczos_impl(const sylv_sep_problem *p, const double *Y, double *X,
+                 const sylv_lanczos_opts *o, sylv_lanczos_stats *stats, void *ws,
+                 size_t ws_bytes, hipStream_t s) {
+    const int k = p->k, f = p->f;
+    LzLayout L;
+    if (!make_lz_layout(p, o, L)) return SYLV_E_INVALID;
+    int rc = check_ws(ws, ws_bytes, L.total);
+    if (rc) return rc;
+    char *base = reinterpret_cast<char *>(ws);
+    // small parameters to the host (Lemma 2's eigenproblem is solved here)
+    double tau[kMaxK], A[kMaxF * kMaxK], t[kMaxF];
+    HIP_TRY(hipMemcpyAsync(tau, p->tau, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(A, p->A, sizeof(double) * f * k, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(t, p->t, sizeof(double) * f, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int j = 0; j < k; ++j)
+        if (!(tau[j] > 0.0) || !isfinite(tau[j])) { set_err("tau[%d] must be finite and > 0", j); return SYLV_E_INVALID; }
+    for (int i = 0; i < f; ++i)
+        if (!(t[i] > 0.0) || !isfinite(t[i])) { set_err("t[%d] must be finite and > 0", i); return SYLV_E_INVALID; }
+    LzConst C;
+    memset(&C, 0, sizeof(C));
+    const double ks = p->kappa * p->kappa;
+    C.coef[0] = (ks + 4.0) * (ks + 4.0) + 4.0;
+    C.coef[1] = -2.0 * (ks + 4.0);
+    C.coef[2] = 2.0;
+    C.coef[3] = 1.0;
+    for (int j = 0; j < k; ++j) {
+        C.tau[j] = tau[j];
+        for (int i = 0; i < f; ++i) C.tap[j][i] = t[i] * A[i * k + j] / tau[j];
+        for (int q = 0; q < k; ++q) {
+            double v = 0.0;
+            for (int i = 0; i < f; ++i) v += A[i * k + j] * t[i] * A[i * k + q];
+            C.ata[j][q] = v;
+        }
+    }
+    // Lemma 2: P^-1/2 A^T T A P^-1/2 = V diag(rho) V^T, U = P^1/2 V
+    double Sm[kMaxK][kMaxK], Vm[kMaxK][kMaxK];
+    for (int j = 0; j < k; ++j)
+        for (int q = 0; q < k; ++q) Sm[j][q] = C.ata[j][q] / sqrt(tau[j] * tau[q]);
+    sym_eig(k, Sm, C.rho, Vm);
+    if (!(C.rho[0] > 0.0)) { set_err("A^T T A is not positive definite (A must have full column rank)"); return SYLV_E_INVALID; }
+    for (int j = 0; j < k; ++j)
+        for (int q = 0; q < k; ++q) C.U[j][q] = sqrt(tau[j]) * Vm[j][q];
+    C.tol = o->tol;
+
+    LzArgs a;
+    memset(&a, 0, sizeof(a));
+    a.ny = (int)p->ny; a.nx = (int)p->nx; a.n_pix = (int)(p->ny * p->nx); a.k = k; a.f = f;
+    a.tiles_x = (a.nx + kTileX - 1) / kTileX;
+    a.ntiles = lz_tiles(a.ny, a.nx);
+    a.nchunks = chunks_for(a.n_pix);
+    a.nred = L.nred;
+    a.c = reinterpret_cast<const LzConst *>(base + L.cst);
+    a.st = reinterpret_cast<LzState *>(base + L.state);
+    a.H = reinterpret_cast<double *>(base + L.H);
+    a.B = reinterpret_cast<double *>(base + L.B);
+    a.Binv = reinterpret_cast<double *>(base + L.Binv);
+    a.hist = reinterpret_cast<double *>(base + L.hist);
+    a.partial = reinterpret_cast<double *>(base + L.partial);
+    a.n = p->n;
+    a.Y = Y;
+    a.Yh = reinterpret_cast<double *>(base + L.Yh);
+    a.Wn = reinterpret_cast<double *>(base + L.Wn);
+    a.Wa = reinterpret_cast<double *>(base + L.Wa);
+    a.basis = reinterpret_cast<double *>(base + L.basis);
+    a.X = X;
+    a.G = reinterpret_cast<const double *>(base + L.G);
+
+    HIP_TRY(hipMemcpyAsync(base + L.cst, &C, sizeof(C), hipMemcpyHostToDevice, s));
+    HIP_TRY(lz_launch_init(a, o->max_iter, s));
+    HIP_TRY(lz_launch_start(a, s));
+    HostFlags *fl = nullptr;
+    if ((rc = host_flags(fl))) return rc;
+    // Lanczos steps in batches, one batch always queued ahead of the completion check
+    const int chunk = o->check_every > 0 ? o->check_every : 8;
+    int it = 1;
+    auto enqueue_batch = [&](int slot) -> int {
+        for (int c = 0; c < chunk && it <= o->max_iter; ++c, ++it) HIP_TRY(lz_launch_step(a, it, s));
+        HIP_TRY(lz_launch_flag(a, fl->pinned + slot, s));
+        HIP_TRY(hipEventRecord(fl->ev[slot], s));
+        return SYLV_OK;
+    };
+    if ((rc = enqueue_batch(0))) return rc;
+    for (int cur = 0;; cur ^= 1) {
+        const bool more = it <= o->max_iter;
+        if (more && (rc = enqueue_batch(cur ^ 1))) return rc;
+        int running = 0;
+        if ((rc = wait_count(fl, cur, running))) return rc;
+        if (running == 0 || !more) {
+            if (more && (rc = wait_count(fl, cur ^ 1, running))) return rc;
+            break;
+        }
+    }
+    // coefficients of the approximation from H and B (host), then assemble and check on the device
+    LzState st;
+    HIP_TRY(hipMemcpyAsync(&st, base + L.state, sizeof(LzState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int iters = std::max(0, std::min(st.iter, o->max_iter));
+    int status = st.done ? st.status : SYLV_NOT_CONVERGED;
+    std::vector<double> Hh((size_t)iters * kLzStride), Bh((size_t)(iters + 1) * kLzStride), Gh;
+    if (iters > 0) {
+        HIP_TRY(hipMemcpyAsync(Hh.data(), base + L.H, sizeof(double) * Hh.size(), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(Bh.data(), base + L.B, sizeof(double) * Bh.size(), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (!lz_coefficients(k, iters, Hh, Bh, C.U, C.rho, tau, Gh)) {
+            status = SYLV_BREAKDOWN;
+            iters = 0;
+        } else {
+            HIP_TRY(hipMemcpyAsync(base + L.G, Gh.data(), sizeof(double) * Gh.size(), hipMemcpyHostToDevice, s));
+        }
+    }
+    HIP_TRY(lz_launch_finish(a, iters, s));
+    HIP_TRY(hipMemcpyAsync(&st, base + L.state, sizeof(LzState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (stats) {
+        stats->status = status;
+        stats->iters = iters;
+        stats->relres_est = (st.nb0 > 0.0 && st.gamma >= 0.0) ? sqrt(st.gamma) / st.nb0 : (st.nb0 > 0.0 ? NAN : 0.0);
+        stats->relres_true = st.bb > 0.0 ? sqrt(st.rr / st.bb) : 0.0;
+    }
+    return SYLV_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -639,6 +977,21 @@ int sylv_pcg_backward(const sylv_problem *prob, const double *Y, const double *X
     return SYLV_OK;
 }
 
+size_t sylv_lanczos_workspace_bytes(const sylv_sep_problem *prob, const sylv_lanczos_opts *opts) {
+    if (!check_sep(prob) || !check_lz_opts(opts)) return 0;
+    LzLayout L;
+    if (!make_lz_layout(prob, opts, L)) return 0;
+    return L.total;
+}
+
+int sylv_lanczos_solve(const sylv_sep_problem *prob, const double *Y, double *X,
+                       const sylv_lanczos_opts *opts, sylv_lanczos_stats *stats, void *ws,
+                       size_t ws_bytes, void *stream) {
+    if (!check_sep(prob) || !check_lz_opts(opts)) return SYLV_E_INVALID;
+    if (!Y || !X) { set_err("null Y or X"); return SYLV_E_INVALID; }
+    return lanczos_impl(prob, Y, X, opts, stats, ws, ws_bytes, reinterpret_cast<hipStream_t>(stream));
+}
+
 const char *sylv_status_string(int code) {
     switch (code) {
         case SYLV_OK: return "ok";
@@ -646,6 +999,7 @@ const char *sylv_status_string(int code) {
         case SYLV_BREAKDOWN: return "breakdown (operator or preconditioner not positive definite)";
         case SYLV_NONFINITE: return "non-finite value";
         case SYLV_STAGNATED: return "refinement stagnated";
+        case SYLV_BAD_INPUT: return "invalid input values (n_p not a positive finite number)";
         case SYLV_E_INVALID: return "invalid argument";
         case SYLV_E_WORKSPACE: return "workspace too small";
         case SYLV_E_HIP: return "HIP runtime error";

@@ -187,4 +187,49 @@ hipError_t launch_bdir(const GroupSet &g, int k, int mixed, int it, hipStream_t 
 hipError_t launch_bapply(const GroupSet &g, int k, int mixed, int it, hipStream_t st);
 hipError_t launch_bupdate(const GroupSet &g, int k, int mixed, int it, hipStream_t st);
 
+// ---- Lanczos-Sylvester (sylv_lanczos.hip) ----------------------------------------------------
+// Small matrices of one solve, computed on the host before the first launch.
+struct LzConst {
+    double coef[4];               // c0, c1, cd, c2 of the 13-point stencil of (kappa^2 - Lap)^2
+    double tap[kMaxK][kMaxF];     // t_f A[f][j] / tau_j: Yhat_p[j] = sum_f Y[f][p] tap[j][f]
+    double tau[kMaxK];
+    double ata[kMaxK][kMaxK];     // A^T T A
+    double U[kMaxK][kMaxK];       // Lhat = U diag(rho) U^-1, U^T P^-1 U = I (Lemma 2)
+    double rho[kMaxK];
+    double tol;
+};
+// Device state of one solve (written only by the one-workgroup finishing kernels).
+struct LzState {
+    double nb0;                   // ||B_0||_F
+    double thresh;                // tol * ||B_0||_F
+    double gamma;                 // Alg. 5's residual estimate after the last step
+    double rr, bb;                // ||b - G x||^2 and ||b||^2 of the final check
+    int32_t iter;                 // Lanczos steps whose coefficients are complete
+    int32_t done, status, max_iter;
+    double S[kMaxK][kMaxK][kMaxK];   // per column l: Schur complement of T_i + rho_l I
+    double y[kMaxK][kMaxK];          // per column l: forward-eliminated right-hand side
+};
+constexpr int kLzStride = kMaxK * kMaxK;   // one k x k coefficient block (row-major, ld kMaxK)
+// Kernel argument block of every Lanczos-Sylvester kernel.
+struct LzArgs {
+    int ny, nx, n_pix, k, f, tiles_x, ntiles, nchunks, nred, vec4;
+    const LzConst *c;
+    LzState *st;
+    double *H;                    // [max_iter] blocks: H_1 .. (symmetric part)
+    double *B;                    // [max_iter + 1] blocks: B_0, B_2, B_3, .. (upper triangular)
+    double *Binv;                 // their inverses
+    double *hist;                 // [max_iter] sqrt(gamma_i) / ||B_0||_F
+    double *partial;              // [kLzSlots][nred]
+    const double *n, *Y;
+    double *Yh, *Wn, *Wa, *basis, *X;
+    const double *G;              // [iters] blocks of the solution coefficients Z
+};
+constexpr int kLzSlots = kMaxK * (kMaxK + 1) / 2 + 1;
+hipError_t lz_launch_init(const LzArgs &a, int max_iter, hipStream_t s);
+hipError_t lz_launch_start(const LzArgs &a, hipStream_t s);
+hipError_t lz_launch_step(const LzArgs &a, int it, hipStream_t s);
+hipError_t lz_launch_flag(const LzArgs &a, int *host_running, hipStream_t s);
+hipError_t lz_launch_finish(const LzArgs &a, int iters, hipStream_t s);
+int lz_tiles(int ny, int nx);
+
 }  // namespace sylv

@@ -122,3 +122,65 @@ def test_binding_refuses_host_tensors():
     with pytest.raises(ValueError):
         dp.c_struct()
     del np
+
+
+# ---- Lanczos-Sylvester entry points ---------------------------------------------------------
+
+def fake_sep(ny=32, nx=32, k=4, f=9, kappa=0.5):
+    return bd._SepProblem(ny, nx, k, f, kappa, FAKE, FAKE, FAKE, FAKE)
+
+
+def test_lanczos_struct_sizes():
+    # int64 x2 + int32 x2 + double + 4 pointers; double + int32 x2; int32 x2 + double x2
+    assert ctypes.sizeof(bd._SepProblem) == 64
+    assert ctypes.sizeof(bd._LzOpts) == 16
+    assert ctypes.sizeof(bd._LzStats) == 24
+
+
+def test_lanczos_workspace_holds_the_basis():
+    L = sy.lib()
+    o = bd._LzOpts(1e-8, 100, 0)
+    n1 = L.sylv_lanczos_workspace_bytes(ctypes.byref(fake_sep(64, 64)), ctypes.byref(o))
+    o2 = bd._LzOpts(1e-8, 200, 0)
+    n2 = L.sylv_lanczos_workspace_bytes(ctypes.byref(fake_sep(64, 64)), ctypes.byref(o2))
+    blk = 64 * 64 * 4 * 8
+    assert n1 >= 100 * blk + 3 * blk            # the basis plus Yhat and two running blocks
+    assert n2 - n1 >= 100 * blk                 # one more block per extra step
+
+
+@pytest.mark.parametrize("bad", [dict(k=0), dict(k=9), dict(f=0), dict(f=17), dict(ny=0),
+                                 dict(kappa=-1.0), dict(kappa=float("nan"))])
+def test_lanczos_invalid_problems_rejected(bad):
+    L = sy.lib()
+    args = dict(ny=8, nx=8, k=3, f=4, kappa=0.5)
+    args.update(bad)
+    p = fake_sep(**args)
+    o = bd._LzOpts(1e-8, 10, 0)
+    assert L.sylv_lanczos_workspace_bytes(ctypes.byref(p), ctypes.byref(o)) == 0
+    st = bd._LzStats()
+    rc = L.sylv_lanczos_solve(ctypes.byref(p), FAKE, FAKE, ctypes.byref(o), ctypes.byref(st),
+                              FAKE, 1 << 30, None)
+    assert rc == bd.SYLV_E_INVALID
+    assert len(L.sylv_last_error()) > 0
+
+
+def test_lanczos_bad_options_rejected():
+    L = sy.lib()
+    p = fake_sep()
+    st = bd._LzStats()
+    for o in [bd._LzOpts(0.0, 10, 0), bd._LzOpts(1.0, 10, 0), bd._LzOpts(1e-8, 0, 0),
+              bd._LzOpts(1e-8, 10, -1), bd._LzOpts(1e-8, 200000, 0)]:
+        assert L.sylv_lanczos_workspace_bytes(ctypes.byref(p), ctypes.byref(o)) == 0
+        rc = L.sylv_lanczos_solve(ctypes.byref(p), FAKE, FAKE, ctypes.byref(o),
+                                  ctypes.byref(st), FAKE, 1 << 30, None)
+        assert rc == bd.SYLV_E_INVALID
+    p.n = None
+    o = bd._LzOpts(1e-8, 10, 0)
+    assert L.sylv_lanczos_solve(ctypes.byref(p), FAKE, FAKE, ctypes.byref(o), ctypes.byref(st),
+                                FAKE, 1 << 30, None) == bd.SYLV_E_INVALID
+    assert L.sylv_lanczos_solve(ctypes.byref(fake_sep()), None, FAKE, ctypes.byref(o),
+                                ctypes.byref(st), FAKE, 1 << 30, None) == bd.SYLV_E_INVALID
+
+
+def test_bad_input_status_string():
+    assert "n_p" in sy.status_string(bd.SYLV_BAD_INPUT)

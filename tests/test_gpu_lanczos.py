@@ -1,0 +1,157 @@
+"""GPU parity of the Lanczos-Sylvester solver (Alg. 4 + Alg. 5) against the CPU oracle, through
+the C ABI."""
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import paper_2204_08057_amd as sy  # noqa: E402
+from oracle import lanczos as olz  # noqa: E402
+from oracle import operator as op  # noqa: E402
+from oracle import solve as osv  # noqa: E402
+from workloads import make_problem  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def say(*a):
+    print("[lanczos]", *a, flush=True)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) /
+                 max(np.linalg.norm(np.asarray(b)), 1e-300))
+
+
+def sep(ny, nx, k, f, seed, kappa=0.45):
+    p = make_problem(ny, nx, k, f, seed=seed, noise="separable", kappa=np.full(k, kappa))
+    return p, p.meta["t"], p.meta["n"]
+
+
+def run(p, t, n, tol, max_iter=400, check_every=0, Y=None):
+    sp = sy.SepProblem.from_numpy(p.ny, p.nx, p.kappa[0], p.tau, p.A, t, n)
+    Yd = torch.as_tensor(p.Y if Y is None else Y, dtype=torch.float64, device="cuda")
+    X, st = sy.lanczos_solve(sp, Yd, sy.LanczosOptions(tol=tol, max_iter=max_iter,
+                                                        check_every=check_every))
+    return X.cpu().numpy(), st
+
+
+# grids with ragged tiles in x and y, wrap coincidences (sides < 5), every k template.  The block
+# Krylov space must keep full rank up to convergence (Alg. 4 has no deflation), so every grid
+# has many more pixels than steps times k.
+SHAPES = [(8, 8, 3, 5), (70, 45, 4, 9), (2, 150, 2, 3), (33, 130, 1, 2), (16, 16, 8, 16),
+          (4, 40, 5, 6), (24, 20, 6, 9), (9, 11, 7, 8)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_converged_solution_matches_oracle(shape):
+    ny, nx, k, f = shape
+    p, t, n = sep(ny, nx, k, f, 3000 + ny * 7 + nx)
+    say("converged", shape)
+    ref = olz.lanczos_sylvester(p, t, n, tol=1e-10, max_iter=400)
+    X, st = run(p, t, n, 1e-10)
+    assert st["status"] == 0, st
+    assert ref["converged"]
+    # The stopping step is a floating-point decision taken on an estimate that, late in a run
+    # without reorthogonalisation, differs in rounding between the two sides: the GPU's stop must
+    # be valid, and the oracle's own estimate at that step close to the tolerance.
+    assert st["relres_est"] <= 1e-10
+    j = st["iters"]
+    assert abs(j - ref["iters"]) <= max(1, ref["iters"] // 20), (st, ref["iters"])
+    if j <= len(ref["history"]):
+        assert ref["history"][j - 1] <= 1e-9, (j, ref["history"][j - 3:j + 2])
+    assert rel(X, ref["x"]) < 1e-7
+    # the recomputed residual of eq. (Axb) agrees with the oracle's operator
+    r_or = rel(op.apply(p, X), op.rhs(p))
+    assert st["relres_true"] == pytest.approx(r_or, rel=1e-3, abs=1e-14)
+    if p.n_pix * k <= 3000:
+        assert rel(X, osv.solve_dense(p)) < 1e-7
+
+
+@pytest.mark.parametrize("shape", [(12, 10, 3, 5), (70, 45, 4, 9), (16, 16, 8, 16)])
+def test_every_step_matches_oracle(shape):
+    """After j steps (max_iter = j) the GPU holds the oracle's j-th Galerkin approximation and
+    Alg. 5's estimate sqrt(gamma_j)/||B_0||_F."""
+    ny, nx, k, f = shape
+    p, t, n = sep(ny, nx, k, f, 3100 + ny)
+    say("steps", shape)
+    for j in (1, 2, 3, 5, 8):
+        ref = olz.lanczos_sylvester(p, t, n, tol=1e-300, max_iter=j)
+        X, st = run(p, t, n, 1e-15, max_iter=j, check_every=3)
+        assert st["status"] == sy.binding.SYLV_NOT_CONVERGED and st["iters"] == j, st
+        assert rel(X, ref["x"]) < 1e-10, j
+        assert st["relres_est"] == pytest.approx(ref["history"][-1], rel=1e-7), j
+
+
+def test_repeatable_bitwise():
+    p, t, n = sep(40, 56, 4, 9, 3200)
+    X1, s1 = run(p, t, n, 1e-9)
+    X2, s2 = run(p, t, n, 1e-9)
+    assert np.array_equal(X1, X2) and s1 == s2
+
+
+def test_printed_planck_constants():
+    """The paper's printed A and T (App. B), kappa = 0 (the paper's D^2 prior)."""
+    A, T = [], None
+    with open(os.path.join(HERE, "golden", "planck_mixing.txt")) as fh:
+        for line in fh:
+            if line.startswith("A "):
+                A.append([float(v) for v in line.split()[1:]])
+            elif line.startswith("T "):
+                T = np.array([float(v) for v in line.split()[1:]])
+    A = np.array(A)
+    ny, nx = 24, 20
+    nvec = np.random.default_rng(19).integers(1, 4, ny * nx).astype(float)
+    p = make_problem(ny, nx, 4, 9, seed=19, kappa=np.zeros(4), tau=np.ones(4), A=A)
+    p.W = np.outer(T, nvec)
+    ref = olz.lanczos_sylvester(p, T, nvec, tol=1e-12, max_iter=300)
+    X, st = run(p, T, nvec, 1e-12, max_iter=300)
+    assert st["status"] == 0
+    assert rel(X, ref["x"]) < 1e-8
+    assert rel(X, osv.solve_kohler(p, T, nvec)) < 1e-7
+
+
+def test_zero_data_gives_zero_solution():
+    p, t, n = sep(16, 20, 3, 4, 3300)
+    X, st = run(p, t, n, 1e-8, Y=np.zeros_like(p.Y))
+    assert st["status"] == 0 and st["iters"] == 0
+    assert np.all(X == 0.0)
+
+
+def test_invalid_pixel_precision_reported():
+    p, t, n = sep(16, 20, 3, 4, 3301)
+    n = n.copy()
+    n[17] = 0.0
+    X, st = run(p, t, n, 1e-8)
+    assert st["status"] == sy.binding.SYLV_BAD_INPUT and st["iters"] == 0
+
+
+def test_rank_deficient_mixing_rejected():
+    p, t, n = sep(8, 8, 3, 4, 3302)
+    p.A[:, 2] = p.A[:, 1]
+    with pytest.raises(sy.SylvError):
+        run(p, t, n, 1e-8)
+
+
+def test_full_size_1024_matches_cg_and_sampled_residual():
+    """1024 x 1024, k = 4, f = 9 (one level-10 HEALPix patch with Planck's map and source
+    counts): the Lanczos-Sylvester solution equals the float64 PCG solution of the same system,
+    and the residual at sampled pixels, computed by the oracle's operator, is small."""
+    p, t, n = sep(1024, 1024, 4, 9, 3400, kappa=0.3)
+    say("full size 1024^2")
+    X, st = run(p, t, n, 1e-10, max_iter=600)
+    assert st["status"] == 0, st
+    assert st["relres_true"] < 1e-8, st
+    dp = sy.DeviceProblem.from_numpy(p)
+    Xc, sc = sy.pcg_solve(dp, Y=torch.as_tensor(p.Y, device="cuda"),
+                          opts=sy.SolveOptions(tol=1e-11, precision=sy.SYLV_PREC_F64))
+    assert sc[0]["status"] == 0
+    assert rel(X, Xc.cpu().numpy().reshape(p.k, p.n_pix)) < 1e-7
+    pix = np.random.default_rng(5).choice(p.n_pix, 3000, replace=False)
+    gx = op.apply_at(p, X, pix)
+    b = p.A.T @ (p.W[:, pix] * p.Y[:, pix])          # B^T C Y at those pixels (eq. (mu*))
+    assert rel(gx, b) < 1e-7
