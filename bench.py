@@ -13,7 +13,8 @@ runs on.  Prints one JSON line.
 
 --mode pmc runs only a device copy of known size, the applies and one solve of each precision,
 for hardware-counter runs (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE) that calibrate the
-HBM-traffic figure.
+HBM-traffic figure.  --mode sylv runs only the Lanczos-Sylvester workload (1024^2, k = 4, f = 9,
+separable noise, common kappa) against PCG on the same system.
 """
 from __future__ import annotations
 
@@ -202,7 +203,51 @@ def bench_other_workloads(sy, torch, steps, warmup):
     out["grad_512"] = {"forward": summarize(ms_f, st), "backward_ms": round(ms_b, 3),
                        "backward_iters": stb["iters"], "backward_ok": stb["status"] == 0}
     log(f"grad_512: {out['grad_512']}")
+    out["sylv_1024"] = bench_sylvester(sy, torch, steps, warmup)
     return out
+
+
+def bench_sylvester(sy, torch, steps, warmup, max_iter=800):
+    """1024^2, k = 4, f = 9, separable noise, common kappa: the Lanczos-Sylvester solver
+    (Alg. 4 + Alg. 5) against float64 and mixed PCG on the same system, all to 1e-8."""
+    from workloads import WORKLOADS, workload
+    prob = workload("sylv_1024")[0]
+    tol = WORKLOADS["sylv_1024"]["tol"]
+    t, n = prob.meta["t"], prob.meta["n"]
+    sp = sy.SepProblem.from_numpy(prob.ny, prob.nx, prob.kappa[0], prob.tau, prob.A, t, n)
+    Y = torch.as_tensor(prob.Y, device="cuda")
+    lo = sy.LanczosOptions(tol=tol, max_iter=max_iter)
+    ws = torch.empty(sy.lanczos_workspace_bytes(sp, lo), dtype=torch.uint8, device="cuda")
+    X = torch.empty((prob.k, prob.n_pix), dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        sy.lanczos_solve(sp, Y, lo, ws=ws, out=X)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        _, st = sy.lanczos_solve(sp, Y, lo, ws=ws, out=X)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+    res = {"lanczos_sylvester": {"ms": round(statistics.median(times), 3), "iters": st["iters"],
+                                 "relres_est": st["relres_est"],
+                                 "relres_true": st["relres_true"],
+                                 "ok": st["status"] == 0,
+                                 "workspace_gb": round(ws.numel() / 1e9, 2)}}
+    log(f"sylv_1024 lanczos: {res['lanczos_sylvester']}")
+    del ws
+    dp = sy.DeviceProblem.from_numpy(prob)
+    xs = {"lanczos_sylvester": X}
+    for label, prec in (("pcg_f64", sy.SYLV_PREC_F64), ("pcg_mixed", sy.SYLV_PREC_MIXED)):
+        o = sy.SolveOptions(tol=tol, precision=prec)
+        ms, stl, Xc = time_solves(sy, torch, dp, Y, None, o, 1, steps, warmup)
+        res[label] = summarize(ms, stl)
+        xs[label] = Xc.reshape(prob.k, prob.n_pix)
+        log(f"sylv_1024 {label}: {res[label]}")
+    xref = xs["pcg_f64"]
+    res["rel_diff_lanczos_vs_pcg_f64"] = float(torch.linalg.norm(X - xref) /
+                                               torch.linalg.norm(xref))
+    res["kappa"] = float(prob.kappa[0])
+    return res
 
 
 def main():
@@ -214,7 +259,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the 2048^2, batched and differentiable workloads")
-    ap.add_argument("--mode", default="bench", choices=["bench", "pmc"])
+    ap.add_argument("--mode", default="bench", choices=["bench", "pmc", "sylv"],
+                    help="pmc: copy + applies + one solve of each precision (counter runs); "
+                         "sylv: only the Lanczos-Sylvester workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver has no "
@@ -228,6 +275,10 @@ def main():
     from workloads import WORKLOADS, workload
 
     torch.cuda.set_device(0)
+    if args.mode == "sylv":
+        print(json.dumps({"mode": "sylv", "sylv_1024": bench_sylvester(
+            sy, torch, max(2, args.steps // 2), max(1, args.warmup))}), flush=True)
+        return
     name = "het_1024"
     cfg = WORKLOADS[name]
     prob = workload(name)[0]

@@ -513,7 +513,7 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
 // ---- Lanczos-Sylvester (Section 3.3, Alg. 4 and Alg. 5) ---------------------------------------
 
 struct LzLayout {
-    size_t cst, state, H, B, Binv, hist, G, partial, Yh, Wn, Wa, basis, total;
+    size_t cst, state, H, B, Binv, hist, G, partial, partial2, Yh, Wa0, Wa1, basis, total;
     int nred;
 };
 
@@ -551,9 +551,10 @@ bool make_lz_layout(const sylv_sep_problem *p, const sylv_lanczos_opts *o, LzLay
     L.hist = off;    off = align_up(off + sizeof(double) * mi);
     L.G = off;       off = align_up(off + sizeof(double) * kLzStride * mi);
     L.partial = off; off = align_up(off + sizeof(double) * kLzSlots * L.nred);
+    L.partial2 = off; off = align_up(off + sizeof(double) * kLzSlots);
     L.Yh = off;      off = align_up(off + vb);
-    L.Wn = off;      off = align_up(off + vb);
-    L.Wa = off;      off = align_up(off + vb);
+    L.Wa0 = off;     off = align_up(off + vb);
+    L.Wa1 = off;     off = align_up(off + vb);
     L.basis = off;   off = align_up(off + vb * mi);
     L.total = off;
     return true;
@@ -782,11 +783,12 @@ int lanczos_impl(const sylv_sep_problem *p, const double *Y, double *X,
     a.Binv = reinterpret_cast<double *>(base + L.Binv);
     a.hist = reinterpret_cast<double *>(base + L.hist);
     a.partial = reinterpret_cast<double *>(base + L.partial);
+    a.partial2 = reinterpret_cast<double *>(base + L.partial2);
     a.n = p->n;
     a.Y = Y;
     a.Yh = reinterpret_cast<double *>(base + L.Yh);
-    a.Wn = reinterpret_cast<double *>(base + L.Wn);
-    a.Wa = reinterpret_cast<double *>(base + L.Wa);
+    a.Wa0 = reinterpret_cast<double *>(base + L.Wa0);
+    a.Wa1 = reinterpret_cast<double *>(base + L.Wa1);
     a.basis = reinterpret_cast<double *>(base + L.basis);
     a.X = X;
     a.G = reinterpret_cast<const double *>(base + L.G);

@@ -212,19 +212,21 @@ struct LzState {
 constexpr int kLzStride = kMaxK * kMaxK;   // one k x k coefficient block (row-major, ld kMaxK)
 // Kernel argument block of every Lanczos-Sylvester kernel.
 struct LzArgs {
-    int ny, nx, n_pix, k, f, tiles_x, ntiles, nchunks, nred, vec4;
+    int ny, nx, n_pix, k, f, tiles_x, ntiles, nchunks, nred;
     const LzConst *c;
     LzState *st;
     double *H;                    // [max_iter] blocks: H_1 .. (symmetric part)
     double *B;                    // [max_iter + 1] blocks: B_0, B_2, B_3, .. (upper triangular)
     double *Binv;                 // their inverses
     double *hist;                 // [max_iter] sqrt(gamma_i) / ||B_0||_F
-    double *partial;              // [kLzSlots][nred]
+    double *partial;              // [kLzSlots][nred]: per-workgroup partials of a pass
+    double *partial2;             // [kLzSlots]: the final sums of a pass
     const double *n, *Y;
-    double *Yh, *Wn, *Wa, *basis, *X;
+    double *Yh, *Wa0, *Wa1, *basis, *X;
     const double *G;              // [iters] blocks of the solution coefficients Z
 };
-constexpr int kLzSlots = kMaxK * (kMaxK + 1) / 2 + 1;
+// P = V^T N Wa (k^2), C = V^T N V and E = Wa^T N Wa (k(k+1)/2 each), plus one count
+constexpr int kLzSlots = kMaxK * kMaxK + kMaxK * (kMaxK + 1) + 1;
 hipError_t lz_launch_init(const LzArgs &a, int max_iter, hipStream_t s);
 hipError_t lz_launch_start(const LzArgs &a, hipStream_t s);
 hipError_t lz_launch_step(const LzArgs &a, int it, hipStream_t s);

@@ -1,23 +1,28 @@
 // Lanczos-Sylvester kernels (Section 3.3): the symmetric block Lanczos process for N^-1 D2 in the
 // N inner product (Alg. 4) and the device side of the symmetric sparse Sylvester solver around
-// it (Alg. 5).  One Lanczos step i is four launches:
+// it (Alg. 5).  One Lanczos step i is one pass over the grid and a two-stage reduction:
 //
-//   k_lz_stencil<STEP>  V_i = W_(i-1) B_i^-1 formed while the tile and its 2-pixel halo are staged
-//                       in LDS (the Cholesky-QR normalisation of the previous block, fused), V_i
-//                       stored as basis block i, W = N^-1 D2 V_i - V_(i-1) B_i^T (13-point stencil
-//                       of (kappa^2 - Lap)^2), partials of H_i = V_i^T N W;
-//   k_lz_hfin           H_i (symmetric part) from the partials, fixed order;
-//   k_lz_orth           W <- W - V_i H_i, partials of the N-Gram matrix W^T N W;
-//   k_lz_qr             W^T N W = B_(i+1)^T B_(i+1) (Cholesky), B_(i+1)^-1, and Alg. 5's residual
-//                       estimate gamma, carried by a block forward elimination of T_i + rho_l I
-//                       (one thread per eigenvalue rho_l of Lhat) instead of an eigendecomposition
-//                       of T_i at every step; the stopping test.
+//   k_lz_stencil<STEP>  stages Wa_(i-1) and V_(i-1) (tile + 2-pixel periodic halo) and forms, per
+//                       staged pixel, the orthogonalised block of the previous step
+//                       W_(i-1) = Wa_(i-1) - V_(i-1) H_(i-1) and its Cholesky-QR normalisation
+//                       V_i = W_(i-1) B_i^-1 in LDS; stores V_i (basis block i) and
+//                       Wa_i = N^-1 D2 V_i - V_(i-1) B_i^T (13-point stencil of (kappa^2 - Lap)^2),
+//                       with the partials of P = V_i^T N Wa_i, C = V_i^T N V_i, E = Wa_i^T N Wa_i;
+//   k_lz_reduce         one workgroup per reduced quantity: the fixed-order sum of the partials;
+//   k_lz_fin            H_i = sym(P) (Alg. 4), the N-Gram matrix of W_i = Wa_i - V_i H_i by the
+//                       exact expansion W_i^T N W_i = E - P^T H_i - H_i P + H_i C H_i (no
+//                       orthogonality assumed), its Cholesky factor B_(i+1) and inverse, and
+//                       Alg. 5's residual estimate gamma, carried by a block forward elimination of
+//                       T_i + rho_l I (one thread per eigenvalue rho_l of Lhat) instead of an
+//                       eigendecomposition of T_i per step; the stopping test.
 //
-// The blocks V_i stay in the workspace, so the approximation M = sum_i V_i G_i is one streaming
-// pass over them (k_lz_assemble) once the host has solved the small projected equation for the
-// G_i, instead of the paper's second Lanczos pass.  A last stencil pass recomputes the residual
-// of eq. (Axb) for the statistics.  All reductions are per-workgroup partials summed in a fixed
-// order by a one-workgroup kernel, so results are bitwise repeatable.
+// Evaluating the Gram matrix by the expansion lets W_i live only in registers of the next pass,
+// so a step moves (4k + 1) planes instead of materialising W, orthogonalising it and reading it
+// again.  The blocks V_i stay in the workspace, so the approximation M = sum_i V_i G_i is one
+// streaming pass over them (k_lz_assemble) once the host has solved the small projected equation
+// for the G_i, instead of the paper's second Lanczos pass.  A last stencil pass recomputes the
+// residual of eq. (Axb).  All reductions sum per-workgroup partials in a fixed order, so results
+// are bitwise repeatable.
 
 #include "sylv_device.h"
 
@@ -34,37 +39,55 @@ __device__ __forceinline__ const double *cblk(const double *base, int i) {
 }
 __device__ __forceinline__ double *wblk(double *base, int i) { return base + (size_t)i * kLzStride; }
 
-// Workgroup partial of the packed symmetric matrix sum_t wt_t sym(u_t w_t^T) (upper triangle row
-// by row, K (K + 1) / 2 values) and, if EXTRA, one more scalar; stored at partial[slot * nred +
-// blkid].  Each value is reduced in turn, so only one is live at a time.
-template <int K, int NP, bool EXTRA>
-__device__ __forceinline__ void sym_partials(const double (&u)[NP][K], const double (&w)[NP][K],
-                                             const double (&wt)[NP], double extra,
-                                             double *partial, int nred, int blkid) {
-    constexpr int PK = K * (K + 1) / 2;
-    constexpr int NV = PK + (EXTRA ? 1 : 0);
-    __shared__ double sm[NV][kBlock / 64];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    int e = 0;
-#pragma unroll
-    for (int a = 0; a < K; ++a) {
-#pragma unroll
-        for (int b = a; b < K; ++b, ++e) {
-            double v = 0.0;
-#pragma unroll
-            for (int t = 0; t < NP; ++t) v += wt[t] * (0.5 * (u[t][a] * w[t][b] + u[t][b] * w[t][a]));
-            v = wave_sum(v);
-            if (lane == 0) sm[e][wid] = v;
-        }
-    }
-    if constexpr (EXTRA) {
-        const double v = wave_sum(extra);
-        if (lane == 0) sm[PK][wid] = v;
-    }
+template <int K>
+constexpr int lz_nv_step() { return K * K + K * (K + 1); }   // P, C, E
+template <int K>
+constexpr int lz_nv_start() { return K * (K + 1) / 2 + 1; }  // Gram of Yhat, invalid-n count
+
+// Workgroup-reduce one value per thread (fixed order) into slot `e` of the LDS table.
+__device__ __forceinline__ void put_wave(double v, double (*sm)[kBlock / 64], int e) {
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) sm[e][threadIdx.x >> 6] = v;
+}
+template <int NV>
+__device__ __forceinline__ void store_partials(double (*sm)[kBlock / 64], double *partial,
+                                               int nred, int blkid) {
     __syncthreads();
-    if (threadIdx.x < NV) {
-        const int i = threadIdx.x;
+    for (int i = threadIdx.x; i < NV; i += kBlock)
         gp(partial)[(size_t)i * nred + blkid] = (sm[i][0] + sm[i][1]) + (sm[i][2] + sm[i][3]);
+}
+
+// Workgroup partials of NV values per thread through LDS (red: at least CH * (kBlock + 16)
+// doubles, free on entry): in chunks of CH values every thread stores its values, then 16 threads
+// per value sum 16 strided entries each and one thread per value sums those 16 (fixed order).
+// Partial v of the workgroup goes to partial[v * nred + blkid].
+template <int NV, int CH>
+__device__ __forceinline__ void lds_partials(const double (&vals)[NV], double *red,
+                                             double *partial, int nred, int blkid) {
+    static_assert(CH * 16 <= kBlock, "16 threads per value of a chunk");
+    double *red2 = red + CH * kBlock;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int c0 = 0; c0 < NV; c0 += CH) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < CH; ++i)
+            if (c0 + i < NV) red[i * kBlock + tid] = vals[c0 + i];
+        __syncthreads();
+        if (tid < CH * 16) {
+            const int i = tid >> 4, g = tid & 15;
+            double s = 0.0;
+#pragma unroll
+            for (int u = 0; u < kBlock / 16; ++u) s += red[i * kBlock + u * 16 + g];
+            red2[i * 16 + g] = s;
+        }
+        __syncthreads();
+        if (tid < CH && c0 + tid < NV) {
+            double s = 0.0;
+#pragma unroll
+            for (int g = 0; g < 16; ++g) s += red2[tid * 16 + g];
+            gp(partial)[(size_t)(c0 + tid) * nred + blkid] = s;
+        }
     }
 }
 
@@ -74,11 +97,8 @@ __device__ __forceinline__ void sym_partials(const double (&u)[NP][K], const dou
 // positive or not finite.
 template <int K>
 __device__ bool chol_upper(const double (&g)[K][K], double (&r)[K][K]) {
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-#pragma unroll
+    for (int i = 0; i < K; ++i)
         for (int j = 0; j < K; ++j) r[i][j] = 0.0;
-    }
     for (int i = 0; i < K; ++i) {
         double d = g[i][i];
         for (int a = 0; a < i; ++a) d -= r[a][i] * r[a][i];
@@ -135,8 +155,8 @@ __global__ void k_lz_init(LzArgs a, int max_iter) {
     }
 }
 
-// Start block Yhat = Y^T T A P^-1 (eq. (Axb-Sylv)), written to Yh and to the running block W,
-// with the partials of its N-Gram matrix and a count of invalid n_p.
+// Start block Yhat = Y^T T A P^-1 (eq. (Axb-Sylv)) into Yh, with the partials of its N-Gram
+// matrix (packed upper triangle) and a count of invalid n_p.
 template <int K>
 __global__ __launch_bounds__(kBlock) void k_lz_start(LzArgs a) {
     const int chunk = xcd_remap(blockIdx.x, a.nchunks);
@@ -162,26 +182,38 @@ __global__ __launch_bounds__(kBlock) void k_lz_start(LzArgs a) {
                 for (int j = 0; j < K; ++j) yh[e][j] += y * c->tap[j][fi];
             }
 #pragma unroll
-            for (int j = 0; j < K; ++j) {
-                gp(a.Yh)[(size_t)j * n_pix + p] = yh[e][j];
-                gp(a.Wn)[(size_t)j * n_pix + p] = yh[e][j];
-            }
+            for (int j = 0; j < K; ++j) gp(a.Yh)[(size_t)j * n_pix + p] = yh[e][j];
         }
     }
-    sym_partials<K, 4, true>(yh, yh, wt, bad, a.partial, a.nred, chunk);
+    constexpr int NV = lz_nv_start<K>();
+    __shared__ double sm[NV][kBlock / 64];
+    int e = 0;
+#pragma unroll
+    for (int r = 0; r < K; ++r)
+#pragma unroll
+        for (int q = r; q < K; ++q, ++e) {
+            double v = 0.0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) v += wt[t] * (yh[t][r] * yh[t][q]);
+            put_wave(v, sm, e);
+        }
+    put_wave(bad, sm, NV - 1);
+    store_partials<NV>(sm, a.partial, a.nred, chunk);
 }
 
-// Stencil kernels.  STEP: one Lanczos step's product (see the file comment).  RESID: residual of
-// eq. (Axb) for X: r_j = n_p tau_j Yhat_j - (tau_j D2 X_j + n_p (A^T T A X_p)_j), with the
-// partials of ||r||^2 and ||b||^2.
+// Stencil kernels.  STEP: one Lanczos step (see the file comment).  RESID: residual of eq. (Axb)
+// for X: r_j = n_p tau_j Yhat_j - (tau_j D2 X_j + n_p (A^T T A X_p)_j), with the partials of
+// ||r||^2 and ||b||^2.
 template <int K, int MODE>
 __global__ __launch_bounds__(kBlock) void k_lz_stencil(LzArgs a, int it) {
     constexpr int R = kLzRows;
     constexpr int LH = kWavesY * R + 4;   // staged rows: tile + 2-row halo above and below
     constexpr int LW = kTileX + 4;        // staged columns
     constexpr int RPW = LH / kWavesY;     // staged rows per wavefront
-    LzState *st = a.st;
-    if (MODE == LZ_STEP && st->done) return;
+    constexpr bool STEP = MODE == LZ_STEP;
+    const LzState *st = a.st;
+    if (STEP && st->done) return;
+    const bool prev = STEP && it > 1;     // a previous block exists
     const int tile = xcd_remap(blockIdx.x, a.ntiles);
     const int nx = a.nx, ny = a.ny, n_pix = a.n_pix;
     const LzConst *c = a.c;
@@ -192,8 +224,11 @@ __global__ __launch_bounds__(kBlock) void k_lz_stencil(LzArgs a, int it) {
     const int iy0 = y0 + ty * R;
     const bool active = (ix < nx) && (iy0 < ny);
 
-    // ---- issue the global loads: staged field, then per-output-pixel data ------------------
-    const GAS double *src = gp(MODE == LZ_STEP ? (const double *)a.Wn : (const double *)a.X);
+    // ---- issue the global loads: staged fields, then per-output-pixel data -----------------
+    const double *src0;                     // STEP: Wa_(i-1) (Yhat at i = 1); RESID: X
+    if constexpr (STEP) src0 = (it == 1) ? a.Yh : ((it & 1) ? a.Wa1 : a.Wa0);
+    else src0 = a.X;
+    const GAS double *vprev = gp(a.basis) + (size_t)(prev ? it - 2 : 0) * K * n_pix;
     const int cmain = wrapi(x0 + tx, nx);
     const int hitem = ty * 64 + tx;
     const int hr = hitem >> 2, hc = hitem & 3;
@@ -203,13 +238,23 @@ __global__ __launch_bounds__(kBlock) void k_lz_stencil(LzArgs a, int it) {
     int soff[RPW];
 #pragma unroll
     for (int rr = 0; rr < RPW; ++rr) soff[rr] = wrapi(y0 - 2 + rr * kWavesY + ty, ny) * nx + cmain;
-    double sa[K][RPW], ha[K];
+    double sa[K][RPW], ha[K], sv[K][RPW], hv[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-        const GAS double *s = src + (size_t)j * n_pix;
+        const GAS double *s = gp(src0) + (size_t)j * n_pix;
 #pragma unroll
         for (int rr = 0; rr < RPW; ++rr) sa[j][rr] = s[soff[rr]];
         ha[j] = hvalid ? s[hoff] : 0.0;
+        if (prev) {
+            const GAS double *v = vprev + (size_t)j * n_pix;
+#pragma unroll
+            for (int rr = 0; rr < RPW; ++rr) sv[j][rr] = v[soff[rr]];
+            hv[j] = hvalid ? v[hoff] : 0.0;
+        } else {
+#pragma unroll
+            for (int rr = 0; rr < RPW; ++rr) sv[j][rr] = 0.0;
+            hv[j] = 0.0;
+        }
     }
     const int ixc = ix < nx ? ix : 0;
     double nv[R], aux[R][K];
@@ -219,39 +264,46 @@ __global__ __launch_bounds__(kBlock) void k_lz_stencil(LzArgs a, int it) {
         nv[t] = gp(a.n)[pix];
 #pragma unroll
         for (int j = 0; j < K; ++j) aux[t][j] = 0.0;
-        if (MODE == LZ_STEP && it > 1) {
-            const GAS double *vo = gp(a.basis) + (size_t)(it - 2) * K * n_pix;
+        if (prev) {          // V_(i-1) at the output pixels (just staged: served by L2)
 #pragma unroll
-            for (int j = 0; j < K; ++j) aux[t][j] = vo[(size_t)j * n_pix + pix];
+            for (int j = 0; j < K; ++j) aux[t][j] = vprev[(size_t)j * n_pix + pix];
         } else if (MODE == LZ_RESID) {
 #pragma unroll
             for (int j = 0; j < K; ++j) aux[t][j] = gp(a.Yh)[(size_t)j * n_pix + pix];
         }
     }
 
-    // ---- stage the field in LDS (STEP: normalised, V_i = W B_i^-1) ---------------------------
+    // ---- stage the field in LDS (STEP: V_i = (Wa_(i-1) - V_(i-1) H_(i-1)) B_i^-1) ------------
     __shared__ double lds[K][LH][LW];
-    const double *Bi = (MODE == LZ_STEP) ? cblk(a.B, it - 1) : nullptr;
-    const double *Binv = (MODE == LZ_STEP) ? cblk(a.Binv, it - 1) : nullptr;
+    const double *Bi = STEP ? cblk(a.B, it - 1) : nullptr;
+    const double *Binv = STEP ? cblk(a.Binv, it - 1) : nullptr;
+    const double *Hp = prev ? cblk(a.H, it - 2) : nullptr;
 #pragma unroll
     for (int rr = 0; rr <= RPW; ++rr) {
         if (rr == RPW && !hvalid) break;
-        double w[K];
-#pragma unroll
-        for (int j = 0; j < K; ++j) w[j] = (rr < RPW) ? sa[j][rr] : ha[j];
         const int row = (rr < RPW) ? rr * kWavesY + ty : hr;
         const int col = (rr < RPW) ? tx + 2 : hcol;
+        if constexpr (STEP) {
+            double w[K];
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            double v;
-            if constexpr (MODE == LZ_STEP) {
-                v = 0.0;
+            for (int j = 0; j < K; ++j) {
+                double v = (rr < RPW) ? sa[j][rr] : ha[j];
+                if (prev) {
+#pragma unroll
+                    for (int q = 0; q < K; ++q) v -= ((rr < RPW) ? sv[q][rr] : hv[q]) * Hp[q * kMaxK + j];
+                }
+                w[j] = v;
+            }
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                double v = 0.0;
 #pragma unroll
                 for (int q = 0; q <= j; ++q) v += w[q] * Binv[q * kMaxK + j];
-            } else {
-                v = w[j];
+                lds[j][row][col] = v;
             }
-            lds[j][row][col] = v;
+        } else {
+#pragma unroll
+            for (int j = 0; j < K; ++j) lds[j][row][col] = (rr < RPW) ? sa[j][rr] : ha[j];
         }
     }
     __syncthreads();
@@ -297,17 +349,18 @@ __global__ __launch_bounds__(kBlock) void k_lz_stencil(LzArgs a, int it) {
         for (int t = 0; t < R; ++t) {
             if (iy0 + t >= ny) continue;
             const int pix = (iy0 + t) * nx + ix;
-            if constexpr (MODE == LZ_STEP) {
+            if constexpr (STEP) {
                 GAS double *vb = gp(a.basis) + (size_t)(it - 1) * K * n_pix;
+                GAS double *wa = gp((it & 1) ? a.Wa0 : a.Wa1);
 #pragma unroll
                 for (int j = 0; j < K; ++j) {
                     double w = acc[j][t] / nv[t];
-                    if (it > 1) {
+                    if (prev) {
 #pragma unroll
                         for (int q = 0; q < K; ++q) w -= aux[t][q] * Bi[j * kMaxK + q];
                     }
                     vb[(size_t)j * n_pix + pix] = ctr[j][t];
-                    gp(a.Wa)[(size_t)j * n_pix + pix] = w;
+                    wa[(size_t)j * n_pix + pix] = w;
                     uo[t][j] = ctr[j][t];
                     wo[t][j] = w;
                 }
@@ -327,120 +380,174 @@ __global__ __launch_bounds__(kBlock) void k_lz_stencil(LzArgs a, int it) {
             }
         }
     }
-    if constexpr (MODE == LZ_STEP) {
-        sym_partials<K, R, false>(uo, wo, wt, 0.0, a.partial, a.nred, tile);
-    } else {
-        double v[2] = {d0, d1};
-        block_partials<2>(v, a.partial, a.nred, 0, tile);
-    }
-}
-
-// H_i from the stencil kernel's partials (its symmetric part, stored as a full block).
-template <int K>
-__global__ __launch_bounds__(kBlock) void k_lz_hfin(LzArgs a, int it) {
-    LzState *st = a.st;
-    if (st->done) return;
-    constexpr int PK = K * (K + 1) / 2;
-    double h[PK];
-    consume<PK>(a.partial, a.nred, 0, a.ntiles, h);
-    if (threadIdx.x == 0) {
-        double *H = wblk(a.H, it - 1);
-        bool fin = true;
+    if constexpr (STEP) {
+        constexpr int NV = lz_nv_step<K>();
+        double vals[NV];
         int e = 0;
-        for (int r = 0; r < K; ++r)
-            for (int q = r; q < K; ++q, ++e) {
-                H[r * kMaxK + q] = h[e];
-                H[q * kMaxK + r] = h[e];
-                fin = fin && isfinite(h[e]);
+#pragma unroll
+        for (int r = 0; r < K; ++r)          // P = V^T N Wa (full)
+#pragma unroll
+            for (int q = 0; q < K; ++q, ++e) {
+                double v = 0.0;
+#pragma unroll
+                for (int t = 0; t < R; ++t) v += wt[t] * (uo[t][r] * wo[t][q]);
+                vals[e] = v;
             }
-        if (!fin) {
-            st->status = SYLV_NONFINITE;
-            st->iter = it - 1;
-            st->done = 1;
-        }
+#pragma unroll
+        for (int r = 0; r < K; ++r)          // C = V^T N V (packed)
+#pragma unroll
+            for (int q = r; q < K; ++q, ++e) {
+                double v = 0.0;
+#pragma unroll
+                for (int t = 0; t < R; ++t) v += wt[t] * (uo[t][r] * uo[t][q]);
+                vals[e] = v;
+            }
+#pragma unroll
+        for (int r = 0; r < K; ++r)          // E = Wa^T N Wa (packed)
+#pragma unroll
+            for (int q = r; q < K; ++q, ++e) {
+                double v = 0.0;
+#pragma unroll
+                for (int t = 0; t < R; ++t) v += wt[t] * (wo[t][r] * wo[t][q]);
+                vals[e] = v;
+            }
+        // the staging buffer is free once every wavefront has finished its stencil reads
+        // (lds_partials starts with a barrier); a chunk of CH values needs CH * (kBlock + 16)
+        // doubles of it and 16 threads per value
+        constexpr int CH0 = (3 * K < 16) ? 3 * K : 16;
+        constexpr int CH = (CH0 < NV) ? CH0 : NV;
+        static_assert(CH * (kBlock + 16) <= K * LH * LW, "reduction scratch exceeds LDS");
+        static_assert(CH * 16 <= kBlock, "one workgroup sums at most kBlock / 16 values at once");
+        lds_partials<NV, CH>(vals, &lds[0][0][0], a.partial, a.nred, tile);
+    } else {
+        __shared__ double sm[2][kBlock / 64];
+        put_wave(d0, sm, 0);
+        put_wave(d1, sm, 1);
+        store_partials<2>(sm, a.partial, a.nred, tile);
     }
 }
 
-// W <- W - V_i H_i and the partials of W^T N W.
-template <int K>
-__global__ __launch_bounds__(kBlock) void k_lz_orth(LzArgs a, int it) {
-    if (a.st->done) return;
-    const int chunk = xcd_remap(blockIdx.x, a.nchunks);
-    const int n_pix = a.n_pix;
-    const double *H = cblk(a.H, it - 1);
-    const GAS double *V = gp(a.basis) + (size_t)(it - 1) * K * n_pix;
-    const GAS double *Wa = gp(a.Wa);
-    double w[4][K], v[4][K], wt[4];
+// Reduction of a pass's workgroup partials: workgroup i sums slot i over all blocks in a fixed
+// order (every thread's loads issued before any is summed) into partial2[i].
+__global__ __launch_bounds__(kBlock) void k_lz_reduce(LzArgs a, int nblocks) {
+    const int i = blockIdx.x;
+    const GAS double *pp = gp(a.partial) + (size_t)i * a.nred;
+    double s = 0.0;
+    int b = threadIdx.x;
+    for (; b + 7 * kBlock < nblocks; b += 8 * kBlock) {
+        double v[8];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int p = chunk * kChunk + e * kBlock + threadIdx.x;
-        const bool in = p < n_pix;
-        wt[e] = in ? gp(a.n)[p] : 0.0;
+        for (int u = 0; u < 8; ++u) v[u] = pp[b + u * kBlock];
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            w[e][j] = in ? Wa[(size_t)j * n_pix + p] : 0.0;
-            v[e][j] = in ? V[(size_t)j * n_pix + p] : 0.0;
-        }
+        for (int u = 0; u < 8; ++u) s += v[u];
     }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int p = chunk * kChunk + e * kBlock + threadIdx.x;
-        double o[K];
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-            double s = w[e][j];
-#pragma unroll
-            for (int q = 0; q < K; ++q) s -= v[e][q] * H[q * kMaxK + j];
-            o[j] = s;
-        }
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-            w[e][j] = o[j];
-            if (p < n_pix) gp(a.Wn)[(size_t)j * n_pix + p] = o[j];
-        }
-    }
-    sym_partials<K, 4, false>(w, w, wt, 0.0, a.partial, a.nred, chunk);
+    for (; b < nblocks; b += kBlock) s += pp[b];
+    __shared__ double sm[1][kBlock / 64];
+    put_wave(s, sm, 0);
+    __syncthreads();
+    if (threadIdx.x == 0) gp(a.partial2)[i] = (sm[0][0] + sm[0][1]) + (sm[0][2] + sm[0][3]);
 }
 
-// Cholesky-QR of the running block in the N inner product: W^T N W = B^T B, B upper.
-//   it == 0: the start block, B_0; ||B_0||_F sets the stopping threshold, and column l of
+// Cholesky-QR of the running block in the N inner product, W^T N W = B^T B with B upper.
+//   it == 0: the start block Yhat: B_0; ||B_0||_F sets the stopping threshold, and column l of
 //            B_0 U starts the forward elimination of column l.
-//   it >= 1: B_(i+1) after step i, then Alg. 5's residual estimate and the stopping test.
+//   it >= 1: H_i and the Gram matrix of W_i from P, C, E (see the file comment), B_(i+1), then
+//            Alg. 5's residual estimate and the stopping test.
 // The estimate: Q F e_l = (T_i + rho_l I)^-1 E_1 B_0 U e_l (eq. (soln-constr)), and gamma is
 // sum_l ||B_(i+1) x_l||^2 with x_l the last block of that vector.  With the Schur complements
 // S_1 = H_1 + rho_l I, S_j = H_j + rho_l I - B_j S_(j-1)^-1 B_j^T and y_1 = B_0 U e_l,
 // y_j = -B_j S_(j-1)^-1 y_(j-1) (block elimination of the block tridiagonal T_i + rho_l I), that
 // last block is x_l = S_i^-1 y_i; each step extends the elimination by one block.
+// Packed upper-triangle index e -> (r, q), r <= q.
 template <int K>
-__global__ __launch_bounds__(kBlock) void k_lz_qr(LzArgs a, int it, int nblocks) {
+__device__ __forceinline__ void unpack(int e, int &r, int &q) {
+    r = 0;
+    while (e >= K - r) { e -= K - r; ++r; }
+    q = r + e;
+}
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_lz_fin(LzArgs a, int it) {
     LzState *st = a.st;
     if (st->done) return;
     constexpr int PK = K * (K + 1) / 2;
-    double g[PK + 1];
-    if (it == 0) {   // start block: one more slot, the count of invalid n_p
-        consume<PK + 1>(a.partial, a.nred, 0, nblocks, g);
-    } else {
-        double gg[PK];
-        consume<PK>(a.partial, a.nred, 0, nblocks, gg);
-#pragma unroll
-        for (int e = 0; e < PK; ++e) g[e] = gg[e];
-        g[PK] = 0.0;
-    }
+    const int tid = threadIdx.x;
+    __shared__ double sP[K][K], sH[K][K], sC[K][K], sE[K][K], sCH[K][K], sG[K][K], sBn[K][K];
+    __shared__ double s_bad, s_gam[K];
     __shared__ int s_ok;         // 0: B valid; 1: zero block; 2: not positive definite; 3: bad
-    __shared__ double s_gam[K];
-    if (threadIdx.x == 0) {
+    // column threads of the residual estimate: prefetch their elimination state and B_i
+    const bool col = it >= 1 && tid < K;
+    double Sprev[K][K], yv[K], Bj[K][K];
+    if (col) {
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            yv[r] = st->y[tid][r];
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+                Sprev[r][q] = (it > 1) ? st->S[tid][r][q] : 0.0;
+                Bj[r][q] = (it > 1) ? cblk(a.B, it - 1)[r * kMaxK + q] : 0.0;
+            }
+        }
+    }
+    const double *p2 = a.partial2;
+    if (it == 0) {
+        if (tid < PK) {
+            int r, q;
+            unpack<K>(tid, r, q);
+            sG[r][q] = p2[tid];
+            sG[q][r] = p2[tid];
+        } else if (tid == PK) {
+            s_bad = p2[PK];
+        }
+        __syncthreads();
+    } else {
+        // P (full), C and E (packed): H = sym(P); W^T N W = E - P^T H - H P + H C H
+        if (tid < K * K) {
+            sP[tid / K][tid % K] = p2[tid];
+        } else if (tid < K * K + PK) {
+            int r, q;
+            unpack<K>(tid - K * K, r, q);
+            sC[r][q] = p2[tid];
+            sC[q][r] = p2[tid];
+        } else if (tid < K * K + 2 * PK) {
+            int r, q;
+            unpack<K>(tid - K * K - PK, r, q);
+            sE[r][q] = p2[tid];
+            sE[q][r] = p2[tid];
+        }
+        __syncthreads();
+        const int r = tid / K, q = tid % K;
+        if (tid < K * K) sH[r][q] = 0.5 * (sP[r][q] + sP[q][r]);
+        __syncthreads();
+        if (tid < K * K) {
+            double v = 0.0;
+#pragma unroll
+            for (int s2 = 0; s2 < K; ++s2) v += sC[r][s2] * sH[s2][q];
+            sCH[r][q] = v;
+        }
+        __syncthreads();
+        if (tid < K * K) {
+            double v = sE[r][q];
+#pragma unroll
+            for (int s2 = 0; s2 < K; ++s2)
+                v += -sP[s2][r] * sH[s2][q] - sH[r][s2] * sP[s2][q] + sH[r][s2] * sCH[s2][q];
+            sG[r][q] = v;
+            wblk(a.H, it - 1)[r * kMaxK + q] = sH[r][q];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
         double G[K][K], Bm[K][K], Bi[K][K];
-        int e = 0;
         bool zero = true, fin = true;
         for (int r = 0; r < K; ++r)
-            for (int q = r; q < K; ++q, ++e) {
-                G[r][q] = g[e];
-                G[q][r] = g[e];
-                zero = zero && g[e] == 0.0;
-                fin = fin && isfinite(g[e]);
+            for (int q = 0; q < K; ++q) {
+                G[r][q] = 0.5 * (sG[r][q] + sG[q][r]);
+                zero = zero && G[r][q] == 0.0;
+                fin = fin && isfinite(G[r][q]) && (it == 0 || isfinite(sH[r][q]));
             }
+        const double bad = (it == 0) ? s_bad : 0.0;
         int ok = 0;
-        if (it == 0 && g[PK] > 0.0) ok = 3;
+        if (it == 0 && bad > 0.0) ok = 3;
         else if (!fin) ok = 3;
         else if (zero) ok = 1;
         else if (!chol_upper<K>(G, Bm)) ok = 2;
@@ -455,6 +562,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_qr(LzArgs a, int it, int nblocks)
             for (int q = 0; q < K; ++q) {
                 Bo[r * kMaxK + q] = Bm[r][q];
                 Bio[r * kMaxK + q] = Bi[r][q];
+                sBn[r][q] = Bm[r][q];
             }
         if (it == 0) {
             double nb = 0.0;
@@ -469,7 +577,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_qr(LzArgs a, int it, int nblocks)
                     st->y[l][r] = v;
                 }
             if (ok != 0) {                        // zero start block: X = 0; invalid n_p / values
-                st->status = (ok == 1) ? SYLV_OK : (g[PK] > 0.0 ? SYLV_BAD_INPUT : SYLV_NONFINITE);
+                st->status = (ok == 1) ? SYLV_OK : (bad > 0.0 ? SYLV_BAD_INPUT : SYLV_NONFINITE);
                 st->iter = 0;
                 st->gamma = 0.0;
                 st->done = 1;
@@ -481,7 +589,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_qr(LzArgs a, int it, int nblocks)
     if (it == 0) return;
     const int ok = s_ok;
     if (ok == 2 || ok == 3) {
-        if (threadIdx.x == 0) {
+        if (tid == 0) {
             st->status = (ok == 2) ? SYLV_BREAKDOWN : SYLV_NONFINITE;
             st->iter = (ok == 2) ? it : it - 1;
             st->gamma = -1.0;
@@ -491,34 +599,30 @@ __global__ __launch_bounds__(kBlock) void k_lz_qr(LzArgs a, int it, int nblocks)
         return;
     }
     // residual estimate: thread l carries column l
-    if (threadIdx.x < K) {
-        const int l = threadIdx.x;
+    if (col) {
+        const int l = tid;
         const double rho = a.c->rho[l];
-        const double *H = cblk(a.H, it - 1);
-        const double *Bn = cblk(a.B, it);          // B_(i+1)
         double S[K][K], y[K];
-        for (int r = 0; r < K; ++r) y[r] = st->y[l][r];
+#pragma unroll
+        for (int r = 0; r < K; ++r) y[r] = yv[r];
         if (it == 1) {
             for (int r = 0; r < K; ++r)
-                for (int q = 0; q < K; ++q) S[r][q] = H[r * kMaxK + q] + (r == q ? rho : 0.0);
+                for (int q = 0; q < K; ++q) S[r][q] = sH[r][q] + (r == q ? rho : 0.0);
         } else {
-            const double *Bj = cblk(a.B, it - 1);  // B_i
-            double So[K][K], Ro[K][K];
-            for (int r = 0; r < K; ++r)
-                for (int q = 0; q < K; ++q) So[r][q] = st->S[l][r][q];
-            chol_upper<K>(So, Ro);                 // S_(i-1) is positive definite
+            double Ro[K][K];
+            chol_upper<K>(Sprev, Ro);              // S_(i-1) is positive definite
             // X = S_(i-1)^-1 B_i^T column by column; S_i = H_i + rho I - B_i X
             double X[K][K];
             for (int q = 0; q < K; ++q) {
                 double bcol[K], xcol[K];
-                for (int r = 0; r < K; ++r) bcol[r] = Bj[q * kMaxK + r];   // column q of B_i^T
+                for (int r = 0; r < K; ++r) bcol[r] = Bj[q][r];   // column q of B_i^T
                 chol_solve<K>(Ro, bcol, xcol);
                 for (int r = 0; r < K; ++r) X[r][q] = xcol[r];
             }
             for (int r = 0; r < K; ++r)
                 for (int q = 0; q < K; ++q) {
-                    double v = H[r * kMaxK + q] + (r == q ? rho : 0.0);
-                    for (int s2 = 0; s2 < K; ++s2) v -= Bj[r * kMaxK + s2] * X[s2][q];
+                    double v = sH[r][q] + (r == q ? rho : 0.0);
+                    for (int s2 = 0; s2 < K; ++s2) v -= Bj[r][s2] * X[s2][q];
                     S[r][q] = v;
                 }
             for (int r = 0; r < K; ++r)           // symmetrise against rounding
@@ -528,10 +632,10 @@ __global__ __launch_bounds__(kBlock) void k_lz_qr(LzArgs a, int it, int nblocks)
                     S[q][r] = m;
                 }
             double z[K];
-            chol_solve<K>(Ro, y, z);
+            chol_solve<K>(Ro, yv, z);
             for (int r = 0; r < K; ++r) {
                 double v = 0.0;
-                for (int q = 0; q < K; ++q) v -= Bj[r * kMaxK + q] * z[q];
+                for (int q = 0; q < K; ++q) v -= Bj[r][q] * z[q];
                 y[r] = v;
             }
         }
@@ -542,7 +646,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_qr(LzArgs a, int it, int nblocks)
             gl = 0.0;
             for (int r = 0; r < K; ++r) {
                 double v = 0.0;
-                for (int q = r; q < K; ++q) v += Bn[r * kMaxK + q] * x[q];
+                for (int q = r; q < K; ++q) v += sBn[r][q] * x[q];
                 gl += v * v;
             }
         } else {
@@ -555,13 +659,12 @@ __global__ __launch_bounds__(kBlock) void k_lz_qr(LzArgs a, int it, int nblocks)
         s_gam[l] = gl;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         double gam = 0.0;
         for (int l = 0; l < K; ++l) gam += s_gam[l];
         st->gamma = gam;
         st->iter = it;
-        const double nb0 = st->nb0;
-        a.hist[it - 1] = sqrt(gam) / nb0;
+        a.hist[it - 1] = sqrt(gam) / st->nb0;
         if (!isfinite(gam)) {
             st->status = SYLV_NONFINITE;
             st->done = 1;
@@ -620,14 +723,18 @@ __global__ __launch_bounds__(kBlock) void k_lz_assemble(LzArgs a, int iters) {
     }
 }
 
-// ||b - G x||^2 and ||b||^2 from the residual pass.
-__global__ __launch_bounds__(kBlock) void k_lz_rfin(LzArgs a) {
-    double s[2];
-    consume<2>(a.partial, a.nred, 0, a.ntiles, s);
+// ||b - G x||^2 and ||b||^2 from the residual pass (after the first reduction stage).
+__global__ void k_lz_rfin(LzArgs a) {
     if (threadIdx.x == 0) {
-        a.st->rr = s[0];
-        a.st->bb = s[1];
+        a.st->rr = a.partial2[0];
+        a.st->bb = a.partial2[1];
     }
+}
+
+// Final sums of the NV slots of a pass with `nblocks` workgroup partials, into partial2[0, NV).
+hipError_t launch_reduce(const LzArgs &a, int nv, int nblocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_lz_reduce, dim3(nv), dim3(kBlock), 0, s, a, nblocks);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -638,20 +745,21 @@ int lz_tiles(int ny, int nx) {
     return tx * ty;
 }
 
+hipError_t lz_launch_init(const LzArgs &a, int max_iter, hipStream_t s) {
+    hipLaunchKernelGGL(k_lz_init, dim3(1), dim3(64), 0, s, a, max_iter);
+    return hipGetLastError();
+}
+
 hipError_t lz_launch_start(const LzArgs &a, hipStream_t s) {
     return dispatch_k(a.k, [&](auto kt) -> hipError_t {
         constexpr int K = decltype(kt)::value;
         hipLaunchKernelGGL((k_lz_start<K>), dim3(a.nchunks), dim3(kBlock), 0, s, a);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_lz_qr<K>), dim3(1), dim3(kBlock), 0, s, a, 0, a.nchunks);
+        if ((e = launch_reduce(a, lz_nv_start<K>(), a.nchunks, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_lz_fin<K>), dim3(1), dim3(kBlock), 0, s, a, 0);
         return hipGetLastError();
     });
-}
-
-hipError_t lz_launch_init(const LzArgs &a, int max_iter, hipStream_t s) {
-    hipLaunchKernelGGL(k_lz_init, dim3(1), dim3(64), 0, s, a, max_iter);
-    return hipGetLastError();
 }
 
 hipError_t lz_launch_step(const LzArgs &a, int it, hipStream_t s) {
@@ -660,11 +768,8 @@ hipError_t lz_launch_step(const LzArgs &a, int it, hipStream_t s) {
         hipLaunchKernelGGL((k_lz_stencil<K, LZ_STEP>), dim3(a.ntiles), dim3(kBlock), 0, s, a, it);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_lz_hfin<K>), dim3(1), dim3(kBlock), 0, s, a, it);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL((k_lz_orth<K>), dim3(a.nchunks), dim3(kBlock), 0, s, a, it);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL((k_lz_qr<K>), dim3(1), dim3(kBlock), 0, s, a, it, a.nchunks);
+        if ((e = launch_reduce(a, lz_nv_step<K>(), a.ntiles, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_lz_fin<K>), dim3(1), dim3(kBlock), 0, s, a, it);
         return hipGetLastError();
     });
 }
@@ -682,7 +787,8 @@ hipError_t lz_launch_finish(const LzArgs &a, int iters, hipStream_t s) {
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_lz_stencil<K, LZ_RESID>), dim3(a.ntiles), dim3(kBlock), 0, s, a, 0);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_lz_rfin, dim3(1), dim3(kBlock), 0, s, a);
+        if ((e = launch_reduce(a, 2, a.ntiles, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_lz_rfin, dim3(1), dim3(64), 0, s, a);
         return hipGetLastError();
     });
 }

@@ -171,6 +171,10 @@ WORKLOADS = {
                            k=3, f=6, noise="hetero", tol=1e-8, precision="mixed"),
     "grad_512": dict(index=4, ny=512, nx=512, k=4, f=9, noise="hetero", tol=1e-10,
                      precision="f64"),
+    # the case the paper solves in Sylvester form (Section 3.3): separable noise t_f n_p and one
+    # kappa shared by the components (the first kappa draw of the seed)
+    "sylv_1024": dict(index=5, ny=1024, nx=1024, k=4, f=9, noise="separable",
+                      common_kappa=True, tol=1e-8, precision="f64"),
 }
 
 
@@ -191,8 +195,12 @@ def workload(name: str, scale: Optional[int] = None) -> List[Problem]:
         return out
     ny = cfg["ny"] if scale is None else scale
     nx = cfg["nx"] if scale is None else scale
+    kappa = None
+    if cfg.get("common_kappa"):
+        # make_problem's first draw, repeated for every component
+        kappa = np.full(cfg["k"], np.random.default_rng(seed).uniform(0.1, 1.0, size=cfg["k"])[0])
     return [make_problem(ny, nx, cfg["k"], cfg["f"], seed, noise=cfg["noise"],
-                         mask_frac=cfg.get("mask_frac", 0.0), name=name)]
+                         mask_frac=cfg.get("mask_frac", 0.0), kappa=kappa, name=name)]
 
 
 def po_draws(prob: Problem, nrhs: int, seed: int):
