@@ -43,6 +43,18 @@ int apply_rows_request() {
     return rows;
 }
 
+// Rows per lane of the Lanczos-Sylvester stencil kernels (2, or 4 for k <= 4); SYLV_LZ_ROWS
+// overrides the default for tuning experiments.
+int lz_rows_for(int k) {
+    static int req = -1;
+    if (req < 0) {
+        const char *e = getenv("SYLV_LZ_ROWS");
+        req = e ? atoi(e) : 0;
+    }
+    if (req > 0 && lz_rows_valid(k, req)) return req;
+    return 2;
+}
+
 int tiles_for(int ny, int nx, int rows) {
     const int tx = (nx + kTileX - 1) / kTileX;
     const int ty = (ny + kWavesY * rows - 1) / (kWavesY * rows);
@@ -538,7 +550,7 @@ bool check_lz_opts(const sylv_lanczos_opts *o) {
 
 bool make_lz_layout(const sylv_sep_problem *p, const sylv_lanczos_opts *o, LzLayout &L) {
     const size_t n = (size_t)p->ny * p->nx, k = (size_t)p->k, mi = (size_t)o->max_iter;
-    const int nt = lz_tiles((int)p->ny, (int)p->nx), nc = chunks_for((int)n);
+    const int nt = lz_tiles((int)p->ny, (int)p->nx, 2), nc = chunks_for((int)n);   // 2 rows: most tiles
     L.nred = std::max(nt, nc);
     const size_t vb = sizeof(double) * k * n;
     if (vb && mi > ((size_t)1 << 62) / vb) { set_err("basis size overflows"); return false; }
@@ -773,7 +785,8 @@ int lanczos_impl(const sylv_sep_problem *p, const double *Y, double *X,
     memset(&a, 0, sizeof(a));
     a.ny = (int)p->ny; a.nx = (int)p->nx; a.n_pix = (int)(p->ny * p->nx); a.k = k; a.f = f;
     a.tiles_x = (a.nx + kTileX - 1) / kTileX;
-    a.ntiles = lz_tiles(a.ny, a.nx);
+    a.rows = lz_rows_for(k);
+    a.ntiles = lz_tiles(a.ny, a.nx, a.rows);
     a.nchunks = chunks_for(a.n_pix);
     a.nred = L.nred;
     a.c = reinterpret_cast<const LzConst *>(base + L.cst);

@@ -212,7 +212,7 @@ struct LzState {
 constexpr int kLzStride = kMaxK * kMaxK;   // one k x k coefficient block (row-major, ld kMaxK)
 // Kernel argument block of every Lanczos-Sylvester kernel.
 struct LzArgs {
-    int ny, nx, n_pix, k, f, tiles_x, ntiles, nchunks, nred;
+    int ny, nx, n_pix, k, f, tiles_x, ntiles, nchunks, nred, rows;
     const LzConst *c;
     LzState *st;
     double *H;                    // [max_iter] blocks: H_1 .. (symmetric part)
@@ -232,6 +232,7 @@ hipError_t lz_launch_start(const LzArgs &a, hipStream_t s);
 hipError_t lz_launch_step(const LzArgs &a, int it, hipStream_t s);
 hipError_t lz_launch_flag(const LzArgs &a, int *host_running, hipStream_t s);
 hipError_t lz_launch_finish(const LzArgs &a, int iters, hipStream_t s);
-int lz_tiles(int ny, int nx);
+int lz_tiles(int ny, int nx, int rows);
+int lz_rows_valid(int k, int rows);
 
 }  // namespace sylv

@@ -31,7 +31,6 @@ namespace {
 
 using namespace dev;
 
-constexpr int kLzRows = 2;           // output rows per lane in the stencil kernels
 enum { LZ_STEP = 0, LZ_RESID = 1 };
 
 __device__ __forceinline__ const double *cblk(const double *base, int i) {
@@ -89,6 +88,14 @@ __device__ __forceinline__ void lds_partials(const double (&vals)[NV], double *r
             gp(partial)[(size_t)(c0 + tid) * nred + blkid] = s;
         }
     }
+}
+
+// Packed upper-triangle index e -> (r, q), r <= q.
+template <int K>
+__device__ __forceinline__ void unpack(int e, int &r, int &q) {
+    r = 0;
+    while (e >= K - r) { e -= K - r; ++r; }
+    q = r + e;
 }
 
 // ---- small dense helpers (one thread) -------------------------------------------------------
@@ -204,9 +211,8 @@ __global__ __launch_bounds__(kBlock) void k_lz_start(LzArgs a) {
 // Stencil kernels.  STEP: one Lanczos step (see the file comment).  RESID: residual of eq. (Axb)
 // for X: r_j = n_p tau_j Yhat_j - (tau_j D2 X_j + n_p (A^T T A X_p)_j), with the partials of
 // ||r||^2 and ||b||^2.
-template <int K, int MODE>
+template <int K, int MODE, int R>
 __global__ __launch_bounds__(kBlock) void k_lz_stencil(LzArgs a, int it) {
-    constexpr int R = kLzRows;
     constexpr int LH = kWavesY * R + 4;   // staged rows: tile + 2-row halo above and below
     constexpr int LW = kTileX + 4;        // staged columns
     constexpr int RPW = LH / kWavesY;     // staged rows per wavefront
@@ -352,9 +358,10 @@ __global__ __launch_bounds__(kBlock) void k_lz_stencil(LzArgs a, int it) {
             if constexpr (STEP) {
                 GAS double *vb = gp(a.basis) + (size_t)(it - 1) * K * n_pix;
                 GAS double *wa = gp((it & 1) ? a.Wa0 : a.Wa1);
+                const double ninv = 1.0 / nv[t];
 #pragma unroll
                 for (int j = 0; j < K; ++j) {
-                    double w = acc[j][t] / nv[t];
+                    double w = acc[j][t] * ninv;
                     if (prev) {
 #pragma unroll
                         for (int q = 0; q < K; ++q) w -= aux[t][q] * Bi[j * kMaxK + q];
@@ -458,33 +465,28 @@ __global__ __launch_bounds__(kBlock) void k_lz_reduce(LzArgs a, int nblocks) {
 // S_1 = H_1 + rho_l I, S_j = H_j + rho_l I - B_j S_(j-1)^-1 B_j^T and y_1 = B_0 U e_l,
 // y_j = -B_j S_(j-1)^-1 y_(j-1) (block elimination of the block tridiagonal T_i + rho_l I), that
 // last block is x_l = S_i^-1 y_i; each step extends the elimination by one block.
-// Packed upper-triangle index e -> (r, q), r <= q.
-template <int K>
-__device__ __forceinline__ void unpack(int e, int &r, int &q) {
-    r = 0;
-    while (e >= K - r) { e -= K - r; ++r; }
-    q = r + e;
-}
-
 template <int K>
 __global__ __launch_bounds__(kBlock) void k_lz_fin(LzArgs a, int it) {
     LzState *st = a.st;
     if (st->done) return;
     constexpr int PK = K * (K + 1) / 2;
+    constexpr int kCol0 = 64;    // the column threads form the second wavefront, so that their
+                                 // elimination runs beside thread 0's Cholesky-QR
     const int tid = threadIdx.x;
     __shared__ double sP[K][K], sH[K][K], sC[K][K], sE[K][K], sCH[K][K], sG[K][K], sBn[K][K];
     __shared__ double s_bad, s_gam[K];
     __shared__ int s_ok;         // 0: B valid; 1: zero block; 2: not positive definite; 3: bad
     // column threads of the residual estimate: prefetch their elimination state and B_i
-    const bool col = it >= 1 && tid < K;
+    const int l = tid - kCol0;
+    const bool col = it >= 1 && l >= 0 && l < K;
     double Sprev[K][K], yv[K], Bj[K][K];
     if (col) {
 #pragma unroll
         for (int r = 0; r < K; ++r) {
-            yv[r] = st->y[tid][r];
+            yv[r] = st->y[l][r];
 #pragma unroll
             for (int q = 0; q < K; ++q) {
-                Sprev[r][q] = (it > 1) ? st->S[tid][r][q] : 0.0;
+                Sprev[r][q] = (it > 1) ? st->S[l][r][q] : 0.0;
                 Bj[r][q] = (it > 1) ? cblk(a.B, it - 1)[r * kMaxK + q] : 0.0;
             }
         }
@@ -536,6 +538,10 @@ __global__ __launch_bounds__(kBlock) void k_lz_fin(LzArgs a, int it) {
         }
         __syncthreads();
     }
+    // thread 0: Cholesky-QR of the block.  Column threads (meanwhile): extend the elimination
+    // of T_i + rho_l I by H_i and solve for its last block x_l.
+    double xl[K];
+    bool xok = true;
     if (tid == 0) {
         double G[K][K], Bm[K][K], Bi[K][K];
         bool zero = true, fin = true;
@@ -570,11 +576,11 @@ __global__ __launch_bounds__(kBlock) void k_lz_fin(LzArgs a, int it) {
                 for (int q = 0; q < K; ++q) nb += Bm[r][q] * Bm[r][q];
             st->nb0 = sqrt(nb);
             st->thresh = a.c->tol * sqrt(nb);
-            for (int l = 0; l < K; ++l)          // y_1 for column l: B_0 U e_l
+            for (int c = 0; c < K; ++c)          // y_1 for column c: B_0 U e_c
                 for (int r = 0; r < K; ++r) {
                     double v = 0.0;
-                    for (int q = 0; q < K; ++q) v += Bm[r][q] * a.c->U[q][l];
-                    st->y[l][r] = v;
+                    for (int q = 0; q < K; ++q) v += Bm[r][q] * a.c->U[q][c];
+                    st->y[c][r] = v;
                 }
             if (ok != 0) {                        // zero start block: X = 0; invalid n_p / values
                 st->status = (ok == 1) ? SYLV_OK : (bad > 0.0 ? SYLV_BAD_INPUT : SYLV_NONFINITE);
@@ -584,23 +590,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_fin(LzArgs a, int it) {
             }
         }
         s_ok = ok;
-    }
-    __syncthreads();
-    if (it == 0) return;
-    const int ok = s_ok;
-    if (ok == 2 || ok == 3) {
-        if (tid == 0) {
-            st->status = (ok == 2) ? SYLV_BREAKDOWN : SYLV_NONFINITE;
-            st->iter = (ok == 2) ? it : it - 1;
-            st->gamma = -1.0;
-            a.hist[it - 1] = -1.0;
-            st->done = 1;
-        }
-        return;
-    }
-    // residual estimate: thread l carries column l
-    if (col) {
-        const int l = tid;
+    } else if (col) {
         const double rho = a.c->rho[l];
         double S[K][K], y[K];
 #pragma unroll
@@ -639,29 +629,44 @@ __global__ __launch_bounds__(kBlock) void k_lz_fin(LzArgs a, int it) {
                 y[r] = v;
             }
         }
-        double Rs[K][K], x[K];
-        double gl;
-        if (chol_upper<K>(S, Rs)) {
-            chol_solve<K>(Rs, y, x);
-            gl = 0.0;
+        double Rs[K][K];
+        if (chol_upper<K>(S, Rs)) chol_solve<K>(Rs, y, xl);
+        else xok = false;
+        for (int r = 0; r < K; ++r) {
+            st->y[l][r] = y[r];
+            for (int q = 0; q < K; ++q) st->S[l][r][q] = S[r][q];
+        }
+    }
+    __syncthreads();
+    if (it == 0) return;
+    const int ok = s_ok;
+    if (ok == 2 || ok == 3) {
+        if (tid == 0) {
+            st->status = (ok == 2) ? SYLV_BREAKDOWN : SYLV_NONFINITE;
+            st->iter = (ok == 2) ? it : it - 1;
+            st->gamma = -1.0;
+            a.hist[it - 1] = -1.0;
+            st->done = 1;
+        }
+        return;
+    }
+    if (col) {                                    // gamma_l = ||B_(i+1) x_l||^2
+        double gl = 0.0;
+        if (xok) {
             for (int r = 0; r < K; ++r) {
                 double v = 0.0;
-                for (int q = r; q < K; ++q) v += sBn[r][q] * x[q];
+                for (int q = r; q < K; ++q) v += sBn[r][q] * xl[q];
                 gl += v * v;
             }
         } else {
             gl = __builtin_nan("");
-        }
-        for (int r = 0; r < K; ++r) {
-            st->y[l][r] = y[r];
-            for (int q = 0; q < K; ++q) st->S[l][r][q] = S[r][q];
         }
         s_gam[l] = gl;
     }
     __syncthreads();
     if (tid == 0) {
         double gam = 0.0;
-        for (int l = 0; l < K; ++l) gam += s_gam[l];
+        for (int c = 0; c < K; ++c) gam += s_gam[c];
         st->gamma = gam;
         st->iter = it;
         a.hist[it - 1] = sqrt(gam) / st->nb0;
@@ -739,11 +744,13 @@ hipError_t launch_reduce(const LzArgs &a, int nv, int nblocks, hipStream_t s) {
 
 }  // namespace
 
-int lz_tiles(int ny, int nx) {
+int lz_tiles(int ny, int nx, int rows) {
     const int tx = (nx + kTileX - 1) / kTileX;
-    const int ty = (ny + kWavesY * kLzRows - 1) / (kWavesY * kLzRows);
+    const int ty = (ny + kWavesY * rows - 1) / (kWavesY * rows);
     return tx * ty;
 }
+
+int lz_rows_valid(int k, int rows) { return rows == 2 || (rows == 4 && k <= 4); }
 
 hipError_t lz_launch_init(const LzArgs &a, int max_iter, hipStream_t s) {
     hipLaunchKernelGGL(k_lz_init, dim3(1), dim3(64), 0, s, a, max_iter);
@@ -765,7 +772,12 @@ hipError_t lz_launch_start(const LzArgs &a, hipStream_t s) {
 hipError_t lz_launch_step(const LzArgs &a, int it, hipStream_t s) {
     return dispatch_k(a.k, [&](auto kt) -> hipError_t {
         constexpr int K = decltype(kt)::value;
-        hipLaunchKernelGGL((k_lz_stencil<K, LZ_STEP>), dim3(a.ntiles), dim3(kBlock), 0, s, a, it);
+        if (K <= 4 && a.rows == 4)
+            hipLaunchKernelGGL((k_lz_stencil<K, LZ_STEP, (K <= 4 ? 4 : 2)>), dim3(a.ntiles),
+                               dim3(kBlock), 0, s, a, it);
+        else
+            hipLaunchKernelGGL((k_lz_stencil<K, LZ_STEP, 2>), dim3(a.ntiles), dim3(kBlock), 0, s,
+                               a, it);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         if ((e = launch_reduce(a, lz_nv_step<K>(), a.ntiles, s)) != hipSuccess) return e;
@@ -785,7 +797,12 @@ hipError_t lz_launch_finish(const LzArgs &a, int iters, hipStream_t s) {
         hipLaunchKernelGGL((k_lz_assemble<K>), dim3(a.nchunks), dim3(kBlock), 0, s, a, iters);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_lz_stencil<K, LZ_RESID>), dim3(a.ntiles), dim3(kBlock), 0, s, a, 0);
+        if (K <= 4 && a.rows == 4)
+            hipLaunchKernelGGL((k_lz_stencil<K, LZ_RESID, (K <= 4 ? 4 : 2)>), dim3(a.ntiles),
+                               dim3(kBlock), 0, s, a, 0);
+        else
+            hipLaunchKernelGGL((k_lz_stencil<K, LZ_RESID, 2>), dim3(a.ntiles), dim3(kBlock), 0,
+                               s, a, 0);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = launch_reduce(a, 2, a.ntiles, s)) != hipSuccess) return e;
         hipLaunchKernelGGL(k_lz_rfin, dim3(1), dim3(64), 0, s, a);
