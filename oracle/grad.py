@@ -41,7 +41,7 @@ def implicit_grads(prob, x, lam):
         E = np.zeros((k, k))
         E[j, j] = 1.0
         E = sp.csr_matrix(E)
-        L = op.prior_factor(prob.ny, prob.nx, prob.kappa[j])
+        L = op.prior_factor(prob.ny, prob.nx, prob.kappa[j], op.boundary_of(prob))
         dG_tau = sp.kron(E, (L.T @ L))
         dL = 2.0 * prob.kappa[j] * I
         dG_kap = sp.kron(E, prob.tau[j] * (dL.T @ L + L.T @ dL))

@@ -51,7 +51,8 @@ def sylvester_data(prob, t: np.ndarray, nvec: np.ndarray):
         raise ValueError("the Sylvester form needs n_p > 0 at every pixel (N invertible)")
     if not np.array_equal(prob.W, np.outer(t, nvec)):
         raise ValueError("the Sylvester form needs W = t (x) n")
-    D2 = op.prior_block(prob.ny, prob.nx, kap[0], 1.0)      # (kappa^2 I - Lap)^T (kappa^2 I - Lap)
+    D2 = op.prior_block(prob.ny, prob.nx, kap[0], 1.0,      # (kappa^2 I - Lap)^T (kappa^2 I - Lap)
+                        op.boundary_of(prob))
     tau = np.asarray(prob.tau, dtype=np.float64)
     P = np.diag(tau)
     Pinv = np.diag(1.0 / tau)

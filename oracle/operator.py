@@ -27,30 +27,48 @@ def _shift(ny: int, nx: int, dy: int, dx: int) -> sp.csr_matrix:
     return sp.csr_matrix((np.ones(n), (p, cols)), shape=(n, n))
 
 
-def laplacian(ny: int, nx: int) -> sp.csr_matrix:
-    """Graph Laplacian of the periodic 4-neighbour grid: Lap = Sx + Sx^T + Sy + Sy^T - 4 I.
+def laplacian(ny: int, nx: int, boundary: str = "periodic") -> sp.csr_matrix:
+    """Graph Laplacian of the 4-neighbour pixel grid (Section 3, definition of D): off-diagonal
+    entries count neighbour links, the diagonal is minus the row sum of the off-diagonal part.
 
-    Off-diagonal entries count neighbour links, the diagonal is minus the row sum of the
-    off-diagonal part (Section 3, definition of D).  On grids with a side below 3 two
-    neighbour links land on the same pixel; the sparse sum adds them, which keeps
-    Lap = (polynomial in the shift operators) for every grid size.
+    periodic: Lap = Sx + Sx^T + Sy + Sy^T - 4 I.  On grids with a side below 3 two neighbour
+              links land on the same pixel; the sparse sum adds them, which keeps
+              Lap = (polynomial in the shift operators) for every grid size.
+    face:     links only between pixels inside the grid (one HEALPix base face, whose
+              neighbours are confined to the face, App. A); border pixels have fewer links and
+              a correspondingly smaller diagonal.  Lap 1 = 0 and rank N - 1 (App. C).
     """
-    sx = _shift(ny, nx, 0, 1)
-    sy = _shift(ny, nx, 1, 0)
     n = ny * nx
-    return (sx + sx.T + sy + sy.T - 4.0 * sp.identity(n, format="csr")).tocsr()
+    if boundary == "periodic":
+        sx = _shift(ny, nx, 0, 1)
+        sy = _shift(ny, nx, 1, 0)
+        return (sx + sx.T + sy + sy.T - 4.0 * sp.identity(n, format="csr")).tocsr()
+    if boundary != "face":
+        raise ValueError(f"unknown boundary {boundary!r}")
+    p = np.arange(n).reshape(ny, nx)
+    rows = np.concatenate([p[:, :-1].ravel(), p[:-1, :].ravel()])     # right and down links
+    cols = np.concatenate([p[:, 1:].ravel(), p[1:, :].ravel()])
+    adj = sp.csr_matrix((np.ones(rows.size), (rows, cols)), shape=(n, n))
+    adj = (adj + adj.T).tocsr()
+    deg = np.asarray(adj.sum(axis=1)).ravel()
+    return (adj - sp.diags(deg)).tocsr()
 
 
-def prior_factor(ny: int, nx: int, kappa: float) -> sp.csr_matrix:
+def prior_factor(ny: int, nx: int, kappa: float, boundary: str = "periodic") -> sp.csr_matrix:
     """L = kappa^2 I - Lap."""
     n = ny * nx
-    return (kappa * kappa * sp.identity(n, format="csr") - laplacian(ny, nx)).tocsr()
+    return (kappa * kappa * sp.identity(n, format="csr") - laplacian(ny, nx, boundary)).tocsr()
 
 
-def prior_block(ny: int, nx: int, kappa: float, tau: float) -> sp.csr_matrix:
+def prior_block(ny: int, nx: int, kappa: float, tau: float,
+                boundary: str = "periodic") -> sp.csr_matrix:
     """Q_j = tau L^T L, formed by an explicit sparse product (no stencil coefficients)."""
-    L = prior_factor(ny, nx, kappa)
+    L = prior_factor(ny, nx, kappa, boundary)
     return (tau * (L.T @ L)).tocsr()
+
+
+def boundary_of(prob) -> str:
+    return getattr(prob, "boundary", "periodic")
 
 
 def posterior_precision(prob, dense: bool = False):
@@ -65,7 +83,7 @@ def posterior_precision(prob, dense: bool = False):
         E = np.zeros((k, k))
         E[j, j] = 1.0
         G = G + sp.kron(sp.csr_matrix(E), prior_block(prob.ny, prob.nx, prob.kappa[j],
-                                                        prob.tau[j]))
+                                                        prob.tau[j], boundary_of(prob)))
     for fi in range(f):
         a = prob.A[fi]
         G = G + sp.kron(sp.csr_matrix(np.outer(a, a)), sp.diags(prob.W[fi]))
@@ -109,16 +127,26 @@ def apply(prob, X: np.ndarray, G=None) -> np.ndarray:
 def apply_terms(prob, X: np.ndarray) -> np.ndarray:
     """Independent evaluation of G(X) = sum_j Q_j X E_jj + sum_f D_f X a_f a_f^T.
 
-    Uses np.roll for the Laplacian (applied twice) and an explicit per-frequency mixing sum, so a
-    mistake in the Kronecker assembly does not cancel against it.
+    Uses np.roll (periodic) or a zero-padded neighbour sum with counted links (face) for the
+    Laplacian, applied twice, and an explicit per-frequency mixing sum, so a mistake in the
+    Kronecker assembly does not cancel against it.
     """
     ny, nx, k = prob.ny, prob.nx, prob.k
     Xg = np.asarray(X, dtype=np.float64).reshape(k, ny, nx)
     out = np.zeros_like(Xg)
+    face = boundary_of(prob) == "face"
+    # face: neighbours outside the grid are absent; pad with zeros and count present links
+    deg = None
+    if face:
+        one = np.pad(np.ones((ny, nx)), 1)
+        deg = one[:-2, 1:-1] + one[2:, 1:-1] + one[1:-1, :-2] + one[1:-1, 2:]
     for j in range(k):
         u = Xg[j]
 
         def lap(v):
+            if face:
+                vp = np.pad(v, 1)
+                return vp[:-2, 1:-1] + vp[2:, 1:-1] + vp[1:-1, :-2] + vp[1:-1, 2:] - deg * v
             return (np.roll(v, 1, axis=1) + np.roll(v, -1, axis=1) + np.roll(v, 1, axis=0)
                     + np.roll(v, -1, axis=0) - 4.0 * v)
 
@@ -144,7 +172,7 @@ def apply_at(prob, X: np.ndarray, pixels: np.ndarray) -> np.ndarray:
     pixels = np.asarray(pixels, dtype=np.int64)
     Xp = np.asarray(X, dtype=np.float64).reshape(k, -1)
     out = np.zeros((k, len(pixels)))
-    lap = laplacian(ny, nx)
+    lap = laplacian(ny, nx, boundary_of(prob))
     n = ny * nx
     for j in range(k):
         L = (prob.kappa[j] ** 2 * sp.identity(n, format="csr") - lap).tocsr()

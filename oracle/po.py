@@ -18,7 +18,8 @@ from . import operator as op
 
 
 def prior_root(prob) -> sp.csr_matrix:
-    blocks = [np.sqrt(prob.tau[j]) * op.prior_factor(prob.ny, prob.nx, prob.kappa[j]).T
+    blocks = [np.sqrt(prob.tau[j]) * op.prior_factor(prob.ny, prob.nx, prob.kappa[j],
+                                                     op.boundary_of(prob)).T
               for j in range(prob.k)]
     return sp.block_diag(blocks, format="csr")
 

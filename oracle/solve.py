@@ -41,6 +41,8 @@ def fourier_symbols(prob):
 
 
 def _homoscedastic_weights(prob) -> np.ndarray:
+    if op.boundary_of(prob) != "periodic":
+        raise ValueError("the Fourier solve needs a periodic grid")
     w = prob.W[:, :1]
     if not np.all(prob.W == w):
         raise ValueError("solve_fft needs W[f, p] independent of p")
@@ -93,7 +95,8 @@ def solve_kohler(prob, t: np.ndarray, nvec: np.ndarray) -> np.ndarray:
     nvec = np.asarray(nvec, dtype=np.float64)
     if not np.allclose(prob.W, np.outer(t, nvec), rtol=1e-14, atol=0):
         raise ValueError("solve_kohler needs W = t (x) n")
-    Q0 = op.prior_block(prob.ny, prob.nx, kap[0], 1.0)        # tau factored out into P
+    Q0 = op.prior_block(prob.ny, prob.nx, kap[0], 1.0,        # tau factored out into P
+                        op.boundary_of(prob))
     P = np.diag(prob.tau)
     Pinv = np.diag(1.0 / prob.tau)
     T = np.diag(t)

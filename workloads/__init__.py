@@ -42,7 +42,7 @@ __all__ = [
 
 @dataclass
 class Problem:
-    """One posterior-mean system on a periodic ny x nx grid.
+    """One posterior-mean system on an ny x nx grid, periodic or one HEALPix-like face.
 
     Pixel p = iy * nx + ix.  Arrays are float64 numpy arrays:
       kappa[k], tau[k]   prior hyperparameters of component j (Q_j = tau_j (kappa_j^2 I - Lap)^2)
@@ -62,6 +62,7 @@ class Problem:
     Y: np.ndarray
     name: str = ""
     meta: dict = field(default_factory=dict)
+    boundary: str = "periodic"     # "periodic" (torus) or "face" (links only inside the grid)
 
     @property
     def n_pix(self) -> int:
@@ -104,6 +105,7 @@ def make_problem(
     A: Optional[np.ndarray] = None,
     sigma: Optional[np.ndarray] = None,
     name: str = "",
+    boundary: str = "periodic",
 ) -> Problem:
     """Draw one problem.  Draw order is fixed: kappa, tau, A, sigma, weights/mask, sources, noise.
 
@@ -155,7 +157,10 @@ def make_problem(
         # the factors of W[f, p] = t_f n_p (W holds exactly their rounded products)
         meta["t"] = base.copy()
         meta["n"] = nsep[0].copy()
-    return Problem(ny, nx, k, f, kap, ta, Am, W, np.ascontiguousarray(Y), name=name, meta=meta)
+    if boundary not in ("periodic", "face"):
+        raise ValueError(f"unknown boundary {boundary!r}")
+    return Problem(ny, nx, k, f, kap, ta, Am, W, np.ascontiguousarray(Y), name=name, meta=meta,
+                   boundary=boundary)
 
 
 # Named workloads.  Sizes follow the paper's per-patch pixel counts (N = 4^h, App. A) and its
