@@ -204,7 +204,25 @@ def bench_other_workloads(sy, torch, steps, warmup):
                        "backward_iters": stb["iters"], "backward_ok": stb["status"] == 0}
     log(f"grad_512: {out['grad_512']}")
     out["sylv_1024"] = bench_sylvester(sy, torch, steps, warmup)
+    out["healpix_sky_1024"] = bench_sky(sy, torch, steps, warmup)
     return out
+
+
+def bench_sky(sy, torch, steps, warmup):
+    """A full sky at HEALPix level 10: 12 independent 1024^2 faces (links only inside a face),
+    k = 4, f = 9, solved in one batched call to 1e-8, mixed precision and float64."""
+    from workloads import WORKLOADS, workload
+    probs = workload("healpix_sky_1024")
+    tol = WORKLOADS["healpix_sky_1024"]["tol"]
+    dps = [sy.DeviceProblem.from_numpy(p) for p in probs]
+    Y = torch.cat([torch.as_tensor(p.Y.ravel(), device="cuda") for p in probs])
+    res = {"faces": len(probs), "pixels_per_map": sum(p.n_pix for p in probs)}
+    for label, prec in (("mixed", sy.SYLV_PREC_MIXED), ("f64", sy.SYLV_PREC_F64)):
+        o = sy.SolveOptions(tol=tol, precision=prec)
+        ms, st, _ = time_solves(sy, torch, dps, Y, None, o, 1, steps, warmup)
+        res[label] = summarize(ms, st)
+        log(f"healpix_sky_1024 {label}: {res[label]}")
+    return res
 
 
 def bench_sylvester(sy, torch, steps, warmup, max_iter=800):
@@ -259,9 +277,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the 2048^2, batched and differentiable workloads")
-    ap.add_argument("--mode", default="bench", choices=["bench", "pmc", "sylv"],
+    ap.add_argument("--mode", default="bench", choices=["bench", "pmc", "sylv", "sky"],
                     help="pmc: copy + applies + one solve of each precision (counter runs); "
-                         "sylv: only the Lanczos-Sylvester workload")
+                         "sylv: only the Lanczos-Sylvester workload; sky: only the 12-face "
+                         "full-sky workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver has no "
@@ -277,6 +296,10 @@ def main():
     torch.cuda.set_device(0)
     if args.mode == "sylv":
         print(json.dumps({"mode": "sylv", "sylv_1024": bench_sylvester(
+            sy, torch, max(2, args.steps // 2), max(1, args.warmup))}), flush=True)
+        return
+    if args.mode == "sky":
+        print(json.dumps({"mode": "sky", "healpix_sky_1024": bench_sky(
             sy, torch, max(2, args.steps // 2), max(1, args.warmup))}), flush=True)
         return
     name = "het_1024"

@@ -32,6 +32,8 @@
  *    failed.  Numerical outcomes of a solve (converged, not converged, breakdown, non-finite
  *    values) are reported per solve in sylv_pcg_stats.status, not as the return value.
  *  - Limits: 1 <= k <= 8, 1 <= f <= 16, ny, nx >= 1, ny * nx < 2^31.
+ *  - Lap is the graph Laplacian of the pixel grid (Section 3's D): periodic, or one HEALPix base
+ *    face whose border pixels have fewer neighbours (sylv_problem.boundary).
  */
 #ifndef SYLV_H
 #define SYLV_H
@@ -64,6 +66,11 @@ extern "C" {
 #define SYLV_PREC_F64   0       /* every vector and every apply in float64                       */
 #define SYLV_PREC_MIXED 1       /* float32 vectors and applies inside float64 refinement         */
 
+#define SYLV_BC_PERIODIC 0      /* periodic grid: every pixel has 4 neighbours (torus)            */
+#define SYLV_BC_FACE     1      /* one HEALPix base face: 4-neighbour links only inside the grid,
+                                   so border pixels have 2 or 3 (App. A; D of Section 3 with minus
+                                   the row sum on the diagonal)                                  */
+
 #define SYLV_PC_NONE   0        /* z = r (plain Alg. 2)                                           */
 #define SYLV_PC_JACOBI 1        /* z = r / diag(G)                                                */
 #define SYLV_PC_BLOCK  2        /* z_p = (G_pp)^-1 r_p, G_pp the k x k block of pixel p           */
@@ -77,6 +84,8 @@ typedef struct sylv_problem {
     const double *tau;     /* [k]  tau_j > 0      (prior precision scale; the paper's phi_l)     */
     const double *A;       /* [f * k] mixing matrix, row-major                                   */
     const double *W;       /* [f * n_pix] noise precision per map and pixel, >= 0 (0 = masked)   */
+    int32_t boundary;      /* SYLV_BC_PERIODIC or SYLV_BC_FACE (all problems of one call alike)  */
+    int32_t reserved;      /* 0                                                                   */
 } sylv_problem;
 
 typedef struct sylv_pcg_opts {
@@ -196,6 +205,8 @@ typedef struct sylv_sep_problem {
     const double *A;       /* [f * k] mixing matrix, row-major, full column rank                 */
     const double *t;       /* [f]  t_f > 0 (per-map noise precision, T)                          */
     const double *n;       /* [n_pix] n_p > 0 (per-pixel noise precision, N; no masked pixels)   */
+    int32_t boundary;      /* SYLV_BC_PERIODIC or SYLV_BC_FACE                                   */
+    int32_t reserved;      /* 0                                                                   */
 } sylv_sep_problem;
 
 typedef struct sylv_lanczos_opts {

@@ -6,6 +6,8 @@ stream.  Importing works without a GPU; calling any solver function requires the
 and a GPU, and raises otherwise (there is no CPU fallback).
 """
 from .binding import (  # noqa: F401
+    SYLV_BC_FACE,
+    SYLV_BC_PERIODIC,
     SYLV_F32,
     SYLV_F64,
     SYLV_PC_BLOCK,

@@ -30,6 +30,8 @@ SYLV_F64 = 0
 SYLV_F32 = 1
 SYLV_PREC_F64 = 0
 SYLV_PREC_MIXED = 1
+SYLV_BC_PERIODIC = 0
+SYLV_BC_FACE = 1
 SYLV_PC_NONE = 0
 SYLV_PC_JACOBI = 1
 SYLV_PC_BLOCK = 2
@@ -49,7 +51,8 @@ class SylvError(RuntimeError):
 class _Problem(ctypes.Structure):
     _fields_ = [("ny", ctypes.c_int64), ("nx", ctypes.c_int64), ("k", ctypes.c_int32),
                 ("f", ctypes.c_int32), ("kappa", ctypes.c_void_p), ("tau", ctypes.c_void_p),
-                ("A", ctypes.c_void_p), ("W", ctypes.c_void_p)]
+                ("A", ctypes.c_void_p), ("W", ctypes.c_void_p), ("boundary", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class _Opts(ctypes.Structure):
@@ -71,7 +74,15 @@ STATS_BYTES = ctypes.sizeof(_Stats)
 class _SepProblem(ctypes.Structure):
     _fields_ = [("ny", ctypes.c_int64), ("nx", ctypes.c_int64), ("k", ctypes.c_int32),
                 ("f", ctypes.c_int32), ("kappa", ctypes.c_double), ("tau", ctypes.c_void_p),
-                ("A", ctypes.c_void_p), ("t", ctypes.c_void_p), ("n", ctypes.c_void_p)]
+                ("A", ctypes.c_void_p), ("t", ctypes.c_void_p), ("n", ctypes.c_void_p),
+                ("boundary", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+def boundary_code(b) -> int:
+    """SYLV_BC_* from 'periodic' / 'face' (or the code itself)."""
+    if isinstance(b, str):
+        return {"periodic": SYLV_BC_PERIODIC, "face": SYLV_BC_FACE}[b]
+    return int(b)
 
 
 class _LzOpts(ctypes.Structure):
@@ -174,6 +185,7 @@ class DeviceProblem:
     tau: "object"
     A: "object"
     W: "object"
+    boundary: int = SYLV_BC_PERIODIC
 
     @property
     def k(self) -> int:
@@ -194,13 +206,14 @@ class DeviceProblem:
             if t.dtype != torch.float64:
                 raise ValueError(f"{name} must be float64")
         return _Problem(self.ny, self.nx, self.k, self.f, _ptr(self.kappa), _ptr(self.tau),
-                        _ptr(self.A), _ptr(self.W))
+                        _ptr(self.A), _ptr(self.W), boundary_code(self.boundary), 0)
 
     @staticmethod
     def from_numpy(prob, device="cuda"):
         torch = _torch()
         t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=device).contiguous()  # noqa
-        return DeviceProblem(prob.ny, prob.nx, t(prob.kappa), t(prob.tau), t(prob.A), t(prob.W))
+        return DeviceProblem(prob.ny, prob.nx, t(prob.kappa), t(prob.tau), t(prob.A), t(prob.W),
+                             boundary_code(getattr(prob, "boundary", "periodic")))
 
 
 @dataclass
@@ -381,10 +394,11 @@ class SylvSolve:
     _fn = None
 
     @classmethod
-    def apply(cls, kappa, tau, A, W, Y, ny: int, nx: int, opts: Optional[SolveOptions] = None):
+    def apply(cls, kappa, tau, A, W, Y, ny: int, nx: int, opts: Optional[SolveOptions] = None,
+              boundary="periodic"):
         if cls._fn is None:
             cls._fn = _make_function()
-        return cls._fn.apply(kappa, tau, A, W, Y, ny, nx, opts)
+        return cls._fn.apply(kappa, tau, A, W, Y, ny, nx, opts, boundary_code(boundary))
 
 
 def _make_function():
@@ -392,16 +406,16 @@ def _make_function():
 
     class _SylvSolveFn(torch.autograd.Function):
         @staticmethod
-        def forward(ctx, kappa, tau, A, W, Y, ny, nx, opts):
+        def forward(ctx, kappa, tau, A, W, Y, ny, nx, opts, bc):
             opts = opts or SolveOptions(tol=1e-10)
             prob = DeviceProblem(ny, nx, kappa.detach().contiguous(), tau.detach().contiguous(),
-                                 A.detach().contiguous(), W.detach().contiguous())
+                                 A.detach().contiguous(), W.detach().contiguous(), bc)
             Yc = Y.detach().contiguous()
             X, stats = pcg_solve(prob, Y=Yc, opts=opts)
             if stats[0]["status"] != SYLV_OK:
                 raise SylvError(stats[0]["status"], f"forward solve: {stats[0]}")
             ctx.save_for_backward(kappa, tau, A, W, Y, X)
-            ctx.ny, ctx.nx, ctx.opts = ny, nx, opts
+            ctx.ny, ctx.nx, ctx.opts, ctx.bc = ny, nx, opts, bc
             return X
 
         @staticmethod
@@ -409,12 +423,12 @@ def _make_function():
             kappa, tau, A, W, Y, X = ctx.saved_tensors
             prob = DeviceProblem(ctx.ny, ctx.nx, kappa.detach().contiguous(),
                                  tau.detach().contiguous(), A.detach().contiguous(),
-                                 W.detach().contiguous())
+                                 W.detach().contiguous(), ctx.bc)
             _, g, st = pcg_backward(prob, Y.detach().contiguous(), X.detach(),
                                     gX.detach().to(torch.float64).contiguous(), ctx.opts)
             if st["status"] != SYLV_OK:
                 raise SylvError(st["status"], f"adjoint solve: {st}")
-            return g["kappa"], g["tau"], g["A"], g["W"], g["Y"], None, None, None
+            return g["kappa"], g["tau"], g["A"], g["W"], g["Y"], None, None, None, None
 
     return _SylvSolveFn
 
@@ -433,6 +447,7 @@ class SepProblem:
     A: "object"
     t: "object"
     n: "object"
+    boundary: int = SYLV_BC_PERIODIC
 
     @property
     def k(self) -> int:
@@ -452,13 +467,14 @@ class SepProblem:
             if getattr(self, name).dtype != torch.float64:
                 raise ValueError(f"{name} must be float64")
         return _SepProblem(self.ny, self.nx, self.k, self.f, float(self.kappa), _ptr(self.tau),
-                           _ptr(self.A), _ptr(self.t), _ptr(self.n))
+                           _ptr(self.A), _ptr(self.t), _ptr(self.n),
+                           boundary_code(self.boundary), 0)
 
     @staticmethod
-    def from_numpy(ny, nx, kappa, tau, A, t, n, device="cuda"):
+    def from_numpy(ny, nx, kappa, tau, A, t, n, device="cuda", boundary="periodic"):
         torch = _torch()
         c = lambda a: torch.as_tensor(a, dtype=torch.float64, device=device).contiguous()  # noqa
-        return SepProblem(ny, nx, float(kappa), c(tau), c(A), c(t), c(n))
+        return SepProblem(ny, nx, float(kappa), c(tau), c(A), c(t), c(n), boundary_code(boundary))
 
 
 @dataclass

@@ -90,6 +90,7 @@ bool check_problem(const sylv_problem *p, int idx) {
     if (p->ny < 1 || p->nx < 1) { set_err("problem %d: grid %lld x %lld", idx, (long long)p->ny, (long long)p->nx); return false; }
     if (p->ny * p->nx >= (int64_t)1 << 30) { set_err("problem %d: n_pix too large", idx); return false; }
     if (!p->kappa || !p->tau || !p->A || !p->W) { set_err("problem %d: null parameter pointer", idx); return false; }
+    if (p->boundary != SYLV_BC_PERIODIC && p->boundary != SYLV_BC_FACE) { set_err("problem %d: boundary %d", idx, p->boundary); return false; }
     return true;
 }
 
@@ -196,7 +197,7 @@ int prepare_operator(const sylv_problem &p, const ProbLayout &P, char *base, int
                      hipStream_t s) {
     double *coef = reinterpret_cast<double *>(base + P.coef);
     HIP_TRY(launch_coef(p.kappa, p.tau, p.k, (int)p.ny, (int)p.nx, coef, s));
-    HIP_TRY(launch_setup(p.W, p.A, p.f, (int)(p.ny * p.nx), coef, pc,
+    HIP_TRY(launch_setup(p.W, p.A, p.f, (int)p.ny, (int)p.nx, p.boundary, coef, pc,
                          reinterpret_cast<double *>(base + P.M64),
                          reinterpret_cast<float *>(base + P.M32),
                          reinterpret_cast<double *>(base + P.P64),
@@ -336,6 +337,9 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
     const int k = probs[0].k;
     for (int g = 1; g < nprob; ++g)
         if (probs[g].k != k) { set_err("all problems of a call must share k"); return SYLV_E_INVALID; }
+    const int bc = probs[0].boundary;
+    for (int g = 1; g < nprob; ++g)
+        if (probs[g].boundary != bc) { set_err("all problems of a call must share the boundary"); return SYLV_E_INVALID; }
     int rc = check_opts(opts);
     if (rc) return rc;
     if (!X || !stats) { set_err("null X or stats"); return SYLV_E_INVALID; }
@@ -345,8 +349,9 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
     if (rc) return rc;
     char *base = reinterpret_cast<char *>(ws);
     const int mixed = opts->precision == SYLV_PREC_MIXED;
-    const int rows64 = apply_rows_for(k, SYLV_F64, apply_rows_request());
-    const int rows32 = apply_rows_for(k, SYLV_F32, apply_rows_request());
+    // face grids run the apply kernels with 2 rows per lane
+    const int rows64 = bc == SYLV_BC_FACE ? 2 : apply_rows_for(k, SYLV_F64, apply_rows_request());
+    const int rows32 = bc == SYLV_BC_FACE ? 2 : apply_rows_for(k, SYLV_F32, apply_rows_request());
     const int pc = opts->precond;
 
     // instance table
@@ -409,6 +414,7 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
     set.total_chunks = cpre[ninst];
     set.rows64 = rows64;
     set.rows32 = rows32;
+    set.bc = bc;
 
     // block CG groups: one per problem, its nrhs instances in order
     const bool block = opts->block != 0;
@@ -455,6 +461,7 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
         gset.total_chunks = gc[nprob];
         gset.rows64 = kBlockRows;
         gset.rows32 = kBlockRows;
+        gset.bc = bc;
     }
 
     // operator set-up and right-hand sides
@@ -537,6 +544,7 @@ bool check_sep(const sylv_sep_problem *p) {
     if (p->ny * p->nx >= (int64_t)1 << 30) { set_err("n_pix too large"); return false; }
     if (!(p->kappa >= 0.0) || !isfinite(p->kappa)) { set_err("kappa must be finite and >= 0"); return false; }
     if (!p->tau || !p->A || !p->t || !p->n) { set_err("null parameter pointer"); return false; }
+    if (p->boundary != SYLV_BC_PERIODIC && p->boundary != SYLV_BC_FACE) { set_err("boundary %d", p->boundary); return false; }
     return true;
 }
 
@@ -780,12 +788,14 @@ int lanczos_impl(const sylv_sep_problem *p, const double *Y, double *X,
     for (int j = 0; j < k; ++j)
         for (int q = 0; q < k; ++q) C.U[j][q] = sqrt(tau[j]) * Vm[j][q];
     C.tol = o->tol;
+    C.kappa2 = ks;
 
     LzArgs a;
     memset(&a, 0, sizeof(a));
     a.ny = (int)p->ny; a.nx = (int)p->nx; a.n_pix = (int)(p->ny * p->nx); a.k = k; a.f = f;
     a.tiles_x = (a.nx + kTileX - 1) / kTileX;
-    a.rows = lz_rows_for(k);
+    a.bc = p->boundary;
+    a.rows = a.bc == SYLV_BC_FACE ? 2 : lz_rows_for(k);
     a.ntiles = lz_tiles(a.ny, a.nx, a.rows);
     a.nchunks = chunks_for(a.n_pix);
     a.nred = L.nred;
@@ -918,8 +928,8 @@ int sylv_apply(const sylv_problem *prob, int32_t dtype, const void *X, void *Y, 
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     char *base = reinterpret_cast<char *>(ws);
     HIP_TRY(launch_apply_plain(reinterpret_cast<const Inst *>(base + L.table), prob->k, dtype,
-                               apply_rows_for(prob->k, dtype, apply_rows_request()), (int)prob->ny,
-                               (int)prob->nx, nrhs, X, Y, s));
+                               apply_rows_for(prob->k, dtype, apply_rows_request()),
+                               prob->boundary, (int)prob->ny, (int)prob->nx, nrhs, X, Y, s));
     return SYLV_OK;
 }
 
@@ -961,7 +971,7 @@ int sylv_po_perturb(const sylv_problem *prob, const double *xi, const double *ze
     if (nrhs > 65535) { set_err("nrhs > 65535"); return SYLV_E_INVALID; }
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     HIP_TRY(launch_po(prob->kappa, prob->tau, prob->A, prob->W, xi, zeta, eta, prob->k, prob->f,
-                      (int)prob->ny, (int)prob->nx, nrhs, s));
+                      (int)prob->ny, (int)prob->nx, prob->boundary, nrhs, s));
     return SYLV_OK;
 }
 
@@ -987,7 +997,7 @@ int sylv_pcg_backward(const sylv_problem *prob, const double *Y, const double *X
     char *base = reinterpret_cast<char *>(ws);
     HIP_TRY(launch_grad(reinterpret_cast<const double *>(base + L.prob[0].coef), prob->A,
                         prob->W, Y, Xstar, Lambda, prob->k, prob->f, (int)prob->ny,
-                        (int)prob->nx, dkappa, dtau, dA, dW, dY,
+                        (int)prob->nx, prob->boundary, dkappa, dtau, dA, dW, dY,
                         reinterpret_cast<double *>(base + L.gpartial), s));
     return SYLV_OK;
 }

@@ -152,7 +152,7 @@ __global__ __launch_bounds__(kBlock) void k_bdir(const Inst *__restrict__ tab,
 
 // Q = G P for the active columns of a group, sharing the per-pixel mixing blocks, and the
 // partials of P^T Q.  Same tiling and LDS staging as the single-vector apply.
-template <typename T, int K, int R, int S>
+template <typename T, int K, int R, int S, int BC>
 __global__ __launch_bounds__(kBlock) void k_bapply(const Inst *__restrict__ tab,
                                                    const Group *__restrict__ groups,
                                                    const int *__restrict__ gtprefix, int ngroup,
@@ -190,6 +190,21 @@ __global__ __launch_bounds__(kBlock) void k_bapply(const Inst *__restrict__ tab,
     int soff[RPW];
 #pragma unroll
     for (int rr = 0; rr < RPW; ++rr) soff[rr] = wrapi(y0 - 2 + rr * kWavesY + ty, ny) * nx + cmain;
+    // face grids: staged positions outside the face hold 0 (absent neighbours)
+    bool sin[RPW];
+    bool hin = hvalid;
+#pragma unroll
+    for (int rr = 0; rr < RPW; ++rr) sin[rr] = true;
+    if constexpr (BC == BC_FACE) {
+        const bool colin = x0 + tx < nx;
+#pragma unroll
+        for (int rr = 0; rr < RPW; ++rr) {
+            const int ry = y0 - 2 + rr * kWavesY + ty;
+            sin[rr] = colin && ry >= 0 && ry < ny;
+        }
+        const int hy = y0 - 2 + hr, hx = x0 - 2 + hcol;
+        hin = hvalid && hy >= 0 && hy < ny && hx >= 0 && hx < nx;
+    }
 
     T m[R][MK];
     {
@@ -213,15 +228,16 @@ __global__ __launch_bounds__(kBlock) void k_bapply(const Inst *__restrict__ tab,
 #pragma unroll
         for (int j = 0; j < K; ++j) {
 #pragma unroll
-            for (int rr = 0; rr < RPW; ++rr) sa[j][rr] = u[(size_t)j * n_pix + soff[rr]];
-            ha[j] = hvalid ? u[(size_t)j * n_pix + hoff] : (T)0;
+            for (int rr = 0; rr < RPW; ++rr)
+                sa[j][rr] = sin[rr] ? u[(size_t)j * n_pix + soff[rr]] : (T)0;
+            ha[j] = hin ? u[(size_t)j * n_pix + hoff] : (T)0;
         }
         __syncthreads();   // previous column's stencil reads are done
 #pragma unroll
         for (int j = 0; j < K; ++j) {
 #pragma unroll
             for (int rr = 0; rr < RPW; ++rr) lds[j][rr * kWavesY + ty][tx + 2] = sa[j][rr];
-            if (hvalid) lds[j][hr][hcol] = ha[j];
+            if (hvalid) lds[j][hr][hcol] = ha[j];   // 0 outside a face (hin)
         }
         __syncthreads();
         T q[K][R];
@@ -235,6 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_bapply(const Inst *__restrict__ tab,
             for (int j = 0; j < K; ++j) {
                 const double *cj = I0.coef + j * kCoefStride;
                 const T c0 = (T)cj[0], c1 = (T)cj[1], cd = (T)cj[2], c2 = (T)cj[3];
+                const T tj = (T)cj[6], k2 = (T)(cj[5] * cj[5]);
                 T cc[R + 4], l1[R + 2], r1[R + 2], l2[R], r2[R];
 #pragma unroll
                 for (int t = 0; t < R + 4; ++t) cc[t] = lds[j][lr + t][tx + 2];
@@ -250,10 +267,21 @@ __global__ __launch_bounds__(kBlock) void k_bapply(const Inst *__restrict__ tab,
                 }
 #pragma unroll
                 for (int t = 0; t < R; ++t) {
-                    const T n4 = (cc[t + 1] + cc[t + 3]) + (l1[t + 1] + r1[t + 1]);
                     const T d4 = (l1[t] + r1[t]) + (l1[t + 2] + r1[t + 2]);
                     const T f4 = (cc[t] + cc[t + 4]) + (l2[t] + r2[t]);
-                    q[j][t] = c0 * cc[t + 2] + c1 * n4 + cd * d4 + c2 * f4;
+                    if constexpr (BC == BC_FACE) {
+                        const int iy = iy0 + t;
+                        const T dp = (T)face_deg(ix, iy, nx, ny);
+                        const T e0 = k2 + dp, b0 = (T)2 * k2 + dp;
+                        const T en = (b0 + (T)face_deg(ix, iy - 1, nx, ny)) * cc[t + 1] +
+                                     (b0 + (T)face_deg(ix, iy + 1, nx, ny)) * cc[t + 3] +
+                                     (b0 + (T)face_deg(ix - 1, iy, nx, ny)) * l1[t + 1] +
+                                     (b0 + (T)face_deg(ix + 1, iy, nx, ny)) * r1[t + 1];
+                        q[j][t] = tj * (e0 * e0 + dp) * cc[t + 2] - tj * en + cd * d4 + c2 * f4;
+                    } else {
+                        const T n4 = (cc[t + 1] + cc[t + 3]) + (l1[t + 1] + r1[t + 1]);
+                        q[j][t] = c0 * cc[t + 2] + c1 * n4 + cd * d4 + c2 * f4;
+                    }
                     pc[b][j][t] = (iy0 + t < ny) ? cc[t + 2] : (T)0;
                 }
             }
@@ -647,14 +675,19 @@ template <typename T, int K, int S>
 hipError_t launch_bapply_t(const GroupSet &gset, int rows, int total, const int *prefix, int it,
                            hipStream_t st) {
     const dim3 grid(total);
+    if (gset.bc == SYLV_BC_FACE) {
+        hipLaunchKernelGGL((k_bapply<T, K, 2, S, BC_FACE>), grid, dim3(kBlock), 0, st,
+                           gset.table, gset.groups, prefix, gset.ngroup, (int)grid.x, it);
+        return hipGetLastError();
+    }
     switch (rows) {
         case 4:
-            hipLaunchKernelGGL((k_bapply<T, K, 4, S>), grid, dim3(kBlock), 0, st, gset.table,
-                               gset.groups, prefix, gset.ngroup, (int)grid.x, it);
+            hipLaunchKernelGGL((k_bapply<T, K, 4, S, BC_PERIODIC>), grid, dim3(kBlock), 0, st,
+                               gset.table, gset.groups, prefix, gset.ngroup, (int)grid.x, it);
             break;
         default:
-            hipLaunchKernelGGL((k_bapply<T, K, 2, S>), grid, dim3(kBlock), 0, st, gset.table,
-                               gset.groups, prefix, gset.ngroup, (int)grid.x, it);
+            hipLaunchKernelGGL((k_bapply<T, K, 2, S, BC_PERIODIC>), grid, dim3(kBlock), 0, st,
+                               gset.table, gset.groups, prefix, gset.ngroup, (int)grid.x, it);
             break;
     }
     return hipGetLastError();

@@ -24,6 +24,14 @@ __device__ __forceinline__ int wrapi(int v, int n) {
     return v;
 }
 
+// Grid boundary of the pixel graph (template parameter of the stencil kernels).
+enum { BC_PERIODIC = SYLV_BC_PERIODIC, BC_FACE = SYLV_BC_FACE };
+
+// Number of 4-neighbours of pixel (ix, iy) inside an nx x ny face (the minus diagonal of D).
+__device__ __forceinline__ int face_deg(int ix, int iy, int nx, int ny) {
+    return (ix > 0) + (ix < nx - 1) + (iy > 0) + (iy < ny - 1);
+}
+
 // Give XCD x (which receives workgroups x, x+8, x+16, ...) a contiguous range of logical ids.
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
     const int q = nb / kXcd, rem = nb % kXcd;

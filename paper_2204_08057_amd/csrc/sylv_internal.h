@@ -95,6 +95,7 @@ struct InstSet {
     int total_tiles32;
     int total_chunks;
     int rows64, rows32;   // rows per lane of the float64 / float32 apply kernels
+    int bc;               // SYLV_BC_* of every instance (face grids use 2 rows per lane)
 };
 
 inline int packed_size(int k) { return k * (k + 1) / 2; }
@@ -137,6 +138,7 @@ struct GroupSet {
     int ngroup, s;
     int total_tiles, total_tiles32, total_chunks;
     int rows64, rows32;
+    int bc;
 };
 
 // ---- launchers (sylv_kernels.hip) -------------------------------------------------------
@@ -147,13 +149,13 @@ int apply_rows_valid(int rows);
 int apply_rows_for(int k, int dtype, int request);
 hipError_t launch_coef(const double *kappa, const double *tau, int k, int ny, int nx,
                        double *coef, hipStream_t s);
-hipError_t launch_setup(const double *W, const double *A, int f, int n_pix, const double *coef,
-                        int pc, double *M64, float *M32, double *P64, float *P32, int k,
-                        hipStream_t s);
+hipError_t launch_setup(const double *W, const double *A, int f, int ny, int nx, int bc,
+                        const double *coef, int pc, double *M64, float *M32, double *P64,
+                        float *P32, int k, hipStream_t s);
 hipError_t launch_rhs(const double *W, const double *Y, const double *A, int f, int n_pix,
                       const double *bext, double *b, int k, hipStream_t s);
-hipError_t launch_apply_plain(const Inst *table0, int k, int dtype, int rows, int ny, int nx,
-                              int nrhs, const void *in, void *out, hipStream_t s);
+hipError_t launch_apply_plain(const Inst *table0, int k, int dtype, int rows, int bc, int ny,
+                              int nx, int nrhs, const void *in, void *out, hipStream_t s);
 hipError_t launch_precond_plain(const Inst *table0, int k, int dtype, int n_pix, int nrhs,
                                 const void *in, void *out, hipStream_t s);
 // residual r = b - G x (float64); phase 0: initial (sets ||b||, ||r0||, threshold),
@@ -170,9 +172,9 @@ hipError_t launch_count_running(const InstSet &set, int inner, int *out, hipStre
 hipError_t launch_stats(const InstSet &set, void *stats, int mixed, hipStream_t s);
 hipError_t launch_po(const double *kappa, const double *tau, const double *A, const double *W,
                      const double *xi, const double *zeta, double *eta, int k, int f, int ny,
-                     int nx, int nrhs, hipStream_t s);
+                     int nx, int bc, int nrhs, hipStream_t s);
 hipError_t launch_grad(const double *coef, const double *A, const double *W, const double *Y,
-                       const double *X, const double *Lm, int k, int f, int ny, int nx,
+                       const double *X, const double *Lm, int k, int f, int ny, int nx, int bc,
                        double *dkappa, double *dtau, double *dA, double *dW, double *dY,
                        double *partial, hipStream_t s);
 int grad_blocks(int n_pix);
@@ -197,6 +199,7 @@ struct LzConst {
     double U[kMaxK][kMaxK];       // Lhat = U diag(rho) U^-1, U^T P^-1 U = I (Lemma 2)
     double rho[kMaxK];
     double tol;
+    double kappa2;                // kappa^2 (face grids: per-pixel stencil coefficients)
 };
 // Device state of one solve (written only by the one-workgroup finishing kernels).
 struct LzState {
@@ -212,7 +215,7 @@ struct LzState {
 constexpr int kLzStride = kMaxK * kMaxK;   // one k x k coefficient block (row-major, ld kMaxK)
 // Kernel argument block of every Lanczos-Sylvester kernel.
 struct LzArgs {
-    int ny, nx, n_pix, k, f, tiles_x, ntiles, nchunks, nred, rows;
+    int ny, nx, n_pix, k, f, tiles_x, ntiles, nchunks, nred, rows, bc;
     const LzConst *c;
     LzState *st;
     double *H;                    // [max_iter] blocks: H_1 .. (symmetric part)

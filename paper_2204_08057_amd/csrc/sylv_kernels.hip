@@ -62,13 +62,28 @@ __global__ void k_coef(const double *__restrict__ kappa, const double *__restric
 // positive definite (negative tau, say) gets NaN entries so the solve reports it.
 template <int K>
 __global__ __launch_bounds__(kBlock) void k_setup(const double *__restrict__ W,
-                                                  const double *__restrict__ A, int f, int n_pix,
+                                                  const double *__restrict__ A, int f, int ny,
+                                                  int nx, int bc,
                                                   const double *__restrict__ coef, int pc,
                                                   double *__restrict__ M64, float *__restrict__ M32,
                                                   double *__restrict__ P64, float *__restrict__ P32) {
     constexpr int MK = K * (K + 1) / 2;
+    const int n_pix = ny * nx;
     const int pix = blockIdx.x * kBlock + threadIdx.x;
     if (pix >= n_pix) return;
+    // diagonal of Q_j at this pixel: periodic grids share one value (with the wrap coincidences
+    // of tiny grids); on a face it is tau ((kappa^2 + d)^2 + d), d = in-face neighbours
+    double qd[K];
+    {
+        const int iy = pix / nx, ix = pix - iy * nx;
+        const double d = (double)face_deg(ix, iy, nx, ny);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const double *cj = coef + j * kCoefStride;
+            const double e = cj[5] * cj[5] + d;
+            qd[j] = (bc == SYLV_BC_FACE) ? cj[6] * (e * e + d) : cj[4];
+        }
+    }
     double m[MK];
 #pragma unroll
     for (int e = 0; e < MK; ++e) m[e] = 0.0;
@@ -90,7 +105,7 @@ __global__ __launch_bounds__(kBlock) void k_setup(const double *__restrict__ W,
     if (pc == SYLV_PC_JACOBI) {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            const double d = 1.0 / (coef[j * kCoefStride + 4] + m[pidx<K>(j, j)]);
+            const double d = 1.0 / (qd[j] + m[pidx<K>(j, j)]);
             P64[(size_t)j * n_pix + pix] = d;
             P32[(size_t)j * n_pix + pix] = (float)d;
         }
@@ -100,7 +115,7 @@ __global__ __launch_bounds__(kBlock) void k_setup(const double *__restrict__ W,
         for (int i = 0; i < K; ++i)
 #pragma unroll
             for (int j = 0; j < K; ++j) {
-                a[i][j] = m[pidx<K>(i, j)] + (i == j ? coef[i * kCoefStride + 4] : 0.0);
+                a[i][j] = m[pidx<K>(i, j)] + (i == j ? qd[i] : 0.0);
                 l[i][j] = 0.0;
             }
         bool ok = true;
@@ -186,7 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_rhs(const double *__restrict__ W,
 //   AM_RESID : r = b - G(x) and the ||r||^2, ||b||^2 partials   (initial / true residual)
 enum ApplyMode { AM_PLAIN = 0, AM_CG = 1, AM_RESID = 2 };
 
-template <typename T, int K, int R, int MODE>
+template <typename T, int K, int R, int MODE, int BC>
 __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
                                                   const int *__restrict__ tprefix, int ninst,
                                                   int nb, int it,
@@ -239,18 +254,33 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
     int soff[RPW];
 #pragma unroll
     for (int rr = 0; rr < RPW; ++rr) soff[rr] = wrapi(y0 - 2 + rr * kWavesY + ty, ny) * nx + cmain;
+    // face grids: staged positions outside the face hold 0 (absent neighbours)
+    bool sin[RPW];
+    bool hin = hvalid;
+#pragma unroll
+    for (int rr = 0; rr < RPW; ++rr) sin[rr] = true;
+    if constexpr (BC == BC_FACE) {
+        const bool colin = x0 + tx < nx;
+#pragma unroll
+        for (int rr = 0; rr < RPW; ++rr) {
+            const int ry = y0 - 2 + rr * kWavesY + ty;
+            sin[rr] = colin && ry >= 0 && ry < ny;
+        }
+        const int hy = y0 - 2 + hr, hx = x0 - 2 + hcol;
+        hin = hvalid && hy >= 0 && hy < ny && hx >= 0 && hx < nx;
+    }
     T sa[K][RPW], sb[K][RPW], ha[K], hb[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         const GAS T *a = u0 + (size_t)j * n_pix;
 #pragma unroll
-        for (int rr = 0; rr < RPW; ++rr) sa[j][rr] = a[soff[rr]];
-        ha[j] = hvalid ? a[hoff] : (T)0;
+        for (int rr = 0; rr < RPW; ++rr) sa[j][rr] = sin[rr] ? a[soff[rr]] : (T)0;
+        ha[j] = hin ? a[hoff] : (T)0;
         if constexpr (MODE == AM_CG) {
             const GAS T *zz = u1 + (size_t)j * n_pix;
 #pragma unroll
-            for (int rr = 0; rr < RPW; ++rr) sb[j][rr] = zz[soff[rr]];
-            hb[j] = hvalid ? zz[hoff] : (T)0;
+            for (int rr = 0; rr < RPW; ++rr) sb[j][rr] = sin[rr] ? zz[soff[rr]] : (T)0;
+            hb[j] = hin ? zz[hoff] : (T)0;
         }
     }
     // CG (it >= 1): x += alpha_(it-1) p_(it-1) on the staged interior values (each pixel of the
@@ -351,6 +381,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
         for (int j = 0; j < K; ++j) {
             const double *cj = I.coef + j * kCoefStride;
             const T c0 = (T)cj[0], c1 = (T)cj[1], cd = (T)cj[2], c2 = (T)cj[3];
+            const T tj = (T)cj[6], k2 = (T)(cj[5] * cj[5]);
             T cc[R + 4], l1[R + 2], r1[R + 2], l2[R], r2[R];
 #pragma unroll
             for (int t = 0; t < R + 4; ++t) cc[t] = lds[j][lr + t][tx + 2];
@@ -366,10 +397,23 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
             }
 #pragma unroll
             for (int t = 0; t < R; ++t) {
-                const T n4 = (cc[t + 1] + cc[t + 3]) + (l1[t + 1] + r1[t + 1]);
                 const T d4 = (l1[t] + r1[t]) + (l1[t + 2] + r1[t + 2]);
                 const T f4 = (cc[t] + cc[t + 4]) + (l2[t] + r2[t]);
-                acc[j][t] = c0 * cc[t + 2] + c1 * n4 + cd * d4 + c2 * f4;
+                if constexpr (BC == BC_FACE) {
+                    // tau ((kappa^2 + d_p)^2 + d_p) at the centre, -tau (2 kappa^2 + d_p + d_q)
+                    // at edge neighbour q (absent neighbours are staged as 0)
+                    const int iy = iy0 + t;
+                    const T dp = (T)face_deg(ix, iy, nx, ny);
+                    const T e0 = k2 + dp, b0 = (T)2 * k2 + dp;
+                    const T en = (b0 + (T)face_deg(ix, iy - 1, nx, ny)) * cc[t + 1] +
+                                 (b0 + (T)face_deg(ix, iy + 1, nx, ny)) * cc[t + 3] +
+                                 (b0 + (T)face_deg(ix - 1, iy, nx, ny)) * l1[t + 1] +
+                                 (b0 + (T)face_deg(ix + 1, iy, nx, ny)) * r1[t + 1];
+                    acc[j][t] = tj * (e0 * e0 + dp) * cc[t + 2] - tj * en + cd * d4 + c2 * f4;
+                } else {
+                    const T n4 = (cc[t + 1] + cc[t + 3]) + (l1[t + 1] + r1[t + 1]);
+                    acc[j][t] = c0 * cc[t + 2] + c1 * n4 + cd * d4 + c2 * f4;
+                }
                 ctr[j][t] = cc[t + 2];
             }
         }
@@ -786,7 +830,8 @@ __global__ __launch_bounds__(kBlock) void k_po(const double *__restrict__ kappa,
                                                const double *__restrict__ W,
                                                const double *__restrict__ xi,
                                                const double *__restrict__ zeta,
-                                               double *__restrict__ eta, int f, int ny, int nx) {
+                                               double *__restrict__ eta, int f, int ny, int nx,
+                                               int bc) {
     const int n_pix = ny * nx;
     const int pix = blockIdx.x * kBlock + threadIdx.x;
     if (pix >= n_pix) return;
@@ -797,12 +842,17 @@ __global__ __launch_bounds__(kBlock) void k_po(const double *__restrict__ kappa,
     const int iy = pix / nx, ix = pix - iy * nx;
     const int n = wrapi(iy - 1, ny) * nx + ix, s = wrapi(iy + 1, ny) * nx + ix;
     const int w = iy * nx + wrapi(ix - 1, nx), e = iy * nx + wrapi(ix + 1, nx);
+    // face grids: neighbours outside the face are absent and the diagonal counts the others
+    const bool face = bc == SYLV_BC_FACE;
+    const double hn = (!face || iy > 0) ? 1.0 : 0.0, hs = (!face || iy < ny - 1) ? 1.0 : 0.0;
+    const double hw = (!face || ix > 0) ? 1.0 : 0.0, he = (!face || ix < nx - 1) ? 1.0 : 0.0;
+    const double dg = face ? (hn + hs) + (hw + he) : 4.0;
     double acc[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         const double *u = xr + (size_t)j * n_pix;
         const double kp = kappa[j], t = tau[j];
-        const double lu = (kp * kp + 4.0) * u[pix] - ((u[n] + u[s]) + (u[w] + u[e]));
+        const double lu = (kp * kp + dg) * u[pix] - ((hn * u[n] + hs * u[s]) + (hw * u[w] + he * u[e]));
         acc[j] = sqrt(t) * lu;
     }
     for (int fi = 0; fi < f; ++fi) {
@@ -826,7 +876,7 @@ __global__ __launch_bounds__(kBlock) void k_grad(const double *__restrict__ coef
                                                  const double *__restrict__ Y,
                                                  const double *__restrict__ X,
                                                  const double *__restrict__ Lm, int f, int ny,
-                                                 int nx, double *__restrict__ dW,
+                                                 int nx, int bc, double *__restrict__ dW,
                                                  double *__restrict__ dY,
                                                  double *__restrict__ partial) {
     const int n_pix = ny * nx;
@@ -843,16 +893,21 @@ __global__ __launch_bounds__(kBlock) void k_grad(const double *__restrict__ coef
         const int iy = pix / nx, ix = pix - iy * nx;
         const int n = wrapi(iy - 1, ny) * nx + ix, s = wrapi(iy + 1, ny) * nx + ix;
         const int w = iy * nx + wrapi(ix - 1, nx), e = iy * nx + wrapi(ix + 1, nx);
+        // face grids: neighbours outside the face are absent and the diagonal counts the others
+        const bool face = bc == SYLV_BC_FACE;
+        const double hn = (!face || iy > 0) ? 1.0 : 0.0, hs = (!face || iy < ny - 1) ? 1.0 : 0.0;
+        const double hw = (!face || ix > 0) ? 1.0 : 0.0, he = (!face || ix < nx - 1) ? 1.0 : 0.0;
+        const double dg = face ? (hn + hs) + (hw + he) : 4.0;
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const double kp = coef[j * kCoefStride + 5];
-            const double d = kp * kp + 4.0;
+            const double d = kp * kp + dg;
             const double *u = X + (size_t)j * n_pix;
             const double *v = Lm + (size_t)j * n_pix;
             xs[j] = u[pix];
             lm[j] = v[pix];
-            tx[j] = d * xs[j] - ((u[n] + u[s]) + (u[w] + u[e]));
-            tl[j] = d * lm[j] - ((v[n] + v[s]) + (v[w] + v[e]));
+            tx[j] = d * xs[j] - ((hn * u[n] + hs * u[s]) + (hw * u[w] + he * u[e]));
+            tl[j] = d * lm[j] - ((hn * v[n] + hs * v[s]) + (hw * v[w] + he * v[e]));
         }
     }
 #pragma unroll
@@ -907,24 +962,30 @@ __global__ void k_grad_fin(const double *__restrict__ partial, int nv, int nblk,
     }
 }
 
+// Face grids always run with 2 rows per lane (the host sizes their tiles accordingly).
 template <typename T, int K, int MODE>
-hipError_t launch_apply_rows(int rows, dim3 grid, hipStream_t s, const Inst *table,
+hipError_t launch_apply_rows(int rows, int bc, dim3 grid, hipStream_t s, const Inst *table,
                              const int *tprefix, int ninst, int it, const void *in, void *out) {
     const T *i = reinterpret_cast<const T *>(in);
     T *o = reinterpret_cast<T *>(out);
     const int nb = (int)grid.x;
+    if (bc == SYLV_BC_FACE) {
+        hipLaunchKernelGGL((k_apply<T, K, 2, MODE, BC_FACE>), grid, dim3(kBlock), 0, s, table,
+                           tprefix, ninst, nb, it, i, o);
+        return hipGetLastError();
+    }
     switch (rows) {
         case 2:
-            hipLaunchKernelGGL((k_apply<T, K, 2, MODE>), grid, dim3(kBlock), 0, s, table,
-                               tprefix, ninst, nb, it, i, o);
+            hipLaunchKernelGGL((k_apply<T, K, 2, MODE, BC_PERIODIC>), grid, dim3(kBlock), 0, s,
+                               table, tprefix, ninst, nb, it, i, o);
             break;
         case 8:
-            hipLaunchKernelGGL((k_apply<T, K, 8, MODE>), grid, dim3(kBlock), 0, s, table,
-                               tprefix, ninst, nb, it, i, o);
+            hipLaunchKernelGGL((k_apply<T, K, 8, MODE, BC_PERIODIC>), grid, dim3(kBlock), 0, s,
+                               table, tprefix, ninst, nb, it, i, o);
             break;
         default:
-            hipLaunchKernelGGL((k_apply<T, K, 4, MODE>), grid, dim3(kBlock), 0, s, table,
-                               tprefix, ninst, nb, it, i, o);
+            hipLaunchKernelGGL((k_apply<T, K, 4, MODE, BC_PERIODIC>), grid, dim3(kBlock), 0, s,
+                               table, tprefix, ninst, nb, it, i, o);
             break;
     }
     return hipGetLastError();
@@ -953,13 +1014,14 @@ hipError_t launch_coef(const double *kappa, const double *tau, int k, int ny, in
     return hipGetLastError();
 }
 
-hipError_t launch_setup(const double *W, const double *A, int f, int n_pix, const double *coef,
-                        int pc, double *M64, float *M32, double *P64, float *P32, int k,
-                        hipStream_t s) {
+hipError_t launch_setup(const double *W, const double *A, int f, int ny, int nx, int bc,
+                        const double *coef, int pc, double *M64, float *M32, double *P64,
+                        float *P32, int k, hipStream_t s) {
+    const long n_pix = (long)ny * nx;
     return dispatch_k(k, [&](auto tag) {
         constexpr int K = decltype(tag)::value;
         hipLaunchKernelGGL((k_setup<K>), dim3(blocks_for(n_pix, kBlock)), dim3(kBlock), 0, s, W,
-                           A, f, n_pix, coef, pc, M64, M32, P64, P32);
+                           A, f, ny, nx, bc, coef, pc, M64, M32, P64, P32);
         return hipGetLastError();
     });
 }
@@ -974,18 +1036,19 @@ hipError_t launch_rhs(const double *W, const double *Y, const double *A, int f, 
     });
 }
 
-hipError_t launch_apply_plain(const Inst *table0, int k, int dtype, int rows, int ny, int nx,
-                              int nrhs, const void *in, void *out, hipStream_t s) {
+hipError_t launch_apply_plain(const Inst *table0, int k, int dtype, int rows, int bc, int ny,
+                              int nx, int nrhs, const void *in, void *out, hipStream_t s) {
+    if (bc == SYLV_BC_FACE) rows = 2;
     const unsigned tx = blocks_for(nx, kTileX);
     const unsigned ty = blocks_for(ny, kWavesY * rows);
     const dim3 grid(tx * ty, nrhs);
     return dispatch_k(k, [&](auto tag) {
         constexpr int K = decltype(tag)::value;
         if (dtype == SYLV_F64)
-            return launch_apply_rows<double, K, AM_PLAIN>(rows, grid, s, table0, nullptr, 1, 0,
-                                                          in, out);
-        return launch_apply_rows<float, K, AM_PLAIN>(rows, grid, s, table0, nullptr, 1, 0, in,
-                                                     out);
+            return launch_apply_rows<double, K, AM_PLAIN>(rows, bc, grid, s, table0, nullptr, 1,
+                                                          0, in, out);
+        return launch_apply_rows<float, K, AM_PLAIN>(rows, bc, grid, s, table0, nullptr, 1, 0,
+                                                     in, out);
     });
 }
 
@@ -1010,8 +1073,8 @@ hipError_t launch_resid(const InstSet &set, int k, int phase, hipStream_t s) {
     (void)phase;
     return dispatch_k(k, [&](auto tag) {
         constexpr int K = decltype(tag)::value;
-        return launch_apply_rows<double, K, AM_RESID>(set.rows64, dim3(set.total_tiles), s,
-                                                      set.table, set.tprefix, set.ninst, 0,
+        return launch_apply_rows<double, K, AM_RESID>(set.rows64, set.bc, dim3(set.total_tiles),
+                                                      s, set.table, set.tprefix, set.ninst, 0,
                                                       nullptr, nullptr);
     });
 }
@@ -1025,10 +1088,11 @@ hipError_t launch_cg_apply(const InstSet &set, int k, int mixed, int it, hipStre
     return dispatch_k(k, [&](auto tag) {
         constexpr int K = decltype(tag)::value;
         if (mixed)
-            return launch_apply_rows<float, K, AM_CG>(set.rows32, dim3(set.total_tiles32), s,
-                                                      set.table, set.tprefix32, set.ninst, it,
-                                                      nullptr, nullptr);
-        return launch_apply_rows<double, K, AM_CG>(set.rows64, dim3(set.total_tiles), s,
+            return launch_apply_rows<float, K, AM_CG>(set.rows32, set.bc,
+                                                      dim3(set.total_tiles32), s, set.table,
+                                                      set.tprefix32, set.ninst, it, nullptr,
+                                                      nullptr);
+        return launch_apply_rows<double, K, AM_CG>(set.rows64, set.bc, dim3(set.total_tiles), s,
                                                    set.table, set.tprefix, set.ninst, it,
                                                    nullptr, nullptr);
     });
@@ -1093,25 +1157,25 @@ hipError_t launch_stats(const InstSet &set, void *stats, int mixed, hipStream_t 
 
 hipError_t launch_po(const double *kappa, const double *tau, const double *A, const double *W,
                      const double *xi, const double *zeta, double *eta, int k, int f, int ny,
-                     int nx, int nrhs, hipStream_t s) {
+                     int nx, int bc, int nrhs, hipStream_t s) {
     return dispatch_k(k, [&](auto tag) {
         constexpr int K = decltype(tag)::value;
         const dim3 grid(blocks_for((long)ny * nx, kBlock), nrhs);
         hipLaunchKernelGGL((k_po<K>), grid, dim3(kBlock), 0, s, kappa, tau, A, W, xi, zeta, eta,
-                           f, ny, nx);
+                           f, ny, nx, bc);
         return hipGetLastError();
     });
 }
 
 hipError_t launch_grad(const double *coef, const double *A, const double *W, const double *Y,
-                       const double *X, const double *Lm, int k, int f, int ny, int nx,
+                       const double *X, const double *Lm, int k, int f, int ny, int nx, int bc,
                        double *dkappa, double *dtau, double *dA, double *dW, double *dY,
                        double *partial, hipStream_t s) {
     const int nblk = grad_blocks(ny * nx);
     hipError_t e = dispatch_k(k, [&](auto tag) {
         constexpr int K = decltype(tag)::value;
         hipLaunchKernelGGL((k_grad<K>), dim3(nblk), dim3(kBlock), 0, s, coef, A, W, Y, X, Lm, f,
-                           ny, nx, dW, dY, partial);
+                           ny, nx, bc, dW, dY, partial);
         return hipGetLastError();
     });
     if (e != hipSuccess) return e;

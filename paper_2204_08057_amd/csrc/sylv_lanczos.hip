@@ -211,7 +211,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_start(LzArgs a) {
 // Stencil kernels.  STEP: one Lanczos step (see the file comment).  RESID: residual of eq. (Axb)
 // for X: r_j = n_p tau_j Yhat_j - (tau_j D2 X_j + n_p (A^T T A X_p)_j), with the partials of
 // ||r||^2 and ||b||^2.
-template <int K, int MODE, int R>
+template <int K, int MODE, int R, int BC>
 __global__ __launch_bounds__(kBlock) void k_lz_stencil(LzArgs a, int it) {
     constexpr int LH = kWavesY * R + 4;   // staged rows: tile + 2-row halo above and below
     constexpr int LW = kTileX + 4;        // staged columns
@@ -244,18 +244,33 @@ __global__ __launch_bounds__(kBlock) void k_lz_stencil(LzArgs a, int it) {
     int soff[RPW];
 #pragma unroll
     for (int rr = 0; rr < RPW; ++rr) soff[rr] = wrapi(y0 - 2 + rr * kWavesY + ty, ny) * nx + cmain;
+    // face grids: staged positions outside the face hold 0 (absent neighbours)
+    bool sin[RPW];
+    bool hin = hvalid;
+#pragma unroll
+    for (int rr = 0; rr < RPW; ++rr) sin[rr] = true;
+    if constexpr (BC == BC_FACE) {
+        const bool colin = x0 + tx < nx;
+#pragma unroll
+        for (int rr = 0; rr < RPW; ++rr) {
+            const int ry = y0 - 2 + rr * kWavesY + ty;
+            sin[rr] = colin && ry >= 0 && ry < ny;
+        }
+        const int hy = y0 - 2 + hr, hx = x0 - 2 + hcol;
+        hin = hvalid && hy >= 0 && hy < ny && hx >= 0 && hx < nx;
+    }
     double sa[K][RPW], ha[K], sv[K][RPW], hv[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         const GAS double *s = gp(src0) + (size_t)j * n_pix;
 #pragma unroll
-        for (int rr = 0; rr < RPW; ++rr) sa[j][rr] = s[soff[rr]];
-        ha[j] = hvalid ? s[hoff] : 0.0;
+        for (int rr = 0; rr < RPW; ++rr) sa[j][rr] = sin[rr] ? s[soff[rr]] : 0.0;
+        ha[j] = hin ? s[hoff] : 0.0;
         if (prev) {
             const GAS double *v = vprev + (size_t)j * n_pix;
 #pragma unroll
-            for (int rr = 0; rr < RPW; ++rr) sv[j][rr] = v[soff[rr]];
-            hv[j] = hvalid ? v[hoff] : 0.0;
+            for (int rr = 0; rr < RPW; ++rr) sv[j][rr] = sin[rr] ? v[soff[rr]] : 0.0;
+            hv[j] = hin ? v[hoff] : 0.0;
         } else {
 #pragma unroll
             for (int rr = 0; rr < RPW; ++rr) sv[j][rr] = 0.0;
@@ -316,6 +331,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_stencil(LzArgs a, int it) {
 
     // ---- 13-point stencil of (kappa^2 - Lap)^2 from LDS --------------------------------------
     const double c0 = c->coef[0], c1 = c->coef[1], cd = c->coef[2], c2 = c->coef[3];
+    const double k2 = c->kappa2;
     double uo[R][K], wo[R][K], wt[R];
     double d0 = 0.0, d1 = 0.0;
 #pragma unroll
@@ -344,10 +360,23 @@ __global__ __launch_bounds__(kBlock) void k_lz_stencil(LzArgs a, int it) {
             }
 #pragma unroll
             for (int t = 0; t < R; ++t) {
-                const double n4 = (cc[t + 1] + cc[t + 3]) + (l1[t + 1] + r1[t + 1]);
                 const double d4 = (l1[t] + r1[t]) + (l1[t + 2] + r1[t + 2]);
                 const double f4 = (cc[t] + cc[t + 4]) + (l2[t] + r2[t]);
-                acc[j][t] = c0 * cc[t + 2] + c1 * n4 + cd * d4 + c2 * f4;
+                if constexpr (BC == BC_FACE) {
+                    // (kappa^2 + d_p)^2 + d_p at the centre, -(2 kappa^2 + d_p + d_q) at edge
+                    // neighbour q (absent neighbours are staged as 0)
+                    const int iy = iy0 + t;
+                    const double dp = (double)face_deg(ix, iy, nx, ny);
+                    const double e0 = k2 + dp, b0 = 2.0 * k2 + dp;
+                    const double en = (b0 + face_deg(ix, iy - 1, nx, ny)) * cc[t + 1] +
+                                      (b0 + face_deg(ix, iy + 1, nx, ny)) * cc[t + 3] +
+                                      (b0 + face_deg(ix - 1, iy, nx, ny)) * l1[t + 1] +
+                                      (b0 + face_deg(ix + 1, iy, nx, ny)) * r1[t + 1];
+                    acc[j][t] = (e0 * e0 + dp) * cc[t + 2] - en + cd * d4 + c2 * f4;
+                } else {
+                    const double n4 = (cc[t + 1] + cc[t + 3]) + (l1[t + 1] + r1[t + 1]);
+                    acc[j][t] = c0 * cc[t + 2] + c1 * n4 + cd * d4 + c2 * f4;
+                }
                 ctr[j][t] = cc[t + 2];
             }
         }
@@ -772,12 +801,15 @@ hipError_t lz_launch_start(const LzArgs &a, hipStream_t s) {
 hipError_t lz_launch_step(const LzArgs &a, int it, hipStream_t s) {
     return dispatch_k(a.k, [&](auto kt) -> hipError_t {
         constexpr int K = decltype(kt)::value;
-        if (K <= 4 && a.rows == 4)
-            hipLaunchKernelGGL((k_lz_stencil<K, LZ_STEP, (K <= 4 ? 4 : 2)>), dim3(a.ntiles),
+        if (a.bc == SYLV_BC_FACE)
+            hipLaunchKernelGGL((k_lz_stencil<K, LZ_STEP, 2, BC_FACE>), dim3(a.ntiles),
                                dim3(kBlock), 0, s, a, it);
+        else if (K <= 4 && a.rows == 4)
+            hipLaunchKernelGGL((k_lz_stencil<K, LZ_STEP, (K <= 4 ? 4 : 2), BC_PERIODIC>),
+                               dim3(a.ntiles), dim3(kBlock), 0, s, a, it);
         else
-            hipLaunchKernelGGL((k_lz_stencil<K, LZ_STEP, 2>), dim3(a.ntiles), dim3(kBlock), 0, s,
-                               a, it);
+            hipLaunchKernelGGL((k_lz_stencil<K, LZ_STEP, 2, BC_PERIODIC>), dim3(a.ntiles),
+                               dim3(kBlock), 0, s, a, it);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         if ((e = launch_reduce(a, lz_nv_step<K>(), a.ntiles, s)) != hipSuccess) return e;
@@ -797,12 +829,15 @@ hipError_t lz_launch_finish(const LzArgs &a, int iters, hipStream_t s) {
         hipLaunchKernelGGL((k_lz_assemble<K>), dim3(a.nchunks), dim3(kBlock), 0, s, a, iters);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        if (K <= 4 && a.rows == 4)
-            hipLaunchKernelGGL((k_lz_stencil<K, LZ_RESID, (K <= 4 ? 4 : 2)>), dim3(a.ntiles),
+        if (a.bc == SYLV_BC_FACE)
+            hipLaunchKernelGGL((k_lz_stencil<K, LZ_RESID, 2, BC_FACE>), dim3(a.ntiles),
                                dim3(kBlock), 0, s, a, 0);
+        else if (K <= 4 && a.rows == 4)
+            hipLaunchKernelGGL((k_lz_stencil<K, LZ_RESID, (K <= 4 ? 4 : 2), BC_PERIODIC>),
+                               dim3(a.ntiles), dim3(kBlock), 0, s, a, 0);
         else
-            hipLaunchKernelGGL((k_lz_stencil<K, LZ_RESID, 2>), dim3(a.ntiles), dim3(kBlock), 0,
-                               s, a, 0);
+            hipLaunchKernelGGL((k_lz_stencil<K, LZ_RESID, 2, BC_PERIODIC>), dim3(a.ntiles),
+                               dim3(kBlock), 0, s, a, 0);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = launch_reduce(a, 2, a.ntiles, s)) != hipSuccess) return e;
         hipLaunchKernelGGL(k_lz_rfin, dim3(1), dim3(64), 0, s, a);

@@ -15,8 +15,8 @@ pytestmark = pytest.mark.skipif(not os.path.exists(bd.library_path()),
 FAKE = 0x100000  # never dereferenced: every call below fails validation before any HIP call
 
 
-def fake_problem(ny=32, nx=32, k=3, f=6):
-    return bd._Problem(ny, nx, k, f, FAKE, FAKE, FAKE, FAKE)
+def fake_problem(ny=32, nx=32, k=3, f=6, boundary=0):
+    return bd._Problem(ny, nx, k, f, FAKE, FAKE, FAKE, FAKE, boundary, 0)
 
 
 def test_every_declared_symbol_is_exported():
@@ -33,8 +33,9 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_header_struct_sizes_match_binding():
-    # int64 x2 + int32 x2 + 4 pointers; double, int32 x2, double, int32 x4; int32 x4 + double x2
-    assert ctypes.sizeof(bd._Problem) == 56
+    # int64 x2 + int32 x2 + 4 pointers + int32 x2; double, int32 x2, double, int32 x4;
+    # int32 x4 + double x2
+    assert ctypes.sizeof(bd._Problem) == 64
     assert ctypes.sizeof(bd._Opts) == 40
     assert ctypes.sizeof(bd._Stats) == 32
 
@@ -56,7 +57,7 @@ def test_workspace_bytes_grows_with_problem():
 
 
 @pytest.mark.parametrize("bad", [dict(k=0), dict(k=9), dict(f=0), dict(f=17), dict(ny=0),
-                                 dict(nx=-3)])
+                                 dict(nx=-3), dict(boundary=2), dict(boundary=-1)])
 def test_invalid_problems_rejected(bad):
     L = sy.lib()
     args = dict(ny=8, nx=8, k=3, f=4)
@@ -126,13 +127,13 @@ def test_binding_refuses_host_tensors():
 
 # ---- Lanczos-Sylvester entry points ---------------------------------------------------------
 
-def fake_sep(ny=32, nx=32, k=4, f=9, kappa=0.5):
-    return bd._SepProblem(ny, nx, k, f, kappa, FAKE, FAKE, FAKE, FAKE)
+def fake_sep(ny=32, nx=32, k=4, f=9, kappa=0.5, boundary=0):
+    return bd._SepProblem(ny, nx, k, f, kappa, FAKE, FAKE, FAKE, FAKE, boundary, 0)
 
 
 def test_lanczos_struct_sizes():
-    # int64 x2 + int32 x2 + double + 4 pointers; double + int32 x2; int32 x2 + double x2
-    assert ctypes.sizeof(bd._SepProblem) == 64
+    # int64 x2 + int32 x2 + double + 4 pointers + int32 x2; double + int32 x2; int32 x2 + double x2
+    assert ctypes.sizeof(bd._SepProblem) == 72
     assert ctypes.sizeof(bd._LzOpts) == 16
     assert ctypes.sizeof(bd._LzStats) == 24
 
@@ -149,7 +150,7 @@ def test_lanczos_workspace_holds_the_basis():
 
 
 @pytest.mark.parametrize("bad", [dict(k=0), dict(k=9), dict(f=0), dict(f=17), dict(ny=0),
-                                 dict(kappa=-1.0), dict(kappa=float("nan"))])
+                                 dict(kappa=-1.0), dict(kappa=float("nan")), dict(boundary=3)])
 def test_lanczos_invalid_problems_rejected(bad):
     L = sy.lib()
     args = dict(ny=8, nx=8, k=3, f=4, kappa=0.5)

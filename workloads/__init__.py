@@ -180,6 +180,10 @@ WORKLOADS = {
     # kappa shared by the components (the first kappa draw of the seed)
     "sylv_1024": dict(index=5, ny=1024, nx=1024, k=4, f=9, noise="separable",
                       common_kappa=True, tol=1e-8, precision="f64"),
+    # a full sky at HEALPix level 10: the 12 base faces (1024 x 1024 pixels each, links only
+    # inside a face, App. A), 4 sources, 9 maps, solved as 12 independent problems in one call
+    "healpix_sky_1024": dict(index=6, sizes=[1024] * 12, nrhs=1, k=4, f=9, noise="hetero",
+                             boundary="face", tol=1e-8, precision="f64+mixed"),
 }
 
 
@@ -196,7 +200,8 @@ def workload(name: str, scale: Optional[int] = None) -> List[Problem]:
         for g, side in enumerate(cfg["sizes"]):
             s = side if scale is None else max(4, side // scale)
             out.append(make_problem(s, s, cfg["k"], cfg["f"], seed * 100 + g, noise=cfg["noise"],
-                                    name=f"{name}[{g}]"))
+                                    name=f"{name}[{g}]",
+                                    boundary=cfg.get("boundary", "periodic")))
         return out
     ny = cfg["ny"] if scale is None else scale
     nx = cfg["nx"] if scale is None else scale
