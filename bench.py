@@ -130,7 +130,7 @@ def summarize(ms, st):
             "all_ok": all(s["status"] == 0 for s in st)}
 
 
-def bench_other_workloads(sy, torch, steps, warmup):
+def bench_other_workloads(sy, torch, steps, warmup, cpu=False):
     """The other workloads of the solver, timed the same way (not the headline value)."""
     from workloads import WORKLOADS, workload
     out = {}
@@ -203,12 +203,12 @@ def bench_other_workloads(sy, torch, steps, warmup):
     out["grad_512"] = {"forward": summarize(ms_f, st), "backward_ms": round(ms_b, 3),
                        "backward_iters": stb["iters"], "backward_ok": stb["status"] == 0}
     log(f"grad_512: {out['grad_512']}")
-    out["sylv_1024"] = bench_sylvester(sy, torch, steps, warmup)
-    out["healpix_sky_1024"] = bench_sky(sy, torch, steps, warmup)
+    out["sylv_1024"] = bench_sylvester(sy, torch, steps, warmup, cpu=cpu)
+    out["healpix_sky_1024"] = bench_sky(sy, torch, steps, warmup, cpu=cpu)
     return out
 
 
-def bench_sky(sy, torch, steps, warmup):
+def bench_sky(sy, torch, steps, warmup, cpu=False):
     """A full sky at HEALPix level 10: 12 independent 1024^2 faces (links only inside a face),
     k = 4, f = 9, solved in one batched call to 1e-8, mixed precision and float64."""
     from workloads import WORKLOADS, workload
@@ -222,10 +222,30 @@ def bench_sky(sy, torch, steps, warmup):
         ms, st, _ = time_solves(sy, torch, dps, Y, None, o, 1, steps, warmup)
         res[label] = summarize(ms, st)
         log(f"healpix_sky_1024 {label}: {res[label]}")
+    if cpu:
+        # the oracle's PCG (assembled sparse G, block-Jacobi) on one full-size face, bounded
+        from oracle import operator as op
+        from oracle import pcg as opcg
+        p0 = probs[0]
+        t0 = time.perf_counter()
+        G = op.posterior_precision(p0)
+        t1 = time.perf_counter()
+        nit = 20
+        opcg.pcg(p0, G=G, tol=0.0, max_iter=nit, precond="block")
+        t2 = time.perf_counter()
+        per_it = (t2 - t1) / nit
+        est = 12 * ((t1 - t0) + per_it * res["f64"]["iters_max"])
+        res["cpu_oracle"] = {"kind": "oracle", "assembly_ms_per_face": round((t1 - t0) * 1e3, 1),
+                             "ms_per_iteration_per_face": round(per_it * 1e3, 1),
+                             "estimate_full_sky_ms": round(est * 1e3, 0),
+                             "sample": f"assembly and {nit} PCG iterations of the oracle on one "
+                                       "1024^2 face; the estimate scales them to 12 faces and "
+                                       "the float64 GPU run's iteration count"}
+        log(f"healpix_sky_1024 cpu oracle: {res['cpu_oracle']}")
     return res
 
 
-def bench_sylvester(sy, torch, steps, warmup, max_iter=800):
+def bench_sylvester(sy, torch, steps, warmup, max_iter=800, cpu=False):
     """1024^2, k = 4, f = 9, separable noise, common kappa: the Lanczos-Sylvester solver
     (Alg. 4 + Alg. 5) against float64 and mixed PCG on the same system, all to 1e-8."""
     from workloads import WORKLOADS, workload
@@ -265,6 +285,19 @@ def bench_sylvester(sy, torch, steps, warmup, max_iter=800):
     res["rel_diff_lanczos_vs_pcg_f64"] = float(torch.linalg.norm(X - xref) /
                                                torch.linalg.norm(xref))
     res["kappa"] = float(prob.kappa[0])
+    if cpu:
+        # the oracle's Alg. 5 (eigendecomposition of T_i every step, second Lanczos pass) on
+        # the same full-size problem, for a bounded number of steps
+        from oracle import lanczos as olz
+        nsteps = 25
+        t0 = time.perf_counter()
+        olz.lanczos_sylvester(prob, t, n, tol=1e-300, max_iter=nsteps)
+        wall = time.perf_counter() - t0
+        res["cpu_oracle"] = {"kind": "oracle", "ms": round(wall * 1e3, 1), "steps": nsteps,
+                             "ms_per_step": round(wall * 1e3 / nsteps, 2),
+                             "sample": f"first {nsteps} of {st['iters']} steps of the oracle's "
+                                       "Alg. 5 at full size, with its assembly pass"}
+        log(f"sylv_1024 cpu oracle: {res['cpu_oracle']}")
     return res
 
 
@@ -423,7 +456,7 @@ def main():
     }
     if not args.no_extra:
         line["other_workloads"] = bench_other_workloads(sy, torch, max(2, args.steps // 2),
-                                                        max(1, args.warmup))
+                                                        max(1, args.warmup), cpu=not args.no_cpu)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(prob, tol)
