@@ -82,6 +82,34 @@ def traffic_from_counters(kernel_hash: str):
     return d.get("traffic_bytes_per_launch")
 
 
+def cg_iteration_seconds(sy, torch, dp, Y, ws, precision, n1=40, n2=140, reps=5):
+    """Wall time of one conjugate-gradient iteration (fused apply + update + the amortised
+    completion checks), measured as the difference between solves stopped after n1 and n2
+    iterations divided by n2 - n1, so that set-up and the final residual cancel.  Mixed
+    precision: one float32 inner run (refine_max 1, inner tolerance below reach)."""
+    def median_time(n):
+        o = sy.SolveOptions(tol=1e-15, precision=precision, max_iter=n, refine_max=1,
+                            inner_tol=1e-30)
+        sy.pcg_solve(dp, Y=Y, opts=o, ws=ws, return_stats=False)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            sy.pcg_solve(dp, Y=Y, opts=o, ws=ws, return_stats=False)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return statistics.median(ts)
+    return (median_time(n2) - median_time(n1)) / (n2 - n1)
+
+
+def cg_iteration_bytes_per_pixel(k: int, elem: int) -> int:
+    """Algorithmic bytes of one CG iteration per pixel: the fused apply reads p_old, z, x and the
+    k(k+1)/2 mixing planes and writes p, q, x; the update reads r, q and the float32
+    block-Jacobi planes and writes r, z."""
+    mk = k * (k + 1) // 2
+    return (6 * k + mk) * elem + 4 * k * elem + mk * 4
+
+
 def cpu_baseline(prob, tol):
     """The oracle (plain float64 CPU PCG with the same block-Jacobi preconditioner and stopping
     rule, including assembly of the operator) on the full workload, timed on this host."""
@@ -205,7 +233,43 @@ def bench_other_workloads(sy, torch, steps, warmup, cpu=False):
     log(f"grad_512: {out['grad_512']}")
     out["sylv_1024"] = bench_sylvester(sy, torch, steps, warmup, cpu=cpu)
     out["healpix_sky_1024"] = bench_sky(sy, torch, steps, warmup, cpu=cpu)
+    out["sweep_1024"] = bench_sweep(sy, torch)
     return out
+
+
+def bench_sweep(sy, torch):
+    """Ten solves over a hyperparameter sweep (kappa +1 %, tau -1 % per step) at 1024^2, k = 3,
+    f = 9, to 1e-8 relative to ||b||: each solve from zero, or warm-started from the previous
+    solution.  Total time and iterations of the sweep."""
+    from workloads import WORKLOADS, sweep_parameters, workload
+    cfg = WORKLOADS["sweep_1024"]
+    prob = workload("sweep_1024")[0]
+    params = sweep_parameters(prob, cfg["steps"], cfg["dk"], cfg["dt"])
+    Y = torch.as_tensor(prob.Y, device="cuda")
+    dp = sy.DeviceProblem.from_numpy(prob)
+    res = {"steps": cfg["steps"], "dk": cfg["dk"], "dt": cfg["dt"]}
+    for label, prec in (("mixed", sy.SYLV_PREC_MIXED), ("f64", sy.SYLV_PREC_F64)):
+        o = sy.SolveOptions(tol=cfg["tol"], precision=prec, stop_ref=sy.SYLV_STOP_B)
+        ws = torch.empty(sy.workspace_bytes([dp], 1, o), dtype=torch.uint8, device="cuda")
+        for mode in ("cold", "warm"):
+            for rep in range(2):            # the first pass warms up
+                X = None
+                iters, worst = 0, 0.0
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for kap, tau in params:
+                    dp.kappa.copy_(torch.as_tensor(kap))
+                    dp.tau.copy_(torch.as_tensor(tau))
+                    X, st = sy.pcg_solve(dp, Y=Y, X0=X if mode == "warm" else None, opts=o,
+                                         ws=ws)
+                    iters += st[0]["iters"]
+                    worst = max(worst, st[0]["relres_true"])
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) * 1e3
+            res[f"{label}_{mode}"] = {"ms": round(ms, 3), "iters_total": iters,
+                                      "relres_true_max": worst}
+            log(f"sweep_1024 {label} {mode}: {res[f'{label}_{mode}']}")
+    return res
 
 
 def bench_sky(sy, torch, steps, warmup, cpu=False):
@@ -310,7 +374,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the 2048^2, batched and differentiable workloads")
-    ap.add_argument("--mode", default="bench", choices=["bench", "pmc", "sylv", "sky"],
+    ap.add_argument("--mode", default="bench", choices=["bench", "pmc", "sylv", "sky", "sweep"],
                     help="pmc: copy + applies + one solve of each precision (counter runs); "
                          "sylv: only the Lanczos-Sylvester workload; sky: only the 12-face "
                          "full-sky workload")
@@ -330,6 +394,9 @@ def main():
     if args.mode == "sylv":
         print(json.dumps({"mode": "sylv", "sylv_1024": bench_sylvester(
             sy, torch, max(2, args.steps // 2), max(1, args.warmup))}), flush=True)
+        return
+    if args.mode == "sweep":
+        print(json.dumps({"mode": "sweep", "sweep_1024": bench_sweep(sy, torch)}), flush=True)
         return
     if args.mode == "sky":
         print(json.dumps({"mode": "sky", "healpix_sky_1024": bench_sky(
@@ -407,6 +474,16 @@ def main():
     gbs64 = b64 / (t64 * 1e-3) / 1e9
     log(f"apply f32 {t32 * 1e3:.2f} us {gbs32:.0f} GB/s; f64 {t64 * 1e3:.2f} us {gbs64:.0f} GB/s")
 
+    # the dominant loop: one CG iteration, timed live for both precisions
+    cg_it = {}
+    for label, prec, elem in (("f32", sy.SYLV_PREC_MIXED, 4), ("f64", sy.SYLV_PREC_F64, 8)):
+        sec = cg_iteration_seconds(sy, torch, dp, Y, ws, prec)
+        nb = cg_iteration_bytes_per_pixel(k, elem) * n_pix
+        cg_it[label] = {"us": round(sec * 1e6, 2), "algorithmic_bytes": nb,
+                        "achieved": round(nb / sec / 1e9, 1), "peak": PEAK_HBM_GBS,
+                        "unit": "GB/s", "frac": round(nb / sec / 1e9 / PEAK_HBM_GBS, 4)}
+        log(f"CG iteration {label}: {cg_it[label]}")
+
     khash = kernel_source_hash()
     traffic = traffic_from_counters(khash)
 
@@ -453,6 +530,9 @@ def main():
             "algorithmic_bytes_per_launch": b32,
         },
         "kernel_source_sha": khash,
+        "roofline_cg_iteration": dict(cg_it, bound="hbm", note=(
+            "fused CG apply + update + amortised completion checks per iteration, from solves "
+            "stopped after 40 and 140 iterations; float32 = the inner runs of the mixed path")),
     }
     if not args.no_extra:
         line["other_workloads"] = bench_other_workloads(sy, torch, max(2, args.steps // 2),

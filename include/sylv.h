@@ -71,6 +71,9 @@ extern "C" {
                                    so border pixels have 2 or 3 (App. A; D of Section 3 with minus
                                    the row sum on the diagonal)                                  */
 
+#define SYLV_STOP_R0 0          /* stopping test relative to the initial residual (Alg. 2)        */
+#define SYLV_STOP_B  1          /* stopping test relative to ||b||                                 */
+
 #define SYLV_PC_NONE   0        /* z = r (plain Alg. 2)                                           */
 #define SYLV_PC_JACOBI 1        /* z = r / diag(G)                                                */
 #define SYLV_PC_BLOCK  2        /* z_p = (G_pp)^-1 r_p, G_pp the k x k block of pixel p           */
@@ -89,7 +92,8 @@ typedef struct sylv_problem {
 } sylv_problem;
 
 typedef struct sylv_pcg_opts {
-    double  tol;           /* stop when ||b - G x||_2 <= tol * ||b - G x0||_2 (Alg. 2 test)       */
+    double  tol;           /* stop when ||b - G x||_2 <= tol * ||b - G x0||_2 (Alg. 2 test; see
+                              stop_ref)                                                           */
     int32_t max_iter;      /* iteration cap of each (inner) conjugate-gradient run               */
     int32_t precision;     /* SYLV_PREC_F64 or SYLV_PREC_MIXED                                   */
     double  inner_tol;     /* mixed: smallest relative reduction asked of one float32 inner run
@@ -101,6 +105,10 @@ typedef struct sylv_pcg_opts {
                               (nrhs must be 2, 4 or 8): s x s Gram matrices in float64, alpha and
                               beta from s x s Cholesky solves, converged columns deflated;
                               0: independent CG per right-hand side                              */
+    int32_t stop_ref;      /* reference of the stopping test: SYLV_STOP_R0 (||b - G x0||, Alg. 2's
+                              test) or SYLV_STOP_B (||b||, for warm starts over a sweep of
+                              hyperparameters); the same when x0 = 0                            */
+    int32_t reserved;      /* 0                                                                   */
 } sylv_pcg_opts;
 
 /* Per-solve result, written by the device into caller memory (DEVICE pointer). */

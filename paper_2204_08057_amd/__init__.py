@@ -15,6 +15,8 @@ from .binding import (  # noqa: F401
     SYLV_PC_NONE,
     SYLV_PREC_F64,
     SYLV_PREC_MIXED,
+    SYLV_STOP_B,
+    SYLV_STOP_R0,
     STATUS_NAMES,
     DeviceProblem,
     LanczosOptions,

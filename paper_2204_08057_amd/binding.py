@@ -32,6 +32,8 @@ SYLV_PREC_F64 = 0
 SYLV_PREC_MIXED = 1
 SYLV_BC_PERIODIC = 0
 SYLV_BC_FACE = 1
+SYLV_STOP_R0 = 0
+SYLV_STOP_B = 1
 SYLV_PC_NONE = 0
 SYLV_PC_JACOBI = 1
 SYLV_PC_BLOCK = 2
@@ -59,7 +61,8 @@ class _Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("inner_tol", ctypes.c_double),
                 ("refine_max", ctypes.c_int32), ("precond", ctypes.c_int32),
-                ("check_every", ctypes.c_int32), ("block", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("stop_ref", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -226,10 +229,11 @@ class SolveOptions:
     precond: int = SYLV_PC_BLOCK
     check_every: int = 0
     block: int = 0
+    stop_ref: int = SYLV_STOP_R0
 
     def c_struct(self) -> _Opts:
         return _Opts(self.tol, self.max_iter, self.precision, self.inner_tol, self.refine_max,
-                     self.precond, self.check_every, self.block)
+                     self.precond, self.check_every, self.block, self.stop_ref, 0)
 
 
 def workspace_bytes(problems: Sequence[DeviceProblem], nrhs: int = 1,

@@ -225,6 +225,7 @@ int check_opts(const sylv_pcg_opts *o) {
     if (o->precond < SYLV_PC_NONE || o->precond > SYLV_PC_BLOCK) { set_err("bad precond"); return SYLV_E_INVALID; }
     if (o->inner_tol < 0.0 || o->inner_tol >= 1.0) { set_err("inner_tol must be in [0, 1)"); return SYLV_E_INVALID; }
     if (o->refine_max < 0 || o->check_every < 0) { set_err("negative refine_max/check_every"); return SYLV_E_INVALID; }
+    if (o->stop_ref != SYLV_STOP_R0 && o->stop_ref != SYLV_STOP_B) { set_err("bad stop_ref"); return SYLV_E_INVALID; }
     return SYLV_OK;
 }
 
@@ -469,7 +470,7 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
         rc = prepare_operator(probs[g], L.prob[g], base, pc, s);
         if (rc) return rc;
     }
-    HIP_TRY(launch_state_init(set, opts->tol, opts->max_iter, s));
+    HIP_TRY(launch_state_init(set, opts->tol, opts->max_iter, opts->stop_ref, s));
     for (int i = 0; i < ninst; ++i) {
         const Inst &I = tab[i];
         HIP_TRY(launch_rhs(I.W, I.Y, I.A, I.f, I.n_pix, I.bext, I.b, k, s));

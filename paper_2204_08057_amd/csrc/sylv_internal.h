@@ -47,7 +47,7 @@ struct DevState {
     int32_t pend;    // stopping decision of the last apply (-1: continue); the apply's own
                      // workgroups must all finish it (x update), so `done` is only set by the
                      // following update kernel
-    int32_t pad;
+    int32_t ref;     // stopping reference: SYLV_STOP_R0 or SYLV_STOP_B
 };
 
 // One solve instance = one (problem, right-hand side) pair.  Pointers are into the caller's
@@ -167,7 +167,8 @@ hipError_t launch_pinit(const InstSet &set, int k, int mixed, double inner_tol, 
 hipError_t launch_cg_apply(const InstSet &set, int k, int mixed, int it, hipStream_t s);
 hipError_t launch_cg_update(const InstSet &set, int k, int mixed, int it, hipStream_t s);
 hipError_t launch_refine_axpy(const InstSet &set, int k, hipStream_t s);
-hipError_t launch_state_init(const InstSet &set, double tol, int max_iter, hipStream_t s);
+hipError_t launch_state_init(const InstSet &set, double tol, int max_iter, int ref,
+                             hipStream_t s);
 hipError_t launch_count_running(const InstSet &set, int inner, int *out, hipStream_t s);
 hipError_t launch_stats(const InstSet &set, void *stats, int mixed, hipStream_t s);
 hipError_t launch_po(const double *kappa, const double *tau, const double *A, const double *W,

@@ -481,7 +481,9 @@ __global__ __launch_bounds__(kBlock) void k_resid_fin(const Inst *__restrict__ t
         st->rr0 = rr;
         st->rr = rr;
         st->rr_prev = rr;
-        st->thresh = st->tol * st->tol * rr;
+        // Alg. 2's test is relative to the initial residual; warm starts over a parameter
+        // sweep may ask for ||b|| instead
+        st->thresh = st->tol * st->tol * (st->ref == SYLV_STOP_B ? s[1] : rr);
         if (!finite_d(rr) || !finite_d(s[1])) { st->status = SYLV_NONFINITE; st->done = 1; }
         else if (rr == 0.0) { st->status = SYLV_OK; st->done = 1; }
     } else if (phase == 2) {
@@ -771,7 +773,8 @@ __global__ __launch_bounds__(kBlock) void k_precond_plain(const Inst *__restrict
 }
 
 // Reset the run states of every instance before a solve.
-__global__ void k_state_init(const Inst *__restrict__ tab, int ninst, double tol, int max_iter) {
+__global__ void k_state_init(const Inst *__restrict__ tab, int ninst, double tol, int max_iter,
+                             int ref) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ninst) return;
     DevState *ss[2] = {tab[i].st, tab[i].st_in};
@@ -780,7 +783,7 @@ __global__ void k_state_init(const Inst *__restrict__ tab, int ninst, double tol
         st->rho[0] = 0.0; st->rho[1] = 0.0; st->rr = 0.0; st->rr0 = 0.0; st->bb = 0.0;
         st->thresh = 0.0; st->tol = tol; st->rel_true = 0.0; st->rr_prev = 0.0;
         st->iter = 0; st->max_iter = max_iter; st->status = SYLV_OK; st->done = 0;
-        st->total_iter = 0; st->outer = 0; st->pend = -1; st->pad = 0;
+        st->total_iter = 0; st->outer = 0; st->pend = -1; st->ref = ref;
     }
 }
 
@@ -1137,9 +1140,10 @@ hipError_t launch_refine_axpy(const InstSet &set, int k, hipStream_t s) {
     });
 }
 
-hipError_t launch_state_init(const InstSet &set, double tol, int max_iter, hipStream_t s) {
+hipError_t launch_state_init(const InstSet &set, double tol, int max_iter, int ref,
+                             hipStream_t s) {
     hipLaunchKernelGGL(k_state_init, dim3(blocks_for(set.ninst, 64)), dim3(64), 0, s, set.table,
-                       set.ninst, tol, max_iter);
+                       set.ninst, tol, max_iter, ref);
     return hipGetLastError();
 }
 

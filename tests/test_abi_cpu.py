@@ -36,7 +36,7 @@ def test_header_struct_sizes_match_binding():
     # int64 x2 + int32 x2 + 4 pointers + int32 x2; double, int32 x2, double, int32 x4;
     # int32 x4 + double x2
     assert ctypes.sizeof(bd._Problem) == 64
-    assert ctypes.sizeof(bd._Opts) == 40
+    assert ctypes.sizeof(bd._Opts) == 48
     assert ctypes.sizeof(bd._Stats) == 32
 
 
@@ -78,7 +78,7 @@ def test_null_pointers_and_bad_options_rejected():
     st = FAKE
     for opts in [bd._Opts(0.0, 10, 0, 0.0, 0, 2, 0, 0), bd._Opts(1e-8, 0, 0, 0.0, 0, 2, 0, 0),
                  bd._Opts(1e-8, 10, 7, 0.0, 0, 2, 0, 0), bd._Opts(1e-8, 10, 0, 0.0, 0, 9, 0, 0),
-                 bd._Opts(1e-8, 10, 1, 2.0, 0, 2, 0, 0)]:
+                 bd._Opts(1e-8, 10, 1, 2.0, 0, 2, 0, 0), bd._Opts(1e-8, 10, 0, 0.0, 0, 2, 0, 0, 2)]:
         rc = L.sylv_pcg_solve(ctypes.byref(p), 1, 1, FAKE, None, FAKE, ctypes.byref(opts), st,
                               FAKE, 1 << 40, None)
         assert rc == bd.SYLV_E_INVALID, L.sylv_last_error()

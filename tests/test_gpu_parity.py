@@ -212,6 +212,37 @@ def test_solve_warm_start_and_zero_rhs():
     assert st0["status"] == 0 and st0["iters"] == 0 and np.all(x0 == 0)
 
 
+@pytest.mark.parametrize("precision", [sy.SYLV_PREC_F64, sy.SYLV_PREC_MIXED])
+def test_sweep_warm_start_saves_iterations(precision):
+    """Repeated solves over a hyperparameter sweep: with the stopping test relative to ||b||, a
+    solve warm-started from the previous parameter's solution meets the same tolerance in fewer
+    iterations and agrees with the dense solution."""
+    prob = make_problem(40, 36, 3, 6, seed=810, noise="hetero")
+    dp = sy.DeviceProblem.from_numpy(prob)
+    Y = dev(prob.Y)
+    say("sweep warm start", precision)
+    tol = 1e-10
+    o = sy.SolveOptions(tol=tol, precision=precision, stop_ref=sy.SYLV_STOP_B)
+    X0, st0 = sy.pcg_solve(dp, Y=Y, opts=o)
+    assert st0[0]["status"] == 0
+    prob.kappa = prob.kappa * 1.01
+    prob.tau = prob.tau * 0.99
+    dp.kappa.copy_(dev(prob.kappa))
+    dp.tau.copy_(dev(prob.tau))
+    Xc, stc = sy.pcg_solve(dp, Y=Y, opts=o)
+    Xw, stw = sy.pcg_solve(dp, Y=Y, X0=X0, opts=o)
+    assert stc[0]["status"] == 0 and stw[0]["status"] == 0
+    assert stw[0]["iters"] < stc[0]["iters"], (stw, stc)
+    xs = osv.solve_dense(prob)
+    bound = 1e-7 if precision == sy.SYLV_PREC_F64 else 1e-6
+    for X in (Xc, Xw):
+        assert rel(host(X).reshape(xs.shape), xs) < bound
+    assert stw[0]["relres_true"] <= tol * 1.01
+    # with x0 = 0 both references give the same threshold, hence the same run
+    Xr, str_ = sy.pcg_solve(dp, Y=Y, opts=sy.SolveOptions(tol=tol, precision=precision))
+    assert str_[0]["iters"] == stc[0]["iters"] and np.array_equal(host(Xr), host(Xc))
+
+
 def test_solve_fully_masked_uses_prior_only():
     prob = make_problem(12, 12, 2, 3, seed=802, mask_frac=0.0)
     prob.W[:] = 0.0

@@ -184,7 +184,16 @@ WORKLOADS = {
     # inside a face, App. A), 4 sources, 9 maps, solved as 12 independent problems in one call
     "healpix_sky_1024": dict(index=6, sizes=[1024] * 12, nrhs=1, k=4, f=9, noise="hetero",
                              boundary="face", tol=1e-8, precision="f64+mixed"),
+    # repeated solves over a hyperparameter sweep (the INLA-style use named as future work in
+    # the conclusion): `steps` solves with kappa_j scaled by (1 + dk)^s and tau_j by (1 - dt)^s
+    "sweep_1024": dict(index=7, ny=1024, nx=1024, k=3, f=9, noise="hetero", tol=1e-8,
+                       steps=10, dk=0.01, dt=0.01, precision="f64+mixed"),
 }
+
+
+def sweep_parameters(prob: Problem, steps: int, dk: float, dt: float):
+    """(kappa, tau) of each solve of a hyperparameter sweep around the drawn values."""
+    return [(prob.kappa * (1.0 + dk) ** s, prob.tau * (1.0 - dt) ** s) for s in range(steps)]
 
 
 def workload(name: str, scale: Optional[int] = None) -> List[Problem]:
