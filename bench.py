@@ -104,10 +104,10 @@ def cg_iteration_seconds(sy, torch, dp, Y, ws, precision, n1=40, n2=140, reps=5)
 
 def cg_iteration_bytes_per_pixel(k: int, elem: int) -> int:
     """Algorithmic bytes of one CG iteration per pixel: the fused apply reads p_old, z, x and the
-    k(k+1)/2 mixing planes and writes p, q, x; the update reads r, q and the float32
-    block-Jacobi planes and writes r, z."""
+    k(k+1)/2 mixing planes and writes p, q, x; the update reads r, q and the bfloat16
+    block-Jacobi factor planes and writes r, z."""
     mk = k * (k + 1) // 2
-    return (6 * k + mk) * elem + 4 * k * elem + mk * 4
+    return (6 * k + mk) * elem + 4 * k * elem + mk * 2
 
 
 def cpu_baseline(prob, tol):

@@ -67,7 +67,7 @@ int chunks_for(int n_pix) { return (n_pix + kChunk - 1) / kChunk; }
 constexpr int kBlockRows = 2;
 
 struct ProbLayout {
-    size_t coef, M64, M32, P64, P32;
+    size_t coef, M64, M32, P64, P32, P16;
 };
 struct InstLayout {
     size_t st, partial, b, r, z, p, p2, q, r32, z32, p32, p32b, q32, d32;
@@ -109,6 +109,7 @@ bool make_layout(const sylv_problem *probs, int nprob, int nrhs, bool solve, Lay
         P.M32 = off;  off = align_up(off + sizeof(float) * mk * n);
         P.P64 = off;  off = align_up(off + sizeof(double) * mk * n);
         P.P32 = off;  off = align_up(off + sizeof(float) * mk * n);
+        P.P16 = off;  off = align_up(off + sizeof(unsigned short) * mk * n);
     }
     const int ninst = solve ? nprob * nrhs : 1;
     L.table = off;   off = align_up(off + sizeof(Inst) * ninst);
@@ -190,6 +191,7 @@ Inst operator_inst(const sylv_problem &p, const ProbLayout &P, char *base, int p
     I.M32 = reinterpret_cast<const float *>(base + P.M32);
     I.P64 = reinterpret_cast<const double *>(base + P.P64);
     I.P32 = reinterpret_cast<const float *>(base + P.P32);
+    I.P16 = reinterpret_cast<const unsigned short *>(base + P.P16);
     return I;
 }
 
@@ -201,7 +203,8 @@ int prepare_operator(const sylv_problem &p, const ProbLayout &P, char *base, int
                          reinterpret_cast<double *>(base + P.M64),
                          reinterpret_cast<float *>(base + P.M32),
                          reinterpret_cast<double *>(base + P.P64),
-                         reinterpret_cast<float *>(base + P.P32), p.k, s));
+                         reinterpret_cast<float *>(base + P.P32),
+                         reinterpret_cast<unsigned short *>(base + P.P16), p.k, s));
     return SYLV_OK;
 }
 

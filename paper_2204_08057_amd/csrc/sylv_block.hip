@@ -84,7 +84,7 @@ __global__ __launch_bounds__(kBlock) void k_bpinit(const Inst *__restrict__ tab,
                 }
             }
         }
-        precond_pixel<T, K>(I0.pc, Pcg(I0), n_pix, valid ? pix : 0, rv[r], zv[r]);
+        precond_cg_pixel<T, K>(I0.pc, Pcg(I0), n_pix, valid ? pix : 0, rv[r], zv[r]);
         if (use) {
 #pragma unroll
             for (int j = 0; j < K; ++j) {
@@ -388,7 +388,7 @@ __global__ __launch_bounds__(kBlock) void k_bupdate(const Inst *__restrict__ tab
         for (int r = 0; r < S; ++r) {
             if (!act[r]) continue;
             const Inst &I = tab[G.inst0 + r];
-            precond_pixel<T, K>(I0.pc, Pcg(I0), n_pix, pix, rv[r], zv[r]);
+            precond_cg_pixel<T, K>(I0.pc, Pcg(I0), n_pix, pix, rv[r], zv[r]);
 #pragma unroll
             for (int j = 0; j < K; ++j) Sel<T>::z(I)[(size_t)j * n_pix + pix] = zv[r][j];
         }

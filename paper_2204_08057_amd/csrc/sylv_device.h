@@ -128,6 +128,22 @@ __device__ __forceinline__ void st4(GAS float *p, const float (&v)[4]) {
     reinterpret_cast<GAS fvec4 *>(p)[0] = a;
 }
 
+// bfloat16 planes (the preconditioner factor of CG runs): the top 16 bits of a float32.
+typedef unsigned short hvec4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float bf16_value(unsigned short h) {
+    return __uint_as_float((unsigned)h << 16);
+}
+// float32 -> bfloat16, rounding to nearest with ties to even; NaN stays NaN.
+__device__ __forceinline__ unsigned short bf16_round(float v) {
+    const unsigned u = __float_as_uint(v);
+    if (v != v) return (unsigned short)((u >> 16) | 0x40u);
+    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ void ld4(const GAS unsigned short *p, float (&v)[4]) {
+    const hvec4 a = reinterpret_cast<const GAS hvec4 *>(p)[0];
+    v[0] = bf16_value(a.x); v[1] = bf16_value(a.y); v[2] = bf16_value(a.z); v[3] = bf16_value(a.w);
+}
+
 // Field selectors by precision (all return global-address-space pointers).
 template <typename T> struct Sel;
 template <> struct Sel<double> {
@@ -141,10 +157,12 @@ template <> struct Sel<double> {
     static __device__ __forceinline__ DevState *st(const Inst &I) { return I.st; }
 };
 
-// Preconditioner blocks used inside CG runs: float32 for both precisions.  The preconditioner
-// only has to be fixed and positive definite, so rounding its entries does not change what the
-// solve converges to, and it halves their traffic in float64 runs.
-__device__ __forceinline__ const GAS float *Pcg(const Inst &I) { return gp(I.P32); }
+// Preconditioner of CG runs (both precisions): the block inverse as Pinv = G^T G with
+// G = L^-1 (L the Cholesky factor of the diagonal block), G stored in bfloat16.  A
+// preconditioner only has to be fixed and positive definite; G^T G stays so whatever the
+// rounding of G's entries (its diagonal stays positive), so the solve converges to the same
+// solution while reading a quarter of the bytes of float64 blocks.
+__device__ __forceinline__ const GAS unsigned short *Pcg(const Inst &I) { return gp(I.P16); }
 template <> struct Sel<float> {
     static __device__ __forceinline__ const GAS float *M(const Inst &I) { return gp(I.M32); }
     static __device__ __forceinline__ const GAS float *P(const Inst &I) { return gp(I.P32); }
@@ -182,41 +200,84 @@ __device__ __forceinline__ void precond_pixel(int pc, const GAS PT *P, int n_pix
     }
 }
 
-template <typename T, int K, typename PT>
-__device__ __forceinline__ void precond_vec4(int pc, const GAS PT *P, int n_pix, int p0,
-                                             const T (&r)[K][4], T (&z)[K][4]) {
+// z = G^T (G r) at one pixel from the bfloat16 factor planes (block kind: G[a][c], a >= c, at
+// plane pidx(c, a); Jacobi kind: one plane per component holding 1 / diagonal).
+template <typename T, int K>
+__device__ __forceinline__ void precond_cg_pixel(int pc, const GAS unsigned short *F, int n_pix,
+                                                 int pix, const T (&r)[K], T (&z)[K]) {
     if (pc == SYLV_PC_BLOCK) {
         constexpr int MK = K * (K + 1) / 2;
-        T pm[MK][4];
+        T g[MK];
 #pragma unroll
-        for (int e = 0; e < MK; ++e) {
-            PT tmp[4];
-            ld4(P + (size_t)e * n_pix + p0, tmp);
+        for (int e = 0; e < MK; ++e) g[e] = (T)bf16_value(F[(size_t)e * n_pix + pix]);
+        T t[K];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) pm[e][q] = (T)tmp[q];
+        for (int a = 0; a < K; ++a) {
+            T s = 0;
+#pragma unroll
+            for (int c = 0; c <= a; ++c) s += g[pidx<K>(c, a)] * r[c];
+            t[a] = s;
         }
 #pragma unroll
-        for (int j = 0; j < K; ++j)
+        for (int c = 0; c < K; ++c) {
+            T s = 0;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
+            for (int a = c; a < K; ++a) s += g[pidx<K>(c, a)] * t[a];
+            z[c] = s;
+        }
+    } else if (pc == SYLV_PC_JACOBI) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) z[j] = (T)bf16_value(F[(size_t)j * n_pix + pix]) * r[j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < K; ++j) z[j] = r[j];
+    }
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void precond_cg_vec4(int pc, const GAS unsigned short *F, int n_pix,
+                                                int p0, const T (&r)[K][4], T (&z)[K][4]) {
+    if (pc == SYLV_PC_BLOCK) {
+        constexpr int MK = K * (K + 1) / 2;
+        T g[MK][4];
+#pragma unroll
+        for (int e = 0; e < MK; ++e) {
+            float tmp[4];
+            ld4(F + (size_t)e * n_pix + p0, tmp);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) g[e][q] = (T)tmp[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            T t[K];
+#pragma unroll
+            for (int a = 0; a < K; ++a) {
                 T s = 0;
 #pragma unroll
-                for (int i = 0; i < K; ++i) s += pm[pidx<K>(j, i)][e] * r[i][e];
-                z[j][e] = s;
+                for (int c = 0; c <= a; ++c) s += g[pidx<K>(c, a)][q] * r[c][q];
+                t[a] = s;
             }
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                T s = 0;
+#pragma unroll
+                for (int a = c; a < K; ++a) s += g[pidx<K>(c, a)][q] * t[a];
+                z[c][q] = s;
+            }
+        }
     } else if (pc == SYLV_PC_JACOBI) {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            PT d[4];
-            ld4(P + (size_t)j * n_pix + p0, d);
+            float d[4];
+            ld4(F + (size_t)j * n_pix + p0, d);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) z[j][e] = (T)d[e] * r[j][e];
+            for (int q = 0; q < 4; ++q) z[j][q] = (T)d[q] * r[j][q];
         }
     } else {
 #pragma unroll
         for (int j = 0; j < K; ++j)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) z[j][e] = r[j][e];
+            for (int q = 0; q < 4; ++q) z[j][q] = r[j][q];
     }
 }
 

@@ -71,6 +71,7 @@ struct Inst {
     const float *M32;
     const double *P64;   // packed preconditioner blocks
     const float *P32;
+    const unsigned short *P16;   // bfloat16 factor G = L^-1 of the blocks (CG runs)
     // float64 vectors.  The search direction is double-buffered: the apply of iteration i reads
     // the previous direction from p[i & 1] (including stencil halos owned by other workgroups)
     // and writes the new one to p[(i + 1) & 1], so no workgroup overwrites a value another one
@@ -151,7 +152,7 @@ hipError_t launch_coef(const double *kappa, const double *tau, int k, int ny, in
                        double *coef, hipStream_t s);
 hipError_t launch_setup(const double *W, const double *A, int f, int ny, int nx, int bc,
                         const double *coef, int pc, double *M64, float *M32, double *P64,
-                        float *P32, int k, hipStream_t s);
+                        float *P32, unsigned short *P16, int k, hipStream_t s);
 hipError_t launch_rhs(const double *W, const double *Y, const double *A, int f, int n_pix,
                       const double *bext, double *b, int k, hipStream_t s);
 hipError_t launch_apply_plain(const Inst *table0, int k, int dtype, int rows, int bc, int ny,

@@ -66,7 +66,8 @@ __global__ __launch_bounds__(kBlock) void k_setup(const double *__restrict__ W,
                                                   int nx, int bc,
                                                   const double *__restrict__ coef, int pc,
                                                   double *__restrict__ M64, float *__restrict__ M32,
-                                                  double *__restrict__ P64, float *__restrict__ P32) {
+                                                  double *__restrict__ P64, float *__restrict__ P32,
+                                                  unsigned short *__restrict__ P16) {
     constexpr int MK = K * (K + 1) / 2;
     const int n_pix = ny * nx;
     const int pix = blockIdx.x * kBlock + threadIdx.x;
@@ -108,6 +109,7 @@ __global__ __launch_bounds__(kBlock) void k_setup(const double *__restrict__ W,
             const double d = 1.0 / (qd[j] + m[pidx<K>(j, j)]);
             P64[(size_t)j * n_pix + pix] = d;
             P32[(size_t)j * n_pix + pix] = (float)d;
+            P16[(size_t)j * n_pix + pix] = bf16_round((float)d);
         }
     } else if (pc == SYLV_PC_BLOCK) {
         double a[K][K], l[K][K];
@@ -136,7 +138,8 @@ __global__ __launch_bounds__(kBlock) void k_setup(const double *__restrict__ W,
                 l[r][c] = v * inv;
             }
         }
-        // inverse = L^-T L^-1, column by column
+        // inverse = L^-T L^-1, column by column; y = L^-1 e_col is column col of G = L^-1
+        const double bad = ok ? 0.0 : __builtin_nan("");
         double inv[K][K];
 #pragma unroll
         for (int col = 0; col < K; ++col) {
@@ -149,6 +152,9 @@ __global__ __launch_bounds__(kBlock) void k_setup(const double *__restrict__ W,
                 y[r] = v / l[r][r];
             }
 #pragma unroll
+            for (int r = col; r < K; ++r)
+                P16[(size_t)pidx<K>(col, r) * n_pix + pix] = bf16_round((float)(y[r] + bad));
+#pragma unroll
             for (int r = K - 1; r >= 0; --r) {
                 double v = y[r];
 #pragma unroll
@@ -156,7 +162,6 @@ __global__ __launch_bounds__(kBlock) void k_setup(const double *__restrict__ W,
                 inv[r][col] = v / l[r][r];
             }
         }
-        const double bad = ok ? 0.0 : __builtin_nan("");
 #pragma unroll
         for (int i = 0; i < K; ++i)
 #pragma unroll
@@ -543,7 +548,7 @@ __global__ __launch_bounds__(kBlock) void k_update(const Inst *__restrict__ tab,
     GAS T *r = Sel<T>::r(I);
     GAS T *z = Sel<T>::z(I);
     const GAS T *q = Sel<T>::q(I);
-    const GAS float *P = Pcg(I);
+    const GAS unsigned short *P = Pcg(I);
     const int pc = I.pc;
     const int p0 = chunk * kChunk + threadIdx.x * 4;
     const bool vec = I.vec4 && p0 + 4 <= n_pix;
@@ -585,7 +590,7 @@ __global__ __launch_bounds__(kBlock) void k_update(const Inst *__restrict__ tab,
                 for (int e = 0; e < 4; ++e) rv[j][e] -= alpha * qv[j][e];
                 st4(r + (size_t)j * n_pix + p0, rv[j]);
             }
-            precond_vec4<T, K>(pc, P, n_pix, p0, rv, zv);
+            precond_cg_vec4<T, K>(pc, P, n_pix, p0, rv, zv);
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 st4(z + (size_t)j * n_pix + p0, zv[j]);
@@ -605,7 +610,7 @@ __global__ __launch_bounds__(kBlock) void k_update(const Inst *__restrict__ tab,
                     rs[j] = r[o] - alpha * q[o];
                     r[o] = rs[j];
                 }
-                precond_pixel<T, K>(pc, P, n_pix, pix, rs, zs);
+                precond_cg_pixel<T, K>(pc, P, n_pix, pix, rs, zs);
 #pragma unroll
                 for (int j = 0; j < K; ++j) {
                     z[(size_t)j * n_pix + pix] = zs[j];
@@ -657,7 +662,7 @@ __global__ __launch_bounds__(kBlock) void k_pinit(const Inst *__restrict__ tab,
     const GAS double *r64 = gp(I.r);
     GAS T *rr_out = Sel<T>::r(I);
     GAS T *z = Sel<T>::z(I);
-    const GAS float *P = Pcg(I);
+    const GAS unsigned short *P = Pcg(I);
     const int pc = I.pc;
     const int p0 = chunk * kChunk + threadIdx.x * 4;
     double rz = 0.0, rr = 0.0;
@@ -676,7 +681,7 @@ __global__ __launch_bounds__(kBlock) void k_pinit(const Inst *__restrict__ tab,
                 st4(gp(I.d32) + o, zero4);
             }
         }
-        precond_vec4<T, K>(pc, P, n_pix, p0, rv, zv);
+        precond_cg_vec4<T, K>(pc, P, n_pix, p0, rv, zv);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             st4(z + (size_t)j * n_pix + p0, zv[j]);
@@ -699,7 +704,7 @@ __global__ __launch_bounds__(kBlock) void k_pinit(const Inst *__restrict__ tab,
                     gp(I.d32)[o] = 0.0f;
                 }
             }
-            precond_pixel<T, K>(pc, P, n_pix, pix, rv, zv);
+            precond_cg_pixel<T, K>(pc, P, n_pix, pix, rv, zv);
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 z[(size_t)j * n_pix + pix] = zv[j];
@@ -1019,12 +1024,12 @@ hipError_t launch_coef(const double *kappa, const double *tau, int k, int ny, in
 
 hipError_t launch_setup(const double *W, const double *A, int f, int ny, int nx, int bc,
                         const double *coef, int pc, double *M64, float *M32, double *P64,
-                        float *P32, int k, hipStream_t s) {
+                        float *P32, unsigned short *P16, int k, hipStream_t s) {
     const long n_pix = (long)ny * nx;
     return dispatch_k(k, [&](auto tag) {
         constexpr int K = decltype(tag)::value;
         hipLaunchKernelGGL((k_setup<K>), dim3(blocks_for(n_pix, kBlock)), dim3(kBlock), 0, s, W,
-                           A, f, ny, nx, bc, coef, pc, M64, M32, P64, P32);
+                           A, f, ny, nx, bc, coef, pc, M64, M32, P64, P32, P16);
         return hipGetLastError();
     });
 }
