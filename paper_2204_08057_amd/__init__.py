@@ -25,6 +25,7 @@ from .binding import (  # noqa: F401
     SylvError,
     SylvSolve,
     apply,
+    apply_launcher,
     declared_symbols,
     lanczos_solve,
     lanczos_workspace_bytes,

@@ -280,6 +280,31 @@ def apply(problem: DeviceProblem, X, ws=None, prepared: bool = False, out=None):
     return Y
 
 
+def apply_launcher(problem: DeviceProblem, X, Y, ws):
+    """A zero-argument callable that launches Y = G(X) on the current stream, with every
+    argument marshalled once: for tight loops of applies on an operator already prepared in
+    `ws` (the per-call cost is one foreign-function call).  X and Y as for `apply`."""
+    torch = _torch()
+    if X.dtype not in (torch.float64, torch.float32) or Y.dtype != X.dtype:
+        raise ValueError("X and Y must both be float64 or both float32")
+    if X.shape != Y.shape or X.shape[-2:] != (problem.k, problem.n_pix):
+        raise ValueError(f"X, Y shapes {tuple(X.shape)}, {tuple(Y.shape)} != (..., {problem.k}, "
+                         f"{problem.n_pix})")
+    dtype = SYLV_F64 if X.dtype == torch.float64 else SYLV_F32
+    nrhs = 1 if X.dim() == 2 else X.shape[0]
+    ps = problem.c_struct()
+    fn = lib().sylv_apply
+    args = (ctypes.byref(ps), dtype, _ptr(X), _ptr(Y), nrhs, 1, _ptr(ws), ws.numel(), _stream())
+
+    def launch():
+        rc = fn(*args)
+        if rc:
+            _check(rc)
+
+    launch.keep = (ps, X, Y, ws)   # the marshalled pointers stay valid while the callable lives
+    return launch
+
+
 def precond(problem: DeviceProblem, R, kind: int = SYLV_PC_BLOCK, ws=None,
             prepared: bool = False):
     torch = _torch()

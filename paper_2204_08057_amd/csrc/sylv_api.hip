@@ -237,6 +237,7 @@ int check_opts(const sylv_pcg_opts *o) {
 // events per host thread, created on first use and kept for the life of the thread.
 struct HostFlags {
     static constexpr int kSlots = 4;
+    static constexpr int kStride = 4;   // ints per slot (the completion report of k_count_running)
     int *pinned = nullptr;
     hipEvent_t ev[kSlots] = {};
     bool ready = false;
@@ -252,7 +253,8 @@ int host_flags(HostFlags *&out) {
     HostFlags &f = g_flags;
     if (!f.ready) {
         HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&f.pinned),
-                              sizeof(int) * HostFlags::kSlots, hipHostMallocDefault));
+                              sizeof(int) * HostFlags::kSlots * HostFlags::kStride,
+                              hipHostMallocDefault));
         for (int i = 0; i < HostFlags::kSlots; ++i)
             HIP_TRY(hipEventCreateWithFlags(&f.ev[i], hipEventDisableTiming));
         f.ready = true;
@@ -263,15 +265,46 @@ int host_flags(HostFlags *&out) {
 
 // Enqueue "how many runs are unfinished" into slot `slot` (inner = 1: the float32 inner runs).
 int post_count(const InstSet &set, int inner, HostFlags *f, int slot, hipStream_t s) {
-    HIP_TRY(launch_count_running(set, inner, f->pinned + slot, s));
+    HIP_TRY(launch_count_running(set, inner, f->pinned + slot * HostFlags::kStride, s));
     HIP_TRY(hipEventRecord(f->ev[slot], s));
+    return SYLV_OK;
+}
+
+struct Report {
+    int running;   // runs not finished
+    int iter;      // latest iteration tested among them
+    double gap;    // max log2(rr / thresh) among them (0: unknown)
+};
+
+int wait_report(HostFlags *f, int slot, Report &r) {
+    HIP_TRY(hipEventSynchronize(f->ev[slot]));
+    const volatile int *p = f->pinned + slot * HostFlags::kStride;
+    r.running = p[0];
+    r.iter = p[1];
+    r.gap = p[2] / 256.0;
     return SYLV_OK;
 }
 
 int wait_count(HostFlags *f, int slot, int &value) {
     HIP_TRY(hipEventSynchronize(f->ev[slot]));
-    value = *reinterpret_cast<volatile int *>(f->pinned + slot);
+    value = *reinterpret_cast<volatile int *>(f->pinned + slot * HostFlags::kStride);
     return SYLV_OK;
+}
+
+// Iterations still to queue after those already queued (indices below `queued`), from the last
+// two completion reports: the gap to the threshold shrinks about linearly in log scale, so the
+// slowest run stops near iteration iter + gap / rate.  Returns `chunk` while no rate is known,
+// 0 when the queued iterations should already finish every run, and otherwise the estimate plus
+// a margin, never more than `chunk`.  A short estimate costs one more host round trip, an
+// over-estimate a few early-exit launches; the result of the solve does not depend on it.
+int next_batch(const Report &prev, const Report &cur, bool have_prev, int queued, int chunk) {
+    if (!have_prev || cur.iter <= prev.iter || cur.gap <= 0.0 || prev.gap <= cur.gap) return chunk;
+    const double rate = (prev.gap - cur.gap) / (cur.iter - prev.iter);
+    const double stop = cur.iter + cur.gap / rate;
+    const double left = stop - (queued - 1);
+    if (left <= 0.0) return 0;
+    const int n = (int)ceil(left * 1.1) + 2;
+    return n < chunk ? n : chunk;
 }
 
 // Conjugate-gradient iterations in batches of `chunk`, with one batch always queued ahead of the
@@ -282,21 +315,43 @@ int wait_count(HostFlags *f, int slot, int &value) {
 int run_cg_loop(const InstSet &set, int k, int mixed, int chunk, int max_iter, HostFlags *f,
                 hipStream_t s) {
     int it = 0, rc;
-    auto enqueue_batch = [&](int slot) -> int {
-        for (int c = 0; c < chunk && it <= max_iter; ++c, ++it) {
+    // batches queued and not yet waited for, oldest first, in slots 0 and 1 used alternately
+    int pend[2], npend = 0, next_slot = 0;
+    auto enqueue_batch = [&](int n) -> int {
+        for (int c = 0; c < n && it <= max_iter; ++c, ++it) {
             HIP_TRY(launch_cg_apply(set, k, mixed, it, s));
             HIP_TRY(launch_cg_update(set, k, mixed, it, s));
         }
+        pend[npend++] = next_slot;
+        const int slot = next_slot;
+        next_slot ^= 1;
         return post_count(set, mixed, f, slot, s);
     };
-    if ((rc = enqueue_batch(0))) return rc;
-    for (int cur = 0;; cur ^= 1) {
-        const bool more = it <= max_iter;
-        if (more && (rc = enqueue_batch(cur ^ 1))) return rc;
-        int running = 0;
-        if ((rc = wait_count(f, cur, running))) return rc;
-        if (running == 0 || !more) {
-            if (more && (rc = wait_count(f, cur ^ 1, running))) return rc;   // drain the lookahead
+    Report prev{}, cur{};
+    bool have_prev = false, have_cur = false;
+    if ((rc = enqueue_batch(chunk))) return rc;
+    for (;;) {
+        // keep one batch queued ahead of the report being waited for, sized by the estimate
+        if (it <= max_iter && npend < 2) {
+            int n = have_cur ? next_batch(prev, cur, have_prev, it, chunk) : chunk;
+            if (npend == 0 && n < 4) n = 4;   // the estimate fell short: the run goes on
+            if (n > 0 && (rc = enqueue_batch(n))) return rc;
+        }
+        if (npend == 0) break;   // every iteration up to max_iter has been waited for
+        const int slot = pend[0];
+        pend[0] = pend[1];
+        --npend;
+        prev = cur;
+        have_prev = have_cur;
+        if ((rc = wait_report(f, slot, cur))) return rc;
+        have_cur = true;
+        if (cur.running == 0) {
+            while (npend > 0) {   // drain the lookahead (its kernels returned at once)
+                Report r;
+                if ((rc = wait_report(f, pend[0], r))) return rc;
+                pend[0] = pend[1];
+                --npend;
+            }
             break;
         }
     }
@@ -830,7 +885,7 @@ int lanczos_impl(const sylv_sep_problem *p, const double *Y, double *X,
     int it = 1;
     auto enqueue_batch = [&](int slot) -> int {
         for (int c = 0; c < chunk && it <= o->max_iter; ++c, ++it) HIP_TRY(lz_launch_step(a, it, s));
-        HIP_TRY(lz_launch_flag(a, fl->pinned + slot, s));
+        HIP_TRY(lz_launch_flag(a, fl->pinned + slot * HostFlags::kStride, s));
         HIP_TRY(hipEventRecord(fl->ev[slot], s));
         return SYLV_OK;
     };

@@ -793,17 +793,26 @@ __global__ void k_state_init(const Inst *__restrict__ tab, int ninst, double tol
 }
 
 // Number of instances whose run (outer or inner) has not finished.
+// Completion report for the host: out[0] = runs not finished; out[1] = the latest iteration
+// tested among them; out[2] = max over them of log2(rr / thresh) in 1/256 units (how far the
+// slowest run still is from its threshold, rounded up, 0 when unknown), from which the host sizes
+// the next batch of iterations.
 __global__ void k_count_running(const Inst *__restrict__ tab, int ninst, int inner,
                                 int *__restrict__ out) {
-    __shared__ int cnt;
-    if (threadIdx.x == 0) cnt = 0;
+    __shared__ int cnt, last, gap;
+    if (threadIdx.x == 0) { cnt = 0; last = 0; gap = 0; }
     __syncthreads();
     for (int i = threadIdx.x; i < ninst; i += blockDim.x) {
         const DevState *st = inner ? tab[i].st_in : tab[i].st;
-        if (!st->done) atomicAdd(&cnt, 1);
+        if (st->done) continue;
+        atomicAdd(&cnt, 1);
+        atomicMax(&last, st->iter);
+        const double q = st->rr / st->thresh;
+        if (st->thresh > 0.0 && q > 1.0 && q < 1e300)
+            atomicMax(&gap, (int)fmin(ceil(256.0 * log2(q)), 1e9));
     }
     __syncthreads();
-    if (threadIdx.x == 0) out[0] = cnt;
+    if (threadIdx.x == 0) { out[0] = cnt; out[1] = last; out[2] = gap; }
 }
 
 __global__ void k_stats(const Inst *__restrict__ tab, int ninst, sylv_pcg_stats *__restrict__ out,

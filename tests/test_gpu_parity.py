@@ -93,6 +93,27 @@ def test_apply_several_rhs_prepared():
         assert rel(Y1[r], op.apply(prob, X[r])) < 1e-13
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_apply_launcher_matches_apply(dtype):
+    """The pre-marshalled launcher runs the same entry point: bitwise the apply's output, also
+    when launched repeatedly."""
+    say("apply launcher", dtype)
+    prob = make_problem(40, 72, 3, 6, seed=301, noise="hetero")
+    X = random_maps(prob, 8, nrhs=2)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    dp = sy.DeviceProblem.from_numpy(prob)
+    ws = sy.binding.prepare(dp, sy.SYLV_PC_NONE)
+    Xd = dev(X, tdt)
+    ref = host(sy.apply(dp, Xd, ws=ws, prepared=True))
+    Y = torch.empty_like(Xd)
+    launch = sy.apply_launcher(dp, Xd, Y, ws)
+    for _ in range(3):
+        launch()
+    assert np.array_equal(host(Y), ref)
+    with pytest.raises(ValueError):
+        sy.apply_launcher(dp, Xd, torch.empty(3, 5, dtype=tdt, device="cuda"), ws)
+
+
 @pytest.mark.parametrize("kind", [sy.SYLV_PC_BLOCK, sy.SYLV_PC_JACOBI, sy.SYLV_PC_NONE])
 @pytest.mark.parametrize("ny,nx,k,f", [(1, 1, 3, 4), (2, 3, 2, 3), (24, 20, 4, 9),
                                        (13, 9, 8, 5)])
