@@ -162,11 +162,10 @@ def summarize(ms, st):
             "all_ok": all(s["status"] == 0 for s in st)}
 
 
-def bench_other_workloads(sy, torch, steps, warmup, cpu=False):
-    """The other workloads of the solver, timed the same way (not the headline value)."""
-    from workloads import WORKLOADS, workload
-    out = {}
-    # 2048^2, k = 4, f = 9, 10% masked pixels: mixed precision vs float64
+def bench_masked(sy, torch, steps, warmup):
+    """2048^2, k = 4, f = 9, 10 % masked pixels (beyond the last-level cache): mixed precision vs
+    float64 solves and the stand-alone applies."""
+    from workloads import workload
     prob = workload("masked_2048")[0]
     dp = sy.DeviceProblem.from_numpy(prob)
     Y = torch.as_tensor(prob.Y, device="cuda")
@@ -187,8 +186,13 @@ def bench_other_workloads(sy, torch, steps, warmup, cpu=False):
         res[label] = {"us": round(t * 1e3, 2), "algorithmic_bytes": nb,
                       "gbs": round(nb / (t * 1e-3) / 1e9, 1)}
         log(f"masked_2048 {label}: {res[label]}")
-    out["masked_2048"] = res
-    del dp, Y, ws_app, X64
+    return res
+
+
+def bench_other_workloads(sy, torch, steps, warmup, cpu=False):
+    """The other workloads of the solver, timed the same way (not the headline value)."""
+    from workloads import WORKLOADS, workload
+    out = {"masked_2048": bench_masked(sy, torch, steps, warmup)}
     # 8 uneven grids x 8 perturbation-optimisation right-hand sides (64 posterior samples)
     probs = workload("batched_8grids")
     nrhs = WORKLOADS["batched_8grids"]["nrhs"]
@@ -378,10 +382,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the 2048^2, batched and differentiable workloads")
-    ap.add_argument("--mode", default="bench", choices=["bench", "pmc", "sylv", "sky", "sweep"],
+    ap.add_argument("--mode", default="bench",
+                    choices=["bench", "pmc", "sylv", "sky", "sweep", "masked"],
                     help="pmc: copy + applies + one solve of each precision (counter runs); "
                          "sylv: only the Lanczos-Sylvester workload; sky: only the 12-face "
-                         "full-sky workload")
+                         "full-sky workload; sweep: only the hyperparameter sweep; masked: only "
+                         "the 2048^2 masked workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver has no "
@@ -398,6 +404,10 @@ def main():
     if args.mode == "sylv":
         print(json.dumps({"mode": "sylv", "sylv_1024": bench_sylvester(
             sy, torch, max(2, args.steps // 2), max(1, args.warmup))}), flush=True)
+        return
+    if args.mode == "masked":
+        print(json.dumps({"mode": "masked", "masked_2048": bench_masked(
+            sy, torch, args.steps, args.warmup)}), flush=True)
         return
     if args.mode == "sweep":
         print(json.dumps({"mode": "sweep", "sweep_1024": bench_sweep(sy, torch)}), flush=True)

@@ -80,7 +80,7 @@ extern "C" {
 
 /* One posterior-mean system (Section 2, Section 3).  Host struct of device pointers. */
 typedef struct sylv_problem {
-    int64_t ny, nx;        /* periodic grid, n_pix = ny * nx                                     */
+    int64_t ny, nx;        /* grid, n_pix = ny * nx < 2^29 (else SYLV_E_INVALID)                 */
     int32_t k;             /* components (the paper's m: sources)                                */
     int32_t f;             /* maps (the paper's n: frequencies)                                  */
     const double *kappa;   /* [k]  kappa_j >= 0   (prior range parameter)                        */
@@ -205,7 +205,7 @@ int sylv_pcg_backward(const sylv_problem *prob, const double *Y, const double *X
 
 /* Host struct of device pointers. */
 typedef struct sylv_sep_problem {
-    int64_t ny, nx;        /* periodic grid, n_pix = ny * nx                                     */
+    int64_t ny, nx;        /* grid, n_pix = ny * nx < 2^29 (else SYLV_E_INVALID)                 */
     int32_t k;             /* components (the paper's m), 1..8                                   */
     int32_t f;             /* maps (the paper's n), 1..16                                        */
     double  kappa;         /* common kappa >= 0 (host value; 0 = the paper's D^2 prior)          */

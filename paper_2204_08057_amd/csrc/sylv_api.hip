@@ -88,7 +88,7 @@ bool check_problem(const sylv_problem *p, int idx) {
     if (p->k < 1 || p->k > kMaxK) { set_err("problem %d: k=%d outside [1, %d]", idx, p->k, kMaxK); return false; }
     if (p->f < 1 || p->f > kMaxF) { set_err("problem %d: f=%d outside [1, %d]", idx, p->f, kMaxF); return false; }
     if (p->ny < 1 || p->nx < 1) { set_err("problem %d: grid %lld x %lld", idx, (long long)p->ny, (long long)p->nx); return false; }
-    if (p->ny * p->nx >= (int64_t)1 << 30) { set_err("problem %d: n_pix too large", idx); return false; }
+    if (p->ny * p->nx >= (int64_t)1 << 29) { set_err("problem %d: n_pix >= 2^29", idx); return false; }
     if (!p->kappa || !p->tau || !p->A || !p->W) { set_err("problem %d: null parameter pointer", idx); return false; }
     if (p->boundary != SYLV_BC_PERIODIC && p->boundary != SYLV_BC_FACE) { set_err("problem %d: boundary %d", idx, p->boundary); return false; }
     return true;
@@ -600,7 +600,7 @@ bool check_sep(const sylv_sep_problem *p) {
     if (p->k < 1 || p->k > kMaxK) { set_err("k=%d outside [1, %d]", p->k, kMaxK); return false; }
     if (p->f < 1 || p->f > kMaxF) { set_err("f=%d outside [1, %d]", p->f, kMaxF); return false; }
     if (p->ny < 1 || p->nx < 1) { set_err("grid %lld x %lld", (long long)p->ny, (long long)p->nx); return false; }
-    if (p->ny * p->nx >= (int64_t)1 << 30) { set_err("n_pix too large"); return false; }
+    if (p->ny * p->nx >= (int64_t)1 << 29) { set_err("n_pix >= 2^29"); return false; }
     if (!(p->kappa >= 0.0) || !isfinite(p->kappa)) { set_err("kappa must be finite and >= 0"); return false; }
     if (!p->tau || !p->A || !p->t || !p->n) { set_err("null parameter pointer"); return false; }
     if (p->boundary != SYLV_BC_PERIODIC && p->boundary != SYLV_BC_FACE) { set_err("boundary %d", p->boundary); return false; }

@@ -24,6 +24,95 @@ __device__ __forceinline__ int wrapi(int v, int n) {
     return v;
 }
 
+// Periodic wrap of v into [0, n) for the stencil kernels, whose indices lie at most 66 outside:
+// one conditional step on grids of 128 or more, the loop on smaller ones (a uniform branch).
+__device__ __forceinline__ int wrapf(int v, int n) {
+    if (n >= 128) {
+        v += (v < 0) ? n : 0;
+        v -= (v >= n) ? n : 0;
+        return v;
+    }
+    return wrapi(v, n);
+}
+
+// Plane access through buffer resources.  A plane (n elements of T at a base that is the same
+// for the whole wavefront: callers build plane pointers from workgroup-uniform values only) is
+// described by a resource held in scalar registers; each access gives a 32-bit byte offset per
+// lane, so no 64-bit address arithmetic is spent per access, and the hardware range check
+// returns 0 for a load (drops a store) outside [0, n).  Every problem has fewer than 2^29
+// pixels, so n * sizeof(T) < 2^32.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+constexpr int kRsrcWord3 = 0x00020000;   // raw buffer, 32-bit data format (gfx9 family)
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const GAS T *plane, uint32_t n) {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)uniform_u64((uint64_t)plane), 0,
+                                             (int)(n * (uint32_t)sizeof(T)), kRsrcWord3);
+}
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+// Vector elements are read by value (a.x) and converted with __uint_as_float / join_f64: this
+// compiler mis-reads __builtin_bit_cast of a vector element expression (it reads element 0).
+// float64 from / to its two 32-bit halves (low word first in memory)
+__device__ __forceinline__ double join_f64(unsigned lo, unsigned hi) {
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ unsigned lo_f64(double v) {
+    return (unsigned)__builtin_bit_cast(unsigned long long, v);
+}
+__device__ __forceinline__ unsigned hi_f64(double v) {
+    return (unsigned)(__builtin_bit_cast(unsigned long long, v) >> 32);
+}
+
+__device__ __forceinline__ float bld(const GAS float *plane, uint32_t n, uint32_t i) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(plane_rsrc(plane, n), i * 4u, 0, 0));
+}
+__device__ __forceinline__ double bld(const GAS double *plane, uint32_t n, uint32_t i) {
+    const u32x2 a = __builtin_amdgcn_raw_buffer_load_b64(plane_rsrc(plane, n), i * 8u, 0, 0);
+    return join_f64(a.x, a.y);
+}
+__device__ __forceinline__ void bst(GAS float *plane, uint32_t n, uint32_t i, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), plane_rsrc((const GAS float *)plane, n), i * 4u, 0, 0);
+}
+__device__ __forceinline__ void bst(GAS double *plane, uint32_t n, uint32_t i, double v) {
+    const u32x2 a = {lo_f64(v), hi_f64(v)};
+    __builtin_amdgcn_raw_buffer_store_b64(a, plane_rsrc((const GAS double *)plane, n), i * 8u, 0, 0);
+}
+// four consecutive elements starting at i (i % 4 == 0, planes 16-byte aligned)
+__device__ __forceinline__ void bld4(const GAS float *plane, uint32_t n, uint32_t i, float (&v)[4]) {
+    const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(plane_rsrc(plane, n), i * 4u, 0, 0);
+    v[0] = __uint_as_float(a.x); v[1] = __uint_as_float(a.y);
+    v[2] = __uint_as_float(a.z); v[3] = __uint_as_float(a.w);
+}
+__device__ __forceinline__ void bld4(const GAS double *plane, uint32_t n, uint32_t i, double (&v)[4]) {
+    const __amdgpu_buffer_rsrc_t r = plane_rsrc(plane, n);
+    const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, i * 8u, 0, 0);
+    const u32x4 b = __builtin_amdgcn_raw_buffer_load_b128(r, i * 8u + 16u, 0, 0);
+    v[0] = join_f64(a.x, a.y); v[1] = join_f64(a.z, a.w);
+    v[2] = join_f64(b.x, b.y); v[3] = join_f64(b.z, b.w);
+}
+__device__ __forceinline__ void bld4(const GAS unsigned short *plane, uint32_t n, uint32_t i,
+                                     float (&v)[4]) {
+    const u32x2 a = __builtin_amdgcn_raw_buffer_load_b64(plane_rsrc(plane, n), i * 2u, 0, 0);
+    v[0] = __uint_as_float(a.x << 16); v[1] = __uint_as_float(a.x & 0xffff0000u);
+    v[2] = __uint_as_float(a.y << 16); v[3] = __uint_as_float(a.y & 0xffff0000u);
+}
+__device__ __forceinline__ void bst4(GAS float *plane, uint32_t n, uint32_t i, const float (&v)[4]) {
+    const u32x4 a = {__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]),
+                     __float_as_uint(v[3])};
+    __builtin_amdgcn_raw_buffer_store_b128(a, plane_rsrc((const GAS float *)plane, n), i * 4u, 0, 0);
+}
+__device__ __forceinline__ void bst4(GAS double *plane, uint32_t n, uint32_t i, const double (&v)[4]) {
+    const __amdgpu_buffer_rsrc_t r = plane_rsrc((const GAS double *)plane, n);
+    const u32x4 a = {lo_f64(v[0]), hi_f64(v[0]), lo_f64(v[1]), hi_f64(v[1])};
+    const u32x4 b = {lo_f64(v[2]), hi_f64(v[2]), lo_f64(v[3]), hi_f64(v[3])};
+    __builtin_amdgcn_raw_buffer_store_b128(a, r, i * 8u, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(b, r, i * 8u + 16u, 0, 0);
+}
+
 // Grid boundary of the pixel graph (template parameter of the stencil kernels).
 enum { BC_PERIODIC = SYLV_BC_PERIODIC, BC_FACE = SYLV_BC_FACE };
 
@@ -243,7 +332,7 @@ __device__ __forceinline__ void precond_cg_vec4(int pc, const GAS unsigned short
 #pragma unroll
         for (int e = 0; e < MK; ++e) {
             float tmp[4];
-            ld4(F + (size_t)e * n_pix + p0, tmp);
+            bld4(F + (size_t)e * n_pix, (uint32_t)n_pix, (uint32_t)p0, tmp);
 #pragma unroll
             for (int q = 0; q < 4; ++q) g[e][q] = (T)tmp[q];
         }
@@ -269,7 +358,7 @@ __device__ __forceinline__ void precond_cg_vec4(int pc, const GAS unsigned short
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             float d[4];
-            ld4(F + (size_t)j * n_pix + p0, d);
+            bld4(F + (size_t)j * n_pix, (uint32_t)n_pix, (uint32_t)p0, d);
 #pragma unroll
             for (int q = 0; q < 4; ++q) z[j][q] = (T)d[q] * r[j][q];
         }

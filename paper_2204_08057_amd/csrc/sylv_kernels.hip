@@ -221,6 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
     const Inst &I = tab[ii];
     const int tile = (MODE == AM_PLAIN) ? L : L - tprefix[ii];
     const int nx = I.nx, ny = I.ny, n_pix = I.n_pix;
+    const uint32_t np = (uint32_t)n_pix;   // plane length for buffer accesses
     DevState *st = (MODE == AM_CG) ? Sel<T>::st(I) : nullptr;
     if constexpr (MODE == AM_CG) {
         if (st->done) return;
@@ -250,15 +251,16 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
     // Staging: rows by whole wavefronts (coalesced), the 4 halo columns of all rows by one lane
     // each.  Every staged column is the periodic wrap of x0 - 2 + c, so ragged tiles see true
     // neighbours.
-    const int cmain = wrapi(x0 + tx, nx);
+    const int cmain = wrapf(x0 + tx, nx);
     const int hitem = ty * 64 + tx;                     // halo item: (row, one of 4 columns)
     const int hr = hitem >> 2, hc = hitem & 3;
     const int hcol = (hc < 2) ? hc : (kTileX + hc);     // staged columns 0, 1, 66, 67
     const bool hvalid = hitem < 4 * LH;
-    const int hoff = hvalid ? wrapi(y0 - 2 + hr, ny) * nx + wrapi(x0 - 2 + hcol, nx) : 0;
-    int soff[RPW];
+    const uint32_t hoff = hvalid ? (uint32_t)(wrapf(y0 - 2 + hr, ny) * nx + wrapf(x0 - 2 + hcol, nx)) : 0u;
+    uint32_t soff[RPW];
 #pragma unroll
-    for (int rr = 0; rr < RPW; ++rr) soff[rr] = wrapi(y0 - 2 + rr * kWavesY + ty, ny) * nx + cmain;
+    for (int rr = 0; rr < RPW; ++rr)
+        soff[rr] = (uint32_t)(wrapf(y0 - 2 + rr * kWavesY + ty, ny) * nx + cmain);
     // face grids: staged positions outside the face hold 0 (absent neighbours)
     bool sin[RPW];
     bool hin = hvalid;
@@ -279,13 +281,13 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
     for (int j = 0; j < K; ++j) {
         const GAS T *a = u0 + (size_t)j * n_pix;
 #pragma unroll
-        for (int rr = 0; rr < RPW; ++rr) sa[j][rr] = sin[rr] ? a[soff[rr]] : (T)0;
-        ha[j] = hin ? a[hoff] : (T)0;
+        for (int rr = 0; rr < RPW; ++rr) sa[j][rr] = sin[rr] ? bld(a, np, soff[rr]) : (T)0;
+        ha[j] = hin ? bld(a, np, hoff) : (T)0;
         if constexpr (MODE == AM_CG) {
             const GAS T *zz = u1 + (size_t)j * n_pix;
 #pragma unroll
-            for (int rr = 0; rr < RPW; ++rr) sb[j][rr] = sin[rr] ? zz[soff[rr]] : (T)0;
-            hb[j] = hin ? zz[hoff] : (T)0;
+            for (int rr = 0; rr < RPW; ++rr) sb[j][rr] = sin[rr] ? bld(zz, np, soff[rr]) : (T)0;
+            hb[j] = hin ? bld(zz, np, hoff) : (T)0;
         }
     }
     // CG (it >= 1): x += alpha_(it-1) p_(it-1) on the staged interior values (each pixel of the
@@ -303,7 +305,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
         for (int j = 0; j < K; ++j)
 #pragma unroll
             for (int rr = 0; rr < RPW; ++rr)
-                xs[j][rr] = xin[rr] ? xx[(size_t)j * n_pix + soff[rr]] : (T)0;
+                xs[j][rr] = xin[rr] ? bld(xx + (size_t)j * n_pix, np, soff[rr]) : (T)0;
     }
     // per-pixel mixing blocks (and, for the residual, b) of this lane's R output pixels
     T m[R][MK];
@@ -315,11 +317,11 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
         for (int t = 0; t < R; ++t) {
             const int pix = (iy0 + t < ny ? iy0 + t : 0) * nx + ixc;
 #pragma unroll
-            for (int e = 0; e < MK; ++e) m[t][e] = M[(size_t)e * n_pix + pix];
+            for (int e = 0; e < MK; ++e) m[t][e] = bld(M + (size_t)e * n_pix, np, (uint32_t)pix);
             if constexpr (MODE == AM_RESID) {
                 const GAS double *bb = gp(I.b);
 #pragma unroll
-                for (int j = 0; j < K; ++j) bpre[t][j] = bb[(size_t)j * n_pix + pix];
+                for (int j = 0; j < K; ++j) bpre[t][j] = bld(bb + (size_t)j * n_pix, np, (uint32_t)pix);
             }
         }
     }
@@ -352,7 +354,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
             for (int j = 0; j < K; ++j)
 #pragma unroll
                 for (int rr2 = 0; rr2 < RPW; ++rr2)
-                    if (xin[rr2]) xx[(size_t)j * n_pix + soff[rr2]] = xs[j][rr2] + a * sa[j][rr2];
+                    if (xin[rr2]) bst(xx + (size_t)j * n_pix, np, soff[rr2], xs[j][rr2] + a * sa[j][rr2]);
         }
         if (status >= 0) return;
         if (it > 0) beta = (T)(rz / st->rho[(it - 1) & 1]);
@@ -436,14 +438,14 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
                 if constexpr (MODE == AM_PLAIN) {
                     GAS T *o = gp(ext_out) + (size_t)blockIdx.y * K * n_pix;
 #pragma unroll
-                    for (int j = 0; j < K; ++j) o[(size_t)j * n_pix + pix] = acc[j][t];
+                    for (int j = 0; j < K; ++j) bst(o + (size_t)j * n_pix, np, (uint32_t)pix, acc[j][t]);
                 } else if constexpr (MODE == AM_CG) {
                     GAS T *pp = Sel<T>::p(I, it + 1);
                     GAS T *qq = Sel<T>::q(I);
 #pragma unroll
                     for (int j = 0; j < K; ++j) {
-                        pp[(size_t)j * n_pix + pix] = ctr[j][t];
-                        qq[(size_t)j * n_pix + pix] = acc[j][t];
+                        bst(pp + (size_t)j * n_pix, np, (uint32_t)pix, ctr[j][t]);
+                        bst(qq + (size_t)j * n_pix, np, (uint32_t)pix, acc[j][t]);
                         d0 += (double)ctr[j][t] * (double)acc[j][t];
                     }
                 } else {
@@ -452,7 +454,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
                     for (int j = 0; j < K; ++j) {
                         const double bv = bpre[t][j];
                         const double res = bv - (double)acc[j][t];
-                        rv[(size_t)j * n_pix + pix] = res;
+                        bst(rv + (size_t)j * n_pix, np, (uint32_t)pix, res);
                         d0 += res * res;
                         d1 += bv * bv;
                     }
@@ -545,6 +547,7 @@ __global__ __launch_bounds__(kBlock) void k_update(const Inst *__restrict__ tab,
         return;
     }
     const int n_pix = I.n_pix;
+    const uint32_t np = (uint32_t)n_pix;   // plane length for buffer accesses
     GAS T *r = Sel<T>::r(I);
     GAS T *z = Sel<T>::z(I);
     const GAS T *q = Sel<T>::q(I);
@@ -557,9 +560,8 @@ __global__ __launch_bounds__(kBlock) void k_update(const Inst *__restrict__ tab,
     if (vec) {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            const size_t o = (size_t)j * n_pix + p0;
-            ld4(r + o, rv[j]);
-            ld4(q + o, qv[j]);
+            bld4(r + (size_t)j * n_pix, np, (uint32_t)p0, rv[j]);
+            bld4(q + (size_t)j * n_pix, np, (uint32_t)p0, qv[j]);
         }
     }
     double s[1];
@@ -588,12 +590,12 @@ __global__ __launch_bounds__(kBlock) void k_update(const Inst *__restrict__ tab,
             for (int j = 0; j < K; ++j) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) rv[j][e] -= alpha * qv[j][e];
-                st4(r + (size_t)j * n_pix + p0, rv[j]);
+                bst4(r + (size_t)j * n_pix, np, (uint32_t)p0, rv[j]);
             }
             precond_cg_vec4<T, K>(pc, P, n_pix, p0, rv, zv);
 #pragma unroll
             for (int j = 0; j < K; ++j) {
-                st4(z + (size_t)j * n_pix + p0, zv[j]);
+                bst4(z + (size_t)j * n_pix, np, (uint32_t)p0, zv[j]);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     rz += (double)rv[j][e] * (double)zv[j][e];
@@ -659,6 +661,7 @@ __global__ __launch_bounds__(kBlock) void k_pinit(const Inst *__restrict__ tab,
         }
     }
     const int n_pix = I.n_pix;
+    const uint32_t np = (uint32_t)n_pix;   // plane length for buffer accesses
     const GAS double *r64 = gp(I.r);
     GAS T *rr_out = Sel<T>::r(I);
     GAS T *z = Sel<T>::z(I);
@@ -670,21 +673,21 @@ __global__ __launch_bounds__(kBlock) void k_pinit(const Inst *__restrict__ tab,
         T rv[K][4], zv[K][4];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            const size_t o = (size_t)j * n_pix + p0;
+            const size_t o = (size_t)j * n_pix;
             double r4[4];
-            ld4(r64 + o, r4);
+            bld4(r64 + o, np, (uint32_t)p0, r4);
 #pragma unroll
             for (int e = 0; e < 4; ++e) rv[j][e] = (T)r4[e];
             if constexpr (sizeof(T) == 4) {
-                st4(rr_out + o, rv[j]);
+                bst4(rr_out + o, np, (uint32_t)p0, rv[j]);
                 const float zero4[4] = {0.f, 0.f, 0.f, 0.f};
-                st4(gp(I.d32) + o, zero4);
+                bst4(gp(I.d32) + o, np, (uint32_t)p0, zero4);
             }
         }
         precond_cg_vec4<T, K>(pc, P, n_pix, p0, rv, zv);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            st4(z + (size_t)j * n_pix + p0, zv[j]);
+            bst4(z + (size_t)j * n_pix, np, (uint32_t)p0, zv[j]);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 rz += (double)rv[j][e] * (double)zv[j][e];
@@ -730,6 +733,7 @@ __global__ __launch_bounds__(kBlock) void k_refine_axpy(const Inst *__restrict__
     if (st_in == SYLV_NONFINITE || st_in == SYLV_BREAKDOWN) return;
     const int chunk = L - cprefix[ii];
     const int n_pix = I.n_pix;
+    const uint32_t np = (uint32_t)n_pix;   // plane length for buffer accesses
     const int p0 = chunk * kChunk + threadIdx.x * 4;
     GAS double *x = gp(I.x);
     const GAS float *d = gp(I.d32);
@@ -738,14 +742,14 @@ __global__ __launch_bounds__(kBlock) void k_refine_axpy(const Inst *__restrict__
         float dv[K][4];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            ld4(x + (size_t)j * n_pix + p0, xv[j]);
-            ld4(d + (size_t)j * n_pix + p0, dv[j]);
+            bld4(x + (size_t)j * n_pix, np, (uint32_t)p0, xv[j]);
+            bld4(d + (size_t)j * n_pix, np, (uint32_t)p0, dv[j]);
         }
 #pragma unroll
         for (int j = 0; j < K; ++j) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) xv[j][e] += (double)dv[j][e];
-            st4(x + (size_t)j * n_pix + p0, xv[j]);
+            bst4(x + (size_t)j * n_pix, np, (uint32_t)p0, xv[j]);
         }
         return;
     }
