@@ -33,6 +33,15 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Optional override of the apply kernels' rows per lane (2, 4 or 8) for tuning experiments.
+// Partial count above which an instance's CG reductions are folded separately: kPreReduce, or
+// SYLV_PREREDUCE_MIN from the environment (read at every solve call; tests set 0 to force it).
+int prereduce_min() {
+    const char *e = getenv("SYLV_PREREDUCE_MIN");
+    if (!e || !*e) return kPreReduce;
+    const int v = atoi(e);
+    return v >= 0 ? v : kPreReduce;
+}
+
 int apply_rows_request() {
     static int rows = -1;
     if (rows < 0) {
@@ -320,7 +329,9 @@ int run_cg_loop(const InstSet &set, int k, int mixed, int chunk, int max_iter, H
     auto enqueue_batch = [&](int n) -> int {
         for (int c = 0; c < n && it <= max_iter; ++c, ++it) {
             HIP_TRY(launch_cg_apply(set, k, mixed, it, s));
+            HIP_TRY(launch_prereduce_pq(set, mixed, s));
             HIP_TRY(launch_cg_update(set, k, mixed, it, s));
+            HIP_TRY(launch_prereduce_rz(set, s));
         }
         pend[npend++] = next_slot;
         const int slot = next_slot;
@@ -419,6 +430,8 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
     std::vector<int> pre(3 * (ninst + 1));
     int *tpre = pre.data(), *tpre32 = tpre + (ninst + 1), *cpre = tpre32 + (ninst + 1);
     size_t xoff = 0, yoff = 0;
+    int any_pre = 0;
+    const int pre_min = prereduce_min();
     tpre[0] = tpre32[0] = cpre[0] = 0;
     for (int g = 0; g < nprob; ++g) {
         const sylv_problem &p = probs[g];
@@ -450,6 +463,8 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
             I.st_in = I.st + 1;
             I.partial = reinterpret_cast<double *>(base + IL.partial);
             I.vec4 = (I.n_pix % 4 == 0) && aligned16(I.x) ? 1 : 0;
+            I.pre = std::max(std::max(I.ntiles, I.ntiles32), I.nchunks) > pre_min ? 1 : 0;
+            any_pre |= I.pre;
             tab[i] = I;
             tpre[i + 1] = tpre[i] + I.ntiles;
             tpre32[i + 1] = tpre32[i] + I.ntiles32;
@@ -474,6 +489,7 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
     set.rows64 = rows64;
     set.rows32 = rows32;
     set.bc = bc;
+    set.any_pre = any_pre;
 
     // block CG groups: one per problem, its nrhs instances in order
     const bool block = opts->block != 0;
@@ -545,6 +561,7 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
             HIP_TRY(launch_bgram(gset, 0, mixed, inner_tol, opts->max_iter, s));
         } else {
             HIP_TRY(launch_pinit(set, k, mixed, inner_tol, opts->max_iter, s));
+            HIP_TRY(launch_prereduce_rz(set, s));
         }
         return SYLV_OK;
     };

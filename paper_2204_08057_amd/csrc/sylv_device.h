@@ -171,17 +171,26 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], double *partial,
 }
 
 // Fixed-order sum over nblocks partials of quantities slot0..slot0+NV-1; every thread of the
-// workgroup receives the result.
+// workgroup receives the result.  Each thread keeps four independent running sums so that four
+// loads are in flight at a time (the partials are read from L2 with its full latency).
 template <int NV>
 __device__ __forceinline__ void consume(const double *partial, int nred, int slot0, int nblocks,
                                         double (&out)[NV]) {
     __shared__ double sm[NV][kBlock / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const GAS double *pp = gp(partial);
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += kBlock) s += pp[(size_t)(slot0 + i) * nred + b];
+        const GAS double *pp = gp(partial) + (size_t)(slot0 + i) * nred;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int b = threadIdx.x;
+        for (; b + 3 * kBlock < nblocks; b += 4 * kBlock) {
+            a0 += pp[b];
+            a1 += pp[b + kBlock];
+            a2 += pp[b + 2 * kBlock];
+            a3 += pp[b + 3 * kBlock];
+        }
+        for (; b < nblocks; b += kBlock) a0 += pp[b];
+        double s = (a0 + a1) + (a2 + a3);
         s = wave_sum(s);
         if (lane == 0) sm[i][wid] = s;
     }

@@ -22,6 +22,11 @@ constexpr int kChunk = 1024;     // pixels per workgroup in streaming kernels (4
 enum Slot { SLOT_PQ = 0, SLOT_RZ = 1, SLOT_RR = 2, SLOT_RES_RR = 3, SLOT_RES_BB = 4 };
 constexpr int kNumSlots = 5;
 constexpr int kMaxRestarts = 3;   // residual replacements of a float64 run
+// Every workgroup of a consuming CG kernel re-reduces the producer's per-workgroup partials in a
+// fixed order (no atomics, bitwise repeatable).  That read grows with the square of the
+// workgroup count, so instances with more partials than this fold them first in a separate
+// one-workgroup-per-instance kernel.
+constexpr int kPreReduce = 2048;
 
 // Solver state of one conjugate-gradient run, in device memory.  The scalars of the recurrence
 // (Alg. 2: alpha, beta, <r, z>, ||r||) are formed on the device; the host only reads `done`.
@@ -62,6 +67,8 @@ struct Inst {
     int32_t pc;          // preconditioner kind (SYLV_PC_*)
     int32_t vec4;        // 1 if n_pix % 4 == 0 and every plane is 16-byte aligned
     int32_t f;           // maps of the problem
+    int32_t pre;         // 1: the CG reductions are folded by k_prereduce before their
+                         // consumers, which then read one value (large grids, see kPreReduce)
     const double *coef;  // [K * kCoefStride]
     const double *A;     // [f * K]
     const double *W;     // [f * n_pix]
@@ -96,6 +103,7 @@ struct InstSet {
     int total_tiles32;
     int total_chunks;
     int rows64, rows32;   // rows per lane of the float64 / float32 apply kernels
+    int any_pre;          // some instance has Inst::pre set
     int bc;               // SYLV_BC_* of every instance (face grids use 2 rows per lane)
 };
 
@@ -171,6 +179,10 @@ hipError_t launch_refine_axpy(const InstSet &set, int k, hipStream_t s);
 hipError_t launch_state_init(const InstSet &set, double tol, int max_iter, int ref,
                              hipStream_t s);
 hipError_t launch_count_running(const InstSet &set, int inner, int *out, hipStream_t s);
+// Fold the partials of <p, q> (after a CG apply) or of <r, z>, ||r||^2 (after an update or a
+// run start) of the instances with Inst::pre set; a no-op launch is skipped when none has it.
+hipError_t launch_prereduce_pq(const InstSet &set, int mixed, hipStream_t s);
+hipError_t launch_prereduce_rz(const InstSet &set, hipStream_t s);
 hipError_t launch_stats(const InstSet &set, void *stats, int mixed, hipStream_t s);
 hipError_t launch_po(const double *kappa, const double *tau, const double *A, const double *W,
                      const double *xi, const double *zeta, double *eta, int k, int f, int ny,

@@ -330,7 +330,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
     T beta = 0;
     if constexpr (MODE == AM_CG) {
         double s[2];
-        consume<2>(I.partial, I.nred, SLOT_RZ, I.nchunks, s);
+        consume<2>(I.partial, I.nred, SLOT_RZ, I.pre ? 1 : I.nchunks, s);
         const double rz = s[0], rr = s[1];
         // float64 runs stop against ||b - G x0|| (threshold set by the initial residual pass,
         // also across restarts); a float32 inner run against its own starting residual
@@ -565,7 +565,7 @@ __global__ __launch_bounds__(kBlock) void k_update(const Inst *__restrict__ tab,
         }
     }
     double s[1];
-    consume<1>(I.partial, I.nred, SLOT_PQ, sizeof(T) == 4 ? I.ntiles32 : I.ntiles, s);
+    consume<1>(I.partial, I.nred, SLOT_PQ, I.pre ? 1 : (sizeof(T) == 4 ? I.ntiles32 : I.ntiles), s);
     const double pq = s[0];
     int status = -1;
     if (!finite_d(pq)) status = SYLV_NONFINITE;
@@ -797,6 +797,24 @@ __global__ void k_state_init(const Inst *__restrict__ tab, int ninst, double tol
 }
 
 // Number of instances whose run (outer or inner) has not finished.
+// Fold the nblocks partials of quantities slot0..slot0+NV-1 of one instance (one workgroup per
+// instance, same fixed order as consume) into entry 0, for instances with Inst::pre set.
+// count: 0 = float64 apply tiles, 1 = float32 apply tiles, 2 = streaming chunks.
+template <int NV>
+__global__ __launch_bounds__(kBlock) void k_prereduce(const Inst *__restrict__ tab, int slot0,
+                                                      int count) {
+    const Inst &I = tab[blockIdx.x];
+    if (!I.pre) return;
+    const int nb = count == 0 ? I.ntiles : count == 1 ? I.ntiles32 : I.nchunks;
+    double v[NV];
+    consume<NV>(I.partial, I.nred, slot0, nb, v);   // every read precedes its final barrier
+    if (threadIdx.x == 0) {
+        GAS double *pp = gp(I.partial);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) pp[(size_t)(slot0 + i) * I.nred] = v[i];
+    }
+}
+
 // Completion report for the host: out[0] = runs not finished; out[1] = the latest iteration
 // tested among them; out[2] = max over them of log2(rr / thresh) in 1/256 units (how far the
 // slowest run still is from its threshold, rounded up, 0 when unknown), from which the host sizes
@@ -1168,6 +1186,20 @@ hipError_t launch_state_init(const InstSet &set, double tol, int max_iter, int r
 hipError_t launch_count_running(const InstSet &set, int inner, int *out, hipStream_t s) {
     hipLaunchKernelGGL(k_count_running, dim3(1), dim3(256), 0, s, set.table, set.ninst, inner,
                        out);
+    return hipGetLastError();
+}
+
+hipError_t launch_prereduce_pq(const InstSet &set, int mixed, hipStream_t s) {
+    if (!set.any_pre) return hipSuccess;
+    hipLaunchKernelGGL(k_prereduce<1>, dim3(set.ninst), dim3(kBlock), 0, s, set.table,
+                       (int)SLOT_PQ, mixed ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_prereduce_rz(const InstSet &set, hipStream_t s) {
+    if (!set.any_pre) return hipSuccess;
+    hipLaunchKernelGGL(k_prereduce<2>, dim3(set.ninst), dim3(kBlock), 0, s, set.table,
+                       (int)SLOT_RZ, 2);
     return hipGetLastError();
 }
 

@@ -276,6 +276,33 @@ def test_solve_fully_masked_uses_prior_only():
     assert rel(host(X), osv.solve_dense(prob, b=Bx)) < 1e-8
 
 
+@pytest.mark.parametrize("precision", [sy.SYLV_PREC_F64, sy.SYLV_PREC_MIXED])
+def test_folded_reductions_match(precision, monkeypatch):
+    """Large grids fold the CG partials in a separate kernel before their consumers; forcing that
+    path on small grids (threshold 0) gives the same iterations and, up to the summation order of
+    the dot products, the same solution as the default path, also in a batch of uneven grids."""
+    probs = [make_problem(s0, s1, 3, 5, seed=820 + i, noise="hetero")
+             for i, (s0, s1) in enumerate([(20, 18), (9, 33), (24, 24)])]
+    dps = [sy.DeviceProblem.from_numpy(p) for p in probs]
+    Y = torch.cat([dev(p.Y.ravel()) for p in probs])
+    opts = sy.SolveOptions(tol=1e-10, precision=precision)
+    say("folded reductions", precision)
+    Xa, sa = sy.pcg_solve(dps, Y=Y, opts=opts)
+    monkeypatch.setenv("SYLV_PREREDUCE_MIN", "0")
+    Xb, sb = sy.pcg_solve(dps, Y=Y, opts=opts)
+    monkeypatch.delenv("SYLV_PREREDUCE_MIN")
+    assert all(a["status"] == 0 and b["status"] == 0 for a, b in zip(sa, sb)), (sa, sb)
+    for a, b in zip(sa, sb):
+        assert abs(a["iters"] - b["iters"]) <= 1, (a, b)
+    xa, xb = host(Xa), host(Xb)
+    assert rel(xb, xa) < 1e-8
+    off = 0
+    for p in probs:
+        n = p.k * p.n_pix
+        assert rel(xb[off:off + n].reshape(p.k, p.n_pix), osv.solve_dense(p)) < 1e-7
+        off += n
+
+
 def test_solve_not_converged_reported():
     prob = make_problem(32, 32, 3, 6, seed=803)
     say("max_iter=2")
