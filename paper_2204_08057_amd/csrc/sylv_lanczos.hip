@@ -222,6 +222,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_stencil(LzArgs a, int it) {
     const bool prev = STEP && it > 1;     // a previous block exists
     const int tile = xcd_remap(blockIdx.x, a.ntiles);
     const int nx = a.nx, ny = a.ny, n_pix = a.n_pix;
+    const uint32_t np = (uint32_t)n_pix;   // plane length for buffer accesses
     const LzConst *c = a.c;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const int tile_x = tile % a.tiles_x, tile_y = tile / a.tiles_x;
@@ -235,15 +236,16 @@ __global__ __launch_bounds__(kBlock) void k_lz_stencil(LzArgs a, int it) {
     if constexpr (STEP) src0 = (it == 1) ? a.Yh : ((it & 1) ? a.Wa1 : a.Wa0);
     else src0 = a.X;
     const GAS double *vprev = gp(a.basis) + (size_t)(prev ? it - 2 : 0) * K * n_pix;
-    const int cmain = wrapi(x0 + tx, nx);
+    const int cmain = wrapf(x0 + tx, nx);
     const int hitem = ty * 64 + tx;
     const int hr = hitem >> 2, hc = hitem & 3;
     const int hcol = (hc < 2) ? hc : (kTileX + hc);
     const bool hvalid = hitem < 4 * LH;
-    const int hoff = hvalid ? wrapi(y0 - 2 + hr, ny) * nx + wrapi(x0 - 2 + hcol, nx) : 0;
-    int soff[RPW];
+    const uint32_t hoff = hvalid ? (uint32_t)(wrapf(y0 - 2 + hr, ny) * nx + wrapf(x0 - 2 + hcol, nx)) : 0u;
+    uint32_t soff[RPW];
 #pragma unroll
-    for (int rr = 0; rr < RPW; ++rr) soff[rr] = wrapi(y0 - 2 + rr * kWavesY + ty, ny) * nx + cmain;
+    for (int rr = 0; rr < RPW; ++rr)
+        soff[rr] = (uint32_t)(wrapf(y0 - 2 + rr * kWavesY + ty, ny) * nx + cmain);
     // face grids: staged positions outside the face hold 0 (absent neighbours)
     bool sin[RPW];
     bool hin = hvalid;
@@ -264,13 +266,13 @@ __global__ __launch_bounds__(kBlock) void k_lz_stencil(LzArgs a, int it) {
     for (int j = 0; j < K; ++j) {
         const GAS double *s = gp(src0) + (size_t)j * n_pix;
 #pragma unroll
-        for (int rr = 0; rr < RPW; ++rr) sa[j][rr] = sin[rr] ? s[soff[rr]] : 0.0;
-        ha[j] = hin ? s[hoff] : 0.0;
+        for (int rr = 0; rr < RPW; ++rr) sa[j][rr] = sin[rr] ? bld(s, np, soff[rr]) : 0.0;
+        ha[j] = hin ? bld(s, np, hoff) : 0.0;
         if (prev) {
             const GAS double *v = vprev + (size_t)j * n_pix;
 #pragma unroll
-            for (int rr = 0; rr < RPW; ++rr) sv[j][rr] = sin[rr] ? v[soff[rr]] : 0.0;
-            hv[j] = hin ? v[hoff] : 0.0;
+            for (int rr = 0; rr < RPW; ++rr) sv[j][rr] = sin[rr] ? bld(v, np, soff[rr]) : 0.0;
+            hv[j] = hin ? bld(v, np, hoff) : 0.0;
         } else {
 #pragma unroll
             for (int rr = 0; rr < RPW; ++rr) sv[j][rr] = 0.0;
@@ -282,15 +284,15 @@ __global__ __launch_bounds__(kBlock) void k_lz_stencil(LzArgs a, int it) {
 #pragma unroll
     for (int t = 0; t < R; ++t) {
         const int pix = (iy0 + t < ny ? iy0 + t : 0) * nx + ixc;
-        nv[t] = gp(a.n)[pix];
+        nv[t] = bld(gp(a.n), np, (uint32_t)pix);
 #pragma unroll
         for (int j = 0; j < K; ++j) aux[t][j] = 0.0;
         if (prev) {          // V_(i-1) at the output pixels (just staged: served by L2)
 #pragma unroll
-            for (int j = 0; j < K; ++j) aux[t][j] = vprev[(size_t)j * n_pix + pix];
+            for (int j = 0; j < K; ++j) aux[t][j] = bld(vprev + (size_t)j * n_pix, np, (uint32_t)pix);
         } else if (MODE == LZ_RESID) {
 #pragma unroll
-            for (int j = 0; j < K; ++j) aux[t][j] = gp(a.Yh)[(size_t)j * n_pix + pix];
+            for (int j = 0; j < K; ++j) aux[t][j] = bld(gp(a.Yh) + (size_t)j * n_pix, np, (uint32_t)pix);
         }
     }
 
@@ -395,8 +397,8 @@ __global__ __launch_bounds__(kBlock) void k_lz_stencil(LzArgs a, int it) {
 #pragma unroll
                         for (int q = 0; q < K; ++q) w -= aux[t][q] * Bi[j * kMaxK + q];
                     }
-                    vb[(size_t)j * n_pix + pix] = ctr[j][t];
-                    wa[(size_t)j * n_pix + pix] = w;
+                    bst(vb + (size_t)j * n_pix, np, (uint32_t)pix, ctr[j][t]);
+                    bst(wa + (size_t)j * n_pix, np, (uint32_t)pix, w);
                     uo[t][j] = ctr[j][t];
                     wo[t][j] = w;
                 }
