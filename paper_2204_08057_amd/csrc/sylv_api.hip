@@ -204,7 +204,9 @@ Inst operator_inst(const sylv_problem &p, const ProbLayout &P, char *base, int p
     return I;
 }
 
-int prepare_operator(const sylv_problem &p, const ProbLayout &P, char *base, int pc,
+// exact = 1 also stores the exact block inverses (float64 and float32) that the stand-alone
+// sylv_precond reads; CG runs read only the bfloat16 factor.
+int prepare_operator(const sylv_problem &p, const ProbLayout &P, char *base, int pc, int exact,
                      hipStream_t s) {
     double *coef = reinterpret_cast<double *>(base + P.coef);
     HIP_TRY(launch_coef(p.kappa, p.tau, p.k, (int)p.ny, (int)p.nx, coef, s));
@@ -213,7 +215,7 @@ int prepare_operator(const sylv_problem &p, const ProbLayout &P, char *base, int
                          reinterpret_cast<float *>(base + P.M32),
                          reinterpret_cast<double *>(base + P.P64),
                          reinterpret_cast<float *>(base + P.P32),
-                         reinterpret_cast<unsigned short *>(base + P.P16), p.k, s));
+                         reinterpret_cast<unsigned short *>(base + P.P16), exact, p.k, s));
     return SYLV_OK;
 }
 
@@ -541,7 +543,7 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
 
     // operator set-up and right-hand sides
     for (int g = 0; g < nprob; ++g) {
-        rc = prepare_operator(probs[g], L.prob[g], base, pc, s);
+        rc = prepare_operator(probs[g], L.prob[g], base, pc, 0, s);
         if (rc) return rc;
     }
     HIP_TRY(launch_state_init(set, opts->tol, opts->max_iter, opts->stop_ref, s));
@@ -976,7 +978,7 @@ int sylv_prepare(const sylv_problem *prob, int32_t precond, void *ws, size_t ws_
     if (rc) return rc;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     char *base = reinterpret_cast<char *>(ws);
-    rc = prepare_operator(*prob, L.prob[0], base, precond, s);
+    rc = prepare_operator(*prob, L.prob[0], base, precond, 1, s);
     if (rc) return rc;
     Inst I = operator_inst(*prob, L.prob[0], base, precond);
     I.ntiles = 0;

@@ -160,7 +160,7 @@ hipError_t launch_coef(const double *kappa, const double *tau, int k, int ny, in
                        double *coef, hipStream_t s);
 hipError_t launch_setup(const double *W, const double *A, int f, int ny, int nx, int bc,
                         const double *coef, int pc, double *M64, float *M32, double *P64,
-                        float *P32, unsigned short *P16, int k, hipStream_t s);
+                        float *P32, unsigned short *P16, int exact, int k, hipStream_t s);
 hipError_t launch_rhs(const double *W, const double *Y, const double *A, int f, int n_pix,
                       const double *bext, double *b, int k, hipStream_t s);
 hipError_t launch_apply_plain(const Inst *table0, int k, int dtype, int rows, int bc, int ny,

@@ -67,7 +67,7 @@ __global__ __launch_bounds__(kBlock) void k_setup(const double *__restrict__ W,
                                                   const double *__restrict__ coef, int pc,
                                                   double *__restrict__ M64, float *__restrict__ M32,
                                                   double *__restrict__ P64, float *__restrict__ P32,
-                                                  unsigned short *__restrict__ P16) {
+                                                  unsigned short *__restrict__ P16, int exact) {
     constexpr int MK = K * (K + 1) / 2;
     const int n_pix = ny * nx;
     const int pix = blockIdx.x * kBlock + threadIdx.x;
@@ -107,8 +107,10 @@ __global__ __launch_bounds__(kBlock) void k_setup(const double *__restrict__ W,
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const double d = 1.0 / (qd[j] + m[pidx<K>(j, j)]);
-            P64[(size_t)j * n_pix + pix] = d;
-            P32[(size_t)j * n_pix + pix] = (float)d;
+            if (exact) {
+                P64[(size_t)j * n_pix + pix] = d;
+                P32[(size_t)j * n_pix + pix] = (float)d;
+            }
             P16[(size_t)j * n_pix + pix] = bf16_round((float)d);
         }
     } else if (pc == SYLV_PC_BLOCK) {
@@ -162,14 +164,16 @@ __global__ __launch_bounds__(kBlock) void k_setup(const double *__restrict__ W,
                 inv[r][col] = v / l[r][r];
             }
         }
+        if (exact) {
 #pragma unroll
-        for (int i = 0; i < K; ++i)
+            for (int i = 0; i < K; ++i)
 #pragma unroll
-            for (int j = i; j < K; ++j) {
-                const double v = 0.5 * (inv[i][j] + inv[j][i]) + bad;
-                P64[(size_t)pidx<K>(i, j) * n_pix + pix] = v;
-                P32[(size_t)pidx<K>(i, j) * n_pix + pix] = (float)v;
-            }
+                for (int j = i; j < K; ++j) {
+                    const double v = 0.5 * (inv[i][j] + inv[j][i]) + bad;
+                    P64[(size_t)pidx<K>(i, j) * n_pix + pix] = v;
+                    P32[(size_t)pidx<K>(i, j) * n_pix + pix] = (float)v;
+                }
+        }
     }
 }
 
@@ -1055,12 +1059,12 @@ hipError_t launch_coef(const double *kappa, const double *tau, int k, int ny, in
 
 hipError_t launch_setup(const double *W, const double *A, int f, int ny, int nx, int bc,
                         const double *coef, int pc, double *M64, float *M32, double *P64,
-                        float *P32, unsigned short *P16, int k, hipStream_t s) {
+                        float *P32, unsigned short *P16, int exact, int k, hipStream_t s) {
     const long n_pix = (long)ny * nx;
     return dispatch_k(k, [&](auto tag) {
         constexpr int K = decltype(tag)::value;
         hipLaunchKernelGGL((k_setup<K>), dim3(blocks_for(n_pix, kBlock)), dim3(kBlock), 0, s, W,
-                           A, f, ny, nx, bc, coef, pc, M64, M32, P64, P32, P16);
+                           A, f, ny, nx, bc, coef, pc, M64, M32, P64, P32, P16, exact);
         return hipGetLastError();
     });
 }
