@@ -106,12 +106,15 @@ def cg_iteration_seconds(sy, torch, dp, Y, ws, precision, n1=40, n2=140, reps=5)
     return (median_time(n2) - median_time(n1)) / (n2 - n1)
 
 
-def cg_iteration_bytes_per_pixel(k: int, elem: int) -> int:
-    """Algorithmic bytes of one CG iteration per pixel: the fused apply reads p_old, z, x and the
-    k(k+1)/2 mixing planes and writes p, q, x; the update reads r, q and the bfloat16
-    block-Jacobi factor planes and writes r, z."""
+def cg_iteration_bytes_per_pixel(k: int, elem: int) -> float:
+    """Algorithmic bytes of one CG iteration per pixel: the fused apply reads p_old, z and the
+    k(k+1)/2 mixing planes and writes p, q, and it advances x (float32: read and write x every
+    iteration; float64: every second iteration, reading x and p_(i-2) and writing x, i.e. 1.5 k
+    planes per iteration on average); the update reads r, q and the bfloat16 block-Jacobi factor
+    planes and writes r, z."""
     mk = k * (k + 1) // 2
-    return (6 * k + mk) * elem + 4 * k * elem + mk * 2
+    x_planes = 2.0 * k if elem == 4 else 1.5 * k
+    return (4 * k + mk + x_planes) * elem + 4 * k * elem + mk * 2
 
 
 def cpu_baseline(prob, tol):
@@ -492,7 +495,7 @@ def main():
     cg_it = {}
     for label, prec, elem in (("f32", sy.SYLV_PREC_MIXED, 4), ("f64", sy.SYLV_PREC_F64, 8)):
         sec = cg_iteration_seconds(sy, torch, dp, Y, ws, prec)
-        nb = cg_iteration_bytes_per_pixel(k, elem) * n_pix
+        nb = int(cg_iteration_bytes_per_pixel(k, elem) * n_pix)
         cg_it[label] = {"us": round(sec * 1e6, 2), "algorithmic_bytes": nb,
                         "achieved": round(nb / sec / 1e9, 1), "peak": PEAK_HBM_GBS,
                         "unit": "GB/s", "frac": round(nb / sec / 1e9 / PEAK_HBM_GBS, 4)}

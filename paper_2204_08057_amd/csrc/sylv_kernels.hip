@@ -294,9 +294,17 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
             hb[j] = hin ? bld(zz, np, hoff) : (T)0;
         }
     }
-    // CG (it >= 1): x += alpha_(it-1) p_(it-1) on the staged interior values (each pixel of the
-    // grid is interior to exactly one tile); prefetch x there.
-    T xs[K][RPW];
+    // CG: x += alpha_(it-1) p_(it-1) on the staged interior values (each pixel of the grid is
+    // interior to exactly one tile).  Float64 runs advance x every second iteration instead: even
+    // it >= 2 adds alpha_(it-2) p_(it-2) and then alpha_(it-1) p_(it-1) (the rounding of two single
+    // steps), odd it touches x only when the run stops there; p_(it-2) is read at this
+    // workgroup's own interior pixels from the buffer that receives p_it at the same pixels below,
+    // so no other workgroup overwrites it first.  That saves half of the x traffic; the float32
+    // apply is latency-bound at these sizes and runs faster with one step per iteration.
+    constexpr bool kPairX = sizeof(T) == 8;
+    const bool pair = kPairX && it >= 2 && (it & 1) == 0;   // this apply adds two steps
+    const bool xnow = it > 0 && (!kPairX || pair);           // x advances here in any case
+    T xs[K][RPW], po[K][RPW];
     bool xin[RPW];
     if constexpr (MODE == AM_CG) {
 #pragma unroll
@@ -304,12 +312,17 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
             const int r = rr * kWavesY + ty;
             xin[rr] = it > 0 && r >= 2 && r < LH - 2 && (y0 + r - 2) < ny && (x0 + tx) < nx;
         }
-        const GAS T *xx = Sel<T>::x(I);
+        if (xnow) {
+            const GAS T *xx = Sel<T>::x(I);
+            const GAS T *p2 = Sel<T>::p(I, it + 1);
 #pragma unroll
-        for (int j = 0; j < K; ++j)
+            for (int j = 0; j < K; ++j)
 #pragma unroll
-            for (int rr = 0; rr < RPW; ++rr)
-                xs[j][rr] = xin[rr] ? bld(xx + (size_t)j * n_pix, np, soff[rr]) : (T)0;
+                for (int rr = 0; rr < RPW; ++rr) {
+                    xs[j][rr] = xin[rr] ? bld(xx + (size_t)j * n_pix, np, soff[rr]) : (T)0;
+                    if (pair) po[j][rr] = xin[rr] ? bld(p2 + (size_t)j * n_pix, np, soff[rr]) : (T)0;
+                }
+        }
     }
     // per-pixel mixing blocks (and, for the residual, b) of this lane's R output pixels
     T m[R][MK];
@@ -351,14 +364,35 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
             st->pend = status;
             if (it == 0 && sizeof(T) == 4) { st->rr0 = rr; st->thresh = thresh; }
         }
-        if (it > 0) {   // x_it = x_(it-1) + alpha_(it-1) p_(it-1), also when the run stops here
-            const T a = (T)st->alpha[(it - 1) & 1];
+        if (it > 0 && (xnow || status >= 0)) {   // x_it, also when the run stops here
+            const T a1 = (T)st->alpha[(it - 1) & 1];
             GAS T *xx = Sel<T>::x(I);
+            if (pair) {
+                const T a2 = (T)st->alpha[it & 1];   // alpha_(it-2): update(it) has not run yet
 #pragma unroll
-            for (int j = 0; j < K; ++j)
+                for (int j = 0; j < K; ++j)
 #pragma unroll
-                for (int rr2 = 0; rr2 < RPW; ++rr2)
-                    if (xin[rr2]) bst(xx + (size_t)j * n_pix, np, soff[rr2], xs[j][rr2] + a * sa[j][rr2]);
+                    for (int rr2 = 0; rr2 < RPW; ++rr2)
+                        if (xin[rr2]) {
+                            const T x1 = xs[j][rr2] + a2 * po[j][rr2];
+                            bst(xx + (size_t)j * n_pix, np, soff[rr2], x1 + a1 * sa[j][rr2]);
+                        }
+            } else if (xnow) {
+#pragma unroll
+                for (int j = 0; j < K; ++j)
+#pragma unroll
+                    for (int rr2 = 0; rr2 < RPW; ++rr2)
+                        if (xin[rr2]) bst(xx + (size_t)j * n_pix, np, soff[rr2], xs[j][rr2] + a1 * sa[j][rr2]);
+            } else {   // float64, odd it: the run stops here; alpha_(it-2) p_(it-2) is in x
+#pragma unroll
+                for (int j = 0; j < K; ++j)
+#pragma unroll
+                    for (int rr2 = 0; rr2 < RPW; ++rr2)
+                        if (xin[rr2]) {
+                            const T x0v = bld(xx + (size_t)j * n_pix, np, soff[rr2]);
+                            bst(xx + (size_t)j * n_pix, np, soff[rr2], x0v + a1 * sa[j][rr2]);
+                        }
+            }
         }
         if (status >= 0) return;
         if (it > 0) beta = (T)(rz / st->rho[(it - 1) & 1]);

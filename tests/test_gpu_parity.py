@@ -303,6 +303,28 @@ def test_folded_reductions_match(precision, monkeypatch):
         off += n
 
 
+@pytest.mark.parametrize("precision", [sy.SYLV_PREC_F64, sy.SYLV_PREC_MIXED])
+def test_iterate_complete_at_every_stop(precision):
+    """Runs stopped after j = 1..7 iterations (odd and even: float64 runs advance x two steps at a
+    time and flush a pending step when they stop) hold the j-th iterate: the recomputed residual
+    b - G x equals the recursive residual of the run."""
+    prob = make_problem(40, 36, 3, 5, seed=830, noise="hetero")
+    dp = sy.DeviceProblem.from_numpy(prob)
+    say("stops", precision)
+    for j in range(1, 8):
+        X, st = sy.pcg_solve(dp, Y=dev(prob.Y), opts=sy.SolveOptions(
+            tol=1e-14, max_iter=j, precision=sy.SYLV_PREC_F64, check_every=1))
+        s0 = st[0]
+        assert s0["status"] == sy.binding.SYLV_NOT_CONVERGED and s0["iters"] == j, s0
+        assert s0["relres_true"] == pytest.approx(s0["relres_rec"], rel=1e-9), (j, s0)
+        x = host(X).reshape(prob.k, prob.n_pix)
+        assert rel(op.apply(prob, x), op.rhs(prob)) == pytest.approx(s0["relres_true"], rel=1e-6)
+    if precision == sy.SYLV_PREC_MIXED:
+        X, st = sy.pcg_solve(dp, Y=dev(prob.Y), opts=sy.SolveOptions(tol=1e-10, precision=precision))
+        assert st[0]["status"] == 0
+        assert rel(host(X).reshape(prob.k, prob.n_pix), osv.solve_dense(prob)) < 1e-7
+
+
 def test_solve_not_converged_reported():
     prob = make_problem(32, 32, 3, 6, seed=803)
     say("max_iter=2")
