@@ -42,6 +42,15 @@ int prereduce_min() {
     return v >= 0 ? v : kPreReduce;
 }
 
+// Safety factor of the inner tolerance of mixed runs: kInnerSafety, or SYLV_INNER_SAFETY from
+// the environment (in (0, 1], read at every solve call).
+double inner_safety() {
+    const char *e = getenv("SYLV_INNER_SAFETY");
+    if (!e || !*e) return kInnerSafety;
+    const double v = atof(e);
+    return (v > 0.0 && v <= 1.0) ? v : kInnerSafety;
+}
+
 int apply_rows_request() {
     static int rows = -1;
     if (rows < 0) {
@@ -380,9 +389,9 @@ int run_block_loop(const GroupSet &gset, const InstSet &set, int k, int mixed, i
         for (int c = 0; c < chunk && it <= max_iter; ++c, ++it) {
             if (it > 0) HIP_TRY(launch_bdir(gset, k, mixed, it, s));
             HIP_TRY(launch_bapply(gset, k, mixed, it, s));
-            HIP_TRY(launch_bgram(gset, 1, mixed, 0.0, max_iter, s));
+            HIP_TRY(launch_bgram(gset, 1, mixed, 0.0, 0.0, max_iter, s));
             HIP_TRY(launch_bupdate(gset, k, mixed, it, s));
-            HIP_TRY(launch_bgram(gset, 2, mixed, 0.0, max_iter, s));
+            HIP_TRY(launch_bgram(gset, 2, mixed, 0.0, 0.0, max_iter, s));
         }
         return post_count(set, mixed, f, slot, s);
     };
@@ -557,12 +566,13 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
     HIP_TRY(launch_resid(set, k, 0, s));   // r0 = b - G x0, ||b||, ||r0||
     HIP_TRY(launch_resid_fin(set, 0, s));
     const double inner_tol = opts->inner_tol > 0.0 ? opts->inner_tol : 1e-5;
+    const double safety = inner_safety();
     auto start_run = [&]() -> int {
         if (block) {
             HIP_TRY(launch_bpinit(gset, k, mixed, s));
-            HIP_TRY(launch_bgram(gset, 0, mixed, inner_tol, opts->max_iter, s));
+            HIP_TRY(launch_bgram(gset, 0, mixed, inner_tol, safety, opts->max_iter, s));
         } else {
-            HIP_TRY(launch_pinit(set, k, mixed, inner_tol, opts->max_iter, s));
+            HIP_TRY(launch_pinit(set, k, mixed, inner_tol, safety, opts->max_iter, s));
             HIP_TRY(launch_prereduce_rz(set, s));
         }
         return SYLV_OK;

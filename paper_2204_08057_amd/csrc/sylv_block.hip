@@ -460,7 +460,8 @@ __device__ void chol_solve_small(const double (&l)[kMaxS][kMaxS], double (&b)[kM
 template <int S>
 __global__ __launch_bounds__(kBlock) void k_bgram(const Inst *__restrict__ tab,
                                                   const Group *__restrict__ groups, int phase,
-                                                  int mixed, double inner_tol, int max_iter) {
+                                                  int mixed, double inner_tol, double safety,
+                                                  int max_iter) {
     constexpr int NG = gram_n<S>();
     constexpr int NQ = NG + S;
     const Group &G = groups[blockIdx.x];
@@ -504,7 +505,7 @@ __global__ __launch_bounds__(kBlock) void k_bgram(const Inst *__restrict__ tab,
             if (mixed) {
                 act = !I.st->done;
                 if (act) {
-                    const double need = 0.3 * sqrt(I.st->thresh / fmax(I.st->rr, 1e-300));
+                    const double need = safety * sqrt(I.st->thresh / fmax(I.st->rr, 1e-300));
                     tol = fmin(0.1, fmax(inner_tol, need));
                 }
                 st->tol = tol;
@@ -714,12 +715,12 @@ hipError_t launch_bpinit(const GroupSet &g, int k, int mixed, hipStream_t st) {
     });
 }
 
-hipError_t launch_bgram(const GroupSet &g, int phase, int mixed, double inner_tol, int max_iter,
-                        hipStream_t st) {
+hipError_t launch_bgram(const GroupSet &g, int phase, int mixed, double inner_tol, double safety,
+                        int max_iter, hipStream_t st) {
     return dispatch_s(g.s, [&](auto stag) {
         constexpr int S = decltype(stag)::value;
         hipLaunchKernelGGL((k_bgram<S>), dim3(g.ngroup), dim3(kBlock), 0, st, g.table, g.groups,
-                           phase, mixed, inner_tol, max_iter);
+                           phase, mixed, inner_tol, safety, max_iter);
         return hipGetLastError();
     });
 }

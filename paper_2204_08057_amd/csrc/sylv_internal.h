@@ -27,6 +27,12 @@ constexpr int kMaxRestarts = 3;   // residual replacements of a float64 run
 // workgroup count, so instances with more partials than this fold them first in a separate
 // one-workgroup-per-instance kernel.
 constexpr int kPreReduce = 2048;
+// Mixed precision: a float32 inner run asks for safety * sqrt(threshold / ||r||^2) of its
+// starting residual, so that the refinement step lands below the outer threshold with margin.
+// The float64 residual after the step tracks the float32 recursive one to a few per cent at these
+// levels (it lands at about safety * tol), so 0.7 keeps a 30 % margin; smaller factors only
+// overshoot the tolerance at the price of extra iterations (0.3: 4 more at 1024^2, 7 at 2048^2).
+constexpr double kInnerSafety = 0.7;
 
 // Solver state of one conjugate-gradient run, in device memory.  The scalars of the recurrence
 // (Alg. 2: alpha, beta, <r, z>, ||r||) are formed on the device; the host only reads `done`.
@@ -171,8 +177,8 @@ hipError_t launch_precond_plain(const Inst *table0, int k, int dtype, int n_pix,
 // 1: final true residual only, 2: refinement step of the mixed path
 hipError_t launch_resid(const InstSet &set, int k, int phase, hipStream_t s);
 hipError_t launch_resid_fin(const InstSet &set, int phase, hipStream_t s);
-hipError_t launch_pinit(const InstSet &set, int k, int mixed, double inner_tol, int max_iter,
-                        hipStream_t s);
+hipError_t launch_pinit(const InstSet &set, int k, int mixed, double inner_tol, double safety,
+                        int max_iter, hipStream_t s);
 hipError_t launch_cg_apply(const InstSet &set, int k, int mixed, int it, hipStream_t s);
 hipError_t launch_cg_update(const InstSet &set, int k, int mixed, int it, hipStream_t s);
 hipError_t launch_refine_axpy(const InstSet &set, int k, hipStream_t s);
@@ -197,8 +203,8 @@ int grad_nv(int k, int f);
 // block CG (sylv_block.hip); s in {2, 4, 8}
 int block_rhs_supported(int s);
 hipError_t launch_bpinit(const GroupSet &g, int k, int mixed, hipStream_t st);
-hipError_t launch_bgram(const GroupSet &g, int phase, int mixed, double inner_tol, int max_iter,
-                        hipStream_t st);
+hipError_t launch_bgram(const GroupSet &g, int phase, int mixed, double inner_tol, double safety,
+                        int max_iter, hipStream_t st);
 hipError_t launch_bdir(const GroupSet &g, int k, int mixed, int it, hipStream_t st);
 hipError_t launch_bapply(const GroupSet &g, int k, int mixed, int it, hipStream_t st);
 hipError_t launch_bupdate(const GroupSet &g, int k, int mixed, int it, hipStream_t st);

@@ -669,12 +669,13 @@ __global__ __launch_bounds__(kBlock) void k_update(const Inst *__restrict__ tab,
 // T = double: r is the float64 residual of the float64 run.
 // T = float : start of an inner run of the mixed path: the float64 outer residual I.r is
 //             rounded to float32 (r32), the correction d32 is zeroed, and the inner tolerance
-//             asks for the reduction that brings the outer residual to tolerance (with a 0.3
-//             safety factor), but never less than `inner_tol` nor more than 0.1.
+//             asks for the reduction that brings the outer residual to tolerance (times the
+//             `safety` factor), but never less than `inner_tol` nor more than 0.1.
 template <typename T, int K>
 __global__ __launch_bounds__(kBlock) void k_pinit(const Inst *__restrict__ tab,
                                                   const int *__restrict__ cprefix, int ninst,
-                                                  int nb, double inner_tol, int max_iter) {
+                                                  int nb, double inner_tol, double safety,
+                                                  int max_iter) {
     const int L = xcd_remap(blockIdx.x, nb);
     const int ii = find_inst(cprefix, ninst, L);
     const Inst &I = tab[ii];
@@ -694,7 +695,7 @@ __global__ __launch_bounds__(kBlock) void k_pinit(const Inst *__restrict__ tab,
         if constexpr (sizeof(T) == 4) {
             st->done = 0;
             st->status = SYLV_OK;
-            const double need = 0.3 * sqrt(outer->thresh / fmax(outer->rr, 1e-300));
+            const double need = safety * sqrt(outer->thresh / fmax(outer->rr, 1e-300));
             st->tol = fmin(0.1, fmax(inner_tol, need));
         }
     }
@@ -1189,17 +1190,17 @@ hipError_t launch_cg_update(const InstSet &set, int k, int mixed, int it, hipStr
     });
 }
 
-hipError_t launch_pinit(const InstSet &set, int k, int mixed, double inner_tol, int max_iter,
-                        hipStream_t s) {
+hipError_t launch_pinit(const InstSet &set, int k, int mixed, double inner_tol, double safety,
+                        int max_iter, hipStream_t s) {
     return dispatch_k(k, [&](auto tag) {
         constexpr int K = decltype(tag)::value;
         const dim3 grid(set.total_chunks);
         if (mixed)
             hipLaunchKernelGGL((k_pinit<float, K>), grid, dim3(kBlock), 0, s, set.table,
-                               set.cprefix, set.ninst, (int)grid.x, inner_tol, max_iter);
+                               set.cprefix, set.ninst, (int)grid.x, inner_tol, safety, max_iter);
         else
             hipLaunchKernelGGL((k_pinit<double, K>), grid, dim3(kBlock), 0, s, set.table,
-                               set.cprefix, set.ninst, (int)grid.x, inner_tol, max_iter);
+                               set.cprefix, set.ninst, (int)grid.x, inner_tol, safety, max_iter);
         return hipGetLastError();
     });
 }
