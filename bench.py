@@ -192,11 +192,10 @@ def bench_masked(sy, torch, steps, warmup):
     return res
 
 
-def bench_other_workloads(sy, torch, steps, warmup, cpu=False):
-    """The other workloads of the solver, timed the same way (not the headline value)."""
+def bench_batched(sy, torch, steps, warmup):
+    """8 uneven grids x 8 perturbation-optimisation right-hand sides (64 posterior samples):
+    independent and block CG, mixed precision and float64."""
     from workloads import WORKLOADS, workload
-    out = {"masked_2048": bench_masked(sy, torch, steps, warmup)}
-    # 8 uneven grids x 8 perturbation-optimisation right-hand sides (64 posterior samples)
     probs = workload("batched_8grids")
     nrhs = WORKLOADS["batched_8grids"]["nrhs"]
     dps = [sy.DeviceProblem.from_numpy(p) for p in probs]
@@ -221,8 +220,14 @@ def bench_other_workloads(sy, torch, steps, warmup, cpu=False):
         log(f"batched_8grids {label}: {res[label]}")
     res["right_hand_sides"] = len(probs) * nrhs
     res["pixels"] = sum(p.n_pix for p in probs)
-    out["batched_8grids"] = res
-    del dps, Y, B
+    return res
+
+
+def bench_other_workloads(sy, torch, steps, warmup, cpu=False):
+    """The other workloads of the solver, timed the same way (not the headline value)."""
+    from workloads import WORKLOADS, workload
+    out = {"masked_2048": bench_masked(sy, torch, steps, warmup),
+           "batched_8grids": bench_batched(sy, torch, steps, warmup)}
     # 512^2, k = 4, f = 9: forward solve + adjoint (gradients w.r.t. kappa, tau, A, W, Y)
     prob = workload("grad_512")[0]
     dp = sy.DeviceProblem.from_numpy(prob)
@@ -386,11 +391,11 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the 2048^2, batched and differentiable workloads")
     ap.add_argument("--mode", default="bench",
-                    choices=["bench", "pmc", "sylv", "sky", "sweep", "masked"],
+                    choices=["bench", "pmc", "sylv", "sky", "sweep", "masked", "batched"],
                     help="pmc: copy + applies + one solve of each precision (counter runs); "
                          "sylv: only the Lanczos-Sylvester workload; sky: only the 12-face "
                          "full-sky workload; sweep: only the hyperparameter sweep; masked: only "
-                         "the 2048^2 masked workload")
+                         "the 2048^2 masked workload; batched: only the 8-grid batch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver has no "
@@ -407,6 +412,10 @@ def main():
     if args.mode == "sylv":
         print(json.dumps({"mode": "sylv", "sylv_1024": bench_sylvester(
             sy, torch, max(2, args.steps // 2), max(1, args.warmup))}), flush=True)
+        return
+    if args.mode == "batched":
+        print(json.dumps({"mode": "batched", "batched_8grids": bench_batched(
+            sy, torch, args.steps, args.warmup)}), flush=True)
         return
     if args.mode == "masked":
         print(json.dumps({"mode": "masked", "masked_2048": bench_masked(

@@ -414,38 +414,53 @@ __global__ __launch_bounds__(kBlock) void k_bupdate(const Inst *__restrict__ tab
 }
 
 // ---- small dense float64 algebra (one thread) -----------------------------------------------
-// Cholesky of the n x n leading block of a (row stride kMaxS), in place (lower triangle).
-// Fails when a pivot is not positive or falls below 1e-13 of the largest diagonal entry.
-__device__ bool chol_small(double (&a)[kMaxS][kMaxS], int n) {
+// Cholesky in place (lower triangle); fails when an active pivot is not positive or falls below
+// 1e-13 of the largest active diagonal entry.
+// The same factorisation and solve on the full S x S system with the inactive rows and columns
+// set to the identity (and zero right-hand sides): the loops are static, so the matrices stay in
+// registers, and every term an inactive index adds is an exact zero, so the active entries are
+// bitwise those of the compacted system.  The breakdown test scales by the active diagonal only.
+template <int S>
+__device__ __forceinline__ bool chol_masked(double (&a)[S][S], const bool (&act)[S]) {
     double dmax = 0.0;
-    for (int i = 0; i < n; ++i) dmax = fmax(dmax, fabs(a[i][i]));
-    for (int c = 0; c < n; ++c) {
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+        if (act[i]) dmax = fmax(dmax, fabs(a[i][i]));
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < S; ++c) {
         double s = a[c][c];
+#pragma unroll
         for (int t = 0; t < c; ++t) s -= a[c][t] * a[c][t];
-        if (!(s > 1e-13 * dmax) || !isfinite(s)) return false;
-        const double d = sqrt(s);
+        if (act[c] && (!(s > 1e-13 * dmax) || !isfinite(s))) ok = false;
+        const double d = sqrt(s > 0.0 ? s : 1.0);
         a[c][c] = d;
-        for (int r = c + 1; r < n; ++r) {
+#pragma unroll
+        for (int r = c + 1; r < S; ++r) {
             double v = a[r][c];
+#pragma unroll
             for (int t = 0; t < c; ++t) v -= a[r][t] * a[c][t];
             a[r][c] = v / d;
         }
     }
-    return true;
+    return ok;
 }
-
-// Solve (L L^T) X = B for n x n B in place (columns independently).
-__device__ void chol_solve_small(const double (&l)[kMaxS][kMaxS], double (&b)[kMaxS][kMaxS],
-                                 int n) {
-    for (int col = 0; col < n; ++col) {
-        for (int r = 0; r < n; ++r) {
+template <int S>
+__device__ __forceinline__ void chol_solve_masked(const double (&l)[S][S], double (&b)[S][S]) {
+#pragma unroll
+    for (int col = 0; col < S; ++col) {
+#pragma unroll
+        for (int r = 0; r < S; ++r) {
             double v = b[r][col];
+#pragma unroll
             for (int t = 0; t < r; ++t) v -= l[r][t] * b[t][col];
             b[r][col] = v / l[r][r];
         }
-        for (int r = n - 1; r >= 0; --r) {
+#pragma unroll
+        for (int r = S - 1; r >= 0; --r) {
             double v = b[r][col];
-            for (int t = r + 1; t < n; ++t) v -= l[t][r] * b[t][col];
+#pragma unroll
+            for (int t = r + 1; t < S; ++t) v -= l[t][r] * b[t][col];
             b[r][col] = v / l[r][r];
         }
     }
@@ -457,6 +472,24 @@ __device__ void chol_solve_small(const double (&l)[kMaxS][kMaxS], double (&b)[kM
 //  phase 2: per-column stopping test, beta = (R^T Z)_old^-1 (R^T Z)_new (after k_bupdate)
 // Column states are mirrored into each instance's DevState (float64 run, or the inner run of
 // the mixed path), which the completion count and the statistics read.
+// Fold the per-workgroup partials of one Gram quantity of one group (fixed order, four loads in
+// flight per thread) into entry 0: grid (groups, quantities).  Phase 1 sums the P^T Q partials
+// of the apply tiles, phases 0 and 2 the R^T Z and ||r||^2 partials of the streaming chunks.
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_bgram_fold(const Group *__restrict__ groups,
+                                                       int phase, int mixed) {
+    constexpr int NG = gram_n<S>();
+    constexpr int NQ = NG + S;
+    const Group &G = groups[blockIdx.x];
+    const int i = blockIdx.y;
+    if (i >= ((phase == 1) ? NG : NQ)) return;
+    if (phase != 0 && G.gs->done) return;
+    const int nsum = (phase == 1) ? (mixed ? G.ntiles32 : G.ntiles) : G.nchunks;
+    double v[1];
+    consume<1>(G.partial, G.nred, i, nsum, v);   // every read precedes its final barrier
+    if (threadIdx.x == 0) gp(G.partial)[(size_t)i * G.nred] = v[0];
+}
+
 template <int S>
 __global__ __launch_bounds__(kBlock) void k_bgram(const Inst *__restrict__ tab,
                                                   const Group *__restrict__ groups, int phase,
@@ -467,17 +500,11 @@ __global__ __launch_bounds__(kBlock) void k_bgram(const Inst *__restrict__ tab,
     const Group &G = groups[blockIdx.x];
     GroupState *gs = G.gs;
     if (phase != 0 && gs->done) return;
-    const int nsum = (phase == 1) ? (mixed ? G.ntiles32 : G.ntiles) : G.nchunks;
     const int nq = (phase == 1) ? NG : NQ;
+    // k_bgram_fold has summed every quantity's partials into entry 0
     __shared__ double q[NQ];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const GAS double *pp = gp(G.partial);
-    for (int i = wid; i < nq; i += kBlock / 64) {
-        double s = 0.0;
-        for (int b = lane; b < nsum; b += 64) s += pp[(size_t)i * G.nred + b];
-        s = wave_sum(s);
-        if (lane == 0) q[i] = s;
-    }
+    for (int i = threadIdx.x; i < nq; i += kBlock) q[i] = pp[(size_t)i * G.nred];
     __syncthreads();
     if (threadIdx.x != 0) return;
 
@@ -548,48 +575,63 @@ __global__ __launch_bounds__(kBlock) void k_bgram(const Inst *__restrict__ tab,
         return;
     }
 
-    int A[kMaxS], n = 0;
-    for (int r = 0; r < S; ++r)
-        if (gs->active[r]) A[n++] = r;
+    bool act0[S];   // columns active at entry (static loops keep the small arrays in registers)
+#pragma unroll
+    for (int r = 0; r < S; ++r) act0[r] = gs->active[r] != 0;
 
     if (phase == 1) {
-        double alpha[kMaxS][kMaxS];
-        for (int a = 0; a < kMaxS; ++a)
-            for (int b = 0; b < kMaxS; ++b) alpha[a][b] = 0.0;
+        double alpha[S][S];
+#pragma unroll
+        for (int a = 0; a < S; ++a)
+#pragma unroll
+            for (int b = 0; b < S; ++b) alpha[a][b] = 0.0;
         bool ok = false;
         if (gs->mode == BM_BLOCK) {
-            double l[kMaxS][kMaxS], x[kMaxS][kMaxS];
-            for (int a = 0; a < n; ++a)
-                for (int b = 0; b < n; ++b) {
-                    l[a][b] = q[pidx<S>(A[a], A[b])];
-                    x[a][b] = gs->rz[A[a]][A[b]];
+            bool act[S];
+#pragma unroll
+            for (int r = 0; r < S; ++r) act[r] = gs->active[r] != 0;
+            double l[S][S], x[S][S];
+#pragma unroll
+            for (int a = 0; a < S; ++a)
+#pragma unroll
+                for (int b = 0; b < S; ++b) {
+                    const bool on = act[a] && act[b];
+                    l[a][b] = on ? q[pidx<S>(a, b)] : (a == b ? 1.0 : 0.0);
+                    x[a][b] = on ? gs->rz[a][b] : 0.0;
                 }
-            ok = chol_small(l, n);
+            ok = chol_masked<S>(l, act);
             if (ok) {
-                chol_solve_small(l, x, n);
-                for (int a = 0; a < n; ++a)
-                    for (int b = 0; b < n; ++b) {
+                chol_solve_masked<S>(l, x);
+#pragma unroll
+                for (int a = 0; a < S; ++a)
+#pragma unroll
+                    for (int b = 0; b < S; ++b) {
                         if (!isfinite(x[a][b])) ok = false;
-                        alpha[A[a]][A[b]] = x[a][b];
+                        alpha[a][b] = x[a][b];
                     }
             }
             if (!ok) {
                 gs->mode = BM_DIAG;
                 gs->restart = 1;
-                for (int a = 0; a < kMaxS; ++a)
-                    for (int b = 0; b < kMaxS; ++b) alpha[a][b] = 0.0;
+#pragma unroll
+                for (int a = 0; a < S; ++a)
+#pragma unroll
+                    for (int b = 0; b < S; ++b) alpha[a][b] = 0.0;
             }
         }
         if (gs->mode == BM_DIAG) {
-            for (int a = 0; a < n; ++a) {
-                const int r = A[a];
+#pragma unroll
+            for (int r = 0; r < S; ++r) {
+                if (!act0[r]) continue;
                 const double pq = q[pidx<S>(r, r)];
                 if (!isfinite(pq)) finish(r, SYLV_NONFINITE);
                 else if (!(pq > 0.0)) finish(r, SYLV_BREAKDOWN);
                 else alpha[r][r] = gs->rz[r][r] / pq;
             }
         }
+#pragma unroll
         for (int a = 0; a < S; ++a)
+#pragma unroll
             for (int b = 0; b < S; ++b) gs->alpha[a][b] = alpha[a][b];
         int left = 0;
         for (int r = 0; r < S; ++r) left += gs->active[r];
@@ -599,8 +641,9 @@ __global__ __launch_bounds__(kBlock) void k_bgram(const Inst *__restrict__ tab,
 
     // phase 2
     gs->iter += 1;
-    for (int a = 0; a < n; ++a) {
-        const int r = A[a];
+#pragma unroll
+    for (int r = 0; r < S; ++r) {
+        if (!act0[r]) continue;
         const double rr = q[NG + r];
         gs->rr[r] = rr;
         DevState *st = state(r);
@@ -610,44 +653,61 @@ __global__ __launch_bounds__(kBlock) void k_bgram(const Inst *__restrict__ tab,
         else if (rr <= gs->thresh[r]) finish(r, SYLV_OK);
         else if (gs->iter >= max_iter) finish(r, SYLV_NOT_CONVERGED);
     }
-    int B[kMaxS], m = 0;
-    for (int r = 0; r < S; ++r)
-        if (gs->active[r]) B[m++] = r;
-    double beta[kMaxS][kMaxS];
-    for (int a = 0; a < kMaxS; ++a)
-        for (int b = 0; b < kMaxS; ++b) beta[a][b] = 0.0;
+    bool act1[S];   // columns still active after this step's stopping tests
+    int m = 0;
+#pragma unroll
+    for (int r = 0; r < S; ++r) {
+        act1[r] = gs->active[r] != 0;
+        m += act1[r] ? 1 : 0;
+    }
+    double beta[S][S];
+#pragma unroll
+    for (int a = 0; a < S; ++a)
+#pragma unroll
+        for (int b = 0; b < S; ++b) beta[a][b] = 0.0;
     if (gs->restart) {
         gs->restart = 0;
     } else if (gs->mode == BM_BLOCK && m > 0) {
-        double l[kMaxS][kMaxS], x[kMaxS][kMaxS];
-        for (int a = 0; a < m; ++a)
-            for (int b = 0; b < m; ++b) {
-                l[a][b] = gs->rz[B[a]][B[b]];
-                x[a][b] = q[pidx<S>(B[a], B[b])];
+        const bool (&act)[S] = act1;
+        double l[S][S], x[S][S];
+#pragma unroll
+        for (int a = 0; a < S; ++a)
+#pragma unroll
+            for (int b = 0; b < S; ++b) {
+                const bool on = act[a] && act[b];
+                l[a][b] = on ? gs->rz[a][b] : (a == b ? 1.0 : 0.0);
+                x[a][b] = on ? q[pidx<S>(a, b)] : 0.0;
             }
-        bool ok = chol_small(l, m);
+        bool ok = chol_masked<S>(l, act);
         if (ok) {
-            chol_solve_small(l, x, m);
-            for (int a = 0; a < m; ++a)
-                for (int b = 0; b < m; ++b) {
+            chol_solve_masked<S>(l, x);
+#pragma unroll
+            for (int a = 0; a < S; ++a)
+#pragma unroll
+                for (int b = 0; b < S; ++b) {
                     if (!isfinite(x[a][b])) ok = false;
-                    beta[B[a]][B[b]] = x[a][b];
+                    beta[a][b] = x[a][b];
                 }
         }
         if (!ok) {   // restart as independent CG
             gs->mode = BM_DIAG;
-            for (int a = 0; a < kMaxS; ++a)
-                for (int b = 0; b < kMaxS; ++b) beta[a][b] = 0.0;
+#pragma unroll
+            for (int a = 0; a < S; ++a)
+#pragma unroll
+                for (int b = 0; b < S; ++b) beta[a][b] = 0.0;
         }
     } else if (gs->mode == BM_DIAG) {
-        for (int a = 0; a < m; ++a) {
-            const int r = B[a];
+#pragma unroll
+        for (int r = 0; r < S; ++r) {
+            if (!act1[r]) continue;
             const double rzn = q[pidx<S>(r, r)], rzo = gs->rz[r][r];
             if (!(rzn > 0.0)) finish(r, SYLV_BREAKDOWN);
             else beta[r][r] = rzn / rzo;
         }
     }
+#pragma unroll
     for (int a = 0; a < S; ++a)
+#pragma unroll
         for (int b = 0; b < S; ++b) {
             gs->rz[a][b] = q[pidx<S>(a, b)];
             gs->beta[a][b] = beta[a][b];
@@ -719,6 +779,10 @@ hipError_t launch_bgram(const GroupSet &g, int phase, int mixed, double inner_to
                         int max_iter, hipStream_t st) {
     return dispatch_s(g.s, [&](auto stag) {
         constexpr int S = decltype(stag)::value;
+        hipLaunchKernelGGL((k_bgram_fold<S>), dim3(g.ngroup, gram_n<S>() + S), dim3(kBlock), 0,
+                           st, g.groups, phase, mixed);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_bgram<S>), dim3(g.ngroup), dim3(kBlock), 0, st, g.table, g.groups,
                            phase, mixed, inner_tol, safety, max_iter);
         return hipGetLastError();
