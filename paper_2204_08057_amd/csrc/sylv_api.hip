@@ -545,8 +545,6 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
         gset.total_tiles = gt[nprob];
         gset.total_tiles32 = gt32[nprob];
         gset.total_chunks = gc[nprob];
-        gset.rows64 = kBlockRows;
-        gset.rows32 = kBlockRows;
         gset.bc = bc;
     }
 

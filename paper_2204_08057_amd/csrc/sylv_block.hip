@@ -732,8 +732,10 @@ hipError_t dispatch_s(int s, F &&fn) {
     }
 }
 
+// The block apply keeps every column's direction at its output pixels in registers: 2 rows per
+// lane on every grid.
 template <typename T, int K, int S>
-hipError_t launch_bapply_t(const GroupSet &gset, int rows, int total, const int *prefix, int it,
+hipError_t launch_bapply_t(const GroupSet &gset, int total, const int *prefix, int it,
                            hipStream_t st) {
     const dim3 grid(total);
     if (gset.bc == SYLV_BC_FACE) {
@@ -741,16 +743,8 @@ hipError_t launch_bapply_t(const GroupSet &gset, int rows, int total, const int 
                            gset.table, gset.groups, prefix, gset.ngroup, (int)grid.x, it);
         return hipGetLastError();
     }
-    switch (rows) {
-        case 4:
-            hipLaunchKernelGGL((k_bapply<T, K, 4, S, BC_PERIODIC>), grid, dim3(kBlock), 0, st,
-                               gset.table, gset.groups, prefix, gset.ngroup, (int)grid.x, it);
-            break;
-        default:
-            hipLaunchKernelGGL((k_bapply<T, K, 2, S, BC_PERIODIC>), grid, dim3(kBlock), 0, st,
-                               gset.table, gset.groups, prefix, gset.ngroup, (int)grid.x, it);
-            break;
-    }
+    hipLaunchKernelGGL((k_bapply<T, K, 2, S, BC_PERIODIC>), grid, dim3(kBlock), 0, st, gset.table,
+                       gset.groups, prefix, gset.ngroup, (int)grid.x, it);
     return hipGetLastError();
 }
 
@@ -812,9 +806,9 @@ hipError_t launch_bapply(const GroupSet &g, int k, int mixed, int it, hipStream_
         return dispatch_k(k, [&](auto tag) {
             constexpr int K = decltype(tag)::value;
             if (mixed)
-                return launch_bapply_t<float, K, S>(g, g.rows32, g.total_tiles32, g.gtprefix32,
+                return launch_bapply_t<float, K, S>(g, g.total_tiles32, g.gtprefix32,
                                                     it, st);
-            return launch_bapply_t<double, K, S>(g, g.rows64, g.total_tiles, g.gtprefix, it, st);
+            return launch_bapply_t<double, K, S>(g, g.total_tiles, g.gtprefix, it, st);
         });
     });
 }

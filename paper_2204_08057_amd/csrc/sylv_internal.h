@@ -27,6 +27,10 @@ constexpr int kMaxRestarts = 3;   // residual replacements of a float64 run
 // workgroup count, so instances with more partials than this fold them first in a separate
 // one-workgroup-per-instance kernel.
 constexpr int kPreReduce = 2048;
+// Largest rows per lane of the apply kernels that keeps their register window without spills.
+constexpr int apply_rows_cap(bool f64, int k) {
+    return f64 ? (k <= 2 ? 8 : k <= 3 ? 4 : 2) : (k <= 2 ? 8 : k <= 5 ? 4 : 2);
+}
 // Mixed precision: a float32 inner run asks for safety * sqrt(threshold / ||r||^2) of its
 // starting residual, so that the refinement step lands below the outer threshold with margin.
 // The float64 residual after the step tracks the float32 recursive one to a few per cent at these
@@ -152,7 +156,6 @@ struct GroupSet {
     const int *gcprefix;         // device [ngroup + 1] chunks
     int ngroup, s;
     int total_tiles, total_tiles32, total_chunks;
-    int rows64, rows32;
     int bc;
 };
 

@@ -1040,10 +1040,12 @@ __global__ void k_grad_fin(const double *__restrict__ partial, int nv, int nblk,
     }
 }
 
-// Face grids always run with 2 rows per lane (the host sizes their tiles accordingly).
+// Face grids always run with 2 rows per lane (the host sizes their tiles accordingly).  Only the
+// row counts that apply_rows_for can return for (T, K) are instantiated.
 template <typename T, int K, int MODE>
 hipError_t launch_apply_rows(int rows, int bc, dim3 grid, hipStream_t s, const Inst *table,
                              const int *tprefix, int ninst, int it, const void *in, void *out) {
+    constexpr int cap = apply_rows_cap(sizeof(T) == 8, K);
     const T *i = reinterpret_cast<const T *>(in);
     T *o = reinterpret_cast<T *>(out);
     const int nb = (int)grid.x;
@@ -1052,20 +1054,22 @@ hipError_t launch_apply_rows(int rows, int bc, dim3 grid, hipStream_t s, const I
                            tprefix, ninst, nb, it, i, o);
         return hipGetLastError();
     }
-    switch (rows) {
-        case 2:
-            hipLaunchKernelGGL((k_apply<T, K, 2, MODE, BC_PERIODIC>), grid, dim3(kBlock), 0, s,
-                               table, tprefix, ninst, nb, it, i, o);
-            break;
-        case 8:
+    if constexpr (cap >= 8) {
+        if (rows == 8) {
             hipLaunchKernelGGL((k_apply<T, K, 8, MODE, BC_PERIODIC>), grid, dim3(kBlock), 0, s,
                                table, tprefix, ninst, nb, it, i, o);
-            break;
-        default:
+            return hipGetLastError();
+        }
+    }
+    if constexpr (cap >= 4) {
+        if (rows == 4) {
             hipLaunchKernelGGL((k_apply<T, K, 4, MODE, BC_PERIODIC>), grid, dim3(kBlock), 0, s,
                                table, tprefix, ninst, nb, it, i, o);
-            break;
+            return hipGetLastError();
+        }
     }
+    hipLaunchKernelGGL((k_apply<T, K, 2, MODE, BC_PERIODIC>), grid, dim3(kBlock), 0, s, table,
+                       tprefix, ninst, nb, it, i, o);
     return hipGetLastError();
 }
 
@@ -1079,7 +1083,7 @@ int apply_rows_for(int k, int dtype, int request) {
     // default: 4 rows where the register window leaves >= 2 waves per SIMD, else 2
     int rows = request;
     if (!apply_rows_valid(rows)) rows = (dtype == SYLV_F64) ? (k <= 3 ? 4 : 2) : (k <= 4 ? 4 : 2);
-    const int cap = (dtype == SYLV_F64) ? (k <= 2 ? 8 : k <= 3 ? 4 : 2) : (k <= 2 ? 8 : k <= 5 ? 4 : 2);
+    const int cap = apply_rows_cap(dtype == SYLV_F64, k);
     return rows < cap ? rows : cap;
 }
 
