@@ -220,6 +220,26 @@ def test_solve_full_size_heteroscedastic(precision):
     assert rel(Yg[:, pix], op.apply_at(prob, x, pix)) < 1e-13
 
 
+@pytest.mark.parametrize("precision", [sy.SYLV_PREC_F64, sy.SYLV_PREC_MIXED])
+def test_solve_full_size_masked_2048(precision):
+    """The 2048^2, k = 4, f = 9 workload with 10 % masked pixels at its timing tolerance 1e-8
+    (4096 partials per reduction, so the CG reductions are folded in a separate kernel): the
+    residual b - G x at sampled pixels (random ones, the first row and column, masked ones),
+    computed by the oracle's operator, is small, and the recursive and true residuals agree."""
+    prob = workload("masked_2048")[0]
+    say("solve masked_2048", precision)
+    x, st = _solve(prob, precision, tol=1e-8)
+    assert st["status"] == 0 and st["relres_true"] <= 1e-8, st
+    rng = np.random.default_rng(2048)
+    masked = np.flatnonzero(prob.W[0] == 0.0)
+    edge = np.concatenate([np.arange(0, prob.nx, 5), np.arange(0, prob.n_pix, 5 * prob.nx)])
+    pix = np.unique(np.concatenate([rng.choice(prob.n_pix, 1500, replace=False), edge,
+                                    masked[:200]]))
+    gx = op.apply_at(prob, x, pix)
+    b = prob.A.T @ (prob.W[:, pix] * prob.Y[:, pix])
+    assert rel(gx, b) < 3e-8
+
+
 def test_solve_warm_start_and_zero_rhs():
     prob = make_problem(20, 24, 3, 5, seed=800)
     xs = osv.solve_dense(prob)
