@@ -240,6 +240,65 @@ def test_solve_full_size_masked_2048(precision):
     assert rel(gx, b) < 3e-8
 
 
+def test_backward_full_size_512():
+    """The 512^2, k = 4, f = 9 differentiable-solve workload at its tolerance 1e-10: the forward
+    and adjoint solutions satisfy G x = b and G lambda = gbar at sampled pixels (the oracle's
+    operator, one pixel at a time), and every gradient equals the oracle's contraction
+    lambda^T (db/dtheta - dG/dtheta x) formed from the GPU's own x and lambda."""
+    prob = workload("grad_512")[0]
+    dp = sy.DeviceProblem.from_numpy(prob)
+    opts = sy.SolveOptions(tol=1e-10)
+    say("backward grad_512")
+    X, st = sy.pcg_solve(dp, Y=dev(prob.Y), opts=opts)
+    assert st[0]["status"] == 0, st
+    gbar = random_maps(prob, 5120)
+    lam, g, stb = sy.pcg_backward(dp, dev(prob.Y), X.reshape(prob.k, prob.n_pix), dev(gbar), opts)
+    assert stb["status"] == 0 and stb["relres_true"] <= 1e-10, stb
+    x, lm = host(X).reshape(prob.k, prob.n_pix), host(lam)
+    pix = np.unique(np.concatenate([np.random.default_rng(512).choice(prob.n_pix, 1500,
+                                                                       replace=False),
+                                    np.arange(0, prob.nx, 3)]))
+    b = prob.A.T @ (prob.W[:, pix] * prob.Y[:, pix])
+    assert rel(op.apply_at(prob, x, pix), b) < 1e-9
+    assert rel(op.apply_at(prob, lm, pix), gbar[:, pix]) < 1e-9
+    g_ref = og.implicit_grads(prob, x, lm)
+    for name in ("kappa", "tau", "A", "W", "Y"):
+        assert rel(host(g[name]), g_ref[name]) < 1e-10, name
+
+
+@pytest.mark.parametrize("block", [0, 1])
+def test_batched_full_size_8grids(block):
+    """The 8 uneven grids (256^2 .. 1024^2) x 8 perturbation-optimisation right-hand sides of
+    the batched workload, mixed precision to 1e-8, independent and block CG in one call: every
+    one of the 64 solutions satisfies G x = b + eta at sampled pixels (oracle operator; eta from
+    the GPU's perturbation map, which its own tests pin)."""
+    from workloads import WORKLOADS
+    probs = workload("batched_8grids")
+    nrhs = WORKLOADS["batched_8grids"]["nrhs"]
+    dps = [sy.DeviceProblem.from_numpy(p) for p in probs]
+    etas = []
+    for g_, (p, d) in enumerate(zip(probs, dps)):
+        xi, zeta = po_draws(p, nrhs, seed=7700 + g_)
+        etas.append(host(sy.po_perturb(d, dev(xi), dev(zeta))).reshape(nrhs, p.k, p.n_pix))
+    Y = torch.cat([dev(p.Y.ravel()) for p in probs])
+    B = torch.cat([dev(e.ravel()) for e in etas])
+    say("batched full size, block", block)
+    X, st = sy.pcg_solve(dps, Y=Y, Bextra=B, nrhs=nrhs,
+                         opts=sy.SolveOptions(tol=1e-8, precision=sy.SYLV_PREC_MIXED, block=block))
+    X = host(X)
+    rng = np.random.default_rng(88)
+    off = 0
+    for g_, p in enumerate(probs):
+        pix = rng.choice(p.n_pix, 300, replace=False)
+        b = p.A.T @ (p.W[:, pix] * p.Y[:, pix])
+        for r in range(nrhs):
+            s_ = st[g_ * nrhs + r]
+            assert s_["status"] == 0 and s_["relres_true"] <= 1e-8, (g_, r, s_)
+            x = X[off:off + p.k * p.n_pix].reshape(p.k, p.n_pix)
+            off += p.k * p.n_pix
+            assert rel(op.apply_at(p, x, pix), b + etas[g_][r][:, pix]) < 3e-8, (g_, r)
+
+
 def test_solve_warm_start_and_zero_rhs():
     prob = make_problem(20, 24, 3, 5, seed=800)
     xs = osv.solve_dense(prob)
