@@ -25,8 +25,9 @@ constexpr int kMaxRestarts = 3;   // residual replacements of a float64 run
 // Every workgroup of a consuming CG kernel re-reduces the producer's per-workgroup partials in a
 // fixed order (no atomics, bitwise repeatable).  That read grows with the square of the
 // workgroup count, so instances with more partials than this fold them first in a separate
-// one-workgroup-per-instance kernel.
-constexpr int kPreReduce = 2048;
+// one-workgroup-per-instance kernel.  Measured: folding 1024 partials (1024^2 at 4 rows per lane)
+// costs more in launches than it saves; 2048 (a 1024^2 face at 2 rows) and up gain.
+constexpr int kPreReduce = 1024;
 // Largest rows per lane of the apply kernels that keeps their register window without spills.
 constexpr int apply_rows_cap(bool f64, int k) {
     return f64 ? (k <= 2 ? 8 : k <= 3 ? 4 : 2) : (k <= 2 ? 8 : k <= 5 ? 4 : 2);
