@@ -24,14 +24,18 @@
  *    comes from the caller's workspace `ws` of `ws_bytes` bytes (256-byte aligned), sized by
  *    sylv_workspace_bytes().  The workspace must not be shared by calls that overlap in time.
  *  - `stream` is a hipStream_t (NULL = the null stream).  sylv_apply, sylv_precond,
- *    sylv_prepare, sylv_rhs and sylv_po_perturb only enqueue work.  sylv_pcg_solve and
- *    sylv_pcg_backward enqueue work and synchronise `stream` a few times to test convergence;
- *    they return when the solve has finished.
+ *    sylv_prepare, sylv_rhs and sylv_po_perturb only enqueue work, with no host
+ *    synchronisation, so they may be captured into a HIP graph.  sylv_pcg_solve and
+ *    sylv_pcg_backward with the adaptive schedule (the default) enqueue work and synchronise
+ *    `stream` a few times to test convergence, returning when the solve has finished; with
+ *    schedule = SYLV_SCHED_FIXED they only enqueue work and may be captured as well.
+ *    sylv_lanczos_solve synchronises at every convergence check (its small projected problems
+ *    are solved on the host) and refuses a capturing stream.
  *  - Return value: 0 on success, a negative SYLV_E_* code when the arguments are rejected before
  *    any work is enqueued (then sylv_last_error() describes why), or SYLV_E_HIP when a HIP call
  *    failed.  Numerical outcomes of a solve (converged, not converged, breakdown, non-finite
  *    values) are reported per solve in sylv_pcg_stats.status, not as the return value.
- *  - Limits: 1 <= k <= 8, 1 <= f <= 16, ny, nx >= 1, ny * nx < 2^31.
+ *  - Limits: 1 <= k <= 8, 1 <= f <= 16, ny, nx >= 1, ny * nx < 2^29.
  *  - Lap is the graph Laplacian of the pixel grid (Section 3's D): periodic, or one HEALPix base
  *    face whose border pixels have fewer neighbours (sylv_problem.boundary).
  */
@@ -74,6 +78,10 @@ extern "C" {
 #define SYLV_STOP_R0 0          /* stopping test relative to the initial residual (Alg. 2)        */
 #define SYLV_STOP_B  1          /* stopping test relative to ||b||                                 */
 
+#define SYLV_SCHED_ADAPTIVE 0   /* host checks convergence between batches of queued iterations  */
+#define SYLV_SCHED_FIXED    1   /* every iteration up to the caps is queued at once, no host
+                                   synchronisation (graph capture)                               */
+
 #define SYLV_PC_NONE   0        /* z = r (plain Alg. 2)                                           */
 #define SYLV_PC_JACOBI 1        /* z = r / diag(G)                                                */
 #define SYLV_PC_BLOCK  2        /* z_p = (G_pp)^-1 r_p, G_pp the k x k block of pixel p           */
@@ -108,7 +116,16 @@ typedef struct sylv_pcg_opts {
     int32_t stop_ref;      /* reference of the stopping test: SYLV_STOP_R0 (||b - G x0||, Alg. 2's
                               test) or SYLV_STOP_B (||b||, for warm starts over a sweep of
                               hyperparameters); the same when x0 = 0                            */
-    int32_t reserved;      /* 0                                                                   */
+    int32_t schedule;      /* SYLV_SCHED_ADAPTIVE: batches of check_every iterations are queued
+                              ahead of a host convergence check, and a float64 run whose
+                              recomputed residual misses the threshold is restarted from its x
+                              (at most 3 times).  SYLV_SCHED_FIXED: max_iter + 1 iterations per
+                              (inner) run and refine_max refinement steps are queued at once with
+                              no host synchronisation and no restart, so the call may be captured
+                              into a HIP graph; launches after a run has converged return at once
+                              (about 1-2 us each), so max_iter and refine_max should be set near
+                              what the solve needs.  Both schedules compute the same iterates: the
+                              device takes every stopping decision.                             */
 } sylv_pcg_opts;
 
 /* Per-solve result, written by the device into caller memory (DEVICE pointer). */

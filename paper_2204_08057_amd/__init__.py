@@ -15,6 +15,8 @@ from .binding import (  # noqa: F401
     SYLV_PC_NONE,
     SYLV_PREC_F64,
     SYLV_PREC_MIXED,
+    SYLV_SCHED_ADAPTIVE,
+    SYLV_SCHED_FIXED,
     SYLV_STOP_B,
     SYLV_STOP_R0,
     STATUS_NAMES,
@@ -36,6 +38,8 @@ from .binding import (  # noqa: F401
     po_perturb,
     precond,
     rhs,
+    solve_launcher,
+    stats_list,
     status_string,
     workspace_bytes,
 )

@@ -34,6 +34,8 @@ SYLV_BC_PERIODIC = 0
 SYLV_BC_FACE = 1
 SYLV_STOP_R0 = 0
 SYLV_STOP_B = 1
+SYLV_SCHED_ADAPTIVE = 0
+SYLV_SCHED_FIXED = 1
 SYLV_PC_NONE = 0
 SYLV_PC_JACOBI = 1
 SYLV_PC_BLOCK = 2
@@ -62,7 +64,7 @@ class _Opts(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("inner_tol", ctypes.c_double),
                 ("refine_max", ctypes.c_int32), ("precond", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("stop_ref", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("stop_ref", ctypes.c_int32), ("schedule", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -230,10 +232,11 @@ class SolveOptions:
     check_every: int = 0
     block: int = 0
     stop_ref: int = SYLV_STOP_R0
+    schedule: int = SYLV_SCHED_ADAPTIVE
 
     def c_struct(self) -> _Opts:
         return _Opts(self.tol, self.max_iter, self.precision, self.inner_tol, self.refine_max,
-                     self.precond, self.check_every, self.block, self.stop_ref, 0)
+                     self.precond, self.check_every, self.block, self.stop_ref, self.schedule)
 
 
 def workspace_bytes(problems: Sequence[DeviceProblem], nrhs: int = 1,
@@ -385,6 +388,45 @@ def pcg_solve(problems, Y=None, Bextra=None, X0=None, opts: Optional[SolveOption
     if return_stats:
         return X, _stats_list(stats, len(probs) * nrhs)
     return X, stats
+
+
+def solve_launcher(problems, X, stats, ws, Y=None, Bextra=None,
+                   opts: Optional[SolveOptions] = None, nrhs: int = 1):
+    """A zero-argument callable that enqueues one sylv_pcg_solve on the stream current at call
+    time, with every argument marshalled once and nothing allocated or synchronised by the
+    call: with opts.schedule = SYLV_SCHED_FIXED it can be captured into a graph
+    (torch.cuda.graph).  X holds the initial guess on entry and the solution on return, stats
+    is a device uint8 tensor of nprob * nrhs * STATS_BYTES bytes (read with `stats_list`), ws a
+    workspace of at least workspace_bytes(problems, nrhs, opts) bytes."""
+    torch = _torch()
+    probs = [problems] if isinstance(problems, DeviceProblem) else list(problems)
+    opts = opts or SolveOptions()
+    total = sum(nrhs * p.k * p.n_pix for p in probs)
+    if X.dtype != torch.float64 or X.numel() != total:
+        raise ValueError(f"X must be float64 with {total} elements")
+    if stats.dtype != torch.uint8 or stats.numel() < len(probs) * nrhs * STATS_BYTES:
+        raise ValueError("stats too small")
+    nbytes = workspace_bytes(probs, nrhs, opts)
+    if ws.numel() < nbytes:
+        raise ValueError(f"workspace of {ws.numel()} bytes, {nbytes} needed")
+    arr = (_Problem * len(probs))(*[p.c_struct() for p in probs])
+    o = opts.c_struct()
+    fn = lib().sylv_pcg_solve
+    args = (arr, len(probs), nrhs, _ptr(Y), _ptr(Bextra), _ptr(X), ctypes.byref(o), _ptr(stats),
+            _ptr(ws), ws.numel())
+
+    def launch():
+        rc = fn(*args, _stream())
+        if rc:
+            _check(rc)
+
+    launch.keep = (arr, o, probs, X, stats, ws, Y, Bextra)
+    return launch
+
+
+def stats_list(stats, n: int):
+    """The first n sylv_pcg_stats records of a device stats tensor, as dicts (synchronises)."""
+    return _stats_list(stats, n)
 
 
 def pcg_backward(problem: DeviceProblem, Y, Xstar, Gbar, opts: Optional[SolveOptions] = None,

@@ -249,6 +249,19 @@ int check_opts(const sylv_pcg_opts *o) {
     if (o->inner_tol < 0.0 || o->inner_tol >= 1.0) { set_err("inner_tol must be in [0, 1)"); return SYLV_E_INVALID; }
     if (o->refine_max < 0 || o->check_every < 0) { set_err("negative refine_max/check_every"); return SYLV_E_INVALID; }
     if (o->stop_ref != SYLV_STOP_R0 && o->stop_ref != SYLV_STOP_B) { set_err("bad stop_ref"); return SYLV_E_INVALID; }
+    if (o->schedule != SYLV_SCHED_ADAPTIVE && o->schedule != SYLV_SCHED_FIXED) { set_err("bad schedule"); return SYLV_E_INVALID; }
+    return SYLV_OK;
+}
+
+// A call that must synchronise refuses a stream under graph capture (a wait there would fail
+// half-way through the enqueued work).
+int refuse_capture(hipStream_t s, const char *what) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &cs));
+    if (cs != hipStreamCaptureStatusNone) {
+        set_err("%s synchronises with the host and cannot be captured", what);
+        return SYLV_E_INVALID;
+    }
     return SYLV_OK;
 }
 
@@ -332,18 +345,29 @@ int next_batch(const Report &prev, const Report &cur, bool have_prev, int queued
 // (stopping test on the residual of update(it-1), new direction, q = G p) followed by
 // update(it); a run that has stopped turns every later kernel of the loop into a no-op, and
 // apply(max_iter) always stops it, so the loop ends.
+static_assert(sizeof(Inst) % 4 == 0 && sizeof(Group) % 4 == 0, "tables upload as 32-bit words");
+
+int cg_iteration(const InstSet &set, int k, int mixed, int it, hipStream_t s) {
+    HIP_TRY(launch_cg_apply(set, k, mixed, it, s));
+    HIP_TRY(launch_prereduce_pq(set, mixed, s));
+    HIP_TRY(launch_cg_update(set, k, mixed, it, s));
+    HIP_TRY(launch_prereduce_rz(set, s));
+    return SYLV_OK;
+}
+
 int run_cg_loop(const InstSet &set, int k, int mixed, int chunk, int max_iter, HostFlags *f,
                 hipStream_t s) {
     int it = 0, rc;
+    if (!f) {   // fixed schedule: every iteration up to the cap, no host check
+        for (; it <= max_iter; ++it)
+            if ((rc = cg_iteration(set, k, mixed, it, s))) return rc;
+        return SYLV_OK;
+    }
     // batches queued and not yet waited for, oldest first, in slots 0 and 1 used alternately
     int pend[2], npend = 0, next_slot = 0;
     auto enqueue_batch = [&](int n) -> int {
-        for (int c = 0; c < n && it <= max_iter; ++c, ++it) {
-            HIP_TRY(launch_cg_apply(set, k, mixed, it, s));
-            HIP_TRY(launch_prereduce_pq(set, mixed, s));
-            HIP_TRY(launch_cg_update(set, k, mixed, it, s));
-            HIP_TRY(launch_prereduce_rz(set, s));
-        }
+        for (int c = 0; c < n && it <= max_iter; ++c, ++it)
+            if (int e = cg_iteration(set, k, mixed, it, s)) return e;
         pend[npend++] = next_slot;
         const int slot = next_slot;
         next_slot ^= 1;
@@ -382,17 +406,27 @@ int run_cg_loop(const InstSet &set, int k, int mixed, int chunk, int max_iter, H
 
 // Block-CG iterations: P = Z + P beta (from the second iteration), Q = G P with the P^T Q
 // Gram, alpha, the block update with the R^T Z Gram, beta and the per-column stopping test.
+int block_iteration(const GroupSet &gset, int k, int mixed, int it, int max_iter,
+                    hipStream_t s) {
+    if (it > 0) HIP_TRY(launch_bdir(gset, k, mixed, it, s));
+    HIP_TRY(launch_bapply(gset, k, mixed, it, s));
+    HIP_TRY(launch_bgram(gset, 1, mixed, 0.0, 0.0, max_iter, s));
+    HIP_TRY(launch_bupdate(gset, k, mixed, it, s));
+    HIP_TRY(launch_bgram(gset, 2, mixed, 0.0, 0.0, max_iter, s));
+    return SYLV_OK;
+}
+
 int run_block_loop(const GroupSet &gset, const InstSet &set, int k, int mixed, int chunk,
                    int max_iter, HostFlags *f, hipStream_t s) {
     int it = 0, rc;
+    if (!f) {   // fixed schedule
+        for (; it <= max_iter; ++it)
+            if ((rc = block_iteration(gset, k, mixed, it, max_iter, s))) return rc;
+        return SYLV_OK;
+    }
     auto enqueue_batch = [&](int slot) -> int {
-        for (int c = 0; c < chunk && it <= max_iter; ++c, ++it) {
-            if (it > 0) HIP_TRY(launch_bdir(gset, k, mixed, it, s));
-            HIP_TRY(launch_bapply(gset, k, mixed, it, s));
-            HIP_TRY(launch_bgram(gset, 1, mixed, 0.0, 0.0, max_iter, s));
-            HIP_TRY(launch_bupdate(gset, k, mixed, it, s));
-            HIP_TRY(launch_bgram(gset, 2, mixed, 0.0, 0.0, max_iter, s));
-        }
+        for (int c = 0; c < chunk && it <= max_iter; ++c, ++it)
+            if (int e = block_iteration(gset, k, mixed, it, max_iter, s)) return e;
         return post_count(set, mixed, f, slot, s);
     };
     if ((rc = enqueue_batch(0))) return rc;
@@ -424,10 +458,17 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
     int rc = check_opts(opts);
     if (rc) return rc;
     if (!X || !stats) { set_err("null X or stats"); return SYLV_E_INVALID; }
+    const bool fixed = opts->schedule == SYLV_SCHED_FIXED;
     if (!Y && !Bextra) { set_err("need Y or Bextra"); return SYLV_E_INVALID; }
+    const bool block = opts->block != 0;
+    if (block && !block_rhs_supported(nrhs)) {
+        set_err("block CG needs nrhs in {2, 4, 8} (got %d)", nrhs);
+        return SYLV_E_INVALID;
+    }
     make_layout(probs, nprob, nrhs, true, L);
     rc = check_ws(ws, ws_bytes, L.total);
     if (rc) return rc;
+    if (!fixed && (rc = refuse_capture(s, "the adaptive schedule"))) return rc;
     char *base = reinterpret_cast<char *>(ws);
     const int mixed = opts->precision == SYLV_PREC_MIXED;
     // face grids run the apply kernels with 2 rows per lane
@@ -484,10 +525,8 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
         xoff += (size_t)nrhs * k * n;
         yoff += (size_t)p.f * n;
     }
-    HIP_TRY(hipMemcpyAsync(base + L.table, tab.data(), sizeof(Inst) * ninst,
-                           hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(base + L.tprefix, pre.data(), sizeof(int) * 3 * (ninst + 1),
-                           hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_upload(base + L.table, tab.data(), sizeof(Inst) * ninst, s));
+    HIP_TRY(launch_upload(base + L.tprefix, pre.data(), sizeof(int) * 3 * (ninst + 1), s));
     InstSet set;
     set.table = reinterpret_cast<const Inst *>(base + L.table);
     set.tprefix = reinterpret_cast<const int *>(base + L.tprefix);
@@ -503,11 +542,6 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
     set.any_pre = any_pre;
 
     // block CG groups: one per problem, its nrhs instances in order
-    const bool block = opts->block != 0;
-    if (block && !block_rhs_supported(nrhs)) {
-        set_err("block CG needs nrhs in {2, 4, 8} (got %d)", nrhs);
-        return SYLV_E_INVALID;
-    }
     GroupSet gset;
     memset(&gset, 0, sizeof(gset));
     if (block) {
@@ -531,10 +565,8 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
             gt32[g + 1] = gt32[g] + G.ntiles32;
             gc[g + 1] = gc[g] + G.nchunks;
         }
-        HIP_TRY(hipMemcpyAsync(base + L.groups, grp.data(), sizeof(Group) * nprob,
-                               hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(base + L.gprefix, gpre.data(), sizeof(int) * 3 * (nprob + 1),
-                               hipMemcpyHostToDevice, s));
+        HIP_TRY(launch_upload(base + L.groups, grp.data(), sizeof(Group) * nprob, s));
+        HIP_TRY(launch_upload(base + L.gprefix, gpre.data(), sizeof(int) * 3 * (nprob + 1), s));
         gset.table = set.table;
         gset.groups = reinterpret_cast<const Group *>(base + L.groups);
         gset.gtprefix = reinterpret_cast<const int *>(base + L.gprefix);
@@ -559,8 +591,8 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
         HIP_TRY(launch_rhs(I.W, I.Y, I.A, I.f, I.n_pix, I.bext, I.b, k, s));
     }
     const int chunk = opts->check_every > 0 ? opts->check_every : 8;
-    HostFlags *flags = nullptr;
-    if ((rc = host_flags(flags))) return rc;
+    HostFlags *flags = nullptr;   // stays null under the fixed schedule
+    if (!fixed && (rc = host_flags(flags))) return rc;
     HIP_TRY(launch_resid(set, k, 0, s));   // r0 = b - G x0, ||b||, ||r0||
     HIP_TRY(launch_resid_fin(set, 0, s));
     const double inner_tol = opts->inner_tol > 0.0 ? opts->inner_tol : 1e-5;
@@ -587,6 +619,7 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
             if ((rc = loop())) return rc;
             HIP_TRY(launch_resid(set, k, 1, s));   // true residual of the result
             HIP_TRY(launch_resid_fin(set, 1, s));
+            if (fixed) break;   // no restart: a reopened run reports SYLV_NOT_CONVERGED
             if ((rc = post_count(set, 0, flags, 2, s))) return rc;
             int reopened = 0;
             if ((rc = wait_count(flags, 2, reopened))) return rc;
@@ -603,6 +636,10 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
             HIP_TRY(launch_refine_axpy(set, k, s));
             HIP_TRY(launch_resid(set, k, 2, s));   // float64 residual of the new x
             HIP_TRY(launch_resid_fin(set, 2, s));
+            if (fixed) {
+                if (o + 1 < refine_max && (rc = start_run())) return rc;
+                continue;
+            }
             if ((rc = post_count(set, 0, flags, 2, s))) return rc;
             if (o + 1 < refine_max && (rc = start_run())) return rc;
             int running = 0;
@@ -838,6 +875,7 @@ int lanczos_impl(const sylv_sep_problem *p, const double *Y, double *X,
     if (!make_lz_layout(p, o, L)) return SYLV_E_INVALID;
     int rc = check_ws(ws, ws_bytes, L.total);
     if (rc) return rc;
+    if ((rc = refuse_capture(s, "sylv_lanczos_solve"))) return rc;
     char *base = reinterpret_cast<char *>(ws);
     // small parameters to the host (Lemma 2's eigenproblem is solved here)
     double tau[kMaxK], A[kMaxF * kMaxK], t[kMaxF];
@@ -991,9 +1029,7 @@ int sylv_prepare(const sylv_problem *prob, int32_t precond, void *ws, size_t ws_
     Inst I = operator_inst(*prob, L.prob[0], base, precond);
     I.ntiles = 0;
     I.nchunks = chunks_for(I.n_pix);
-    HIP_TRY(hipMemcpyAsync(base + L.table, &I, sizeof(Inst), hipMemcpyHostToDevice, s));
-    // pageable source: make sure the copy has consumed it before `I` goes out of scope
-    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(launch_upload(base + L.table, &I, sizeof(Inst), s));
     return SYLV_OK;
 }
 

@@ -22,6 +22,7 @@ constexpr int kChunk = 1024;     // pixels per workgroup in streaming kernels (4
 enum Slot { SLOT_PQ = 0, SLOT_RZ = 1, SLOT_RR = 2, SLOT_RES_RR = 3, SLOT_RES_BB = 4 };
 constexpr int kNumSlots = 5;
 constexpr int kMaxRestarts = 3;   // residual replacements of a float64 run
+constexpr int kUploadWords = 512; // 32-bit words per table-upload launch (2 KiB of arguments)
 // Every workgroup of a consuming CG kernel re-reduces the producer's per-workgroup partials in a
 // fixed order (no atomics, bitwise repeatable).  That read grows with the square of the
 // workgroup count, so instances with more partials than this fold them first in a separate
@@ -189,6 +190,9 @@ hipError_t launch_refine_axpy(const InstSet &set, int k, hipStream_t s);
 hipError_t launch_state_init(const InstSet &set, double tol, int max_iter, int ref,
                              hipStream_t s);
 hipError_t launch_count_running(const InstSet &set, int inner, int *out, hipStream_t s);
+// Copy `bytes` (a multiple of 4) of host memory to device memory `dst` in stream order, through
+// kernel arguments (kUploadWords words per launch).  `src` may be freed on return.
+hipError_t launch_upload(void *dst, const void *src, size_t bytes, hipStream_t s);
 // Fold the partials of <p, q> (after a CG apply) or of <r, z>, ||r||^2 (after an update or a
 // run start) of the instances with Inst::pre set; a no-op launch is skipped when none has it.
 hipError_t launch_prereduce_pq(const InstSet &set, int mixed, hipStream_t s);

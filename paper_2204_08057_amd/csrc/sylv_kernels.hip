@@ -25,6 +25,10 @@
 //  * pointers read from the instance table are cast to the global address space so that
 //    memory accesses compile to global_* rather than flat_* instructions.
 
+#include <string.h>
+
+#include <algorithm>
+
 #include "sylv_device.h"
 
 namespace sylv {
@@ -229,6 +233,10 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
     DevState *st = (MODE == AM_CG) ? Sel<T>::st(I) : nullptr;
     if constexpr (MODE == AM_CG) {
         if (st->done) return;
+    } else if constexpr (MODE == AM_RESID) {
+        // `it` is the residual phase; a refinement step (2) of a finished run is a no-op, as is
+        // the reduction that would read these partials
+        if (it == 2 && I.st->done) return;
     }
 
     // u = field to apply: the input (plain), x (residual), or z + beta p_old (CG; z alone at
@@ -876,6 +884,16 @@ __global__ void k_count_running(const Inst *__restrict__ tab, int ninst, int inn
     if (threadIdx.x == 0) { out[0] = cnt; out[1] = last; out[2] = gap; }
 }
 
+// Host-to-device copy of a small table through the kernel arguments: the bytes travel with the
+// launch itself, so the copy needs neither a host-side staging buffer that must outlive the call
+// nor a synchronisation, and a captured graph keeps its own copy of them.
+struct UploadChunk {
+    uint32_t w[kUploadWords];
+};
+__global__ void k_upload(uint32_t *__restrict__ dst, int nwords, UploadChunk c) {
+    for (int i = threadIdx.x; i < nwords; i += blockDim.x) dst[i] = c.w[i];
+}
+
 __global__ void k_stats(const Inst *__restrict__ tab, int ninst, sylv_pcg_stats *__restrict__ out,
                         int mixed) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1152,11 +1170,10 @@ hipError_t launch_precond_plain(const Inst *table0, int k, int dtype, int n_pix,
 }
 
 hipError_t launch_resid(const InstSet &set, int k, int phase, hipStream_t s) {
-    (void)phase;
     return dispatch_k(k, [&](auto tag) {
         constexpr int K = decltype(tag)::value;
         return launch_apply_rows<double, K, AM_RESID>(set.rows64, set.bc, dim3(set.total_tiles),
-                                                      s, set.table, set.tprefix, set.ninst, 0,
+                                                      s, set.table, set.tprefix, set.ninst, phase,
                                                       nullptr, nullptr);
     });
 }
@@ -1224,6 +1241,23 @@ hipError_t launch_state_init(const InstSet &set, double tol, int max_iter, int r
     hipLaunchKernelGGL(k_state_init, dim3(blocks_for(set.ninst, 64)), dim3(64), 0, s, set.table,
                        set.ninst, tol, max_iter, ref);
     return hipGetLastError();
+}
+
+hipError_t launch_upload(void *dst, const void *src, size_t bytes, hipStream_t s) {
+    if (bytes % 4 != 0 || ((uintptr_t)dst & 3u) != 0) return hipErrorInvalidValue;
+    const size_t words = bytes / 4;
+    const uint32_t *w = static_cast<const uint32_t *>(src);
+    for (size_t off = 0; off < words; off += kUploadWords) {
+        const int n = (int)std::min<size_t>(kUploadWords, words - off);
+        UploadChunk c;
+        memcpy(c.w, w + off, sizeof(uint32_t) * n);
+        for (int i = n; i < kUploadWords; ++i) c.w[i] = 0u;
+        hipLaunchKernelGGL(k_upload, dim3(1), dim3(256), 0, s,
+                           static_cast<uint32_t *>(dst) + off, n, c);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_count_running(const InstSet &set, int inner, int *out, hipStream_t s) {
