@@ -19,6 +19,7 @@ separable noise, common kappa) against PCG on the same system.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -157,6 +158,72 @@ def time_solves(sy, torch, probs, Y, B, opts, nrhs, steps, warmup):
     return ms, st, X
 
 
+def graph_solve(sy, torch, probs, Y, B, opts, nrhs, steps, warmup):
+    """The same solve under the fixed schedule, captured once into a HIP graph and replayed.
+
+    The caps of the fixed schedule come from the adaptive solve: max_iter per (inner) run starts
+    at 1.1 x the iterations per run plus 2 and grows until the capped solve converges (refine_max
+    = the refinement steps the adaptive solve took).  Each replay re-zeroes x and solves; the
+    median replay time is reported, and the replayed result must equal the eager fixed-schedule
+    solve bitwise."""
+    import math
+    plist = probs if isinstance(probs, list) else [probs]
+    n = len(plist) * nrhs
+    _, st = sy.pcg_solve(probs, Y=Y, Bextra=B, opts=opts, nrhs=nrhs)
+    mixed = opts.precision == sy.SYLV_PREC_MIXED
+    outer = max(s["outer"] for s in st)
+    per_run = max(s["iters"] for s in st) / (outer if mixed else 1)
+    m = int(math.ceil(per_run * 1.1)) + 2
+    fixed = None
+    for _ in range(8):
+        cand = dataclasses.replace(opts, max_iter=m, schedule=sy.SYLV_SCHED_FIXED,
+                                   refine_max=outer if mixed else opts.refine_max)
+        _, stc = sy.pcg_solve(probs, Y=Y, Bextra=B, opts=cand, nrhs=nrhs)
+        if all(s["status"] == 0 for s in stc):
+            fixed = cand
+            break
+        m = int(m * 1.15) + 2
+    if fixed is None:
+        return {"error": "no converging caps found"}
+    total = sum(nrhs * p.k * p.n_pix for p in plist)
+    X = torch.zeros(total, dtype=torch.float64, device="cuda")
+    stats = torch.zeros(n * sy.binding.STATS_BYTES, dtype=torch.uint8, device="cuda")
+    ws = torch.empty(sy.workspace_bytes(plist, nrhs, fixed), dtype=torch.uint8, device="cuda")
+    launch = sy.solve_launcher(probs, X, stats, ws, Y=Y, Bextra=B, opts=fixed, nrhs=nrhs)
+
+    def solve():
+        X.zero_()
+        launch()
+
+    solve()
+    torch.cuda.synchronize()
+    X_eager = X.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        solve()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        solve()
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        g.replay()
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+    st_g = sy.stats_list(stats, n)
+    out = summarize(statistics.median(times), st_g)
+    out.update({"max_iter": fixed.max_iter, "refine_max": fixed.refine_max if mixed else None,
+                "equal_to_eager": bool(torch.equal(X, X_eager))})
+    del g
+    return out
+
+
 def summarize(ms, st):
     return {"ms": round(ms, 3),
             "iters_max": max(s["iters"] for s in st),
@@ -218,6 +285,10 @@ def bench_batched(sy, torch, steps, warmup):
         ms, st, _ = time_solves(sy, torch, dps, Y, B, o, nrhs, steps, warmup)
         res[label] = summarize(ms, st)
         log(f"batched_8grids {label}: {res[label]}")
+    # the block-CG batch as one graph launch (fixed schedule)
+    o = sy.SolveOptions(tol=1e-8, precision=sy.SYLV_PREC_MIXED, block=1)
+    res["graph_block_mixed"] = graph_solve(sy, torch, dps, Y, B, o, nrhs, steps, warmup)
+    log(f"batched_8grids graph_block_mixed: {res['graph_block_mixed']}")
     res["right_hand_sides"] = len(probs) * nrhs
     res["pixels"] = sum(p.n_pix for p in probs)
     return res
@@ -485,6 +556,13 @@ def main():
         results[label] = dict(ms=ms, ms_mean=ms_mean, stats=st, X=X)
         log(f"{label}: median {ms:.3f} ms/solve (mean {ms_mean:.3f})  {st}")
 
+    # the same solves captured once into a HIP graph (fixed schedule) and replayed
+    graph = {}
+    for label in ("mixed", "f64"):
+        graph[label] = graph_solve(sy, torch, dp, Y, None, opts[label], 1, args.steps,
+                                   args.warmup)
+        log(f"graph replay {label}: {graph[label]}")
+
     # reference solution: float64 PCG to a 1e-12 relative residual (not timed)
     xref, st_ref = sy.pcg_solve(dp, Y=Y, ws=ws, opts=sy.SolveOptions(
         tol=1e-12, precision=sy.SYLV_PREC_F64, precond=sy.SYLV_PC_BLOCK))
@@ -539,6 +617,7 @@ def main():
         "relres_true_mixed": results["mixed"]["stats"]["relres_true"],
         "rel_err_vs_ref": {"mixed": err["mixed"], "fp64": err["f64"],
                            "reference": "float64 PCG to relres 1e-12 on the GPU"},
+        "graph_replay": graph,
         "ms_mean": {"mixed": round(results["mixed"]["ms_mean"], 4),
                     "fp64": round(results["f64"]["ms_mean"], 4)},
         "apply_f32_us": round(t32 * 1e3, 3),

@@ -556,7 +556,9 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
             G.inst0 = g * nrhs;
             G.ntiles = tiles_for(ny, nx, kBlockRows);
             G.ntiles32 = tiles_for(ny, nx, kBlockRows);
-            G.nchunks = (ny * nx + kBlockPix - 1) / kBlockPix;
+            const int bv = kBlock * block_vec(!mixed);
+            G.nchunks = (ny * nx + bv - 1) / bv;
+            G.vec = (ny * nx) % block_vec(!mixed) == 0 ? 1 : 0;
             G.nred = L.gnred[g];
             G.gs = reinterpret_cast<GroupState *>(base + L.gstate[g]);
             G.partial = reinterpret_cast<double *>(base + L.gpart[g]);

@@ -47,7 +47,154 @@ __device__ __forceinline__ void zero_acc(double (&acc)[kBlock / 64][NQ]) {
     __syncthreads();
 }
 
-// ---------------------------------------------------------------------------------------------
+// ---- the streaming block kernels: V = block_vec pixels per thread ---------------------------
+// V consecutive pixels of one plane move as one buffer access per lane (8 bytes) when every lane
+// of the wavefront holds V pixels of the grid and the group's planes allow it (F = true), else
+// element by element with bounds checks.  Kernels decide F once per wavefront.
+template <typename T, int V, bool F>
+__device__ __forceinline__ void ldv(const GAS T *plane, uint32_t n, uint32_t i, T (&v)[V]) {
+    if constexpr (V == 2 && sizeof(T) == 4 && F) {
+        {
+            const u32x2 a = __builtin_amdgcn_raw_buffer_load_b64(plane_rsrc(plane, n), i * 4u, 0, 0);
+            v[0] = __uint_as_float(a.x);
+            v[1] = __uint_as_float(a.y);
+            return;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < V; ++e) v[e] = (i + e < n) ? bld(plane, n, i + e) : (T)0;
+}
+template <typename T, int V, bool F>
+__device__ __forceinline__ void stv(GAS T *plane, uint32_t n, uint32_t i, const T (&v)[V]) {
+    if constexpr (V == 2 && sizeof(T) == 4 && F) {
+        {
+            const u32x2 a = {__float_as_uint(v[0]), __float_as_uint(v[1])};
+            __builtin_amdgcn_raw_buffer_store_b64(a, plane_rsrc((const GAS float *)plane, n),
+                                                  i * 4u, 0, 0);
+            return;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < V; ++e)
+        if (i + e < n) bst(plane, n, i + e, v[e]);
+}
+
+// Preconditioner of one pixel from the bfloat16 factor planes (block kind: G = L^-1 with
+// G[a][c], a >= c, at plane pidx(c, a); Jacobi kind: 1 / diagonal per component), loaded once
+// and applied to every column of the group: z = G^T (G r).  Same arithmetic as
+// precond_cg_pixel.
+template <typename T, int K>
+struct PcPix {
+    T g[K * (K + 1) / 2];
+};
+template <typename T, int K>
+__device__ __forceinline__ void pc_load(int pc, const GAS unsigned short *F, int n_pix, int pix,
+                                        bool valid, PcPix<T, K> &c) {
+    constexpr int MK = K * (K + 1) / 2;
+    const int ne = (pc == SYLV_PC_BLOCK) ? MK : (pc == SYLV_PC_JACOBI) ? K : 0;
+#pragma unroll
+    for (int e = 0; e < MK; ++e)
+        c.g[e] = (valid && e < ne) ? (T)bf16_value(F[(size_t)e * n_pix + pix]) : (T)0;
+}
+template <typename T, int K>
+__device__ __forceinline__ void pc_apply(int pc, const PcPix<T, K> &c, const T (&r)[K],
+                                         T (&z)[K]) {
+    if (pc == SYLV_PC_BLOCK) {
+        T t[K];
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            T s = 0;
+#pragma unroll
+            for (int q = 0; q <= a; ++q) s += c.g[pidx<K>(q, a)] * r[q];
+            t[a] = s;
+        }
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            T s = 0;
+#pragma unroll
+            for (int a = q; a < K; ++a) s += c.g[pidx<K>(q, a)] * t[a];
+            z[q] = s;
+        }
+    } else if (pc == SYLV_PC_JACOBI) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) z[j] = c.g[j] * r[j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < K; ++j) z[j] = r[j];
+    }
+}
+
+// The s x s coefficients (alpha or beta) of the current step, rounded to T, staged in LDS by the
+// workgroup: read once from the group state, before any plane is written (the state could
+// otherwise alias those stores and be re-read from memory at every use).
+template <typename T, int S>
+__device__ __forceinline__ void stage_coef(const double (&src)[kMaxS][kMaxS], T (&dst)[S][S]) {
+    for (int i = threadIdx.x; i < S * S; i += kBlock) dst[i / S][i % S] = (T)src[i / S][i % S];
+    __syncthreads();
+}
+
+template <bool B>
+struct BTag {
+    static constexpr bool value = B;
+};
+
+// 1 when every lane of the calling wavefront holds V whole pixels of the grid and the group's
+// planes allow wide accesses; the same value in every lane.
+__device__ __forceinline__ bool wave_full(int chunk, int v, int n_pix, int vec) {
+    const int plast = (chunk * kBlock + (int)(threadIdx.x | 63u)) * v;
+    return __builtin_amdgcn_readfirstlane((vec && plast + v <= n_pix) ? 1 : 0) != 0;
+}
+
+// Z = Minv R column by column (handed to `dst` for the columns in `use`), with the R^T Z and
+// ||r_c||^2 sums of the thread's pixels added to its wavefront's slots of `acc` (the kernel
+// zeroes and flushes acc, one array for every wavefront of the workgroup whichever code path it
+// took).  rv holds the residuals of the thread's V pixels (zero for pixels outside the grid and
+// for unused columns, whose terms are then exact zeros).
+template <typename T, int K, int S, int V, typename Dst>
+__device__ __forceinline__ void precond_and_gram(const Inst *__restrict__ tab, const Group &G,
+                                                 const T (&rv)[S][K][V], const bool (&use)[S],
+                                                 int p0, bool valid,
+                                                 double (&acc)[kBlock / 64][gram_n<S>() + S],
+                                                 Dst &&dst) {
+    constexpr int NG = gram_n<S>();
+    const Inst &I0 = tab[G.inst0];
+    const int n_pix = I0.n_pix;
+    PcPix<T, K> pcv[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e)
+        pc_load<T, K>(I0.pc, Pcg(I0), n_pix, p0 + e, valid && p0 + e < n_pix, pcv[e]);
+    const int wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int b = 0; b < S; ++b) {
+        T zb[K][V];
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            T r1[K], z1[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) r1[j] = rv[b][j][e];
+            pc_apply<T, K>(I0.pc, pcv[e], r1, z1);
+#pragma unroll
+            for (int j = 0; j < K; ++j) zb[j][e] = z1[j];
+        }
+        if (valid && use[b]) dst(b, zb);
+#pragma unroll
+        for (int a = 0; a <= b; ++a) {
+            double v = 0.0;
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+#pragma unroll
+                for (int e = 0; e < V; ++e) v += (double)rv[a][j][e] * (double)zb[j][e];
+            wave_accum(v, &acc[wid][pidx<S>(a, b)]);
+        }
+        double v = 0.0;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+#pragma unroll
+            for (int e = 0; e < V; ++e) v += (double)rv[b][j][e] * (double)rv[b][j][e];
+        wave_accum(v, &acc[wid][NG + b]);
+    }
+}
+
 // Start of a block run: per column r, r_r = rounded residual (float32 inner run) or the float64
 // residual, z_r = Minv r_r, P_0 = Z_0, and the partials of R^T Z and ||r_r||^2.
 template <typename T, int K, int S>
@@ -55,60 +202,58 @@ __global__ __launch_bounds__(kBlock) void k_bpinit(const Inst *__restrict__ tab,
                                                    const Group *__restrict__ groups,
                                                    const int *__restrict__ gcprefix, int ngroup,
                                                    int nb) {
-    constexpr int NQ = gram_n<S>() + S;
+    constexpr int V = block_vec(sizeof(T) == 8);
     const int L = xcd_remap(blockIdx.x, nb);
     const int g = find_inst(gcprefix, ngroup, L);
     const Group &G = groups[g];
     const int chunk = L - gcprefix[g];
     const Inst &I0 = tab[G.inst0];
     const int n_pix = I0.n_pix;
-    const int pix = chunk * kBlockPix + threadIdx.x;
-    const bool valid = pix < n_pix;
+    const uint32_t np = (uint32_t)n_pix;
+    const int p0 = (chunk * kBlock + threadIdx.x) * V;
+    const bool valid = p0 < n_pix;
+    constexpr int NQ = gram_n<S>() + S;
     __shared__ double acc[kBlock / 64][NQ];
     zero_acc<NQ>(acc);
-    T rv[S][K], zv[S][K];
+    auto body = [&](auto ftag) {
+        constexpr bool F = decltype(ftag)::value;
+        T rv[S][K][V];
+        bool use[S];
 #pragma unroll
-    for (int r = 0; r < S; ++r) {
-        const Inst &I = tab[G.inst0 + r];
-        const bool use = valid && !I.st->done;   // outer run finished / initial residual zero
-#pragma unroll
-        for (int j = 0; j < K; ++j) rv[r][j] = 0;
-        if (use) {
+        for (int r = 0; r < S; ++r) {
+            const Inst &I = tab[G.inst0 + r];
+            use[r] = !I.st->done;   // outer run finished / initial residual zero
 #pragma unroll
             for (int j = 0; j < K; ++j) {
-                const size_t o = (size_t)j * n_pix + pix;
-                rv[r][j] = (T)gp(I.r)[o];
-                if constexpr (sizeof(T) == 4) {
-                    gp(I.r32)[o] = rv[r][j];
-                    gp(I.d32)[o] = 0.0f;
+#pragma unroll
+                for (int e = 0; e < V; ++e) rv[r][j][e] = 0;
+                if (valid && use[r]) {
+                    double r64[V];
+                    ldv<double, V, false>(gp(I.r) + (size_t)j * n_pix, np, (uint32_t)p0, r64);
+#pragma unroll
+                    for (int e = 0; e < V; ++e) rv[r][j][e] = (T)r64[e];
+                    if constexpr (sizeof(T) == 4) {
+                        float zero[V];
+#pragma unroll
+                        for (int e = 0; e < V; ++e) zero[e] = 0.0f;
+                        stv<float, V, F>(gp(I.r32) + (size_t)j * n_pix, np, (uint32_t)p0, rv[r][j]);
+                        stv<float, V, F>(gp(I.d32) + (size_t)j * n_pix, np, (uint32_t)p0, zero);
+                    }
                 }
             }
         }
-        precond_cg_pixel<T, K>(I0.pc, Pcg(I0), n_pix, valid ? pix : 0, rv[r], zv[r]);
-        if (use) {
+        precond_and_gram<T, K, S, V>(tab, G, rv, use, p0, valid, acc,
+                                     [&](int r, const T (&zb)[K][V]) {
+            const Inst &I = tab[G.inst0 + r];
 #pragma unroll
             for (int j = 0; j < K; ++j) {
-                const size_t o = (size_t)j * n_pix + pix;
-                Sel<T>::z(I)[o] = zv[r][j];
-                Sel<T>::p(I, 0)[o] = zv[r][j];
+                stv<T, V, F>(Sel<T>::z(I) + (size_t)j * n_pix, np, (uint32_t)p0, zb[j]);
+                stv<T, V, F>(Sel<T>::p(I, 0) + (size_t)j * n_pix, np, (uint32_t)p0, zb[j]);
             }
-        }
-    }
-    const int wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int a = 0; a < S; ++a) {
-#pragma unroll
-        for (int b = a; b < S; ++b) {
-            double v = 0.0;
-#pragma unroll
-            for (int j = 0; j < K; ++j) v += (double)rv[a][j] * (double)zv[b][j];
-            wave_accum(v, &acc[wid][pidx<S>(a, b)]);
-        }
-        double v = 0.0;
-#pragma unroll
-        for (int j = 0; j < K; ++j) v += (double)rv[a][j] * (double)rv[a][j];
-        wave_accum(v, &acc[wid][gram_n<S>() + a]);
-    }
+        });
+    };
+    if (wave_full(chunk, V, n_pix, G.vec)) body(BTag<true>{});
+    else body(BTag<false>{});
     flush_partials<NQ>(acc, G.partial, G.nred, chunk);
 }
 
@@ -118,6 +263,7 @@ __global__ __launch_bounds__(kBlock) void k_bdir(const Inst *__restrict__ tab,
                                                  const Group *__restrict__ groups,
                                                  const int *__restrict__ gcprefix, int ngroup,
                                                  int nb, int it) {
+    constexpr int V = block_vec(sizeof(T) == 8);
     const int L = xcd_remap(blockIdx.x, nb);
     const int g = find_inst(gcprefix, ngroup, L);
     const Group &G = groups[g];
@@ -126,28 +272,50 @@ __global__ __launch_bounds__(kBlock) void k_bdir(const Inst *__restrict__ tab,
     const int chunk = L - gcprefix[g];
     const Inst &I0 = tab[G.inst0];
     const int n_pix = I0.n_pix;
-    const int pix = chunk * kBlockPix + threadIdx.x;
-    if (pix >= n_pix) return;
-    int act[S];
+    const uint32_t np = (uint32_t)n_pix;
+    const int p0 = (chunk * kBlock + threadIdx.x) * V;
+    const bool full = wave_full(chunk, V, n_pix, G.vec);
+    bool act[S];
 #pragma unroll
-    for (int r = 0; r < S; ++r) act[r] = gs->active[r];
+    for (int r = 0; r < S; ++r) act[r] = __builtin_amdgcn_readfirstlane(gs->active[r]) != 0;
+    __shared__ T beta[S][S];
+    stage_coef<T, S>(gs->beta, beta);
+    if (p0 >= n_pix) return;
+    auto body = [&](auto ftag) {
+        constexpr bool F = decltype(ftag)::value;
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        const size_t o = (size_t)j * n_pix + pix;
-        T po[S];
+        for (int j = 0; j < K; ++j) {
+            T po[S][V], zz[S][V];
 #pragma unroll
-        for (int c = 0; c < S; ++c) po[c] = act[c] ? Sel<T>::p(tab[G.inst0 + c], it - 1)[o] : (T)0;
+            for (int c = 0; c < S; ++c) {
 #pragma unroll
-        for (int r = 0; r < S; ++r) {
-            if (!act[r]) continue;
-            const Inst &I = tab[G.inst0 + r];
-            T v = Sel<T>::z(I)[o];
+                for (int e = 0; e < V; ++e) po[c][e] = zz[c][e] = 0;
+                if (act[c]) {
+                    const Inst &I = tab[G.inst0 + c];
+                    ldv<T, V, F>(Sel<T>::p(I, it - 1) + (size_t)j * n_pix, np, (uint32_t)p0, po[c]);
+                    ldv<T, V, F>(Sel<T>::z(I) + (size_t)j * n_pix, np, (uint32_t)p0, zz[c]);
+                }
+            }
 #pragma unroll
-            for (int c = 0; c < S; ++c)
-                if (act[c]) v += (T)gs->beta[c][r] * po[c];
-            Sel<T>::p(I, it)[o] = v;
+            for (int r = 0; r < S; ++r) {
+                if (!act[r]) continue;
+                T v[V];
+#pragma unroll
+                for (int e = 0; e < V; ++e) v[e] = zz[r][e];
+#pragma unroll
+                for (int c = 0; c < S; ++c) {
+                    if (!act[c]) continue;
+                    const T b = beta[c][r];
+#pragma unroll
+                    for (int e = 0; e < V; ++e) v[e] += b * po[c][e];
+                }
+                stv<T, V, F>(Sel<T>::p(tab[G.inst0 + r], it) + (size_t)j * n_pix, np,
+                             (uint32_t)p0, v);
+            }
         }
-    }
+    };
+    if (full) body(BTag<true>{});
+    else body(BTag<false>{});
 }
 
 // Q = G P for the active columns of a group, sharing the per-pixel mixing blocks, and the
@@ -217,14 +385,24 @@ __global__ __launch_bounds__(kBlock) void k_bapply(const Inst *__restrict__ tab,
             for (int e = 0; e < MK; ++e) m[t][e] = M[(size_t)e * n_pix + pix];
         }
     }
+    // every value read from memory that a store below could alias is read first: the active
+    // columns and the stencil coefficients
+    bool act[S];
+#pragma unroll
+    for (int r = 0; r < S; ++r) act[r] = __builtin_amdgcn_readfirstlane(gs->active[r]) != 0;
+    T cf[K][6];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const double *cj = I0.coef + j * kCoefStride;
+        cf[j][0] = (T)cj[0]; cf[j][1] = (T)cj[1]; cf[j][2] = (T)cj[2]; cf[j][3] = (T)cj[3];
+        cf[j][4] = (T)cj[6]; cf[j][5] = (T)(cj[5] * cj[5]);
+    }
     T pc[S][K][R];   // centres of every column's direction at this lane's output pixels
     const int wid = ty;
-#pragma unroll
-    for (int b = 0; b < S; ++b) {
-        if (!gs->active[b]) continue;
-        const Inst &Ib = tab[G.inst0 + b];
-        const GAS T *u = Sel<T>::p(Ib, it);
-        T sa[K][RPW], ha[K];
+    // staged values of one column, loaded one column ahead of its stencil
+    T sa[K][RPW], ha[K];
+    auto load_col = [&](int c) {
+        const GAS T *u = Sel<T>::p(tab[G.inst0 + c], it);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
 #pragma unroll
@@ -232,6 +410,16 @@ __global__ __launch_bounds__(kBlock) void k_bapply(const Inst *__restrict__ tab,
                 sa[j][rr] = sin[rr] ? u[(size_t)j * n_pix + soff[rr]] : (T)0;
             ha[j] = hin ? u[(size_t)j * n_pix + hoff] : (T)0;
         }
+    };
+    {
+        int c0 = 0;
+        while (c0 < S && !act[c0]) ++c0;
+        if (c0 < S) load_col(c0);
+    }
+#pragma unroll
+    for (int b = 0; b < S; ++b) {
+        if (!act[b]) continue;
+        const Inst &Ib = tab[G.inst0 + b];
         __syncthreads();   // previous column's stencil reads are done
 #pragma unroll
         for (int j = 0; j < K; ++j) {
@@ -240,6 +428,11 @@ __global__ __launch_bounds__(kBlock) void k_bapply(const Inst *__restrict__ tab,
             if (hvalid) lds[j][hr][hcol] = ha[j];   // 0 outside a face (hin)
         }
         __syncthreads();
+        {   // the next active column's loads fly during this column's stencil
+            int nc = b + 1;
+            while (nc < S && !act[nc]) ++nc;
+            if (nc < S) load_col(nc);
+        }
         T q[K][R];
 #pragma unroll
         for (int j = 0; j < K; ++j)
@@ -249,9 +442,8 @@ __global__ __launch_bounds__(kBlock) void k_bapply(const Inst *__restrict__ tab,
             const int lr = ty * R;
 #pragma unroll
             for (int j = 0; j < K; ++j) {
-                const double *cj = I0.coef + j * kCoefStride;
-                const T c0 = (T)cj[0], c1 = (T)cj[1], cd = (T)cj[2], c2 = (T)cj[3];
-                const T tj = (T)cj[6], k2 = (T)(cj[5] * cj[5]);
+                const T c0 = cf[j][0], c1 = cf[j][1], cd = cf[j][2], c2 = cf[j][3];
+                const T tj = cf[j][4], k2 = cf[j][5];
                 T cc[R + 4], l1[R + 2], r1[R + 2], l2[R], r2[R];
 #pragma unroll
                 for (int t = 0; t < R + 4; ++t) cc[t] = lds[j][lr + t][tx + 2];
@@ -317,7 +509,7 @@ __global__ __launch_bounds__(kBlock) void k_bapply(const Inst *__restrict__ tab,
         // Gram entries (a, b), a <= b, with this column's q
 #pragma unroll
         for (int a = 0; a <= b; ++a) {
-            if (!gs->active[a]) continue;
+            if (!act[a]) continue;
             double v = 0.0;
 #pragma unroll
             for (int j = 0; j < K; ++j)
@@ -335,7 +527,7 @@ __global__ __launch_bounds__(kBlock) void k_bupdate(const Inst *__restrict__ tab
                                                     const Group *__restrict__ groups,
                                                     const int *__restrict__ gcprefix, int ngroup,
                                                     int nb, int it) {
-    constexpr int NQ = gram_n<S>() + S;
+    constexpr int V = block_vec(sizeof(T) == 8);
     const int L = xcd_remap(blockIdx.x, nb);
     const int g = find_inst(gcprefix, ngroup, L);
     const Group &G = groups[g];
@@ -344,72 +536,75 @@ __global__ __launch_bounds__(kBlock) void k_bupdate(const Inst *__restrict__ tab
     const int chunk = L - gcprefix[g];
     const Inst &I0 = tab[G.inst0];
     const int n_pix = I0.n_pix;
-    const int pix = chunk * kBlockPix + threadIdx.x;
-    const bool valid = pix < n_pix;
+    const uint32_t np = (uint32_t)n_pix;
+    const int p0 = (chunk * kBlock + threadIdx.x) * V;
+    const bool valid = p0 < n_pix;
+    bool act[S];
+#pragma unroll
+    for (int r = 0; r < S; ++r) act[r] = __builtin_amdgcn_readfirstlane(gs->active[r]) != 0;
+    __shared__ T alpha[S][S];
+    stage_coef<T, S>(gs->alpha, alpha);
+    constexpr int NQ = gram_n<S>() + S;
     __shared__ double acc[kBlock / 64][NQ];
     zero_acc<NQ>(acc);
-    int act[S];
+    auto body = [&](auto ftag) {
+        constexpr bool F = decltype(ftag)::value;
+        T rv[S][K][V];
 #pragma unroll
-    for (int r = 0; r < S; ++r) act[r] = gs->active[r];
-    T rv[S][K], zv[S][K];
+        for (int r = 0; r < S; ++r)
 #pragma unroll
-    for (int r = 0; r < S; ++r)
+            for (int j = 0; j < K; ++j)
 #pragma unroll
-        for (int j = 0; j < K; ++j) rv[r][j] = zv[r][j] = 0;
-    if (valid) {
+                for (int e = 0; e < V; ++e) rv[r][j][e] = 0;
+        if (valid) {
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            const size_t o = (size_t)j * n_pix + pix;
-            T pj[S], qj[S];
-#pragma unroll
-            for (int c = 0; c < S; ++c) {
-                pj[c] = act[c] ? Sel<T>::p(tab[G.inst0 + c], it)[o] : (T)0;
-                qj[c] = act[c] ? Sel<T>::q(tab[G.inst0 + c])[o] : (T)0;
-            }
-#pragma unroll
-            for (int r = 0; r < S; ++r) {
-                if (!act[r]) continue;
-                const Inst &I = tab[G.inst0 + r];
-                T xv = Sel<T>::x(I)[o];
-                T rr = Sel<T>::r(I)[o];
+            for (int j = 0; j < K; ++j) {
+                const size_t o = (size_t)j * n_pix;
+                T pj[S][V], qj[S][V];
 #pragma unroll
                 for (int c = 0; c < S; ++c) {
-                    if (!act[c]) continue;
-                    const T a = (T)gs->alpha[c][r];
-                    xv += a * pj[c];
-                    rr -= a * qj[c];
+#pragma unroll
+                    for (int e = 0; e < V; ++e) pj[c][e] = qj[c][e] = 0;
+                    if (act[c]) {
+                        const Inst &I = tab[G.inst0 + c];
+                        ldv<T, V, F>(Sel<T>::p(I, it) + o, np, (uint32_t)p0, pj[c]);
+                        ldv<T, V, F>(Sel<T>::q(I) + o, np, (uint32_t)p0, qj[c]);
+                    }
                 }
-                Sel<T>::x(I)[o] = xv;
-                Sel<T>::r(I)[o] = rr;
-                rv[r][j] = rr;
+#pragma unroll
+                for (int r = 0; r < S; ++r) {
+                    if (!act[r]) continue;
+                    const Inst &I = tab[G.inst0 + r];
+                    T xv[V], rr[V];
+                    ldv<T, V, F>(Sel<T>::x(I) + o, np, (uint32_t)p0, xv);
+                    ldv<T, V, F>(Sel<T>::r(I) + o, np, (uint32_t)p0, rr);
+#pragma unroll
+                    for (int c = 0; c < S; ++c) {
+                        if (!act[c]) continue;
+                        const T a = alpha[c][r];
+#pragma unroll
+                        for (int e = 0; e < V; ++e) {
+                            xv[e] += a * pj[c][e];
+                            rr[e] -= a * qj[c][e];
+                        }
+                    }
+                    stv<T, V, F>(Sel<T>::x(I) + o, np, (uint32_t)p0, xv);
+                    stv<T, V, F>(Sel<T>::r(I) + o, np, (uint32_t)p0, rr);
+#pragma unroll
+                    for (int e = 0; e < V; ++e) rv[r][j][e] = rr[e];
+                }
             }
         }
-#pragma unroll
-        for (int r = 0; r < S; ++r) {
-            if (!act[r]) continue;
+        precond_and_gram<T, K, S, V>(tab, G, rv, act, p0, valid, acc,
+                                     [&](int r, const T (&zb)[K][V]) {
             const Inst &I = tab[G.inst0 + r];
-            precond_cg_pixel<T, K>(I0.pc, Pcg(I0), n_pix, pix, rv[r], zv[r]);
 #pragma unroll
-            for (int j = 0; j < K; ++j) Sel<T>::z(I)[(size_t)j * n_pix + pix] = zv[r][j];
-        }
-    }
-    const int wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int a = 0; a < S; ++a) {
-        if (!act[a]) continue;
-#pragma unroll
-        for (int b = a; b < S; ++b) {
-            if (!act[b]) continue;
-            double v = 0.0;
-#pragma unroll
-            for (int j = 0; j < K; ++j) v += (double)rv[a][j] * (double)zv[b][j];
-            wave_accum(v, &acc[wid][pidx<S>(a, b)]);
-        }
-        double v = 0.0;
-#pragma unroll
-        for (int j = 0; j < K; ++j) v += (double)rv[a][j] * (double)rv[a][j];
-        wave_accum(v, &acc[wid][gram_n<S>() + a]);
-    }
+            for (int j = 0; j < K; ++j)
+                stv<T, V, F>(Sel<T>::z(I) + (size_t)j * n_pix, np, (uint32_t)p0, zb[j]);
+        });
+    };
+    if (wave_full(chunk, V, n_pix, G.vec)) body(BTag<true>{});
+    else body(BTag<false>{});
     flush_partials<NQ>(acc, G.partial, G.nred, chunk);
 }
 

@@ -125,7 +125,10 @@ inline int packed_size(int k) { return k * (k + 1) / 2; }
 constexpr int kMaxS = 8;                           // right-hand sides per group
 constexpr int kGramQ = kMaxS * (kMaxS + 1) / 2;    // packed s x s Gram entries
 constexpr int kBlockQ = kGramQ + kMaxS;            // + per-column ||r||^2
-constexpr int kBlockPix = 256;                     // pixels per workgroup, streaming block kernels
+constexpr int kBlockPix = 256;                     // smallest streaming chunk of the block kernels
+// Pixels per thread of the streaming block kernels (one 8-byte access per plane and lane):
+// chunks of kBlock * block_vec pixels.
+constexpr int block_vec(bool f64) { return f64 ? 1 : 2; }
 enum BlockMode { BM_BLOCK = 0, BM_DIAG = 1 };
 
 // State of one block-CG run of a group (device memory, written only by the Gram kernel).
@@ -143,9 +146,9 @@ struct GroupState {
 struct Group {
     int32_t inst0;               // instance of right-hand side 0 (the group's s instances follow)
     int32_t ntiles, ntiles32;    // apply tiles (float64 / float32 rows per lane)
-    int32_t nchunks;             // kBlockPix-pixel chunks
+    int32_t nchunks;             // streaming chunks (kBlock * block_vec pixels)
     int32_t nred;                // partial stride
-    int32_t pad;
+    int32_t vec;                 // 1: n_pix is a multiple of block_vec (wide plane accesses)
     GroupState *gs;
     double *partial;             // [kBlockQ][nred]
 };
