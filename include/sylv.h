@@ -30,7 +30,8 @@
  *    `stream` a few times to test convergence, returning when the solve has finished; with
  *    schedule = SYLV_SCHED_FIXED they only enqueue work and may be captured as well.
  *    sylv_lanczos_solve synchronises at every convergence check (its small projected problems
- *    are solved on the host) and refuses a capturing stream.
+ *    are solved on the host) and refuses a capturing stream; sylv_autotune times whole solves
+ *    and synchronises as well.
  *  - Return value: 0 on success, a negative SYLV_E_* code when the arguments are rejected before
  *    any work is enqueued (then sylv_last_error() describes why), or SYLV_E_HIP when a HIP call
  *    failed.  Numerical outcomes of a solve (converged, not converged, breakdown, non-finite
@@ -109,9 +110,9 @@ typedef struct sylv_pcg_opts {
     int32_t refine_max;    /* mixed: maximum number of float64 refinement steps (0 = 8)          */
     int32_t precond;       /* SYLV_PC_NONE, SYLV_PC_JACOBI or SYLV_PC_BLOCK                       */
     int32_t check_every;   /* iterations enqueued between host convergence checks (0 = 8)        */
-    int32_t block;         /* 1: block CG over the nrhs right-hand sides of each problem
-                              (nrhs must be 2, 4 or 8): s x s Gram matrices in float64, alpha and
-                              beta from s x s Cholesky solves, converged columns deflated;
+    int32_t block;         /* 1: block CG over blocks of s right-hand sides of each problem
+                              (s = block_size): s x s Gram matrices in float64, alpha and beta
+                              from s x s Cholesky solves, converged columns deflated;
                               0: independent CG per right-hand side                              */
     int32_t stop_ref;      /* reference of the stopping test: SYLV_STOP_R0 (||b - G x0||, Alg. 2's
                               test) or SYLV_STOP_B (||b||, for warm starts over a sweep of
@@ -126,6 +127,14 @@ typedef struct sylv_pcg_opts {
                               (about 1-2 us each), so max_iter and refine_max should be set near
                               what the solve needs.  Both schedules compute the same iterates: the
                               device takes every stopping decision.                             */
+    int32_t block_size;    /* block = 1: columns per block, 2, 4 or 8, dividing nrhs (0 = nrhs,
+                              which must then be 2, 4 or 8); the nrhs / s blocks of a problem
+                              iterate independently of each other                               */
+    int32_t apply_rows;    /* output rows per lane of the independent-CG operator applies: 2, 4
+                              or 8, lowered where a precision and k would overflow registers
+                              (0 = default: 4 at k <= 3 in float64 and k <= 4 in float32, else
+                              2; face grids always 2).  Changes the tiling, so reductions round
+                              differently, never the arithmetic per pixel                       */
 } sylv_pcg_opts;
 
 /* Per-solve result, written by the device into caller memory (DEVICE pointer). */
@@ -261,6 +270,32 @@ size_t sylv_lanczos_workspace_bytes(const sylv_sep_problem *prob, const sylv_lan
 int sylv_lanczos_solve(const sylv_sep_problem *prob, const double *Y, double *X,
                        const sylv_lanczos_opts *opts, sylv_lanczos_stats *stats, void *ws,
                        size_t ws_bytes, void *stream);
+
+/* ---- autotuning of the solver configuration --------------------------------------------- */
+
+/* Result of sylv_autotune: the configuration to copy into sylv_pcg_opts. */
+typedef struct sylv_tune_result {
+    int32_t block;         /* 0: independent CG, 1: block CG                                    */
+    int32_t block_size;    /* columns per block (block = 1), else 0                             */
+    int32_t apply_rows;    /* rows per lane of the operator applies (independent CG), else 0    */
+    int32_t candidates;    /* configurations timed                                              */
+    double  ms;            /* time to tolerance of the chosen configuration                     */
+    double  ms_given;      /* time to tolerance with the configuration of `opts` as given        */
+} sylv_tune_result;
+
+/* Time whole solves of this batch (same arguments as sylv_pcg_solve) under every candidate
+ * configuration and report the fastest that converges for every right-hand side: independent CG
+ * with 2, 4 and 8 output rows per lane of the applies, and block CG with every block size in
+ * {2, 4, 8} that divides nrhs.  Each candidate is solved twice from x0 = 0 and timed with HIP
+ * events around the whole call (set-up included); the shorter run counts.  X and stats are
+ * scratch: X is zeroed before every solve and holds the last candidate's solution on return.
+ * ws must hold sylv_workspace_bytes(probs, nprob, nrhs, opts) bytes (the same for every
+ * candidate).  Synchronises `stream`; not capturable.  Intended to run once per batch shape,
+ * with the result kept by the caller. */
+int sylv_autotune(const sylv_problem *probs, int32_t nprob, int32_t nrhs, const double *Y,
+                  const double *Bextra, double *X, const sylv_pcg_opts *opts,
+                  sylv_pcg_stats *stats, sylv_tune_result *out, void *ws, size_t ws_bytes,
+                  void *stream);
 
 /* Human-readable name of a status or return code (static string). */
 const char *sylv_status_string(int code);

@@ -28,6 +28,7 @@ from .binding import (  # noqa: F401
     SylvSolve,
     apply,
     apply_launcher,
+    autotune,
     declared_symbols,
     lanczos_solve,
     lanczos_workspace_bytes,

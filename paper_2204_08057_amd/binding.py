@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes
 import os
 import re
+import dataclasses
 from dataclasses import dataclass
 from typing import List, Optional, Sequence
 
@@ -64,7 +65,8 @@ class _Opts(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("inner_tol", ctypes.c_double),
                 ("refine_max", ctypes.c_int32), ("precond", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("stop_ref", ctypes.c_int32), ("schedule", ctypes.c_int32)]
+                ("stop_ref", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("block_size", ctypes.c_int32), ("apply_rows", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -74,6 +76,12 @@ class _Stats(ctypes.Structure):
 
 
 STATS_BYTES = ctypes.sizeof(_Stats)
+
+
+class _TuneResult(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("block_size", ctypes.c_int32),
+                ("apply_rows", ctypes.c_int32), ("candidates", ctypes.c_int32),
+                ("ms", ctypes.c_double), ("ms_given", ctypes.c_double)]
 
 
 class _SepProblem(ctypes.Structure):
@@ -132,8 +140,11 @@ def lib():
         L.sylv_lanczos_workspace_bytes.argtypes = [SP, LO]
         L.sylv_lanczos_workspace_bytes.restype = sz
         L.sylv_lanczos_solve.argtypes = [SP, vp, vp, LO, ctypes.POINTER(_LzStats), vp, sz, vp]
+        L.sylv_autotune.argtypes = [P, i32, i32, vp, vp, vp, O, vp, ctypes.POINTER(_TuneResult),
+                                    vp, sz, vp]
         for name in ("sylv_prepare", "sylv_apply", "sylv_precond", "sylv_rhs", "sylv_po_perturb",
-                     "sylv_pcg_solve", "sylv_pcg_backward", "sylv_lanczos_solve"):
+                     "sylv_pcg_solve", "sylv_pcg_backward", "sylv_lanczos_solve",
+                     "sylv_autotune"):
             getattr(L, name).restype = ctypes.c_int
         L.sylv_status_string.argtypes = [ctypes.c_int]
         L.sylv_status_string.restype = ctypes.c_char_p
@@ -233,10 +244,13 @@ class SolveOptions:
     block: int = 0
     stop_ref: int = SYLV_STOP_R0
     schedule: int = SYLV_SCHED_ADAPTIVE
+    block_size: int = 0
+    apply_rows: int = 0
 
     def c_struct(self) -> _Opts:
         return _Opts(self.tol, self.max_iter, self.precision, self.inner_tol, self.refine_max,
-                     self.precond, self.check_every, self.block, self.stop_ref, self.schedule)
+                     self.precond, self.check_every, self.block, self.stop_ref, self.schedule,
+                     self.block_size, self.apply_rows)
 
 
 def workspace_bytes(problems: Sequence[DeviceProblem], nrhs: int = 1,
@@ -422,6 +436,57 @@ def solve_launcher(problems, X, stats, ws, Y=None, Bextra=None,
 
     launch.keep = (arr, o, probs, X, stats, ws, Y, Bextra)
     return launch
+
+
+def _tune_key(probs, nrhs, opts) -> str:
+    grids = ",".join(f"{p.ny}x{p.nx}" for p in probs)
+    return (f"k{probs[0].k} f{probs[0].f} bc{probs[0].boundary} grids[{grids}] nrhs{nrhs} "
+            f"prec{opts.precision} pc{opts.precond} tol{opts.tol:g} sched{opts.schedule}")
+
+
+def autotune(problems, Y=None, Bextra=None, opts: Optional[SolveOptions] = None, nrhs: int = 1,
+             ws=None, cache: Optional[str] = None):
+    """Time whole solves of this batch under every candidate configuration (sylv_autotune) and
+    return (options with the fastest configuration filled in, result dict).  With `cache` (a
+    JSON file path) a result stored for the same batch shape and options is reused, and a new
+    one is stored."""
+    import json
+    torch = _torch()
+    probs = [problems] if isinstance(problems, DeviceProblem) else list(problems)
+    opts = opts or SolveOptions()
+    key = _tune_key(probs, nrhs, opts)
+    stored = {}
+    if cache is not None and os.path.exists(cache):
+        with open(cache) as fh:
+            stored = json.load(fh)
+        if key in stored:
+            r = dict(stored[key], cached=True)
+            return dataclasses.replace(opts, block=r["block"], block_size=r["block_size"],
+                                       apply_rows=r["apply_rows"]), r
+    dev = probs[0].W.device
+    total = sum(nrhs * p.k * p.n_pix for p in probs)
+    X = torch.zeros(total, dtype=torch.float64, device=dev)
+    stats = torch.zeros(len(probs) * nrhs * STATS_BYTES, dtype=torch.uint8, device=dev)
+    nbytes = workspace_bytes(probs, nrhs, opts)
+    if ws is None or ws.numel() < nbytes:
+        ws = _workspace(nbytes, dev)
+    arr = (_Problem * len(probs))(*[p.c_struct() for p in probs])
+    o = opts.c_struct()
+    res = _TuneResult()
+    rc = lib().sylv_autotune(arr, len(probs), nrhs, _ptr(Y), _ptr(Bextra), _ptr(X),
+                             ctypes.byref(o), _ptr(stats), ctypes.byref(res), _ptr(ws),
+                             ws.numel(), _stream())
+    if rc != SYLV_OK:
+        raise SylvError(rc, lib().sylv_last_error().decode())
+    r = dict(block=res.block, block_size=res.block_size, apply_rows=res.apply_rows,
+             candidates=res.candidates, ms=res.ms, ms_given=res.ms_given, cached=False)
+    if cache is not None:
+        stored[key] = {n: r[n] for n in ("block", "block_size", "apply_rows", "candidates", "ms",
+                                         "ms_given")}
+        with open(cache, "w") as fh:
+            json.dump(stored, fh, indent=1, sort_keys=True)
+    return dataclasses.replace(opts, block=r["block"], block_size=r["block_size"],
+                               apply_rows=r["apply_rows"]), r
 
 
 def stats_list(stats, n: int):

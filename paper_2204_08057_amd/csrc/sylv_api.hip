@@ -14,6 +14,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <utility>
 #include <vector>
 
 using namespace sylv;
@@ -112,6 +113,11 @@ bool check_problem(const sylv_problem *p, int idx) {
     return true;
 }
 
+// Block CG groups a problem's right-hand sides into blocks of 2, 4 or 8 columns.
+int max_groups_per_problem(int nrhs) { return nrhs % 2 == 0 ? nrhs / 2 : 0; }
+int block_size_for(int nrhs, int requested) { return requested > 0 ? requested : nrhs; }
+bool block_size_ok(int nrhs, int bs) { return block_rhs_supported(bs) && nrhs % bs == 0; }
+
 // Workspace: per-problem operator regions first (so that the layout of the operator of a single
 // problem does not depend on the call), then the instance table and prefixes, the run states,
 // reduction partials, solver vectors and the gradient partials.
@@ -158,19 +164,23 @@ bool make_layout(const sylv_problem *probs, int nprob, int nrhs, bool solve, Lay
                 I.d32 = off; off = align_up(off + sizeof(float) * vk);
             }
         }
-        // block CG tables (sized whenever a call could use them)
-        L.groups = off; off = align_up(off + sizeof(Group) * nprob);
-        L.gprefix = off; off = align_up(off + sizeof(int) * 3 * (nprob + 1));
-        L.gstate.resize(nprob);
-        L.gpart.resize(nprob);
-        L.gnred.resize(nprob);
-        if (block_rhs_supported(nrhs)) {
-            for (int g = 0; g < nprob; ++g) {
-                const int ny = (int)probs[g].ny, nx = (int)probs[g].nx;
-                const int n = ny * nx;
-                L.gnred[g] = std::max(tiles_for(ny, nx, 2), (n + kBlockPix - 1) / kBlockPix);
-                L.gstate[g] = off; off = align_up(off + sizeof(GroupState));
-                L.gpart[g] = off;  off = align_up(off + sizeof(double) * kBlockQ * L.gnred[g]);
+        // block CG tables, sized whenever a call could use them: up to nrhs / 2 groups (blocks
+        // of 2 columns) per problem, group (g, b) at index g * (nrhs / 2) + b
+        const int gpp = max_groups_per_problem(nrhs);
+        const int ng = nprob * gpp;
+        L.groups = off; off = align_up(off + sizeof(Group) * std::max(ng, 1));
+        L.gprefix = off; off = align_up(off + sizeof(int) * 3 * (ng + 1));
+        L.gstate.resize(ng);
+        L.gpart.resize(ng);
+        L.gnred.resize(ng);
+        for (int g = 0; g < nprob; ++g) {
+            const int ny = (int)probs[g].ny, nx = (int)probs[g].nx;
+            const int n = ny * nx;
+            for (int b = 0; b < gpp; ++b) {
+                const int i = g * gpp + b;
+                L.gnred[i] = std::max(tiles_for(ny, nx, 2), (n + kBlockPix - 1) / kBlockPix);
+                L.gstate[i] = off; off = align_up(off + sizeof(GroupState));
+                L.gpart[i] = off;  off = align_up(off + sizeof(double) * kBlockQ * L.gnred[i]);
             }
         }
         if (nprob == 1 && nrhs == 1) {
@@ -250,6 +260,8 @@ int check_opts(const sylv_pcg_opts *o) {
     if (o->refine_max < 0 || o->check_every < 0) { set_err("negative refine_max/check_every"); return SYLV_E_INVALID; }
     if (o->stop_ref != SYLV_STOP_R0 && o->stop_ref != SYLV_STOP_B) { set_err("bad stop_ref"); return SYLV_E_INVALID; }
     if (o->schedule != SYLV_SCHED_ADAPTIVE && o->schedule != SYLV_SCHED_FIXED) { set_err("bad schedule"); return SYLV_E_INVALID; }
+    if (o->block_size != 0 && !block_rhs_supported(o->block_size)) { set_err("block_size must be 0, 2, 4 or 8"); return SYLV_E_INVALID; }
+    if (o->apply_rows != 0 && !apply_rows_valid(o->apply_rows)) { set_err("apply_rows must be 0, 2, 4 or 8"); return SYLV_E_INVALID; }
     return SYLV_OK;
 }
 
@@ -461,8 +473,10 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
     const bool fixed = opts->schedule == SYLV_SCHED_FIXED;
     if (!Y && !Bextra) { set_err("need Y or Bextra"); return SYLV_E_INVALID; }
     const bool block = opts->block != 0;
-    if (block && !block_rhs_supported(nrhs)) {
-        set_err("block CG needs nrhs in {2, 4, 8} (got %d)", nrhs);
+    const int bsize = block_size_for(nrhs, opts->block_size);
+    if (block && !block_size_ok(nrhs, bsize)) {
+        set_err("block CG needs a block size in {2, 4, 8} dividing nrhs (block %d, nrhs %d)",
+                bsize, nrhs);
         return SYLV_E_INVALID;
     }
     make_layout(probs, nprob, nrhs, true, L);
@@ -472,8 +486,9 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
     char *base = reinterpret_cast<char *>(ws);
     const int mixed = opts->precision == SYLV_PREC_MIXED;
     // face grids run the apply kernels with 2 rows per lane
-    const int rows64 = bc == SYLV_BC_FACE ? 2 : apply_rows_for(k, SYLV_F64, apply_rows_request());
-    const int rows32 = bc == SYLV_BC_FACE ? 2 : apply_rows_for(k, SYLV_F32, apply_rows_request());
+    const int rreq = opts->apply_rows > 0 ? opts->apply_rows : apply_rows_request();
+    const int rows64 = bc == SYLV_BC_FACE ? 2 : apply_rows_for(k, SYLV_F64, rreq);
+    const int rows32 = bc == SYLV_BC_FACE ? 2 : apply_rows_for(k, SYLV_F32, rreq);
     const int pc = opts->precond;
 
     // instance table
@@ -541,44 +556,49 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
     set.bc = bc;
     set.any_pre = any_pre;
 
-    // block CG groups: one per problem, its nrhs instances in order
+    // block CG groups: nrhs / bsize per problem, each bsize consecutive instances
     GroupSet gset;
     memset(&gset, 0, sizeof(gset));
     if (block) {
-        std::vector<Group> grp(nprob);
-        std::vector<int> gpre(3 * (nprob + 1));
-        int *gt = gpre.data(), *gt32 = gt + (nprob + 1), *gc = gt32 + (nprob + 1);
+        const int per = nrhs / bsize, gpp = max_groups_per_problem(nrhs);
+        const int ngroup = nprob * per;
+        std::vector<Group> grp(ngroup);
+        std::vector<int> gpre(3 * (ngroup + 1));
+        int *gt = gpre.data(), *gt32 = gt + (ngroup + 1), *gc = gt32 + (ngroup + 1);
         gt[0] = gt32[0] = gc[0] = 0;
         for (int g = 0; g < nprob; ++g) {
             const int ny = (int)probs[g].ny, nx = (int)probs[g].nx;
-            Group G;
-            memset(&G, 0, sizeof(G));
-            G.inst0 = g * nrhs;
-            G.ntiles = tiles_for(ny, nx, kBlockRows);
-            G.ntiles32 = tiles_for(ny, nx, kBlockRows);
-            const int bv = kBlock * block_vec(!mixed);
-            G.nchunks = (ny * nx + bv - 1) / bv;
-            G.vec = (ny * nx) % block_vec(!mixed) == 0 ? 1 : 0;
-            G.nred = L.gnred[g];
-            G.gs = reinterpret_cast<GroupState *>(base + L.gstate[g]);
-            G.partial = reinterpret_cast<double *>(base + L.gpart[g]);
-            grp[g] = G;
-            gt[g + 1] = gt[g] + G.ntiles;
-            gt32[g + 1] = gt32[g] + G.ntiles32;
-            gc[g + 1] = gc[g] + G.nchunks;
+            for (int b = 0; b < per; ++b) {
+                const int gi = g * per + b, slot = g * gpp + b;
+                Group G;
+                memset(&G, 0, sizeof(G));
+                G.inst0 = g * nrhs + b * bsize;
+                G.ntiles = tiles_for(ny, nx, kBlockRows);
+                G.ntiles32 = tiles_for(ny, nx, kBlockRows);
+                const int bv = kBlock * block_vec(!mixed);
+                G.nchunks = (ny * nx + bv - 1) / bv;
+                G.vec = (ny * nx) % block_vec(!mixed) == 0 ? 1 : 0;
+                G.nred = L.gnred[slot];
+                G.gs = reinterpret_cast<GroupState *>(base + L.gstate[slot]);
+                G.partial = reinterpret_cast<double *>(base + L.gpart[slot]);
+                grp[gi] = G;
+                gt[gi + 1] = gt[gi] + G.ntiles;
+                gt32[gi + 1] = gt32[gi] + G.ntiles32;
+                gc[gi + 1] = gc[gi] + G.nchunks;
+            }
         }
-        HIP_TRY(launch_upload(base + L.groups, grp.data(), sizeof(Group) * nprob, s));
-        HIP_TRY(launch_upload(base + L.gprefix, gpre.data(), sizeof(int) * 3 * (nprob + 1), s));
+        HIP_TRY(launch_upload(base + L.groups, grp.data(), sizeof(Group) * ngroup, s));
+        HIP_TRY(launch_upload(base + L.gprefix, gpre.data(), sizeof(int) * 3 * (ngroup + 1), s));
         gset.table = set.table;
         gset.groups = reinterpret_cast<const Group *>(base + L.groups);
         gset.gtprefix = reinterpret_cast<const int *>(base + L.gprefix);
-        gset.gtprefix32 = gset.gtprefix + (nprob + 1);
-        gset.gcprefix = gset.gtprefix32 + (nprob + 1);
-        gset.ngroup = nprob;
-        gset.s = nrhs;
-        gset.total_tiles = gt[nprob];
-        gset.total_tiles32 = gt32[nprob];
-        gset.total_chunks = gc[nprob];
+        gset.gtprefix32 = gset.gtprefix + (ngroup + 1);
+        gset.gcprefix = gset.gtprefix32 + (ngroup + 1);
+        gset.ngroup = ngroup;
+        gset.s = bsize;
+        gset.total_tiles = gt[ngroup];
+        gset.total_tiles32 = gt32[ngroup];
+        gset.total_chunks = gc[ngroup];
         gset.bc = bc;
     }
 
@@ -997,6 +1017,121 @@ int lanczos_impl(const sylv_sep_problem *p, const double *Y, double *X,
     return SYLV_OK;
 }
 
+// ---- autotuning (configuration choice by timing whole solves) --------------------------------
+
+struct EventPair {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~EventPair() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+};
+
+// One solve from x0 = 0 under `o`, timed with events around the whole call; `ok` when every
+// right-hand side converged.
+int timed_solve(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
+                const double *Bextra, double *X, size_t xbytes, const sylv_pcg_opts &o,
+                sylv_pcg_stats *stats, void *ws, size_t ws_bytes, hipStream_t s, EventPair &ev,
+                double &ms, bool &ok) {
+    HIP_TRY(hipMemsetAsync(X, 0, xbytes, s));
+    HIP_TRY(hipEventRecord(ev.e0, s));
+    Layout L;
+    const int rc = solve_impl(probs, nprob, nrhs, Y, Bextra, X, &o, stats, ws, ws_bytes, s, L);
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(ev.e1, s));
+    HIP_TRY(hipEventSynchronize(ev.e1));
+    float t = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&t, ev.e0, ev.e1));
+    ms = t;
+    std::vector<sylv_pcg_stats> h((size_t)nprob * nrhs);
+    HIP_TRY(hipMemcpy(h.data(), stats, sizeof(sylv_pcg_stats) * h.size(), hipMemcpyDeviceToHost));
+    ok = true;
+    for (const sylv_pcg_stats &st : h) ok = ok && st.status == SYLV_OK;
+    return SYLV_OK;
+}
+
+int autotune_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
+                  const double *Bextra, double *X, const sylv_pcg_opts *opts,
+                  sylv_pcg_stats *stats, sylv_tune_result *out, void *ws, size_t ws_bytes,
+                  hipStream_t s) {
+    if (!probs || nprob < 1 || nrhs < 1) { set_err("null problems or nprob, nrhs < 1"); return SYLV_E_INVALID; }
+    if (!out || !X || !stats) { set_err("null X, stats or out"); return SYLV_E_INVALID; }
+    int rc = check_opts(opts);
+    if (rc) return rc;
+    for (int g = 0; g < nprob; ++g)
+        if (!check_problem(&probs[g], g)) return SYLV_E_INVALID;
+    if ((rc = refuse_capture(s, "sylv_autotune"))) return rc;
+    size_t xbytes = 0;
+    for (int g = 0; g < nprob; ++g)
+        xbytes += sizeof(double) * (size_t)nrhs * probs[g].k * probs[g].ny * probs[g].nx;
+    EventPair ev;
+    HIP_TRY(hipEventCreate(&ev.e0));
+    HIP_TRY(hipEventCreate(&ev.e1));
+
+    // candidates: independent CG at each distinct effective tiling, block CG at each block size
+    struct Cand { int block, bsize, rows; };
+    std::vector<Cand> cands;
+    const int k = probs[0].k;
+    const bool face = probs[0].boundary == SYLV_BC_FACE;
+    std::vector<std::pair<int, int>> tilings;
+    for (int rows : {2, 4, 8}) {
+        const std::pair<int, int> t = face ? std::make_pair(2, 2)
+                                           : std::make_pair(apply_rows_for(k, SYLV_F64, rows),
+                                                            apply_rows_for(k, SYLV_F32, rows));
+        if (std::find(tilings.begin(), tilings.end(), t) != tilings.end()) continue;
+        tilings.push_back(t);
+        cands.push_back({0, 0, rows});
+    }
+    for (int bs : {2, 4, 8})
+        if (block_size_ok(nrhs, bs)) cands.push_back({1, bs, 0});
+
+    // the configuration as given first (it also warms up the allocator and the code paths)
+    double ms_given = -1.0, best = -1.0;
+    bool ok = false;
+    Cand pick{0, 0, 0};
+    {
+        double t0 = 0.0, t1 = 0.0;
+        if ((rc = timed_solve(probs, nprob, nrhs, Y, Bextra, X, xbytes, *opts, stats, ws, ws_bytes,
+                              s, ev, t0, ok)))
+            return rc;
+        if ((rc = timed_solve(probs, nprob, nrhs, Y, Bextra, X, xbytes, *opts, stats, ws, ws_bytes,
+                              s, ev, t1, ok)))
+            return rc;
+        ms_given = ok ? std::min(t0, t1) : -1.0;
+    }
+    for (const Cand &c : cands) {
+        sylv_pcg_opts o = *opts;
+        o.block = c.block;
+        o.block_size = c.bsize;
+        o.apply_rows = c.rows;
+        double t = 1e300;
+        bool all_ok = true;
+        for (int rep = 0; rep < 2; ++rep) {
+            double ms = 0.0;
+            if ((rc = timed_solve(probs, nprob, nrhs, Y, Bextra, X, xbytes, o, stats, ws, ws_bytes,
+                                  s, ev, ms, ok)))
+                return rc;
+            all_ok = all_ok && ok;
+            t = std::min(t, ms);
+        }
+        if (all_ok && (best < 0.0 || t < best)) {
+            best = t;
+            pick = c;
+        }
+    }
+    out->block = pick.block;
+    out->block_size = pick.bsize;
+    out->apply_rows = pick.rows;
+    out->candidates = (int32_t)cands.size();
+    out->ms = best;
+    out->ms_given = ms_given;
+    if (best < 0.0) {
+        set_err("no candidate configuration converged for every right-hand side");
+        return SYLV_NOT_CONVERGED;
+    }
+    return SYLV_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1124,6 +1259,14 @@ int sylv_pcg_backward(const sylv_problem *prob, const double *Y, const double *X
                         (int)prob->nx, prob->boundary, dkappa, dtau, dA, dW, dY,
                         reinterpret_cast<double *>(base + L.gpartial), s));
     return SYLV_OK;
+}
+
+int sylv_autotune(const sylv_problem *probs, int32_t nprob, int32_t nrhs, const double *Y,
+                  const double *Bextra, double *X, const sylv_pcg_opts *opts,
+                  sylv_pcg_stats *stats, sylv_tune_result *out, void *ws, size_t ws_bytes,
+                  void *stream) {
+    return autotune_impl(probs, nprob, nrhs, Y, Bextra, X, opts, stats, out, ws, ws_bytes,
+                         reinterpret_cast<hipStream_t>(stream));
 }
 
 size_t sylv_lanczos_workspace_bytes(const sylv_sep_problem *prob, const sylv_lanczos_opts *opts) {

@@ -33,10 +33,11 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_header_struct_sizes_match_binding():
-    # int64 x2 + int32 x2 + 4 pointers + int32 x2; double, int32 x2, double, int32 x4;
-    # int32 x4 + double x2
+    # int64 x2 + int32 x2 + 4 pointers + int32 x2; double, int32 x2, double, int32 x8;
+    # int32 x4 + double x2 (stats and tune result)
     assert ctypes.sizeof(bd._Problem) == 64
-    assert ctypes.sizeof(bd._Opts) == 48
+    assert ctypes.sizeof(bd._Opts) == 56
+    assert ctypes.sizeof(bd._TuneResult) == 32
     assert ctypes.sizeof(bd._Stats) == 32
 
 
@@ -80,7 +81,10 @@ def test_null_pointers_and_bad_options_rejected():
                  bd._Opts(1e-8, 10, 7, 0.0, 0, 2, 0, 0), bd._Opts(1e-8, 10, 0, 0.0, 0, 9, 0, 0),
                  bd._Opts(1e-8, 10, 1, 2.0, 0, 2, 0, 0), bd._Opts(1e-8, 10, 0, 0.0, 0, 2, 0, 0, 2),
                  bd._Opts(1e-8, 10, 0, 0.0, 0, 2, 0, 0, 0, 2), bd._Opts(1e-8, 10, 0, 0.0, 0, 2, 0, 0, 0, -1),
-                 bd._Opts(1e-8, 10, 0, 0.0, 0, 2, 0, 1, 0, 1)]:
+                 bd._Opts(1e-8, 10, 0, 0.0, 0, 2, 0, 1, 0, 1),
+                 bd._Opts(1e-8, 10, 0, 0.0, 0, 2, 0, 0, 0, 0, 3, 0),
+                 bd._Opts(1e-8, 10, 0, 0.0, 0, 2, 0, 0, 0, 0, 0, 5),
+                 bd._Opts(1e-8, 10, 0, 0.0, 0, 2, 0, 1, 0, 0, 4, 0)]:
         rc = L.sylv_pcg_solve(ctypes.byref(p), 1, 1, FAKE, None, FAKE, ctypes.byref(opts), st,
                               FAKE, 1 << 40, None)
         assert rc == bd.SYLV_E_INVALID, L.sylv_last_error()
@@ -92,6 +96,24 @@ def test_null_pointers_and_bad_options_rejected():
     arr = (bd._Problem * 2)(fake_problem(k=3), fake_problem(k=4))
     assert L.sylv_pcg_solve(arr, 2, 1, FAKE, None, FAKE, ctypes.byref(ok), st, FAKE, 1 << 40,
                             None) == bd.SYLV_E_INVALID
+
+
+def test_autotune_arguments_rejected():
+    L = sy.lib()
+    p = fake_problem()
+    ok = bd._Opts(1e-8, 10, 0, 0.0, 0, 2, 0, 0)
+    res = bd._TuneResult()
+    # no result struct, no X, bad options, bad problem: rejected before any HIP call
+    assert L.sylv_autotune(ctypes.byref(p), 1, 1, FAKE, None, FAKE, ctypes.byref(ok), FAKE, None,
+                           FAKE, 1 << 40, None) == bd.SYLV_E_INVALID
+    assert L.sylv_autotune(ctypes.byref(p), 1, 1, FAKE, None, None, ctypes.byref(ok), FAKE,
+                           ctypes.byref(res), FAKE, 1 << 40, None) == bd.SYLV_E_INVALID
+    bad = bd._Opts(1e-8, 10, 0, 0.0, 0, 2, 0, 0, 0, 0, 0, 3)
+    assert L.sylv_autotune(ctypes.byref(p), 1, 1, FAKE, None, FAKE, ctypes.byref(bad), FAKE,
+                           ctypes.byref(res), FAKE, 1 << 40, None) == bd.SYLV_E_INVALID
+    q = fake_problem(k=0)
+    assert L.sylv_autotune(ctypes.byref(q), 1, 1, FAKE, None, FAKE, ctypes.byref(ok), FAKE,
+                           ctypes.byref(res), FAKE, 1 << 40, None) == bd.SYLV_E_INVALID
 
 
 def test_workspace_too_small_and_misaligned():
