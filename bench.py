@@ -285,6 +285,14 @@ def bench_batched(sy, torch, steps, warmup):
         ms, st, _ = time_solves(sy, torch, dps, Y, B, o, nrhs, steps, warmup)
         res[label] = summarize(ms, st)
         log(f"batched_8grids {label}: {res[label]}")
+    # the configuration chosen by the autotuner (whole solves timed per candidate)
+    base = sy.SolveOptions(tol=1e-8, precision=sy.SYLV_PREC_MIXED)
+    tuned, tres = sy.autotune(dps, Y=Y, Bextra=B, opts=base, nrhs=nrhs)
+    ms, st, _ = time_solves(sy, torch, dps, Y, B, tuned, nrhs, steps, warmup)
+    res["autotuned_mixed"] = dict(summarize(ms, st), block=tuned.block,
+                                  block_size=tuned.block_size, apply_rows=tuned.apply_rows,
+                                  candidates=tres["candidates"])
+    log(f"batched_8grids autotuned_mixed: {res['autotuned_mixed']}")
     # the block-CG batch as one graph launch (fixed schedule)
     o = sy.SolveOptions(tol=1e-8, precision=sy.SYLV_PREC_MIXED, block=1)
     res["graph_block_mixed"] = graph_solve(sy, torch, dps, Y, B, o, nrhs, steps, warmup)
