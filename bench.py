@@ -138,6 +138,19 @@ def cpu_baseline(prob, tol):
                        f"relres {res['relres_true']:.2e}); host reports {os.cpu_count()} CPUs")
 
 
+def oracle_sample(prob, nit=10):
+    """Seconds for the oracle's assembly of G and per PCG iteration (block-Jacobi) on `prob`:
+    a bounded sample that estimates scale linearly in pixels (sparse operators)."""
+    from oracle import operator as op
+    from oracle import pcg as opcg
+    t0 = time.perf_counter()
+    G = op.posterior_precision(prob)
+    t1 = time.perf_counter()
+    opcg.pcg(prob, G=G, tol=0.0, max_iter=nit, precond="block")
+    t2 = time.perf_counter()
+    return t1 - t0, (t2 - t1) / nit
+
+
 def time_solves(sy, torch, probs, Y, B, opts, nrhs, steps, warmup):
     """Median time of `steps` solves after `warmup`, with the last stats."""
     plist = probs if isinstance(probs, list) else [probs]
@@ -232,7 +245,7 @@ def summarize(ms, st):
             "all_ok": all(s["status"] == 0 for s in st)}
 
 
-def bench_masked(sy, torch, steps, warmup):
+def bench_masked(sy, torch, steps, warmup, cpu=False):
     """2048^2, k = 4, f = 9, 10 % masked pixels (beyond the last-level cache): mixed precision vs
     float64 solves and the stand-alone applies."""
     from workloads import workload
@@ -256,10 +269,22 @@ def bench_masked(sy, torch, steps, warmup):
         res[label] = {"us": round(t * 1e3, 2), "algorithmic_bytes": nb,
                       "gbs": round(nb / (t * 1e-3) / 1e9, 1)}
         log(f"masked_2048 {label}: {res[label]}")
+    if cpu:
+        # the oracle on a 512^2 grid of the same recipe, scaled by the pixel count
+        from workloads import make_problem
+        small = make_problem(512, 512, prob.k, prob.f, seed=1002, noise="hetero", mask_frac=0.1)
+        ta, tit = oracle_sample(small)
+        scale = prob.n_pix / small.n_pix
+        est = scale * (ta + tit * res["f64"]["iters_max"])
+        res["cpu_oracle"] = {"kind": "oracle", "estimate_ms": round(est * 1e3, 0),
+                             "sample": "assembly and 10 block-Jacobi PCG iterations of the oracle "
+                                       "on a 512^2 grid of the same recipe, scaled by the pixel "
+                                       "count (16x) and the float64 GPU run's iteration count"}
+        log(f"masked_2048 cpu oracle: {res['cpu_oracle']}")
     return res
 
 
-def bench_batched(sy, torch, steps, warmup):
+def bench_batched(sy, torch, steps, warmup, cpu=False):
     """8 uneven grids x 8 perturbation-optimisation right-hand sides (64 posterior samples):
     independent and block CG, mixed precision and float64."""
     from workloads import WORKLOADS, workload
@@ -299,14 +324,26 @@ def bench_batched(sy, torch, steps, warmup):
     log(f"batched_8grids graph_block_mixed: {res['graph_block_mixed']}")
     res["right_hand_sides"] = len(probs) * nrhs
     res["pixels"] = sum(p.n_pix for p in probs)
+    if cpu:
+        # the oracle on the batch's smallest grid, scaled by pixels, right-hand sides and the
+        # float64 independent-CG iteration count (one assembly per grid)
+        ta, tit = oracle_sample(probs[0])
+        scale = res["pixels"] / probs[0].n_pix
+        est = scale * (ta + tit * nrhs * res["independent_f64"]["iters_max"])
+        res["cpu_oracle"] = {"kind": "oracle", "estimate_ms": round(est * 1e3, 0),
+                             "sample": f"assembly and 10 block-Jacobi PCG iterations of the oracle "
+                                       f"on the {probs[0].ny}^2 grid, scaled by the batch's pixel "
+                                       f"count, {nrhs} right-hand sides per grid and the float64 "
+                                       "GPU run's iteration count"}
+        log(f"batched_8grids cpu oracle: {res['cpu_oracle']}")
     return res
 
 
 def bench_other_workloads(sy, torch, steps, warmup, cpu=False):
     """The other workloads of the solver, timed the same way (not the headline value)."""
     from workloads import WORKLOADS, workload
-    out = {"masked_2048": bench_masked(sy, torch, steps, warmup),
-           "batched_8grids": bench_batched(sy, torch, steps, warmup)}
+    out = {"masked_2048": bench_masked(sy, torch, steps, warmup, cpu=cpu),
+           "batched_8grids": bench_batched(sy, torch, steps, warmup, cpu=cpu)}
     # 512^2, k = 4, f = 9: forward solve + adjoint (gradients w.r.t. kappa, tau, A, W, Y)
     prob = workload("grad_512")[0]
     dp = sy.DeviceProblem.from_numpy(prob)
