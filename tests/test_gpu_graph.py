@@ -246,3 +246,57 @@ def test_synchronising_calls_refused_under_capture():
     # the stream is usable afterwards
     Xa, sa = sy.pcg_solve(dp, Y=dev(p.Y), opts=opts)
     assert sa[0]["status"] == 0
+
+
+def test_fixed_schedule_backward_equals_adaptive():
+    """The adjoint solve and its gradient reductions under the fixed schedule (capturable) equal
+    the adaptive call bitwise."""
+    p = make_problem(24, 20, 3, 5, seed=7500, noise="hetero", mask_frac=0.1)
+    dp = sy.DeviceProblem.from_numpy(p)
+    Yd = dev(p.Y)
+    X, st = sy.pcg_solve(dp, Y=Yd, opts=opts_for(sy.SYLV_PREC_F64, sy.SYLV_SCHED_ADAPTIVE))
+    gbar = dev(np.random.default_rng(7501).standard_normal((p.k, p.n_pix)))
+    say("backward fixed vs adaptive")
+    out = []
+    for sched in (sy.SYLV_SCHED_ADAPTIVE, sy.SYLV_SCHED_FIXED):
+        o = opts_for(sy.SYLV_PREC_F64, sched, tol=1e-12)
+        out.append(sy.pcg_backward(dp, Yd, X, gbar, o))
+    (la, ga, sa), (lf, gf, sf) = out
+    assert sa["status"] == 0 and sa == sf
+    assert torch.equal(la, lf)
+    for name in ga:
+        assert torch.equal(ga[name], gf[name]), name
+
+
+@pytest.mark.parametrize("precision,bound", PRECISIONS)
+def test_graph_face_batch(precision, bound):
+    """Three face grids (HEALPix-like, links only inside a face) in one captured solve."""
+    probs = [make_problem(s0, s1, 3, 4, seed=7600 + i, noise="hetero", boundary="face")
+             for i, (s0, s1) in enumerate([(16, 16), (12, 20), (9, 7)])]
+    dps = [sy.DeviceProblem.from_numpy(p) for p in probs]
+    Yd = torch.cat([dev(p.Y.ravel()) for p in probs])
+    opts = opts_for(precision, sy.SYLV_SCHED_FIXED)
+    X, stats, ws = buffers(dps, 1, opts)
+    launch = sy.solve_launcher(dps, X, stats, ws, Y=Yd, opts=opts)
+
+    def solve():
+        X.zero_()
+        launch()
+
+    say("face graph", precision)
+    solve()
+    torch.cuda.synchronize()
+    Xe, se = X.clone(), sy.stats_list(stats, len(probs))
+    g = capture(solve)
+    for rep in range(2):
+        X.fill_(3.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(X, Xe) and sy.stats_list(stats, len(probs)) == se, rep
+    Xh, off = host(Xe), 0
+    for i, p in enumerate(probs):
+        assert se[i]["status"] == 0, se
+        n = p.k * p.n_pix
+        assert rel(Xh[off:off + n].reshape(p.k, p.n_pix), osv.solve_dense(p)) < bound, i
+        off += n
