@@ -50,6 +50,36 @@ def block_jacobi(prob, G=None, kind: str = "block"):
     return apply_inv, inv
 
 
+def fourier_preconditioner(prob):
+    """Minv = (Q + I (x) Mbar)^-1 applied through the 2-D DFT, on periodic grids.
+
+    Each prior block Q_j = tau_j (kappa_j^2 I - Lap)^2 is a polynomial in the periodic Laplacian,
+    so the DFT diagonalises it: the mode whose -Lap eigenvalue is lam gets tau_j (kappa_j^2 +
+    lam)^2.  The data term's per-pixel blocks M_p = sum_f W[f, p] a_f a_f^T are replaced by their
+    mean over pixels, Mbar = sum_f mean_p(W[f, :]) a_f a_f^T, so one k x k block remains per mode
+    (a fixed SPD operator; the paper allows any preconditioner, Section 3.2, remarks after
+    Alg. 2).  When W does not depend on the pixel this is G^-1 exactly.
+    Returns a function r[k, n_pix] -> z[k, n_pix]."""
+    from .solve import fourier_symbols
+    if op.boundary_of(prob) != "periodic":
+        raise ValueError("the Fourier preconditioner needs a periodic grid")
+    k, ny, nx = prob.k, prob.ny, prob.nx
+    wbar = prob.W.mean(axis=1)                          # [f]
+    mbar = (prob.A.T * wbar) @ prob.A                   # sum_f wbar_f a_f a_f^T, [k, k]
+    lam = fourier_symbols(prob)                         # [ny, nx]
+    blk = np.broadcast_to(mbar, (ny, nx, k, k)).copy()
+    for j in range(k):
+        blk[:, :, j, j] += prob.tau[j] * (prob.kappa[j] ** 2 + lam) ** 2
+    inv = np.linalg.inv(blk)                            # [ny, nx, k, k]
+
+    def apply_inv(r):
+        rh = np.fft.fft2(np.asarray(r, dtype=np.float64).reshape(k, ny, nx), axes=(1, 2))
+        zh = np.einsum("yxij,jyx->iyx", inv, rh)
+        return np.fft.ifft2(zh, axes=(1, 2)).real.reshape(k, ny * nx)
+
+    return apply_inv
+
+
 def pcg(prob, b=None, x0=None, tol=1e-12, max_iter=10000, precond="block", G=None,
         record=False):
     """Solve G x = b.  Returns dict(x, iters, relres_rec, relres_true, history[, iterates])."""
@@ -58,7 +88,10 @@ def pcg(prob, b=None, x0=None, tol=1e-12, max_iter=10000, precond="block", G=Non
     if b is None:
         b = op.rhs(prob)
     k, n_pix = prob.k, prob.n_pix
-    Minv, _ = block_jacobi(prob, G, precond)
+    if precond == "fourier":
+        Minv = fourier_preconditioner(prob)
+    else:
+        Minv, _ = block_jacobi(prob, G, precond)
     bv = np.asarray(b, dtype=np.float64).reshape(k, n_pix)
     x = np.zeros((k, n_pix)) if x0 is None else np.array(x0, dtype=np.float64).reshape(k, n_pix)
 

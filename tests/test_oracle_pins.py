@@ -391,3 +391,52 @@ def test_po_sample_statistics():
     sd = np.sqrt(np.diag(Ginv))
     assert np.max(np.abs(X.mean(0) - xs) / sd) < 5.0 / np.sqrt(s) * 1.5
     assert rel(cov, Ginv) < 0.05
+
+
+# ---- Fourier preconditioner (Q + I (x) Mbar)^-1 ----------------------------------------------
+
+@pytest.mark.parametrize("shape", [(8, 8), (6, 10), (5, 3), (1, 7)])
+def test_fourier_preconditioner_inverts_homoscedastic_operator(shape):
+    """With W independent of the pixel, Mbar = M_p and the preconditioner is G^-1: the sparse
+    assembled operator undoes it (odd, even and degenerate grid sides)."""
+    p = make_problem(shape[0], shape[1], 3, 5, seed=9000 + shape[0], noise="homo")
+    Minv = opcg.fourier_preconditioner(p)
+    R = np.random.default_rng(9001).standard_normal((p.k, p.n_pix))
+    Z = Minv(R)
+    assert np.linalg.norm(op.apply(p, Z) - R) <= 1e-11 * np.linalg.norm(R)
+
+
+def test_fourier_preconditioner_uses_pixel_mean_of_weights():
+    """For heteroscedastic W the preconditioner is the inverse operator of the problem whose
+    weights are the per-map pixel means."""
+    p = make_problem(7, 9, 4, 6, seed=9010, noise="hetero", mask_frac=0.2)
+    q = make_problem(7, 9, 4, 6, seed=9010, noise="hetero", mask_frac=0.2)
+    q.W = np.repeat(p.W.mean(axis=1, keepdims=True), p.n_pix, axis=1)
+    R = np.random.default_rng(9011).standard_normal((p.k, p.n_pix))
+    Z = opcg.fourier_preconditioner(p)(R)
+    assert np.linalg.norm(op.apply(q, Z) - R) <= 1e-11 * np.linalg.norm(R)
+    assert np.linalg.norm(op.apply(p, Z) - R) > 1e-3 * np.linalg.norm(R)   # not G^-1 itself
+
+
+def test_fourier_preconditioner_symmetric_positive_definite():
+    p = make_problem(5, 4, 2, 3, seed=9020, noise="hetero", mask_frac=0.1)
+    Minv = opcg.fourier_preconditioner(p)
+    n = p.k * p.n_pix
+    P = np.array([Minv(np.eye(n)[i].reshape(p.k, p.n_pix)).ravel() for i in range(n)]).T
+    assert np.abs(P - P.T).max() <= 1e-13 * np.abs(P).max()
+    assert np.linalg.eigvalsh(0.5 * (P + P.T)).min() > 0
+
+
+def test_fourier_pcg_matches_dense_in_fewer_iterations():
+    p = make_problem(32, 32, 3, 6, seed=9030, noise="hetero", mask_frac=0.1)
+    xd = osv.solve_dense(p)
+    rf = opcg.pcg(p, tol=1e-11, precond="fourier")
+    rb = opcg.pcg(p, tol=1e-11, precond="block")
+    assert np.linalg.norm(rf["x"] - xd) <= 1e-8 * np.linalg.norm(xd)
+    assert rf["iters"] < rb["iters"] / 2, (rf["iters"], rb["iters"])
+
+
+def test_fourier_preconditioner_refuses_face_grids():
+    p = make_problem(6, 6, 2, 3, seed=9040, noise="hetero", boundary="face")
+    with pytest.raises(ValueError):
+        opcg.fourier_preconditioner(p)
