@@ -120,3 +120,26 @@ def test_autotune_batch(tmp_path):
     check(probs, etas, X, st, 4, 1e-7)
     tuned2, res2 = sy.autotune(dps, Y=Y, Bextra=B, opts=base, nrhs=4, cache=cache)
     assert res2["cached"] and tuned2 == tuned
+
+
+@pytest.mark.parametrize("precision,bound,tol", PRECISIONS)
+def test_blocks_on_face_grids_and_odd_sizes(precision, bound, tol):
+    """Face grids (links only inside the grid) with odd pixel counts and tails shorter than one
+    wavefront: the element-wise access path of the streaming block kernels."""
+    nrhs = 4
+    probs = [make_problem(s0, s1, 3, 4, seed=8400 + i, noise="hetero", boundary="face")
+             for i, (s0, s1) in enumerate([(5, 7), (13, 11), (3, 1), (17, 16)])]
+    etas, Ycat, Bcat = [], [], []
+    for i, p in enumerate(probs):
+        xi, zeta = po_draws(p, nrhs, seed=8410 + i)
+        eta = opo.perturbation(p, xi, zeta)
+        etas.append(eta)
+        Ycat.append(p.Y.ravel())
+        Bcat.append(eta.ravel())
+    dps = [sy.DeviceProblem.from_numpy(p) for p in probs]
+    say("face blocks", precision)
+    for bs in (2, 4):
+        o = sy.SolveOptions(tol=tol, precision=precision, block=1, block_size=bs)
+        X, st = sy.pcg_solve(dps, Y=dev(np.concatenate(Ycat)), Bextra=dev(np.concatenate(Bcat)),
+                             opts=o, nrhs=nrhs)
+        check(probs, etas, X, st, nrhs, bound)
