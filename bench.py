@@ -363,6 +363,24 @@ def bench_other_workloads(sy, torch, steps, warmup, cpu=False):
     out["grad_512"] = {"forward": summarize(ms_f, st), "backward_ms": round(ms_b, 3),
                        "backward_iters": stb["iters"], "backward_ok": stb["status"] == 0}
     log(f"grad_512: {out['grad_512']}")
+    if cpu:
+        # the oracle at full size: assembly and 10 PCG iterations (scaled to the forward and
+        # adjoint iteration counts of the GPU run) plus its gradient contractions, timed once
+        from oracle import grad as og
+        ta, tit = oracle_sample(prob)
+        xg = X.detach().cpu().numpy().reshape(prob.k, prob.n_pix)
+        lg = torch.randn_like(X).cpu().numpy().reshape(prob.k, prob.n_pix)
+        t0 = time.perf_counter()
+        og.implicit_grads(prob, xg, lg)
+        tg = time.perf_counter() - t0
+        est = ta + tit * (st[0]["iters"] + stb["iters"]) + tg
+        out["grad_512"]["cpu_oracle"] = {
+            "kind": "oracle", "estimate_ms": round(est * 1e3, 0),
+            "gradient_contractions_ms": round(tg * 1e3, 1),
+            "sample": "assembly and 10 block-Jacobi PCG iterations of the oracle at 512^2, scaled "
+                      "to the GPU run's forward + adjoint iteration counts, plus the oracle's "
+                      "gradient contractions at full size"}
+        log(f"grad_512 cpu oracle: {out['grad_512']['cpu_oracle']}")
     out["sylv_1024"] = bench_sylvester(sy, torch, steps, warmup, cpu=cpu)
     out["healpix_sky_1024"] = bench_sky(sy, torch, steps, warmup, cpu=cpu)
     out["sweep_1024"] = bench_sweep(sy, torch)
