@@ -143,3 +143,19 @@ def test_blocks_on_face_grids_and_odd_sizes(precision, bound, tol):
         X, st = sy.pcg_solve(dps, Y=dev(np.concatenate(Ycat)), Bextra=dev(np.concatenate(Bcat)),
                              opts=o, nrhs=nrhs)
         check(probs, etas, X, st, nrhs, bound)
+
+
+@pytest.mark.parametrize("precision,bound,tol", PRECISIONS)
+@pytest.mark.parametrize("k", [1, 2])
+def test_apply_rows_up_to_eight_at_small_k(precision, bound, tol, k):
+    """At k <= 2 the fused CG applies may take 8 output rows per lane (32 rows per tile); a grid
+    with ragged tiles in both directions, every tiling against the dense solve."""
+    p = make_problem(37, 70, k, 3, seed=8500 + k, noise="hetero", mask_frac=0.1)
+    dp = sy.DeviceProblem.from_numpy(p)
+    xs = osv.solve_dense(p)
+    say("rows small k", precision, k)
+    for rows in (2, 4, 8):
+        o = sy.SolveOptions(tol=tol, precision=precision, apply_rows=rows)
+        X, st = sy.pcg_solve(dp, Y=dev(p.Y), opts=o)
+        assert st[0]["status"] == 0, (rows, st)
+        assert rel(X.cpu().numpy(), xs) < bound, rows
