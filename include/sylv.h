@@ -125,8 +125,10 @@ typedef struct sylv_pcg_opts {
                               no host synchronisation and no restart, so the call may be captured
                               into a HIP graph; launches after a run has converged return at once
                               (about 1-2 us each), so max_iter and refine_max should be set near
-                              what the solve needs.  Both schedules compute the same iterates: the
-                              device takes every stopping decision.                             */
+                              what the solve needs; (max_iter + 1) times the refinement steps
+                              (mixed; 1 for float64) may not exceed 65536 (else SYLV_E_INVALID).
+                              Both schedules compute the same iterates: the device takes every
+                              stopping decision.                                                 */
     int32_t block_size;    /* block = 1: columns per block, 2, 4 or 8, dividing nrhs (0 = nrhs,
                               which must then be 2, 4 or 8); the nrhs / s blocks of a problem
                               iterate independently of each other                               */

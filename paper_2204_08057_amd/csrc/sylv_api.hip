@@ -262,6 +262,16 @@ int check_opts(const sylv_pcg_opts *o) {
     if (o->schedule != SYLV_SCHED_ADAPTIVE && o->schedule != SYLV_SCHED_FIXED) { set_err("bad schedule"); return SYLV_E_INVALID; }
     if (o->block_size != 0 && !block_rhs_supported(o->block_size)) { set_err("block_size must be 0, 2, 4 or 8"); return SYLV_E_INVALID; }
     if (o->apply_rows != 0 && !apply_rows_valid(o->apply_rows)) { set_err("apply_rows must be 0, 2, 4 or 8"); return SYLV_E_INVALID; }
+    if (o->schedule == SYLV_SCHED_FIXED) {
+        // every queued iteration is a few launches (graph nodes when captured): keep it bounded
+        const long long steps = o->precision == SYLV_PREC_MIXED ? (o->refine_max > 0 ? o->refine_max : 8) : 1;
+        if ((long long)(o->max_iter + 1) * steps > kMaxFixedIters) {
+            set_err("fixed schedule: (max_iter + 1) * refinement steps = %lld exceeds %d; set "
+                    "max_iter and refine_max near what the solve needs",
+                    (long long)(o->max_iter + 1) * steps, kMaxFixedIters);
+            return SYLV_E_INVALID;
+        }
+    }
     return SYLV_OK;
 }
 

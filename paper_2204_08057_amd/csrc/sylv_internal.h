@@ -23,6 +23,7 @@ enum Slot { SLOT_PQ = 0, SLOT_RZ = 1, SLOT_RR = 2, SLOT_RES_RR = 3, SLOT_RES_BB 
 constexpr int kNumSlots = 5;
 constexpr int kMaxRestarts = 3;   // residual replacements of a float64 run
 constexpr int kUploadWords = 512; // 32-bit words per table-upload launch (2 KiB of arguments)
+constexpr int kMaxFixedIters = 65536;   // iterations one fixed-schedule call may queue
 // Every workgroup of a consuming CG kernel re-reduces the producer's per-workgroup partials in a
 // fixed order (no atomics, bitwise repeatable).  That read grows with the square of the
 // workgroup count, so instances with more partials than this fold them first in a separate
