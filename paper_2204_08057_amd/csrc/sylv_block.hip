@@ -349,15 +349,18 @@ __global__ __launch_bounds__(kBlock) void k_bapply(const Inst *__restrict__ tab,
     __shared__ T lds[K][LH][LW];
     zero_acc<NQ>(acc);
 
-    const int cmain = wrapi(x0 + tx, nx);
+    const uint32_t np = (uint32_t)n_pix;   // plane length for buffer accesses
+    const int cmain = wrapf(x0 + tx, nx);
     const int hitem = ty * 64 + tx;
     const int hr = hitem >> 2, hc = hitem & 3;
     const int hcol = (hc < 2) ? hc : (kTileX + hc);
     const bool hvalid = hitem < 4 * LH;
-    const int hoff = hvalid ? wrapi(y0 - 2 + hr, ny) * nx + wrapi(x0 - 2 + hcol, nx) : 0;
-    int soff[RPW];
+    const uint32_t hoff =
+        hvalid ? (uint32_t)(wrapf(y0 - 2 + hr, ny) * nx + wrapf(x0 - 2 + hcol, nx)) : 0u;
+    uint32_t soff[RPW];
 #pragma unroll
-    for (int rr = 0; rr < RPW; ++rr) soff[rr] = wrapi(y0 - 2 + rr * kWavesY + ty, ny) * nx + cmain;
+    for (int rr = 0; rr < RPW; ++rr)
+        soff[rr] = (uint32_t)(wrapf(y0 - 2 + rr * kWavesY + ty, ny) * nx + cmain);
     // face grids: staged positions outside the face hold 0 (absent neighbours)
     bool sin[RPW];
     bool hin = hvalid;
@@ -380,9 +383,9 @@ __global__ __launch_bounds__(kBlock) void k_bapply(const Inst *__restrict__ tab,
         const int ixc = ix < nx ? ix : 0;
 #pragma unroll
         for (int t = 0; t < R; ++t) {
-            const int pix = (iy0 + t < ny ? iy0 + t : 0) * nx + ixc;
+            const uint32_t pix = (uint32_t)((iy0 + t < ny ? iy0 + t : 0) * nx + ixc);
 #pragma unroll
-            for (int e = 0; e < MK; ++e) m[t][e] = M[(size_t)e * n_pix + pix];
+            for (int e = 0; e < MK; ++e) m[t][e] = bld(M + (size_t)e * n_pix, np, pix);
         }
     }
     // every value read from memory that a store below could alias is read first: the active
@@ -407,8 +410,8 @@ __global__ __launch_bounds__(kBlock) void k_bapply(const Inst *__restrict__ tab,
         for (int j = 0; j < K; ++j) {
 #pragma unroll
             for (int rr = 0; rr < RPW; ++rr)
-                sa[j][rr] = sin[rr] ? u[(size_t)j * n_pix + soff[rr]] : (T)0;
-            ha[j] = hin ? u[(size_t)j * n_pix + hoff] : (T)0;
+                sa[j][rr] = sin[rr] ? bld(u + (size_t)j * n_pix, np, soff[rr]) : (T)0;
+            ha[j] = hin ? bld(u + (size_t)j * n_pix, np, hoff) : (T)0;
         }
     };
     {
@@ -493,7 +496,7 @@ __global__ __launch_bounds__(kBlock) void k_bapply(const Inst *__restrict__ tab,
 #pragma unroll
                     for (int j = 0; j < K; ++j) {
                         q[j][t] = tmp[j];
-                        qq[(size_t)j * n_pix + pix] = tmp[j];
+                        bst(qq + (size_t)j * n_pix, np, (uint32_t)pix, tmp[j]);
                     }
                 } else {
 #pragma unroll
