@@ -265,10 +265,11 @@ int check_opts(const sylv_pcg_opts *o) {
     if (o->schedule == SYLV_SCHED_FIXED) {
         // every queued iteration is a few launches (graph nodes when captured): keep it bounded
         const long long steps = o->precision == SYLV_PREC_MIXED ? (o->refine_max > 0 ? o->refine_max : 8) : 1;
-        if ((long long)(o->max_iter + 1) * steps > kMaxFixedIters) {
+        const long long queued = ((long long)o->max_iter + 1) * steps;
+        if (queued > kMaxFixedIters) {
             set_err("fixed schedule: (max_iter + 1) * refinement steps = %lld exceeds %d; set "
                     "max_iter and refine_max near what the solve needs",
-                    (long long)(o->max_iter + 1) * steps, kMaxFixedIters);
+                    queued, kMaxFixedIters);
             return SYLV_E_INVALID;
         }
     }

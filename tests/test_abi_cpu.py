@@ -86,7 +86,10 @@ def test_null_pointers_and_bad_options_rejected():
                  bd._Opts(1e-8, 10, 0, 0.0, 0, 2, 0, 0, 0, 0, 0, 5),
                  bd._Opts(1e-8, 10, 0, 0.0, 0, 2, 0, 1, 0, 0, 4, 0),
                  bd._Opts(1e-8, 70000, 0, 0.0, 0, 2, 0, 0, 0, 1),
-                 bd._Opts(1e-8, 9000, 1, 0.0, 0, 2, 0, 0, 0, 1)]:
+                 bd._Opts(1e-8, 9000, 1, 0.0, 0, 2, 0, 0, 0, 1),
+                 # max_iter + 1 must not overflow 32 bits and slip past the cap
+                 bd._Opts(1e-8, 2**31 - 1, 0, 0.0, 0, 2, 0, 0, 0, 1),
+                 bd._Opts(1e-8, 2**31 - 1, 1, 0.0, 1, 2, 0, 0, 0, 1)]:
         rc = L.sylv_pcg_solve(ctypes.byref(p), 1, 1, FAKE, None, FAKE, ctypes.byref(opts), st,
                               FAKE, 1 << 40, None)
         assert rc == bd.SYLV_E_INVALID, L.sylv_last_error()

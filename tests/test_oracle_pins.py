@@ -259,6 +259,16 @@ def test_fft_equals_dense(shape):
     assert rel(osv.solve_fft(prob), osv.solve_dense(prob)) < 1e-12
 
 
+@pytest.mark.parametrize("shape", [(8, 8, 3, 6), (6, 10, 4, 9), (1, 5, 2, 3), (4, 3, 1, 2)])
+def test_condition_number_equals_dense_spectrum(shape):
+    """cond_2(G) from the per-mode Fourier blocks equals the ratio of the extreme eigenvalues of
+    the explicitly assembled G (LAPACK dsyevd on the dense Kronecker matrix)."""
+    ny, nx, k, f = shape
+    prob = make_problem(ny, nx, k, f, seed=20 + ny, noise="homo")
+    ev = np.linalg.eigvalsh(op.posterior_precision(prob, dense=True))
+    assert osv.condition_number_fft(prob) == pytest.approx(ev.max() / ev.min(), rel=1e-10)
+
+
 def test_fft_exact_at_1024():
     """The Fourier solve is exact at full size: its residual under the independently
     written sum-of-terms operator is at rounding level."""
