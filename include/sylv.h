@@ -23,6 +23,7 @@
  *  - The caller owns all memory.  The library allocates nothing on the device: scratch space
  *    comes from the caller's workspace `ws` of `ws_bytes` bytes (256-byte aligned), sized by
  *    sylv_workspace_bytes().  The workspace must not be shared by calls that overlap in time.
+ *    (sylv_pcg_solve_noalloc uses a static per-device array of the library instead.)
  *  - `stream` is a hipStream_t (NULL = the null stream).  sylv_apply, sylv_precond,
  *    sylv_prepare, sylv_rhs and sylv_po_perturb only enqueue work, with no host
  *    synchronisation, so they may be captured into a HIP graph.  sylv_pcg_solve and
@@ -198,6 +199,25 @@ int sylv_po_perturb(const sylv_problem *prob, const double *xi, const double *ze
 int sylv_pcg_solve(const sylv_problem *probs, int32_t nprob, int32_t nrhs, const double *Y,
                    const double *Bextra, double *X, const sylv_pcg_opts *opts,
                    sylv_pcg_stats *stats, void *ws, size_t ws_bytes, void *stream);
+
+/* Solve without allocation, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): sylv_pcg_solve with the
+ * same arguments and results, except that the workspace is a static array of
+ * SYLV_NOALLOC_SCRATCH_BYTES bytes that the library holds on each device it runs on (from the
+ * first call on that device until the process ends; the first call on a device looks up its
+ * address with hipGetSymbolAddress).  The call allocates nothing and enqueues only kernels.
+ *  - opts->schedule must be SYLV_SCHED_FIXED (else SYLV_E_INVALID): the adaptive schedule
+ *    needs pinned host memory for its convergence checks.
+ *  - A batch whose workspace (sylv_workspace_bytes(probs, nprob, nrhs, opts)) exceeds
+ *    SYLV_NOALLOC_SCRATCH_BYTES is rejected with SYLV_E_WORKSPACE before any work is enqueued.
+ *  - Every call on one device shares that device's array: calls that overlap in time on one
+ *    device (different streams or threads without ordering between them) race and give wrong
+ *    results.  Calls ordered on one stream are safe; nothing in the array has to be cleared
+ *    between them (each call initialises every region it reads). */
+#define SYLV_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int sylv_pcg_solve_noalloc(const sylv_problem *probs, int32_t nprob, int32_t nrhs,
+                           const double *Y, const double *Bextra, double *X,
+                           const sylv_pcg_opts *opts, sylv_pcg_stats *stats, void *stream);
 
 /* Adjoint of the solve.  Given x* = G^-1 B_rhs (Xstar, [k][n_pix]) and Gbar = dL/dx*, solves
  * G lambda = Gbar (G is symmetric, so this is a second PCG run; Lambda is the initial guess on

@@ -36,6 +36,8 @@ from .binding import (  # noqa: F401
     library_path,
     pcg_backward,
     pcg_solve,
+    pcg_solve_noalloc,
+    NOALLOC_SCRATCH_BYTES,
     po_perturb,
     precond,
     rhs,

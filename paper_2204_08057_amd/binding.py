@@ -134,6 +134,7 @@ def lib():
         L.sylv_rhs.argtypes = [P, vp, vp, vp]
         L.sylv_po_perturb.argtypes = [P, vp, vp, vp, i32, vp]
         L.sylv_pcg_solve.argtypes = [P, i32, i32, vp, vp, vp, O, vp, vp, sz, vp]
+        L.sylv_pcg_solve_noalloc.argtypes = [P, i32, i32, vp, vp, vp, O, vp, vp]
         L.sylv_pcg_backward.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, vp, O, vp, vp, sz, vp]
         SP = ctypes.POINTER(_SepProblem)
         LO = ctypes.POINTER(_LzOpts)
@@ -143,7 +144,8 @@ def lib():
         L.sylv_autotune.argtypes = [P, i32, i32, vp, vp, vp, O, vp, ctypes.POINTER(_TuneResult),
                                     vp, sz, vp]
         for name in ("sylv_prepare", "sylv_apply", "sylv_precond", "sylv_rhs", "sylv_po_perturb",
-                     "sylv_pcg_solve", "sylv_pcg_backward", "sylv_lanczos_solve",
+                     "sylv_pcg_solve", "sylv_pcg_solve_noalloc", "sylv_pcg_backward",
+                     "sylv_lanczos_solve",
                      "sylv_autotune"):
             getattr(L, name).restype = ctypes.c_int
         L.sylv_status_string.argtypes = [ctypes.c_int]
@@ -402,6 +404,38 @@ def pcg_solve(problems, Y=None, Bextra=None, X0=None, opts: Optional[SolveOption
     if return_stats:
         return X, _stats_list(stats, len(probs) * nrhs)
     return X, stats
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # SYLV_NOALLOC_SCRATCH_BYTES
+
+
+def pcg_solve_noalloc(problems, Y=None, Bextra=None, X0=None,
+                      opts: Optional[SolveOptions] = None, nrhs: int = 1):
+    """pcg_solve through sylv_pcg_solve_noalloc: the library's static per-device scratch array
+    is the workspace (at most NOALLOC_SCRATCH_BYTES), so the call itself allocates nothing on
+    the device; opts.schedule must be SYLV_SCHED_FIXED.  Returns (X, stats) like pcg_solve."""
+    torch = _torch()
+    single = isinstance(problems, DeviceProblem)
+    probs = [problems] if single else list(problems)
+    opts = opts or SolveOptions(schedule=SYLV_SCHED_FIXED)
+    k = probs[0].k
+    total = sum(nrhs * k * p.n_pix for p in probs)
+    dev = probs[0].W.device
+    if X0 is None:
+        X = torch.zeros(total, dtype=torch.float64, device=dev)
+    else:
+        X = X0.detach().to(torch.float64).contiguous().clone().reshape(-1)
+        if X.numel() != total:
+            raise ValueError("X0 has the wrong size")
+    stats = torch.zeros(len(probs) * nrhs * STATS_BYTES, dtype=torch.uint8, device=dev)
+    arr = (_Problem * len(probs))(*[p.c_struct() for p in probs])
+    o = opts.c_struct()
+    _check(lib().sylv_pcg_solve_noalloc(arr, len(probs), nrhs, _ptr(Y), _ptr(Bextra), _ptr(X),
+                                        ctypes.byref(o), _ptr(stats), _stream()))
+    if single:
+        X = X.reshape(probs[0].k, probs[0].n_pix) if nrhs == 1 else \
+            X.reshape(nrhs, probs[0].k, probs[0].n_pix)
+    return X, _stats_list(stats, len(probs) * nrhs)
 
 
 def solve_launcher(problems, X, stats, ws, Y=None, Bextra=None,

@@ -14,10 +14,17 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <utility>
 #include <vector>
 
 using namespace sylv;
+
+// The workspace of sylv_pcg_solve_noalloc.  Each device the library runs on holds its own copy
+// from the first use until the process ends.  In host code `scratch` names a host-side stand-in,
+// never device memory: kernels receive the device address from hipGetSymbolAddress.
+static_assert(SYLV_NOALLOC_SCRATCH_BYTES % 256 == 0, "scratch size is a multiple of 256");
+static __device__ __align__(256) unsigned char scratch[SYLV_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -1028,6 +1035,62 @@ int lanczos_impl(const sylv_sep_problem *p, const double *Y, double *X,
     return SYLV_OK;
 }
 
+// ---- solves without allocation: a static per-device scratch array as the workspace ---------
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of the current device's scratch array, looked up once per device.
+int scratch_address(void **out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_err("device index %d outside [0, %d)", dev, kMaxDevices);
+        return SYLV_E_INVALID;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr || ((uintptr_t)ptr & (kAlign - 1)) != 0) {
+            set_err("scratch array of device %d at an unaligned address", dev);
+            return SYLV_E_HIP;
+        }
+        g_scratch_dev[dev] = ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return SYLV_OK;
+}
+
+int solve_noalloc_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
+                       const double *Bextra, double *X, const sylv_pcg_opts *opts,
+                       sylv_pcg_stats *stats, hipStream_t s) {
+    if (!probs || nprob < 1 || nrhs < 1) { set_err("null problems or nprob, nrhs < 1"); return SYLV_E_INVALID; }
+    if (!opts) { set_err("null opts"); return SYLV_E_INVALID; }
+    if (opts->schedule != SYLV_SCHED_FIXED) {
+        set_err("the no-allocation solve runs the fixed schedule only (the adaptive schedule "
+                "needs pinned host memory for its convergence checks)");
+        return SYLV_E_INVALID;
+    }
+    for (int g = 0; g < nprob; ++g)
+        if (!check_problem(&probs[g], g)) return SYLV_E_INVALID;
+    Layout L;
+    make_layout(probs, nprob, nrhs, true, L);
+    if (L.total > SYLV_NOALLOC_SCRATCH_BYTES) {
+        set_err("the batch needs %zu bytes of workspace; the no-allocation solve has %zu "
+                "(use sylv_pcg_solve with a caller workspace)",
+                L.total, (size_t)SYLV_NOALLOC_SCRATCH_BYTES);
+        return SYLV_E_WORKSPACE;
+    }
+    void *ws = nullptr;
+    int rc = scratch_address(&ws);
+    if (rc) return rc;
+    Layout L2;
+    return solve_impl(probs, nprob, nrhs, Y, Bextra, X, opts, stats, ws,
+                      SYLV_NOALLOC_SCRATCH_BYTES, s, L2);
+}
+
 // ---- autotuning (configuration choice by timing whole solves) --------------------------------
 
 struct EventPair {
@@ -1252,6 +1315,13 @@ int sylv_pcg_solve(const sylv_problem *probs, int32_t nprob, int32_t nrhs, const
     Layout L;
     return solve_impl(probs, nprob, nrhs, Y, Bextra, X, opts, stats, ws, ws_bytes,
                       reinterpret_cast<hipStream_t>(stream), L);
+}
+
+int sylv_pcg_solve_noalloc(const sylv_problem *probs, int32_t nprob, int32_t nrhs,
+                           const double *Y, const double *Bextra, double *X,
+                           const sylv_pcg_opts *opts, sylv_pcg_stats *stats, void *stream) {
+    return solve_noalloc_impl(probs, nprob, nrhs, Y, Bextra, X, opts, stats,
+                              reinterpret_cast<hipStream_t>(stream));
 }
 
 int sylv_pcg_backward(const sylv_problem *prob, const double *Y, const double *Xstar,

@@ -214,3 +214,26 @@ def test_lanczos_bad_options_rejected():
 
 def test_bad_input_status_string():
     assert "n_p" in sy.status_string(bd.SYLV_BAD_INPUT)
+
+
+def test_noalloc_solve_refusals_before_any_device_call():
+    """The no-allocation solve refuses the adaptive schedule and batches whose workspace exceeds
+    its static scratch array, before touching the device (FAKE pointers are never read)."""
+    L = sy.lib()
+    fixed = bd._Opts(1e-8, 10, 0, 0.0, 0, 2, 0, 0, 0, bd.SYLV_SCHED_FIXED)
+    adaptive = bd._Opts(1e-8, 10, 0, 0.0, 0, 2, 0, 0, 0, bd.SYLV_SCHED_ADAPTIVE)
+    small = fake_problem(16, 16)
+    rc = L.sylv_pcg_solve_noalloc(ctypes.byref(small), 1, 1, FAKE, None, FAKE,
+                                  ctypes.byref(adaptive), FAKE, None)
+    assert rc == bd.SYLV_E_INVALID and b"fixed schedule" in L.sylv_last_error()
+    big = fake_problem(1024, 1024)
+    need = L.sylv_workspace_bytes(ctypes.byref(big), 1, 1, ctypes.byref(fixed))
+    assert need > bd.NOALLOC_SCRATCH_BYTES
+    rc = L.sylv_pcg_solve_noalloc(ctypes.byref(big), 1, 1, FAKE, None, FAKE,
+                                  ctypes.byref(fixed), FAKE, None)
+    assert rc == bd.SYLV_E_WORKSPACE and b"no-allocation" in L.sylv_last_error()
+    assert L.sylv_pcg_solve_noalloc(None, 1, 1, FAKE, None, FAKE, ctypes.byref(fixed), FAKE,
+                                    None) == bd.SYLV_E_INVALID
+    bad = fake_problem(16, 16, k=9)
+    assert L.sylv_pcg_solve_noalloc(ctypes.byref(bad), 1, 1, FAKE, None, FAKE,
+                                    ctypes.byref(fixed), FAKE, None) == bd.SYLV_E_INVALID
