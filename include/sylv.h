@@ -293,6 +293,40 @@ int sylv_lanczos_solve(const sylv_sep_problem *prob, const double *Y, double *X,
                        const sylv_lanczos_opts *opts, sylv_lanczos_stats *stats, void *ws,
                        size_t ws_bytes, void *stream);
 
+/* ---- sparse-dense Sylvester solver (Section 3.3.1, Alg. 3) ------------------------------------
+ *
+ * The same separable, equal-kappa system as sylv_lanczos_solve, N^-1 D2 M + M Lhat = F
+ * (eq. (Axb-Sylv), F = Y^T T A P^-1), solved by the method the paper compares against
+ * (Alg. 3, the sparse-dense form eq. (sparse-dense-Sylvester) with H = N^-1 D2, L = Lhat): with
+ * Lhat = W R W^-1 and R upper triangular, column i of Xhat = M W solves the shifted sparse
+ * system (H + R_ii I) xhat_i = F W e_i - sum_(l<i) xhat_l R_li, here multiplied through by N,
+ *
+ *     (D2 + R_ii N) xhat_i = N (F W e_i - sum_(l<i) xhat_l R_li),
+ *
+ * whose matrix is symmetric positive definite (R_ii are the eigenvalues of Lhat, positive by
+ * Lemma 2), and M = Xhat W^-1.  Each column system is solved on the GPU by the preconditioned
+ * conjugate-gradient solver of sylv_pcg_solve, as a one-component problem (kappa, tau = 1,
+ * A = sqrt(R_ii), W = n), with the options `opts` (float64 or mixed precision, tolerance
+ * relative to each column's right-hand side).
+ *   decouple = 0: W is orthogonal and R triangular, a real Schur form of Lhat (Alg. 3); the
+ *                 columns are solved one after another, each right-hand side using the
+ *                 previous columns.  (The Schur vectors are obtained from Lemma 2's
+ *                 eigenvectors U by a QR factorisation U = W Ru, R = Ru diag(rho) Ru^-1.)
+ *   decouple = 1: W = U, Lemma 2's eigenvectors, and R = diag(rho): the k column systems are
+ *                 independent and run as one batched solve.
+ * n_p may be 0 (masked pixels) as long as D2 + R_ii N stays positive definite (kappa > 0).
+ *   Y: [f][n_pix] float64;  X: [k][n_pix] float64, the solution M on return (column j = map j).
+ *   stats: [k] DEVICE structs, the conjugate-gradient runs of the column systems (in the order
+ *          of the transformed columns).
+ *   relres_true: DEVICE double or NULL: ||b - G x||_2 / ||b||_2 of eq. (Axb) for the result.
+ * Copies tau, A and t to the host (the k x k decompositions are computed there), synchronises
+ * `stream`, and refuses a capturing stream. */
+size_t sylv_kohler_workspace_bytes(const sylv_sep_problem *prob, int32_t decouple,
+                                   const sylv_pcg_opts *opts);
+int sylv_kohler_solve(const sylv_sep_problem *prob, const double *Y, double *X,
+                      int32_t decouple, const sylv_pcg_opts *opts, sylv_pcg_stats *stats,
+                      double *relres_true, void *ws, size_t ws_bytes, void *stream);
+
 /* ---- autotuning of the solver configuration --------------------------------------------- */
 
 /* Result of sylv_autotune: the configuration to copy into sylv_pcg_opts. */

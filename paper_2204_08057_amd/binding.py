@@ -141,11 +141,14 @@ def lib():
         L.sylv_lanczos_workspace_bytes.argtypes = [SP, LO]
         L.sylv_lanczos_workspace_bytes.restype = sz
         L.sylv_lanczos_solve.argtypes = [SP, vp, vp, LO, ctypes.POINTER(_LzStats), vp, sz, vp]
+        L.sylv_kohler_workspace_bytes.argtypes = [SP, i32, O]
+        L.sylv_kohler_workspace_bytes.restype = sz
+        L.sylv_kohler_solve.argtypes = [SP, vp, vp, i32, O, vp, vp, vp, sz, vp]
         L.sylv_autotune.argtypes = [P, i32, i32, vp, vp, vp, O, vp, ctypes.POINTER(_TuneResult),
                                     vp, sz, vp]
         for name in ("sylv_prepare", "sylv_apply", "sylv_precond", "sylv_rhs", "sylv_po_perturb",
                      "sylv_pcg_solve", "sylv_pcg_solve_noalloc", "sylv_pcg_backward",
-                     "sylv_lanczos_solve",
+                     "sylv_lanczos_solve", "sylv_kohler_solve",
                      "sylv_autotune"):
             getattr(L, name).restype = ctypes.c_int
         L.sylv_status_string.argtypes = [ctypes.c_int]
@@ -684,3 +687,35 @@ def lanczos_solve(problem: SepProblem, Y, opts: Optional[LanczosOptions] = None,
                                     ctypes.byref(st), _ptr(ws), ws.numel(), _stream()))
     return X, {"status": st.status, "status_name": STATUS_NAMES.get(st.status, str(st.status)),
                "iters": st.iters, "relres_est": st.relres_est, "relres_true": st.relres_true}
+
+
+def kohler_workspace_bytes(problem: SepProblem, decouple: bool = False,
+                           opts: Optional[SolveOptions] = None) -> int:
+    opts = opts or SolveOptions()
+    ps, o = problem.c_struct(), opts.c_struct()
+    n = lib().sylv_kohler_workspace_bytes(ctypes.byref(ps), int(bool(decouple)), ctypes.byref(o))
+    if n == 0:
+        _check(SYLV_E_INVALID)
+    return int(n)
+
+
+def kohler_solve(problem: SepProblem, Y, opts: Optional[SolveOptions] = None,
+                 decouple: bool = False, ws=None, out=None):
+    """Solution of eq. (Axb-Sylv) by Alg. 3 with conjugate-gradient column solves on the GPU:
+    (X [k, n_pix] float64, per-column statistics list, relative residual of eq. (Axb))."""
+    torch = _torch()
+    opts = opts or SolveOptions()
+    if Y.dtype != torch.float64:
+        raise ValueError("Y must be float64")
+    nb = kohler_workspace_bytes(problem, decouple, opts)
+    if ws is None or ws.numel() < nb:
+        ws = _workspace(nb, Y.device)
+    X = out if out is not None else torch.empty((problem.k, problem.n_pix), dtype=torch.float64,
+                                                device=Y.device)
+    stats = torch.zeros(problem.k * STATS_BYTES, dtype=torch.uint8, device=Y.device)
+    rel = torch.zeros(1, dtype=torch.float64, device=Y.device)
+    ps, o = problem.c_struct(), opts.c_struct()
+    _check(lib().sylv_kohler_solve(ctypes.byref(ps), _ptr(Y), _ptr(X), int(bool(decouple)),
+                                   ctypes.byref(o), _ptr(stats), _ptr(rel), _ptr(ws), ws.numel(),
+                                   _stream()))
+    return X, _stats_list(stats, problem.k), float(rel.item())

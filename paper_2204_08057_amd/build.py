@@ -17,7 +17,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsylv.so")
-SOURCES = ["sylv_kernels.hip", "sylv_block.hip", "sylv_lanczos.hip", "sylv_api.hip"]
+SOURCES = ["sylv_kernels.hip", "sylv_block.hip", "sylv_lanczos.hip", "sylv_kohler.hip",
+           "sylv_api.hip"]
 ARCH = os.environ.get("SYLV_OFFLOAD_ARCH", "gfx950")
 
 

@@ -907,18 +907,13 @@ bool lz_coefficients(int m, int it, const std::vector<double> &H, const std::vec
     return true;
 }
 
-int lanczos_impl(const sylv_sep_problem *p, const double *Y, double *X,
-                 const sylv_lanczos_opts *o, sylv_lanczos_stats *stats, void *ws,
-                 size_t ws_bytes, hipStream_t s) {
+// Small matrices of a separable problem, on the host: the stencil coefficients of D2, t_f A/tau,
+// A^T T A and Lemma 2's P^-1/2 A^T T A P^-1/2 = V diag(rho) V^T with U = P^1/2 V (so that
+// Lhat = U diag(rho) U^-1).  Copies tau, A and t to the host (synchronises s).
+int sep_constants(const sylv_sep_problem *p, LzConst &C, double tau[kMaxK],
+                  double Vm[kMaxK][kMaxK], hipStream_t s) {
     const int k = p->k, f = p->f;
-    LzLayout L;
-    if (!make_lz_layout(p, o, L)) return SYLV_E_INVALID;
-    int rc = check_ws(ws, ws_bytes, L.total);
-    if (rc) return rc;
-    if ((rc = refuse_capture(s, "sylv_lanczos_solve"))) return rc;
-    char *base = reinterpret_cast<char *>(ws);
-    // small parameters to the host (Lemma 2's eigenproblem is solved here)
-    double tau[kMaxK], A[kMaxF * kMaxK], t[kMaxF];
+    double A[kMaxF * kMaxK], t[kMaxF];
     HIP_TRY(hipMemcpyAsync(tau, p->tau, sizeof(double) * k, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(A, p->A, sizeof(double) * f * k, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(t, p->t, sizeof(double) * f, hipMemcpyDeviceToHost, s));
@@ -927,7 +922,6 @@ int lanczos_impl(const sylv_sep_problem *p, const double *Y, double *X,
         if (!(tau[j] > 0.0) || !isfinite(tau[j])) { set_err("tau[%d] must be finite and > 0", j); return SYLV_E_INVALID; }
     for (int i = 0; i < f; ++i)
         if (!(t[i] > 0.0) || !isfinite(t[i])) { set_err("t[%d] must be finite and > 0", i); return SYLV_E_INVALID; }
-    LzConst C;
     memset(&C, 0, sizeof(C));
     const double ks = p->kappa * p->kappa;
     C.coef[0] = (ks + 4.0) * (ks + 4.0) + 4.0;
@@ -943,16 +937,31 @@ int lanczos_impl(const sylv_sep_problem *p, const double *Y, double *X,
             C.ata[j][q] = v;
         }
     }
-    // Lemma 2: P^-1/2 A^T T A P^-1/2 = V diag(rho) V^T, U = P^1/2 V
-    double Sm[kMaxK][kMaxK], Vm[kMaxK][kMaxK];
+    double Sm[kMaxK][kMaxK];
     for (int j = 0; j < k; ++j)
         for (int q = 0; q < k; ++q) Sm[j][q] = C.ata[j][q] / sqrt(tau[j] * tau[q]);
     sym_eig(k, Sm, C.rho, Vm);
     if (!(C.rho[0] > 0.0)) { set_err("A^T T A is not positive definite (A must have full column rank)"); return SYLV_E_INVALID; }
     for (int j = 0; j < k; ++j)
         for (int q = 0; q < k; ++q) C.U[j][q] = sqrt(tau[j]) * Vm[j][q];
-    C.tol = o->tol;
     C.kappa2 = ks;
+    return SYLV_OK;
+}
+
+int lanczos_impl(const sylv_sep_problem *p, const double *Y, double *X,
+                 const sylv_lanczos_opts *o, sylv_lanczos_stats *stats, void *ws,
+                 size_t ws_bytes, hipStream_t s) {
+    const int k = p->k, f = p->f;
+    LzLayout L;
+    if (!make_lz_layout(p, o, L)) return SYLV_E_INVALID;
+    int rc = check_ws(ws, ws_bytes, L.total);
+    if (rc) return rc;
+    if ((rc = refuse_capture(s, "sylv_lanczos_solve"))) return rc;
+    char *base = reinterpret_cast<char *>(ws);
+    LzConst C;
+    double tau[kMaxK], Vm[kMaxK][kMaxK];
+    if ((rc = sep_constants(p, C, tau, Vm, s))) return rc;
+    C.tol = o->tol;
 
     LzArgs a;
     memset(&a, 0, sizeof(a));
@@ -1032,6 +1041,211 @@ int lanczos_impl(const sylv_sep_problem *p, const double *Y, double *X,
         stats->relres_est = (st.nb0 > 0.0 && st.gamma >= 0.0) ? sqrt(st.gamma) / st.nb0 : (st.nb0 > 0.0 ? NAN : 0.0);
         stats->relres_true = st.bb > 0.0 ? sqrt(st.rr / st.bb) : 0.0;
     }
+    return SYLV_OK;
+}
+
+// ---- sparse-dense Sylvester solver (Section 3.3.1, Alg. 3) ----------------------------------
+
+// Workspace: the shifted column problems' small parameters, the Lanczos start / residual state
+// (F = Yhat is the start block of Alg. 5, and its residual pass checks eq. (Axb)), Xhat, the
+// column right-hand sides, then the conjugate-gradient workspace of the column solves.
+struct KhLayout {
+    size_t par, cst, state, H, B, Binv, hist, G, partial, partial2, Yh, Xh, rhs, solve, total;
+    int nred;
+};
+
+// The column systems as one-component problems: kappa = the common kappa, tau = 1, A = sqrt of
+// the shift, W = n, so that the operator is D2 + shift * N.  Device pointers into `par`
+// (par[0] = kappa, par[1] = 1, par[2 + i] = sqrt(shift_i)).
+void kh_problems(const sylv_sep_problem *p, const double *par, sylv_problem q[kMaxK]) {
+    for (int i = 0; i < p->k; ++i) {
+        sylv_problem &c = q[i];
+        memset(&c, 0, sizeof(c));
+        c.ny = p->ny; c.nx = p->nx; c.k = 1; c.f = 1;
+        c.kappa = par; c.tau = par + 1; c.A = par + 2 + i; c.W = p->n;
+        c.boundary = p->boundary;
+    }
+}
+
+bool make_kh_layout(const sylv_sep_problem *p, int decouple, const sylv_pcg_opts *o,
+                    KhLayout &L) {
+    const size_t n = (size_t)p->ny * p->nx, k = (size_t)p->k;
+    L.nred = std::max(lz_tiles((int)p->ny, (int)p->nx, 2), chunks_for((int)n));
+    const size_t vb = sizeof(double) * k * n;
+    size_t off = 0;
+    L.par = off;      off = align_up(off + sizeof(double) * (2 + kMaxK));
+    L.cst = off;      off = align_up(off + sizeof(LzConst));
+    L.state = off;    off = align_up(off + sizeof(LzState));
+    L.H = off;        off = align_up(off + sizeof(double) * kLzStride * 2);
+    L.B = off;        off = align_up(off + sizeof(double) * kLzStride * 2);
+    L.Binv = off;     off = align_up(off + sizeof(double) * kLzStride * 2);
+    L.hist = off;     off = align_up(off + sizeof(double) * 2);
+    L.G = off;        off = align_up(off + sizeof(double) * kLzStride * 2);
+    L.partial = off;  off = align_up(off + sizeof(double) * kLzSlots * L.nred);
+    L.partial2 = off; off = align_up(off + sizeof(double) * kLzSlots);
+    L.Yh = off;       off = align_up(off + vb);
+    L.Xh = off;       off = align_up(off + vb);
+    L.rhs = off;      off = align_up(off + vb);
+    L.solve = off;
+    // the conjugate-gradient workspace depends only on sizes: lay it out with stand-in pointers
+    sylv_problem q[kMaxK];
+    kh_problems(p, reinterpret_cast<const double *>(kAlign), q);
+    Layout S;
+    make_layout(q, decouple ? p->k : 1, 1, true, S);
+    (void)o;
+    L.total = align_up(off + S.total);
+    return true;
+}
+
+// Real Schur form of Lhat from Lemma 2's eigenvectors: U = Wq Ru (QR, Wq orthogonal, Ru upper
+// triangular) gives Lhat = U diag(rho) U^-1 = Wq (Ru diag(rho) Ru^-1) Wq^T with
+// R = Ru diag(rho) Ru^-1 upper triangular and R_ii = rho_i.  Modified Gram-Schmidt, applied
+// twice.  Returns false if U is numerically singular.
+bool schur_from_eigvecs(int m, const double U[kMaxK][kMaxK], const double rho[kMaxK],
+                        double Wq[kMaxK][kMaxK], double R[kMaxK][kMaxK]) {
+    double Ru[kMaxK][kMaxK] = {};
+    for (int j = 0; j < m; ++j) {
+        double v[kMaxK];
+        for (int i = 0; i < m; ++i) v[i] = U[i][j];
+        for (int pass = 0; pass < 2; ++pass)
+            for (int l = 0; l < j; ++l) {
+                double d = 0.0;
+                for (int i = 0; i < m; ++i) d += Wq[i][l] * v[i];
+                for (int i = 0; i < m; ++i) v[i] -= d * Wq[i][l];
+                Ru[l][j] += d;
+            }
+        double nrm = 0.0;
+        for (int i = 0; i < m; ++i) nrm += v[i] * v[i];
+        nrm = sqrt(nrm);
+        if (!(nrm > 1e-300)) return false;
+        Ru[j][j] = nrm;
+        for (int i = 0; i < m; ++i) Wq[i][j] = v[i] / nrm;
+    }
+    // Ru^-1 (upper triangular), then R = Ru diag(rho) Ru^-1
+    double Ri[kMaxK][kMaxK] = {};
+    for (int j = 0; j < m; ++j) {
+        Ri[j][j] = 1.0 / Ru[j][j];
+        for (int i = j - 1; i >= 0; --i) {
+            double v = 0.0;
+            for (int l = i + 1; l <= j; ++l) v += Ru[i][l] * Ri[l][j];
+            Ri[i][j] = -v / Ru[i][i];
+        }
+    }
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) {
+            double v = 0.0;
+            for (int l = i; l <= j; ++l) v += Ru[i][l] * rho[l] * Ri[l][j];
+            R[i][j] = (j >= i) ? v : 0.0;
+        }
+    return true;
+}
+
+int kohler_impl(const sylv_sep_problem *p, const double *Y, double *X, int decouple,
+                const sylv_pcg_opts *o, sylv_pcg_stats *stats, double *relres, void *ws,
+                size_t ws_bytes, hipStream_t s) {
+    const int k = p->k;
+    KhLayout L;
+    make_kh_layout(p, decouple, o, L);
+    int rc = check_ws(ws, ws_bytes, L.total);
+    if (rc) return rc;
+    if ((rc = refuse_capture(s, "sylv_kohler_solve"))) return rc;
+    char *base = reinterpret_cast<char *>(ws);
+    LzConst C;
+    double tau[kMaxK], Vm[kMaxK][kMaxK];
+    if ((rc = sep_constants(p, C, tau, Vm, s))) return rc;
+    C.tol = o->tol;
+
+    // the column transform W, the triangular R and the back-transform W^-1
+    KhCoef cf;
+    KhBack bk;
+    memset(&cf, 0, sizeof(cf));
+    memset(&bk, 0, sizeof(bk));
+    double shift[kMaxK];
+    if (decouple) {
+        // Lemma 2: Lhat = U diag(rho) U^-1 with U = P^1/2 V, U^-1 = V^T P^-1/2
+        for (int i = 0; i < k; ++i) {
+            shift[i] = C.rho[i];
+            for (int j = 0; j < k; ++j) {
+                cf.Fw[j][i] = C.U[j][i];
+                bk.T[i][j] = Vm[j][i] / sqrt(tau[j]);
+            }
+        }
+    } else {
+        double Wq[kMaxK][kMaxK], R[kMaxK][kMaxK];
+        if (!schur_from_eigvecs(k, C.U, C.rho, Wq, R)) {
+            set_err("Schur vectors of Lhat are singular");
+            return SYLV_E_INVALID;
+        }
+        for (int i = 0; i < k; ++i) {
+            shift[i] = R[i][i];
+            for (int j = 0; j < k; ++j) {
+                cf.Fw[j][i] = Wq[j][i];
+                bk.T[i][j] = Wq[j][i];
+                cf.Rc[j][i] = (j < i) ? R[j][i] : 0.0;
+            }
+        }
+    }
+    for (int i = 0; i < k; ++i)
+        if (!(shift[i] > 0.0)) { set_err("shift %d of the column systems is not positive", i); return SYLV_E_INVALID; }
+    double par[2 + kMaxK];
+    par[0] = p->kappa;
+    par[1] = 1.0;
+    for (int i = 0; i < k; ++i) par[2 + i] = sqrt(shift[i]);
+    HIP_TRY(launch_upload(base + L.par, par, sizeof(double) * (2 + k), s));
+    HIP_TRY(launch_upload(base + L.cst, &C, sizeof(C), s));
+
+    // F = Y^T T A P^-1 into Yh (the Lanczos start kernel), on the Lanczos argument block
+    LzArgs a;
+    memset(&a, 0, sizeof(a));
+    a.ny = (int)p->ny; a.nx = (int)p->nx; a.n_pix = (int)(p->ny * p->nx); a.k = k; a.f = p->f;
+    a.tiles_x = (a.nx + kTileX - 1) / kTileX;
+    a.bc = p->boundary;
+    a.rows = 2;
+    a.ntiles = lz_tiles(a.ny, a.nx, a.rows);
+    a.nchunks = chunks_for(a.n_pix);
+    a.nred = L.nred;
+    a.c = reinterpret_cast<const LzConst *>(base + L.cst);
+    a.st = reinterpret_cast<LzState *>(base + L.state);
+    a.H = reinterpret_cast<double *>(base + L.H);
+    a.B = reinterpret_cast<double *>(base + L.B);
+    a.Binv = reinterpret_cast<double *>(base + L.Binv);
+    a.hist = reinterpret_cast<double *>(base + L.hist);
+    a.partial = reinterpret_cast<double *>(base + L.partial);
+    a.partial2 = reinterpret_cast<double *>(base + L.partial2);
+    a.n = p->n;
+    a.Y = Y;
+    a.Yh = reinterpret_cast<double *>(base + L.Yh);
+    a.X = X;
+    a.G = reinterpret_cast<const double *>(base + L.G);
+    HIP_TRY(lz_launch_init(a, 1, s));
+    HIP_TRY(lz_launch_start(a, s));
+
+    const size_t n = (size_t)a.n_pix;
+    double *Xh = reinterpret_cast<double *>(base + L.Xh);
+    double *rhs = reinterpret_cast<double *>(base + L.rhs);
+    sylv_problem q[kMaxK];
+    kh_problems(p, reinterpret_cast<const double *>(base + L.par), q);
+    void *sws = base + L.solve;
+    const size_t sbytes = ws_bytes - L.solve;
+    HIP_TRY(kh_launch_zero(Xh, (long)(k * n), s));
+    if (decouple) {
+        // every column at once: k independent one-component problems in one batched solve
+        HIP_TRY(kh_launch_rhs(a.Yh, p->n, Xh, cf, k, 0, k, a.n_pix, rhs, s));
+        Layout S;
+        if ((rc = solve_impl(q, k, 1, nullptr, rhs, Xh, o, stats, sws, sbytes, s, S))) return rc;
+    } else {
+        // Alg. 3: column i after columns 0 .. i-1
+        for (int i = 0; i < k; ++i) {
+            HIP_TRY(kh_launch_rhs(a.Yh, p->n, Xh, cf, k, i, i + 1, a.n_pix, rhs, s));
+            Layout S;
+            if ((rc = solve_impl(&q[i], 1, 1, nullptr, rhs + i * n, Xh + i * n, o, stats + i,
+                                 sws, sbytes, s, S)))
+                return rc;
+        }
+    }
+    HIP_TRY(kh_launch_back(Xh, bk, k, a.n_pix, X, s));
+    HIP_TRY(lz_launch_resid(a, s));
+    if (relres) HIP_TRY(kh_launch_relres(a.st, relres, s));
     return SYLV_OK;
 }
 
@@ -1315,6 +1529,26 @@ int sylv_pcg_solve(const sylv_problem *probs, int32_t nprob, int32_t nrhs, const
     Layout L;
     return solve_impl(probs, nprob, nrhs, Y, Bextra, X, opts, stats, ws, ws_bytes,
                       reinterpret_cast<hipStream_t>(stream), L);
+}
+
+size_t sylv_kohler_workspace_bytes(const sylv_sep_problem *prob, int32_t decouple,
+                                   const sylv_pcg_opts *opts) {
+    if (!check_sep(prob) || check_opts(opts) || (decouple != 0 && decouple != 1)) return 0;
+    KhLayout L;
+    make_kh_layout(prob, decouple, opts, L);
+    return L.total;
+}
+
+int sylv_kohler_solve(const sylv_sep_problem *prob, const double *Y, double *X,
+                      int32_t decouple, const sylv_pcg_opts *opts, sylv_pcg_stats *stats,
+                      double *relres_true, void *ws, size_t ws_bytes, void *stream) {
+    if (!check_sep(prob)) return SYLV_E_INVALID;
+    int rc = check_opts(opts);
+    if (rc) return rc;
+    if (decouple != 0 && decouple != 1) { set_err("decouple must be 0 or 1"); return SYLV_E_INVALID; }
+    if (!Y || !X || !stats) { set_err("null Y, X or stats"); return SYLV_E_INVALID; }
+    return kohler_impl(prob, Y, X, decouple, opts, stats, relres_true, ws, ws_bytes,
+                       reinterpret_cast<hipStream_t>(stream));
 }
 
 int sylv_pcg_solve_noalloc(const sylv_problem *probs, int32_t nprob, int32_t nrhs,

@@ -267,7 +267,26 @@ hipError_t lz_launch_start(const LzArgs &a, hipStream_t s);
 hipError_t lz_launch_step(const LzArgs &a, int it, hipStream_t s);
 hipError_t lz_launch_flag(const LzArgs &a, int *host_running, hipStream_t s);
 hipError_t lz_launch_finish(const LzArgs &a, int iters, hipStream_t s);
+// Residual pass of eq. (Axb) for a.X (stencil pass, reduction, ||r||^2 and ||b||^2 into a.st);
+// needs the start block a.Yh (lz_launch_start).
+hipError_t lz_launch_resid(const LzArgs &a, hipStream_t s);
 int lz_tiles(int ny, int nx, int rows);
+
+// ---- sparse-dense Sylvester solver, Alg. 3 (sylv_kohler.hip) -------------------------------
+// Right-hand sides of the shifted column systems: b_i = n (.) (Yh Fw e_i - sum_(l<i) Rc[l][i] xhat_l)
+struct KhCoef {
+    double Fw[kMaxK][kMaxK];      // F -> F W (column transform of the right-hand side)
+    double Rc[kMaxK][kMaxK];      // strictly upper part of R (zero when decoupled)
+};
+struct KhBack {
+    double T[kMaxK][kMaxK];       // M = Xhat T, T = W^-1
+};
+hipError_t kh_launch_rhs(const double *Yh, const double *n, const double *Xh, const KhCoef &c,
+                         int k, int i0, int i1, int n_pix, double *b, hipStream_t s);
+hipError_t kh_launch_back(const double *Xh, const KhBack &t, int k, int n_pix, double *X,
+                          hipStream_t s);
+hipError_t kh_launch_zero(double *x, long n, hipStream_t s);
+hipError_t kh_launch_relres(const LzState *st, double *out, hipStream_t s);
 int lz_rows_valid(int k, int rows);
 
 }  // namespace sylv

@@ -826,11 +826,19 @@ hipError_t lz_launch_flag(const LzArgs &a, int *host_running, hipStream_t s) {
 }
 
 hipError_t lz_launch_finish(const LzArgs &a, int iters, hipStream_t s) {
-    return dispatch_k(a.k, [&](auto kt) -> hipError_t {
+    hipError_t e = dispatch_k(a.k, [&](auto kt) -> hipError_t {
         constexpr int K = decltype(kt)::value;
         hipLaunchKernelGGL((k_lz_assemble<K>), dim3(a.nchunks), dim3(kBlock), 0, s, a, iters);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+    return lz_launch_resid(a, s);
+}
+
+hipError_t lz_launch_resid(const LzArgs &a, hipStream_t s) {
+    return dispatch_k(a.k, [&](auto kt) -> hipError_t {
+        constexpr int K = decltype(kt)::value;
+        hipError_t e;
         if (a.bc == SYLV_BC_FACE)
             hipLaunchKernelGGL((k_lz_stencil<K, LZ_RESID, 2, BC_FACE>), dim3(a.ntiles),
                                dim3(kBlock), 0, s, a, 0);
