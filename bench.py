@@ -499,25 +499,32 @@ def bench_sylvester(sy, torch, steps, warmup, max_iter=800, cpu=False):
     t, n = prob.meta["t"], prob.meta["n"]
     sp = sy.SepProblem.from_numpy(prob.ny, prob.nx, prob.kappa[0], prob.tau, prob.A, t, n)
     Y = torch.as_tensor(prob.Y, device="cuda")
-    lo = sy.LanczosOptions(tol=tol, max_iter=max_iter)
-    ws = torch.empty(sy.lanczos_workspace_bytes(sp, lo), dtype=torch.uint8, device="cuda")
     X = torch.empty((prob.k, prob.n_pix), dtype=torch.float64, device="cuda")
-    for _ in range(warmup):
-        sy.lanczos_solve(sp, Y, lo, ws=ws, out=X)
-    torch.cuda.synchronize()
-    times = []
-    for _ in range(steps):
-        t0 = time.perf_counter()
-        _, st = sy.lanczos_solve(sp, Y, lo, ws=ws, out=X)
+    res = {}
+    # the basis kept in HBM (one streaming assembly pass) and Alg. 5's second Lanczos pass (two
+    # kept blocks; the recurrence runs again from the kept coefficients)
+    for label, mode in (("lanczos_sylvester", sy.SYLV_LZ_KEEP_BASIS),
+                        ("lanczos_sylvester_rerun", sy.SYLV_LZ_RERUN)):
+        lo = sy.LanczosOptions(tol=tol, max_iter=max_iter, assembly=mode)
+        ws = torch.empty(sy.lanczos_workspace_bytes(sp, lo), dtype=torch.uint8, device="cuda")
+        Xm = X if mode == sy.SYLV_LZ_KEEP_BASIS else torch.empty_like(X)
+        for _ in range(warmup):
+            sy.lanczos_solve(sp, Y, lo, ws=ws, out=Xm)
         torch.cuda.synchronize()
-        times.append((time.perf_counter() - t0) * 1e3)
-    res = {"lanczos_sylvester": {"ms": round(statistics.median(times), 3), "iters": st["iters"],
-                                 "relres_est": st["relres_est"],
-                                 "relres_true": st["relres_true"],
-                                 "ok": st["status"] == 0,
-                                 "workspace_gb": round(ws.numel() / 1e9, 2)}}
-    log(f"sylv_1024 lanczos: {res['lanczos_sylvester']}")
-    del ws
+        times = []
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            _, st = sy.lanczos_solve(sp, Y, lo, ws=ws, out=Xm)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+        res[label] = {"ms": round(statistics.median(times), 3), "iters": st["iters"],
+                      "relres_est": st["relres_est"], "relres_true": st["relres_true"],
+                      "ok": st["status"] == 0, "assembly": st["assembly"],
+                      "workspace_gb": round(ws.numel() / 1e9, 3)}
+        if mode == sy.SYLV_LZ_RERUN:
+            res[label]["equal_to_kept_basis"] = bool(torch.equal(Xm, X))
+        log(f"sylv_1024 {label}: {res[label]}")
+        del ws
     dp = sy.DeviceProblem.from_numpy(prob)
     xs = {"lanczos_sylvester": X}
     for label, prec in (("pcg_f64", sy.SYLV_PREC_F64), ("pcg_mixed", sy.SYLV_PREC_MIXED)):

@@ -247,8 +247,9 @@ int sylv_pcg_backward(const sylv_problem *prob, const double *Y, const double *X
  * the symmetric block Lanczos process for N^-1 D2 in the N inner product (Alg. 4) from Yhat,
  * projects the equation on the block Krylov space (eq. (Sylv-small)) and stops on Alg. 5's
  * residual estimate sqrt(gamma) <= tol ||B_0||_F; the Galerkin approximation is then assembled
- * from the Lanczos blocks, which stay in the workspace (the paper's second Lanczos pass is not
- * needed).  All arithmetic is float64.
+ * either from the Lanczos blocks kept in the workspace (SYLV_LZ_KEEP_BASIS) or by the paper's
+ * second Lanczos pass, which regenerates the blocks from the kept coefficients (SYLV_LZ_RERUN,
+ * for grids and step counts whose basis would not fit).  All arithmetic is float64.
  */
 
 /* Host struct of device pointers. */
@@ -265,11 +266,19 @@ typedef struct sylv_sep_problem {
     int32_t reserved;      /* 0                                                                   */
 } sylv_sep_problem;
 
+#define SYLV_LZ_KEEP_BASIS 0  /* keep every Lanczos block; M = sum_i V_i G_i is one streaming
+                                 pass over them (workspace ~ max_iter * k * n_pix doubles)      */
+#define SYLV_LZ_RERUN      1  /* keep only the last two blocks; M is assembled by running the
+                                 Lanczos recurrence a second time from the kept small blocks
+                                 H_i, B_i (Alg. 5's second pass; workspace ~ 5 k n_pix doubles,
+                                 about twice the time)                                           */
+
 typedef struct sylv_lanczos_opts {
     double  tol;           /* stop when sqrt(gamma) <= tol * ||B_0||_F (Alg. 5)                  */
-    int32_t max_iter;      /* Lanczos steps at most; the workspace keeps max_iter basis blocks
-                              of k * n_pix doubles each                                          */
+    int32_t max_iter;      /* Lanczos steps at most                                              */
     int32_t check_every;   /* steps enqueued between host convergence checks (0 = 8)             */
+    int32_t assembly;      /* SYLV_LZ_KEEP_BASIS or SYLV_LZ_RERUN                                */
+    int32_t reserved;      /* 0                                                                   */
 } sylv_lanczos_opts;
 
 /* Result of a Lanczos-Sylvester solve (HOST struct, filled before the call returns). */

@@ -100,7 +100,8 @@ def boundary_code(b) -> int:
 
 class _LzOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
-                ("check_every", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("assembly", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class _LzStats(ctypes.Structure):
@@ -650,19 +651,34 @@ class SepProblem:
         return SepProblem(ny, nx, float(kappa), c(tau), c(A), c(t), c(n), boundary_code(boundary))
 
 
+SYLV_LZ_KEEP_BASIS = 0
+SYLV_LZ_RERUN = 1
+SYLV_LZ_AUTO = -1
+
+
 @dataclass
 class LanczosOptions:
+    """assembly: SYLV_LZ_KEEP_BASIS, SYLV_LZ_RERUN, or SYLV_LZ_AUTO (keep the basis when its
+    max_iter * k * n_pix doubles fit in basis_budget bytes, else the second Lanczos pass)."""
     tol: float = 1e-8
     max_iter: int = 500
     check_every: int = 0
+    assembly: int = SYLV_LZ_AUTO
+    basis_budget: int = 8 << 30
 
-    def c_struct(self) -> _LzOpts:
-        return _LzOpts(self.tol, self.max_iter, self.check_every)
+    def resolved(self, problem: "SepProblem") -> int:
+        if self.assembly != SYLV_LZ_AUTO:
+            return self.assembly
+        basis = 8 * self.max_iter * problem.k * problem.n_pix
+        return SYLV_LZ_KEEP_BASIS if basis <= self.basis_budget else SYLV_LZ_RERUN
+
+    def c_struct(self, problem: "SepProblem") -> _LzOpts:
+        return _LzOpts(self.tol, self.max_iter, self.check_every, self.resolved(problem), 0)
 
 
 def lanczos_workspace_bytes(problem: SepProblem, opts: Optional[LanczosOptions] = None) -> int:
     opts = opts or LanczosOptions()
-    ps, os_ = problem.c_struct(), opts.c_struct()
+    ps, os_ = problem.c_struct(), opts.c_struct(problem)
     n = lib().sylv_lanczos_workspace_bytes(ctypes.byref(ps), ctypes.byref(os_))
     if n == 0:
         _check(SYLV_E_INVALID)
@@ -682,11 +698,12 @@ def lanczos_solve(problem: SepProblem, Y, opts: Optional[LanczosOptions] = None,
     X = out if out is not None else torch.empty((problem.k, problem.n_pix), dtype=torch.float64,
                                                 device=Y.device)
     st = _LzStats()
-    ps, os_ = problem.c_struct(), opts.c_struct()
+    ps, os_ = problem.c_struct(), opts.c_struct(problem)
     _check(lib().sylv_lanczos_solve(ctypes.byref(ps), _ptr(Y), _ptr(X), ctypes.byref(os_),
                                     ctypes.byref(st), _ptr(ws), ws.numel(), _stream()))
     return X, {"status": st.status, "status_name": STATUS_NAMES.get(st.status, str(st.status)),
-               "iters": st.iters, "relres_est": st.relres_est, "relres_true": st.relres_true}
+               "iters": st.iters, "relres_est": st.relres_est, "relres_true": st.relres_true,
+               "assembly": "keep_basis" if os_.assembly == SYLV_LZ_KEEP_BASIS else "rerun"}
 
 
 def kohler_workspace_bytes(problem: SepProblem, decouple: bool = False,

@@ -716,6 +716,7 @@ bool check_lz_opts(const sylv_lanczos_opts *o) {
     if (!(o->tol > 0.0) || !(o->tol < 1.0)) { set_err("tol must be in (0, 1)"); return false; }
     if (o->max_iter < 1 || o->max_iter > 100000) { set_err("max_iter must be in [1, 100000]"); return false; }
     if (o->check_every < 0) { set_err("negative check_every"); return false; }
+    if (o->assembly != SYLV_LZ_KEEP_BASIS && o->assembly != SYLV_LZ_RERUN) { set_err("assembly must be SYLV_LZ_KEEP_BASIS or SYLV_LZ_RERUN"); return false; }
     return true;
 }
 
@@ -738,7 +739,7 @@ bool make_lz_layout(const sylv_sep_problem *p, const sylv_lanczos_opts *o, LzLay
     L.Yh = off;      off = align_up(off + vb);
     L.Wa0 = off;     off = align_up(off + vb);
     L.Wa1 = off;     off = align_up(off + vb);
-    L.basis = off;   off = align_up(off + vb * mi);
+    L.basis = off;   off = align_up(off + vb * (o->assembly == SYLV_LZ_RERUN ? 2 : mi));
     L.total = off;
     return true;
 }
@@ -988,6 +989,7 @@ int lanczos_impl(const sylv_sep_problem *p, const double *Y, double *X,
     a.basis = reinterpret_cast<double *>(base + L.basis);
     a.X = X;
     a.G = reinterpret_cast<const double *>(base + L.G);
+    a.ring = o->assembly == SYLV_LZ_RERUN ? 1 : 0;
 
     HIP_TRY(hipMemcpyAsync(base + L.cst, &C, sizeof(C), hipMemcpyHostToDevice, s));
     HIP_TRY(lz_launch_init(a, o->max_iter, s));
@@ -1032,7 +1034,14 @@ int lanczos_impl(const sylv_sep_problem *p, const double *Y, double *X,
             HIP_TRY(hipMemcpyAsync(base + L.G, Gh.data(), sizeof(double) * Gh.size(), hipMemcpyHostToDevice, s));
         }
     }
-    HIP_TRY(lz_launch_finish(a, iters, s));
+    if (a.ring && iters > 0) {
+        // Alg. 5's second pass: the recurrence again from Yhat with the kept H, B blocks, adding
+        // V_i G_(i-1) into X step by step; then the residual pass
+        for (int i = 1; i <= iters; ++i) HIP_TRY(lz_launch_replay(a, i, s));
+        HIP_TRY(lz_launch_resid(a, s));
+    } else {
+        HIP_TRY(lz_launch_finish(a, iters, s));
+    }
     HIP_TRY(hipMemcpyAsync(&st, base + L.state, sizeof(LzState), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (stats) {

@@ -259,6 +259,8 @@ struct LzArgs {
     const double *n, *Y;
     double *Yh, *Wa0, *Wa1, *basis, *X;
     const double *G;              // [iters] blocks of the solution coefficients Z
+    int ring;                     // 0: basis block i in slot i (all kept); 1: two slots, i & 1
+                                  // (the solution is assembled by a second Lanczos pass)
 };
 // P = V^T N Wa (k^2), C = V^T N V and E = Wa^T N Wa (k(k+1)/2 each), plus one count
 constexpr int kLzSlots = kMaxK * kMaxK + kMaxK * (kMaxK + 1) + 1;
@@ -267,6 +269,9 @@ hipError_t lz_launch_start(const LzArgs &a, hipStream_t s);
 hipError_t lz_launch_step(const LzArgs &a, int it, hipStream_t s);
 hipError_t lz_launch_flag(const LzArgs &a, int *host_running, hipStream_t s);
 hipError_t lz_launch_finish(const LzArgs &a, int iters, hipStream_t s);
+// Step `it` of the second Lanczos pass (a.ring = 1): regenerate V_it from the kept H, B blocks
+// and add V_it G_(it-1) into a.X.
+hipError_t lz_launch_replay(const LzArgs &a, int it, hipStream_t s);
 // Residual pass of eq. (Axb) for a.X (stencil pass, reduction, ||r||^2 and ||b||^2 into a.st);
 // needs the start block a.Yh (lz_launch_start).
 hipError_t lz_launch_resid(const LzArgs &a, hipStream_t s);

@@ -37,6 +37,11 @@ __device__ __forceinline__ const double *cblk(const double *base, int i) {
     return base + (size_t)i * kLzStride;
 }
 __device__ __forceinline__ double *wblk(double *base, int i) { return base + (size_t)i * kLzStride; }
+// Workspace slot of basis block i (0-based): one slot per step when the blocks are kept, two
+// alternating slots when the solution is assembled by a second Lanczos pass.
+__device__ __forceinline__ size_t lz_slot(const LzArgs &a, int i) {
+    return a.ring ? (size_t)(i & 1) : (size_t)i;
+}
 
 template <int K>
 constexpr int lz_nv_step() { return K * K + K * (K + 1); }   // P, C, E
@@ -211,14 +216,17 @@ __global__ __launch_bounds__(kBlock) void k_lz_start(LzArgs a) {
 // Stencil kernels.  STEP: one Lanczos step (see the file comment).  RESID: residual of eq. (Axb)
 // for X: r_j = n_p tau_j Yhat_j - (tau_j D2 X_j + n_p (A^T T A X_p)_j), with the partials of
 // ||r||^2 and ||b||^2.
+// replay = 1 (STEP only): step `it` of the second Lanczos pass of Alg. 5, which regenerates V_i
+// from the kept H and B blocks (the same instructions as the first pass, so V_i is bitwise the
+// same) and adds V_i G_(i-1) into X instead of forming Gram partials.
 template <int K, int MODE, int R, int BC>
-__global__ __launch_bounds__(kBlock) void k_lz_stencil(LzArgs a, int it) {
+__global__ __launch_bounds__(kBlock) void k_lz_stencil(LzArgs a, int it, int replay) {
     constexpr int LH = kWavesY * R + 4;   // staged rows: tile + 2-row halo above and below
     constexpr int LW = kTileX + 4;        // staged columns
     constexpr int RPW = LH / kWavesY;     // staged rows per wavefront
     constexpr bool STEP = MODE == LZ_STEP;
     const LzState *st = a.st;
-    if (STEP && st->done) return;
+    if (STEP && !replay && st->done) return;
     const bool prev = STEP && it > 1;     // a previous block exists
     const int tile = xcd_remap(blockIdx.x, a.ntiles);
     const int nx = a.nx, ny = a.ny, n_pix = a.n_pix;
@@ -235,7 +243,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_stencil(LzArgs a, int it) {
     const double *src0;                     // STEP: Wa_(i-1) (Yhat at i = 1); RESID: X
     if constexpr (STEP) src0 = (it == 1) ? a.Yh : ((it & 1) ? a.Wa1 : a.Wa0);
     else src0 = a.X;
-    const GAS double *vprev = gp(a.basis) + (size_t)(prev ? it - 2 : 0) * K * n_pix;
+    const GAS double *vprev = gp(a.basis) + (prev ? lz_slot(a, it - 2) : 0) * K * n_pix;
     const int cmain = wrapf(x0 + tx, nx);
     const int hitem = ty * 64 + tx;
     const int hr = hitem >> 2, hc = hitem & 3;
@@ -387,7 +395,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_stencil(LzArgs a, int it) {
             if (iy0 + t >= ny) continue;
             const int pix = (iy0 + t) * nx + ix;
             if constexpr (STEP) {
-                GAS double *vb = gp(a.basis) + (size_t)(it - 1) * K * n_pix;
+                GAS double *vb = gp(a.basis) + lz_slot(a, it - 1) * K * n_pix;
                 GAS double *wa = gp((it & 1) ? a.Wa0 : a.Wa1);
                 const double ninv = 1.0 / nv[t];
 #pragma unroll
@@ -403,6 +411,17 @@ __global__ __launch_bounds__(kBlock) void k_lz_stencil(LzArgs a, int it) {
                     wo[t][j] = w;
                 }
                 wt[t] = nv[t];
+                if (replay) {   // M += V_i G_(i-1) (M = V_1 G_0 at the first step)
+                    const double *Gs = cblk(a.G, it - 1);
+                    GAS double *xo = gp(a.X);
+#pragma unroll
+                    for (int j = 0; j < K; ++j) {
+                        double m = (it > 1) ? bld(xo + (size_t)j * n_pix, np, (uint32_t)pix) : 0.0;
+#pragma unroll
+                        for (int q = 0; q < K; ++q) m += ctr[q][t] * Gs[q * kMaxK + j];
+                        bst(xo + (size_t)j * n_pix, np, (uint32_t)pix, m);
+                    }
+                }
             } else {
 #pragma unroll
                 for (int j = 0; j < K; ++j) {
@@ -419,6 +438,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_stencil(LzArgs a, int it) {
         }
     }
     if constexpr (STEP) {
+        if (replay) return;
         constexpr int NV = lz_nv_step<K>();
         double vals[NV];
         int e = 0;
@@ -800,24 +820,37 @@ hipError_t lz_launch_start(const LzArgs &a, hipStream_t s) {
     });
 }
 
-hipError_t lz_launch_step(const LzArgs &a, int it, hipStream_t s) {
+// The step kernel of the first (replay = 0) or second (replay = 1) Lanczos pass.
+static hipError_t launch_step_kernel(const LzArgs &a, int it, int replay, hipStream_t s) {
     return dispatch_k(a.k, [&](auto kt) -> hipError_t {
         constexpr int K = decltype(kt)::value;
         if (a.bc == SYLV_BC_FACE)
             hipLaunchKernelGGL((k_lz_stencil<K, LZ_STEP, 2, BC_FACE>), dim3(a.ntiles),
-                               dim3(kBlock), 0, s, a, it);
+                               dim3(kBlock), 0, s, a, it, replay);
         else if (K <= 4 && a.rows == 4)
             hipLaunchKernelGGL((k_lz_stencil<K, LZ_STEP, (K <= 4 ? 4 : 2), BC_PERIODIC>),
-                               dim3(a.ntiles), dim3(kBlock), 0, s, a, it);
+                               dim3(a.ntiles), dim3(kBlock), 0, s, a, it, replay);
         else
             hipLaunchKernelGGL((k_lz_stencil<K, LZ_STEP, 2, BC_PERIODIC>), dim3(a.ntiles),
-                               dim3(kBlock), 0, s, a, it);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        if ((e = launch_reduce(a, lz_nv_step<K>(), a.ntiles, s)) != hipSuccess) return e;
+                               dim3(kBlock), 0, s, a, it, replay);
+        return hipGetLastError();
+    });
+}
+
+hipError_t lz_launch_step(const LzArgs &a, int it, hipStream_t s) {
+    hipError_t e = launch_step_kernel(a, it, 0, s);
+    if (e != hipSuccess) return e;
+    return dispatch_k(a.k, [&](auto kt) -> hipError_t {
+        constexpr int K = decltype(kt)::value;
+        hipError_t e2 = launch_reduce(a, lz_nv_step<K>(), a.ntiles, s);
+        if (e2 != hipSuccess) return e2;
         hipLaunchKernelGGL((k_lz_fin<K>), dim3(1), dim3(kBlock), 0, s, a, it);
         return hipGetLastError();
     });
+}
+
+hipError_t lz_launch_replay(const LzArgs &a, int it, hipStream_t s) {
+    return launch_step_kernel(a, it, 1, s);
 }
 
 hipError_t lz_launch_flag(const LzArgs &a, int *host_running, hipStream_t s) {
@@ -841,13 +874,13 @@ hipError_t lz_launch_resid(const LzArgs &a, hipStream_t s) {
         hipError_t e;
         if (a.bc == SYLV_BC_FACE)
             hipLaunchKernelGGL((k_lz_stencil<K, LZ_RESID, 2, BC_FACE>), dim3(a.ntiles),
-                               dim3(kBlock), 0, s, a, 0);
+                               dim3(kBlock), 0, s, a, 0, 0);
         else if (K <= 4 && a.rows == 4)
             hipLaunchKernelGGL((k_lz_stencil<K, LZ_RESID, (K <= 4 ? 4 : 2), BC_PERIODIC>),
-                               dim3(a.ntiles), dim3(kBlock), 0, s, a, 0);
+                               dim3(a.ntiles), dim3(kBlock), 0, s, a, 0, 0);
         else
             hipLaunchKernelGGL((k_lz_stencil<K, LZ_RESID, 2, BC_PERIODIC>), dim3(a.ntiles),
-                               dim3(kBlock), 0, s, a, 0);
+                               dim3(kBlock), 0, s, a, 0, 0);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = launch_reduce(a, 2, a.ntiles, s)) != hipSuccess) return e;
         hipLaunchKernelGGL(k_lz_rfin, dim3(1), dim3(64), 0, s, a);

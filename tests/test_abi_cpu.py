@@ -163,7 +163,7 @@ def fake_sep(ny=32, nx=32, k=4, f=9, kappa=0.5, boundary=0):
 def test_lanczos_struct_sizes():
     # int64 x2 + int32 x2 + double + 4 pointers + int32 x2; double + int32 x2; int32 x2 + double x2
     assert ctypes.sizeof(bd._SepProblem) == 72
-    assert ctypes.sizeof(bd._LzOpts) == 16
+    assert ctypes.sizeof(bd._LzOpts) == 24
     assert ctypes.sizeof(bd._LzStats) == 24
 
 
@@ -176,6 +176,24 @@ def test_lanczos_workspace_holds_the_basis():
     blk = 64 * 64 * 4 * 8
     assert n1 >= 100 * blk + 3 * blk            # the basis plus Yhat and two running blocks
     assert n2 - n1 >= 100 * blk                 # one more block per extra step
+    # the second-pass assembly keeps two blocks whatever the step count
+    r1 = L.sylv_lanczos_workspace_bytes(ctypes.byref(fake_sep(64, 64)),
+                                        ctypes.byref(bd._LzOpts(1e-8, 100, 0, bd.SYLV_LZ_RERUN)))
+    r2 = L.sylv_lanczos_workspace_bytes(ctypes.byref(fake_sep(64, 64)),
+                                        ctypes.byref(bd._LzOpts(1e-8, 200, 0, bd.SYLV_LZ_RERUN)))
+    assert 5 * blk <= r1 < 6 * blk + (1 << 20)
+    assert r2 - r1 <= 100 * 5 * 64 * 8     # only the small k x k blocks grow with the steps
+
+
+def test_lanczos_auto_assembly_follows_the_budget():
+    """Python side: SYLV_LZ_AUTO keeps the basis when it fits the budget, else reruns."""
+    o = sy.LanczosOptions(max_iter=800, basis_budget=1 << 30)
+
+    class P:
+        k, n_pix = 4, 1024 * 1024
+    assert o.resolved(P) == bd.SYLV_LZ_RERUN        # 800 * 4 * 2^20 * 8 B = 26.8 GB
+    P.n_pix = 64 * 64
+    assert o.resolved(P) == bd.SYLV_LZ_KEEP_BASIS
 
 
 @pytest.mark.parametrize("bad", [dict(k=0), dict(k=9), dict(f=0), dict(f=17), dict(ny=0),
@@ -199,7 +217,8 @@ def test_lanczos_bad_options_rejected():
     p = fake_sep()
     st = bd._LzStats()
     for o in [bd._LzOpts(0.0, 10, 0), bd._LzOpts(1.0, 10, 0), bd._LzOpts(1e-8, 0, 0),
-              bd._LzOpts(1e-8, 10, -1), bd._LzOpts(1e-8, 200000, 0)]:
+              bd._LzOpts(1e-8, 10, -1), bd._LzOpts(1e-8, 200000, 0),
+              bd._LzOpts(1e-8, 10, 0, 2), bd._LzOpts(1e-8, 10, 0, -1)]:
         assert L.sylv_lanczos_workspace_bytes(ctypes.byref(p), ctypes.byref(o)) == 0
         rc = L.sylv_lanczos_solve(ctypes.byref(p), FAKE, FAKE, ctypes.byref(o),
                                   ctypes.byref(st), FAKE, 1 << 30, None)

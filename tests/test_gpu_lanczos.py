@@ -32,11 +32,13 @@ def sep(ny, nx, k, f, seed, kappa=0.45):
     return p, p.meta["t"], p.meta["n"]
 
 
-def run(p, t, n, tol, max_iter=400, check_every=0, Y=None):
-    sp = sy.SepProblem.from_numpy(p.ny, p.nx, p.kappa[0], p.tau, p.A, t, n)
+def run(p, t, n, tol, max_iter=400, check_every=0, Y=None, assembly=sy.SYLV_LZ_AUTO):
+    sp = sy.SepProblem.from_numpy(p.ny, p.nx, p.kappa[0], p.tau, p.A, t, n,
+                                  boundary=p.boundary)
     Yd = torch.as_tensor(p.Y if Y is None else Y, dtype=torch.float64, device="cuda")
     X, st = sy.lanczos_solve(sp, Yd, sy.LanczosOptions(tol=tol, max_iter=max_iter,
-                                                        check_every=check_every))
+                                                        check_every=check_every,
+                                                        assembly=assembly))
     return X.cpu().numpy(), st
 
 
@@ -85,6 +87,45 @@ def test_every_step_matches_oracle(shape):
         assert st["status"] == sy.binding.SYLV_NOT_CONVERGED and st["iters"] == j, st
         assert rel(X, ref["x"]) < 1e-10, j
         assert st["relres_est"] == pytest.approx(ref["history"][-1], rel=1e-7), j
+
+
+@pytest.mark.parametrize("shape", [(12, 10, 3, 5), (70, 45, 4, 9), (16, 16, 8, 16),
+                                   (33, 130, 1, 2)])
+def test_second_pass_assembly_every_step(shape):
+    """Alg. 5's second Lanczos pass (two kept blocks, M accumulated while the recurrence is run
+    again from the kept H and B): after j steps it holds the oracle's j-th approximation, as the
+    kept-basis assembly does."""
+    ny, nx, k, f = shape
+    p, t, n = sep(ny, nx, k, f, 3150 + ny)
+    say("second pass, steps", shape)
+    for j in (1, 2, 3, 5, 8):
+        ref = olz.lanczos_sylvester(p, t, n, tol=1e-300, max_iter=j)
+        X, st = run(p, t, n, 1e-15, max_iter=j, check_every=3, assembly=sy.SYLV_LZ_RERUN)
+        assert st["assembly"] == "rerun"
+        assert st["status"] == sy.binding.SYLV_NOT_CONVERGED and st["iters"] == j, st
+        assert rel(X, ref["x"]) < 1e-10, j
+
+
+@pytest.mark.parametrize("boundary", ["periodic", "face"])
+@pytest.mark.parametrize("shape", [(8, 8, 3, 5), (70, 45, 4, 9), (24, 20, 6, 9), (9, 11, 7, 8)])
+def test_second_pass_equals_kept_basis(shape, boundary):
+    """Converged solves: the second-pass assembly regenerates every block bitwise (same kernel
+    instructions, same kept coefficients), so its result equals the kept-basis one to rounding
+    of the sums, with the same step count and residuals."""
+    ny, nx, k, f = shape
+    p = make_problem(ny, nx, k, f, seed=3160 + ny, noise="separable", kappa=np.full(k, 0.45),
+                     boundary=boundary)
+    t, n = p.meta["t"], p.meta["n"]
+    say("second pass vs kept basis", shape, boundary)
+    Xk, sk = run(p, t, n, 1e-10, assembly=sy.SYLV_LZ_KEEP_BASIS)
+    Xr, sr = run(p, t, n, 1e-10, assembly=sy.SYLV_LZ_RERUN)
+    assert sk["status"] == 0 and sr["status"] == 0
+    assert sk["iters"] == sr["iters"] and sk["relres_est"] == sr["relres_est"]
+    assert rel(Xr, Xk) <= 1e-13
+    say("  bitwise equal" if np.array_equal(Xr, Xk) else f"  rel diff {rel(Xr, Xk):.1e}")
+    assert sr["relres_true"] == pytest.approx(sk["relres_true"], rel=1e-6, abs=1e-15)
+    if p.n_pix * k <= 4000:
+        assert rel(Xr, osv.solve_dense(p)) < 1e-7
 
 
 def test_repeatable_bitwise():
@@ -142,10 +183,15 @@ def test_full_size_1024_matches_cg_and_sampled_residual():
     counts): the Lanczos-Sylvester solution equals the float64 PCG solution of the same system,
     and the residual at sampled pixels, computed by the oracle's operator, is small."""
     p, t, n = sep(1024, 1024, 4, 9, 3400, kappa=0.3)
-    say("full size 1024^2")
-    X, st = run(p, t, n, 1e-10, max_iter=600)
+    say("full size 1024^2, kept basis")
+    X, st = run(p, t, n, 1e-10, max_iter=600, assembly=sy.SYLV_LZ_KEEP_BASIS)
     assert st["status"] == 0, st
     assert st["relres_true"] < 1e-8, st
+    say("full size 1024^2, second pass")
+    Xr, sr = run(p, t, n, 1e-10, max_iter=600, assembly=sy.SYLV_LZ_RERUN)
+    assert sr["status"] == 0 and sr["iters"] == st["iters"], sr
+    assert rel(Xr, X) <= 1e-12
+    assert sr["relres_true"] < 1e-8, sr
     dp = sy.DeviceProblem.from_numpy(p)
     Xc, sc = sy.pcg_solve(dp, Y=torch.as_tensor(p.Y, device="cuda"),
                           opts=sy.SolveOptions(tol=1e-11, precision=sy.SYLV_PREC_F64))
