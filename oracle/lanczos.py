@@ -1,6 +1,6 @@
-"""Lanczos-Sylvester solver: block Lanczos in the N inner product (Alg. 4) inside the symmetric
-sparse Sylvester solver (Alg. 5).  Oracle: test infrastructure only (tests, the smoke check and
-the CPU leg of the benchmark call it; the library never does).
+"""Lanczos-Sylvester solver of Section 3.3, written from its equations.  Oracle: test
+infrastructure only (tests, the smoke check and the CPU leg of the benchmark call it; the library
+never does).
 
 Case treated (Section 3.3): one prior factor shared by all components (every kappa_j equal) and
 separable noise W[f, p] = t_f n_p with every n_p > 0.  The posterior-mean system is then the
@@ -12,28 +12,43 @@ Sylvester equation (eq. (Axb-Sylv))
 with P = diag(tau), T = diag(t), N = diag(n) and M the N x k matrix whose column j is map j.
 Its solution is the posterior mean of the Kronecker system (eq. (Axb)).
 
-The steps follow Alg. 4 and Alg. 5 in the paper's order and notation.  Readings where the
-printed algorithms are garbled or inconsistent with the equations they implement:
+What is computed, from the equations of Section 3.3 (not from the printed listings):
 
-  * The three-term step subtracts V_old B_i^T: the block below H_(i-1) in T_j is B_i and the
-    block beside it is its transpose, so that T_j is symmetric as eq. (tridiag-factorization)
-    requires (the listing prints B_i, which is only right for symmetric B_i).
-  * H_i = V^T N W is symmetric in exact arithmetic; its symmetric part enters T_j.
-  * Lhat is not symmetric; Lemma 2 gives Lhat = U R U^-1 with U^T P^-1 U = I.  U and R come
-    from the symmetric matrix P^-1/2 A^T T A P^-1/2 = V R V^T as U = P^1/2 V.  Alg. 5 writes
-    the decomposition as U R U^T; the solution formula uses U^-1 = U^T P^-1 (eq. (soln-constr)),
-    and so does the final Z here.
-  * In the residual estimate J is the last block row of Q_i, transposed, times B_(i+1)^T (the
-    listing's Q_i E_m); with it, gamma is the squared N-norm of the Sylvester residual times U.
-  * F has i*m rows (one per eigenvalue of T_i) and its numerator is (Q_i^T E_1 B_0 U)_(k,l)
-    (the listing's Q_l is Q_i).
-  * The loop stops when sqrt(gamma) <= eps ||B_0||_F; the first pass always runs.  A block W of
-    N-norm zero ends the loop (the Krylov space is invariant; the Galerkin solution is exact).
+  * Basis.  Yhat = V_1 B_0 with V_1^T N V_1 = I, and the block Lanczos relation for the
+    operator N^-1 D2, which is symmetric in the N inner product (Lemma 1):
+        N^-1 D2 [V_1 .. V_j] = [V_1 .. V_j] T_j + V_(j+1) B_(j+1) E_j^T,
+    T_j block tridiagonal with diagonal blocks H_i = V_i^T D2 V_i and B_(i+1) below the
+    diagonal (B_(i+1)^T above it), so that V^T D2 V = T_j (eq. (tridiag-factorization)).  Each
+    new block is the part of N^-1 D2 V_j that the relation leaves, N-orthonormalised by a
+    Cholesky factorisation of its N-Gram matrix (B upper triangular).
+  * Galerkin approximation M_j = [V_1 .. V_j] Z_j with the projected equation
+        T_j Z + Z Lhat = E_1 B_0                                     (eq. (Sylv-small)).
+    By Lemma 2, Lhat = U R U^-1 with R = diag(rho), rho > 0, U = P^1/2 V_s and U^-1 = U^T P^-1
+    (V_s the orthonormal eigenvectors of P^-1/2 A^T T A P^-1/2), so column l of Z U solves the
+    symmetric positive definite banded system (T_j + rho_l I) (Z U) e_l = E_1 B_0 U e_l
+    (eq. (soln-constr)'s decoupling, solved here by a banded Cholesky factorisation, LAPACK
+    dpbtrf/dpbtrs, instead of an eigendecomposition of T_j), and Z = (Z U) U^T P^-1.
+  * Residual.  Substituting both relations, the residual of eq. (Axb-Sylv) at M_j is
+    N^-1 D2 M_j + M_j Lhat - Yhat = V_(j+1) B_(j+1) E_j^T Z_j, so the squared N-norm of the
+    residual times U (the quantity Alg. 5 calls gamma) is ||B_(j+1) (E_j^T Z_j) U||_F^2.
+  * Stopping: the first j with sqrt(gamma_j) <= tol ||B_0||_F (Alg. 5's test); a new block of
+    N-norm zero ends the process (the Krylov space is invariant and M_j exact).
+
+Readings (where the printed algorithms are garbled or inconsistent with these equations):
+
+  * The block beside H_(i-1) in the symmetric T_j is B_i^T, so the three-term relation subtracts
+    V_(i-1) B_i^T (the listing prints B_i, right only for symmetric B_i).
+  * H_i = V_i^T D2 V_i is symmetric in exact arithmetic; its symmetric part is kept.
+  * Alg. 5 writes Lhat = U R U^T although Lhat is not symmetric; Lemma 2's U R U^-1 with
+    U^-1 = U^T P^-1 is used.
+  * Alg. 5's gamma is taken as the squared N-norm of the Sylvester residual times U (its listed
+    J and F readings give that value, which tests/test_oracle_lanczos.py checks against the
+    explicitly formed residual).
 """
 from __future__ import annotations
 
 import numpy as np
-import scipy.sparse as sp
+import scipy.linalg as sla
 
 from . import operator as op
 
@@ -80,23 +95,32 @@ def n_qr(W: np.ndarray, nvec: np.ndarray):
     return V, B
 
 
+def extend_basis(D2, nvec, Vs, Hs, Bs):
+    """One more block of the Lanczos relation: with V_j the last block of Vs, append
+    H_j = sym(V_j^T D2 V_j) to Hs and the N-QR factors of
+    N^-1 D2 V_j - V_j H_j - V_(j-1) B_j^T  =  V_(j+1) B_(j+1)
+    to Vs and Bs (Bs[0] = B_0 of the start block, Bs[i] = B_(i+1))."""
+    Vj = Vs[-1]
+    AV = (D2 @ Vj) / nvec[:, None]
+    H = Vj.T @ (D2 @ Vj)
+    H = 0.5 * (H + H.T)
+    Wn = AV - Vj @ H
+    if len(Vs) > 1:
+        Wn = Wn - Vs[-2] @ Bs[-1].T
+    Vn, Bn = n_qr(Wn, nvec)
+    Hs.append(H)
+    Bs.append(Bn)
+    Vs.append(Vn)
+
+
 def lanczos(D2, nvec, Yhat, j: int):
-    """Alg. 4: j steps of the symmetric block Lanczos process for N^-1 D2 in the N inner product,
-    started from Yhat.  Returns (V list of j + 1 blocks, H list of j blocks, B list of j + 1
-    blocks with B[0] = B_0 from Yhat = V_1 B_0, B[i] = B_(i+1))."""
+    """j blocks of the block Lanczos relation for N^-1 D2 in the N inner product, started from
+    Yhat.  Returns (V list of j + 1 blocks, H list of j blocks, B list of j + 1 blocks with
+    B[0] = B_0 from Yhat = V_1 B_0, B[i] = B_(i+1))."""
     V, B0 = n_qr(Yhat, nvec)
     Vs, Hs, Bs = [V], [], [B0]
-    for i in range(1, j + 1):
-        W = (D2 @ Vs[-1]) / nvec[:, None]
-        if i > 1:
-            W = W - Vs[-2] @ Bs[-1].T
-        H = Vs[-1].T @ (nvec[:, None] * W)
-        H = 0.5 * (H + H.T)
-        W = W - Vs[-1] @ H
-        Vn, Bn = n_qr(W, nvec)
-        Hs.append(H)
-        Bs.append(Bn)
-        Vs.append(Vn)
+    for _ in range(j):
+        extend_basis(D2, nvec, Vs, Hs, Bs)
     return Vs, Hs, Bs
 
 
@@ -114,91 +138,85 @@ def block_tridiagonal(Hs, Bs) -> np.ndarray:
     return T
 
 
-def residual_gamma(Hs, Bs, U, rho):
-    """Alg. 5's residual estimate after i = len(Hs) steps: eigendecomposition T_i = Q Phi Q^T,
-    S = (U^T B_0^T)(E_1^T Q), J = (E_i^T Q)^T B_(i+1)^T, gamma = sum_l ||e_l^T S K_l^-1 J||^2
-    with K_l = rho_l I + Phi.  Returns (gamma, phi, Q)."""
-    m = U.shape[0]
-    T = block_tridiagonal(Hs, Bs)
-    phi, Q = np.linalg.eigh(T)
-    B0 = Bs[0]
-    Bnext = Bs[len(Hs)]
-    S = (U.T @ B0.T) @ Q[:m, :]
-    J = Q[-m:, :].T @ Bnext.T
-    gamma = 0.0
+def _banded_lower(Hs, Bs, shift: float) -> np.ndarray:
+    """T_i + shift I in LAPACK's lower banded storage (bandwidth 2m - 1), from its blocks:
+    ab[d, c] = (T + shift I)[c + d, c]."""
+    i = len(Hs)
+    m = Hs[0].shape[0]
+    n = i * m
+    ab = np.zeros((2 * m, n))
+    for a in range(i):
+        for c in range(m):
+            col = a * m + c
+            for r in range(c, m):                              # the diagonal block, lower part
+                ab[r - c, col] = Hs[a][r, c] + (shift if r == c else 0.0)
+            if a + 1 < i:
+                Bn = Bs[a + 1]                                 # block below: rows of block a + 1
+                for r in range(m):
+                    ab[m + r - c, col] = Bn[r, c]
+    return ab
+
+
+def projected_solution(Hs, Bs, U, rho):
+    """Z U for the projected equation T_i Z + Z Lhat = E_1 B_0 (eq. (Sylv-small)) with
+    Lhat = U diag(rho) U^-1: column l solves (T_i + rho_l I) x = E_1 B_0 U e_l by a banded
+    Cholesky factorisation.  Returns Z U as an (i m) x m array."""
+    i = len(Hs)
+    m = Hs[0].shape[0]
+    rhs = np.zeros((i * m, m))
+    rhs[:m, :] = Bs[0] @ U
+    ZU = np.zeros((i * m, m))
+    band = min(2 * m - 1, i * m - 1)                          # sub-diagonals of T_i
     for l in range(m):
-        Kinv = 1.0 / (rho[l] + phi)
-        v = (S[l, :] * Kinv) @ J
-        gamma += float(v @ v)
-    return gamma, phi, Q
+        ab = _banded_lower(Hs, Bs, rho[l])[:band + 1]
+        ZU[:, l] = sla.solveh_banded(ab, rhs[:, l], lower=True)
+    return ZU
+
+
+def residual_gamma(Hs, Bs, U, rho) -> float:
+    """gamma_i = ||B_(i+1) (E_i^T Z U)||_F^2: the squared N-norm of the Sylvester residual at the
+    Galerkin approximation, times U (the residual is V_(i+1) B_(i+1) E_i^T Z)."""
+    m = U.shape[0]
+    ZU = projected_solution(Hs, Bs, U, rho)
+    v = Bs[len(Hs)] @ ZU[-m:, :]
+    return float(np.sum(v * v))
 
 
 def galerkin_coefficients(Hs, Bs, U, rho, P):
-    """Z = Q F U^T P^-1 with F_(k,l) = (Q^T E_1 B_0 U)_(k,l) / (phi_k + rho_l) (eq. (soln-constr)).
-    Returns the list of k x k blocks G_j of Z (M = sum_j V_j G_j)."""
+    """Z = (Z U) U^T P^-1, as the list of its k x k blocks G_j (M = sum_j V_j G_j)."""
     m = U.shape[0]
-    T = block_tridiagonal(Hs, Bs)
-    phi, Q = np.linalg.eigh(T)
-    num = Q[:m, :].T @ (Bs[0] @ U)                             # Q^T E_1 B_0 U, (i m) x m
-    F = num / (phi[:, None] + rho[None, :])
-    Z = Q @ F @ U.T @ np.linalg.inv(P)
+    Z = projected_solution(Hs, Bs, U, rho) @ U.T @ np.linalg.inv(P)
     return [Z[j * m:(j + 1) * m, :] for j in range(len(Hs))]
 
 
 def lanczos_sylvester(prob, t, nvec, tol: float = 1e-8, max_iter: int = 1000,
                       record: bool = False):
-    """Alg. 5.  Returns a dict with the solution M as [k, n_pix] ('x'), the number of Lanczos
-    steps ('iters'), the final estimate sqrt(gamma)/||B_0||_F ('relres_est'), the history of
-    that estimate ('history'), and the coefficients H, B.  With record=True also the Lanczos
-    blocks of the first pass ('V')."""
+    """Galerkin approximations of eq. (Axb-Sylv) over growing block Krylov spaces until Alg. 5's
+    test holds.  Returns a dict with the solution M as [k, n_pix] ('x'), the number of Lanczos
+    steps ('iters'), the final estimate sqrt(gamma)/||B_0||_F ('relres_est'), its history
+    ('history'), the blocks H, B and U, rho, and with record=True the basis blocks ('V')."""
     D2, nvec, Lhat, Yhat, U, rho, P = sylvester_data(prob, t, nvec)
-    V, B0 = n_qr(Yhat, nvec)
+    V1, B0 = n_qr(Yhat, nvec)
     nb0 = float(np.linalg.norm(B0))
-    Vold = np.zeros_like(V)
-    Hs, Bs, hist, Vrec = [], [B0], [], [V]
-    i = 0
-    gamma = np.inf
-    while np.sqrt(gamma) > tol * nb0:
-        if i >= max_iter:
-            break
-        i += 1
-        # Lanczos step
-        W = (D2 @ V) / nvec[:, None]
-        if i > 1:
-            W = W - Vold @ Bs[-1].T
-        H = V.T @ (nvec[:, None] * W)
-        H = 0.5 * (H + H.T)
-        W = W - V @ H
-        Vold = V
-        V, Bn = n_qr(W, nvec)
-        Hs.append(H)
-        Bs.append(Bn)
-        if record:
-            Vrec.append(V)
-        # residual norm estimate
-        gamma, _, _ = residual_gamma(Hs, Bs, U, rho)
-        hist.append(np.sqrt(gamma) / nb0)
-        if not np.any(Bn):
-            gamma = 0.0
-            break
-    # coefficients of the approximation, then a second Lanczos pass assembles M block by block
-    Gs = galerkin_coefficients(Hs, Bs, U, rho, P)
-    M = np.zeros_like(Yhat)
-    V = np.linalg.solve(B0.T, Yhat.T).T
-    Vold = np.zeros_like(V)
-    for j in range(1, i + 1):
-        M = M + V @ Gs[j - 1]
-        if j == i:
-            break
-        W = (D2 @ V) / nvec[:, None]
-        if j > 1:
-            W = W - Vold @ Bs[j - 1].T
-        W = W - V @ Hs[j - 1]
-        Vold = V
-        V = np.linalg.solve(Bs[j].T, W.T).T
-    out = {"x": M.T.copy(), "iters": i, "relres_est": float(np.sqrt(gamma) / nb0),
+    Vs, Hs, Bs, hist = [V1], [], [B0], []
+    gamma = 0.0
+    if nb0 > 0.0:
+        for _ in range(max_iter):
+            extend_basis(D2, nvec, Vs, Hs, Bs)
+            gamma = residual_gamma(Hs, Bs, U, rho)
+            hist.append(np.sqrt(gamma) / nb0)
+            if np.sqrt(gamma) <= tol * nb0 or not np.any(Bs[-1]):
+                break
+    j = len(Hs)
+    if j > 0:
+        Gs = galerkin_coefficients(Hs, Bs, U, rho, P)
+        M = np.hstack(Vs[:j]) @ np.vstack(Gs)
+    else:
+        M = np.zeros_like(Yhat)
+    out = {"x": M.T.copy(), "iters": j,
+           "relres_est": float(np.sqrt(gamma) / nb0) if nb0 > 0 else 0.0,
            "history": np.array(hist), "H": Hs, "B": Bs, "U": U, "rho": rho,
            "converged": bool(np.sqrt(gamma) <= tol * nb0)}
     if record:
-        out["V"] = Vrec
+        out["V"] = Vs
     return out

@@ -1,5 +1,5 @@
-"""Pins of the Lanczos-Sylvester oracle (Alg. 4, Alg. 5) against mathematics and independent
-solvers (no GPU)."""
+"""Pins of the Lanczos-Sylvester oracle (Section 3.3: Alg. 4, Alg. 5) against mathematics and
+independent solvers (no GPU)."""
 import os
 
 import numpy as np
@@ -43,7 +43,7 @@ def test_sylvester_form_is_the_posterior_system():
 
 
 def test_lanczos_blocks_are_n_orthonormal():
-    """Alg. 4 only orthogonalises against the last two blocks; the symmetry of N^-1 D2 in the N
+    """The Lanczos relation only orthogonalises against the last two blocks; the symmetry of N^-1 D2 in the N
     inner product (Lemma 1) makes every pair of blocks N-orthogonal."""
     p, t, n = sep_problem(7, 6, 3, 5, 2002)
     D2, nvec, _, Yhat, _, _, _ = olz.sylvester_data(p, t, n)
@@ -72,7 +72,7 @@ def test_lanczos_tridiagonal_factorisation():
     assert rel((D2 @ Vj) / nvec[:, None], np.hstack(Vs) @ Tbar) < 1e-10
 
 
-@pytest.mark.parametrize("shape", [(6, 5, 3, 4), (9, 8, 4, 9), (1, 7, 2, 3), (4, 4, 1, 2)])
+@pytest.mark.parametrize("shape", [(6, 5, 3, 4), (9, 8, 4, 9), (1, 24, 2, 3), (4, 4, 1, 2)])
 def test_lanczos_sylvester_equals_dense(shape):
     ny, nx, k, f = shape
     p, t, n = sep_problem(ny, nx, k, f, 2004 + ny)
@@ -81,6 +81,23 @@ def test_lanczos_sylvester_equals_dense(shape):
     xd = osv.solve_dense(p)
     assert rel(res["x"], xd) < 1e-8
     assert rel(res["x"], osv.solve_kohler(p, t, n)) < 1e-8
+
+
+def test_projected_solution_is_the_small_sylvester_solution():
+    """The coefficients Z of the Galerkin approximation solve T_i Z + Z Lhat = E_1 B_0
+    (eq. (Sylv-small)): the oracle's decoupled banded solves against LAPACK's Bartels-Stewart
+    solver (scipy.linalg.solve_sylvester) on the explicitly assembled T_i."""
+    import scipy.linalg as sla
+    p, t, n = sep_problem(8, 7, 4, 6, 2008)
+    D2, nvec, Lhat, Yhat, U, rho, P = olz.sylvester_data(p, t, n)
+    Vs, Hs, Bs = olz.lanczos(D2, nvec, Yhat, 6)
+    for i in range(1, 7):
+        T = olz.block_tridiagonal(Hs[:i], Bs[:i + 1])
+        C = np.zeros((i * p.k, p.k))
+        C[:p.k, :] = Bs[0]
+        Zref = sla.solve_sylvester(T, Lhat, C)
+        Z = np.vstack(olz.galerkin_coefficients(Hs[:i], Bs[:i + 1], U, rho, P))
+        assert rel(Z, Zref) < 1e-10, i
 
 
 def test_gamma_is_the_residual_norm():
