@@ -592,6 +592,32 @@ def test_block_cg_needs_fewer_iterations():
     assert its[1] <= its[0]
 
 
+@pytest.mark.parametrize("s", [2, 4, 8])
+def test_block_cg_iterates_match_oracle_block_pcg(s):
+    """Runs stopped after j = 1..5 block iterations hold the oracle's block-CG iterates (O'Leary's
+    recurrence; float64, no preconditioner so that both sides apply the same operator): this
+    shows the block recurrence is the one taken, since independent CG's iterates differ."""
+    from oracle import block_pcg as obp
+    p = make_problem(20, 18, 2, 3, seed=1550 + s, noise="hetero")
+    rng = np.random.default_rng(1551)
+    B = rng.standard_normal((s, p.k * p.n_pix))
+    dp = sy.DeviceProblem.from_numpy(p)
+    its = obp.block_pcg(p, B, max_iter=5, precond="none")
+    say("block iterates vs oracle, s =", s)
+    for j in range(1, 6):
+        for block in (1, 0):
+            X, st = sy.pcg_solve([dp], Bextra=dev(B.ravel()), nrhs=s, opts=sy.SolveOptions(
+                tol=1e-15, max_iter=j, block=block, block_size=s if block else 0,
+                precond=sy.SYLV_PC_NONE, check_every=1))
+            assert all(c["status"] == sy.binding.SYLV_NOT_CONVERGED and c["iters"] == j
+                       for c in st), st
+            e = rel(host(X).reshape(s, -1), its[j])
+            if block:
+                assert e < 1e-9, (j, e)
+            elif j >= 2:
+                assert e > 1e-4, (j, e)       # independent CG is a different iteration
+
+
 def test_block_cg_rejects_unsupported_block_size():
     p = make_problem(8, 8, 2, 3, seed=1600)
     dp = sy.DeviceProblem.from_numpy(p)
