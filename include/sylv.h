@@ -24,6 +24,13 @@
  *    comes from the caller's workspace `ws` of `ws_bytes` bytes (256-byte aligned), sized by
  *    sylv_workspace_bytes().  The workspace must not be shared by calls that overlap in time.
  *    (sylv_pcg_solve_noalloc uses a static per-device array of the library instead.)
+ *  - Host-side state: solves with the adaptive schedule (and the Lanczos-Sylvester solver) read
+ *    their convergence reports from one small pinned host block with four events per calling
+ *    host thread, allocated on the thread's first such call (hipHostMalloc, hipEventCreate) and
+ *    kept until the thread ends.  sylv_lanczos_solve and sylv_kohler_solve copy tau, A and t to
+ *    the host (the k x k decompositions run there) and sylv_lanczos_stats is a host struct; every
+ *    other result is written to device memory.  The enqueue-only calls and fixed-schedule solves
+ *    touch no host state but the thread-local last-error string.
  *  - `stream` is a hipStream_t (NULL = the null stream).  sylv_apply, sylv_precond,
  *    sylv_prepare, sylv_rhs and sylv_po_perturb only enqueue work, with no host
  *    synchronisation, so they may be captured into a HIP graph.  sylv_pcg_solve and
