@@ -586,6 +586,58 @@ def bench_sylvester(sy, torch, steps, warmup, max_iter=800, cpu=False):
     return res
 
 
+def pmc_workload(sy, torch, mode):
+    """Short runs for hardware-counter passes (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE), each
+    with a 256 MiB device copy that calibrates the counters.
+    pmc_block: 20 iterations of block CG (all 8 columns of every group active throughout) and of
+    independent CG on the 8-grid batch, mixed and float64.  pmc_masked: 3 stand-alone applies of
+    each precision and one mixed and one float64 solve of the 2048^2 masked workload."""
+    from workloads import WORKLOADS, workload
+    nbytes = 256 << 20
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").uniform_()
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    out = {"mode": mode, "copy_bytes": nbytes}
+    if mode == "pmc_block":
+        probs = workload("batched_8grids")
+        nrhs = WORKLOADS["batched_8grids"]["nrhs"]
+        dps = [sy.DeviceProblem.from_numpy(p) for p in probs]
+        Y = torch.cat([torch.as_tensor(p.Y.ravel(), device="cuda") for p in probs])
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(1003)
+        B = torch.cat([torch.randn((nrhs, p.k, p.n_pix), generator=gen, dtype=torch.float64,
+                                   device="cuda").reshape(-1) for p in probs])
+        for prec in (sy.SYLV_PREC_MIXED, sy.SYLV_PREC_F64):
+            for blk in (1, 0):
+                o = sy.SolveOptions(tol=1e-14, max_iter=20, precision=prec, block=blk,
+                                    refine_max=1, inner_tol=1e-30)
+                sy.pcg_solve(dps, Y=Y, Bextra=B, opts=o, nrhs=nrhs)
+        torch.cuda.synchronize()
+        out["pixels"] = sum(p.n_pix for p in probs)
+        out["k"], out["s"] = probs[0].k, nrhs
+    else:
+        prob = workload("masked_2048")[0]
+        dp = sy.DeviceProblem.from_numpy(prob)
+        Y = torch.as_tensor(prob.Y, device="cuda")
+        ws_app = sy.binding.prepare(dp, sy.SYLV_PC_NONE)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(7)
+        X64 = torch.randn((prob.k, prob.n_pix), generator=gen, dtype=torch.float64, device="cuda")
+        X32 = X64.float()
+        for _ in range(3):
+            sy.apply(dp, X32, ws=ws_app, prepared=True)
+            sy.apply(dp, X64, ws=ws_app, prepared=True)
+        for prec in (sy.SYLV_PREC_MIXED, sy.SYLV_PREC_F64):
+            sy.pcg_solve(dp, Y=Y, opts=sy.SolveOptions(tol=1e-8, precision=prec))
+        torch.cuda.synchronize()
+        out["apply_f32_bytes"] = apply_bytes_per_pixel(prob.k, 4, prob.f) * prob.n_pix
+        out["apply_f64_bytes"] = apply_bytes_per_pixel(prob.k, 8, prob.f) * prob.n_pix
+    out["kernel_source_sha"] = kernel_source_hash()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -596,7 +648,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the 2048^2, batched and differentiable workloads")
     ap.add_argument("--mode", default="bench",
-                    choices=["bench", "pmc", "sylv", "sky", "sweep", "masked", "batched"],
+                    choices=["bench", "pmc", "pmc_block", "pmc_masked", "sylv", "sky", "sweep",
+                             "masked", "batched"],
                     help="pmc: copy + applies + one solve of each precision (counter runs); "
                          "sylv: only the Lanczos-Sylvester workload; sky: only the 12-face "
                          "full-sky workload; sweep: only the hyperparameter sweep; masked: only "
@@ -614,6 +667,9 @@ def main():
     from workloads import WORKLOADS, workload
 
     torch.cuda.set_device(0)
+    if args.mode in ("pmc_block", "pmc_masked"):
+        print(json.dumps(pmc_workload(sy, torch, args.mode)), flush=True)
+        return
     if args.mode == "sylv":
         print(json.dumps({"mode": "sylv", "sylv_1024": bench_sylvester(
             sy, torch, max(2, args.steps // 2), max(1, args.warmup))}), flush=True)

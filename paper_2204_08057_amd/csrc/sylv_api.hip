@@ -59,6 +59,15 @@ double inner_safety() {
     return (v > 0.0 && v <= 1.0) ? v : kInnerSafety;
 }
 
+// Whether kernels stream their once-touched planes past the last-level cache: when the bytes a
+// solve (or apply) keeps touching exceed kStreamBytes, or as SYLV_STREAM (0 or 1) forces for
+// experiments (read at every call).
+int stream_policy(double working_set_bytes) {
+    const char *e = getenv("SYLV_STREAM");
+    if (e && (e[0] == '0' || e[0] == '1') && e[1] == 0) return e[0] - '0';
+    return working_set_bytes > kStreamBytes ? 1 : 0;
+}
+
 int apply_rows_request() {
     static int rows = -1;
     if (rows < 0) {
@@ -573,6 +582,17 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
     set.rows32 = rows32;
     set.bc = bc;
     set.any_pre = any_pre;
+    {
+        // bytes the CG loop keeps touching: per problem the mixing blocks and the bfloat16
+        // preconditioner factor, per instance x, r, z, two directions and q
+        const double es = mixed ? 4.0 : 8.0;
+        double wsb = 0.0;
+        for (int g = 0; g < nprob; ++g) {
+            const double n = (double)probs[g].ny * probs[g].nx, mk = packed_size(k);
+            wsb += n * (mk * es + 2.0 * mk) + n * nrhs * 6.0 * k * es;
+        }
+        set.stream = stream_policy(wsb);
+    }
 
     // block CG groups: nrhs / bsize per problem, each bsize consecutive instances
     GroupSet gset;
@@ -1483,9 +1503,12 @@ int sylv_apply(const sylv_problem *prob, int32_t dtype, const void *X, void *Y, 
     }
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     char *base = reinterpret_cast<char *>(ws);
+    const double es = dtype == SYLV_F64 ? 8.0 : 4.0, n = (double)prob->ny * prob->nx;
+    const int streamed = stream_policy(n * (2.0 * prob->k * nrhs + packed_size(prob->k)) * es);
     HIP_TRY(launch_apply_plain(reinterpret_cast<const Inst *>(base + L.table), prob->k, dtype,
                                apply_rows_for(prob->k, dtype, apply_rows_request()),
-                               prob->boundary, (int)prob->ny, (int)prob->nx, nrhs, X, Y, s));
+                               prob->boundary, streamed, (int)prob->ny, (int)prob->nx, nrhs, X,
+                               Y, s));
     return SYLV_OK;
 }
 

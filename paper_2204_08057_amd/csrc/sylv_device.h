@@ -67,50 +67,62 @@ __device__ __forceinline__ unsigned hi_f64(double v) {
     return (unsigned)(__builtin_bit_cast(unsigned long long, v) >> 32);
 }
 
+// AUX: the cache-policy bits of the buffer instruction; kNT (the non-temporal bit) streams data
+// that the kernel touches once past the caches (see k_apply / k_update).
+constexpr int kNT = 2;
+template <int AUX = 0>
 __device__ __forceinline__ float bld(const GAS float *plane, uint32_t n, uint32_t i) {
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(plane_rsrc(plane, n), i * 4u, 0, 0));
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(plane_rsrc(plane, n), i * 4u, 0, AUX));
 }
+template <int AUX = 0>
 __device__ __forceinline__ double bld(const GAS double *plane, uint32_t n, uint32_t i) {
-    const u32x2 a = __builtin_amdgcn_raw_buffer_load_b64(plane_rsrc(plane, n), i * 8u, 0, 0);
+    const u32x2 a = __builtin_amdgcn_raw_buffer_load_b64(plane_rsrc(plane, n), i * 8u, 0, AUX);
     return join_f64(a.x, a.y);
 }
+template <int AUX = 0>
 __device__ __forceinline__ void bst(GAS float *plane, uint32_t n, uint32_t i, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), plane_rsrc((const GAS float *)plane, n), i * 4u, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), plane_rsrc((const GAS float *)plane, n), i * 4u, 0, AUX);
 }
+template <int AUX = 0>
 __device__ __forceinline__ void bst(GAS double *plane, uint32_t n, uint32_t i, double v) {
     const u32x2 a = {lo_f64(v), hi_f64(v)};
-    __builtin_amdgcn_raw_buffer_store_b64(a, plane_rsrc((const GAS double *)plane, n), i * 8u, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(a, plane_rsrc((const GAS double *)plane, n), i * 8u, 0, AUX);
 }
 // four consecutive elements starting at i (i % 4 == 0, planes 16-byte aligned)
+template <int AUX = 0>
 __device__ __forceinline__ void bld4(const GAS float *plane, uint32_t n, uint32_t i, float (&v)[4]) {
-    const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(plane_rsrc(plane, n), i * 4u, 0, 0);
+    const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(plane_rsrc(plane, n), i * 4u, 0, AUX);
     v[0] = __uint_as_float(a.x); v[1] = __uint_as_float(a.y);
     v[2] = __uint_as_float(a.z); v[3] = __uint_as_float(a.w);
 }
+template <int AUX = 0>
 __device__ __forceinline__ void bld4(const GAS double *plane, uint32_t n, uint32_t i, double (&v)[4]) {
     const __amdgpu_buffer_rsrc_t r = plane_rsrc(plane, n);
-    const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, i * 8u, 0, 0);
-    const u32x4 b = __builtin_amdgcn_raw_buffer_load_b128(r, i * 8u + 16u, 0, 0);
+    const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, i * 8u, 0, AUX);
+    const u32x4 b = __builtin_amdgcn_raw_buffer_load_b128(r, i * 8u + 16u, 0, AUX);
     v[0] = join_f64(a.x, a.y); v[1] = join_f64(a.z, a.w);
     v[2] = join_f64(b.x, b.y); v[3] = join_f64(b.z, b.w);
 }
+template <int AUX = 0>
 __device__ __forceinline__ void bld4(const GAS unsigned short *plane, uint32_t n, uint32_t i,
                                      float (&v)[4]) {
-    const u32x2 a = __builtin_amdgcn_raw_buffer_load_b64(plane_rsrc(plane, n), i * 2u, 0, 0);
+    const u32x2 a = __builtin_amdgcn_raw_buffer_load_b64(plane_rsrc(plane, n), i * 2u, 0, AUX);
     v[0] = __uint_as_float(a.x << 16); v[1] = __uint_as_float(a.x & 0xffff0000u);
     v[2] = __uint_as_float(a.y << 16); v[3] = __uint_as_float(a.y & 0xffff0000u);
 }
+template <int AUX = 0>
 __device__ __forceinline__ void bst4(GAS float *plane, uint32_t n, uint32_t i, const float (&v)[4]) {
     const u32x4 a = {__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]),
                      __float_as_uint(v[3])};
-    __builtin_amdgcn_raw_buffer_store_b128(a, plane_rsrc((const GAS float *)plane, n), i * 4u, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(a, plane_rsrc((const GAS float *)plane, n), i * 4u, 0, AUX);
 }
+template <int AUX = 0>
 __device__ __forceinline__ void bst4(GAS double *plane, uint32_t n, uint32_t i, const double (&v)[4]) {
     const __amdgpu_buffer_rsrc_t r = plane_rsrc((const GAS double *)plane, n);
     const u32x4 a = {lo_f64(v[0]), hi_f64(v[0]), lo_f64(v[1]), hi_f64(v[1])};
     const u32x4 b = {lo_f64(v[2]), hi_f64(v[2]), lo_f64(v[3]), hi_f64(v[3])};
-    __builtin_amdgcn_raw_buffer_store_b128(a, r, i * 8u, 0, 0);
-    __builtin_amdgcn_raw_buffer_store_b128(b, r, i * 8u + 16u, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(a, r, i * 8u, 0, AUX);
+    __builtin_amdgcn_raw_buffer_store_b128(b, r, i * 8u + 16u, 0, AUX);
 }
 
 // Grid boundary of the pixel graph (template parameter of the stencil kernels).
@@ -332,7 +344,7 @@ __device__ __forceinline__ void precond_cg_pixel(int pc, const GAS unsigned shor
     }
 }
 
-template <typename T, int K>
+template <typename T, int K, int AUX = 0>
 __device__ __forceinline__ void precond_cg_vec4(int pc, const GAS unsigned short *F, int n_pix,
                                                 int p0, const T (&r)[K][4], T (&z)[K][4]) {
     if (pc == SYLV_PC_BLOCK) {
@@ -341,7 +353,7 @@ __device__ __forceinline__ void precond_cg_vec4(int pc, const GAS unsigned short
 #pragma unroll
         for (int e = 0; e < MK; ++e) {
             float tmp[4];
-            bld4(F + (size_t)e * n_pix, (uint32_t)n_pix, (uint32_t)p0, tmp);
+            bld4<AUX>(F + (size_t)e * n_pix, (uint32_t)n_pix, (uint32_t)p0, tmp);
 #pragma unroll
             for (int q = 0; q < 4; ++q) g[e][q] = (T)tmp[q];
         }
@@ -367,7 +379,7 @@ __device__ __forceinline__ void precond_cg_vec4(int pc, const GAS unsigned short
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             float d[4];
-            bld4(F + (size_t)j * n_pix, (uint32_t)n_pix, (uint32_t)p0, d);
+            bld4<AUX>(F + (size_t)j * n_pix, (uint32_t)n_pix, (uint32_t)p0, d);
 #pragma unroll
             for (int q = 0; q < 4; ++q) z[j][q] = (T)d[q] * r[j][q];
         }

@@ -118,6 +118,8 @@ struct InstSet {
     int rows64, rows32;   // rows per lane of the float64 / float32 apply kernels
     int any_pre;          // some instance has Inst::pre set
     int bc;               // SYLV_BC_* of every instance (face grids use 2 rows per lane)
+    int stream;           // 1: the working set exceeds the last-level cache, so the CG kernels
+                          // stream their once-touched planes with non-temporal accesses
 };
 
 inline int packed_size(int k) { return k * (k + 1) / 2; }
@@ -178,8 +180,10 @@ hipError_t launch_setup(const double *W, const double *A, int f, int ny, int nx,
                         float *P32, unsigned short *P16, int exact, int k, hipStream_t s);
 hipError_t launch_rhs(const double *W, const double *Y, const double *A, int f, int n_pix,
                       const double *bext, double *b, int k, hipStream_t s);
-hipError_t launch_apply_plain(const Inst *table0, int k, int dtype, int rows, int bc, int ny,
-                              int nx, int nrhs, const void *in, void *out, hipStream_t s);
+hipError_t launch_apply_plain(const Inst *table0, int k, int dtype, int rows, int bc, int stream,
+                              int ny, int nx, int nrhs, const void *in, void *out, hipStream_t s);
+// Working sets above this many bytes are streamed past the last-level cache (256 MB on MI355X).
+constexpr double kStreamBytes = 256.0 * (1 << 20);
 hipError_t launch_precond_plain(const Inst *table0, int k, int dtype, int n_pix, int nrhs,
                                 const void *in, void *out, hipStream_t s);
 // residual r = b - G x (float64); phase 0: initial (sets ||b||, ||r0||, threshold),

@@ -214,7 +214,11 @@ __global__ __launch_bounds__(kBlock) void k_rhs(const double *__restrict__ W,
 //   AM_RESID : r = b - G(x) and the ||r||^2, ||b||^2 partials   (initial / true residual)
 enum ApplyMode { AM_PLAIN = 0, AM_CG = 1, AM_RESID = 2 };
 
-template <typename T, int K, int R, int MODE, int BC>
+// CP: cache policy of the data this kernel touches once (bit 0: the per-pixel mixing blocks, b
+// and the interior x / p_(it-2) loads; bit 1: every store) -- non-temporal when the solve's
+// working set exceeds the last-level cache (the staged fields keep the default: their halos are
+// re-read by neighbouring tiles through the cache).
+template <typename T, int K, int R, int MODE, int BC, int CP>
 __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
                                                   const int *__restrict__ tprefix, int ninst,
                                                   int nb, int it,
@@ -224,6 +228,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
     constexpr int LH = kWavesY * R + 4;   // staged rows: tile + 2-row halo above and below
     constexpr int LW = kTileX + 4;        // staged columns: tile + 2-column halo left and right
     constexpr int RPW = LH / kWavesY;     // staged rows per wavefront
+    constexpr int LA = (CP & 1) ? kNT : 0, SA = (CP & 2) ? kNT : 0;
     const int L = xcd_remap(blockIdx.x, nb);
     const int ii = (MODE == AM_PLAIN) ? 0 : find_inst(tprefix, ninst, L);
     const Inst &I = tab[ii];
@@ -327,8 +332,8 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
             for (int j = 0; j < K; ++j)
 #pragma unroll
                 for (int rr = 0; rr < RPW; ++rr) {
-                    xs[j][rr] = xin[rr] ? bld(xx + (size_t)j * n_pix, np, soff[rr]) : (T)0;
-                    if (pair) po[j][rr] = xin[rr] ? bld(p2 + (size_t)j * n_pix, np, soff[rr]) : (T)0;
+                    xs[j][rr] = xin[rr] ? bld<LA>(xx + (size_t)j * n_pix, np, soff[rr]) : (T)0;
+                    if (pair) po[j][rr] = xin[rr] ? bld<LA>(p2 + (size_t)j * n_pix, np, soff[rr]) : (T)0;
                 }
         }
     }
@@ -342,11 +347,11 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
         for (int t = 0; t < R; ++t) {
             const int pix = (iy0 + t < ny ? iy0 + t : 0) * nx + ixc;
 #pragma unroll
-            for (int e = 0; e < MK; ++e) m[t][e] = bld(M + (size_t)e * n_pix, np, (uint32_t)pix);
+            for (int e = 0; e < MK; ++e) m[t][e] = bld<LA>(M + (size_t)e * n_pix, np, (uint32_t)pix);
             if constexpr (MODE == AM_RESID) {
                 const GAS double *bb = gp(I.b);
 #pragma unroll
-                for (int j = 0; j < K; ++j) bpre[t][j] = bld(bb + (size_t)j * n_pix, np, (uint32_t)pix);
+                for (int j = 0; j < K; ++j) bpre[t][j] = bld<LA>(bb + (size_t)j * n_pix, np, (uint32_t)pix);
             }
         }
     }
@@ -383,22 +388,22 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
                     for (int rr2 = 0; rr2 < RPW; ++rr2)
                         if (xin[rr2]) {
                             const T x1 = xs[j][rr2] + a2 * po[j][rr2];
-                            bst(xx + (size_t)j * n_pix, np, soff[rr2], x1 + a1 * sa[j][rr2]);
+                            bst<SA>(xx + (size_t)j * n_pix, np, soff[rr2], x1 + a1 * sa[j][rr2]);
                         }
             } else if (xnow) {
 #pragma unroll
                 for (int j = 0; j < K; ++j)
 #pragma unroll
                     for (int rr2 = 0; rr2 < RPW; ++rr2)
-                        if (xin[rr2]) bst(xx + (size_t)j * n_pix, np, soff[rr2], xs[j][rr2] + a1 * sa[j][rr2]);
+                        if (xin[rr2]) bst<SA>(xx + (size_t)j * n_pix, np, soff[rr2], xs[j][rr2] + a1 * sa[j][rr2]);
             } else {   // float64, odd it: the run stops here; alpha_(it-2) p_(it-2) is in x
 #pragma unroll
                 for (int j = 0; j < K; ++j)
 #pragma unroll
                     for (int rr2 = 0; rr2 < RPW; ++rr2)
                         if (xin[rr2]) {
-                            const T x0v = bld(xx + (size_t)j * n_pix, np, soff[rr2]);
-                            bst(xx + (size_t)j * n_pix, np, soff[rr2], x0v + a1 * sa[j][rr2]);
+                            const T x0v = bld<LA>(xx + (size_t)j * n_pix, np, soff[rr2]);
+                            bst<SA>(xx + (size_t)j * n_pix, np, soff[rr2], x0v + a1 * sa[j][rr2]);
                         }
             }
         }
@@ -484,14 +489,14 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
                 if constexpr (MODE == AM_PLAIN) {
                     GAS T *o = gp(ext_out) + (size_t)blockIdx.y * K * n_pix;
 #pragma unroll
-                    for (int j = 0; j < K; ++j) bst(o + (size_t)j * n_pix, np, (uint32_t)pix, acc[j][t]);
+                    for (int j = 0; j < K; ++j) bst<SA>(o + (size_t)j * n_pix, np, (uint32_t)pix, acc[j][t]);
                 } else if constexpr (MODE == AM_CG) {
                     GAS T *pp = Sel<T>::p(I, it + 1);
                     GAS T *qq = Sel<T>::q(I);
 #pragma unroll
                     for (int j = 0; j < K; ++j) {
-                        bst(pp + (size_t)j * n_pix, np, (uint32_t)pix, ctr[j][t]);
-                        bst(qq + (size_t)j * n_pix, np, (uint32_t)pix, acc[j][t]);
+                        bst<SA>(pp + (size_t)j * n_pix, np, (uint32_t)pix, ctr[j][t]);
+                        bst<SA>(qq + (size_t)j * n_pix, np, (uint32_t)pix, acc[j][t]);
                         d0 += (double)ctr[j][t] * (double)acc[j][t];
                     }
                 } else {
@@ -500,7 +505,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
                     for (int j = 0; j < K; ++j) {
                         const double bv = bpre[t][j];
                         const double res = bv - (double)acc[j][t];
-                        bst(rv + (size_t)j * n_pix, np, (uint32_t)pix, res);
+                        bst<SA>(rv + (size_t)j * n_pix, np, (uint32_t)pix, res);
                         d0 += res * res;
                         d1 += bv * bv;
                     }
@@ -573,10 +578,12 @@ __global__ __launch_bounds__(kBlock) void k_resid_fin(const Inst *__restrict__ t
 //   <r, z>, ||r||^2 partials for the next stopping test and beta.  The matching x += alpha p is
 //   done by the next iteration's apply, which reads p anyway (alpha is kept in the state).
 // T = double: the float64 run.  T = float: an inner run of the mixed path.
-template <typename T, int K>
+// CP as for k_apply (bit 0: the loads of r, q and the preconditioner factor; bit 1: the stores).
+template <typename T, int K, int CP>
 __global__ __launch_bounds__(kBlock) void k_update(const Inst *__restrict__ tab,
                                                    const int *__restrict__ cprefix, int ninst,
                                                    int nb, int it) {
+    constexpr int LA = (CP & 1) ? kNT : 0, SA = (CP & 2) ? kNT : 0;
     const int L = xcd_remap(blockIdx.x, nb);
     const int ii = find_inst(cprefix, ninst, L);
     const Inst &I = tab[ii];
@@ -606,8 +613,8 @@ __global__ __launch_bounds__(kBlock) void k_update(const Inst *__restrict__ tab,
     if (vec) {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            bld4(r + (size_t)j * n_pix, np, (uint32_t)p0, rv[j]);
-            bld4(q + (size_t)j * n_pix, np, (uint32_t)p0, qv[j]);
+            bld4<LA>(r + (size_t)j * n_pix, np, (uint32_t)p0, rv[j]);
+            bld4<LA>(q + (size_t)j * n_pix, np, (uint32_t)p0, qv[j]);
         }
     }
     double s[1];
@@ -636,12 +643,12 @@ __global__ __launch_bounds__(kBlock) void k_update(const Inst *__restrict__ tab,
             for (int j = 0; j < K; ++j) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) rv[j][e] -= alpha * qv[j][e];
-                bst4(r + (size_t)j * n_pix, np, (uint32_t)p0, rv[j]);
+                bst4<SA>(r + (size_t)j * n_pix, np, (uint32_t)p0, rv[j]);
             }
-            precond_cg_vec4<T, K>(pc, P, n_pix, p0, rv, zv);
+            precond_cg_vec4<T, K, LA>(pc, P, n_pix, p0, rv, zv);
 #pragma unroll
             for (int j = 0; j < K; ++j) {
-                bst4(z + (size_t)j * n_pix, np, (uint32_t)p0, zv[j]);
+                bst4<SA>(z + (size_t)j * n_pix, np, (uint32_t)p0, zv[j]);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     rz += (double)rv[j][e] * (double)zv[j][e];
@@ -1060,35 +1067,54 @@ __global__ void k_grad_fin(const double *__restrict__ partial, int nv, int nblk,
 
 // Face grids always run with 2 rows per lane (the host sizes their tiles accordingly).  Only the
 // row counts that apply_rows_for can return for (T, K) are instantiated.
-template <typename T, int K, int MODE>
-hipError_t launch_apply_rows(int rows, int bc, dim3 grid, hipStream_t s, const Inst *table,
-                             const int *tprefix, int ninst, int it, const void *in, void *out) {
+template <typename T, int K, int MODE, int CP>
+hipError_t launch_apply_rows_cp(int rows, int bc, dim3 grid, hipStream_t s, const Inst *table,
+                                const int *tprefix, int ninst, int it, const void *in, void *out) {
     constexpr int cap = apply_rows_cap(sizeof(T) == 8, K);
     const T *i = reinterpret_cast<const T *>(in);
     T *o = reinterpret_cast<T *>(out);
     const int nb = (int)grid.x;
     if (bc == SYLV_BC_FACE) {
-        hipLaunchKernelGGL((k_apply<T, K, 2, MODE, BC_FACE>), grid, dim3(kBlock), 0, s, table,
+        hipLaunchKernelGGL((k_apply<T, K, 2, MODE, BC_FACE, CP>), grid, dim3(kBlock), 0, s, table,
                            tprefix, ninst, nb, it, i, o);
         return hipGetLastError();
     }
     if constexpr (cap >= 8) {
         if (rows == 8) {
-            hipLaunchKernelGGL((k_apply<T, K, 8, MODE, BC_PERIODIC>), grid, dim3(kBlock), 0, s,
+            hipLaunchKernelGGL((k_apply<T, K, 8, MODE, BC_PERIODIC, CP>), grid, dim3(kBlock), 0, s,
                                table, tprefix, ninst, nb, it, i, o);
             return hipGetLastError();
         }
     }
     if constexpr (cap >= 4) {
         if (rows == 4) {
-            hipLaunchKernelGGL((k_apply<T, K, 4, MODE, BC_PERIODIC>), grid, dim3(kBlock), 0, s,
+            hipLaunchKernelGGL((k_apply<T, K, 4, MODE, BC_PERIODIC, CP>), grid, dim3(kBlock), 0, s,
                                table, tprefix, ninst, nb, it, i, o);
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((k_apply<T, K, 2, MODE, BC_PERIODIC>), grid, dim3(kBlock), 0, s, table,
+    hipLaunchKernelGGL((k_apply<T, K, 2, MODE, BC_PERIODIC, CP>), grid, dim3(kBlock), 0, s, table,
                        tprefix, ninst, nb, it, i, o);
     return hipGetLastError();
+}
+
+// Streaming policy of each precision (measured on 2048^2 grids): float64 applies gain most from
+// non-temporal loads of the once-read planes, float32 applies and updates from non-temporal
+// stores; both at once, or either inside the last-level cache, is slower.  The float64 update
+// keeps the default policy: it reads q right after the apply wrote it, and streaming its loads
+// slowed whole float64 solves (batched grids +6 %).
+template <typename T>
+constexpr int stream_cp() { return sizeof(T) == 8 ? 1 : 2; }
+
+template <typename T, int K, int MODE>
+hipError_t launch_apply_rows(int rows, int bc, int stream, dim3 grid, hipStream_t s,
+                             const Inst *table, const int *tprefix, int ninst, int it,
+                             const void *in, void *out) {
+    if (stream)
+        return launch_apply_rows_cp<T, K, MODE, stream_cp<T>()>(rows, bc, grid, s, table, tprefix,
+                                                                ninst, it, in, out);
+    return launch_apply_rows_cp<T, K, MODE, 0>(rows, bc, grid, s, table, tprefix, ninst, it, in,
+                                               out);
 }
 
 }  // namespace
@@ -1136,8 +1162,8 @@ hipError_t launch_rhs(const double *W, const double *Y, const double *A, int f, 
     });
 }
 
-hipError_t launch_apply_plain(const Inst *table0, int k, int dtype, int rows, int bc, int ny,
-                              int nx, int nrhs, const void *in, void *out, hipStream_t s) {
+hipError_t launch_apply_plain(const Inst *table0, int k, int dtype, int rows, int bc, int stream,
+                              int ny, int nx, int nrhs, const void *in, void *out, hipStream_t s) {
     if (bc == SYLV_BC_FACE) rows = 2;
     const unsigned tx = blocks_for(nx, kTileX);
     const unsigned ty = blocks_for(ny, kWavesY * rows);
@@ -1145,10 +1171,10 @@ hipError_t launch_apply_plain(const Inst *table0, int k, int dtype, int rows, in
     return dispatch_k(k, [&](auto tag) {
         constexpr int K = decltype(tag)::value;
         if (dtype == SYLV_F64)
-            return launch_apply_rows<double, K, AM_PLAIN>(rows, bc, grid, s, table0, nullptr, 1,
-                                                          0, in, out);
-        return launch_apply_rows<float, K, AM_PLAIN>(rows, bc, grid, s, table0, nullptr, 1, 0,
-                                                     in, out);
+            return launch_apply_rows<double, K, AM_PLAIN>(rows, bc, stream, grid, s, table0,
+                                                          nullptr, 1, 0, in, out);
+        return launch_apply_rows<float, K, AM_PLAIN>(rows, bc, stream, grid, s, table0, nullptr,
+                                                     1, 0, in, out);
     });
 }
 
@@ -1172,9 +1198,10 @@ hipError_t launch_precond_plain(const Inst *table0, int k, int dtype, int n_pix,
 hipError_t launch_resid(const InstSet &set, int k, int phase, hipStream_t s) {
     return dispatch_k(k, [&](auto tag) {
         constexpr int K = decltype(tag)::value;
-        return launch_apply_rows<double, K, AM_RESID>(set.rows64, set.bc, dim3(set.total_tiles),
-                                                      s, set.table, set.tprefix, set.ninst, phase,
-                                                      nullptr, nullptr);
+        return launch_apply_rows<double, K, AM_RESID>(set.rows64, set.bc, set.stream,
+                                                      dim3(set.total_tiles), s, set.table,
+                                                      set.tprefix, set.ninst, phase, nullptr,
+                                                      nullptr);
     });
 }
 
@@ -1187,13 +1214,13 @@ hipError_t launch_cg_apply(const InstSet &set, int k, int mixed, int it, hipStre
     return dispatch_k(k, [&](auto tag) {
         constexpr int K = decltype(tag)::value;
         if (mixed)
-            return launch_apply_rows<float, K, AM_CG>(set.rows32, set.bc,
+            return launch_apply_rows<float, K, AM_CG>(set.rows32, set.bc, set.stream,
                                                       dim3(set.total_tiles32), s, set.table,
                                                       set.tprefix32, set.ninst, it, nullptr,
                                                       nullptr);
-        return launch_apply_rows<double, K, AM_CG>(set.rows64, set.bc, dim3(set.total_tiles), s,
-                                                   set.table, set.tprefix, set.ninst, it,
-                                                   nullptr, nullptr);
+        return launch_apply_rows<double, K, AM_CG>(set.rows64, set.bc, set.stream,
+                                                   dim3(set.total_tiles), s, set.table,
+                                                   set.tprefix, set.ninst, it, nullptr, nullptr);
     });
 }
 
@@ -1201,11 +1228,14 @@ hipError_t launch_cg_update(const InstSet &set, int k, int mixed, int it, hipStr
     return dispatch_k(k, [&](auto tag) {
         constexpr int K = decltype(tag)::value;
         const dim3 grid(set.total_chunks);
-        if (mixed)
-            hipLaunchKernelGGL((k_update<float, K>), grid, dim3(kBlock), 0, s, set.table,
+        if (mixed && set.stream)
+            hipLaunchKernelGGL((k_update<float, K, stream_cp<float>()>), grid, dim3(kBlock), 0, s,
+                               set.table, set.cprefix, set.ninst, (int)grid.x, it);
+        else if (mixed)
+            hipLaunchKernelGGL((k_update<float, K, 0>), grid, dim3(kBlock), 0, s, set.table,
                                set.cprefix, set.ninst, (int)grid.x, it);
         else
-            hipLaunchKernelGGL((k_update<double, K>), grid, dim3(kBlock), 0, s, set.table,
+            hipLaunchKernelGGL((k_update<double, K, 0>), grid, dim3(kBlock), 0, s, set.table,
                                set.cprefix, set.ninst, (int)grid.x, it);
         return hipGetLastError();
     });

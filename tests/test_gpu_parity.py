@@ -660,3 +660,27 @@ def test_float64_final_update_reaches_every_tile():
     assert s_["status"] == 0 and s_["outer"] == 1, s_
     assert s_["relres_true"] <= 1e-8, s_
     assert s_["relres_true"] == pytest.approx(s_["relres_rec"], rel=0.05), s_
+
+
+@pytest.mark.parametrize("precision", [sy.SYLV_PREC_F64, sy.SYLV_PREC_MIXED])
+def test_streaming_cache_policy_changes_no_result(precision, monkeypatch):
+    """Working sets beyond the last-level cache switch the CG kernels and applies to
+    non-temporal loads or stores (SYLV_STREAM forces either policy): a cache hint only, so
+    solves and applies are bitwise the same under both, and match the oracle."""
+    prob = make_problem(36, 40, 4, 9, seed=1580, noise="hetero", mask_frac=0.1)
+    dp = sy.DeviceProblem.from_numpy(prob)
+    Xr = random_maps(prob, seed=1581)
+    out = {}
+    for mode in ("0", "1"):
+        monkeypatch.setenv("SYLV_STREAM", mode)
+        say("streaming policy", mode, "precision", precision)
+        X, st = sy.pcg_solve(dp, Y=dev(prob.Y), opts=sy.SolveOptions(
+            tol=1e-12 if precision == sy.SYLV_PREC_F64 else 1e-11, precision=precision))
+        assert st[0]["status"] == 0, st
+        dt = torch.float64 if precision == sy.SYLV_PREC_F64 else torch.float32
+        Y = sy.apply(dp, dev(Xr, dt))
+        out[mode] = (host(X), host(Y), st[0]["iters"])
+    assert np.array_equal(out["0"][0], out["1"][0]) and out["0"][2] == out["1"][2]
+    assert np.array_equal(out["0"][1], out["1"][1])
+    bound = 1e-8 if precision == sy.SYLV_PREC_F64 else 1e-7
+    assert rel(out["1"][0].reshape(prob.k, prob.n_pix), osv.solve_dense(prob)) <= bound
