@@ -97,9 +97,6 @@ int tiles_for(int ny, int nx, int rows) {
 }
 int chunks_for(int n_pix) { return (n_pix + kChunk - 1) / kChunk; }
 
-// The block apply keeps every column's direction at its output pixels in registers, so it runs
-// with 2 rows per lane.
-constexpr int kBlockRows = 2;
 
 struct ProbLayout {
     size_t coef, M64, M32, P64, P32, P16;
@@ -194,7 +191,7 @@ bool make_layout(const sylv_problem *probs, int nprob, int nrhs, bool solve, Lay
             const int n = ny * nx;
             for (int b = 0; b < gpp; ++b) {
                 const int i = g * gpp + b;
-                L.gnred[i] = std::max(tiles_for(ny, nx, 2), (n + kBlockPix - 1) / kBlockPix);
+                L.gnred[i] = std::max(tiles_for(ny, nx, kBlockRows), (n + kBlockPix - 1) / kBlockPix);
                 L.gstate[i] = off; off = align_up(off + sizeof(GroupState));
                 L.gpart[i] = off;  off = align_up(off + sizeof(double) * kBlockQ * L.gnred[i]);
             }
@@ -638,6 +635,7 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
         gset.total_tiles32 = gt32[ngroup];
         gset.total_chunks = gc[ngroup];
         gset.bc = bc;
+        gset.stream = set.stream;
     }
 
     // operator set-up and right-hand sides

@@ -64,19 +64,19 @@ __device__ __forceinline__ void ldv(const GAS T *plane, uint32_t n, uint32_t i, 
 #pragma unroll
     for (int e = 0; e < V; ++e) v[e] = (i + e < n) ? bld(plane, n, i + e) : (T)0;
 }
-template <typename T, int V, bool F>
+template <typename T, int V, bool F, int AUX = 0>
 __device__ __forceinline__ void stv(GAS T *plane, uint32_t n, uint32_t i, const T (&v)[V]) {
     if constexpr (V == 2 && sizeof(T) == 4 && F) {
         {
             const u32x2 a = {__float_as_uint(v[0]), __float_as_uint(v[1])};
             __builtin_amdgcn_raw_buffer_store_b64(a, plane_rsrc((const GAS float *)plane, n),
-                                                  i * 4u, 0, 0);
+                                                  i * 4u, 0, AUX);
             return;
         }
     }
 #pragma unroll
     for (int e = 0; e < V; ++e)
-        if (i + e < n) bst(plane, n, i + e, v[e]);
+        if (i + e < n) bst<AUX>(plane, n, i + e, v[e]);
 }
 
 // Preconditioner of one pixel from the bfloat16 factor planes (block kind: G = L^-1 with
@@ -257,8 +257,9 @@ __global__ __launch_bounds__(kBlock) void k_bpinit(const Inst *__restrict__ tab,
     flush_partials<NQ>(acc, G.partial, G.nred, chunk);
 }
 
-// P_it = Z + P_(it-1) beta on the active columns (it >= 1).
-template <typename T, int K, int S>
+// P_it = Z + P_(it-1) beta on the active columns (it >= 1).  SA: cache policy of the stores
+// (non-temporal when the batch exceeds the last-level cache, float32 only).
+template <typename T, int K, int S, int SA>
 __global__ __launch_bounds__(kBlock) void k_bdir(const Inst *__restrict__ tab,
                                                  const Group *__restrict__ groups,
                                                  const int *__restrict__ gcprefix, int ngroup,
@@ -309,7 +310,7 @@ __global__ __launch_bounds__(kBlock) void k_bdir(const Inst *__restrict__ tab,
 #pragma unroll
                     for (int e = 0; e < V; ++e) v[e] += b * po[c][e];
                 }
-                stv<T, V, F>(Sel<T>::p(tab[G.inst0 + r], it) + (size_t)j * n_pix, np,
+                stv<T, V, F, SA>(Sel<T>::p(tab[G.inst0 + r], it) + (size_t)j * n_pix, np,
                              (uint32_t)p0, v);
             }
         }
@@ -320,7 +321,7 @@ __global__ __launch_bounds__(kBlock) void k_bdir(const Inst *__restrict__ tab,
 
 // Q = G P for the active columns of a group, sharing the per-pixel mixing blocks, and the
 // partials of P^T Q.  Same tiling and LDS staging as the single-vector apply.
-template <typename T, int K, int R, int S, int BC>
+template <typename T, int K, int R, int S, int BC, int SA>
 __global__ __launch_bounds__(kBlock) void k_bapply(const Inst *__restrict__ tab,
                                                    const Group *__restrict__ groups,
                                                    const int *__restrict__ gtprefix, int ngroup,
@@ -496,7 +497,7 @@ __global__ __launch_bounds__(kBlock) void k_bapply(const Inst *__restrict__ tab,
 #pragma unroll
                     for (int j = 0; j < K; ++j) {
                         q[j][t] = tmp[j];
-                        bst(qq + (size_t)j * n_pix, np, (uint32_t)pix, tmp[j]);
+                        bst<SA>(qq + (size_t)j * n_pix, np, (uint32_t)pix, tmp[j]);
                     }
                 } else {
 #pragma unroll
@@ -525,7 +526,7 @@ __global__ __launch_bounds__(kBlock) void k_bapply(const Inst *__restrict__ tab,
 }
 
 // X += P alpha, R -= Q alpha, Z = Minv R on the active columns; partials of R^T Z, ||r_c||^2.
-template <typename T, int K, int S>
+template <typename T, int K, int S, int SA>
 __global__ __launch_bounds__(kBlock) void k_bupdate(const Inst *__restrict__ tab,
                                                     const Group *__restrict__ groups,
                                                     const int *__restrict__ gcprefix, int ngroup,
@@ -591,8 +592,8 @@ __global__ __launch_bounds__(kBlock) void k_bupdate(const Inst *__restrict__ tab
                             rr[e] -= a * qj[c][e];
                         }
                     }
-                    stv<T, V, F>(Sel<T>::x(I) + o, np, (uint32_t)p0, xv);
-                    stv<T, V, F>(Sel<T>::r(I) + o, np, (uint32_t)p0, rr);
+                    stv<T, V, F, SA>(Sel<T>::x(I) + o, np, (uint32_t)p0, xv);
+                    stv<T, V, F, SA>(Sel<T>::r(I) + o, np, (uint32_t)p0, rr);
 #pragma unroll
                     for (int e = 0; e < V; ++e) rv[r][j][e] = rr[e];
                 }
@@ -603,7 +604,7 @@ __global__ __launch_bounds__(kBlock) void k_bupdate(const Inst *__restrict__ tab
             const Inst &I = tab[G.inst0 + r];
 #pragma unroll
             for (int j = 0; j < K; ++j)
-                stv<T, V, F>(Sel<T>::z(I) + (size_t)j * n_pix, np, (uint32_t)p0, zb[j]);
+                stv<T, V, F, SA>(Sel<T>::z(I) + (size_t)j * n_pix, np, (uint32_t)p0, zb[j]);
         });
     };
     if (wave_full(chunk, V, n_pix, G.vec)) body(BTag<true>{});
@@ -932,18 +933,27 @@ hipError_t dispatch_s(int s, F &&fn) {
 
 // The block apply keeps every column's direction at its output pixels in registers: 2 rows per
 // lane on every grid.
-template <typename T, int K, int S>
-hipError_t launch_bapply_t(const GroupSet &gset, int total, const int *prefix, int it,
-                           hipStream_t st) {
+template <typename T, int K, int S, int SA>
+hipError_t launch_bapply_sa(const GroupSet &gset, int total, const int *prefix, int it,
+                            hipStream_t st) {
     const dim3 grid(total);
     if (gset.bc == SYLV_BC_FACE) {
-        hipLaunchKernelGGL((k_bapply<T, K, 2, S, BC_FACE>), grid, dim3(kBlock), 0, st,
+        hipLaunchKernelGGL((k_bapply<T, K, kBlockRows, S, BC_FACE, SA>), grid, dim3(kBlock), 0, st,
                            gset.table, gset.groups, prefix, gset.ngroup, (int)grid.x, it);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL((k_bapply<T, K, 2, S, BC_PERIODIC>), grid, dim3(kBlock), 0, st, gset.table,
-                       gset.groups, prefix, gset.ngroup, (int)grid.x, it);
+    hipLaunchKernelGGL((k_bapply<T, K, kBlockRows, S, BC_PERIODIC, SA>), grid, dim3(kBlock), 0, st,
+                       gset.table, gset.groups, prefix, gset.ngroup, (int)grid.x, it);
     return hipGetLastError();
+}
+
+// Batches beyond the last-level cache stream the float32 stores (as the single-vector kernels).
+template <typename T, int K, int S>
+hipError_t launch_bapply_t(const GroupSet &gset, int total, const int *prefix, int it,
+                           hipStream_t st) {
+    if (sizeof(T) == 4 && gset.stream)
+        return launch_bapply_sa<T, K, S, kNT>(gset, total, prefix, it, st);
+    return launch_bapply_sa<T, K, S, 0>(gset, total, prefix, it, st);
 }
 
 }  // namespace
@@ -987,11 +997,14 @@ hipError_t launch_bdir(const GroupSet &g, int k, int mixed, int it, hipStream_t 
         return dispatch_k(k, [&](auto tag) {
             constexpr int K = decltype(tag)::value;
             const dim3 grid(g.total_chunks);
-            if (mixed)
-                hipLaunchKernelGGL((k_bdir<float, K, S>), grid, dim3(kBlock), 0, st, g.table,
+            if (mixed && g.stream)
+                hipLaunchKernelGGL((k_bdir<float, K, S, kNT>), grid, dim3(kBlock), 0, st, g.table,
+                                   g.groups, g.gcprefix, g.ngroup, (int)grid.x, it);
+            else if (mixed)
+                hipLaunchKernelGGL((k_bdir<float, K, S, 0>), grid, dim3(kBlock), 0, st, g.table,
                                    g.groups, g.gcprefix, g.ngroup, (int)grid.x, it);
             else
-                hipLaunchKernelGGL((k_bdir<double, K, S>), grid, dim3(kBlock), 0, st, g.table,
+                hipLaunchKernelGGL((k_bdir<double, K, S, 0>), grid, dim3(kBlock), 0, st, g.table,
                                    g.groups, g.gcprefix, g.ngroup, (int)grid.x, it);
             return hipGetLastError();
         });
@@ -1017,12 +1030,15 @@ hipError_t launch_bupdate(const GroupSet &g, int k, int mixed, int it, hipStream
         return dispatch_k(k, [&](auto tag) {
             constexpr int K = decltype(tag)::value;
             const dim3 grid(g.total_chunks);
-            if (mixed)
-                hipLaunchKernelGGL((k_bupdate<float, K, S>), grid, dim3(kBlock), 0, st, g.table,
-                                   g.groups, g.gcprefix, g.ngroup, (int)grid.x, it);
+            if (mixed && g.stream)
+                hipLaunchKernelGGL((k_bupdate<float, K, S, kNT>), grid, dim3(kBlock), 0, st,
+                                   g.table, g.groups, g.gcprefix, g.ngroup, (int)grid.x, it);
+            else if (mixed)
+                hipLaunchKernelGGL((k_bupdate<float, K, S, 0>), grid, dim3(kBlock), 0, st,
+                                   g.table, g.groups, g.gcprefix, g.ngroup, (int)grid.x, it);
             else
-                hipLaunchKernelGGL((k_bupdate<double, K, S>), grid, dim3(kBlock), 0, st, g.table,
-                                   g.groups, g.gcprefix, g.ngroup, (int)grid.x, it);
+                hipLaunchKernelGGL((k_bupdate<double, K, S, 0>), grid, dim3(kBlock), 0, st,
+                                   g.table, g.groups, g.gcprefix, g.ngroup, (int)grid.x, it);
             return hipGetLastError();
         });
     });

@@ -129,6 +129,9 @@ constexpr int kMaxS = 8;                           // right-hand sides per group
 constexpr int kGramQ = kMaxS * (kMaxS + 1) / 2;    // packed s x s Gram entries
 constexpr int kBlockQ = kGramQ + kMaxS;            // + per-column ||r||^2
 constexpr int kBlockPix = 256;                     // smallest streaming chunk of the block kernels
+// Rows per lane of the block apply, which keeps every column's direction at its output pixels
+// in registers for the P^T Q Gram.
+constexpr int kBlockRows = 2;
 // Pixels per thread of the streaming block kernels (one 8-byte access per plane and lane):
 // chunks of kBlock * block_vec pixels.
 constexpr int block_vec(bool f64) { return f64 ? 1 : 2; }
@@ -165,6 +168,7 @@ struct GroupSet {
     int ngroup, s;
     int total_tiles, total_tiles32, total_chunks;
     int bc;
+    int stream;                  // as InstSet::stream
 };
 
 // ---- launchers (sylv_kernels.hip) -------------------------------------------------------
