@@ -94,6 +94,13 @@ extern "C" {
 #define SYLV_PC_NONE   0        /* z = r (plain Alg. 2)                                           */
 #define SYLV_PC_JACOBI 1        /* z = r / diag(G)                                                */
 #define SYLV_PC_BLOCK  2        /* z_p = (G_pp)^-1 r_p, G_pp the k x k block of pixel p           */
+#define SYLV_PC_FOURIER 3       /* z = (Q + I (x) Mbar)^-1 r through the 2-D DFT: the operator
+                                   with the weights replaced by their pixel means (Mbar =
+                                   sum_f mean_p(W[f, p]) a_f a_f^T), exact for pixel-independent
+                                   weights.  Periodic grids whose sides are powers of two in
+                                   [4, 4096], k * ny complex values within the column pass's 64 KB
+                                   of LDS (float32: k * ny <= 8192, float64: <= 4096 minus
+                                   padding); independent CG only (else SYLV_E_INVALID)          */
 
 /* One posterior-mean system (Section 2, Section 3).  Host struct of device pointers. */
 typedef struct sylv_problem {

@@ -40,6 +40,7 @@ SYLV_SCHED_FIXED = 1
 SYLV_PC_NONE = 0
 SYLV_PC_JACOBI = 1
 SYLV_PC_BLOCK = 2
+SYLV_PC_FOURIER = 3
 
 STATUS_NAMES = {
     SYLV_OK: "ok", SYLV_NOT_CONVERGED: "not converged", SYLV_BREAKDOWN: "breakdown",

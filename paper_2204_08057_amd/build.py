@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsylv.so")
 SOURCES = ["sylv_kernels.hip", "sylv_block.hip", "sylv_lanczos.hip", "sylv_kohler.hip",
-           "sylv_api.hip"]
+           "sylv_fourier.hip", "sylv_api.hip"]
 ARCH = os.environ.get("SYLV_OFFLOAD_ARCH", "gfx950")
 
 

@@ -38,6 +38,9 @@ void set_err(const char *fmt, ...) {
 }
 
 constexpr size_t kAlign = 256;
+// Prefix-sum arrays of the instance table: float64 and float32 apply tiles, streaming chunks,
+// and the Fourier preconditioner's row-pass and column-pass workgroups.
+constexpr int kPrefixArrays = 5;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Optional override of the apply kernels' rows per lane (2, 4 or 8) for tuning experiments.
@@ -100,9 +103,11 @@ int chunks_for(int n_pix) { return (n_pix + kChunk - 1) / kChunk; }
 
 struct ProbLayout {
     size_t coef, M64, M32, P64, P32, P16;
+    size_t fsym, fpart;   // Fourier preconditioner: symbol block and the weight-mean partials
 };
 struct InstLayout {
     size_t st, partial, b, r, z, p, p2, q, r32, z32, p32, p32b, q32, d32;
+    size_t fs;            // Fourier preconditioner: half spectrum (0 = none)
     int nred;
 };
 struct Layout {
@@ -112,8 +117,20 @@ struct Layout {
     std::vector<int> gnred;
     size_t groups = 0, gprefix = 0;
     size_t table = 0, tprefix = 0, count = 0, gpartial = 0;
+    size_t fs1 = 0;       // stand-alone Fourier preconditioner's half spectrum (0 = none)
     size_t total = 0;
 };
+
+// Whether a grid can take the Fourier preconditioner in some precision (the stand-alone
+// workspace then holds its spectrum), and the half spectrum's bytes (complex float64).
+bool fp_grid(const sylv_problem &p) {
+    char why[160];
+    return p.boundary == SYLV_BC_PERIODIC &&
+           fp_supported((int)p.ny, (int)p.nx, p.k, SYLV_F32, why, sizeof(why));
+}
+size_t fp_spectrum_bytes(const sylv_problem &p) {
+    return (size_t)16 * p.k * (size_t)(p.nx / 2 + 1) * (size_t)p.ny;
+}
 
 bool check_problem(const sylv_problem *p, int idx) {
     if (!p) { set_err("problem %d: null pointer", idx); return false; }
@@ -134,7 +151,8 @@ bool block_size_ok(int nrhs, int bs) { return block_rhs_supported(bs) && nrhs % 
 // Workspace: per-problem operator regions first (so that the layout of the operator of a single
 // problem does not depend on the call), then the instance table and prefixes, the run states,
 // reduction partials, solver vectors and the gradient partials.
-bool make_layout(const sylv_problem *probs, int nprob, int nrhs, bool solve, Layout &L) {
+bool make_layout(const sylv_problem *probs, int nprob, int nrhs, bool solve, Layout &L,
+                 int pc = SYLV_PC_BLOCK) {
     size_t off = 0;
     L.prob.resize(nprob);
     for (int g = 0; g < nprob; ++g) {
@@ -147,10 +165,16 @@ bool make_layout(const sylv_problem *probs, int nprob, int nrhs, bool solve, Lay
         P.P64 = off;  off = align_up(off + sizeof(double) * mk * n);
         P.P32 = off;  off = align_up(off + sizeof(float) * mk * n);
         P.P16 = off;  off = align_up(off + sizeof(unsigned short) * mk * n);
+        P.fsym = off; off = align_up(off + sizeof(double) * (kMaxK * kMaxK + 2 * kMaxK));
+        P.fpart = off; off = align_up(off + sizeof(double) * fp_setup_partials((int)n, probs[g].f));
+    }
+    if (!solve && nprob == 1 && fp_grid(probs[0])) {
+        L.fs1 = off;
+        off = align_up(off + fp_spectrum_bytes(probs[0]));
     }
     const int ninst = solve ? nprob * nrhs : 1;
     L.table = off;   off = align_up(off + sizeof(Inst) * ninst);
-    L.tprefix = off; off = align_up(off + sizeof(int) * 3 * (ninst + 1));
+    L.tprefix = off; off = align_up(off + sizeof(int) * kPrefixArrays * (ninst + 1));
     L.count = off;   off = align_up(off + sizeof(int) * 4);
     if (solve) {
         L.inst.resize(ninst);
@@ -160,7 +184,7 @@ bool make_layout(const sylv_problem *probs, int nprob, int nrhs, bool solve, Lay
             const size_t vk = (size_t)k * n;
             for (int r = 0; r < nrhs; ++r) {
                 InstLayout &I = L.inst[(size_t)g * nrhs + r];
-                I.nred = std::max(tiles_for(ny, nx, 2), chunks_for((int)n));
+                I.nred = std::max(std::max(tiles_for(ny, nx, 2), chunks_for((int)n)), nx / 2 + 1);
                 I.st = off;      off = align_up(off + 2 * sizeof(DevState));
                 I.partial = off; off = align_up(off + sizeof(double) * kNumSlots * I.nred);
                 I.b = off;   off = align_up(off + sizeof(double) * vk);
@@ -175,6 +199,11 @@ bool make_layout(const sylv_problem *probs, int nprob, int nrhs, bool solve, Lay
                 I.p32b = off; off = align_up(off + sizeof(float) * vk);
                 I.q32 = off; off = align_up(off + sizeof(float) * vk);
                 I.d32 = off; off = align_up(off + sizeof(float) * vk);
+                I.fs = 0;
+                if (pc == SYLV_PC_FOURIER) {
+                    I.fs = off;
+                    off = align_up(off + fp_spectrum_bytes(probs[g]));
+                }
             }
         }
         // block CG tables, sized whenever a call could use them: up to nrhs / 2 groups (blocks
@@ -248,6 +277,10 @@ int prepare_operator(const sylv_problem &p, const ProbLayout &P, char *base, int
                          reinterpret_cast<double *>(base + P.P64),
                          reinterpret_cast<float *>(base + P.P32),
                          reinterpret_cast<unsigned short *>(base + P.P16), exact, p.k, s));
+    if (pc == SYLV_PC_FOURIER)
+        HIP_TRY(launch_fp_setup(p.W, p.A, p.f, p.k, (int)(p.ny * p.nx), coef,
+                                reinterpret_cast<double *>(base + P.fpart),
+                                reinterpret_cast<double *>(base + P.fsym), s));
     return SYLV_OK;
 }
 
@@ -268,7 +301,7 @@ int check_opts(const sylv_pcg_opts *o) {
     if (!(o->tol > 0.0) || !(o->tol < 1.0)) { set_err("tol must be in (0, 1)"); return SYLV_E_INVALID; }
     if (o->max_iter < 1) { set_err("max_iter must be >= 1"); return SYLV_E_INVALID; }
     if (o->precision != SYLV_PREC_F64 && o->precision != SYLV_PREC_MIXED) { set_err("bad precision"); return SYLV_E_INVALID; }
-    if (o->precond < SYLV_PC_NONE || o->precond > SYLV_PC_BLOCK) { set_err("bad precond"); return SYLV_E_INVALID; }
+    if (o->precond < SYLV_PC_NONE || o->precond > SYLV_PC_FOURIER) { set_err("bad precond"); return SYLV_E_INVALID; }
     if (o->inner_tol < 0.0 || o->inner_tol >= 1.0) { set_err("inner_tol must be in [0, 1)"); return SYLV_E_INVALID; }
     if (o->refine_max < 0 || o->check_every < 0) { set_err("negative refine_max/check_every"); return SYLV_E_INVALID; }
     if (o->stop_ref != SYLV_STOP_R0 && o->stop_ref != SYLV_STOP_B) { set_err("bad stop_ref"); return SYLV_E_INVALID; }
@@ -383,10 +416,20 @@ int next_batch(const Report &prev, const Report &cur, bool have_prev, int queued
 // apply(max_iter) always stops it, so the loop ends.
 static_assert(sizeof(Inst) % 4 == 0 && sizeof(Group) % 4 == 0, "tables upload as 32-bit words");
 
+// The Fourier preconditioner's three passes (z and <r, z> of every unfinished run).
+int fourier_apply(const InstSet &set, int k, int mixed, hipStream_t s) {
+    HIP_TRY(launch_fp_apply(set, k, mixed, mixed, nullptr, nullptr, s));
+    return SYLV_OK;
+}
+
 int cg_iteration(const InstSet &set, int k, int mixed, int it, hipStream_t s) {
     HIP_TRY(launch_cg_apply(set, k, mixed, it, s));
     HIP_TRY(launch_prereduce_pq(set, mixed, s));
     HIP_TRY(launch_cg_update(set, k, mixed, it, s));
+    if (set.fourier) {
+        const int rc = fourier_apply(set, k, mixed, s);
+        if (rc) return rc;
+    }
     HIP_TRY(launch_prereduce_rz(set, s));
     return SYLV_OK;
 }
@@ -503,7 +546,20 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
                 bsize, nrhs);
         return SYLV_E_INVALID;
     }
-    make_layout(probs, nprob, nrhs, true, L);
+    const int fourier = opts->precond == SYLV_PC_FOURIER;
+    if (fourier) {
+        if (block) { set_err("block CG takes the per-pixel preconditioners only"); return SYLV_E_INVALID; }
+        const int dt = opts->precision == SYLV_PREC_MIXED ? SYLV_F32 : SYLV_F64;
+        for (int g = 0; g < nprob; ++g) {
+            char why[200];
+            if (probs[g].boundary != SYLV_BC_PERIODIC) { set_err("problem %d: the Fourier preconditioner needs a periodic grid", g); return SYLV_E_INVALID; }
+            if (!fp_supported((int)probs[g].ny, (int)probs[g].nx, k, dt, why, sizeof(why))) {
+                set_err("problem %d: %s", g, why);
+                return SYLV_E_INVALID;
+            }
+        }
+    }
+    make_layout(probs, nprob, nrhs, true, L, opts->precond);
     rc = check_ws(ws, ws_bytes, L.total);
     if (rc) return rc;
     if (!fixed && (rc = refuse_capture(s, "the adaptive schedule"))) return rc;
@@ -518,12 +574,14 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
     // instance table
     const int ninst = nprob * nrhs;
     std::vector<Inst> tab(ninst);
-    std::vector<int> pre(3 * (ninst + 1));
+    std::vector<int> pre(kPrefixArrays * (ninst + 1));
     int *tpre = pre.data(), *tpre32 = tpre + (ninst + 1), *cpre = tpre32 + (ninst + 1);
+    int *fpa = cpre + (ninst + 1), *fpb = fpa + (ninst + 1);
+    size_t fp_lds_rows = 0, fp_lds_cols = 0;
     size_t xoff = 0, yoff = 0;
     int any_pre = 0;
     const int pre_min = prereduce_min();
-    tpre[0] = tpre32[0] = cpre[0] = 0;
+    tpre[0] = tpre32[0] = cpre[0] = fpa[0] = fpb[0] = 0;
     for (int g = 0; g < nprob; ++g) {
         const sylv_problem &p = probs[g];
         const size_t n = (size_t)p.ny * p.nx;
@@ -554,18 +612,34 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
             I.st_in = I.st + 1;
             I.partial = reinterpret_cast<double *>(base + IL.partial);
             I.vec4 = (I.n_pix % 4 == 0) && aligned16(I.x) ? 1 : 0;
+            int nfa = 0, nfb = 0;
+            if (fourier) {
+                I.fs = reinterpret_cast<double *>(base + IL.fs);
+                I.fsym = reinterpret_cast<const double *>(base + L.prob[g].fsym);
+                I.lognx = __builtin_ctz((unsigned)I.nx);
+                I.logny = __builtin_ctz((unsigned)I.ny);
+                I.frb = fp_rows_per_block(I.nx, I.ny, mixed ? SYLV_F32 : SYLV_F64);
+                I.nfft = I.nx / 2 + 1;
+                nfa = k * (I.ny / I.frb);
+                nfb = I.nfft;
+                const int dt = mixed ? SYLV_F32 : SYLV_F64;
+                fp_lds_rows = std::max(fp_lds_rows, fp_lds_bytes(0, I.nx, I.frb, dt));
+                fp_lds_cols = std::max(fp_lds_cols, fp_lds_bytes(1, I.ny, k, dt));
+            }
             I.pre = std::max(std::max(I.ntiles, I.ntiles32), I.nchunks) > pre_min ? 1 : 0;
             any_pre |= I.pre;
             tab[i] = I;
             tpre[i + 1] = tpre[i] + I.ntiles;
             tpre32[i + 1] = tpre32[i] + I.ntiles32;
             cpre[i + 1] = cpre[i] + I.nchunks;
+            fpa[i + 1] = fpa[i] + nfa;
+            fpb[i + 1] = fpb[i] + nfb;
         }
         xoff += (size_t)nrhs * k * n;
         yoff += (size_t)p.f * n;
     }
     HIP_TRY(launch_upload(base + L.table, tab.data(), sizeof(Inst) * ninst, s));
-    HIP_TRY(launch_upload(base + L.tprefix, pre.data(), sizeof(int) * 3 * (ninst + 1), s));
+    HIP_TRY(launch_upload(base + L.tprefix, pre.data(), sizeof(int) * kPrefixArrays * (ninst + 1), s));
     InstSet set;
     set.table = reinterpret_cast<const Inst *>(base + L.table);
     set.tprefix = reinterpret_cast<const int *>(base + L.tprefix);
@@ -579,6 +653,13 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
     set.rows32 = rows32;
     set.bc = bc;
     set.any_pre = any_pre;
+    set.fourier = fourier;
+    set.fprefa = set.cprefix + (ninst + 1);
+    set.fprefb = set.fprefa + (ninst + 1);
+    set.total_fa = fpa[ninst];
+    set.total_fb = fpb[ninst];
+    set.fp_lds_rows = fp_lds_rows;
+    set.fp_lds_cols = fp_lds_cols;
     {
         // bytes the CG loop keeps touching: per problem the mixing blocks and the bfloat16
         // preconditioner factor, per instance x, r, z, two directions and q
@@ -661,6 +742,10 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
             HIP_TRY(launch_bgram(gset, 0, mixed, inner_tol, safety, opts->max_iter, s));
         } else {
             HIP_TRY(launch_pinit(set, k, mixed, inner_tol, safety, opts->max_iter, s));
+            if (fourier) {
+                const int rc2 = fourier_apply(set, k, mixed, s);
+                if (rc2) return rc2;
+            }
             HIP_TRY(launch_prereduce_rz(set, s));
         }
         return SYLV_OK;
@@ -1118,7 +1203,7 @@ bool make_kh_layout(const sylv_sep_problem *p, int decouple, const sylv_pcg_opts
     sylv_problem q[kMaxK];
     kh_problems(p, reinterpret_cast<const double *>(kAlign), q);
     Layout S;
-    make_layout(q, decouple ? p->k : 1, 1, true, S);
+    make_layout(q, decouple ? p->k : 1, 1, true, S, o ? o->precond : SYLV_PC_BLOCK);
     (void)o;
     L.total = align_up(off + S.total);
     return true;
@@ -1317,7 +1402,7 @@ int solve_noalloc_impl(const sylv_problem *probs, int nprob, int nrhs, const dou
     for (int g = 0; g < nprob; ++g)
         if (!check_problem(&probs[g], g)) return SYLV_E_INVALID;
     Layout L;
-    make_layout(probs, nprob, nrhs, true, L);
+    make_layout(probs, nprob, nrhs, true, L, opts->precond);
     if (L.total > SYLV_NOALLOC_SCRATCH_BYTES) {
         set_err("the batch needs %zu bytes of workspace; the no-allocation solve has %zu "
                 "(use sylv_pcg_solve with a caller workspace)",
@@ -1461,7 +1546,7 @@ size_t sylv_workspace_bytes(const sylv_problem *probs, int32_t nprob, int32_t nr
         if (nprob != 1) return 0;
         make_layout(probs, 1, 1, false, L);
     } else {
-        make_layout(probs, nprob, nrhs, true, L);
+        make_layout(probs, nprob, nrhs, true, L, opts->precond);
     }
     return L.total;
 }
@@ -1469,7 +1554,11 @@ size_t sylv_workspace_bytes(const sylv_problem *probs, int32_t nprob, int32_t nr
 int sylv_prepare(const sylv_problem *prob, int32_t precond, void *ws, size_t ws_bytes,
                  void *stream) {
     if (!check_problem(prob, 0)) return SYLV_E_INVALID;
-    if (precond < SYLV_PC_NONE || precond > SYLV_PC_BLOCK) { set_err("bad precond"); return SYLV_E_INVALID; }
+    if (precond < SYLV_PC_NONE || precond > SYLV_PC_FOURIER) { set_err("bad precond"); return SYLV_E_INVALID; }
+    if (precond == SYLV_PC_FOURIER && !fp_grid(*prob)) {
+        set_err("the Fourier preconditioner needs a periodic grid whose sides are powers of two in [4, 4096]");
+        return SYLV_E_INVALID;
+    }
     Layout L;
     make_layout(prob, 1, 1, false, L);
     int rc = check_ws(ws, ws_bytes, L.total);
@@ -1515,7 +1604,12 @@ int sylv_precond(const sylv_problem *prob, int32_t dtype, int32_t precond, const
                  void *stream) {
     if (!check_problem(prob, 0)) return SYLV_E_INVALID;
     if (dtype != SYLV_F64 && dtype != SYLV_F32) { set_err("bad dtype"); return SYLV_E_INVALID; }
-    if (precond < SYLV_PC_NONE || precond > SYLV_PC_BLOCK) { set_err("bad precond"); return SYLV_E_INVALID; }
+    if (precond < SYLV_PC_NONE || precond > SYLV_PC_FOURIER) { set_err("bad precond"); return SYLV_E_INVALID; }
+    if (precond == SYLV_PC_FOURIER) {
+        char why[200];
+        if (prob->boundary != SYLV_BC_PERIODIC) { set_err("the Fourier preconditioner needs a periodic grid"); return SYLV_E_INVALID; }
+        if (!fp_supported((int)prob->ny, (int)prob->nx, prob->k, dtype, why, sizeof(why))) { set_err("%s", why); return SYLV_E_INVALID; }
+    }
     if (!R || !Z || nrhs < 1) { set_err("null R/Z or nrhs < 1"); return SYLV_E_INVALID; }
     Layout L;
     make_layout(prob, 1, 1, false, L);
@@ -1527,6 +1621,42 @@ int sylv_precond(const sylv_problem *prob, int32_t dtype, int32_t precond, const
     }
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     char *base = reinterpret_cast<char *>(ws);
+    if (precond == SYLV_PC_FOURIER) {
+        // one instance without run state: its spectrum in the stand-alone region
+        Inst I = operator_inst(*prob, L.prob[0], base, precond);
+        I.nchunks = chunks_for(I.n_pix);
+        I.fs = reinterpret_cast<double *>(base + L.fs1);
+        I.fsym = reinterpret_cast<const double *>(base + L.prob[0].fsym);
+        I.lognx = __builtin_ctz((unsigned)I.nx);
+        I.logny = __builtin_ctz((unsigned)I.ny);
+        I.frb = fp_rows_per_block(I.nx, I.ny, dtype);
+        I.nfft = I.nx / 2 + 1;
+        I.partial = nullptr;
+        const int k = prob->k;
+        int pre[kPrefixArrays * 2] = {0, 0, 0, 0, 0, 0, 0, k * (I.ny / I.frb), 0, I.nfft};
+        HIP_TRY(launch_upload(base + L.table, &I, sizeof(Inst), s));
+        HIP_TRY(launch_upload(base + L.tprefix, pre, sizeof(pre), s));
+        InstSet set;
+        memset(&set, 0, sizeof(set));
+        set.table = reinterpret_cast<const Inst *>(base + L.table);
+        set.tprefix = reinterpret_cast<const int *>(base + L.tprefix);
+        set.tprefix32 = set.tprefix + 2;
+        set.cprefix = set.tprefix32 + 2;
+        set.fprefa = set.cprefix + 2;
+        set.fprefb = set.fprefa + 2;
+        set.ninst = 1;
+        set.total_fa = pre[7];
+        set.total_fb = pre[9];
+        set.fourier = 1;
+        set.fp_lds_rows = fp_lds_bytes(0, I.nx, I.frb, dtype);
+        set.fp_lds_cols = fp_lds_bytes(1, I.ny, k, dtype);
+        const size_t es = dtype == SYLV_F64 ? 8 : 4, plane = (size_t)k * I.n_pix * es;
+        for (int r = 0; r < nrhs; ++r)
+            HIP_TRY(launch_fp_apply(set, k, dtype == SYLV_F32, -1,
+                                    static_cast<const char *>(R) + r * plane,
+                                    static_cast<char *>(Z) + r * plane, s));
+        return SYLV_OK;
+    }
     HIP_TRY(launch_precond_plain(reinterpret_cast<const Inst *>(base + L.table), prob->k, dtype,
                                  (int)(prob->ny * prob->nx), nrhs, R, Z, s));
     return SYLV_OK;

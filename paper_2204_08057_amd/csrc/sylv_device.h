@@ -211,6 +211,34 @@ __device__ __forceinline__ void consume(const double *partial, int nred, int slo
     for (int i = 0; i < NV; ++i) out[i] = (sm[i][0] + sm[i][1]) + (sm[i][2] + sm[i][3]);
 }
 
+// Two reduced quantities with different producers: slot a over na workgroup partials and slot b
+// over nb (one shared table and one barrier, like consume<2>).
+__device__ __forceinline__ void consume_pair(const double *partial, int nred, int slot_a, int na,
+                                             int slot_b, int nb, double (&out)[2]) {
+    __shared__ double sm[2][kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const GAS double *pp = gp(partial) + (size_t)(i ? slot_b : slot_a) * nred;
+        const int nblocks = i ? nb : na;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int b = threadIdx.x;
+        for (; b + 3 * kBlock < nblocks; b += 4 * kBlock) {
+            a0 += pp[b];
+            a1 += pp[b + kBlock];
+            a2 += pp[b + 2 * kBlock];
+            a3 += pp[b + 3 * kBlock];
+        }
+        for (; b < nblocks; b += kBlock) a0 += pp[b];
+        double s = (a0 + a1) + (a2 + a3);
+        s = wave_sum(s);
+        if (lane == 0) sm[i][wid] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i) out[i] = (sm[i][0] + sm[i][1]) + (sm[i][2] + sm[i][3]);
+}
+
 __device__ __forceinline__ bool finite_d(double v) { return isfinite(v); }
 
 // ---- vector access helpers (clang vector types: usable in the global address space) --------

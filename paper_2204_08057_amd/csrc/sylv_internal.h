@@ -19,8 +19,10 @@ constexpr int kChunk = 1024;     // pixels per workgroup in streaming kernels (4
 // one value per producing workgroup).  A kernel that needs a reduced value re-reduces the
 // producer's partials itself, in a fixed order, at its start: kernel boundaries make them
 // visible without any device-wide fence, and every workgroup obtains bitwise the same scalar.
-enum Slot { SLOT_PQ = 0, SLOT_RZ = 1, SLOT_RR = 2, SLOT_RES_RR = 3, SLOT_RES_BB = 4 };
-constexpr int kNumSlots = 5;
+// SLOT_FRZ: <r, z> of the Fourier preconditioner, one partial per column workgroup of its
+// column pass (the update and start kernels then leave SLOT_RZ at zero).
+enum Slot { SLOT_PQ = 0, SLOT_RZ = 1, SLOT_RR = 2, SLOT_RES_RR = 3, SLOT_RES_BB = 4, SLOT_FRZ = 5 };
+constexpr int kNumSlots = 6;
 constexpr int kMaxRestarts = 3;   // residual replacements of a float64 run
 constexpr int kUploadWords = 512; // 32-bit words per table-upload launch (2 KiB of arguments)
 constexpr int kMaxFixedIters = 65536;   // iterations one fixed-schedule call may queue
@@ -102,6 +104,12 @@ struct Inst {
     DevState *st;        // float64 run (or outer refinement state)
     DevState *st_in;     // float32 inner run
     double *partial;     // [kNumSlots][nred]
+    // Fourier preconditioner (pc == SYLV_PC_FOURIER, periodic grids with power-of-two sides)
+    double *fs;          // half spectrum S[k][nx/2 + 1][ny], complex (float64 or float32 pairs)
+    const double *fsym;  // Mbar [kMaxK][kMaxK], kappa_j^2 [kMaxK], tau_j [kMaxK]
+    int32_t lognx, logny;
+    int32_t frb;         // grid rows per workgroup of the row passes
+    int32_t nfft;        // column workgroups = nx/2 + 1 (partials of <r, z>)
 };
 
 // Launch-time view of the instances: a device table plus prefix sums that map a flat
@@ -120,6 +128,12 @@ struct InstSet {
     int bc;               // SYLV_BC_* of every instance (face grids use 2 rows per lane)
     int stream;           // 1: the working set exceeds the last-level cache, so the CG kernels
                           // stream their once-touched planes with non-temporal accesses
+    // Fourier preconditioner: prefix sums of the row-pass and column-pass workgroups
+    const int *fprefa, *fprefb;
+    int total_fa, total_fb;
+    int fourier;          // pc == SYLV_PC_FOURIER
+    size_t fp_lds_rows, fp_lds_cols;  // dynamic LDS of the row and column passes (largest over
+                                      // the set's instances)
 };
 
 inline int packed_size(int k) { return k * (k + 1) / 2; }
@@ -186,6 +200,24 @@ hipError_t launch_rhs(const double *W, const double *Y, const double *A, int f, 
                       const double *bext, double *b, int k, hipStream_t s);
 hipError_t launch_apply_plain(const Inst *table0, int k, int dtype, int rows, int bc, int stream,
                               int ny, int nx, int nrhs, const void *in, void *out, hipStream_t s);
+// ---- Fourier preconditioner (sylv_fourier.hip) ------------------------------------------------
+// Supported shapes: periodic, ny and nx powers of two in [4, 4096], k x ny within the column
+// pass's LDS (why: the reason otherwise).
+bool fp_supported(int ny, int nx, int k, int dtype, char *why, size_t why_len);
+int fp_rows_per_block(int nx, int ny, int dtype);
+size_t fp_setup_partials(int n_pix, int f);
+// Mbar, kappa^2 and tau of a problem into fsym (part: fp_setup_partials doubles of scratch).
+hipError_t launch_fp_setup(const double *W, const double *A, int f, int k, int n_pix,
+                           const double *coef, double *part, double *fsym, hipStream_t s);
+// z = Fourier preconditioner of r for every instance of the set, in float32 (f32) or float64;
+// inner = 1: the float32 inner runs of the mixed path, 0: the float64 runs, -1: the stand-alone
+// preconditioner (one instance without run state: r read from rin, z written to zout).
+hipError_t launch_fp_apply(const InstSet &set, int k, int f32, int inner, const void *rin,
+                           void *zout, hipStream_t s);
+// Dynamic LDS bytes of a row pass (pass 0: m rows of length n) or of the column pass (pass 1:
+// m components of length n) in precision dtype.
+size_t fp_lds_bytes(int pass, int n, int m, int dtype);
+
 // Working sets above this many bytes are streamed past the last-level cache (256 MB on MI355X).
 constexpr double kStreamBytes = 256.0 * (1 << 20);
 hipError_t launch_precond_plain(const Inst *table0, int k, int dtype, int n_pix, int nrhs,

@@ -360,7 +360,12 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
     T beta = 0;
     if constexpr (MODE == AM_CG) {
         double s[2];
-        consume<2>(I.partial, I.nred, SLOT_RZ, I.pre ? 1 : I.nchunks, s);
+        if (I.pc == SYLV_PC_FOURIER && !I.pre) {
+            // <r, z> from the Fourier preconditioner's column pass, ||r||^2 from the update
+            consume_pair(I.partial, I.nred, SLOT_FRZ, I.nfft, SLOT_RR, I.nchunks, s);
+        } else {
+            consume<2>(I.partial, I.nred, SLOT_RZ, I.pre ? 1 : I.nchunks, s);
+        }
         const double rz = s[0], rr = s[1];
         // float64 runs stop against ||b - G x0|| (threshold set by the initial residual pass,
         // also across restarts); a float32 inner run against its own starting residual
@@ -645,14 +650,21 @@ __global__ __launch_bounds__(kBlock) void k_update(const Inst *__restrict__ tab,
                 for (int e = 0; e < 4; ++e) rv[j][e] -= alpha * qv[j][e];
                 bst4<SA>(r + (size_t)j * n_pix, np, (uint32_t)p0, rv[j]);
             }
-            precond_cg_vec4<T, K, LA>(pc, P, n_pix, p0, rv, zv);
+            if (pc == SYLV_PC_FOURIER) {   // z and <r, z> come from the Fourier passes
 #pragma unroll
-            for (int j = 0; j < K; ++j) {
-                bst4<SA>(z + (size_t)j * n_pix, np, (uint32_t)p0, zv[j]);
+                for (int j = 0; j < K; ++j)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    rz += (double)rv[j][e] * (double)zv[j][e];
-                    rr += (double)rv[j][e] * (double)rv[j][e];
+                    for (int e = 0; e < 4; ++e) rr += (double)rv[j][e] * (double)rv[j][e];
+            } else {
+                precond_cg_vec4<T, K, LA>(pc, P, n_pix, p0, rv, zv);
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    bst4<SA>(z + (size_t)j * n_pix, np, (uint32_t)p0, zv[j]);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        rz += (double)rv[j][e] * (double)zv[j][e];
+                        rr += (double)rv[j][e] * (double)rv[j][e];
+                    }
                 }
             }
         } else {
@@ -664,6 +676,11 @@ __global__ __launch_bounds__(kBlock) void k_update(const Inst *__restrict__ tab,
                     const size_t o = (size_t)j * n_pix + pix;
                     rs[j] = r[o] - alpha * q[o];
                     r[o] = rs[j];
+                }
+                if (pc == SYLV_PC_FOURIER) {
+#pragma unroll
+                    for (int j = 0; j < K; ++j) rr += (double)rs[j] * (double)rs[j];
+                    continue;
                 }
                 precond_cg_pixel<T, K>(pc, P, n_pix, pix, rs, zs);
 #pragma unroll
@@ -738,14 +755,21 @@ __global__ __launch_bounds__(kBlock) void k_pinit(const Inst *__restrict__ tab,
                 bst4(gp(I.d32) + o, np, (uint32_t)p0, zero4);
             }
         }
-        precond_cg_vec4<T, K>(pc, P, n_pix, p0, rv, zv);
+        if (pc == SYLV_PC_FOURIER) {   // z and <r, z> come from the Fourier passes
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            bst4(z + (size_t)j * n_pix, np, (uint32_t)p0, zv[j]);
+            for (int j = 0; j < K; ++j)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                rz += (double)rv[j][e] * (double)zv[j][e];
-                rr += (double)rv[j][e] * (double)rv[j][e];
+                for (int e = 0; e < 4; ++e) rr += (double)rv[j][e] * (double)rv[j][e];
+        } else {
+            precond_cg_vec4<T, K>(pc, P, n_pix, p0, rv, zv);
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                bst4(z + (size_t)j * n_pix, np, (uint32_t)p0, zv[j]);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    rz += (double)rv[j][e] * (double)zv[j][e];
+                    rr += (double)rv[j][e] * (double)rv[j][e];
+                }
             }
         }
     } else {
@@ -760,6 +784,11 @@ __global__ __launch_bounds__(kBlock) void k_pinit(const Inst *__restrict__ tab,
                     rr_out[o] = rv[j];
                     gp(I.d32)[o] = 0.0f;
                 }
+            }
+            if (pc == SYLV_PC_FOURIER) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) rr += (double)rv[j] * (double)rv[j];
+                continue;
             }
             precond_cg_pixel<T, K>(pc, P, n_pix, pix, rv, zv);
 #pragma unroll
@@ -861,7 +890,15 @@ __global__ __launch_bounds__(kBlock) void k_prereduce(const Inst *__restrict__ t
     if (!I.pre) return;
     const int nb = count == 0 ? I.ntiles : count == 1 ? I.ntiles32 : I.nchunks;
     double v[NV];
-    consume<NV>(I.partial, I.nred, slot0, nb, v);   // every read precedes its final barrier
+    if (NV == 2 && slot0 == SLOT_RZ && I.pc == SYLV_PC_FOURIER) {
+        // <r, z> from the Fourier column pass, ||r||^2 from the streaming kernel
+        double w[2];
+        consume_pair(I.partial, I.nred, SLOT_FRZ, I.nfft, SLOT_RR, nb, w);
+        v[0] = w[0];
+        v[NV - 1] = w[1];
+    } else {
+        consume<NV>(I.partial, I.nred, slot0, nb, v);   // every read precedes its final barrier
+    }
     if (threadIdx.x == 0) {
         GAS double *pp = gp(I.partial);
 #pragma unroll

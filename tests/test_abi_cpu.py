@@ -256,3 +256,31 @@ def test_noalloc_solve_refusals_before_any_device_call():
     bad = fake_problem(16, 16, k=9)
     assert L.sylv_pcg_solve_noalloc(ctypes.byref(bad), 1, 1, FAKE, None, FAKE,
                                     ctypes.byref(fixed), FAKE, None) == bd.SYLV_E_INVALID
+
+
+def test_fourier_preconditioner_refusals_before_any_device_call():
+    """The Fourier preconditioner takes periodic grids whose sides are powers of two in
+    [4, 4096], columns that fit its LDS pass, and independent CG; anything else is refused before
+    any work is enqueued (FAKE pointers are never read)."""
+    L = sy.lib()
+    st = FAKE
+    fourier = bd._Opts(1e-8, 10, 0, 0.0, 0, bd.SYLV_PC_FOURIER, 0, 0)
+    for p in (fake_problem(24, 32), fake_problem(32, 2), fake_problem(16, 16, boundary=1),
+              fake_problem(8192, 8), fake_problem(4096, 64, k=8)):
+        rc = L.sylv_pcg_solve(ctypes.byref(p), 1, 1, FAKE, None, FAKE, ctypes.byref(fourier),
+                              st, FAKE, 1 << 40, None)
+        assert rc == bd.SYLV_E_INVALID and len(L.sylv_last_error()) > 0
+    block = bd._Opts(1e-8, 10, 0, 0.0, 0, bd.SYLV_PC_FOURIER, 0, 1, 0, 0, 2, 0)
+    rc = L.sylv_pcg_solve(ctypes.byref(fake_problem(16, 16)), 1, 2, FAKE, None, FAKE,
+                          ctypes.byref(block), st, FAKE, 1 << 40, None)
+    assert rc == bd.SYLV_E_INVALID and b"block CG" in L.sylv_last_error()
+    # the stand-alone application refuses the same shapes
+    rc = L.sylv_precond(ctypes.byref(fake_problem(24, 32)), 0, bd.SYLV_PC_FOURIER, FAKE,
+                        FAKE * 2, 1, 1, FAKE, 1 << 40, None)
+    assert rc == bd.SYLV_E_INVALID
+    # the solve workspace holds one half spectrum per right-hand side
+    p = fake_problem(64, 64)
+    plain = bd._Opts(1e-8, 10, 0, 0.0, 0, 2, 0, 0)
+    n0 = L.sylv_workspace_bytes(ctypes.byref(p), 1, 2, ctypes.byref(plain))
+    n1 = L.sylv_workspace_bytes(ctypes.byref(p), 1, 2, ctypes.byref(fourier))
+    assert n1 - n0 >= 2 * 16 * 3 * 33 * 64

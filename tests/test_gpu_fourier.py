@@ -1,0 +1,160 @@
+"""GPU parity of the Fourier preconditioner (the operator with pixel-mean weights, inverted mode
+by mode through the 2-D DFT) against the CPU oracle, through the C ABI: the stand-alone
+application in float64 and float32 against the oracle's numpy-FFT application, and conjugate
+gradient solves preconditioned by it against dense Cholesky, the oracle's PCG with the same
+preconditioner (iteration counts) and, at 1024^2, the oracle's PCG reference solution."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import paper_2204_08057_amd as sy  # noqa: E402
+from oracle import pcg as opcg  # noqa: E402
+from oracle import solve as osv  # noqa: E402
+from workloads import make_problem, random_maps, workload  # noqa: E402
+
+DEV = "cuda"
+
+
+def say(*a):
+    print("[fourier]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+# (ny, nx, k, f): odd and even powers of two (radix-2 last stage), rectangular, tiny and every k
+SHAPES = [(4, 4, 1, 2), (8, 16, 3, 5), (16, 8, 2, 3), (32, 64, 4, 9), (64, 64, 3, 6),
+          (128, 32, 8, 16), (4, 256, 5, 4), (512, 8, 2, 3), (16, 16, 6, 7), (8, 32, 7, 8)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_preconditioner_application_matches_oracle(shape):
+    ny, nx, k, f = shape
+    p = make_problem(ny, nx, k, f, seed=5000 + ny + nx, noise="hetero", mask_frac=0.1)
+    dp = sy.DeviceProblem.from_numpy(p)
+    R = random_maps(p, seed=5001, nrhs=2)
+    ref = np.stack([opcg.fourier_preconditioner(p)(R[i]) for i in range(2)])
+    say("application", shape)
+    Z64 = host(sy.precond(dp, dev(R), kind=sy.SYLV_PC_FOURIER))
+    assert rel(Z64, ref) <= 1e-12
+    Z32 = host(sy.precond(dp, dev(R, torch.float32), kind=sy.SYLV_PC_FOURIER))
+    assert rel(Z32, ref) <= 2e-5
+
+
+@pytest.mark.parametrize("precision,tol,bound", [(sy.SYLV_PREC_F64, 1e-12, 1e-8),
+                                                 (sy.SYLV_PREC_MIXED, 1e-11, 1e-7)])
+@pytest.mark.parametrize("shape", [(8, 16, 3, 5), (32, 64, 4, 9), (16, 16, 6, 7), (64, 32, 2, 3)])
+def test_solve_matches_dense(shape, precision, tol, bound):
+    ny, nx, k, f = shape
+    p = make_problem(ny, nx, k, f, seed=5100 + ny * nx, noise="hetero", mask_frac=0.1)
+    dp = sy.DeviceProblem.from_numpy(p)
+    say("solve", shape, precision)
+    X, st = sy.pcg_solve(dp, Y=dev(p.Y), opts=sy.SolveOptions(
+        tol=tol, precision=precision, precond=sy.SYLV_PC_FOURIER))
+    assert st[0]["status"] == 0, st
+    assert rel(host(X).reshape(p.k, p.n_pix), osv.solve_dense(p)) <= bound
+
+
+@pytest.mark.parametrize("shape", [(32, 64, 4, 9), (64, 64, 3, 6), (128, 128, 3, 9)])
+def test_iteration_count_matches_oracle(shape):
+    """Float64 runs to 1e-8 take the oracle's iteration count with the same preconditioner to
+    within 1 (same algorithm; reductions round differently)."""
+    ny, nx, k, f = shape
+    p = make_problem(ny, nx, k, f, seed=5200 + ny, noise="hetero")
+    ref = opcg.pcg(p, tol=1e-8, max_iter=2000, precond="fourier")
+    say("iterations", shape, "oracle", ref["iters"])
+    dp = sy.DeviceProblem.from_numpy(p)
+    X, st = sy.pcg_solve(dp, Y=dev(p.Y), opts=sy.SolveOptions(tol=1e-8,
+                                                              precond=sy.SYLV_PC_FOURIER))
+    assert st[0]["status"] == 0, st
+    say("  gpu", st[0]["iters"])
+    assert abs(st[0]["iters"] - ref["iters"]) <= 1
+
+
+def test_homoscedastic_grid_solves_in_one_iteration():
+    """With pixel-independent weights the preconditioner is G^-1 itself: one iteration."""
+    p = make_problem(64, 32, 3, 6, seed=5300, noise="homo")
+    dp = sy.DeviceProblem.from_numpy(p)
+    X, st = sy.pcg_solve(dp, Y=dev(p.Y), opts=sy.SolveOptions(tol=1e-10,
+                                                              precond=sy.SYLV_PC_FOURIER))
+    assert st[0]["status"] == 0 and st[0]["iters"] <= 2, st
+    assert rel(host(X).reshape(p.k, p.n_pix), osv.solve_fft(p)) <= 1e-9
+
+
+def test_batch_of_uneven_grids_and_right_hand_sides():
+    probs = [make_problem(32, 64, 3, 5, seed=5400, noise="hetero"),
+             make_problem(16, 16, 3, 5, seed=5401, noise="hetero", mask_frac=0.1)]
+    nrhs = 2
+    rng = np.random.default_rng(5402)
+    Bx = [rng.standard_normal((nrhs, q.k, q.n_pix)) for q in probs]
+    dps = [sy.DeviceProblem.from_numpy(q) for q in probs]
+    say("batch")
+    for precision, tol, bound in ((sy.SYLV_PREC_F64, 1e-12, 1e-8),
+                                  (sy.SYLV_PREC_MIXED, 1e-11, 1e-7)):
+        X, st = sy.pcg_solve(dps, Y=torch.cat([dev(q.Y.ravel()) for q in probs]),
+                             Bextra=torch.cat([dev(b.ravel()) for b in Bx]), nrhs=nrhs,
+                             opts=sy.SolveOptions(tol=tol, precision=precision,
+                                                  precond=sy.SYLV_PC_FOURIER))
+        assert all(s["status"] == 0 for s in st), st
+        x = host(X)
+        off = 0
+        from oracle import operator as op
+        for g, q in enumerate(probs):
+            for r in range(nrhs):
+                xs = osv.solve_dense(q, b=op.rhs(q) + Bx[g][r])
+                assert rel(x[off:off + q.k * q.n_pix].reshape(q.k, q.n_pix), xs) <= bound
+                off += q.k * q.n_pix
+
+
+@pytest.mark.parametrize("precision,tol,bound", [(sy.SYLV_PREC_F64, 1e-12, 1e-8),
+                                                 (sy.SYLV_PREC_MIXED, 1e-11, 1e-7)])
+def test_het_1024_whole_solution_vs_oracle(precision, tol, bound):
+    """The timing workload (1024^2, k = 3, f = 9, heteroscedastic) solved with the Fourier
+    preconditioner, whole vector against the oracle's block-Jacobi PCG to 1e-13."""
+    global _HET
+    try:
+        p, ref = _HET
+    except NameError:
+        p = workload("het_1024")[0]
+        say("oracle PCG het_1024 to 1e-13 (CPU)")
+        ref = opcg.pcg(p, tol=1e-13, max_iter=5000, precond="block")["x"]
+        _HET = (p, ref)
+    say("het_1024", precision)
+    dp = sy.DeviceProblem.from_numpy(p)
+    X, st = sy.pcg_solve(dp, Y=dev(p.Y), opts=sy.SolveOptions(
+        tol=tol, precision=precision, precond=sy.SYLV_PC_FOURIER))
+    assert st[0]["status"] == 0, st
+    say("  iterations", st[0]["iters"], "outer", st[0]["outer"])
+    assert rel(host(X).reshape(p.k, p.n_pix), ref) <= bound
+
+
+def test_unsupported_shapes_are_refused():
+    for kw in (dict(ny=24, nx=32), dict(ny=32, nx=2), dict(ny=16, nx=16, boundary="face")):
+        boundary = kw.pop("boundary", "periodic")
+        p = make_problem(kw["ny"], kw["nx"], 3, 4, seed=5500, noise="hetero", boundary=boundary)
+        dp = sy.DeviceProblem.from_numpy(p)
+        with pytest.raises(sy.SylvError):
+            sy.pcg_solve(dp, Y=dev(p.Y), opts=sy.SolveOptions(precond=sy.SYLV_PC_FOURIER))
+    p = make_problem(16, 16, 3, 4, seed=5501, noise="hetero")
+    dp = sy.DeviceProblem.from_numpy(p)
+    with pytest.raises(sy.SylvError):   # block CG takes the per-pixel preconditioners only
+        sy.pcg_solve([dp], Bextra=dev(np.ones(2 * 3 * 256)), nrhs=2,
+                     opts=sy.SolveOptions(precond=sy.SYLV_PC_FOURIER, block=1))
