@@ -329,6 +329,32 @@ def apply_launcher(problem: DeviceProblem, X, Y, ws):
     return launch
 
 
+def precond_launcher(problem: DeviceProblem, R, Z, kind: int, ws):
+    """A zero-argument callable that launches Z = M^-1 R (preconditioner `kind`) on the current
+    stream with every argument marshalled once, for an operator already prepared in `ws` with
+    that preconditioner (`prepare(problem, kind)`).  R and Z as for `precond`."""
+    torch = _torch()
+    if R.dtype not in (torch.float64, torch.float32) or Z.dtype != R.dtype:
+        raise ValueError("R and Z must both be float64 or both float32")
+    if R.shape != Z.shape or R.shape[-2:] != (problem.k, problem.n_pix):
+        raise ValueError(f"R, Z shapes {tuple(R.shape)}, {tuple(Z.shape)} != (..., {problem.k}, "
+                         f"{problem.n_pix})")
+    dtype = SYLV_F64 if R.dtype == torch.float64 else SYLV_F32
+    nrhs = 1 if R.dim() == 2 else R.shape[0]
+    ps = problem.c_struct()
+    fn = lib().sylv_precond
+    args = (ctypes.byref(ps), dtype, kind, _ptr(R), _ptr(Z), nrhs, 1, _ptr(ws), ws.numel(),
+            _stream())
+
+    def launch():
+        rc = fn(*args)
+        if rc:
+            _check(rc)
+
+    launch.keep = (ps, R, Z, ws)
+    return launch
+
+
 def precond(problem: DeviceProblem, R, kind: int = SYLV_PC_BLOCK, ws=None,
             prepared: bool = False):
     torch = _torch()

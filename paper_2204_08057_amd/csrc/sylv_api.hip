@@ -165,7 +165,7 @@ bool make_layout(const sylv_problem *probs, int nprob, int nrhs, bool solve, Lay
         P.P64 = off;  off = align_up(off + sizeof(double) * mk * n);
         P.P32 = off;  off = align_up(off + sizeof(float) * mk * n);
         P.P16 = off;  off = align_up(off + sizeof(unsigned short) * mk * n);
-        P.fsym = off; off = align_up(off + sizeof(double) * (kMaxK * kMaxK + 2 * kMaxK));
+        P.fsym = off; off = align_up(off + fp_table_bytes((int)probs[g].nx, (int)probs[g].ny));
         P.fpart = off; off = align_up(off + sizeof(double) * fp_setup_partials((int)n, probs[g].f));
     }
     if (!solve && nprob == 1 && fp_grid(probs[0])) {
@@ -278,7 +278,7 @@ int prepare_operator(const sylv_problem &p, const ProbLayout &P, char *base, int
                          reinterpret_cast<float *>(base + P.P32),
                          reinterpret_cast<unsigned short *>(base + P.P16), exact, p.k, s));
     if (pc == SYLV_PC_FOURIER)
-        HIP_TRY(launch_fp_setup(p.W, p.A, p.f, p.k, (int)(p.ny * p.nx), coef,
+        HIP_TRY(launch_fp_setup(p.W, p.A, p.f, p.k, (int)p.nx, (int)p.ny, coef,
                                 reinterpret_cast<double *>(base + P.fpart),
                                 reinterpret_cast<double *>(base + P.fsym), s));
     return SYLV_OK;
@@ -578,6 +578,7 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
     int *tpre = pre.data(), *tpre32 = tpre + (ninst + 1), *cpre = tpre32 + (ninst + 1);
     int *fpa = cpre + (ninst + 1), *fpb = fpa + (ninst + 1);
     size_t fp_lds_rows = 0, fp_lds_cols = 0;
+    int fp_cols_gtw = 0, fp_rmask_x = 0, fp_rmask_y = 0;
     size_t xoff = 0, yoff = 0;
     int any_pre = 0;
     const int pre_min = prereduce_min();
@@ -619,12 +620,15 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
                 I.lognx = __builtin_ctz((unsigned)I.nx);
                 I.logny = __builtin_ctz((unsigned)I.ny);
                 I.frb = fp_rows_per_block(I.nx, I.ny, mixed ? SYLV_F32 : SYLV_F64);
-                I.nfft = I.nx / 2 + 1;
+                I.nfft = I.nx / 2;
                 nfa = k * (I.ny / I.frb);
                 nfb = I.nfft;
                 const int dt = mixed ? SYLV_F32 : SYLV_F64;
                 fp_lds_rows = std::max(fp_lds_rows, fp_lds_bytes(0, I.nx, I.frb, dt));
                 fp_lds_cols = std::max(fp_lds_cols, fp_lds_bytes(1, I.ny, k, dt));
+                fp_cols_gtw |= fp_cols_global_twiddles(I.ny, k, dt) ? 1 : 0;
+                fp_rmask_x |= fp_radix_bit(I.lognx);
+                fp_rmask_y |= fp_radix_bit(I.logny);
             }
             I.pre = std::max(std::max(I.ntiles, I.ntiles32), I.nchunks) > pre_min ? 1 : 0;
             any_pre |= I.pre;
@@ -660,6 +664,9 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
     set.total_fb = fpb[ninst];
     set.fp_lds_rows = fp_lds_rows;
     set.fp_lds_cols = fp_lds_cols;
+    set.fp_cols_gtw = fp_cols_gtw;
+    set.fp_rmask_x = fp_rmask_x;
+    set.fp_rmask_y = fp_rmask_y;
     {
         // bytes the CG loop keeps touching: per problem the mixing blocks and the bfloat16
         // preconditioner factor, per instance x, r, z, two directions and q
@@ -1630,7 +1637,7 @@ int sylv_precond(const sylv_problem *prob, int32_t dtype, int32_t precond, const
         I.lognx = __builtin_ctz((unsigned)I.nx);
         I.logny = __builtin_ctz((unsigned)I.ny);
         I.frb = fp_rows_per_block(I.nx, I.ny, dtype);
-        I.nfft = I.nx / 2 + 1;
+        I.nfft = I.nx / 2;
         I.partial = nullptr;
         const int k = prob->k;
         int pre[kPrefixArrays * 2] = {0, 0, 0, 0, 0, 0, 0, k * (I.ny / I.frb), 0, I.nfft};
@@ -1650,6 +1657,9 @@ int sylv_precond(const sylv_problem *prob, int32_t dtype, int32_t precond, const
         set.fourier = 1;
         set.fp_lds_rows = fp_lds_bytes(0, I.nx, I.frb, dtype);
         set.fp_lds_cols = fp_lds_bytes(1, I.ny, k, dtype);
+        set.fp_cols_gtw = fp_cols_global_twiddles(I.ny, k, dtype) ? 1 : 0;
+        set.fp_rmask_x = fp_radix_bit(I.lognx);
+        set.fp_rmask_y = fp_radix_bit(I.logny);
         const size_t es = dtype == SYLV_F64 ? 8 : 4, plane = (size_t)k * I.n_pix * es;
         for (int r = 0; r < nrhs; ++r)
             HIP_TRY(launch_fp_apply(set, k, dtype == SYLV_F32, -1,

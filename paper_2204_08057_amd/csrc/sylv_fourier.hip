@@ -16,16 +16,24 @@
 //      S[j][c][y], c in [0, nx/2] (the rows of S are the columns of the grid's spectrum);
 //   B  per column c of the half spectrum, all k components at once: forward FFT along y (length
 //      ny), the k x k solve of every mode (its block formed and factored in registers), the
-//      <r, z> partial by Parseval's identity, inverse FFT along y, back into S;
+//      <r, z> partial by Parseval's identity, inverse FFT along y, back into S.  The columns
+//      c = 0 and c = nx/2 are real (sums of real rows with weights +-1) and travel together as
+//      one complex column, so that the pass has nx/2 workgroups;
 //   C  per row: the full row spectrum from the half (Hermitian symmetry of a real row), inverse
 //      FFT (length nx), the real part scaled by 1 / (nx ny) into z.
-// Every FFT is a Stockham radix-4 (radix-2 for an odd power) transform in LDS with a twiddle table
-// computed per workgroup from sincospi in float64.  T = float for the inner runs of the mixed
-// path, double for float64 runs.
+// Every FFT is a Stockham transform in LDS whose butterflies are DFTs of 16 points (8, 4 or 2 for
+// the last stage) in registers; the first stage reads global memory and the last writes it where
+// the layout allows.  Its twiddles come from per-stage tables made once at set-up (with the
+// per-mode Laplacian eigenvalues) and copied into LDS, so a butterfly reads each twiddle once,
+// from consecutive entries.  The row passes transform two real rows as one complex row.
+// T = float for the inner runs of the mixed path, double for float64 runs.
 
 #include "sylv_device.h"
 
 #include <stdio.h>
+
+#include <algorithm>
+#include <type_traits>
 
 namespace sylv {
 namespace {
@@ -44,313 +52,516 @@ template <typename T>
 __device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b) {
     return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
-// a * conj(b)
-template <typename T>
-__device__ __forceinline__ Cx<T> cmulc(Cx<T> a, Cx<T> b) {
-    return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
-}
 
 // LDS index with one padding slot per 32 entries (breaks the power-of-two strides of the
 // Stockham stores across banks).
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 5); }
 __host__ __device__ constexpr int lds_entries(int n) { return n + (n >> 5) + 1; }
 
-// tw[m] = exp(-2 pi i m / n) for m in [0, n/2); W^m for m >= n/2 is -tw[m - n/2].
-template <typename T>
-__device__ __forceinline__ void make_twiddles(Cx<T> *tw, int n) {
-    for (int m = threadIdx.x; m < n / 2; m += kBlock) {
-        double s, c;
-        sincospi(-2.0 * (double)m / (double)n, &s, &c);
-        tw[m] = {(T)c, (T)s};
-    }
+// Workgroup shape of the three passes: 512 threads (8 wavefronts), and at most kFftCap complex
+// entries of transform data per workgroup (64 KB in float32, 128 KB in float64; the device
+// allows 160 KB of LDS per workgroup).  A thread holds at most kRegPts complex values between two
+// LDS exchanges.
+constexpr int kFT = 512;
+constexpr int kRegPts = 16;
+constexpr int kFftCap = kFT * kRegPts;
+constexpr size_t kMaxLds = 163840;
+static_assert(kFT == 8 * 64, "fp_block_sum sums eight wavefronts");
+
+// ---- set-up tables (per problem, after the symbol block) --------------------------------------
+// In doubles from the start of the problem's Fourier region:
+//   [0, kSymDoubles)   Mbar [kMaxK][kMaxK], kappa_j^2 [kMaxK], tau_j [kMaxK]
+//   lamx[c] = 2 - 2 cos(2 pi c / nx), c in [0, nx/2];  lamy[v] = 2 - 2 cos(2 pi v / ny), v < ny
+//   Stockham twiddles for n = nx and n = ny, complex double, then complex float (n - 1 entries
+//   each, padded to n): stage s (radix R, ns = product of the earlier radices) holds
+//   W_(ns R)^(r kk) at [off_s + (r - 1) ns + kk], r in [1, R), kk in [0, ns).
+constexpr int kSymDoubles = kMaxK * kMaxK + 2 * kMaxK;
+__host__ __device__ constexpr size_t round4(size_t v) { return (v + 3) & ~(size_t)3; }
+struct FpTabs {
+    size_t lamx, lamy, twx64, twy64, twx32, twy32, total;   // offsets / total, in doubles
+};
+__host__ __device__ inline FpTabs fp_tabs(int nx, int ny) {
+    FpTabs t;
+    size_t o = round4(kSymDoubles);
+    t.lamx = o;  o = round4(o + nx / 2 + 1);
+    t.lamy = o;  o = round4(o + ny);
+    t.twx64 = o; o = round4(o + 2 * (size_t)nx);
+    t.twy64 = o; o = round4(o + 2 * (size_t)ny);
+    t.twx32 = o; o = round4(o + (size_t)nx);
+    t.twy32 = o; o = round4(o + (size_t)ny);
+    t.total = o;
+    return t;
 }
 template <typename T>
-__device__ __forceinline__ Cx<T> twiddle(const Cx<T> *tw, int idx, int n) {
-    idx &= n - 1;
-    const int h = n >> 1;
-    if (idx < h) return tw[idx];
-    const Cx<T> w = tw[idx - h];
-    return {-w.x, -w.y};
+__device__ __forceinline__ const Cx<T> *stage_table(const double *base, const FpTabs &t, bool x) {
+    if (sizeof(T) == 8) return reinterpret_cast<const Cx<T> *>(base + (x ? t.twx64 : t.twy64));
+    return reinterpret_cast<const Cx<T> *>(base + (x ? t.twx32 : t.twy32));
 }
 
-// In-place FFTs of `rows` sequences of length n (a power of two, 2 <= n <= 4096) held at
-// buf[lpad(row * n + i)], rows * n <= MT * 4 * kBlock.  INV = 1: the inverse transform
-// (conjugate twiddles), unnormalised.  Stockham autosort: each stage first reads the butterfly
-// inputs of all of the thread's tasks into registers (statically indexed), then, after a
-// barrier, writes the outputs in sorted order.
-template <typename T, int INV, int MT>
-__device__ void fft_lds(Cx<T> *buf, const Cx<T> *tw, int n, int logn, int rows) {
-    int ns = 1;
-    for (int lg = 0; lg < logn;) {
-        const bool r4 = logn - lg >= 2;
-        const int radix = r4 ? 4 : 2;
-        const int m = n / radix;                      // tasks per row
-        const int ntask = rows * m;
-        const int tstep = n / (ns * radix);           // W_(ns radix)^(r kk) = W_n^(r kk tstep)
-        Cx<T> v[4 * MT];
-        if (r4) {
+// log2 of the radix of the stage that starts at log2-position lg of a length-2^logn transform:
+// radix-16 stages, then one of radix fft_last_radix(logn).
+__host__ __device__ constexpr int stage_log_radix(int logn, int lg) {
+    return logn - lg >= 4 ? 4 : logn - lg;
+}
+__host__ __device__ constexpr int fft_last_radix(int logn) {
+    return (logn & 3) == 0 ? 16 : 1 << (logn & 3);
+}
+
+// ---- DFTs of R = 2, 4, 8, 16 points in registers, natural order in and out ----------------
+// Forward: X[k] = sum_j x[j] exp(-2 pi i j k / R); INV = 1 uses exp(+2 pi i j k / R).
+template <typename T, int INV>
+__device__ __forceinline__ Cx<T> mul_mi(Cx<T> a) {   // a * (-i) forward, a * (+i) inverse
+    return INV ? Cx<T>{-a.y, a.x} : Cx<T>{a.y, -a.x};
+}
+template <typename T, int INV>
+__device__ __forceinline__ Cx<T> mul_w8(Cx<T> a, int e) {   // a * W_8^e, e in 0..3
+    const T h = (T)0.70710678118654752440;                  // cos(pi/4)
+    switch (e) {
+        case 0: return a;
+        case 1: return INV ? Cx<T>{h * (a.x - a.y), h * (a.x + a.y)}
+                           : Cx<T>{h * (a.x + a.y), h * (a.y - a.x)};
+        case 2: return mul_mi<T, INV>(a);
+        default: return INV ? Cx<T>{-h * (a.x + a.y), h * (a.x - a.y)}
+                            : Cx<T>{h * (a.y - a.x), -h * (a.x + a.y)};
+    }
+}
+template <typename T, int INV>
+__device__ __forceinline__ void dft4(Cx<T> &a0, Cx<T> &a1, Cx<T> &a2, Cx<T> &a3) {
+    const Cx<T> s0 = cadd(a0, a2), d0 = csub(a0, a2);
+    const Cx<T> s1 = cadd(a1, a3), d1 = mul_mi<T, INV>(csub(a1, a3));
+    a0 = cadd(s0, s1);
+    a1 = cadd(d0, d1);
+    a2 = csub(s0, s1);
+    a3 = csub(d0, d1);
+}
+template <typename T, int R, int INV>
+__device__ __forceinline__ void dft(Cx<T> (&a)[R]) {
+    if constexpr (R == 2) {
+        const Cx<T> t = a[0];
+        a[0] = cadd(t, a[1]);
+        a[1] = csub(t, a[1]);
+    } else if constexpr (R == 4) {
+        dft4<T, INV>(a[0], a[1], a[2], a[3]);
+    } else if constexpr (R == 8) {
+        // even / odd halves (4 points each), then X[k] = E[k] + W_8^k O[k], X[k+4] = E[k] - ...
+        dft4<T, INV>(a[0], a[2], a[4], a[6]);
+        dft4<T, INV>(a[1], a[3], a[5], a[7]);
+        Cx<T> o[8];
 #pragma unroll
-            for (int q = 0; q < MT; ++q) {
-                const int t = threadIdx.x + q * kBlock;
-                if (t >= ntask) break;
-                const int row = t / m, j = t - row * m, kk = j & (ns - 1);
-                const int base = row * n + j;
-                Cx<T> a[4];
+        for (int k = 0; k < 4; ++k) {
+            const Cx<T> e = a[2 * k], w = mul_w8<T, INV>(a[2 * k + 1], k);
+            o[k] = cadd(e, w);
+            o[k + 4] = csub(e, w);
+        }
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    a[r] = buf[lpad(base + r * m)];
-                    if (r > 0 && kk > 0) {
-                        Cx<T> w = twiddle(tw, r * kk * tstep, n);
-                        if (INV) w.y = -w.y;
-                        a[r] = cmul(a[r], w);
-                    }
-                }
-                const Cx<T> s0 = cadd(a[0], a[2]), d0 = csub(a[0], a[2]);
-                const Cx<T> s1 = cadd(a[1], a[3]), e = csub(a[1], a[3]);
-                const Cx<T> d1 = INV ? Cx<T>{-e.y, e.x} : Cx<T>{e.y, -e.x};   // e * (-+i)
-                v[4 * q + 0] = cadd(s0, s1);
-                v[4 * q + 1] = cadd(d0, d1);
-                v[4 * q + 2] = csub(s0, s1);
-                v[4 * q + 3] = csub(d0, d1);
-            }
-        } else {
+        for (int k = 0; k < 8; ++k) a[k] = o[k];
+    } else {
+        static_assert(R == 16, "radix 2, 4, 8 or 16");
+        // 16 = 4 x 4: DFTs over j1 of x[4 j1 + j2], twiddle W_16^(j2 k1), DFTs over j2
+        const T c1 = (T)0.92387953251128675613, s1 = (T)0.38268343236508977173;   // pi/8
+        const T h = (T)0.70710678118654752440;
 #pragma unroll
-            for (int q = 0; q < 2 * MT; ++q) {
-                const int t = threadIdx.x + q * kBlock;
-                if (t >= ntask) break;
-                const int row = t / m, j = t - row * m, kk = j & (ns - 1);
-                const int base = row * n + j;
-                const Cx<T> a0 = buf[lpad(base)];
-                Cx<T> a1 = buf[lpad(base + m)];
-                if (kk > 0) {
-                    Cx<T> w = twiddle(tw, kk * tstep, n);
+        for (int j2 = 0; j2 < 4; ++j2) dft4<T, INV>(a[j2], a[4 + j2], a[8 + j2], a[12 + j2]);
+        // now a[4 k1 + j2] = Y[j2][k1]
+        const T sg = INV ? (T)1 : (T)-1;                       // sign of the sine
+        const Cx<T> w1 = {c1, sg * s1}, w2 = {h, sg * h}, w3 = {s1, sg * c1};
+        const Cx<T> w6 = {-h, sg * h}, w9 = {-c1, -sg * s1};
+        a[4 * 1 + 1] = cmul(a[4 * 1 + 1], w1);
+        a[4 * 1 + 2] = cmul(a[4 * 1 + 2], w2);
+        a[4 * 1 + 3] = cmul(a[4 * 1 + 3], w3);
+        a[4 * 2 + 1] = cmul(a[4 * 2 + 1], w2);
+        a[4 * 2 + 2] = mul_mi<T, INV>(a[4 * 2 + 2]);          // W_16^4
+        a[4 * 2 + 3] = cmul(a[4 * 2 + 3], w6);
+        a[4 * 3 + 1] = cmul(a[4 * 3 + 1], w3);
+        a[4 * 3 + 2] = cmul(a[4 * 3 + 2], w6);
+        a[4 * 3 + 3] = cmul(a[4 * 3 + 3], w9);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1)
+            dft4<T, INV>(a[4 * k1], a[4 * k1 + 1], a[4 * k1 + 2], a[4 * k1 + 3]);
+        // now a[4 k1 + k2] = X[k1 + 4 k2]: transpose the 4 x 4 index
+        Cx<T> o[16];
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) o[k1 + 4 * k2] = a[4 * k1 + k2];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) a[k] = o[k];
+    }
+}
+
+// One Stockham stage of radix R over `rows` sequences of length n = 2^logn held at
+// buf[lpad(row n + i)]; ns = 2^lgns is the product of the radices already applied and tws the
+// stage's twiddle table in LDS.  Butterfly (row, j), j < m = n / R: inputs i = j + r m, twiddled
+// by W_(ns R)^(r kk) (kk = j mod ns), an R-point DFT, outputs at (j - kk) R + kk + r ns.  gin: the
+// inputs come from ldg(row, i) instead of LDS (first stage); gout: the outputs go to stg(row, i,
+// v) (last stage, natural order).  Every read happens before the barrier, every write after it.
+template <typename T, int R, int INV, typename LDG, typename STG>
+__device__ __forceinline__ void fft_stage(Cx<T> *buf, const Cx<T> *tws, int logn, int rows,
+                                          int lgns, bool gin, bool gout, const LDG &ldg,
+                                          const STG &stg) {
+    constexpr int LR = R == 16 ? 4 : R == 8 ? 3 : R == 4 ? 2 : 1;
+    constexpr int MT = kRegPts / R;
+    const int logm = logn - LR, m = 1 << logm, ntask = rows << logm, ns = 1 << lgns;
+    Cx<T> v[MT][R];
+#pragma unroll
+    for (int q = 0; q < MT; ++q) {
+        const int t = threadIdx.x + q * kFT;
+        if (t < ntask) {
+            const int row = t >> logm, j = t & (m - 1);
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                v[q][r] = gin ? ldg(row, j + r * m) : buf[lpad((row << logn) + j + r * m)];
+            const int kk = j & (ns - 1);
+            if (kk) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    Cx<T> w = tws[((r - 1) << lgns) + kk];
                     if (INV) w.y = -w.y;
-                    a1 = cmul(a1, w);
+                    v[q][r] = cmul(v[q][r], w);
                 }
-                v[2 * q] = cadd(a0, a1);
-                v[2 * q + 1] = csub(a0, a1);
             }
+            dft<T, R, INV>(v[q]);
         }
-        __syncthreads();
-        if (r4) {
-#pragma unroll
-            for (int q = 0; q < MT; ++q) {
-                const int t = threadIdx.x + q * kBlock;
-                if (t >= ntask) break;
-                const int row = t / m, j = t - row * m, kk = j & (ns - 1);
-                const int dst = row * n + (j - kk) * 4 + kk;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) buf[lpad(dst + r * ns)] = v[4 * q + r];
-            }
-        } else {
-#pragma unroll
-            for (int q = 0; q < 2 * MT; ++q) {
-                const int t = threadIdx.x + q * kBlock;
-                if (t >= ntask) break;
-                const int row = t / m, j = t - row * m, kk = j & (ns - 1);
-                const int dst = row * n + (j - kk) * 2 + kk;
-                buf[lpad(dst)] = v[2 * q];
-                buf[lpad(dst + ns)] = v[2 * q + 1];
-            }
-        }
-        __syncthreads();
-        ns *= radix;
-        lg += r4 ? 2 : 1;
     }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MT; ++q) {
+        const int t = threadIdx.x + q * kFT;
+        if (t < ntask) {
+            const int row = t >> logm, j = t & (m - 1), kk = j & (ns - 1);
+            const int base = (j - kk) * R + kk;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (gout) stg(row, base + (r << lgns), v[q][r]);
+                else buf[lpad((row << logn) + base + (r << lgns))] = v[q][r];
+            }
+        }
+    }
+    __syncthreads();
 }
 
-// Register budget of the transforms: complex entries per workgroup (rows x n or k x ny) at most
-// 4 * kBlock * MT; MT = 4 in float64 (4096 entries, 64 KB), 8 in float32 (8192 entries).
+// FFTs (INV = 1: inverse, unnormalised) of `rows` sequences of length n = 2^logn, n <= 4096,
+// rows n <= kFftCap, with the stage tables of n at tw: radix-16 stages, then one of radix FR
+// (FR = fft_last_radix(logn), a template parameter so that only two stage bodies are inlined).
+// The first stage reads through ldg when gin, the last writes through stg when gout; otherwise
+// the data start and end in buf in natural order.
+template <typename T, int INV, int FR, typename LDG, typename STG>
+__device__ __forceinline__ void fft_run(Cx<T> *buf, const Cx<T> *tw, int logn, int rows, bool gin,
+                                        const LDG &ldg, bool gout, const STG &stg) {
+    constexpr int LFR = FR == 16 ? 4 : FR == 8 ? 3 : FR == 4 ? 2 : 1;
+    const int n16 = (logn - LFR) >> 2;
+    int off = 0, lg = 0;
+    for (int st = 0; st < n16; ++st) {
+        fft_stage<T, 16, INV>(buf, tw + off, logn, rows, lg, gin && st == 0, false, ldg, stg);
+        off += 15 << lg;
+        lg += 4;
+    }
+    fft_stage<T, FR, INV>(buf, tw + off, logn, rows, lg, gin && n16 == 0, gout, ldg, stg);
+}
+// Copy the n - 1 stage-table entries of a transform into LDS.
 template <typename T>
-constexpr int fft_mt() { return sizeof(T) == 8 ? 4 : 8; }
+__device__ __forceinline__ void load_table(Cx<T> *tw, const Cx<T> *src, int n) {
+    for (int m = threadIdx.x; m < n - 1; m += kFT) tw[m] = src[m];
+}
 
-// The half spectrum S[j][c][y] of an instance: complex T as (re, im) pairs (the buffer holds
-// complex float64), accessed entry by entry.
+// The half spectrum S[j][c][y] of an instance: complex T as (re, im) pairs (the buffer is sized
+// for complex float64).
+typedef float fvec2 __attribute__((ext_vector_type(2)));
+template <typename T>
+using cvec_t = typename std::conditional<sizeof(T) == 8, dvec2, fvec2>::type;
+
 template <typename T>
 __device__ __forceinline__ GAS T *spectrum(const Inst &I) {
     return reinterpret_cast<GAS T *>(gp(I.fs));
 }
 template <typename T>
-__device__ __forceinline__ Cx<T> sload(const GAS T *S, size_t i) {
-    return {S[2 * i], S[2 * i + 1]};
+__device__ __forceinline__ void cstore(GAS T *S, size_t i, Cx<T> v) {
+    cvec_t<T> w;
+    w.x = v.x;
+    w.y = v.y;
+    reinterpret_cast<GAS cvec_t<T> *>(S)[i] = w;
 }
 template <typename T>
-__device__ __forceinline__ void sstore(GAS T *S, size_t i, Cx<T> v) {
-    S[2 * i] = v.x;
-    S[2 * i + 1] = v.y;
+__device__ __forceinline__ Cx<T> cload(const GAS T *S, size_t i) {
+    const cvec_t<T> w = reinterpret_cast<const GAS cvec_t<T> *>(S)[i];
+    return {w.x, w.y};
 }
 
-// Pass A: forward FFT of rows y0 .. y0 + rb of component j of r, half spectrum stored
-// transposed: S[j][c][y], c in [0, nx/2].
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fp_rows_fwd(const Inst *__restrict__ tab,
-                                                        const int *__restrict__ fpre, int ninst,
-                                                        int nb, int inner,
-                                                        const T *__restrict__ rin, int use_in) {
-    extern __shared__ __align__(16) unsigned char fp_lds[];
-    const int L = xcd_remap(blockIdx.x, nb);
-    const int ii = find_inst(fpre, ninst, L);
-    const Inst &I = tab[ii];
-    if (inner >= 0 && (inner ? I.st_in : I.st)->done) return;   // inner < 0: stand-alone
-    const int blk = L - fpre[ii];
-    const int nx = I.nx, ny = I.ny, rb = I.frb, nc = nx / 2 + 1;
-    const int nrb = ny / rb;
-    const int j = blk / nrb, y0 = (blk - j * nrb) * rb;
-    Cx<T> *tw = reinterpret_cast<Cx<T> *>(fp_lds);
-    Cx<T> *buf = tw + nx / 2;
-    make_twiddles<T>(tw, nx);
-    const GAS T *r = (use_in ? gp(rin) : (const GAS T *)Sel<T>::r(I)) + (size_t)j * I.n_pix;
-    const uint32_t np = (uint32_t)I.n_pix;
-    for (int e = threadIdx.x; e < rb * nx; e += kBlock)
-        buf[lpad(e)] = {bld(r, np, (uint32_t)((y0 + e / nx) * nx + (e % nx))), (T)0};
+// Sum over the workgroup in a fixed order (one value per thread).
+__device__ __forceinline__ double fp_block_sum(double v) {
+    __shared__ double sm[kFT / 64];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
     __syncthreads();
-    fft_lds<T, 0, fft_mt<T>()>(buf, tw, nx, I.lognx, rb);
-    GAS T *S = spectrum<T>(I) + (size_t)2 * j * nc * ny;
-    for (int e = threadIdx.x; e < rb * nc; e += kBlock) {
-        const int c = e / rb, yy = e - c * rb;
-        sstore(S, (size_t)c * ny + y0 + yy, buf[lpad(yy * nx + c)]);
-    }
+    return ((sm[0] + sm[1]) + (sm[2] + sm[3])) + ((sm[4] + sm[5]) + (sm[6] + sm[7]));
 }
 
-// Pass B: column c of the half spectrum for every component: forward FFT along y, the per-mode
-// k x k solve, the <r, z> partial (Parseval: each c in (0, nx/2) stands for itself and its
-// conjugate partner), inverse FFT along y.
+// Placeholders for the unused global side of fft_run.
+template <typename T>
+struct NoLoad {
+    __device__ Cx<T> operator()(int, int) const { return {(T)0, (T)0}; }
+};
+template <typename T>
+struct NoStore {
+    __device__ void operator()(int, int, Cx<T>) const {}
+};
+
+// 1 / sqrt(x): the hardware estimate in float32 (the preconditioner only has to be a fixed SPD
+// operator), a rounded division in float64.
+__device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / sqrt(x); }
+
+// The k x k block of a mode with Laplacian eigenvalue lam, factored as L L^T (lower, with the
+// reciprocals of its diagonal), applied to one complex right-hand side: z = (L L^T)^-1 r.
 template <typename T, int K>
-__global__ __launch_bounds__(kBlock) void k_fp_cols(const Inst *__restrict__ tab,
-                                                    const int *__restrict__ fpre, int ninst,
-                                                    int nb, int inner) {
-    extern __shared__ __align__(16) unsigned char fp_lds[];
-    const int L = xcd_remap(blockIdx.x, nb);
-    const int ii = find_inst(fpre, ninst, L);
-    const Inst &I = tab[ii];
-    if (inner >= 0 && (inner ? I.st_in : I.st)->done) return;   // inner < 0: stand-alone
-    const int c = L - fpre[ii];
-    const int nx = I.nx, ny = I.ny, nc = nx / 2 + 1;
-    Cx<T> *tw = reinterpret_cast<Cx<T> *>(fp_lds);
-    Cx<T> *buf = tw + ny / 2;
-    make_twiddles<T>(tw, ny);
-    GAS T *S = spectrum<T>(I);
-    for (int e = threadIdx.x; e < K * ny; e += kBlock) {
-        const int j = e / ny, y = e - j * ny;
-        buf[lpad(e)] = sload(S, ((size_t)j * nc + c) * ny + y);
-    }
-    __syncthreads();
-    fft_lds<T, 0, fft_mt<T>()>(buf, tw, ny, I.logny, K);
-    // per-mode blocks: diag_j tau_j (kappa_j^2 + lam)^2 + Mbar, lam = lx + 4 - 2 cos(2 pi v/ny)
-    const double *fd = I.fsym;   // [kMaxK * kMaxK] Mbar, then kappa^2 [kMaxK], tau [kMaxK]
-    double mb[K][K], k2[K], ta[K];
-#pragma unroll
-    for (int a = 0; a < K; ++a) {
-        k2[a] = fd[kMaxK * kMaxK + a];
-        ta[a] = fd[kMaxK * kMaxK + kMaxK + a];
-#pragma unroll
-        for (int b = 0; b < K; ++b) mb[a][b] = fd[a * kMaxK + b];
-    }
-    double cx, sxu;
-    sincospi(2.0 * (double)c / (double)nx, &sxu, &cx);
-    const double lx = 2.0 - 2.0 * cx;
-    const double wc = (c == 0 || 2 * c == nx) ? 1.0 : 2.0;
-    double rz = 0.0;
-    for (int v = threadIdx.x; v < ny; v += kBlock) {
-        const double lam = lx + 2.0 - 2.0 * (double)twiddle(tw, v, ny).x;
-        T g[K][K];
-#pragma unroll
-        for (int a = 0; a < K; ++a)
-#pragma unroll
-            for (int b = 0; b < K; ++b) {
-                double e = mb[a][b];
-                if (a == b) {
-                    const double s = k2[a] + lam;
-                    e += ta[a] * s * s;
-                }
-                g[a][b] = (T)e;
-            }
-        // Cholesky g = l l^T (lower), then two triangular solves for the real and imaginary parts
+struct ModeSolver {
+    T mb[K][K], k2[K], ta[K];
+    __device__ void load(const double *fd) {
 #pragma unroll
         for (int a = 0; a < K; ++a) {
-            T d = g[a][a];
+            k2[a] = (T)fd[kMaxK * kMaxK + a];
+            ta[a] = (T)fd[kMaxK * kMaxK + kMaxK + a];
 #pragma unroll
-            for (int q = 0; q < a; ++q) d -= g[a][q] * g[a][q];
-            d = sqrt(d);
-            g[a][a] = d;
+            for (int b = 0; b < K; ++b) mb[a][b] = (T)fd[a * kMaxK + b];
+        }
+    }
+    __device__ void solve(T lam, const Cx<T> (&rh)[K], Cx<T> (&zh)[K]) const {
+        T l[K][K], id[K];
 #pragma unroll
-            for (int b = a + 1; b < K; ++b) {
-                T s = g[b][a];
+        for (int a = 0; a < K; ++a) {
 #pragma unroll
-                for (int q = 0; q < a; ++q) s -= g[b][q] * g[a][q];
-                g[b][a] = s / d;
+            for (int b = 0; b <= a; ++b) {
+                T s = mb[a][b];
+                if (a == b) {
+                    const T u = k2[a] + lam;
+                    s += ta[a] * u * u;
+                }
+#pragma unroll
+                for (int q = 0; q < b; ++q) s -= l[a][q] * l[b][q];
+                if (a == b) id[a] = rsqrt_t(s);
+                else l[a][b] = s * id[b];
             }
         }
-        Cx<T> rh[K], zh[K];
-#pragma unroll
-        for (int a = 0; a < K; ++a) rh[a] = buf[lpad(a * ny + v)];
 #pragma unroll
         for (int a = 0; a < K; ++a) {
             Cx<T> s = rh[a];
 #pragma unroll
-            for (int q = 0; q < a; ++q) { s.x -= g[a][q] * zh[q].x; s.y -= g[a][q] * zh[q].y; }
-            zh[a] = {s.x / g[a][a], s.y / g[a][a]};
+            for (int q = 0; q < a; ++q) { s.x -= l[a][q] * zh[q].x; s.y -= l[a][q] * zh[q].y; }
+            zh[a] = {s.x * id[a], s.y * id[a]};
         }
 #pragma unroll
         for (int a = K - 1; a >= 0; --a) {
             Cx<T> s = zh[a];
 #pragma unroll
-            for (int q = a + 1; q < K; ++q) { s.x -= g[q][a] * zh[q].x; s.y -= g[q][a] * zh[q].y; }
-            zh[a] = {s.x / g[a][a], s.y / g[a][a]};
+            for (int q = a + 1; q < K; ++q) { s.x -= l[q][a] * zh[q].x; s.y -= l[q][a] * zh[q].y; }
+            zh[a] = {s.x * id[a], s.y * id[a]};
         }
+    }
+};
+
+template <typename T, int K>
+__device__ __forceinline__ double dot_re(const Cx<T> (&a)[K], const Cx<T> (&b)[K]) {
+    double s = 0.0;
 #pragma unroll
-        for (int a = 0; a < K; ++a) {
-            rz += wc * ((double)rh[a].x * (double)zh[a].x + (double)rh[a].y * (double)zh[a].y);
-            buf[lpad(a * ny + v)] = zh[a];
-        }
-    }
-    __syncthreads();
-    fft_lds<T, 1, fft_mt<T>()>(buf, tw, ny, I.logny, K);
-    for (int e = threadIdx.x; e < K * ny; e += kBlock) {
-        const int j = e / ny, y = e - j * ny;
-        sstore(S, ((size_t)j * nc + c) * ny + y, buf[lpad(e)]);
-    }
-    // <r, z> = rz / (nx ny): the partial of this column (none for the stand-alone application)
-    if (I.partial) {
-        double v1[1] = {rz / ((double)nx * (double)ny)};
-        block_partials<1>(v1, I.partial, I.nred, SLOT_FRZ, c);
-    }
+    for (int q = 0; q < K; ++q) s += (double)a[q].x * (double)b[q].x + (double)a[q].y * (double)b[q].y;
+    return s;
 }
 
-// Pass C: rows y0 .. y0 + rb of component j: the full spectrum of each row from the half
-// (X[nx - c] = conj(X[c])), inverse FFT, z = real part / (nx ny).
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fp_rows_inv(const Inst *__restrict__ tab,
-                                                        const int *__restrict__ fpre, int ninst,
-                                                        int nb, int inner, T *__restrict__ zout,
-                                                        int use_out) {
+// Pass A: forward FFT of rows y0 .. y0 + rb of component j of r (rb even), half spectrum stored
+// transposed: S[j][c][y], c in [0, nx/2].  Two real rows travel as one complex row, u = r_2q +
+// i r_(2q+1) (the first stage reads them from global memory); their spectra separate by
+// Hermitian symmetry, R_2q[c] = (U[c] + conj U[-c]) / 2 and R_(2q+1)[c] = (U[c] - conj U[-c]) /
+// 2i.  The rb rows of one column c are consecutive in S, so the stores come in runs of rb
+// complex values.
+template <typename T, int FR>
+__global__ __launch_bounds__(kFT) void k_fp_rows_fwd(const Inst *__restrict__ tab,
+                                                     const int *__restrict__ fpre, int ninst,
+                                                     int nb, int inner,
+                                                     const T *__restrict__ rin, int use_in) {
     extern __shared__ __align__(16) unsigned char fp_lds[];
     const int L = xcd_remap(blockIdx.x, nb);
     const int ii = find_inst(fpre, ninst, L);
     const Inst &I = tab[ii];
     if (inner >= 0 && (inner ? I.st_in : I.st)->done) return;   // inner < 0: stand-alone
+    if (fft_last_radix(I.lognx) != FR) return;                     // another launch's instance
     const int blk = L - fpre[ii];
-    const int nx = I.nx, ny = I.ny, rb = I.frb, nc = nx / 2 + 1;
-    const int nrb = ny / rb;
-    const int j = blk / nrb, y0 = (blk - j * nrb) * rb;
+    const int nx = I.nx, ny = I.ny, rb = I.frb, nc = nx / 2 + 1, h = rb / 2, ln = I.lognx;
+    const int lrb = __builtin_ctz((unsigned)rb), nrb = ny >> lrb;
+    const int j = blk / nrb, y0 = (blk - j * nrb) << lrb;
     Cx<T> *tw = reinterpret_cast<Cx<T> *>(fp_lds);
-    Cx<T> *buf = tw + nx / 2;
-    make_twiddles<T>(tw, nx);
-    const GAS T *S = spectrum<T>(I) + (size_t)2 * j * nc * ny;
-    for (int e = threadIdx.x; e < rb * nc; e += kBlock) {
-        const int c = e / rb, yy = e - c * rb;
-        const Cx<T> v = sload(S, (size_t)c * ny + y0 + yy);
-        buf[lpad(yy * nx + c)] = v;
-        if (c > 0 && 2 * c < nx) buf[lpad(yy * nx + nx - c)] = {v.x, -v.y};
+    Cx<T> *buf = tw + nx;
+    const FpTabs tb = fp_tabs(nx, ny);
+    load_table<T>(tw, stage_table<T>(I.fsym, tb, true), nx);
+    __syncthreads();
+    const uint32_t np = (uint32_t)I.n_pix;
+    const GAS T *r = (use_in ? gp(rin) : (const GAS T *)Sel<T>::r(I)) + (size_t)j * I.n_pix;
+    const uint32_t o0 = (uint32_t)y0 * (uint32_t)nx;
+    const auto ldg = [&](int q, int i) -> Cx<T> {
+        const uint32_t o = o0 + ((uint32_t)(2 * q) << ln) + (uint32_t)i;
+        return {bld(r, np, o), bld(r, np, o + (uint32_t)nx)};
+    };
+    fft_run<T, 0, FR>(buf, tw, ln, h, true, ldg, false, NoStore<T>());
+    GAS T *S = spectrum<T>(I) + (size_t)2 * j * nc * ny;
+    const T half = (T)0.5;
+    for (int e = threadIdx.x; e < rb * nc; e += kFT) {
+        const int c = e >> lrb, yy = e & (rb - 1), q = yy >> 1;
+        const Cx<T> U = buf[lpad((q << ln) + c)];
+        const Cx<T> V = buf[lpad((q << ln) + ((nx - c) & (nx - 1)))];   // U[-c]
+        const Cx<T> out = (yy & 1) ? Cx<T>{half * (U.y + V.y), half * (V.x - U.x)}
+                                   : Cx<T>{half * (U.x + V.x), half * (U.y - V.y)};
+        cstore(S, (size_t)c * ny + y0 + yy, out);
+    }
+}
+
+// Pass B: column c of the half spectrum for every component: forward FFT along y (first stage
+// from global memory), the per-mode k x k solve, the <r, z> partial (Parseval: each c in
+// (0, nx/2) stands for itself and its conjugate partner), inverse FFT along y (last stage to
+// global memory).  Workgroup 0 takes the two real columns c = 0 and c = nx/2 as w = S[.][0] + i
+// S[.][nx/2]: with W its transform, F0[v] = (W[v] + conj W[-v]) / 2 and Fn[v] = (W[v] - conj
+// W[-v]) / 2i are the two columns' spectra; each is solved with its own eigenvalues, Z0 + i Zn
+// is transformed back, and its real and imaginary parts are the two columns.  A thread owns the
+// modes v and -v together (Z[-v] = conj Z[v] for both columns), so no mode is shared.
+// GTW: the stage twiddles are read from the set-up table in global memory (when the table and
+// the column do not both fit in LDS; float64 columns of 8192 values).
+template <typename T, int K, int FR, bool GTW>
+__global__ __launch_bounds__(kFT, (sizeof(T) == 8 || K > 5) ? 2 : 4) void k_fp_cols(
+    const Inst *__restrict__ tab, const int *__restrict__ fpre, int ninst, int nb, int inner) {
+    extern __shared__ __align__(16) unsigned char fp_lds[];
+    const int L = xcd_remap(blockIdx.x, nb);
+    const int ii = find_inst(fpre, ninst, L);
+    const Inst &I = tab[ii];
+    if (inner >= 0 && (inner ? I.st_in : I.st)->done) return;   // inner < 0: stand-alone
+    if (fft_last_radix(I.logny) != FR) return;                     // another launch's instance
+    const int c = L - fpre[ii];
+    const int nx = I.nx, ny = I.ny, nc = nx / 2 + 1, ln = I.logny, cn = nx / 2;
+    const FpTabs tb = fp_tabs(nx, ny);
+    Cx<T> *buf = reinterpret_cast<Cx<T> *>(fp_lds) + (GTW ? 0 : ny);
+    const Cx<T> *tw = stage_table<T>(I.fsym, tb, false);
+    if (!GTW) {
+        load_table<T>(reinterpret_cast<Cx<T> *>(fp_lds), tw, ny);
+        tw = reinterpret_cast<const Cx<T> *>(fp_lds);
     }
     __syncthreads();
-    fft_lds<T, 1, fft_mt<T>()>(buf, tw, nx, I.lognx, rb);
+    GAS T *S = spectrum<T>(I);
+    const double *lamy = I.fsym + tb.lamy;
+    ModeSolver<T, K> ms;
+    ms.load(I.fsym);
+    double rz = 0.0;
+    // column c (c > 0), or the real columns 0 and nx/2 packed as re + i im (c = 0)
+    const auto ldg = [&](int a, int y) -> Cx<T> {
+        if (c > 0) return cload(S, ((size_t)a * nc + c) * ny + y);
+        return {S[2 * (((size_t)a * nc) * ny + y)], S[2 * (((size_t)a * nc + cn) * ny + y)]};
+    };
+    fft_run<T, 0, FR>(buf, tw, ln, K, true, ldg, false, NoStore<T>());
+    if (c > 0) {
+        const T lx = (T)I.fsym[tb.lamx + c];
+        for (int v = threadIdx.x; v < ny; v += kFT) {
+            Cx<T> rh[K], zh[K];
+#pragma unroll
+            for (int a = 0; a < K; ++a) rh[a] = buf[lpad((a << ln) + v)];
+            ms.solve(lx + (T)lamy[v], rh, zh);
+            rz += 2.0 * dot_re<T, K>(rh, zh);
+#pragma unroll
+            for (int a = 0; a < K; ++a) buf[lpad((a << ln) + v)] = zh[a];
+        }
+    } else {
+        const T lxn = (T)I.fsym[tb.lamx + cn];
+        for (int v = threadIdx.x; v <= ny / 2; v += kFT) {
+            const int w = (ny - v) & (ny - 1);
+            Cx<T> f0[K], fn[K], z0[K], zn[K];
+#pragma unroll
+            for (int a = 0; a < K; ++a) {
+                const Cx<T> P = buf[lpad((a << ln) + v)], M = buf[lpad((a << ln) + w)];
+                f0[a] = {(T)0.5 * (P.x + M.x), (T)0.5 * (P.y - M.y)};
+                fn[a] = {(T)0.5 * (P.y + M.y), (T)0.5 * (M.x - P.x)};
+            }
+            const T ly = (T)lamy[v];
+            ms.solve(ly, f0, z0);
+            ms.solve(lxn + ly, fn, zn);
+            rz += (w == v ? 1.0 : 2.0) * (dot_re<T, K>(f0, z0) + dot_re<T, K>(fn, zn));
+#pragma unroll
+            for (int a = 0; a < K; ++a) {
+                // U[v] = Z0 + i Zn, U[-v] = conj Z0 + i conj Zn
+                buf[lpad((a << ln) + v)] = {z0[a].x - zn[a].y, z0[a].y + zn[a].x};
+                if (w != v) buf[lpad((a << ln) + w)] = {z0[a].x + zn[a].y, zn[a].x - z0[a].y};
+            }
+        }
+    }
+    __syncthreads();
+    const auto stg = [&](int a, int y, Cx<T> v) {
+        if (c > 0) {
+            cstore(S, ((size_t)a * nc + c) * ny + y, v);
+        } else {
+            cstore(S, ((size_t)a * nc) * ny + y, Cx<T>{v.x, (T)0});
+            cstore(S, ((size_t)a * nc + cn) * ny + y, Cx<T>{v.y, (T)0});
+        }
+    };
+    fft_run<T, 1, FR>(buf, tw, ln, K, false, NoLoad<T>(), true, stg);
+    // <r, z> = rz / (nx ny): the partial of this workgroup (none for the stand-alone application)
+    const double tot = fp_block_sum(rz);
+    if (I.partial && threadIdx.x == 0)
+        gp(I.partial)[(size_t)SLOT_FRZ * I.nred + c] = tot / ((double)nx * (double)ny);
+}
+
+// Pass C: rows y0 .. y0 + rb of component j, two real rows per complex inverse FFT: with R_2q
+// and R_(2q+1) the half spectra of the two rows, U[c] = R_2q[c] + i R_(2q+1)[c] and U[-c] =
+// conj R_2q[c] + i conj R_(2q+1)[c]; the inverse FFT of U is r_2q + i r_(2q+1) (times nx), and
+// z = those parts / (nx ny), written by the last stage.
+template <typename T, int FR>
+__global__ __launch_bounds__(kFT) void k_fp_rows_inv(const Inst *__restrict__ tab,
+                                                     const int *__restrict__ fpre, int ninst,
+                                                     int nb, int inner, T *__restrict__ zout,
+                                                     int use_out) {
+    extern __shared__ __align__(16) unsigned char fp_lds[];
+    const int L = xcd_remap(blockIdx.x, nb);
+    const int ii = find_inst(fpre, ninst, L);
+    const Inst &I = tab[ii];
+    if (inner >= 0 && (inner ? I.st_in : I.st)->done) return;   // inner < 0: stand-alone
+    if (fft_last_radix(I.lognx) != FR) return;                     // another launch's instance
+    const int blk = L - fpre[ii];
+    const int nx = I.nx, ny = I.ny, rb = I.frb, nc = nx / 2 + 1, h = rb / 2, ln = I.lognx;
+    const int lrb = __builtin_ctz((unsigned)rb), nrb = ny >> lrb;
+    const int j = blk / nrb, y0 = (blk - j * nrb) << lrb;
+    Cx<T> *tw = reinterpret_cast<Cx<T> *>(fp_lds);
+    Cx<T> *buf = tw + nx;
+    const FpTabs tb = fp_tabs(nx, ny);
+    load_table<T>(tw, stage_table<T>(I.fsym, tb, true), nx);
+    const GAS T *S = spectrum<T>(I) + (size_t)2 * j * nc * ny;
+    // stage: unit u = rows 2q, 2q + 1 of column c = u / h (one 4-vector)
+    const int lh = lrb - 1, units = nc << lh;
+    constexpr int G = sizeof(T) == 8 ? 4 : 8;
+    for (int u0 = 0; u0 < units; u0 += G * kFT) {
+        T a[G][4];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int u = u0 + g * kFT + threadIdx.x;
+            if (u < units) {
+                const int c = u >> lh, q = u & (h - 1);
+                ld4(S + 2 * ((size_t)c * ny + y0 + 2 * q), a[g]);
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int u = u0 + g * kFT + threadIdx.x;
+            if (u < units) {
+                const int c = u >> lh, q = u & (h - 1);
+                const T ex = a[g][0], ey = a[g][1], ox = a[g][2], oy = a[g][3];
+                buf[lpad((q << ln) + c)] = {ex - oy, ey + ox};
+                if (c > 0 && 2 * c < nx) buf[lpad((q << ln) + nx - c)] = {ex + oy, ox - ey};
+            }
+        }
+    }
+    __syncthreads();
     const T scale = (T)(1.0 / ((double)nx * (double)ny));
-    GAS T *z = use_out ? gp(zout) : gp(Sel<T>::z(I));
-    z += (size_t)j * I.n_pix;
     const uint32_t np = (uint32_t)I.n_pix;
-    for (int e = threadIdx.x; e < rb * nx; e += kBlock)
-        bst(z, np, (uint32_t)((y0 + e / nx) * nx + (e % nx)), buf[lpad(e)].x * scale);
+    GAS T *z = (use_out ? gp(zout) : gp(Sel<T>::z(I))) + (size_t)j * I.n_pix;
+    const uint32_t o0 = (uint32_t)y0 * (uint32_t)nx;
+    const auto stg = [&](int q, int i, Cx<T> v) {
+        const uint32_t o = o0 + ((uint32_t)(2 * q) << ln) + (uint32_t)i;
+        bst(z, np, o, v.x * scale);
+        bst(z, np, o + (uint32_t)nx, v.y * scale);
+    };
+    fft_run<T, 1, FR>(buf, tw, ln, h, false, NoLoad<T>(), true, stg);
 }
 
 // Mean over pixels of every weight map, first stage: the workgroup partials of all kMaxF rows
@@ -394,21 +605,81 @@ __global__ __launch_bounds__(kBlock) void k_fp_symbol(const double *__restrict__
     }
 }
 
+// Entry e of the stage table of a length-n transform, in float64 and float32.
+__device__ void stage_entry(int n, int e, double *t64, float *t32) {
+    const int logn = __builtin_ctz((unsigned)n);
+    int off = 0;
+    for (int lg = 0; lg < logn;) {
+        const int lr = stage_log_radix(logn, lg);
+        const int cnt = ((1 << lr) - 1) << lg;
+        if (e < off + cnt) {
+            const int ns = 1 << lg, rm1 = (e - off) >> lg, kk = (e - off) & (ns - 1);
+            // W_(ns R)^(r kk) = exp(-2 pi i r kk / (ns R))
+            double s, c;
+            sincospi(-2.0 * (double)((rm1 + 1) * kk) / (double)(ns << lr), &s, &c);
+            t64[2 * e] = c;
+            t64[2 * e + 1] = s;
+            t32[2 * e] = (float)c;
+            t32[2 * e + 1] = (float)s;
+            return;
+        }
+        off += cnt;
+        lg += lr;
+    }
+}
+// The Laplacian eigenvalue tables and the stage tables of both grid sides: thread e of the grid
+// writes entry e of lamx | lamy | stage table of nx | stage table of ny.
+__global__ __launch_bounds__(kBlock) void k_fp_tables(int nx, int ny, double *__restrict__ base) {
+    const FpTabs tb = fp_tabs(nx, ny);
+    const int nlx = nx / 2 + 1;
+    int e = blockIdx.x * kBlock + threadIdx.x;
+    if (e < nlx) {
+        base[tb.lamx + e] = 2.0 - 2.0 * cospi(2.0 * (double)e / (double)nx);
+        return;
+    }
+    e -= nlx;
+    if (e < ny) {
+        base[tb.lamy + e] = 2.0 - 2.0 * cospi(2.0 * (double)e / (double)ny);
+        return;
+    }
+    e -= ny;
+    if (e < nx - 1) {
+        stage_entry(nx, e, base + tb.twx64, reinterpret_cast<float *>(base + tb.twx32));
+        return;
+    }
+    e -= nx - 1;
+    if (e < ny - 1) stage_entry(ny, e, base + tb.twy64, reinterpret_cast<float *>(base + tb.twy32));
+}
+
+// LDS bytes of a row pass over rb real rows of length nx (rb / 2 complex rows) and of the column
+// pass (k components of length ny), stage tables included.
 template <typename T>
 size_t rows_lds(int nx, int rb) {
-    return sizeof(Cx<T>) * ((size_t)nx / 2 + lds_entries(rb * nx));
+    return sizeof(Cx<T>) * ((size_t)nx + lds_entries(rb / 2 * nx));
 }
 template <typename T>
-size_t cols_lds(int ny, int k) {
-    return sizeof(Cx<T>) * ((size_t)ny / 2 + lds_entries(k * ny));
+size_t cols_lds(int ny, int k, bool table = true) {
+    return sizeof(Cx<T>) * ((table ? (size_t)ny : 0) + lds_entries(k * ny));
+}
+
+// Static LDS of the passes (the column pass's reduction table) kept free beside the dynamic part.
+constexpr size_t kLdsMargin = 1024;
+
+template <typename T>
+int rows_per_block(int nx, int ny) {
+    // runs of at least 64 bytes per column in the transposed stores, at most kFftCap complex
+    // entries, and the LDS of the workgroup within the device's limit
+    int rb = 64 / (int)sizeof(Cx<T>);
+    rb = std::min(rb, 2 * kFftCap / nx);
+    rb = std::min(rb, ny);
+    while (rb > 2 && rows_lds<T>(nx, rb) > kMaxLds - kLdsMargin) rb /= 2;
+    return std::max(rb, 2);
 }
 
 }  // namespace
 
 int fp_rows_per_block(int nx, int ny, int dtype) {
-    const int budget = dtype == SYLV_F64 ? 2048 : 4096;   // complex entries per workgroup
-    const int rb = nx >= budget ? 1 : budget / nx;
-    return rb < ny ? rb : ny;
+    return dtype == SYLV_F64 ? rows_per_block<double>(nx, ny) : rows_per_block<float>(nx, ny);
 }
 
 bool fp_supported(int ny, int nx, int k, int dtype, char *why, size_t why_len) {
@@ -418,25 +689,39 @@ bool fp_supported(int ny, int nx, int k, int dtype, char *why, size_t why_len) {
                  "in [4, 4096] (grid %d x %d)", ny, nx);
         return false;
     }
-    const size_t es = dtype == SYLV_F64 ? sizeof(Cx<double>) : sizeof(Cx<float>);
-    const int cap = dtype == SYLV_F64 ? 4 * kBlock * fft_mt<double>() : 4 * kBlock * fft_mt<float>();
-    if (k * ny > cap || es * ((size_t)ny / 2 + lds_entries(k * ny)) > 65536) {
-        snprintf(why, why_len, "the Fourier preconditioner's column pass holds k x ny complex "
-                 "values in 64 KB of LDS: too many in %s (k = %d, ny = %d)",
-                 dtype == SYLV_F64 ? "float64" : "float32", k, ny);
+    const bool f64 = dtype == SYLV_F64;
+    const size_t cols = f64 ? cols_lds<double>(ny, k, false) : cols_lds<float>(ny, k, false);
+    if (k * ny > kFftCap || cols > kMaxLds - kLdsMargin) {
+        snprintf(why, why_len, "the Fourier preconditioner's column pass holds the k x ny complex "
+                 "values of a column in LDS: at most %d of them, %zu bytes (k = %d, ny = %d, %s)",
+                 kFftCap, (size_t)(kMaxLds - kLdsMargin), k, ny, f64 ? "float64" : "float32");
+        return false;
+    }
+    const int rb = fp_rows_per_block(nx, ny, dtype);
+    const size_t rows = f64 ? rows_lds<double>(nx, rb) : rows_lds<float>(nx, rb);
+    if (rows > kMaxLds - kLdsMargin) {
+        snprintf(why, why_len, "the Fourier preconditioner's row pass needs %zu bytes of LDS "
+                 "(nx = %d, %s)", rows, nx, f64 ? "float64" : "float32");
         return false;
     }
     return true;
 }
 
-hipError_t launch_fp_setup(const double *W, const double *A, int f, int k, int n_pix,
+size_t fp_table_bytes(int nx, int ny) { return sizeof(double) * fp_tabs(nx, ny).total; }
+
+hipError_t launch_fp_setup(const double *W, const double *A, int f, int k, int nx, int ny,
                            const double *coef, double *part, double *fsym, hipStream_t s) {
+    const int n_pix = nx * ny;
     const int nblk = (int)blocks_for(n_pix, kChunk);
     hipLaunchKernelGGL(k_wmean_part, dim3(nblk), dim3(kBlock), 0, s, W, f, n_pix, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_fp_symbol, dim3(1), dim3(kBlock), 0, s, part, nblk, A, f, k, n_pix,
                        coef, fsym);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int nt = (nx / 2 + 1) + ny + (nx - 1) + (ny - 1);
+    hipLaunchKernelGGL(k_fp_tables, dim3((nt + kBlock - 1) / kBlock), dim3(kBlock), 0, s, nx, ny,
+                       fsym);
     return hipGetLastError();
 }
 
@@ -445,15 +730,33 @@ size_t fp_setup_partials(int n_pix, int f) {
     return (size_t)blocks_for(n_pix, kChunk) * kMaxF;
 }
 
+bool fp_cols_global_twiddles(int ny, int k, int dtype) {
+    const size_t b = dtype == SYLV_F64 ? cols_lds<double>(ny, k) : cols_lds<float>(ny, k);
+    return b > kMaxLds - kLdsMargin;
+}
+
+size_t fp_lds_bytes(int pass, int n, int m, int dtype) {
+    // pass 0: a row pass over m rows of length n; pass 1: the column pass, m components of
+    // length n (without the stage table when it is read from global memory)
+    if (!pass) return dtype == SYLV_F64 ? rows_lds<double>(n, m) : rows_lds<float>(n, m);
+    const bool table = !fp_cols_global_twiddles(n, m, dtype);
+    return dtype == SYLV_F64 ? cols_lds<double>(n, m, table) : cols_lds<float>(n, m, table);
+}
+
 // One application z = Fourier preconditioner of r for every instance of the set, in float32 (f32)
 // or float64.  inner: 1 = the float32 inner runs of the mixed path (their r, z and state), 0 = the
 // float64 runs, -1 = the stand-alone preconditioner (one instance, no run state): r read from
 // rin, z written to zout.
-size_t fp_lds_bytes(int pass, int n, int m, int dtype) {
-    // pass 0: a row pass over m rows of length n; pass 1: the column pass, m components of
-    // length n
-    return dtype == SYLV_F64 ? (pass ? cols_lds<double>(n, m) : rows_lds<double>(n, m))
-                             : (pass ? cols_lds<float>(n, m) : rows_lds<float>(n, m));
+// The kernels are instantiated per final radix; a pass is launched once per radix class present
+// in the set (mask bit log2(FR) - 1), and workgroups of other classes return at once.
+template <typename F>
+hipError_t for_each_radix(int mask, F &&fn) {
+    hipError_t e = hipSuccess;
+    if ((mask & 1) && (e = fn(std::integral_constant<int, 2>())) != hipSuccess) return e;
+    if ((mask & 2) && (e = fn(std::integral_constant<int, 4>())) != hipSuccess) return e;
+    if ((mask & 4) && (e = fn(std::integral_constant<int, 8>())) != hipSuccess) return e;
+    if ((mask & 8) && (e = fn(std::integral_constant<int, 16>())) != hipSuccess) return e;
+    return e;
 }
 
 hipError_t launch_fp_apply(const InstSet &set, int k, int f32, int inner, const void *rin,
@@ -464,21 +767,39 @@ hipError_t launch_fp_apply(const InstSet &set, int k, int f32, int inner, const 
         auto run = [&](auto tt) -> hipError_t {
             using T = decltype(tt);
             const size_t lr = set.fp_lds_rows, lc = set.fp_lds_cols;
-            hipLaunchKernelGGL((k_fp_rows_fwd<T>), dim3(set.total_fa), dim3(kBlock), lr, s,
-                               set.table, set.fprefa, set.ninst, set.total_fa, mixed,
-                               reinterpret_cast<const T *>(rin), rin ? 1 : 0);
-            hipError_t e = hipGetLastError();
+            hipError_t e = for_each_radix(set.fp_rmask_x, [&](auto fr) -> hipError_t {
+                constexpr int FR = decltype(fr)::value;
+                hipLaunchKernelGGL((k_fp_rows_fwd<T, FR>), dim3(set.total_fa), dim3(kFT), lr, s,
+                                   set.table, set.fprefa, set.ninst, set.total_fa, mixed,
+                                   reinterpret_cast<const T *>(rin), rin ? 1 : 0);
+                return hipGetLastError();
+            });
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL((k_fp_cols<T, K>), dim3(set.total_fb), dim3(kBlock), lc, s,
-                               set.table, set.fprefb, set.ninst, set.total_fb, mixed);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-            hipLaunchKernelGGL((k_fp_rows_inv<T>), dim3(set.total_fa), dim3(kBlock), lr, s,
-                               set.table, set.fprefa, set.ninst, set.total_fa, mixed,
-                               reinterpret_cast<T *>(zout), zout ? 1 : 0);
-            return hipGetLastError();
+            e = for_each_radix(set.fp_rmask_y, [&](auto fr) -> hipError_t {
+                constexpr int FR = decltype(fr)::value;
+                if (sizeof(T) == 8 && set.fp_cols_gtw)
+                    hipLaunchKernelGGL((k_fp_cols<double, K, FR, true>), dim3(set.total_fb),
+                                       dim3(kFT), lc, s, set.table, set.fprefb, set.ninst,
+                                       set.total_fb, mixed);
+                else
+                    hipLaunchKernelGGL((k_fp_cols<T, K, FR, false>), dim3(set.total_fb), dim3(kFT),
+                                       lc, s, set.table, set.fprefb, set.ninst, set.total_fb,
+                                       mixed);
+                return hipGetLastError();
+            });
+            if (e != hipSuccess) return e;
+            return for_each_radix(set.fp_rmask_x, [&](auto fr) -> hipError_t {
+                constexpr int FR = decltype(fr)::value;
+                hipLaunchKernelGGL((k_fp_rows_inv<T, FR>), dim3(set.total_fa), dim3(kFT), lr, s,
+                                   set.table, set.fprefa, set.ninst, set.total_fa, mixed,
+                                   reinterpret_cast<T *>(zout), zout ? 1 : 0);
+                return hipGetLastError();
+            });
         };
         return f32 ? run(0.0f) : run(0.0);
     });
 }
+
+int fp_radix_bit(int logn) { return fft_last_radix(logn) / 2; }
 
 }  // namespace sylv

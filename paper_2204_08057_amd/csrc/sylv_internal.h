@@ -106,10 +106,11 @@ struct Inst {
     double *partial;     // [kNumSlots][nred]
     // Fourier preconditioner (pc == SYLV_PC_FOURIER, periodic grids with power-of-two sides)
     double *fs;          // half spectrum S[k][nx/2 + 1][ny], complex (float64 or float32 pairs)
-    const double *fsym;  // Mbar [kMaxK][kMaxK], kappa_j^2 [kMaxK], tau_j [kMaxK]
+    const double *fsym;  // Fourier region: Mbar [kMaxK][kMaxK], kappa_j^2 [kMaxK], tau_j
+                         // [kMaxK], then eigenvalue and FFT stage tables
     int32_t lognx, logny;
     int32_t frb;         // grid rows per workgroup of the row passes
-    int32_t nfft;        // column workgroups = nx/2 + 1 (partials of <r, z>)
+    int32_t nfft;        // column workgroups = nx/2 (partials of <r, z>)
 };
 
 // Launch-time view of the instances: a device table plus prefix sums that map a flat
@@ -134,6 +135,8 @@ struct InstSet {
     int fourier;          // pc == SYLV_PC_FOURIER
     size_t fp_lds_rows, fp_lds_cols;  // dynamic LDS of the row and column passes (largest over
                                       // the set's instances)
+    int fp_cols_gtw;      // the column pass reads its twiddles from global memory
+    int fp_rmask_x, fp_rmask_y;   // final FFT radices present (fp_radix_bit) along x and y
 };
 
 inline int packed_size(int k) { return k * (k + 1) / 2; }
@@ -206,8 +209,11 @@ hipError_t launch_apply_plain(const Inst *table0, int k, int dtype, int rows, in
 bool fp_supported(int ny, int nx, int k, int dtype, char *why, size_t why_len);
 int fp_rows_per_block(int nx, int ny, int dtype);
 size_t fp_setup_partials(int n_pix, int f);
-// Mbar, kappa^2 and tau of a problem into fsym (part: fp_setup_partials doubles of scratch).
-hipError_t launch_fp_setup(const double *W, const double *A, int f, int k, int n_pix,
+// Bytes of a problem's Fourier region: the symbol block (Mbar, kappa^2, tau), the Laplacian
+// eigenvalues of both grid sides and the FFT stage tables.
+size_t fp_table_bytes(int nx, int ny);
+// The Fourier region of a problem, fsym (part: fp_setup_partials doubles of scratch).
+hipError_t launch_fp_setup(const double *W, const double *A, int f, int k, int nx, int ny,
                            const double *coef, double *part, double *fsym, hipStream_t s);
 // z = Fourier preconditioner of r for every instance of the set, in float32 (f32) or float64;
 // inner = 1: the float32 inner runs of the mixed path, 0: the float64 runs, -1: the stand-alone
@@ -217,6 +223,11 @@ hipError_t launch_fp_apply(const InstSet &set, int k, int f32, int inner, const 
 // Dynamic LDS bytes of a row pass (pass 0: m rows of length n) or of the column pass (pass 1:
 // m components of length n) in precision dtype.
 size_t fp_lds_bytes(int pass, int n, int m, int dtype);
+// Whether the column pass reads its FFT twiddles from global memory (its column and the table
+// do not both fit in LDS).
+bool fp_cols_global_twiddles(int ny, int k, int dtype);
+// Bit of a transform length's final-radix class in InstSet.fp_rmask_x / fp_rmask_y.
+int fp_radix_bit(int logn);
 
 // Working sets above this many bytes are streamed past the last-level cache (256 MB on MI355X).
 constexpr double kStreamBytes = 256.0 * (1 << 20);

@@ -40,9 +40,12 @@ def host(t):
     return t.detach().cpu().numpy().astype(np.float64)
 
 
-# (ny, nx, k, f): odd and even powers of two (radix-2 last stage), rectangular, tiny and every k
+# (ny, nx, k, f): odd and even powers of two (radix-2 last stage), rectangular, tiny, every k,
+# and the largest tiles: k ny = 8192 column values (above 64 KB of LDS in float32, about 150 KB in
+# float64) and rows of 4096
 SHAPES = [(4, 4, 1, 2), (8, 16, 3, 5), (16, 8, 2, 3), (32, 64, 4, 9), (64, 64, 3, 6),
-          (128, 32, 8, 16), (4, 256, 5, 4), (512, 8, 2, 3), (16, 16, 6, 7), (8, 32, 7, 8)]
+          (128, 32, 8, 16), (4, 256, 5, 4), (512, 8, 2, 3), (16, 16, 6, 7), (8, 32, 7, 8),
+          (2048, 16, 4, 9), (4096, 4, 1, 2), (8, 4096, 2, 3), (1024, 8, 8, 9)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -146,6 +149,17 @@ def test_het_1024_whole_solution_vs_oracle(precision, tol, bound):
     assert rel(host(X).reshape(p.k, p.n_pix), ref) <= bound
 
 
+def test_largest_float64_column_reads_twiddles_from_global_memory():
+    """2 x 4096 complex float64 column values and their twiddle table exceed 160 KB of LDS: the
+    column pass then reads the twiddles from the set-up table in global memory."""
+    p = make_problem(4096, 4, 2, 3, seed=5504, noise="hetero")
+    dp = sy.DeviceProblem.from_numpy(p)
+    R = random_maps(p, seed=5505)
+    ref = opcg.fourier_preconditioner(p)(R)
+    assert rel(host(sy.precond(dp, dev(R), kind=sy.SYLV_PC_FOURIER)), ref) <= 1e-12
+    assert rel(host(sy.precond(dp, dev(R, torch.float32), kind=sy.SYLV_PC_FOURIER)), ref) <= 2e-5
+
+
 def test_unsupported_shapes_are_refused():
     for kw in (dict(ny=24, nx=32), dict(ny=32, nx=2), dict(ny=16, nx=16, boundary="face")):
         boundary = kw.pop("boundary", "periodic")
@@ -153,6 +167,13 @@ def test_unsupported_shapes_are_refused():
         dp = sy.DeviceProblem.from_numpy(p)
         with pytest.raises(sy.SylvError):
             sy.pcg_solve(dp, Y=dev(p.Y), opts=sy.SolveOptions(precond=sy.SYLV_PC_FOURIER))
+    # a column of k ny = 12288 complex values exceeds the column pass's tile in both precisions
+    p = make_problem(4096, 4, 3, 3, seed=5502, noise="hetero")
+    dp = sy.DeviceProblem.from_numpy(p)
+    R = dev(random_maps(p, seed=5503))
+    for dt in (torch.float64, torch.float32):
+        with pytest.raises(sy.SylvError):
+            sy.precond(dp, R.to(dt), kind=sy.SYLV_PC_FOURIER)
     p = make_problem(16, 16, 3, 4, seed=5501, noise="hetero")
     dp = sy.DeviceProblem.from_numpy(p)
     with pytest.raises(sy.SylvError):   # block CG takes the per-pixel preconditioners only
