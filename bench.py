@@ -4,15 +4,17 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 
 One step = one complete mixed-precision solve through the C ABI: operator set-up (stencil
-coefficients, per-pixel mixing and block-Jacobi blocks), right-hand side B^T C Y, initial
+coefficients, per-pixel mixing, the preconditioner's set-up), right-hand side B^T C Y, initial
 residual, float32 inner PCG runs inside float64 refinement until ||b - G x|| <= 1e-8 ||b||, and
-the statistics.  Inputs (kappa, tau, A, W, Y) are resident in HBM before timing starts.  The same
-K steps are then timed for the float64 solver.  The roofline object reports the stand-alone
-operator apply (float32, the precision of the inner runs), timed with HIP events on the stream it
-runs on.  Prints one JSON line.
+the statistics.  Inputs (kappa, tau, A, W, Y) are resident in HBM before timing starts.  Both
+preconditioners are timed (block-Jacobi, and the Fourier preconditioner with pixel-mean weights),
+each for the mixed and the float64 solver; the headline value is the faster mixed solve and
+fp64_ms the float64 solve with the same preconditioner.  The roofline object reports the
+stand-alone operator apply (float32, the precision of the inner runs), timed with HIP events on
+the stream it runs on.  Prints one JSON line.
 
---mode pmc runs only a device copy of known size, the applies and one solve of each precision,
-for hardware-counter runs (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE) that calibrate the
+--mode pmc runs only a device copy of known size, the applies, one solve of each precision with
+each preconditioner and stand-alone Fourier preconditioner applications, for hardware-counter runs (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE) that calibrate the
 HBM-traffic figure.  --mode sylv runs only the Lanczos-Sylvester workload (1024^2, k = 4, f = 9,
 separable noise, common kappa) against PCG on the same system.
 """
@@ -35,14 +37,15 @@ METRIC = "time-to-1e-8 rel. residual @1024² k=3 (FP64 vs mixed); operator-apply
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_apply_f32_het_1024.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2204_08057_amd", "csrc", "sylv_kernels.hip")
+FOURIER_SRC = os.path.join(ROOT, "paper_2204_08057_amd", "csrc", "sylv_fourier.hip")
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+def kernel_source_hash(path: str = KERNEL_SRC) -> str:
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
 def apply_bytes_per_pixel(k: int, elem: int, f: int = None) -> int:
@@ -89,6 +92,27 @@ def traffic_from_counters(kernel_hash: str):
     if d.get("kernel_source_sha") != kernel_hash:
         return None
     return d.get("traffic_bytes_per_launch")
+
+
+def fourier_passes_from_counters():
+    """Per-pass duration and DRAM bytes of the Fourier preconditioner's kernels (float32 and
+    float64, 1024^2, k = 3) from the committed counter summary, if it was taken on the current
+    FFT source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+    except Exception:
+        return None
+    if d.get("fourier_source_sha") != kernel_source_hash(FOURIER_SRC):
+        return None
+    out = {}
+    for name, v in d.get("fourier_kernels", {}).items():
+        gbs = v["algorithmic"] / v["median_us"] / 1e3
+        out[name] = {"us": v["median_us"], "algorithmic_bytes": v["algorithmic"],
+                     "achieved": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4),
+                     "traffic": v["fetch"] + v["write"]}
+    return out
 
 
 def cg_iteration_seconds(sy, torch, dp, Y, ws, precision, precond, n1=40, n2=140, reps=5):
@@ -274,17 +298,19 @@ def summarize(ms, st):
 
 def bench_masked(sy, torch, steps, warmup, cpu=False):
     """2048^2, k = 4, f = 9, 10 % masked pixels (beyond the last-level cache): mixed precision vs
-    float64 solves and the stand-alone applies."""
+    float64 solves with the block-Jacobi and the Fourier preconditioner, and the stand-alone
+    applies."""
     from workloads import workload
     prob = workload("masked_2048")[0]
     dp = sy.DeviceProblem.from_numpy(prob)
     Y = torch.as_tensor(prob.Y, device="cuda")
     res = {}
-    for label, prec in (("mixed", sy.SYLV_PREC_MIXED), ("f64", sy.SYLV_PREC_F64)):
-        o = sy.SolveOptions(tol=1e-8, precision=prec)
-        ms, st, _ = time_solves(sy, torch, dp, Y, None, o, 1, steps, warmup)
-        res[label] = summarize(ms, st)
-        log(f"masked_2048 {label}: {res[label]}")
+    for pc, suffix in ((sy.SYLV_PC_BLOCK, ""), (sy.SYLV_PC_FOURIER, "_fourier")):
+        for label, prec in (("mixed", sy.SYLV_PREC_MIXED), ("f64", sy.SYLV_PREC_F64)):
+            o = sy.SolveOptions(tol=1e-8, precision=prec, precond=pc)
+            ms, st, _ = time_solves(sy, torch, dp, Y, None, o, 1, steps, warmup)
+            res[label + suffix] = summarize(ms, st)
+            log(f"masked_2048 {label + suffix}: {res[label + suffix]}")
     # stand-alone applies at a size far beyond the 256 MB last-level cache: the HBM figure
     ws_app = sy.binding.prepare(dp, sy.SYLV_PC_NONE)
     gen = torch.Generator(device="cuda")
@@ -431,7 +457,7 @@ def bench_other_workloads(sy, torch, steps, warmup, cpu=False):
 def bench_sweep(sy, torch):
     """Ten solves over a hyperparameter sweep (kappa +1 %, tau -1 % per step) at 1024^2, k = 3,
     f = 9, to 1e-8 relative to ||b||: each solve from zero, or warm-started from the previous
-    solution.  Total time and iterations of the sweep."""
+    solution, with either preconditioner.  Total time and iterations of the sweep."""
     from workloads import WORKLOADS, sweep_parameters, workload
     cfg = WORKLOADS["sweep_1024"]
     prob = workload("sweep_1024")[0]
@@ -439,8 +465,11 @@ def bench_sweep(sy, torch):
     Y = torch.as_tensor(prob.Y, device="cuda")
     dp = sy.DeviceProblem.from_numpy(prob)
     res = {"steps": cfg["steps"], "dk": cfg["dk"], "dt": cfg["dt"]}
-    for label, prec in (("mixed", sy.SYLV_PREC_MIXED), ("f64", sy.SYLV_PREC_F64)):
-        o = sy.SolveOptions(tol=cfg["tol"], precision=prec, stop_ref=sy.SYLV_STOP_B)
+    for label, prec, pc in (("mixed", sy.SYLV_PREC_MIXED, sy.SYLV_PC_BLOCK),
+                            ("f64", sy.SYLV_PREC_F64, sy.SYLV_PC_BLOCK),
+                            ("mixed_fourier", sy.SYLV_PREC_MIXED, sy.SYLV_PC_FOURIER),
+                            ("f64_fourier", sy.SYLV_PREC_F64, sy.SYLV_PC_FOURIER)):
+        o = sy.SolveOptions(tol=cfg["tol"], precision=prec, stop_ref=sy.SYLV_STOP_B, precond=pc)
         ws = torch.empty(sy.workspace_bytes([dp], 1, o), dtype=torch.uint8, device="cuda")
         for mode in ("cold", "warm"):
             for rep in range(2):            # the first pass warms up
@@ -660,7 +689,7 @@ def main():
     ap.add_argument("--mode", default="bench",
                     choices=["bench", "pmc", "pmc_block", "pmc_masked", "sylv", "sky", "sweep",
                              "masked", "batched"],
-                    help="pmc: copy + applies + one solve of each precision (counter runs); "
+                    help="pmc: copy + applies + solves + Fourier applications (counter runs); "
                          "sylv: only the Lanczos-Sylvester workload; sky: only the 12-face "
                          "full-sky workload; sweep: only the hyperparameter sweep; masked: only "
                          "the 2048^2 masked workload; batched: only the 8-grid batch")
@@ -721,9 +750,17 @@ def main():
         for _ in range(3):
             sy.apply(dp, X32, ws=ws_app, prepared=True)
             sy.apply(dp, X64, ws=ws_app, prepared=True)
-        # one solve of each precision, so that the counters also cover the CG kernels
-        for prec in (sy.SYLV_PREC_MIXED, sy.SYLV_PREC_F64):
-            sy.pcg_solve(dp, Y=Y, opts=sy.SolveOptions(tol=tol, precision=prec))
+        # one solve of each precision with each preconditioner, so that the counters also cover
+        # the CG kernels and the FFT passes, and three stand-alone Fourier applications of each
+        # precision
+        for pc in (sy.SYLV_PC_BLOCK, sy.SYLV_PC_FOURIER):
+            for prec in (sy.SYLV_PREC_MIXED, sy.SYLV_PREC_F64):
+                sy.pcg_solve(dp, Y=Y, opts=sy.SolveOptions(tol=tol, precision=prec, precond=pc))
+        ws_fp = sy.binding.prepare(dp, sy.SYLV_PC_FOURIER)
+        for R in (X32, X64):
+            launch = sy.precond_launcher(dp, R, torch.empty_like(R), sy.SYLV_PC_FOURIER, ws_fp)
+            for _ in range(3):
+                launch()
         torch.cuda.synchronize()
         print(json.dumps({"mode": "pmc", "copy_bytes": nbytes,
                           "apply_f32_bytes": apply_bytes_per_pixel(k, 4, f) * n_pix,
@@ -848,7 +885,13 @@ def main():
         "apply_f32_gbs": round(gbs32, 1),
         "apply_f64_gbs": round(gbs64, 1),
         "fourier_precond_f32": {"us": round(t_fp * 1e3, 3), "algorithmic_bytes": b_fp,
-                                "gbs": round(b_fp / t_fp / 1e6, 1)},
+                                "gbs": round(b_fp / t_fp / 1e6, 1),
+                                "note": "one stand-alone call (three FFT passes and the call's "
+                                        "two table uploads), HIP events over back-to-back calls"},
+        "roofline_fourier": {"bound": "hbm", "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                             "passes": fourier_passes_from_counters(),
+                             "source": "median active launch of rocprofv3 --kernel-trace and "
+                                       "FETCH_SIZE / WRITE_SIZE runs of bench.py --mode pmc"},
         "roofline": {
             "kernel": "operator apply, float32 (k_apply<float,3,4,plain>)",
             "bound": "hbm",
