@@ -395,12 +395,15 @@ int wait_count(HostFlags *f, int slot, int &value) {
 
 // Iterations still to queue after those already queued (indices below `queued`), from the last
 // two completion reports: the gap to the threshold shrinks about linearly in log scale, so the
-// slowest run stops near iteration iter + gap / rate.  Returns `chunk` while no rate is known,
-// 0 when the queued iterations should already finish every run, and otherwise the estimate plus
-// a margin, never more than `chunk`.  A short estimate costs one more host round trip, an
-// over-estimate a few early-exit launches; the result of the solve does not depend on it.
+// slowest run stops near iteration iter + gap / rate.  Returns half a batch while no rate is
+// known (a run can stop within the next few iterations: short Fourier-preconditioned runs take
+// about ten), 0 when the queued iterations should already finish every run, and otherwise the
+// estimate plus a margin, never more than `chunk`.  A short estimate costs one more host round
+// trip, an over-estimate a few early-exit launches; the result of the solve does not depend on
+// it.
 int next_batch(const Report &prev, const Report &cur, bool have_prev, int queued, int chunk) {
-    if (!have_prev || cur.iter <= prev.iter || cur.gap <= 0.0 || prev.gap <= cur.gap) return chunk;
+    if (!have_prev || cur.iter <= prev.iter || cur.gap <= 0.0 || prev.gap <= cur.gap)
+        return std::max(2, chunk / 2);
     const double rate = (prev.gap - cur.gap) / (cur.iter - prev.iter);
     const double stop = cur.iter + cur.gap / rate;
     const double left = stop - (queued - 1);
@@ -458,7 +461,7 @@ int run_cg_loop(const InstSet &set, int k, int mixed, int chunk, int max_iter, H
     for (;;) {
         // keep one batch queued ahead of the report being waited for, sized by the estimate
         if (it <= max_iter && npend < 2) {
-            int n = have_cur ? next_batch(prev, cur, have_prev, it, chunk) : chunk;
+            int n = next_batch(prev, cur, have_prev && have_cur, it, chunk);
             if (npend == 0 && n < 4) n = 4;   // the estimate fell short: the run goes on
             if (n > 0 && (rc = enqueue_batch(n))) return rc;
         }
