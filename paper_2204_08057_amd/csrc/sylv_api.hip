@@ -184,7 +184,8 @@ bool make_layout(const sylv_problem *probs, int nprob, int nrhs, bool solve, Lay
             const size_t vk = (size_t)k * n;
             for (int r = 0; r < nrhs; ++r) {
                 InstLayout &I = L.inst[(size_t)g * nrhs + r];
-                I.nred = std::max(std::max(tiles_for(ny, nx, 2), chunks_for((int)n)), nx / 2 + 1);
+                I.nred = std::max(std::max(tiles_for(ny, nx, 2), chunks_for((int)n)),
+                                  std::max(nx / 2 + 1, k * ny / 2));
                 I.st = off;      off = align_up(off + 2 * sizeof(DevState));
                 I.partial = off; off = align_up(off + sizeof(double) * kNumSlots * I.nred);
                 I.b = off;   off = align_up(off + sizeof(double) * vk);
@@ -420,17 +421,21 @@ int next_batch(const Report &prev, const Report &cur, bool have_prev, int queued
 static_assert(sizeof(Inst) % 4 == 0 && sizeof(Group) % 4 == 0, "tables upload as 32-bit words");
 
 // The Fourier preconditioner's three passes (z and <r, z> of every unfinished run).
-int fourier_apply(const InstSet &set, int k, int mixed, hipStream_t s) {
-    HIP_TRY(launch_fp_apply(set, k, mixed, mixed, nullptr, nullptr, s));
+// With the Fourier preconditioner, in the float32 inner runs of the mixed path the forward row
+// pass also performs the CG update of iteration `it` (upd = 2) and, at the start of a run, takes
+// the ||r||^2 partials of r (upd = 1); float64 runs keep the streaming update (fused, the float64
+// row pass took longer than the two kernels apart: 42 against 22 + 18 us at 1024^2, k = 3).
+int fourier_apply(const InstSet &set, int k, int mixed, int upd, int it, hipStream_t s) {
+    HIP_TRY(launch_fp_apply(set, k, mixed, mixed, nullptr, nullptr, mixed ? upd : 0, it, s));
     return SYLV_OK;
 }
 
 int cg_iteration(const InstSet &set, int k, int mixed, int it, hipStream_t s) {
     HIP_TRY(launch_cg_apply(set, k, mixed, it, s));
     HIP_TRY(launch_prereduce_pq(set, mixed, s));
-    HIP_TRY(launch_cg_update(set, k, mixed, it, s));
+    if (!(set.fourier && mixed)) HIP_TRY(launch_cg_update(set, k, mixed, it, s));
     if (set.fourier) {
-        const int rc = fourier_apply(set, k, mixed, s);
+        const int rc = fourier_apply(set, k, mixed, 2, it, s);
         if (rc) return rc;
     }
     HIP_TRY(launch_prereduce_rz(set, s));
@@ -596,6 +601,7 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
             I.ntiles = tiles_for(I.ny, I.nx, rows64);
             I.ntiles32 = tiles_for(I.ny, I.nx, rows32);
             I.nchunks = chunks_for(I.n_pix);
+            I.nrr = I.nchunks;
             I.nred = IL.nred;
             I.Y = Y ? Y + yoff : nullptr;
             I.bext = Bextra ? Bextra + xoff + (size_t)r * k * n : nullptr;
@@ -625,6 +631,7 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
                 I.frb = fp_rows_per_block(I.nx, I.ny, mixed ? SYLV_F32 : SYLV_F64);
                 I.nfft = I.nx / 2;
                 nfa = k * (I.ny / I.frb);
+                I.nrr = mixed ? nfa : I.nchunks;   // the producer of ||r||^2 (see fourier_apply)
                 nfb = I.nfft;
                 const int dt = mixed ? SYLV_F32 : SYLV_F64;
                 fp_lds_rows = std::max(fp_lds_rows, fp_lds_bytes(0, I.nx, I.frb, dt));
@@ -753,7 +760,7 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
         } else {
             HIP_TRY(launch_pinit(set, k, mixed, inner_tol, safety, opts->max_iter, s));
             if (fourier) {
-                const int rc2 = fourier_apply(set, k, mixed, s);
+                const int rc2 = fourier_apply(set, k, mixed, 1, 0, s);
                 if (rc2) return rc2;
             }
             HIP_TRY(launch_prereduce_rz(set, s));
@@ -1580,6 +1587,7 @@ int sylv_prepare(const sylv_problem *prob, int32_t precond, void *ws, size_t ws_
     Inst I = operator_inst(*prob, L.prob[0], base, precond);
     I.ntiles = 0;
     I.nchunks = chunks_for(I.n_pix);
+    I.nrr = I.nchunks;
     HIP_TRY(launch_upload(base + L.table, &I, sizeof(Inst), s));
     return SYLV_OK;
 }
@@ -1635,6 +1643,7 @@ int sylv_precond(const sylv_problem *prob, int32_t dtype, int32_t precond, const
         // one instance without run state: its spectrum in the stand-alone region
         Inst I = operator_inst(*prob, L.prob[0], base, precond);
         I.nchunks = chunks_for(I.n_pix);
+        I.nrr = I.nchunks;
         I.fs = reinterpret_cast<double *>(base + L.fs1);
         I.fsym = reinterpret_cast<const double *>(base + L.prob[0].fsym);
         I.lognx = __builtin_ctz((unsigned)I.nx);
@@ -1667,7 +1676,7 @@ int sylv_precond(const sylv_problem *prob, int32_t dtype, int32_t precond, const
         for (int r = 0; r < nrhs; ++r)
             HIP_TRY(launch_fp_apply(set, k, dtype == SYLV_F32, -1,
                                     static_cast<const char *>(R) + r * plane,
-                                    static_cast<char *>(Z) + r * plane, s));
+                                    static_cast<char *>(Z) + r * plane, 0, 0, s));
         return SYLV_OK;
     }
     HIP_TRY(launch_precond_plain(reinterpret_cast<const Inst *>(base + L.table), prob->k, dtype,

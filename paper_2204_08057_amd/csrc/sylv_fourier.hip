@@ -296,6 +296,23 @@ __device__ __forceinline__ double fp_block_sum(double v) {
     return ((sm[0] + sm[1]) + (sm[2] + sm[3])) + ((sm[4] + sm[5]) + (sm[6] + sm[7]));
 }
 
+// Fixed-order sum of `count` partials of slot `slot` (every thread receives it): four running
+// sums per thread, then the workgroup in a fixed order.
+__device__ __forceinline__ double fp_consume(const double *partial, int nred, int slot,
+                                             int count) {
+    const GAS double *pp = gp(partial) + (size_t)slot * nred;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int b = threadIdx.x;
+    for (; b + 3 * kFT < count; b += 4 * kFT) {
+        a0 += pp[b];
+        a1 += pp[b + kFT];
+        a2 += pp[b + 2 * kFT];
+        a3 += pp[b + 3 * kFT];
+    }
+    for (; b < count; b += kFT) a0 += pp[b];
+    return fp_block_sum((a0 + a1) + (a2 + a3));
+}
+
 // Placeholders for the unused global side of fft_run.
 template <typename T>
 struct NoLoad {
@@ -373,18 +390,55 @@ __device__ __forceinline__ double dot_re(const Cx<T> (&a)[K], const Cx<T> (&b)[K
 // Hermitian symmetry, R_2q[c] = (U[c] + conj U[-c]) / 2 and R_(2q+1)[c] = (U[c] - conj U[-c]) /
 // 2i.  The rb rows of one column c are consecutive in S, so the stores come in runs of rb
 // complex values.
+// In a CG run the pass also takes the ||r||^2 partials of its rows (upd = 1, start of a run) and
+// first performs the update of iteration `it` (upd = 2): alpha = rho / <p, q> from the apply's
+// partials (stop and breakdown handled as the streaming update kernel does), r -= alpha q as
+// the first stage loads r and q, r written back.
 template <typename T, int FR>
 __global__ __launch_bounds__(kFT) void k_fp_rows_fwd(const Inst *__restrict__ tab,
                                                      const int *__restrict__ fpre, int ninst,
                                                      int nb, int inner,
-                                                     const T *__restrict__ rin, int use_in) {
+                                                     const T *__restrict__ rin, int use_in,
+                                                     int upd, int it) {
     extern __shared__ __align__(16) unsigned char fp_lds[];
     const int L = xcd_remap(blockIdx.x, nb);
     const int ii = find_inst(fpre, ninst, L);
     const Inst &I = tab[ii];
-    if (inner >= 0 && (inner ? I.st_in : I.st)->done) return;   // inner < 0: stand-alone
     if (fft_last_radix(I.lognx) != FR) return;                     // another launch's instance
     const int blk = L - fpre[ii];
+    T alpha = (T)0;
+    if (inner >= 0) {                                              // inner < 0: stand-alone
+        DevState *st = inner ? I.st_in : I.st;
+        if (st->done) return;
+        if (upd == 2) {
+            const int pend = st->pend;
+            if (pend >= 0) {   // this iteration's apply stopped the run
+                if (blk == 0 && threadIdx.x == 0) {
+                    st->status = pend;
+                    st->done = 1;
+                    st->total_iter += it;
+                }
+                return;
+            }
+            const double pq = fp_consume(I.partial, I.nred, SLOT_PQ,
+                                         I.pre ? 1 : (sizeof(T) == 4 ? I.ntiles32 : I.ntiles));
+            int status = -1;
+            if (!finite_d(pq)) status = SYLV_NONFINITE;
+            else if (!(pq > 0.0)) status = SYLV_BREAKDOWN;
+            const double alpha_d = st->rho[it & 1] / pq;
+            if (blk == 0 && threadIdx.x == 0) {
+                if (status >= 0) {
+                    st->status = status;
+                    st->done = 1;
+                    st->total_iter += it;
+                } else {
+                    st->alpha[it & 1] = alpha_d;
+                }
+            }
+            if (status >= 0) return;
+            alpha = (T)alpha_d;
+        }
+    }
     const int nx = I.nx, ny = I.ny, rb = I.frb, nc = nx / 2 + 1, h = rb / 2, ln = I.lognx;
     const int lrb = __builtin_ctz((unsigned)rb), nrb = ny >> lrb;
     const int j = blk / nrb, y0 = (blk - j * nrb) << lrb;
@@ -394,13 +448,27 @@ __global__ __launch_bounds__(kFT) void k_fp_rows_fwd(const Inst *__restrict__ ta
     load_table<T>(tw, stage_table<T>(I.fsym, tb, true), nx);
     __syncthreads();
     const uint32_t np = (uint32_t)I.n_pix;
-    const GAS T *r = (use_in ? gp(rin) : (const GAS T *)Sel<T>::r(I)) + (size_t)j * I.n_pix;
+    GAS T *r = (use_in ? gp(const_cast<T *>(rin)) : Sel<T>::r(I)) + (size_t)j * I.n_pix;
+    const GAS T *qv = Sel<T>::q(I) + (size_t)j * I.n_pix;
     const uint32_t o0 = (uint32_t)y0 * (uint32_t)nx;
+    double rr = 0.0;
     const auto ldg = [&](int q, int i) -> Cx<T> {
         const uint32_t o = o0 + ((uint32_t)(2 * q) << ln) + (uint32_t)i;
-        return {bld(r, np, o), bld(r, np, o + (uint32_t)nx)};
+        T a = bld(r, np, o), b = bld(r, np, o + (uint32_t)nx);
+        if (upd == 2) {
+            a -= alpha * bld(qv, np, o);
+            b -= alpha * bld(qv, np, o + (uint32_t)nx);
+            bst(r, np, o, a);
+            bst(r, np, o + (uint32_t)nx, b);
+        }
+        rr += (double)a * (double)a + (double)b * (double)b;
+        return {a, b};
     };
     fft_run<T, 0, FR>(buf, tw, ln, h, true, ldg, false, NoStore<T>());
+    if (upd) {   // the ||r||^2 partial of this workgroup's rows
+        const double tot = fp_block_sum(rr);
+        if (threadIdx.x == 0) gp(I.partial)[(size_t)SLOT_RR * I.nred + blk] = tot;
+    }
     GAS T *S = spectrum<T>(I) + (size_t)2 * j * nc * ny;
     const T half = (T)0.5;
     for (int e = threadIdx.x; e < rb * nc; e += kFT) {
@@ -746,7 +814,7 @@ size_t fp_lds_bytes(int pass, int n, int m, int dtype) {
 // One application z = Fourier preconditioner of r for every instance of the set, in float32 (f32)
 // or float64.  inner: 1 = the float32 inner runs of the mixed path (their r, z and state), 0 = the
 // float64 runs, -1 = the stand-alone preconditioner (one instance, no run state): r read from
-// rin, z written to zout.
+// rin, z written to zout.  upd: see k_fp_rows_fwd (runs only).
 // The kernels are instantiated per final radix; a pass is launched once per radix class present
 // in the set (mask bit log2(FR) - 1), and workgroups of other classes return at once.
 template <typename F>
@@ -760,7 +828,7 @@ hipError_t for_each_radix(int mask, F &&fn) {
 }
 
 hipError_t launch_fp_apply(const InstSet &set, int k, int f32, int inner, const void *rin,
-                           void *zout, hipStream_t s) {
+                           void *zout, int upd, int it, hipStream_t s) {
     const int mixed = inner;
     return dispatch_k(k, [&](auto tag) -> hipError_t {
         constexpr int K = decltype(tag)::value;
@@ -771,7 +839,8 @@ hipError_t launch_fp_apply(const InstSet &set, int k, int f32, int inner, const 
                 constexpr int FR = decltype(fr)::value;
                 hipLaunchKernelGGL((k_fp_rows_fwd<T, FR>), dim3(set.total_fa), dim3(kFT), lr, s,
                                    set.table, set.fprefa, set.ninst, set.total_fa, mixed,
-                                   reinterpret_cast<const T *>(rin), rin ? 1 : 0);
+                                   reinterpret_cast<const T *>(rin), rin ? 1 : 0,
+                                   inner >= 0 ? upd : 0, it);
                 return hipGetLastError();
             });
             if (e != hipSuccess) return e;

@@ -111,6 +111,8 @@ struct Inst {
     int32_t lognx, logny;
     int32_t frb;         // grid rows per workgroup of the row passes
     int32_t nfft;        // column workgroups = nx/2 (partials of <r, z>)
+    int32_t nrr;         // partials of ||r||^2 in SLOT_RR: streaming chunks, or in float32 runs
+                         // with the Fourier preconditioner its row-pass workgroups k ny / frb
 };
 
 // Launch-time view of the instances: a device table plus prefix sums that map a flat
@@ -217,9 +219,11 @@ hipError_t launch_fp_setup(const double *W, const double *A, int f, int k, int n
                            const double *coef, double *part, double *fsym, hipStream_t s);
 // z = Fourier preconditioner of r for every instance of the set, in float32 (f32) or float64;
 // inner = 1: the float32 inner runs of the mixed path, 0: the float64 runs, -1: the stand-alone
-// preconditioner (one instance without run state: r read from rin, z written to zout).
+// preconditioner (one instance without run state: r read from rin, z written to zout).  upd
+// (runs only): 1 = start of a run (the ||r||^2 partials of r), 2 = CG iteration it, whose update
+// r -= alpha q (alpha from the apply's <p, q> partials) the forward row pass performs.
 hipError_t launch_fp_apply(const InstSet &set, int k, int f32, int inner, const void *rin,
-                           void *zout, hipStream_t s);
+                           void *zout, int upd, int it, hipStream_t s);
 // Dynamic LDS bytes of a row pass (pass 0: m rows of length n) or of the column pass (pass 1:
 // m components of length n) in precision dtype.
 size_t fp_lds_bytes(int pass, int n, int m, int dtype);

@@ -361,8 +361,8 @@ __global__ __launch_bounds__(kBlock) void k_apply(const Inst *__restrict__ tab,
     if constexpr (MODE == AM_CG) {
         double s[2];
         if (I.pc == SYLV_PC_FOURIER && !I.pre) {
-            // <r, z> from the Fourier preconditioner's column pass, ||r||^2 from the update
-            consume_pair(I.partial, I.nred, SLOT_FRZ, I.nfft, SLOT_RR, I.nchunks, s);
+            // <r, z> from the Fourier preconditioner's column pass, ||r||^2 from its row pass
+            consume_pair(I.partial, I.nred, SLOT_FRZ, I.nfft, SLOT_RR, I.nrr, s);
         } else {
             consume<2>(I.partial, I.nred, SLOT_RZ, I.pre ? 1 : I.nchunks, s);
         }
@@ -891,9 +891,9 @@ __global__ __launch_bounds__(kBlock) void k_prereduce(const Inst *__restrict__ t
     const int nb = count == 0 ? I.ntiles : count == 1 ? I.ntiles32 : I.nchunks;
     double v[NV];
     if (NV == 2 && slot0 == SLOT_RZ && I.pc == SYLV_PC_FOURIER) {
-        // <r, z> from the Fourier column pass, ||r||^2 from the streaming kernel
+        // <r, z> from the Fourier column pass, ||r||^2 from its row pass
         double w[2];
-        consume_pair(I.partial, I.nred, SLOT_FRZ, I.nfft, SLOT_RR, nb, w);
+        consume_pair(I.partial, I.nred, SLOT_FRZ, I.nfft, SLOT_RR, I.nrr, w);
         v[0] = w[0];
         v[NV - 1] = w[1];
     } else {
