@@ -377,6 +377,7 @@ struct Report {
     int running;   // runs not finished
     int iter;      // latest iteration tested among them
     double gap;    // max log2(rr / thresh) among them (0: unknown)
+    double gap0;   // max log2(rr0 / thresh) among them, at their start (0: unknown)
 };
 
 int wait_report(HostFlags *f, int slot, Report &r) {
@@ -385,6 +386,7 @@ int wait_report(HostFlags *f, int slot, Report &r) {
     r.running = p[0];
     r.iter = p[1];
     r.gap = p[2] / 256.0;
+    r.gap0 = p[3] / 256.0;
     return SYLV_OK;
 }
 
@@ -394,18 +396,22 @@ int wait_count(HostFlags *f, int slot, int &value) {
     return SYLV_OK;
 }
 
-// Iterations still to queue after those already queued (indices below `queued`), from the last
-// two completion reports: the gap to the threshold shrinks about linearly in log scale, so the
-// slowest run stops near iteration iter + gap / rate.  Returns half a batch while no rate is
-// known (a run can stop within the next few iterations: short Fourier-preconditioned runs take
-// about ten), 0 when the queued iterations should already finish every run, and otherwise the
-// estimate plus a margin, never more than `chunk`.  A short estimate costs one more host round
-// trip, an over-estimate a few early-exit launches; the result of the solve does not depend on
-// it.
-int next_batch(const Report &prev, const Report &cur, bool have_prev, int queued, int chunk) {
-    if (!have_prev || cur.iter <= prev.iter || cur.gap <= 0.0 || prev.gap <= cur.gap)
-        return std::max(2, chunk / 2);
-    const double rate = (prev.gap - cur.gap) / (cur.iter - prev.iter);
+// Iterations still to queue after those already queued (indices below `queued`): the gap to the
+// threshold shrinks about linearly in log scale, so the slowest run stops near iteration
+// iter + gap / rate, the rate taken from the last two completion reports or, after the first,
+// from the gap at the start of the run.  Returns half a batch while no rate is known (a run can
+// stop within the next few iterations: Fourier-preconditioned runs take about ten), 0 when the
+// queued iterations should already finish every run, and otherwise the estimate plus a margin,
+// never more than `chunk`.  A short estimate costs one more host round trip, an over-estimate a
+// few early-exit launches; the result of the solve does not depend on it.
+int next_batch(const Report &prev, const Report &cur, bool have_prev, bool have_cur, int queued,
+               int chunk) {
+    double rate = 0.0;
+    if (have_cur && have_prev && cur.iter > prev.iter && cur.gap > 0.0 && prev.gap > cur.gap)
+        rate = (prev.gap - cur.gap) / (cur.iter - prev.iter);
+    else if (have_cur && cur.iter > 0 && cur.gap > 0.0 && cur.gap0 > cur.gap)
+        rate = (cur.gap0 - cur.gap) / cur.iter;
+    if (!(rate > 0.0)) return std::max(2, chunk / 2);
     const double stop = cur.iter + cur.gap / rate;
     const double left = stop - (queued - 1);
     if (left <= 0.0) return 0;
@@ -466,7 +472,7 @@ int run_cg_loop(const InstSet &set, int k, int mixed, int chunk, int max_iter, H
     for (;;) {
         // keep one batch queued ahead of the report being waited for, sized by the estimate
         if (it <= max_iter && npend < 2) {
-            int n = next_batch(prev, cur, have_prev && have_cur, it, chunk);
+            int n = next_batch(prev, cur, have_prev, have_cur, it, chunk);
             if (npend == 0 && n < 4) n = 4;   // the estimate fell short: the run goes on
             if (n > 0 && (rc = enqueue_batch(n))) return rc;
         }

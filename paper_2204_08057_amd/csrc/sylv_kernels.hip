@@ -908,24 +908,27 @@ __global__ __launch_bounds__(kBlock) void k_prereduce(const Inst *__restrict__ t
 
 // Completion report for the host: out[0] = runs not finished; out[1] = the latest iteration
 // tested among them; out[2] = max over them of log2(rr / thresh) in 1/256 units (how far the
-// slowest run still is from its threshold, rounded up, 0 when unknown), from which the host sizes
-// the next batch of iterations.
+// slowest run still is from its threshold, rounded up, 0 when unknown); out[3] the same for
+// their starting residuals rr0, so that one report already gives a rate.  The host sizes the
+// next batch of iterations from them.
 __global__ void k_count_running(const Inst *__restrict__ tab, int ninst, int inner,
                                 int *__restrict__ out) {
-    __shared__ int cnt, last, gap;
-    if (threadIdx.x == 0) { cnt = 0; last = 0; gap = 0; }
+    __shared__ int cnt, last, gap, gap0;
+    if (threadIdx.x == 0) { cnt = 0; last = 0; gap = 0; gap0 = 0; }
     __syncthreads();
     for (int i = threadIdx.x; i < ninst; i += blockDim.x) {
         const DevState *st = inner ? tab[i].st_in : tab[i].st;
         if (st->done) continue;
         atomicAdd(&cnt, 1);
         atomicMax(&last, st->iter);
-        const double q = st->rr / st->thresh;
+        const double q = st->rr / st->thresh, q0 = st->rr0 / st->thresh;
         if (st->thresh > 0.0 && q > 1.0 && q < 1e300)
             atomicMax(&gap, (int)fmin(ceil(256.0 * log2(q)), 1e9));
+        if (st->thresh > 0.0 && q0 > 1.0 && q0 < 1e300)
+            atomicMax(&gap0, (int)fmin(ceil(256.0 * log2(q0)), 1e9));
     }
     __syncthreads();
-    if (threadIdx.x == 0) { out[0] = cnt; out[1] = last; out[2] = gap; }
+    if (threadIdx.x == 0) { out[0] = cnt; out[1] = last; out[2] = gap; out[3] = gap0; }
 }
 
 // Host-to-device copy of a small table through the kernel arguments: the bytes travel with the
