@@ -633,17 +633,28 @@ __global__ __launch_bounds__(kFT) void k_fp_rows_inv(const Inst *__restrict__ ta
 }
 
 // Mean over pixels of every weight map, first stage: the workgroup partials of all kMaxF rows
-// (zeros beyond f) in one reduction.
+// (zeros beyond f) in one reduction.  A workgroup sums kWChunk pixels, four consecutive pixels
+// of every map per vector load (grids here have power-of-two sides, so n_pix is a multiple of 4).
+constexpr int kWChunk = 4096;
 __global__ __launch_bounds__(kBlock) void k_wmean_part(const double *__restrict__ W, int f,
                                                        int n_pix, double *__restrict__ part) {
-    const int p0 = blockIdx.x * kChunk;
+    const int p0 = blockIdx.x * kWChunk;
     double v[kMaxF];
 #pragma unroll
     for (int fi = 0; fi < kMaxF; ++fi) {
         double s = 0.0;
-        if (fi < f)
-            for (int e = threadIdx.x; e < kChunk; e += kBlock)
-                if (p0 + e < n_pix) s += W[(size_t)fi * n_pix + p0 + e];
+        if (fi < f) {
+            const GAS double *w = gp(W) + (size_t)fi * n_pix;
+            double a[kWChunk / (4 * kBlock)][4];
+#pragma unroll
+            for (int u = 0; u < kWChunk / (4 * kBlock); ++u) {
+                const int p = p0 + (u * kBlock + threadIdx.x) * 4;
+                if (p < n_pix) ld4(w + p, a[u]);
+                else a[u][0] = a[u][1] = a[u][2] = a[u][3] = 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kWChunk / (4 * kBlock); ++u) s += (a[u][0] + a[u][1]) + (a[u][2] + a[u][3]);
+        }
         v[fi] = s;
     }
     block_partials<kMaxF>(v, part, (int)gridDim.x, 0, blockIdx.x);
@@ -780,7 +791,7 @@ size_t fp_table_bytes(int nx, int ny) { return sizeof(double) * fp_tabs(nx, ny).
 hipError_t launch_fp_setup(const double *W, const double *A, int f, int k, int nx, int ny,
                            const double *coef, double *part, double *fsym, hipStream_t s) {
     const int n_pix = nx * ny;
-    const int nblk = (int)blocks_for(n_pix, kChunk);
+    const int nblk = (int)blocks_for(n_pix, kWChunk);
     hipLaunchKernelGGL(k_wmean_part, dim3(nblk), dim3(kBlock), 0, s, W, f, n_pix, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -795,7 +806,7 @@ hipError_t launch_fp_setup(const double *W, const double *A, int f, int k, int n
 
 size_t fp_setup_partials(int n_pix, int f) {
     (void)f;
-    return (size_t)blocks_for(n_pix, kChunk) * kMaxF;
+    return (size_t)blocks_for(n_pix, kWChunk) * kMaxF;
 }
 
 bool fp_cols_global_twiddles(int ny, int k, int dtype) {
