@@ -300,3 +300,49 @@ def test_graph_face_batch(precision, bound):
         n = p.k * p.n_pix
         assert rel(Xh[off:off + n].reshape(p.k, p.n_pix), osv.solve_dense(p)) < bound, i
         off += n
+
+
+@pytest.mark.parametrize("precision,bound", PRECISIONS)
+def test_graph_fourier_preconditioner(precision, bound):
+    """Fourier-preconditioned solves: the fixed schedule equals the adaptive one bitwise, and a
+    captured solve replays bitwise equal to the eager call, also after new data in place."""
+    p = make_problem(64, 32, 3, 6, seed=7400, noise="hetero", mask_frac=0.1)
+    dp = sy.DeviceProblem.from_numpy(p)
+    Yd = dev(p.Y)
+    fixed = opts_for(precision, sy.SYLV_SCHED_FIXED, precond=sy.SYLV_PC_FOURIER, max_iter=60)
+    adaptive = opts_for(precision, sy.SYLV_SCHED_ADAPTIVE, precond=sy.SYLV_PC_FOURIER,
+                        max_iter=60)
+    say("fourier fixed vs adaptive", precision)
+    Xa, sa = sy.pcg_solve(dp, Y=Yd, opts=adaptive)
+    Xf, sf = sy.pcg_solve(dp, Y=Yd, opts=fixed)
+    assert sa[0]["status"] == 0, sa
+    assert sf == sa and torch.equal(Xf, Xa)
+    assert rel(host(Xa).reshape(p.k, p.n_pix), osv.solve_dense(p)) < bound
+    X, stats, ws = buffers([dp], 1, fixed)
+    launch = sy.solve_launcher(dp, X, stats, ws, Y=Yd, opts=fixed)
+
+    def solve():
+        X.zero_()
+        launch()
+
+    solve()
+    torch.cuda.synchronize()
+    Xe, se = X.clone(), sy.stats_list(stats, 1)
+    assert torch.equal(Xe.reshape(p.k, p.n_pix), Xa)
+    g = capture(solve)
+    for rep in range(3):
+        X.fill_(2.0e3 + rep)
+        stats.zero_()
+        torch.cuda.synchronize()
+        say("fourier replay", rep)
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(X, Xe), rep
+        assert sy.stats_list(stats, 1) == se, rep
+    Y2 = p.Y * 0.5 + np.random.default_rng(7401).standard_normal(p.Y.shape)
+    Yd.copy_(dev(Y2))
+    g.replay()
+    torch.cuda.synchronize()
+    X2, s2 = sy.pcg_solve(dp, Y=dev(Y2), opts=adaptive)
+    assert torch.equal(X.reshape(p.k, p.n_pix), X2)
+    assert sy.stats_list(stats, 1) == s2
