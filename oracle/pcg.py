@@ -51,29 +51,42 @@ def block_jacobi(prob, G=None, kind: str = "block"):
 
 
 def fourier_preconditioner(prob):
-    """Minv = (Q + I (x) Mbar)^-1 applied through the 2-D DFT, on periodic grids.
+    """Minv = (Q + I (x) Mbar)^-1 applied mode by mode in the basis that diagonalises the grid
+    Laplacian: the 2-D DFT on periodic grids, the 2-D cosine transform (DCT-II) on face grids.
 
-    Each prior block Q_j = tau_j (kappa_j^2 I - Lap)^2 is a polynomial in the periodic Laplacian,
-    so the DFT diagonalises it: the mode whose -Lap eigenvalue is lam gets tau_j (kappa_j^2 +
-    lam)^2.  The data term's per-pixel blocks M_p = sum_f W[f, p] a_f a_f^T are replaced by their
-    mean over pixels, Mbar = sum_f mean_p(W[f, :]) a_f a_f^T, so one k x k block remains per mode
-    (a fixed SPD operator; the paper allows any preconditioner, Section 3.2, remarks after
-    Alg. 2).  When W does not depend on the pixel this is G^-1 exactly.
+    Each prior block Q_j = tau_j (kappa_j^2 I - Lap)^2 is a polynomial in the Laplacian, so the
+    mode whose -Lap eigenvalue is lam gets tau_j (kappa_j^2 + lam)^2.  Periodic grid: the Fourier
+    modes, lam = 4 - 2 cos(2 pi u / nx) - 2 cos(2 pi v / ny).  Face grid (links only inside the
+    grid): -Lap is the Kronecker sum of two path-graph Laplacians, whose eigenvectors are the
+    cosines cos(pi u (i + 1/2) / n), lam = 2 - 2 cos(pi u / nx) + 2 - 2 cos(pi v / ny).  The data
+    term's per-pixel blocks M_p = sum_f W[f, p] a_f a_f^T are replaced by their mean over pixels,
+    Mbar = sum_f mean_p(W[f, :]) a_f a_f^T, so one k x k block remains per mode (a fixed SPD
+    operator; the paper allows any preconditioner, Section 3.2, remarks after Alg. 2).  When W
+    does not depend on the pixel this is G^-1 exactly.
     Returns a function r[k, n_pix] -> z[k, n_pix]."""
+    from scipy import fft as sfft
     from .solve import fourier_symbols
-    if op.boundary_of(prob) != "periodic":
-        raise ValueError("the Fourier preconditioner needs a periodic grid")
     k, ny, nx = prob.k, prob.ny, prob.nx
+    face = op.boundary_of(prob) == "face"
     wbar = prob.W.mean(axis=1)                          # [f]
     mbar = (prob.A.T * wbar) @ prob.A                   # sum_f wbar_f a_f a_f^T, [k, k]
-    lam = fourier_symbols(prob)                         # [ny, nx]
+    if face:
+        lam = ((2.0 - 2.0 * np.cos(np.pi * np.arange(nx) / nx))[None, :]
+               + (2.0 - 2.0 * np.cos(np.pi * np.arange(ny) / ny))[:, None])
+    else:
+        lam = fourier_symbols(prob)                     # [ny, nx]
     blk = np.broadcast_to(mbar, (ny, nx, k, k)).copy()
     for j in range(k):
         blk[:, :, j, j] += prob.tau[j] * (prob.kappa[j] ** 2 + lam) ** 2
     inv = np.linalg.inv(blk)                            # [ny, nx, k, k]
 
     def apply_inv(r):
-        rh = np.fft.fft2(np.asarray(r, dtype=np.float64).reshape(k, ny, nx), axes=(1, 2))
+        rr = np.asarray(r, dtype=np.float64).reshape(k, ny, nx)
+        if face:
+            rh = sfft.dctn(rr, type=2, norm="ortho", axes=(1, 2))
+            zh = np.einsum("yxij,jyx->iyx", inv, rh)
+            return sfft.idctn(zh, type=2, norm="ortho", axes=(1, 2)).reshape(k, ny * nx)
+        rh = np.fft.fft2(rr, axes=(1, 2))
         zh = np.einsum("yxij,jyx->iyx", inv, rh)
         return np.fft.ifft2(zh, axes=(1, 2)).real.reshape(k, ny * nx)
 

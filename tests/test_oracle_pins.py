@@ -446,7 +446,47 @@ def test_fourier_pcg_matches_dense_in_fewer_iterations():
     assert rf["iters"] < rb["iters"] / 2, (rf["iters"], rb["iters"])
 
 
-def test_fourier_preconditioner_refuses_face_grids():
-    p = make_problem(6, 6, 2, 3, seed=9040, noise="hetero", boundary="face")
-    with pytest.raises(ValueError):
-        opcg.fourier_preconditioner(p)
+@pytest.mark.parametrize("n", [1, 2, 5, 8])
+def test_path_laplacian_cosine_eigenpairs(n):
+    """The face grid's Laplacian along one side is a path-graph Laplacian; the cosines
+    cos(pi u (i + 1/2) / n) are its eigenvectors with eigenvalue 2 - 2 cos(pi u / n) (brute
+    force on a 1 x n face)."""
+    L = -op.laplacian(1, n, "face").toarray()
+    i = np.arange(n)
+    for u in range(n):
+        v = np.cos(np.pi * u * (i + 0.5) / n)
+        assert np.linalg.norm(L @ v - (2 - 2 * np.cos(np.pi * u / n)) * v) <= 1e-13 * n
+
+
+@pytest.mark.parametrize("shape", [(8, 8), (6, 10), (5, 3), (1, 7), (2, 2)])
+def test_cosine_preconditioner_inverts_homoscedastic_face_operator(shape):
+    """On a face grid the preconditioner works in the cosine basis; with W independent of the
+    pixel it is G^-1 of the assembled face operator."""
+    p = make_problem(shape[0], shape[1], 3, 5, seed=9040 + shape[0], noise="homo",
+                     boundary="face")
+    R = np.random.default_rng(9041).standard_normal((p.k, p.n_pix))
+    Z = opcg.fourier_preconditioner(p)(R)
+    G = op.posterior_precision(p)
+    assert np.linalg.norm((G @ Z.ravel()).reshape(p.k, p.n_pix) - R) <= 1e-11 * np.linalg.norm(R)
+
+
+def test_cosine_preconditioner_face_spd_and_pixel_mean():
+    p = make_problem(5, 4, 2, 3, seed=9050, noise="hetero", mask_frac=0.1, boundary="face")
+    Minv = opcg.fourier_preconditioner(p)
+    n = p.k * p.n_pix
+    P = np.array([Minv(np.eye(n)[i].reshape(p.k, p.n_pix)).ravel() for i in range(n)]).T
+    assert np.abs(P - P.T).max() <= 1e-13 * np.abs(P).max()
+    assert np.linalg.eigvalsh(0.5 * (P + P.T)).min() > 0
+    q = make_problem(5, 4, 2, 3, seed=9050, noise="hetero", mask_frac=0.1, boundary="face")
+    q.W = np.repeat(p.W.mean(axis=1, keepdims=True), p.n_pix, axis=1)
+    R = np.random.default_rng(9051).standard_normal((p.k, p.n_pix))
+    assert np.linalg.norm(op.apply(q, Minv(R)) - R) <= 1e-11 * np.linalg.norm(R)
+
+
+def test_cosine_pcg_on_face_grid_matches_dense_in_fewer_iterations():
+    p = make_problem(32, 24, 3, 6, seed=9060, noise="hetero", mask_frac=0.1, boundary="face")
+    xd = osv.solve_dense(p)
+    rf = opcg.pcg(p, tol=1e-11, precond="fourier")
+    rb = opcg.pcg(p, tol=1e-11, precond="block")
+    assert np.linalg.norm(rf["x"] - xd) <= 1e-8 * np.linalg.norm(xd)
+    assert rf["iters"] < rb["iters"] / 2, (rf["iters"], rb["iters"])
