@@ -122,11 +122,11 @@ struct Layout {
 };
 
 // Whether a grid can take the Fourier preconditioner in some precision (the stand-alone
-// workspace then holds its spectrum), and the half spectrum's bytes (complex float64).
+// workspace then holds its spectrum), and the spectrum's bytes (complex float64 half spectrum;
+// the cosine coefficients of face grids take less).
 bool fp_grid(const sylv_problem &p) {
     char why[160];
-    return p.boundary == SYLV_BC_PERIODIC &&
-           fp_supported((int)p.ny, (int)p.nx, p.k, SYLV_F32, why, sizeof(why));
+    return fp_supported((int)p.ny, (int)p.nx, p.k, SYLV_F32, why, sizeof(why));
 }
 size_t fp_spectrum_bytes(const sylv_problem &p) {
     return (size_t)16 * p.k * (size_t)(p.nx / 2 + 1) * (size_t)p.ny;
@@ -279,7 +279,8 @@ int prepare_operator(const sylv_problem &p, const ProbLayout &P, char *base, int
                          reinterpret_cast<float *>(base + P.P32),
                          reinterpret_cast<unsigned short *>(base + P.P16), exact, p.k, s));
     if (pc == SYLV_PC_FOURIER)
-        HIP_TRY(launch_fp_setup(p.W, p.A, p.f, p.k, (int)p.nx, (int)p.ny, coef,
+        HIP_TRY(launch_fp_setup(p.W, p.A, p.f, p.k, (int)p.nx, (int)p.ny,
+                                p.boundary == SYLV_BC_FACE ? 1 : 0, coef,
                                 reinterpret_cast<double *>(base + P.fpart),
                                 reinterpret_cast<double *>(base + P.fsym), s));
     return SYLV_OK;
@@ -566,7 +567,6 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
         const int dt = opts->precision == SYLV_PREC_MIXED ? SYLV_F32 : SYLV_F64;
         for (int g = 0; g < nprob; ++g) {
             char why[200];
-            if (probs[g].boundary != SYLV_BC_PERIODIC) { set_err("problem %d: the Fourier preconditioner needs a periodic grid", g); return SYLV_E_INVALID; }
             if (!fp_supported((int)probs[g].ny, (int)probs[g].nx, k, dt, why, sizeof(why))) {
                 set_err("problem %d: %s", g, why);
                 return SYLV_E_INVALID;
@@ -1579,7 +1579,7 @@ int sylv_prepare(const sylv_problem *prob, int32_t precond, void *ws, size_t ws_
     if (!check_problem(prob, 0)) return SYLV_E_INVALID;
     if (precond < SYLV_PC_NONE || precond > SYLV_PC_FOURIER) { set_err("bad precond"); return SYLV_E_INVALID; }
     if (precond == SYLV_PC_FOURIER && !fp_grid(*prob)) {
-        set_err("the Fourier preconditioner needs a periodic grid whose sides are powers of two in [4, 4096]");
+        set_err("the Fourier preconditioner needs grid sides that are powers of two in [4, 4096]");
         return SYLV_E_INVALID;
     }
     Layout L;
@@ -1631,7 +1631,6 @@ int sylv_precond(const sylv_problem *prob, int32_t dtype, int32_t precond, const
     if (precond < SYLV_PC_NONE || precond > SYLV_PC_FOURIER) { set_err("bad precond"); return SYLV_E_INVALID; }
     if (precond == SYLV_PC_FOURIER) {
         char why[200];
-        if (prob->boundary != SYLV_BC_PERIODIC) { set_err("the Fourier preconditioner needs a periodic grid"); return SYLV_E_INVALID; }
         if (!fp_supported((int)prob->ny, (int)prob->nx, prob->k, dtype, why, sizeof(why))) { set_err("%s", why); return SYLV_E_INVALID; }
     }
     if (!R || !Z || nrhs < 1) { set_err("null R/Z or nrhs < 1"); return SYLV_E_INVALID; }
@@ -1678,6 +1677,7 @@ int sylv_precond(const sylv_problem *prob, int32_t dtype, int32_t precond, const
         set.fp_cols_gtw = fp_cols_global_twiddles(I.ny, k, dtype) ? 1 : 0;
         set.fp_rmask_x = fp_radix_bit(I.lognx);
         set.fp_rmask_y = fp_radix_bit(I.logny);
+        set.bc = prob->boundary;
         const size_t es = dtype == SYLV_F64 ? 8 : 4, plane = (size_t)k * I.n_pix * es;
         for (int r = 0; r < nrhs; ++r)
             HIP_TRY(launch_fp_apply(set, k, dtype == SYLV_F32, -1,

@@ -71,24 +71,31 @@ static_assert(kFT == 8 * 64, "fp_block_sum sums eight wavefronts");
 // ---- set-up tables (per problem, after the symbol block) --------------------------------------
 // In doubles from the start of the problem's Fourier region:
 //   [0, kSymDoubles)   Mbar [kMaxK][kMaxK], kappa_j^2 [kMaxK], tau_j [kMaxK]
-//   lamx[c] = 2 - 2 cos(2 pi c / nx), c in [0, nx/2];  lamy[v] = 2 - 2 cos(2 pi v / ny), v < ny
+//   lamx[u], u < nx, and lamy[v], v < ny: the Laplacian eigenvalue of each side's modes,
+//   2 - 2 cos(2 pi u / nx) on periodic grids, 2 - 2 cos(pi u / nx) on face grids (cosines)
 //   Stockham twiddles for n = nx and n = ny, complex double, then complex float (n - 1 entries
 //   each, padded to n): stage s (radix R, ns = product of the earlier radices) holds
-//   W_(ns R)^(r kk) at [off_s + (r - 1) ns + kk], r in [1, R), kk in [0, ns).
+//   W_(ns R)^(r kk) at [off_s + (r - 1) ns + kk], r in [1, R), kk in [0, ns)
+//   face grids: exp(-i pi u / 2n), u < n, for n = nx and n = ny, complex double then float (the
+//   cosine transform's twiddles)
 constexpr int kSymDoubles = kMaxK * kMaxK + 2 * kMaxK;
 __host__ __device__ constexpr size_t round4(size_t v) { return (v + 3) & ~(size_t)3; }
 struct FpTabs {
-    size_t lamx, lamy, twx64, twy64, twx32, twy32, total;   // offsets / total, in doubles
+    size_t lamx, lamy, twx64, twy64, twx32, twy32, ctx64, cty64, ctx32, cty32, total;   // doubles
 };
 __host__ __device__ inline FpTabs fp_tabs(int nx, int ny) {
     FpTabs t;
     size_t o = round4(kSymDoubles);
-    t.lamx = o;  o = round4(o + nx / 2 + 1);
+    t.lamx = o;  o = round4(o + nx);
     t.lamy = o;  o = round4(o + ny);
     t.twx64 = o; o = round4(o + 2 * (size_t)nx);
     t.twy64 = o; o = round4(o + 2 * (size_t)ny);
     t.twx32 = o; o = round4(o + (size_t)nx);
     t.twy32 = o; o = round4(o + (size_t)ny);
+    t.ctx64 = o; o = round4(o + 2 * (size_t)nx);
+    t.cty64 = o; o = round4(o + 2 * (size_t)ny);
+    t.ctx32 = o; o = round4(o + (size_t)nx);
+    t.cty32 = o; o = round4(o + (size_t)ny);
     t.total = o;
     return t;
 }
@@ -96,6 +103,20 @@ template <typename T>
 __device__ __forceinline__ const Cx<T> *stage_table(const double *base, const FpTabs &t, bool x) {
     if (sizeof(T) == 8) return reinterpret_cast<const Cx<T> *>(base + (x ? t.twx64 : t.twy64));
     return reinterpret_cast<const Cx<T> *>(base + (x ? t.twx32 : t.twy32));
+}
+
+template <typename T>
+__device__ __forceinline__ const Cx<T> *cos_table(const double *base, const FpTabs &t, bool x) {
+    if (sizeof(T) == 8) return reinterpret_cast<const Cx<T> *>(base + (x ? t.ctx64 : t.cty64));
+    return reinterpret_cast<const Cx<T> *>(base + (x ? t.ctx32 : t.cty32));
+}
+
+// The cosine transform (DCT-II, X[u] = sum_i x[i] cos(pi u (2i + 1) / 2n)) of a real sequence
+// comes from one complex FFT of the reordered sequence v[m] = x[cos_src(m)] (even samples
+// forward, odd samples backward): X[u] = Re(exp(-i pi u / 2n) V[u]).  The inverse forms
+// V[u] = exp(i pi u / 2n) (X[u] - i X[n - u]) (X[n] = 0), transforms back and undoes the order.
+__device__ __forceinline__ int cos_src(int m, int n) {
+    return m < (n >> 1) ? 2 * m : 2 * (n - 1 - m) + 1;
 }
 
 // log2 of the radix of the stage that starts at log2-position lg of a length-2^logn transform:
@@ -342,6 +363,42 @@ struct ModeSolver {
             for (int b = 0; b < K; ++b) mb[a][b] = (T)fd[a * kMaxK + b];
         }
     }
+    // real right-hand side (cosine modes)
+    __device__ void solve_re(T lam, const T (&rh)[K], T (&zh)[K]) const {
+        T l[K][K], id[K];
+        factor(lam, l, id);
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            T s = rh[a];
+#pragma unroll
+            for (int q = 0; q < a; ++q) s -= l[a][q] * zh[q];
+            zh[a] = s * id[a];
+        }
+#pragma unroll
+        for (int a = K - 1; a >= 0; --a) {
+            T s = zh[a];
+#pragma unroll
+            for (int q = a + 1; q < K; ++q) s -= l[q][a] * zh[q];
+            zh[a] = s * id[a];
+        }
+    }
+    __device__ void factor(T lam, T (&l)[K][K], T (&id)[K]) const {
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+#pragma unroll
+            for (int b = 0; b <= a; ++b) {
+                T s = mb[a][b];
+                if (a == b) {
+                    const T u = k2[a] + lam;
+                    s += ta[a] * u * u;
+                }
+#pragma unroll
+                for (int q = 0; q < b; ++q) s -= l[a][q] * l[b][q];
+                if (a == b) id[a] = rsqrt_t(s);
+                else l[a][b] = s * id[b];
+            }
+        }
+    }
     __device__ void solve(T lam, const Cx<T> (&rh)[K], Cx<T> (&zh)[K]) const {
         T l[K][K], id[K];
 #pragma unroll
@@ -377,6 +434,14 @@ struct ModeSolver {
 };
 
 template <typename T, int K>
+__device__ __forceinline__ double dot_r(const T (&a)[K], const T (&b)[K]) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < K; ++q) s += (double)a[q] * (double)b[q];
+    return s;
+}
+
+template <typename T, int K>
 __device__ __forceinline__ double dot_re(const Cx<T> (&a)[K], const Cx<T> (&b)[K]) {
     double s = 0.0;
 #pragma unroll
@@ -394,7 +459,9 @@ __device__ __forceinline__ double dot_re(const Cx<T> (&a)[K], const Cx<T> (&b)[K
 // first performs the update of iteration `it` (upd = 2): alpha = rho / <p, q> from the apply's
 // partials (stop and breakdown handled as the streaming update kernel does), r -= alpha q as
 // the first stage loads r and q, r written back.
-template <typename T, int FR>
+// DCT (face grids): the rows' cosine transforms instead, from the reordered rows; the nx real
+// coefficients of each row are stored transposed, S[j][u][y], u < nx, two rows per 8-byte store.
+template <typename T, int FR, bool DCT>
 __global__ __launch_bounds__(kFT) void k_fp_rows_fwd(const Inst *__restrict__ tab,
                                                      const int *__restrict__ fpre, int ninst,
                                                      int nb, int inner,
@@ -453,7 +520,7 @@ __global__ __launch_bounds__(kFT) void k_fp_rows_fwd(const Inst *__restrict__ ta
     const uint32_t o0 = (uint32_t)y0 * (uint32_t)nx;
     double rr = 0.0;
     const auto ldg = [&](int q, int i) -> Cx<T> {
-        const uint32_t o = o0 + ((uint32_t)(2 * q) << ln) + (uint32_t)i;
+        const uint32_t o = o0 + ((uint32_t)(2 * q) << ln) + (uint32_t)(DCT ? cos_src(i, nx) : i);
         T a = bld(r, np, o), b = bld(r, np, o + (uint32_t)nx);
         if (upd == 2) {
             a -= alpha * bld(qv, np, o);
@@ -468,6 +535,25 @@ __global__ __launch_bounds__(kFT) void k_fp_rows_fwd(const Inst *__restrict__ ta
     if (upd) {   // the ||r||^2 partial of this workgroup's rows
         const double tot = fp_block_sum(rr);
         if (threadIdx.x == 0) gp(I.partial)[(size_t)SLOT_RR * I.nred + blk] = tot;
+    }
+    if (DCT) {
+        // rows 2q, 2q+1: V_2q[u] = (U[u] + conj U[-u]) / 2, V_(2q+1)[u] = (U[u] - conj U[-u]) / 2i,
+        // X[u] = Re(exp(-i pi u / 2nx) V[u])
+        GAS T *Sr = spectrum<T>(I) + (size_t)j * nx * ny;
+        const Cx<T> *ct = cos_table<T>(I.fsym, tb, true);
+        const int lh = lrb - 1;
+        const T hf = (T)0.5;
+        for (int e = threadIdx.x; e < (nx << lh); e += kFT) {
+            const int u = e >> lh, q = e & (h - 1);
+            const Cx<T> U = buf[lpad((q << ln) + u)];
+            const Cx<T> M = buf[lpad((q << ln) + ((nx - u) & (nx - 1)))];
+            const Cx<T> va = {hf * (U.x + M.x), hf * (U.y - M.y)};
+            const Cx<T> vb = {hf * (U.y + M.y), hf * (M.x - U.x)};
+            const Cx<T> w = ct[u];
+            cstore(Sr, ((size_t)u * ny + y0) / 2 + q,
+                   Cx<T>{w.x * va.x - w.y * va.y, w.x * vb.x - w.y * vb.y});
+        }
+        return;
     }
     GAS T *S = spectrum<T>(I) + (size_t)2 * j * nc * ny;
     const T half = (T)0.5;
@@ -491,7 +577,12 @@ __global__ __launch_bounds__(kFT) void k_fp_rows_fwd(const Inst *__restrict__ ta
 // modes v and -v together (Z[-v] = conj Z[v] for both columns), so no mode is shared.
 // GTW: the stage twiddles are read from the set-up table in global memory (when the table and
 // the column do not both fit in LDS; float64 columns of 8192 values).
-template <typename T, int K, int FR, bool GTW>
+// DCT (face grids): workgroup c takes the real coefficient columns u0 = 2c and u1 = 2c + 1 of
+// pass A as one complex column, transforms it by the cosine transform along y (reordered, FFT,
+// split into the two columns' spectra, twiddled), solves the real k x k system of each of the
+// four modes (u0, v), (u0, -v), (u1, v), (u1, -v) a thread owns, and transforms back.  <r, z> by
+// Parseval with the orthonormal weights (1 or 2) / n of each side.
+template <typename T, int K, int FR, bool GTW, bool DCT>
 __global__ __launch_bounds__(kFT, (sizeof(T) == 8 || K > 5) ? 2 : 4) void k_fp_cols(
     const Inst *__restrict__ tab, const int *__restrict__ fpre, int ninst, int nb, int inner) {
     extern __shared__ __align__(16) unsigned char fp_lds[];
@@ -515,6 +606,69 @@ __global__ __launch_bounds__(kFT, (sizeof(T) == 8 || K > 5) ? 2 : 4) void k_fp_c
     ModeSolver<T, K> ms;
     ms.load(I.fsym);
     double rz = 0.0;
+    if constexpr (DCT) {
+        const int u0 = 2 * c, u1 = 2 * c + 1;
+        const size_t pl = (size_t)nx * ny;   // one component's coefficients
+        const auto ldg = [&](int a, int y) -> Cx<T> {
+            const size_t o = a * pl + cos_src(y, ny);
+            return {S[o + (size_t)u0 * ny], S[o + (size_t)u1 * ny]};
+        };
+        fft_run<T, 0, FR>(buf, tw, ln, K, true, ldg, false, NoStore<T>());
+        const Cx<T> *ct = cos_table<T>(I.fsym, tb, false);
+        const T lx0 = (T)I.fsym[tb.lamx + u0], lx1 = (T)I.fsym[tb.lamx + u1];
+        const double wx0 = (u0 == 0 ? 1.0 : 2.0) / nx, wx1 = 2.0 / nx;
+        const T hf = (T)0.5;
+        for (int v = threadIdx.x; v <= ny / 2; v += kFT) {
+            const int w = (ny - v) & (ny - 1);
+            const Cx<T> tv = ct[v], tw2 = ct[w];
+            T c0v[K], c1v[K], c0w[K], c1w[K];
+#pragma unroll
+            for (int a = 0; a < K; ++a) {
+                const Cx<T> P = buf[lpad((a << ln) + v)], M = buf[lpad((a << ln) + w)];
+                const Cx<T> va = {hf * (P.x + M.x), hf * (P.y - M.y)};
+                const Cx<T> vb = {hf * (P.y + M.y), hf * (M.x - P.x)};
+                c0v[a] = tv.x * va.x - tv.y * va.y;     // Re(t_v V0[v])
+                c1v[a] = tv.x * vb.x - tv.y * vb.y;
+                c0w[a] = tw2.x * va.x + tw2.y * va.y;   // Re(t_w conj V0[v]) = Re(t_w V0[w])
+                c1w[a] = tw2.x * vb.x + tw2.y * vb.y;
+            }
+            const T lyv = (T)lamy[v], lyw = (T)lamy[w];
+            const double wyv = (v == 0 ? 1.0 : 2.0) / ny, wyw = (w == 0 ? 1.0 : 2.0) / ny;
+            T z0v[K], z1v[K], z0w[K], z1w[K];
+            ms.solve_re(lx0 + lyv, c0v, z0v);
+            ms.solve_re(lx1 + lyv, c1v, z1v);
+            rz += wx0 * wyv * dot_r<T, K>(c0v, z0v) + wx1 * wyv * dot_r<T, K>(c1v, z1v);
+            if (w != v) {
+                ms.solve_re(lx0 + lyw, c0w, z0w);
+                ms.solve_re(lx1 + lyw, c1w, z1w);
+                rz += wx0 * wyw * dot_r<T, K>(c0w, z0w) + wx1 * wyw * dot_r<T, K>(c1w, z1w);
+            }
+#pragma unroll
+            for (int a = 0; a < K; ++a) {
+                // V[v] = conj(t_v) (Z[v] - i Z[ny - v]) with Z[ny] = 0; U' = V0 + i V1
+                const T m0 = v == 0 ? (T)0 : (w == v ? z0v[a] : z0w[a]);
+                const T m1 = v == 0 ? (T)0 : (w == v ? z1v[a] : z1w[a]);
+                const Cx<T> a0 = {tv.x * z0v[a] - tv.y * m0, -tv.y * z0v[a] - tv.x * m0};
+                const Cx<T> a1 = {tv.x * z1v[a] - tv.y * m1, -tv.y * z1v[a] - tv.x * m1};
+                buf[lpad((a << ln) + v)] = {a0.x - a1.y, a0.y + a1.x};
+                if (w != v) {
+                    const Cx<T> b0 = {tw2.x * z0w[a] - tw2.y * z0v[a], -tw2.y * z0w[a] - tw2.x * z0v[a]};
+                    const Cx<T> b1 = {tw2.x * z1w[a] - tw2.y * z1v[a], -tw2.y * z1w[a] - tw2.x * z1v[a]};
+                    buf[lpad((a << ln) + w)] = {b0.x - b1.y, b0.y + b1.x};
+                }
+            }
+        }
+        __syncthreads();
+        const auto stg = [&](int a, int m, Cx<T> val) {
+            const size_t o = a * pl + cos_src(m, ny);
+            S[o + (size_t)u0 * ny] = val.x;
+            S[o + (size_t)u1 * ny] = val.y;
+        };
+        fft_run<T, 1, FR>(buf, tw, ln, K, false, NoLoad<T>(), true, stg);
+        const double tot = fp_block_sum(rz);
+        if (I.partial && threadIdx.x == 0) gp(I.partial)[(size_t)SLOT_FRZ * I.nred + c] = tot;
+        return;
+    }
     // column c (c > 0), or the real columns 0 and nx/2 packed as re + i im (c = 0)
     const auto ldg = [&](int a, int y) -> Cx<T> {
         if (c > 0) return cload(S, ((size_t)a * nc + c) * ny + y);
@@ -575,7 +729,10 @@ __global__ __launch_bounds__(kFT, (sizeof(T) == 8 || K > 5) ? 2 : 4) void k_fp_c
 // and R_(2q+1) the half spectra of the two rows, U[c] = R_2q[c] + i R_(2q+1)[c] and U[-c] =
 // conj R_2q[c] + i conj R_(2q+1)[c]; the inverse FFT of U is r_2q + i r_(2q+1) (times nx), and
 // z = those parts / (nx ny), written by the last stage.
-template <typename T, int FR>
+// DCT (face grids): the rows' inverse cosine transforms: U[u] = V_2q[u] + i V_(2q+1)[u] with
+// V[u] = exp(i pi u / 2nx) (Z[u] - i Z[nx - u]), the inverse FFT, and the reorder undone as the
+// last stage writes z.
+template <typename T, int FR, bool DCT>
 __global__ __launch_bounds__(kFT) void k_fp_rows_inv(const Inst *__restrict__ tab,
                                                      const int *__restrict__ fpre, int ninst,
                                                      int nb, int inner, T *__restrict__ zout,
@@ -594,9 +751,41 @@ __global__ __launch_bounds__(kFT) void k_fp_rows_inv(const Inst *__restrict__ ta
     Cx<T> *buf = tw + nx;
     const FpTabs tb = fp_tabs(nx, ny);
     load_table<T>(tw, stage_table<T>(I.fsym, tb, true), nx);
+    const int lh = lrb - 1;
+    if (DCT) {
+        const GAS T *Sr = spectrum<T>(I) + (size_t)j * nx * ny;
+        const Cx<T> *ct = cos_table<T>(I.fsym, tb, true);
+        for (int e = threadIdx.x; e < ((nx / 2 + 1) << lh); e += kFT) {
+            const int u = e >> lh, q = e & (h - 1), um = (nx - u) & (nx - 1);
+            const Cx<T> zu = cload(Sr, ((size_t)u * ny + y0) / 2 + q);   // (Z_2q[u], Z_2q+1[u])
+            const Cx<T> zm = u == 0 ? Cx<T>{(T)0, (T)0} : cload(Sr, ((size_t)um * ny + y0) / 2 + q);
+            const Cx<T> t = ct[u];
+            const Cx<T> a0 = {t.x * zu.x - t.y * zm.x, -t.y * zu.x - t.x * zm.x};
+            const Cx<T> a1 = {t.x * zu.y - t.y * zm.y, -t.y * zu.y - t.x * zm.y};
+            buf[lpad((q << ln) + u)] = {a0.x - a1.y, a0.y + a1.x};
+            if (u != 0 && um != u) {
+                const Cx<T> tm = ct[um];
+                const Cx<T> b0 = {tm.x * zm.x - tm.y * zu.x, -tm.y * zm.x - tm.x * zu.x};
+                const Cx<T> b1 = {tm.x * zm.y - tm.y * zu.y, -tm.y * zm.y - tm.x * zu.y};
+                buf[lpad((q << ln) + um)] = {b0.x - b1.y, b0.y + b1.x};
+            }
+        }
+        __syncthreads();
+        const T scale = (T)(1.0 / ((double)nx * (double)ny));
+        const uint32_t np = (uint32_t)I.n_pix;
+        GAS T *z = (use_out ? gp(zout) : gp(Sel<T>::z(I))) + (size_t)j * I.n_pix;
+        const uint32_t o0 = (uint32_t)y0 * (uint32_t)nx;
+        const auto stg = [&](int q, int m, Cx<T> v) {
+            const uint32_t o = o0 + ((uint32_t)(2 * q) << ln) + (uint32_t)cos_src(m, nx);
+            bst(z, np, o, v.x * scale);
+            bst(z, np, o + (uint32_t)nx, v.y * scale);
+        };
+        fft_run<T, 1, FR>(buf, tw, ln, h, false, NoLoad<T>(), true, stg);
+        return;
+    }
     const GAS T *S = spectrum<T>(I) + (size_t)2 * j * nc * ny;
     // stage: unit u = rows 2q, 2q + 1 of column c = u / h (one 4-vector)
-    const int lh = lrb - 1, units = nc << lh;
+    const int units = nc << lh;
     constexpr int G = sizeof(T) == 8 ? 4 : 8;
     for (int u0 = 0; u0 < units; u0 += G * kFT) {
         T a[G][4];
@@ -706,19 +895,22 @@ __device__ void stage_entry(int n, int e, double *t64, float *t32) {
         lg += lr;
     }
 }
-// The Laplacian eigenvalue tables and the stage tables of both grid sides: thread e of the grid
-// writes entry e of lamx | lamy | stage table of nx | stage table of ny.
-__global__ __launch_bounds__(kBlock) void k_fp_tables(int nx, int ny, double *__restrict__ base) {
+// The Laplacian eigenvalue tables, the stage tables of both grid sides and, on face grids, the
+// cosine twiddles: thread e of the grid writes entry e of lamx | lamy | stage table of nx |
+// stage table of ny | cosine twiddles of nx | of ny.
+__global__ __launch_bounds__(kBlock) void k_fp_tables(int nx, int ny, int face,
+                                                      double *__restrict__ base) {
     const FpTabs tb = fp_tabs(nx, ny);
-    const int nlx = nx / 2 + 1;
+    // periodic: 2 - 2 cos(2 pi u / n); face: 2 - 2 cos(pi u / n)
+    const double f = face ? 1.0 : 2.0;
     int e = blockIdx.x * kBlock + threadIdx.x;
-    if (e < nlx) {
-        base[tb.lamx + e] = 2.0 - 2.0 * cospi(2.0 * (double)e / (double)nx);
+    if (e < nx) {
+        base[tb.lamx + e] = 2.0 - 2.0 * cospi(f * (double)e / (double)nx);
         return;
     }
-    e -= nlx;
+    e -= nx;
     if (e < ny) {
-        base[tb.lamy + e] = 2.0 - 2.0 * cospi(2.0 * (double)e / (double)ny);
+        base[tb.lamy + e] = 2.0 - 2.0 * cospi(f * (double)e / (double)ny);
         return;
     }
     e -= ny;
@@ -727,7 +919,23 @@ __global__ __launch_bounds__(kBlock) void k_fp_tables(int nx, int ny, double *__
         return;
     }
     e -= nx - 1;
-    if (e < ny - 1) stage_entry(ny, e, base + tb.twy64, reinterpret_cast<float *>(base + tb.twy32));
+    if (e < ny - 1) {
+        stage_entry(ny, e, base + tb.twy64, reinterpret_cast<float *>(base + tb.twy32));
+        return;
+    }
+    e -= ny - 1;
+    if (!face) return;
+    const bool x = e < nx;
+    const int n = x ? nx : ny, u = x ? e : e - nx;
+    if (u >= n) return;
+    double sn, cs;   // exp(-i pi u / 2n)
+    sincospi(-(double)u / (2.0 * n), &sn, &cs);
+    double *t64 = base + (x ? tb.ctx64 : tb.cty64);
+    float *t32 = reinterpret_cast<float *>(base + (x ? tb.ctx32 : tb.cty32));
+    t64[2 * u] = cs;
+    t64[2 * u + 1] = sn;
+    t32[2 * u] = (float)cs;
+    t32[2 * u + 1] = (float)sn;
 }
 
 // LDS bytes of a row pass over rb real rows of length nx (rb / 2 complex rows) and of the column
@@ -789,7 +997,8 @@ bool fp_supported(int ny, int nx, int k, int dtype, char *why, size_t why_len) {
 size_t fp_table_bytes(int nx, int ny) { return sizeof(double) * fp_tabs(nx, ny).total; }
 
 hipError_t launch_fp_setup(const double *W, const double *A, int f, int k, int nx, int ny,
-                           const double *coef, double *part, double *fsym, hipStream_t s) {
+                           int face, const double *coef, double *part, double *fsym,
+                           hipStream_t s) {
     const int n_pix = nx * ny;
     const int nblk = (int)blocks_for(n_pix, kWChunk);
     hipLaunchKernelGGL(k_wmean_part, dim3(nblk), dim3(kBlock), 0, s, W, f, n_pix, part);
@@ -798,9 +1007,9 @@ hipError_t launch_fp_setup(const double *W, const double *A, int f, int k, int n
     hipLaunchKernelGGL(k_fp_symbol, dim3(1), dim3(kBlock), 0, s, part, nblk, A, f, k, n_pix,
                        coef, fsym);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int nt = (nx / 2 + 1) + ny + (nx - 1) + (ny - 1);
+    const int nt = nx + ny + (nx - 1) + (ny - 1) + (face ? nx + ny : 0);
     hipLaunchKernelGGL(k_fp_tables, dim3((nt + kBlock - 1) / kBlock), dim3(kBlock), 0, s, nx, ny,
-                       fsym);
+                       face, fsym);
     return hipGetLastError();
 }
 
@@ -841,6 +1050,7 @@ hipError_t for_each_radix(int mask, F &&fn) {
 hipError_t launch_fp_apply(const InstSet &set, int k, int f32, int inner, const void *rin,
                            void *zout, int upd, int it, hipStream_t s) {
     const int mixed = inner;
+    const bool dct = set.bc == SYLV_BC_FACE;   // face grids: cosine transforms
     return dispatch_k(k, [&](auto tag) -> hipError_t {
         constexpr int K = decltype(tag)::value;
         auto run = [&](auto tt) -> hipError_t {
@@ -848,31 +1058,50 @@ hipError_t launch_fp_apply(const InstSet &set, int k, int f32, int inner, const 
             const size_t lr = set.fp_lds_rows, lc = set.fp_lds_cols;
             hipError_t e = for_each_radix(set.fp_rmask_x, [&](auto fr) -> hipError_t {
                 constexpr int FR = decltype(fr)::value;
-                hipLaunchKernelGGL((k_fp_rows_fwd<T, FR>), dim3(set.total_fa), dim3(kFT), lr, s,
-                                   set.table, set.fprefa, set.ninst, set.total_fa, mixed,
-                                   reinterpret_cast<const T *>(rin), rin ? 1 : 0,
-                                   inner >= 0 ? upd : 0, it);
+                if (dct)
+                    hipLaunchKernelGGL((k_fp_rows_fwd<T, FR, true>), dim3(set.total_fa), dim3(kFT),
+                                       lr, s, set.table, set.fprefa, set.ninst, set.total_fa,
+                                       mixed, reinterpret_cast<const T *>(rin), rin ? 1 : 0,
+                                       inner >= 0 ? upd : 0, it);
+                else
+                    hipLaunchKernelGGL((k_fp_rows_fwd<T, FR, false>), dim3(set.total_fa),
+                                       dim3(kFT), lr, s, set.table, set.fprefa, set.ninst,
+                                       set.total_fa, mixed, reinterpret_cast<const T *>(rin),
+                                       rin ? 1 : 0, inner >= 0 ? upd : 0, it);
                 return hipGetLastError();
             });
             if (e != hipSuccess) return e;
             e = for_each_radix(set.fp_rmask_y, [&](auto fr) -> hipError_t {
                 constexpr int FR = decltype(fr)::value;
-                if (sizeof(T) == 8 && set.fp_cols_gtw)
-                    hipLaunchKernelGGL((k_fp_cols<double, K, FR, true>), dim3(set.total_fb),
-                                       dim3(kFT), lc, s, set.table, set.fprefb, set.ninst,
-                                       set.total_fb, mixed);
-                else
-                    hipLaunchKernelGGL((k_fp_cols<T, K, FR, false>), dim3(set.total_fb), dim3(kFT),
-                                       lc, s, set.table, set.fprefb, set.ninst, set.total_fb,
-                                       mixed);
+                const dim3 g(set.total_fb), b(kFT);
+                if (sizeof(T) == 8 && set.fp_cols_gtw) {
+                    if (dct)
+                        hipLaunchKernelGGL((k_fp_cols<double, K, FR, true, true>), g, b, lc, s,
+                                           set.table, set.fprefb, set.ninst, set.total_fb, mixed);
+                    else
+                        hipLaunchKernelGGL((k_fp_cols<double, K, FR, true, false>), g, b, lc, s,
+                                           set.table, set.fprefb, set.ninst, set.total_fb, mixed);
+                } else if (dct) {
+                    hipLaunchKernelGGL((k_fp_cols<T, K, FR, false, true>), g, b, lc, s, set.table,
+                                       set.fprefb, set.ninst, set.total_fb, mixed);
+                } else {
+                    hipLaunchKernelGGL((k_fp_cols<T, K, FR, false, false>), g, b, lc, s,
+                                       set.table, set.fprefb, set.ninst, set.total_fb, mixed);
+                }
                 return hipGetLastError();
             });
             if (e != hipSuccess) return e;
             return for_each_radix(set.fp_rmask_x, [&](auto fr) -> hipError_t {
                 constexpr int FR = decltype(fr)::value;
-                hipLaunchKernelGGL((k_fp_rows_inv<T, FR>), dim3(set.total_fa), dim3(kFT), lr, s,
-                                   set.table, set.fprefa, set.ninst, set.total_fa, mixed,
-                                   reinterpret_cast<T *>(zout), zout ? 1 : 0);
+                if (dct)
+                    hipLaunchKernelGGL((k_fp_rows_inv<T, FR, true>), dim3(set.total_fa), dim3(kFT),
+                                       lr, s, set.table, set.fprefa, set.ninst, set.total_fa,
+                                       mixed, reinterpret_cast<T *>(zout), zout ? 1 : 0);
+                else
+                    hipLaunchKernelGGL((k_fp_rows_inv<T, FR, false>), dim3(set.total_fa),
+                                       dim3(kFT), lr, s, set.table, set.fprefa, set.ninst,
+                                       set.total_fa, mixed, reinterpret_cast<T *>(zout),
+                                       zout ? 1 : 0);
                 return hipGetLastError();
             });
         };

@@ -206,17 +206,19 @@ hipError_t launch_rhs(const double *W, const double *Y, const double *A, int f, 
 hipError_t launch_apply_plain(const Inst *table0, int k, int dtype, int rows, int bc, int stream,
                               int ny, int nx, int nrhs, const void *in, void *out, hipStream_t s);
 // ---- Fourier preconditioner (sylv_fourier.hip) ------------------------------------------------
-// Supported shapes: periodic, ny and nx powers of two in [4, 4096], k x ny within the column
-// pass's LDS (why: the reason otherwise).
+// Supported shapes: periodic or face grids with ny and nx powers of two in [4, 4096], k x ny
+// within the column pass's LDS (why: the reason otherwise).
 bool fp_supported(int ny, int nx, int k, int dtype, char *why, size_t why_len);
 int fp_rows_per_block(int nx, int ny, int dtype);
 size_t fp_setup_partials(int n_pix, int f);
 // Bytes of a problem's Fourier region: the symbol block (Mbar, kappa^2, tau), the Laplacian
 // eigenvalues of both grid sides and the FFT stage tables.
 size_t fp_table_bytes(int nx, int ny);
-// The Fourier region of a problem, fsym (part: fp_setup_partials doubles of scratch).
+// The Fourier region of a problem, fsym (part: fp_setup_partials doubles of scratch); face grids
+// (face = 1) take the cosine basis.
 hipError_t launch_fp_setup(const double *W, const double *A, int f, int k, int nx, int ny,
-                           const double *coef, double *part, double *fsym, hipStream_t s);
+                           int face, const double *coef, double *part, double *fsym,
+                           hipStream_t s);
 // z = Fourier preconditioner of r for every instance of the set, in float32 (f32) or float64;
 // inner = 1: the float32 inner runs of the mixed path, 0: the float64 runs, -1: the stand-alone
 // preconditioner (one instance without run state: r read from rin, z written to zout).  upd

@@ -259,13 +259,13 @@ def test_noalloc_solve_refusals_before_any_device_call():
 
 
 def test_fourier_preconditioner_refusals_before_any_device_call():
-    """The Fourier preconditioner takes periodic grids whose sides are powers of two in
+    """The Fourier preconditioner takes periodic or face grids whose sides are powers of two in
     [4, 4096], columns that fit its LDS pass, and independent CG; anything else is refused before
     any work is enqueued (FAKE pointers are never read)."""
     L = sy.lib()
     st = FAKE
     fourier = bd._Opts(1e-8, 10, 0, 0.0, 0, bd.SYLV_PC_FOURIER, 0, 0)
-    for p in (fake_problem(24, 32), fake_problem(32, 2), fake_problem(16, 16, boundary=1),
+    for p in (fake_problem(24, 32), fake_problem(32, 2), fake_problem(24, 16, boundary=1),
               fake_problem(8192, 8), fake_problem(4096, 64, k=8)):
         rc = L.sylv_pcg_solve(ctypes.byref(p), 1, 1, FAKE, None, FAKE, ctypes.byref(fourier),
                               st, FAKE, 1 << 40, None)

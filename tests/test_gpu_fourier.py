@@ -161,7 +161,7 @@ def test_largest_float64_column_reads_twiddles_from_global_memory():
 
 
 def test_unsupported_shapes_are_refused():
-    for kw in (dict(ny=24, nx=32), dict(ny=32, nx=2), dict(ny=16, nx=16, boundary="face")):
+    for kw in (dict(ny=24, nx=32), dict(ny=32, nx=2), dict(ny=24, nx=16, boundary="face")):
         boundary = kw.pop("boundary", "periodic")
         p = make_problem(kw["ny"], kw["nx"], 3, 4, seed=5500, noise="hetero", boundary=boundary)
         dp = sy.DeviceProblem.from_numpy(p)
@@ -179,3 +179,79 @@ def test_unsupported_shapes_are_refused():
     with pytest.raises(sy.SylvError):   # block CG takes the per-pixel preconditioners only
         sy.pcg_solve([dp], Bextra=dev(np.ones(2 * 3 * 256)), nrhs=2,
                      opts=sy.SolveOptions(precond=sy.SYLV_PC_FOURIER, block=1))
+
+
+# ---- face grids (links only inside the grid): the cosine basis ---------------------------------
+
+FACE_SHAPES = [(4, 4, 1, 2), (8, 16, 3, 5), (16, 8, 2, 3), (64, 32, 4, 9), (4, 256, 5, 4),
+               (512, 8, 2, 3), (8, 32, 7, 8), (2048, 16, 4, 9), (8, 4096, 2, 3), (1024, 8, 8, 9)]
+
+
+@pytest.mark.parametrize("shape", FACE_SHAPES)
+def test_face_application_matches_oracle(shape):
+    ny, nx, k, f = shape
+    p = make_problem(ny, nx, k, f, seed=5600 + ny + nx, noise="hetero", mask_frac=0.1,
+                     boundary="face")
+    dp = sy.DeviceProblem.from_numpy(p)
+    R = random_maps(p, seed=5601, nrhs=2)
+    ref = np.stack([opcg.fourier_preconditioner(p)(R[i]) for i in range(2)])
+    say("face application", shape)
+    assert rel(host(sy.precond(dp, dev(R), kind=sy.SYLV_PC_FOURIER)), ref) <= 1e-12
+    assert rel(host(sy.precond(dp, dev(R, torch.float32), kind=sy.SYLV_PC_FOURIER)), ref) <= 2e-5
+
+
+@pytest.mark.parametrize("precision,tol,bound", [(sy.SYLV_PREC_F64, 1e-12, 1e-8),
+                                                 (sy.SYLV_PREC_MIXED, 1e-11, 1e-7)])
+@pytest.mark.parametrize("shape", [(8, 16, 3, 5), (32, 64, 4, 9), (64, 32, 2, 3)])
+def test_face_solve_matches_dense(shape, precision, tol, bound):
+    ny, nx, k, f = shape
+    p = make_problem(ny, nx, k, f, seed=5700 + ny * nx, noise="hetero", mask_frac=0.1,
+                     boundary="face")
+    dp = sy.DeviceProblem.from_numpy(p)
+    say("face solve", shape, precision)
+    X, st = sy.pcg_solve(dp, Y=dev(p.Y), opts=sy.SolveOptions(
+        tol=tol, precision=precision, precond=sy.SYLV_PC_FOURIER))
+    assert st[0]["status"] == 0, st
+    assert rel(host(X).reshape(p.k, p.n_pix), osv.solve_dense(p)) <= bound
+
+
+@pytest.mark.parametrize("shape", [(32, 64, 4, 9), (128, 128, 3, 9)])
+def test_face_iteration_count_matches_oracle(shape):
+    ny, nx, k, f = shape
+    p = make_problem(ny, nx, k, f, seed=5800 + ny, noise="hetero", boundary="face")
+    ref = opcg.pcg(p, tol=1e-8, max_iter=2000, precond="fourier")
+    dp = sy.DeviceProblem.from_numpy(p)
+    X, st = sy.pcg_solve(dp, Y=dev(p.Y), opts=sy.SolveOptions(tol=1e-8,
+                                                              precond=sy.SYLV_PC_FOURIER))
+    say("face iterations", shape, "oracle", ref["iters"], "gpu", st[0]["iters"])
+    assert st[0]["status"] == 0, st
+    assert abs(st[0]["iters"] - ref["iters"]) <= 1
+
+
+def test_face_homoscedastic_grid_solves_in_one_iteration():
+    p = make_problem(32, 64, 3, 6, seed=5900, noise="homo", boundary="face")
+    dp = sy.DeviceProblem.from_numpy(p)
+    X, st = sy.pcg_solve(dp, Y=dev(p.Y), opts=sy.SolveOptions(tol=1e-10,
+                                                              precond=sy.SYLV_PC_FOURIER))
+    assert st[0]["status"] == 0 and st[0]["iters"] <= 2, st
+    assert rel(host(X).reshape(p.k, p.n_pix), osv.solve_dense(p)) <= 1e-9
+
+
+def test_face_batch_of_twelve_faces():
+    """Twelve independent faces in one call (the full-sky layout, App. A), both precisions."""
+    probs = [make_problem(32, 32, 4, 9, seed=6000 + g, noise="hetero", boundary="face")
+             for g in range(12)]
+    dps = [sy.DeviceProblem.from_numpy(q) for q in probs]
+    Y = torch.cat([dev(q.Y.ravel()) for q in probs])
+    say("face batch")
+    for precision, tol, bound in ((sy.SYLV_PREC_F64, 1e-12, 1e-8),
+                                  (sy.SYLV_PREC_MIXED, 1e-11, 1e-7)):
+        X, st = sy.pcg_solve(dps, Y=Y, opts=sy.SolveOptions(tol=tol, precision=precision,
+                                                            precond=sy.SYLV_PC_FOURIER))
+        assert all(s["status"] == 0 for s in st), st
+        x = host(X)
+        off = 0
+        for q in probs:
+            n = q.k * q.n_pix
+            assert rel(x[off:off + n].reshape(q.k, q.n_pix), osv.solve_dense(q)) <= bound
+            off += n
