@@ -494,18 +494,20 @@ def bench_sweep(sy, torch):
 
 def bench_sky(sy, torch, steps, warmup, cpu=False):
     """A full sky at HEALPix level 10: 12 independent 1024^2 faces (links only inside a face),
-    k = 4, f = 9, solved in one batched call to 1e-8, mixed precision and float64."""
+    k = 4, f = 9, solved in one batched call to 1e-8, mixed precision and float64, with the
+    block-Jacobi preconditioner and with the pixel-mean preconditioner in the cosine basis."""
     from workloads import WORKLOADS, workload
     probs = workload("healpix_sky_1024")
     tol = WORKLOADS["healpix_sky_1024"]["tol"]
     dps = [sy.DeviceProblem.from_numpy(p) for p in probs]
     Y = torch.cat([torch.as_tensor(p.Y.ravel(), device="cuda") for p in probs])
     res = {"faces": len(probs), "pixels_per_map": sum(p.n_pix for p in probs)}
-    for label, prec in (("mixed", sy.SYLV_PREC_MIXED), ("f64", sy.SYLV_PREC_F64)):
-        o = sy.SolveOptions(tol=tol, precision=prec)
-        ms, st, _ = time_solves(sy, torch, dps, Y, None, o, 1, steps, warmup)
-        res[label] = summarize(ms, st)
-        log(f"healpix_sky_1024 {label}: {res[label]}")
+    for pc, suffix in ((sy.SYLV_PC_BLOCK, ""), (sy.SYLV_PC_FOURIER, "_cosine")):
+        for label, prec in (("mixed", sy.SYLV_PREC_MIXED), ("f64", sy.SYLV_PREC_F64)):
+            o = sy.SolveOptions(tol=tol, precision=prec, precond=pc)
+            ms, st, _ = time_solves(sy, torch, dps, Y, None, o, 1, steps, warmup)
+            res[label + suffix] = summarize(ms, st)
+            log(f"healpix_sky_1024 {label + suffix}: {res[label + suffix]}")
     if cpu:
         # the oracle's PCG (assembled sparse G, block-Jacobi) on one full-size face, bounded
         from oracle import operator as op
