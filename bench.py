@@ -429,6 +429,23 @@ def bench_other_workloads(sy, torch, steps, warmup, cpu=False):
     ms_b = (time.perf_counter() - t0) / steps * 1e3
     out["grad_512"] = {"forward": summarize(ms_f, st), "backward_ms": round(ms_b, 3),
                        "backward_iters": stb["iters"], "backward_ok": stb["status"] == 0}
+    of = dataclasses.replace(o, precond=sy.SYLV_PC_FOURIER)
+    ms_ff, stf, Xf = time_solves(sy, torch, dp, Y, None, of, 1, steps, warmup)
+    wsf = torch.empty(sy.workspace_bytes([dp], 1, of), dtype=torch.uint8, device="cuda")
+    for _ in range(warmup):
+        sy.pcg_backward(dp, Y, Xf, gbar, of, ws=wsf)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, gf, stbf = sy.pcg_backward(dp, Y, Xf, gbar, of, ws=wsf)
+    torch.cuda.synchronize()
+    out["grad_512"]["fourier"] = {
+        "forward": summarize(ms_ff, stf),
+        "backward_ms": round((time.perf_counter() - t0) / steps * 1e3, 3),
+        "backward_iters": stbf["iters"], "backward_ok": stbf["status"] == 0,
+        "grad_rel_diff_vs_block": {kk: float(torch.linalg.norm(gf[kk] - g[kk]) /
+                                             max(float(torch.linalg.norm(g[kk])), 1e-300))
+                                   for kk in g}}
     log(f"grad_512: {out['grad_512']}")
     if cpu:
         # the oracle at full size: assembly and 10 PCG iterations (scaled to the forward and
@@ -568,8 +585,11 @@ def bench_sylvester(sy, torch, steps, warmup, max_iter=800, cpu=False):
         del ws
     dp = sy.DeviceProblem.from_numpy(prob)
     xs = {"lanczos_sylvester": X}
-    for label, prec in (("pcg_f64", sy.SYLV_PREC_F64), ("pcg_mixed", sy.SYLV_PREC_MIXED)):
-        o = sy.SolveOptions(tol=tol, precision=prec)
+    for label, prec, pc in (("pcg_f64", sy.SYLV_PREC_F64, sy.SYLV_PC_BLOCK),
+                            ("pcg_mixed", sy.SYLV_PREC_MIXED, sy.SYLV_PC_BLOCK),
+                            ("pcg_fourier_f64", sy.SYLV_PREC_F64, sy.SYLV_PC_FOURIER),
+                            ("pcg_fourier_mixed", sy.SYLV_PREC_MIXED, sy.SYLV_PC_FOURIER)):
+        o = sy.SolveOptions(tol=tol, precision=prec, precond=pc)
         ms, stl, Xc = time_solves(sy, torch, dp, Y, None, o, 1, steps, warmup)
         res[label] = summarize(ms, stl)
         xs[label] = Xc.reshape(prob.k, prob.n_pix)
