@@ -127,6 +127,14 @@ __host__ __device__ constexpr int stage_log_radix(int logn, int lg) {
 __host__ __device__ constexpr int fft_last_radix(int logn) {
     return (logn & 3) == 0 ? 16 : 1 << (logn & 3);
 }
+// Kernel classes of a transform length: the lengths of the 1024^2 and 2048^2 grids get kernels
+// of their own (class 100 + log2 n: every stage size, stride and LDS offset a compile-time
+// constant), every other length the kernel of its final radix (class 2, 4, 8 or 16).
+__host__ __device__ constexpr int fft_class(int logn) {
+    return (logn == 10 || logn == 11) ? 100 + logn : fft_last_radix(logn);
+}
+__host__ __device__ constexpr int cls_fr(int cls) { return cls >= 100 ? fft_last_radix(cls - 100) : cls; }
+__host__ __device__ constexpr int cls_ln(int cls) { return cls >= 100 ? cls - 100 : 0; }
 
 // ---- DFTs of R = 2, 4, 8, 16 points in registers, natural order in and out ----------------
 // Forward: X[k] = sum_j x[j] exp(-2 pi i j k / R); INV = 1 uses exp(+2 pi i j k / R).
@@ -272,6 +280,7 @@ __device__ __forceinline__ void fft_run(Cx<T> *buf, const Cx<T> *tw, int logn, i
     constexpr int LFR = FR == 16 ? 4 : FR == 8 ? 3 : FR == 4 ? 2 : 1;
     const int n16 = (logn - LFR) >> 2;
     int off = 0, lg = 0;
+#pragma unroll
     for (int st = 0; st < n16; ++st) {
         fft_stage<T, 16, INV>(buf, tw + off, logn, rows, lg, gin && st == 0, false, ldg, stg);
         off += 15 << lg;
@@ -461,7 +470,7 @@ __device__ __forceinline__ double dot_re(const Cx<T> (&a)[K], const Cx<T> (&b)[K
 // the first stage loads r and q, r written back.
 // DCT (face grids): the rows' cosine transforms instead, from the reordered rows; the nx real
 // coefficients of each row are stored transposed, S[j][u][y], u < nx, two rows per 8-byte store.
-template <typename T, int FR, bool DCT>
+template <typename T, int CLS, bool DCT>
 __global__ __launch_bounds__(kFT) void k_fp_rows_fwd(const Inst *__restrict__ tab,
                                                      const int *__restrict__ fpre, int ninst,
                                                      int nb, int inner,
@@ -471,7 +480,8 @@ __global__ __launch_bounds__(kFT) void k_fp_rows_fwd(const Inst *__restrict__ ta
     const int L = xcd_remap(blockIdx.x, nb);
     const int ii = find_inst(fpre, ninst, L);
     const Inst &I = tab[ii];
-    if (fft_last_radix(I.lognx) != FR) return;                     // another launch's instance
+    if (fft_class(I.lognx) != CLS) return;                         // another launch's instance
+    constexpr int FR = cls_fr(CLS), LN = cls_ln(CLS);
     const int blk = L - fpre[ii];
     T alpha = (T)0;
     if (inner >= 0) {                                              // inner < 0: stand-alone
@@ -506,7 +516,8 @@ __global__ __launch_bounds__(kFT) void k_fp_rows_fwd(const Inst *__restrict__ ta
             alpha = (T)alpha_d;
         }
     }
-    const int nx = I.nx, ny = I.ny, rb = I.frb, nc = nx / 2 + 1, h = rb / 2, ln = I.lognx;
+    const int ln = LN ? LN : I.lognx, nx = 1 << ln;
+    const int ny = I.ny, rb = I.frb, nc = nx / 2 + 1, h = rb / 2;
     const int lrb = __builtin_ctz((unsigned)rb), nrb = ny >> lrb;
     const int j = blk / nrb, y0 = (blk - j * nrb) << lrb;
     Cx<T> *tw = reinterpret_cast<Cx<T> *>(fp_lds);
@@ -582,17 +593,19 @@ __global__ __launch_bounds__(kFT) void k_fp_rows_fwd(const Inst *__restrict__ ta
 // split into the two columns' spectra, twiddled), solves the real k x k system of each of the
 // four modes (u0, v), (u0, -v), (u1, v), (u1, -v) a thread owns, and transforms back.  <r, z> by
 // Parseval with the orthonormal weights (1 or 2) / n of each side.
-template <typename T, int K, int FR, bool GTW, bool DCT>
-__global__ __launch_bounds__(kFT, (sizeof(T) == 8 || K > 5) ? 2 : 4) void k_fp_cols(
+template <typename T, int K, int CLS, bool GTW, bool DCT>
+__global__ __launch_bounds__(kFT, (sizeof(T) == 8 || K > 5 || (DCT && K > 4)) ? 2 : 4) void k_fp_cols(
     const Inst *__restrict__ tab, const int *__restrict__ fpre, int ninst, int nb, int inner) {
     extern __shared__ __align__(16) unsigned char fp_lds[];
     const int L = xcd_remap(blockIdx.x, nb);
     const int ii = find_inst(fpre, ninst, L);
     const Inst &I = tab[ii];
     if (inner >= 0 && (inner ? I.st_in : I.st)->done) return;   // inner < 0: stand-alone
-    if (fft_last_radix(I.logny) != FR) return;                     // another launch's instance
+    if (fft_class(I.logny) != CLS) return;                         // another launch's instance
+    constexpr int FR = cls_fr(CLS), LN = cls_ln(CLS);
     const int c = L - fpre[ii];
-    const int nx = I.nx, ny = I.ny, nc = nx / 2 + 1, ln = I.logny, cn = nx / 2;
+    const int ln = LN ? LN : I.logny, ny = 1 << ln;
+    const int nx = I.nx, nc = nx / 2 + 1, cn = nx / 2;
     const FpTabs tb = fp_tabs(nx, ny);
     Cx<T> *buf = reinterpret_cast<Cx<T> *>(fp_lds) + (GTW ? 0 : ny);
     const Cx<T> *tw = stage_table<T>(I.fsym, tb, false);
@@ -732,7 +745,7 @@ __global__ __launch_bounds__(kFT, (sizeof(T) == 8 || K > 5) ? 2 : 4) void k_fp_c
 // DCT (face grids): the rows' inverse cosine transforms: U[u] = V_2q[u] + i V_(2q+1)[u] with
 // V[u] = exp(i pi u / 2nx) (Z[u] - i Z[nx - u]), the inverse FFT, and the reorder undone as the
 // last stage writes z.
-template <typename T, int FR, bool DCT>
+template <typename T, int CLS, bool DCT>
 __global__ __launch_bounds__(kFT) void k_fp_rows_inv(const Inst *__restrict__ tab,
                                                      const int *__restrict__ fpre, int ninst,
                                                      int nb, int inner, T *__restrict__ zout,
@@ -742,9 +755,11 @@ __global__ __launch_bounds__(kFT) void k_fp_rows_inv(const Inst *__restrict__ ta
     const int ii = find_inst(fpre, ninst, L);
     const Inst &I = tab[ii];
     if (inner >= 0 && (inner ? I.st_in : I.st)->done) return;   // inner < 0: stand-alone
-    if (fft_last_radix(I.lognx) != FR) return;                     // another launch's instance
+    if (fft_class(I.lognx) != CLS) return;                         // another launch's instance
+    constexpr int FR = cls_fr(CLS), LN = cls_ln(CLS);
     const int blk = L - fpre[ii];
-    const int nx = I.nx, ny = I.ny, rb = I.frb, nc = nx / 2 + 1, h = rb / 2, ln = I.lognx;
+    const int ln = LN ? LN : I.lognx, nx = 1 << ln;
+    const int ny = I.ny, rb = I.frb, nc = nx / 2 + 1, h = rb / 2;
     const int lrb = __builtin_ctz((unsigned)rb), nrb = ny >> lrb;
     const int j = blk / nrb, y0 = (blk - j * nrb) << lrb;
     Cx<T> *tw = reinterpret_cast<Cx<T> *>(fp_lds);
@@ -1035,15 +1050,17 @@ size_t fp_lds_bytes(int pass, int n, int m, int dtype) {
 // or float64.  inner: 1 = the float32 inner runs of the mixed path (their r, z and state), 0 = the
 // float64 runs, -1 = the stand-alone preconditioner (one instance, no run state): r read from
 // rin, z written to zout.  upd: see k_fp_rows_fwd (runs only).
-// The kernels are instantiated per final radix; a pass is launched once per radix class present
-// in the set (mask bit log2(FR) - 1), and workgroups of other classes return at once.
+// The kernels are instantiated per length class (fft_class); a pass is launched once per class
+// present in the set (mask bit fp_radix_bit), and workgroups of other classes return at once.
 template <typename F>
-hipError_t for_each_radix(int mask, F &&fn) {
+hipError_t for_each_class(int mask, F &&fn) {
     hipError_t e = hipSuccess;
     if ((mask & 1) && (e = fn(std::integral_constant<int, 2>())) != hipSuccess) return e;
     if ((mask & 2) && (e = fn(std::integral_constant<int, 4>())) != hipSuccess) return e;
     if ((mask & 4) && (e = fn(std::integral_constant<int, 8>())) != hipSuccess) return e;
     if ((mask & 8) && (e = fn(std::integral_constant<int, 16>())) != hipSuccess) return e;
+    if ((mask & 16) && (e = fn(std::integral_constant<int, 110>())) != hipSuccess) return e;
+    if ((mask & 32) && (e = fn(std::integral_constant<int, 111>())) != hipSuccess) return e;
     return e;
 }
 
@@ -1056,8 +1073,8 @@ hipError_t launch_fp_apply(const InstSet &set, int k, int f32, int inner, const 
         auto run = [&](auto tt) -> hipError_t {
             using T = decltype(tt);
             const size_t lr = set.fp_lds_rows, lc = set.fp_lds_cols;
-            hipError_t e = for_each_radix(set.fp_rmask_x, [&](auto fr) -> hipError_t {
-                constexpr int FR = decltype(fr)::value;
+            hipError_t e = for_each_class(set.fp_rmask_x, [&](auto fr) -> hipError_t {
+                constexpr int FR = decltype(fr)::value;   // the class
                 if (dct)
                     hipLaunchKernelGGL((k_fp_rows_fwd<T, FR, true>), dim3(set.total_fa), dim3(kFT),
                                        lr, s, set.table, set.fprefa, set.ninst, set.total_fa,
@@ -1071,8 +1088,8 @@ hipError_t launch_fp_apply(const InstSet &set, int k, int f32, int inner, const 
                 return hipGetLastError();
             });
             if (e != hipSuccess) return e;
-            e = for_each_radix(set.fp_rmask_y, [&](auto fr) -> hipError_t {
-                constexpr int FR = decltype(fr)::value;
+            e = for_each_class(set.fp_rmask_y, [&](auto fr) -> hipError_t {
+                constexpr int FR = decltype(fr)::value;   // the class
                 const dim3 g(set.total_fb), b(kFT);
                 if (sizeof(T) == 8 && set.fp_cols_gtw) {
                     if (dct)
@@ -1091,8 +1108,8 @@ hipError_t launch_fp_apply(const InstSet &set, int k, int f32, int inner, const 
                 return hipGetLastError();
             });
             if (e != hipSuccess) return e;
-            return for_each_radix(set.fp_rmask_x, [&](auto fr) -> hipError_t {
-                constexpr int FR = decltype(fr)::value;
+            return for_each_class(set.fp_rmask_x, [&](auto fr) -> hipError_t {
+                constexpr int FR = decltype(fr)::value;   // the class
                 if (dct)
                     hipLaunchKernelGGL((k_fp_rows_inv<T, FR, true>), dim3(set.total_fa), dim3(kFT),
                                        lr, s, set.table, set.fprefa, set.ninst, set.total_fa,
@@ -1109,6 +1126,9 @@ hipError_t launch_fp_apply(const InstSet &set, int k, int f32, int inner, const 
     });
 }
 
-int fp_radix_bit(int logn) { return fft_last_radix(logn) / 2; }
+int fp_radix_bit(int logn) {
+    const int c = fft_class(logn);
+    return c >= 100 ? 16 << (c - 110) : c / 2;
+}
 
 }  // namespace sylv
