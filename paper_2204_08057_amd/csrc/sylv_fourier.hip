@@ -280,7 +280,6 @@ __device__ __forceinline__ void fft_run(Cx<T> *buf, const Cx<T> *tw, int logn, i
     constexpr int LFR = FR == 16 ? 4 : FR == 8 ? 3 : FR == 4 ? 2 : 1;
     const int n16 = (logn - LFR) >> 2;
     int off = 0, lg = 0;
-#pragma unroll
     for (int st = 0; st < n16; ++st) {
         fft_stage<T, 16, INV>(buf, tw + off, logn, rows, lg, gin && st == 0, false, ldg, stg);
         off += 15 << lg;
@@ -1092,12 +1091,20 @@ hipError_t launch_fp_apply(const InstSet &set, int k, int f32, int inner, const 
                 constexpr int FR = decltype(fr)::value;   // the class
                 const dim3 g(set.total_fb), b(kFT);
                 if (sizeof(T) == 8 && set.fp_cols_gtw) {
-                    if (dct)
-                        hipLaunchKernelGGL((k_fp_cols<double, K, FR, true, true>), g, b, lc, s,
-                                           set.table, set.fprefb, set.ninst, set.total_fb, mixed);
-                    else
-                        hipLaunchKernelGGL((k_fp_cols<double, K, FR, true, false>), g, b, lc, s,
-                                           set.table, set.fprefb, set.ninst, set.total_fb, mixed);
+                    // only float64 columns of k ny = 8192 with ny = 2048 (k <= 4) or 4096 (k <= 2)
+                    // exceed the LDS with their table (fp_cols_global_twiddles)
+                    if constexpr ((FR == 111 && K <= 4) || (FR == 16 && K <= 2)) {
+                        if (dct)
+                            hipLaunchKernelGGL((k_fp_cols<double, K, FR, true, true>), g, b, lc, s,
+                                               set.table, set.fprefb, set.ninst, set.total_fb,
+                                               mixed);
+                        else
+                            hipLaunchKernelGGL((k_fp_cols<double, K, FR, true, false>), g, b, lc,
+                                               s, set.table, set.fprefb, set.ninst, set.total_fb,
+                                               mixed);
+                    } else {
+                        return hipErrorInvalidValue;
+                    }
                 } else if (dct) {
                     hipLaunchKernelGGL((k_fp_cols<T, K, FR, false, true>), g, b, lc, s, set.table,
                                        set.fprefb, set.ninst, set.total_fb, mixed);
