@@ -37,7 +37,7 @@ METRIC = "time-to-1e-8 rel. residual @1024² k=3 (FP64 vs mixed); operator-apply
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_apply_f32_het_1024.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2204_08057_amd", "csrc", "sylv_kernels.hip")
-FOURIER_SRC = os.path.join(ROOT, "paper_2204_08057_amd", "csrc", "sylv_fourier.hip")
+FOURIER_SRC = os.path.join(ROOT, "paper_2204_08057_amd", "csrc", "sylv_fourier_impl.h")
 
 
 def log(*a):

@@ -6,6 +6,7 @@ The library is written next to this file so it travels with the source tree.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import shutil
 import subprocess
@@ -17,8 +18,13 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsylv.so")
-SOURCES = ["sylv_kernels.hip", "sylv_block.hip", "sylv_lanczos.hip", "sylv_kohler.hip",
-           "sylv_fourier.hip", "sylv_api.hip"]
+# longest compile first: the instantiations of the block solver (per right-hand-side count and
+# precision) and of the Fourier preconditioner's passes (per precision and grid type)
+SOURCES = ["sylv_block_s8_f32.hip", "sylv_block_s8_f64.hip", "sylv_block_s4_f32.hip",
+           "sylv_kernels.hip", "sylv_fourier_f64_periodic.hip", "sylv_fourier_f64_face.hip",
+           "sylv_block_s4_f64.hip", "sylv_fourier_f32_periodic.hip", "sylv_fourier_f32_face.hip",
+           "sylv_block_s2_f32.hip", "sylv_block_s2_f64.hip", "sylv_lanczos.hip", "sylv_block.hip",
+           "sylv_kohler.hip", "sylv_fourier.hip", "sylv_api.hip"]
 ARCH = os.environ.get("SYLV_OFFLOAD_ARCH", "gfx950")
 
 
@@ -39,25 +45,25 @@ def flags():
     ]
 
 
-def build(verbose: bool = True, jobs: int = 3) -> str:
-    """Compile every source to an object in a temp dir, then link the shared library."""
+def build(verbose: bool = True, jobs: int = 0) -> str:
+    """Compile every source to an object in a temp dir (jobs at a time, default one per CPU up
+    to 8), then link the shared library."""
     cc = hipcc()
+    jobs = jobs or max(1, min(8, os.cpu_count() or 1))
     tmp = tempfile.mkdtemp(prefix="sylv_build_")
     try:
-        procs = []
-        objs = []
-        for src in SOURCES:
-            obj = os.path.join(tmp, src.replace(".hip", ".o"))
-            objs.append(obj)
+        objs = [os.path.join(tmp, src.replace(".hip", ".o")) for src in SOURCES]
+
+        def compile_one(src, obj):
             cmd = [cc, *flags(), "-c", os.path.join(CSRC, src), "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)
-            procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE,
-                                                stderr=subprocess.STDOUT, text=True)))
-            if len(procs) >= jobs:
-                _wait(procs.pop(0), verbose)
-        for p in procs:
-            _wait(p, verbose)
+            return src, subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT,
+                                       text=True)
+
+        with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as pool:
+            for src, proc in pool.map(compile_one, SOURCES, objs):
+                _check(src, proc, verbose)
         out_tmp = LIB + ".tmp"
         cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", out_tmp]
         if verbose:
@@ -69,12 +75,10 @@ def build(verbose: bool = True, jobs: int = 3) -> str:
     return LIB
 
 
-def _wait(item, verbose):
-    src, proc = item
-    out, _ = proc.communicate()
-    msgs = [ln for ln in out.splitlines() if "packed-fp32-ops" not in ln and ln.strip()]
+def _check(src, proc, verbose):
+    msgs = [ln for ln in proc.stdout.splitlines() if "packed-fp32-ops" not in ln and ln.strip()]
     if proc.returncode != 0:
-        sys.stderr.write(out)
+        sys.stderr.write(proc.stdout)
         raise RuntimeError(f"hipcc failed on {src}")
     if verbose and msgs:
         print("\n".join(msgs))

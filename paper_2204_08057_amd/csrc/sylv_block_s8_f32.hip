@@ -1,0 +1,9 @@
+// Block conjugate gradients: the launches for s = 8 right-hand sides in float32 (the inner runs of the mixed path).
+
+#include "sylv_block_impl.h"
+
+namespace sylv {
+
+template struct BlockLaunch<8, float>;
+
+}  // namespace sylv
