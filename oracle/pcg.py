@@ -50,7 +50,7 @@ def block_jacobi(prob, G=None, kind: str = "block"):
     return apply_inv, inv
 
 
-def fourier_preconditioner(prob):
+def fourier_preconditioner(prob, scaled: bool = False):
     """Minv = (Q + I (x) Mbar)^-1 applied mode by mode in the basis that diagonalises the grid
     Laplacian: the 2-D DFT on periodic grids, the 2-D cosine transform (DCT-II) on face grids.
 
@@ -63,6 +63,10 @@ def fourier_preconditioner(prob):
     Mbar = sum_f mean_p(W[f, :]) a_f a_f^T, so one k x k block remains per mode (a fixed SPD
     operator; the paper allows any preconditioner, Section 3.2, remarks after Alg. 2).  When W
     does not depend on the pixel this is G^-1 exactly.
+    scaled: the diagonally matched variant z = S^-1 (Q + I (x) Mbar)^-1 S^-1 r, S = diag(s) with
+    s^2 = diag(G) / diag(Q + I (x) Mbar) per pixel and component, so that the operator it
+    inverts, S (Q + I (x) Mbar) S, has the diagonal of G (still fixed and SPD; s = 1 when W does
+    not depend on the pixel).
     Returns a function r[k, n_pix] -> z[k, n_pix]."""
     from scipy import fft as sfft
     from .solve import fourier_symbols
@@ -90,7 +94,26 @@ def fourier_preconditioner(prob):
         zh = np.einsum("yxij,jyx->iyx", inv, rh)
         return np.fft.ifft2(zh, axes=(1, 2)).real.reshape(k, ny * nx)
 
-    return apply_inv
+    if not scaled:
+        return apply_inv
+    s = diagonal_scale(prob)
+
+    def apply_scaled(r):
+        return apply_inv(np.asarray(r, dtype=np.float64).reshape(k, ny * nx) / s) / s
+
+    return apply_scaled
+
+
+def diagonal_scale(prob):
+    """s[k, n_pix] with s^2 = diag(G) / diag(Q + I (x) Mbar), both diagonals read from the
+    assembled operators (Q = G minus the data term)."""
+    G = op.posterior_precision(prob)
+    Q = G - op.likelihood_term(prob)
+    wbar = prob.W.mean(axis=1)
+    mbar = (prob.A.T * wbar) @ prob.A
+    dG = G.diagonal().reshape(prob.k, prob.n_pix)
+    dM0 = Q.diagonal().reshape(prob.k, prob.n_pix) + np.diag(mbar)[:, None]
+    return np.sqrt(dG / dM0)
 
 
 def pcg(prob, b=None, x0=None, tol=1e-12, max_iter=10000, precond="block", G=None,
@@ -103,6 +126,8 @@ def pcg(prob, b=None, x0=None, tol=1e-12, max_iter=10000, precond="block", G=Non
     k, n_pix = prob.k, prob.n_pix
     if precond == "fourier":
         Minv = fourier_preconditioner(prob)
+    elif precond == "fourier_diag":
+        Minv = fourier_preconditioner(prob, scaled=True)
     else:
         Minv, _ = block_jacobi(prob, G, precond)
     bv = np.asarray(b, dtype=np.float64).reshape(k, n_pix)
