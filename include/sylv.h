@@ -94,13 +94,22 @@ extern "C" {
 #define SYLV_PC_NONE   0        /* z = r (plain Alg. 2)                                           */
 #define SYLV_PC_JACOBI 1        /* z = r / diag(G)                                                */
 #define SYLV_PC_BLOCK  2        /* z_p = (G_pp)^-1 r_p, G_pp the k x k block of pixel p           */
-#define SYLV_PC_FOURIER 3       /* z = (Q + I (x) Mbar)^-1 r through the 2-D DFT: the operator
-                                   with the weights replaced by their pixel means (Mbar =
-                                   sum_f mean_p(W[f, p]) a_f a_f^T), exact for pixel-independent
-                                   weights.  Periodic grids whose sides are powers of two in
-                                   [4, 4096], k * ny complex values within the column pass's 64 KB
-                                   of LDS (float32: k * ny <= 8192, float64: <= 4096 minus
-                                   padding); independent CG only (else SYLV_E_INVALID)          */
+#define SYLV_PC_FOURIER 3       /* z = (Q + I (x) Mbar)^-1 r through 2-D transforms that
+                                   diagonalise the prior (the DFT on periodic grids, the cosine
+                                   transform DCT-II on face grids): the operator with the
+                                   weights replaced by their pixel means (Mbar = sum_f
+                                   mean_p(W[f, p]) a_f a_f^T), exact for pixel-independent
+                                   weights.  Grid sides powers of two in [4, 4096], k * ny complex
+                                   values within the column pass's LDS (float32: k * ny <= 8192,
+                                   float64: k * ny <= 8192 with the stage twiddles read from
+                                   global memory beyond 4096 minus padding); independent CG only
+                                   (else SYLV_E_INVALID)                                         */
+#define SYLV_PC_FOURIER_DIAG 4  /* z = S^-1 (Q + I (x) Mbar)^-1 S^-1 r, S = diag(s) per pixel and
+                                   component with s^2 = diag(G) / diag(Q + I (x) Mbar): the
+                                   SYLV_PC_FOURIER operator scaled so that its diagonal is G's
+                                   (the heteroscedastic weights enter through the scale; s = 1
+                                   for pixel-independent weights).  Same grids and limits as
+                                   SYLV_PC_FOURIER                                               */
 
 /* One posterior-mean system (Section 2, Section 3).  Host struct of device pointers. */
 typedef struct sylv_problem {
@@ -123,7 +132,7 @@ typedef struct sylv_pcg_opts {
     double  inner_tol;     /* mixed: smallest relative reduction asked of one float32 inner run
                               (0 = 1e-5)                                                          */
     int32_t refine_max;    /* mixed: maximum number of float64 refinement steps (0 = 8)          */
-    int32_t precond;       /* SYLV_PC_NONE, SYLV_PC_JACOBI or SYLV_PC_BLOCK                       */
+    int32_t precond;       /* SYLV_PC_NONE, _JACOBI, _BLOCK, _FOURIER or _FOURIER_DIAG            */
     int32_t check_every;   /* iterations enqueued between host convergence checks (0 = 8)        */
     int32_t block;         /* 1: block CG over blocks of s right-hand sides of each problem
                               (s = block_size): s x s Gram matrices in float64, alpha and beta

@@ -104,6 +104,7 @@ int chunks_for(int n_pix) { return (n_pix + kChunk - 1) / kChunk; }
 struct ProbLayout {
     size_t coef, M64, M32, P64, P32, P16;
     size_t fsym, fpart;   // Fourier preconditioner: symbol block and the weight-mean partials
+    size_t fsc64, fsc32;  // its diagonal scale (SYLV_PC_FOURIER_DIAG), on Fourier grids only
 };
 struct InstLayout {
     size_t st, partial, b, r, z, p, p2, q, r32, z32, p32, p32b, q32, d32;
@@ -124,6 +125,9 @@ struct Layout {
 // Whether a grid can take the Fourier preconditioner in some precision (the stand-alone
 // workspace then holds its spectrum), and the spectrum's bytes (complex float64 half spectrum;
 // the cosine coefficients of face grids take less).
+// The two Fourier-basis preconditioners (plain and diagonally scaled).
+bool is_fourier(int pc) { return pc == SYLV_PC_FOURIER || pc == SYLV_PC_FOURIER_DIAG; }
+
 bool fp_grid(const sylv_problem &p) {
     char why[160];
     return fp_supported((int)p.ny, (int)p.nx, p.k, SYLV_F32, why, sizeof(why));
@@ -167,6 +171,12 @@ bool make_layout(const sylv_problem *probs, int nprob, int nrhs, bool solve, Lay
         P.P16 = off;  off = align_up(off + sizeof(unsigned short) * mk * n);
         P.fsym = off; off = align_up(off + fp_table_bytes((int)probs[g].nx, (int)probs[g].ny));
         P.fpart = off; off = align_up(off + sizeof(double) * fp_setup_partials((int)n, probs[g].f));
+        P.fsc64 = P.fsc32 = 0;
+        if (fp_grid(probs[g])) {
+            const size_t vk = (size_t)probs[g].k * n;
+            P.fsc64 = off; off = align_up(off + sizeof(double) * vk);
+            P.fsc32 = off; off = align_up(off + sizeof(float) * vk);
+        }
     }
     if (!solve && nprob == 1 && fp_grid(probs[0])) {
         L.fs1 = off;
@@ -201,7 +211,7 @@ bool make_layout(const sylv_problem *probs, int nprob, int nrhs, bool solve, Lay
                 I.q32 = off; off = align_up(off + sizeof(float) * vk);
                 I.d32 = off; off = align_up(off + sizeof(float) * vk);
                 I.fs = 0;
-                if (pc == SYLV_PC_FOURIER) {
+                if (is_fourier(pc)) {
                     I.fs = off;
                     off = align_up(off + fp_spectrum_bytes(probs[g]));
                 }
@@ -253,7 +263,11 @@ Inst operator_inst(const sylv_problem &p, const ProbLayout &P, char *base, int p
     I.nx = (int)p.nx;
     I.n_pix = (int)(p.ny * p.nx);
     I.tiles_x = (I.nx + kTileX - 1) / kTileX;
-    I.pc = pc;
+    I.pc = is_fourier(pc) ? SYLV_PC_FOURIER : pc;   // the kernels tell the two apart by fsc64
+    if (pc == SYLV_PC_FOURIER_DIAG) {
+        I.fsc64 = reinterpret_cast<const double *>(base + P.fsc64);
+        I.fsc32 = reinterpret_cast<const float *>(base + P.fsc32);
+    }
     I.f = p.f;
     I.coef = reinterpret_cast<const double *>(base + P.coef);
     I.A = p.A;
@@ -278,11 +292,16 @@ int prepare_operator(const sylv_problem &p, const ProbLayout &P, char *base, int
                          reinterpret_cast<double *>(base + P.P64),
                          reinterpret_cast<float *>(base + P.P32),
                          reinterpret_cast<unsigned short *>(base + P.P16), exact, p.k, s));
-    if (pc == SYLV_PC_FOURIER)
+    if (is_fourier(pc)) {
+        const bool diag = pc == SYLV_PC_FOURIER_DIAG;
         HIP_TRY(launch_fp_setup(p.W, p.A, p.f, p.k, (int)p.nx, (int)p.ny,
                                 p.boundary == SYLV_BC_FACE ? 1 : 0, coef,
                                 reinterpret_cast<double *>(base + P.fpart),
-                                reinterpret_cast<double *>(base + P.fsym), s));
+                                reinterpret_cast<double *>(base + P.fsym),
+                                reinterpret_cast<const double *>(base + P.M64),
+                                diag ? reinterpret_cast<double *>(base + P.fsc64) : nullptr,
+                                diag ? reinterpret_cast<float *>(base + P.fsc32) : nullptr, s));
+    }
     return SYLV_OK;
 }
 
@@ -303,7 +322,7 @@ int check_opts(const sylv_pcg_opts *o) {
     if (!(o->tol > 0.0) || !(o->tol < 1.0)) { set_err("tol must be in (0, 1)"); return SYLV_E_INVALID; }
     if (o->max_iter < 1) { set_err("max_iter must be >= 1"); return SYLV_E_INVALID; }
     if (o->precision != SYLV_PREC_F64 && o->precision != SYLV_PREC_MIXED) { set_err("bad precision"); return SYLV_E_INVALID; }
-    if (o->precond < SYLV_PC_NONE || o->precond > SYLV_PC_FOURIER) { set_err("bad precond"); return SYLV_E_INVALID; }
+    if (o->precond < SYLV_PC_NONE || o->precond > SYLV_PC_FOURIER_DIAG) { set_err("bad precond"); return SYLV_E_INVALID; }
     if (o->inner_tol < 0.0 || o->inner_tol >= 1.0) { set_err("inner_tol must be in [0, 1)"); return SYLV_E_INVALID; }
     if (o->refine_max < 0 || o->check_every < 0) { set_err("negative refine_max/check_every"); return SYLV_E_INVALID; }
     if (o->stop_ref != SYLV_STOP_R0 && o->stop_ref != SYLV_STOP_B) { set_err("bad stop_ref"); return SYLV_E_INVALID; }
@@ -561,7 +580,7 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
                 bsize, nrhs);
         return SYLV_E_INVALID;
     }
-    const int fourier = opts->precond == SYLV_PC_FOURIER;
+    const int fourier = is_fourier(opts->precond);
     if (fourier) {
         if (block) { set_err("block CG takes the per-pixel preconditioners only"); return SYLV_E_INVALID; }
         const int dt = opts->precision == SYLV_PREC_MIXED ? SYLV_F32 : SYLV_F64;
@@ -674,6 +693,7 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
     set.bc = bc;
     set.any_pre = any_pre;
     set.fourier = fourier;
+    set.fp_scaled = opts->precond == SYLV_PC_FOURIER_DIAG ? 1 : 0;
     set.fprefa = set.cprefix + (ninst + 1);
     set.fprefb = set.fprefa + (ninst + 1);
     set.total_fa = fpa[ninst];
@@ -1577,8 +1597,8 @@ size_t sylv_workspace_bytes(const sylv_problem *probs, int32_t nprob, int32_t nr
 int sylv_prepare(const sylv_problem *prob, int32_t precond, void *ws, size_t ws_bytes,
                  void *stream) {
     if (!check_problem(prob, 0)) return SYLV_E_INVALID;
-    if (precond < SYLV_PC_NONE || precond > SYLV_PC_FOURIER) { set_err("bad precond"); return SYLV_E_INVALID; }
-    if (precond == SYLV_PC_FOURIER && !fp_grid(*prob)) {
+    if (precond < SYLV_PC_NONE || precond > SYLV_PC_FOURIER_DIAG) { set_err("bad precond"); return SYLV_E_INVALID; }
+    if (is_fourier(precond) && !fp_grid(*prob)) {
         set_err("the Fourier preconditioner needs grid sides that are powers of two in [4, 4096]");
         return SYLV_E_INVALID;
     }
@@ -1628,8 +1648,8 @@ int sylv_precond(const sylv_problem *prob, int32_t dtype, int32_t precond, const
                  void *stream) {
     if (!check_problem(prob, 0)) return SYLV_E_INVALID;
     if (dtype != SYLV_F64 && dtype != SYLV_F32) { set_err("bad dtype"); return SYLV_E_INVALID; }
-    if (precond < SYLV_PC_NONE || precond > SYLV_PC_FOURIER) { set_err("bad precond"); return SYLV_E_INVALID; }
-    if (precond == SYLV_PC_FOURIER) {
+    if (precond < SYLV_PC_NONE || precond > SYLV_PC_FOURIER_DIAG) { set_err("bad precond"); return SYLV_E_INVALID; }
+    if (is_fourier(precond)) {
         char why[200];
         if (!fp_supported((int)prob->ny, (int)prob->nx, prob->k, dtype, why, sizeof(why))) { set_err("%s", why); return SYLV_E_INVALID; }
     }
@@ -1644,7 +1664,7 @@ int sylv_precond(const sylv_problem *prob, int32_t dtype, int32_t precond, const
     }
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     char *base = reinterpret_cast<char *>(ws);
-    if (precond == SYLV_PC_FOURIER) {
+    if (is_fourier(precond)) {
         // one instance without run state: its spectrum in the stand-alone region
         Inst I = operator_inst(*prob, L.prob[0], base, precond);
         I.nchunks = chunks_for(I.n_pix);
@@ -1672,6 +1692,7 @@ int sylv_precond(const sylv_problem *prob, int32_t dtype, int32_t precond, const
         set.total_fa = pre[7];
         set.total_fb = pre[9];
         set.fourier = 1;
+        set.fp_scaled = precond == SYLV_PC_FOURIER_DIAG ? 1 : 0;
         set.fp_lds_rows = fp_lds_bytes(0, I.nx, I.frb, dtype);
         set.fp_lds_cols = fp_lds_bytes(1, I.ny, k, dtype);
         set.fp_cols_gtw = fp_cols_global_twiddles(I.ny, k, dtype) ? 1 : 0;

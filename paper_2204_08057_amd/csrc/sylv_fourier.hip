@@ -125,6 +125,33 @@ __global__ __launch_bounds__(kBlock) void k_fp_tables(int nx, int ny, int face,
     t32[2 * u + 1] = (float)sn;
 }
 
+// Diagonal scale of SYLV_PC_FOURIER_DIAG: thread e of the grid writes 1 / s for pixel p = e % n_pix
+// of component j = e / n_pix, s^2 = diag(G) / diag(Q + I (x) Mbar).  diag(Q_j) at p is
+// tau_j ((kappa_j^2 + d_p)^2 + d_p), the diagonal of (kappa_j^2 I + L)^2 for the grid Laplacian L
+// with d_p neighbours (4 on periodic grids, whose sides here are at least 4; 2 to 4 on a face);
+// diag(G) adds the pixel's mixing block entry M_p[j][j], diag(Q + I (x) Mbar) adds Mbar[j][j].
+__global__ __launch_bounds__(kBlock) void k_fp_scale(const double *__restrict__ M64,
+                                                     const double *__restrict__ fsym, int k,
+                                                     int nx, int ny, int face,
+                                                     double *__restrict__ sc64,
+                                                     float *__restrict__ sc32) {
+    const int n_pix = nx * ny;
+    const int e = blockIdx.x * kBlock + threadIdx.x;
+    if (e >= k * n_pix) return;
+    const int j = e / n_pix, p = e - j * n_pix;
+    const int y = p / nx, x = p - y * nx;
+    const double d = face ? (double)((x > 0) + (x < nx - 1) + (y > 0) + (y < ny - 1)) : 4.0;
+    const double kap2 = fsym[kMaxK * kMaxK + j], tau = fsym[kMaxK * kMaxK + kMaxK + j];
+    const double t = kap2 + d;
+    const double dq = tau * (t * t + d);
+    const int jj = j * k - (j * (j - 1)) / 2;   // packed index of (j, j)
+    const double dg = dq + M64[(size_t)jj * n_pix + p];
+    const double dm = dq + fsym[j * kMaxK + j];
+    const double v = sqrt(dm / dg);
+    sc64[e] = v;
+    sc32[e] = (float)v;
+}
+
 }  // namespace
 
 int fp_rows_per_block(int nx, int ny, int dtype) {
@@ -160,7 +187,7 @@ size_t fp_table_bytes(int nx, int ny) { return sizeof(double) * fp_tabs(nx, ny).
 
 hipError_t launch_fp_setup(const double *W, const double *A, int f, int k, int nx, int ny,
                            int face, const double *coef, double *part, double *fsym,
-                           hipStream_t s) {
+                           const double *M64, double *sc64, float *sc32, hipStream_t s) {
     const int n_pix = nx * ny;
     const int nblk = (int)blocks_for(n_pix, kWChunk);
     hipLaunchKernelGGL(k_wmean_part, dim3(nblk), dim3(kBlock), 0, s, W, f, n_pix, part);
@@ -172,6 +199,10 @@ hipError_t launch_fp_setup(const double *W, const double *A, int f, int k, int n
     const int nt = nx + ny + (nx - 1) + (ny - 1) + (face ? nx + ny : 0);
     hipLaunchKernelGGL(k_fp_tables, dim3((nt + kBlock - 1) / kBlock), dim3(kBlock), 0, s, nx, ny,
                        face, fsym);
+    if ((e = hipGetLastError()) != hipSuccess || !sc64) return e;
+    const int ns = k * n_pix;
+    hipLaunchKernelGGL(k_fp_scale, dim3((ns + kBlock - 1) / kBlock), dim3(kBlock), 0, s, M64, fsym,
+                       k, nx, ny, face, sc64, sc32);
     return hipGetLastError();
 }
 

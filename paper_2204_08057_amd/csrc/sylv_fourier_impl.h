@@ -315,6 +315,12 @@ template <typename T>
 __device__ __forceinline__ GAS T *spectrum(const Inst &I) {
     return reinterpret_cast<GAS T *>(gp(I.fs));
 }
+// The diagonal scale 1 / s of SYLV_PC_FOURIER_DIAG in precision T (null: plain preconditioner).
+template <typename T>
+__device__ __forceinline__ const T *fscale(const Inst &I) {
+    return sizeof(T) == 8 ? reinterpret_cast<const T *>(I.fsc64)
+                          : reinterpret_cast<const T *>(I.fsc32);
+}
 template <typename T>
 __device__ __forceinline__ void cstore(GAS T *S, size_t i, Cx<T> v) {
     cvec_t<T> w;
@@ -481,7 +487,7 @@ __device__ __forceinline__ double dot_re(const Cx<T> (&a)[K], const Cx<T> (&b)[K
 // the first stage loads r and q, r written back.
 // DCT (face grids): the rows' cosine transforms instead, from the reordered rows; the nx real
 // coefficients of each row are stored transposed, S[j][u][y], u < nx, two rows per 8-byte store.
-template <typename T, int CLS, bool DCT>
+template <typename T, int CLS, bool DCT, bool SC>
 __global__ __launch_bounds__(kFT) void k_fp_rows_fwd(const Inst *__restrict__ tab,
                                                      const int *__restrict__ fpre, int ninst,
                                                      int nb, int inner,
@@ -540,6 +546,8 @@ __global__ __launch_bounds__(kFT) void k_fp_rows_fwd(const Inst *__restrict__ ta
     GAS T *r = (use_in ? gp(const_cast<T *>(rin)) : Sel<T>::r(I)) + (size_t)j * I.n_pix;
     const GAS T *qv = Sel<T>::q(I) + (size_t)j * I.n_pix;
     const uint32_t o0 = (uint32_t)y0 * (uint32_t)nx;
+    // SC (SYLV_PC_FOURIER_DIAG): the transforms take S^-1 r
+    const GAS T *sc = gp(fscale<T>(I)) + (SC ? (size_t)j * I.n_pix : 0);
     double rr = 0.0;
     const auto ldg = [&](int q, int i) -> Cx<T> {
         const uint32_t o = o0 + ((uint32_t)(2 * q) << ln) + (uint32_t)(DCT ? cos_src(i, nx) : i);
@@ -551,6 +559,10 @@ __global__ __launch_bounds__(kFT) void k_fp_rows_fwd(const Inst *__restrict__ ta
             bst(r, np, o + (uint32_t)nx, b);
         }
         rr += (double)a * (double)a + (double)b * (double)b;
+        if constexpr (SC) {
+            a *= bld(sc, np, o);
+            b *= bld(sc, np, o + (uint32_t)nx);
+        }
         return {a, b};
     };
     fft_run<T, 0, FR>(buf, tw, ln, h, true, ldg, false, NoStore<T>());
@@ -756,7 +768,7 @@ __global__ __launch_bounds__(kFT, (sizeof(T) == 8 || K > 5 || (DCT && K > 4)) ? 
 // DCT (face grids): the rows' inverse cosine transforms: U[u] = V_2q[u] + i V_(2q+1)[u] with
 // V[u] = exp(i pi u / 2nx) (Z[u] - i Z[nx - u]), the inverse FFT, and the reorder undone as the
 // last stage writes z.
-template <typename T, int CLS, bool DCT>
+template <typename T, int CLS, bool DCT, bool SC>
 __global__ __launch_bounds__(kFT) void k_fp_rows_inv(const Inst *__restrict__ tab,
                                                      const int *__restrict__ fpre, int ninst,
                                                      int nb, int inner, T *__restrict__ zout,
@@ -778,6 +790,8 @@ __global__ __launch_bounds__(kFT) void k_fp_rows_inv(const Inst *__restrict__ ta
     const FpTabs tb = fp_tabs(nx, ny);
     load_table<T>(tw, stage_table<T>(I.fsym, tb, true), nx);
     const int lh = lrb - 1;
+    // SC (SYLV_PC_FOURIER_DIAG): z = S^-1 times the inverse transform
+    const GAS T *sc = gp(fscale<T>(I)) + (SC ? (size_t)j * I.n_pix : 0);
     if (DCT) {
         const GAS T *Sr = spectrum<T>(I) + (size_t)j * nx * ny;
         const Cx<T> *ct = cos_table<T>(I.fsym, tb, true);
@@ -803,8 +817,13 @@ __global__ __launch_bounds__(kFT) void k_fp_rows_inv(const Inst *__restrict__ ta
         const uint32_t o0 = (uint32_t)y0 * (uint32_t)nx;
         const auto stg = [&](int q, int m, Cx<T> v) {
             const uint32_t o = o0 + ((uint32_t)(2 * q) << ln) + (uint32_t)cos_src(m, nx);
-            bst(z, np, o, v.x * scale);
-            bst(z, np, o + (uint32_t)nx, v.y * scale);
+            T s0 = scale, s1 = scale;
+            if constexpr (SC) {
+                s0 *= bld(sc, np, o);
+                s1 *= bld(sc, np, o + (uint32_t)nx);
+            }
+            bst(z, np, o, v.x * s0);
+            bst(z, np, o + (uint32_t)nx, v.y * s1);
         };
         fft_run<T, 1, FR>(buf, tw, ln, h, false, NoLoad<T>(), true, stg);
         return;
@@ -841,8 +860,13 @@ __global__ __launch_bounds__(kFT) void k_fp_rows_inv(const Inst *__restrict__ ta
     const uint32_t o0 = (uint32_t)y0 * (uint32_t)nx;
     const auto stg = [&](int q, int i, Cx<T> v) {
         const uint32_t o = o0 + ((uint32_t)(2 * q) << ln) + (uint32_t)i;
-        bst(z, np, o, v.x * scale);
-        bst(z, np, o + (uint32_t)nx, v.y * scale);
+        T s0 = scale, s1 = scale;
+        if constexpr (SC) {
+            s0 *= bld(sc, np, o);
+            s1 *= bld(sc, np, o + (uint32_t)nx);
+        }
+        bst(z, np, o, v.x * s0);
+        bst(z, np, o + (uint32_t)nx, v.y * s1);
     };
     fft_run<T, 1, FR>(buf, tw, ln, h, false, NoLoad<T>(), true, stg);
 }
@@ -901,10 +925,16 @@ hipError_t fp_apply_impl(const InstSet &set, int k, int inner, const void *rin, 
         constexpr int K = decltype(tag)::value;
         hipError_t e = for_each_class(set.fp_rmask_x, [&](auto fr) -> hipError_t {
             constexpr int FR = decltype(fr)::value;   // the class
-            hipLaunchKernelGGL((k_fp_rows_fwd<T, FR, DCT>), dim3(set.total_fa), dim3(kFT), lr, s,
-                               set.table, set.fprefa, set.ninst, set.total_fa, mixed,
-                               reinterpret_cast<const T *>(rin), rin ? 1 : 0,
-                               inner >= 0 ? upd : 0, it);
+            if (set.fp_scaled)
+                hipLaunchKernelGGL((k_fp_rows_fwd<T, FR, DCT, true>), dim3(set.total_fa),
+                                   dim3(kFT), lr, s, set.table, set.fprefa, set.ninst,
+                                   set.total_fa, mixed, reinterpret_cast<const T *>(rin),
+                                   rin ? 1 : 0, inner >= 0 ? upd : 0, it);
+            else
+                hipLaunchKernelGGL((k_fp_rows_fwd<T, FR, DCT, false>), dim3(set.total_fa),
+                                   dim3(kFT), lr, s, set.table, set.fprefa, set.ninst,
+                                   set.total_fa, mixed, reinterpret_cast<const T *>(rin),
+                                   rin ? 1 : 0, inner >= 0 ? upd : 0, it);
             return hipGetLastError();
         });
         if (e != hipSuccess) return e;
@@ -928,9 +958,16 @@ hipError_t fp_apply_impl(const InstSet &set, int k, int inner, const void *rin, 
         if (e != hipSuccess) return e;
         return for_each_class(set.fp_rmask_x, [&](auto fr) -> hipError_t {
             constexpr int FR = decltype(fr)::value;   // the class
-            hipLaunchKernelGGL((k_fp_rows_inv<T, FR, DCT>), dim3(set.total_fa), dim3(kFT), lr, s,
-                               set.table, set.fprefa, set.ninst, set.total_fa, mixed,
-                               reinterpret_cast<T *>(zout), zout ? 1 : 0);
+            if (set.fp_scaled)
+                hipLaunchKernelGGL((k_fp_rows_inv<T, FR, DCT, true>), dim3(set.total_fa),
+                                   dim3(kFT), lr, s, set.table, set.fprefa, set.ninst,
+                                   set.total_fa, mixed, reinterpret_cast<T *>(zout),
+                                   zout ? 1 : 0);
+            else
+                hipLaunchKernelGGL((k_fp_rows_inv<T, FR, DCT, false>), dim3(set.total_fa),
+                                   dim3(kFT), lr, s, set.table, set.fprefa, set.ninst,
+                                   set.total_fa, mixed, reinterpret_cast<T *>(zout),
+                                   zout ? 1 : 0);
             return hipGetLastError();
         });
     });

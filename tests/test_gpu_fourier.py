@@ -255,3 +255,110 @@ def test_face_batch_of_twelve_faces():
             n = q.k * q.n_pix
             assert rel(x[off:off + n].reshape(q.k, q.n_pix), osv.solve_dense(q)) <= bound
             off += n
+
+
+# ---- diagonally scaled variant (SYLV_PC_FOURIER_DIAG): z = S^-1 (Q + I (x) Mbar)^-1 S^-1 r ------
+
+DIAG_SHAPES = [("periodic", s) for s in [(8, 16, 3, 5), (32, 64, 4, 9), (128, 32, 8, 16),
+                                         (2048, 16, 4, 9), (8, 4096, 2, 3), (4096, 4, 2, 3)]] + \
+              [("face", s) for s in [(8, 16, 3, 5), (64, 32, 4, 9), (1024, 8, 8, 9)]]
+
+
+@pytest.mark.parametrize("boundary,shape", DIAG_SHAPES)
+def test_diag_application_matches_oracle(boundary, shape):
+    ny, nx, k, f = shape
+    p = make_problem(ny, nx, k, f, seed=5700 + ny + nx, noise="hetero", mask_frac=0.1,
+                     boundary=boundary)
+    dp = sy.DeviceProblem.from_numpy(p)
+    R = random_maps(p, seed=5701, nrhs=2)
+    Minv = opcg.fourier_preconditioner(p, scaled=True)
+    ref = np.stack([Minv(R[i]) for i in range(2)])
+    plain = np.stack([opcg.fourier_preconditioner(p)(R[i]) for i in range(2)])
+    assert rel(plain, ref) > 1e-3   # the scale is not trivial on these weights
+    say("diag application", boundary, shape)
+    assert rel(host(sy.precond(dp, dev(R), kind=sy.SYLV_PC_FOURIER_DIAG)), ref) <= 1e-12
+    assert rel(host(sy.precond(dp, dev(R, torch.float32), kind=sy.SYLV_PC_FOURIER_DIAG)),
+               ref) <= 2e-5
+
+
+@pytest.mark.parametrize("precision,tol,bound", [(sy.SYLV_PREC_F64, 1e-12, 1e-8),
+                                                 (sy.SYLV_PREC_MIXED, 1e-11, 1e-7)])
+@pytest.mark.parametrize("boundary,shape", [("periodic", (32, 64, 4, 9)),
+                                            ("periodic", (16, 16, 6, 7)),
+                                            ("face", (32, 64, 4, 9)), ("face", (64, 32, 2, 3))])
+def test_diag_solve_matches_dense(boundary, shape, precision, tol, bound):
+    ny, nx, k, f = shape
+    p = make_problem(ny, nx, k, f, seed=5800 + ny * nx, noise="hetero", mask_frac=0.1,
+                     boundary=boundary)
+    dp = sy.DeviceProblem.from_numpy(p)
+    say("diag solve", boundary, shape, precision)
+    X, st = sy.pcg_solve(dp, Y=dev(p.Y), opts=sy.SolveOptions(
+        tol=tol, precision=precision, precond=sy.SYLV_PC_FOURIER_DIAG))
+    assert st[0]["status"] == 0, st
+    assert rel(host(X).reshape(p.k, p.n_pix), osv.solve_dense(p)) <= bound
+
+
+@pytest.mark.parametrize("boundary,shape", [("periodic", (64, 64, 3, 6)),
+                                            ("periodic", (128, 128, 3, 9)),
+                                            ("face", (128, 128, 3, 9))])
+def test_diag_iteration_count_matches_oracle(boundary, shape):
+    """Float64 runs to 1e-8 take the oracle's iteration count with the scaled preconditioner to
+    within 1."""
+    ny, nx, k, f = shape
+    p = make_problem(ny, nx, k, f, seed=5900 + ny, noise="hetero", boundary=boundary)
+    ref = opcg.pcg(p, tol=1e-8, max_iter=2000, precond="fourier_diag")
+    say("diag iterations", boundary, shape, "oracle", ref["iters"])
+    dp = sy.DeviceProblem.from_numpy(p)
+    X, st = sy.pcg_solve(dp, Y=dev(p.Y), opts=sy.SolveOptions(
+        tol=1e-8, precond=sy.SYLV_PC_FOURIER_DIAG))
+    assert st[0]["status"] == 0, st
+    say("  gpu", st[0]["iters"])
+    assert abs(st[0]["iters"] - ref["iters"]) <= 1
+
+
+def test_diag_homoscedastic_grid_solves_in_one_iteration():
+    """Pixel-independent weights: s = 1 and the scaled preconditioner is G^-1 as well."""
+    p = make_problem(64, 32, 3, 6, seed=5950, noise="homo")
+    dp = sy.DeviceProblem.from_numpy(p)
+    X, st = sy.pcg_solve(dp, Y=dev(p.Y), opts=sy.SolveOptions(
+        tol=1e-10, precond=sy.SYLV_PC_FOURIER_DIAG))
+    assert st[0]["status"] == 0 and st[0]["iters"] <= 2, st
+    assert rel(host(X).reshape(p.k, p.n_pix), osv.solve_fft(p)) <= 1e-9
+
+
+def test_diag_fixed_schedule_equals_adaptive():
+    """The fixed schedule (no host checks) and the adaptive one run the same iterations: equal
+    solutions, bitwise."""
+    p = make_problem(64, 64, 3, 6, seed=5960, noise="hetero", mask_frac=0.1)
+    dp = sy.DeviceProblem.from_numpy(p)
+    for precision in (sy.SYLV_PREC_F64, sy.SYLV_PREC_MIXED):
+        o = sy.SolveOptions(tol=1e-9, precision=precision, precond=sy.SYLV_PC_FOURIER_DIAG)
+        Xa, sa = sy.pcg_solve(dp, Y=dev(p.Y), opts=o)
+        of = sy.SolveOptions(tol=1e-9, precision=precision, precond=sy.SYLV_PC_FOURIER_DIAG,
+                             schedule=sy.SYLV_SCHED_FIXED, max_iter=sa[0]["iters"] + 5)
+        Xf, sf = sy.pcg_solve(dp, Y=dev(p.Y), opts=of)
+        say("diag fixed", precision, sa[0]["iters"], sf[0]["iters"])
+        assert sa[0]["status"] == 0 and sf[0]["status"] == 0, (sa, sf)
+        assert torch.equal(Xa, Xf)
+
+
+@pytest.mark.parametrize("precision,tol,bound", [(sy.SYLV_PREC_F64, 1e-12, 1e-8),
+                                                 (sy.SYLV_PREC_MIXED, 1e-11, 1e-7)])
+def test_diag_het_1024_whole_solution_vs_oracle(precision, tol, bound):
+    """The timing workload solved with the scaled preconditioner, whole vector against the
+    oracle's block-Jacobi PCG to 1e-13."""
+    global _HET
+    try:
+        p, ref = _HET
+    except NameError:
+        p = workload("het_1024")[0]
+        say("oracle PCG het_1024 to 1e-13 (CPU)")
+        ref = opcg.pcg(p, tol=1e-13, max_iter=5000, precond="block")["x"]
+        _HET = (p, ref)
+    say("diag het_1024", precision)
+    dp = sy.DeviceProblem.from_numpy(p)
+    X, st = sy.pcg_solve(dp, Y=dev(p.Y), opts=sy.SolveOptions(
+        tol=tol, precision=precision, precond=sy.SYLV_PC_FOURIER_DIAG))
+    assert st[0]["status"] == 0, st
+    say("  iterations", st[0]["iters"], "outer", st[0]["outer"])
+    assert rel(host(X).reshape(p.k, p.n_pix), ref) <= bound
