@@ -299,14 +299,15 @@ def summarize(ms, st):
 
 def bench_masked(sy, torch, steps, warmup, cpu=False):
     """2048^2, k = 4, f = 9, 10 % masked pixels (beyond the last-level cache): mixed precision vs
-    float64 solves with the block-Jacobi and the Fourier preconditioner, and the stand-alone
-    applies."""
+    float64 solves with the block-Jacobi, the Fourier and the diagonally scaled Fourier
+    preconditioner, and the stand-alone applies."""
     from workloads import workload
     prob = workload("masked_2048")[0]
     dp = sy.DeviceProblem.from_numpy(prob)
     Y = torch.as_tensor(prob.Y, device="cuda")
     res = {}
-    for pc, suffix in ((sy.SYLV_PC_BLOCK, ""), (sy.SYLV_PC_FOURIER, "_fourier")):
+    for pc, suffix in ((sy.SYLV_PC_BLOCK, ""), (sy.SYLV_PC_FOURIER, "_fourier"),
+                       (sy.SYLV_PC_FOURIER_DIAG, "_fourier_diag")):
         for label, prec in (("mixed", sy.SYLV_PREC_MIXED), ("f64", sy.SYLV_PREC_F64)):
             o = sy.SolveOptions(tol=1e-8, precision=prec, precond=pc)
             ms, st, _ = time_solves(sy, torch, dp, Y, None, o, 1, steps, warmup)
@@ -430,23 +431,25 @@ def bench_other_workloads(sy, torch, steps, warmup, cpu=False):
     ms_b = (time.perf_counter() - t0) / steps * 1e3
     out["grad_512"] = {"forward": summarize(ms_f, st), "backward_ms": round(ms_b, 3),
                        "backward_iters": stb["iters"], "backward_ok": stb["status"] == 0}
-    of = dataclasses.replace(o, precond=sy.SYLV_PC_FOURIER)
-    ms_ff, stf, Xf = time_solves(sy, torch, dp, Y, None, of, 1, steps, warmup)
-    wsf = torch.empty(sy.workspace_bytes([dp], 1, of), dtype=torch.uint8, device="cuda")
-    for _ in range(warmup):
-        sy.pcg_backward(dp, Y, Xf, gbar, of, ws=wsf)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        _, gf, stbf = sy.pcg_backward(dp, Y, Xf, gbar, of, ws=wsf)
-    torch.cuda.synchronize()
-    out["grad_512"]["fourier"] = {
-        "forward": summarize(ms_ff, stf),
-        "backward_ms": round((time.perf_counter() - t0) / steps * 1e3, 3),
-        "backward_iters": stbf["iters"], "backward_ok": stbf["status"] == 0,
-        "grad_rel_diff_vs_block": {kk: float(torch.linalg.norm(gf[kk] - g[kk]) /
-                                             max(float(torch.linalg.norm(g[kk])), 1e-300))
-                                   for kk in g}}
+    for key, pcf in (("fourier", sy.SYLV_PC_FOURIER), ("fourier_diag", sy.SYLV_PC_FOURIER_DIAG)):
+        of = dataclasses.replace(o, precond=pcf)
+        ms_ff, stf, Xf = time_solves(sy, torch, dp, Y, None, of, 1, steps, warmup)
+        wsf = torch.empty(sy.workspace_bytes([dp], 1, of), dtype=torch.uint8, device="cuda")
+        for _ in range(warmup):
+            sy.pcg_backward(dp, Y, Xf, gbar, of, ws=wsf)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, gf, stbf = sy.pcg_backward(dp, Y, Xf, gbar, of, ws=wsf)
+        torch.cuda.synchronize()
+        out["grad_512"][key] = {
+            "forward": summarize(ms_ff, stf),
+            "backward_ms": round((time.perf_counter() - t0) / steps * 1e3, 3),
+            "backward_iters": stbf["iters"], "backward_ok": stbf["status"] == 0,
+            "grad_rel_diff_vs_block": {kk: float(torch.linalg.norm(gf[kk] - g[kk]) /
+                                                 max(float(torch.linalg.norm(g[kk])), 1e-300))
+                                       for kk in g}}
+        del wsf
     log(f"grad_512: {out['grad_512']}")
     if cpu:
         # the oracle at full size: assembly and 10 PCG iterations (scaled to the forward and
@@ -486,7 +489,9 @@ def bench_sweep(sy, torch):
     for label, prec, pc in (("mixed", sy.SYLV_PREC_MIXED, sy.SYLV_PC_BLOCK),
                             ("f64", sy.SYLV_PREC_F64, sy.SYLV_PC_BLOCK),
                             ("mixed_fourier", sy.SYLV_PREC_MIXED, sy.SYLV_PC_FOURIER),
-                            ("f64_fourier", sy.SYLV_PREC_F64, sy.SYLV_PC_FOURIER)):
+                            ("f64_fourier", sy.SYLV_PREC_F64, sy.SYLV_PC_FOURIER),
+                            ("mixed_fourier_diag", sy.SYLV_PREC_MIXED, sy.SYLV_PC_FOURIER_DIAG),
+                            ("f64_fourier_diag", sy.SYLV_PREC_F64, sy.SYLV_PC_FOURIER_DIAG)):
         o = sy.SolveOptions(tol=cfg["tol"], precision=prec, stop_ref=sy.SYLV_STOP_B, precond=pc)
         ws = torch.empty(sy.workspace_bytes([dp], 1, o), dtype=torch.uint8, device="cuda")
         for mode in ("cold", "warm"):
@@ -520,7 +525,8 @@ def bench_sky(sy, torch, steps, warmup, cpu=False):
     dps = [sy.DeviceProblem.from_numpy(p) for p in probs]
     Y = torch.cat([torch.as_tensor(p.Y.ravel(), device="cuda") for p in probs])
     res = {"faces": len(probs), "pixels_per_map": sum(p.n_pix for p in probs)}
-    for pc, suffix in ((sy.SYLV_PC_BLOCK, ""), (sy.SYLV_PC_FOURIER, "_cosine")):
+    for pc, suffix in ((sy.SYLV_PC_BLOCK, ""), (sy.SYLV_PC_FOURIER, "_cosine"),
+                       (sy.SYLV_PC_FOURIER_DIAG, "_cosine_diag")):
         for label, prec in (("mixed", sy.SYLV_PREC_MIXED), ("f64", sy.SYLV_PREC_F64)):
             o = sy.SolveOptions(tol=tol, precision=prec, precond=pc)
             ms, st, _ = time_solves(sy, torch, dps, Y, None, o, 1, steps, warmup)
@@ -589,7 +595,10 @@ def bench_sylvester(sy, torch, steps, warmup, max_iter=800, cpu=False):
     for label, prec, pc in (("pcg_f64", sy.SYLV_PREC_F64, sy.SYLV_PC_BLOCK),
                             ("pcg_mixed", sy.SYLV_PREC_MIXED, sy.SYLV_PC_BLOCK),
                             ("pcg_fourier_f64", sy.SYLV_PREC_F64, sy.SYLV_PC_FOURIER),
-                            ("pcg_fourier_mixed", sy.SYLV_PREC_MIXED, sy.SYLV_PC_FOURIER)):
+                            ("pcg_fourier_mixed", sy.SYLV_PREC_MIXED, sy.SYLV_PC_FOURIER),
+                            ("pcg_fourier_diag_f64", sy.SYLV_PREC_F64, sy.SYLV_PC_FOURIER_DIAG),
+                            ("pcg_fourier_diag_mixed", sy.SYLV_PREC_MIXED,
+                             sy.SYLV_PC_FOURIER_DIAG)):
         o = sy.SolveOptions(tol=tol, precision=prec, precond=pc)
         ms, stl, Xc = time_solves(sy, torch, dp, Y, None, o, 1, steps, warmup)
         res[label] = summarize(ms, stl)
