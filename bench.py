@@ -782,10 +782,10 @@ def main():
         for _ in range(3):
             sy.apply(dp, X32, ws=ws_app, prepared=True)
             sy.apply(dp, X64, ws=ws_app, prepared=True)
-        # one solve of each precision with each preconditioner, so that the counters also cover
-        # the CG kernels and the FFT passes, and three stand-alone Fourier applications of each
-        # precision
-        for pc in (sy.SYLV_PC_BLOCK, sy.SYLV_PC_FOURIER):
+        # one solve of each precision with each preconditioner (block-Jacobi, Fourier, scaled
+        # Fourier), so that the counters also cover the CG kernels and the FFT passes, and three
+        # stand-alone Fourier applications of each precision
+        for pc in (sy.SYLV_PC_BLOCK, sy.SYLV_PC_FOURIER, sy.SYLV_PC_FOURIER_DIAG):
             for prec in (sy.SYLV_PREC_MIXED, sy.SYLV_PREC_F64):
                 sy.pcg_solve(dp, Y=Y, opts=sy.SolveOptions(tol=tol, precision=prec, precond=pc))
         ws_fp = sy.binding.prepare(dp, sy.SYLV_PC_FOURIER)
