@@ -63,10 +63,14 @@ def fourier_preconditioner(prob, scaled: bool = False):
     Mbar = sum_f mean_p(W[f, :]) a_f a_f^T, so one k x k block remains per mode (a fixed SPD
     operator; the paper allows any preconditioner, Section 3.2, remarks after Alg. 2).  When W
     does not depend on the pixel this is G^-1 exactly.
-    scaled: the diagonally matched variant z = S^-1 (Q + I (x) Mbar)^-1 S^-1 r, S = diag(s) with
-    s^2 = diag(G) / diag(Q + I (x) Mbar) per pixel and component, so that the operator it
-    inverts, S (Q + I (x) Mbar) S, has the diagonal of G (still fixed and SPD; s = 1 when W does
-    not depend on the pixel).
+    scaled: True (or "diag") gives the diagonally matched variant z = S^-1 (Q + I (x) Mbar)^-1
+    S^-1 r, S = diag(s) with s^2 = diag(G) / diag(Q + I (x) Mbar) per pixel and component, so that
+    the operator it inverts, S (Q + I (x) Mbar) S, has the diagonal of G (still fixed and SPD;
+    s = 1 when W does not depend on the pixel).  "block" gives the block-matched variant
+    z = T^T (Q + I (x) Mbar)^-1 T r with T block diagonal over the pixels, T_p = L0_p Lp^-1 from
+    the Cholesky factors of G's k x k block at pixel p (Lp Lp^T) and of the same block of
+    Q + I (x) Mbar (L0_p L0_p^T): the operator it inverts, T^-1 (Q + I (x) Mbar) T^-T, has G's
+    pixel blocks.
     Returns a function r[k, n_pix] -> z[k, n_pix]."""
     from scipy import fft as sfft
     from .solve import fourier_symbols
@@ -96,12 +100,40 @@ def fourier_preconditioner(prob, scaled: bool = False):
 
     if not scaled:
         return apply_inv
+    if scaled == "block":
+        T = block_scale(prob)                           # [n_pix, k, k], lower triangular
+
+        def apply_block(r):
+            u = np.einsum("pij,jp->ip", T, np.asarray(r, dtype=np.float64).reshape(k, ny * nx))
+            return np.einsum("pji,jp->ip", T, apply_inv(u))
+
+        return apply_block
     s = diagonal_scale(prob)
 
     def apply_scaled(r):
         return apply_inv(np.asarray(r, dtype=np.float64).reshape(k, ny * nx) / s) / s
 
     return apply_scaled
+
+
+def block_scale(prob):
+    """T[n_pix, k, k] = L0_p Lp^-1 per pixel: Lp, L0_p the Cholesky factors of the k x k pixel
+    blocks of G and of Q + I (x) Mbar, both read from the assembled operators (entry (i, j) of
+    pixel p's block sits on the diagonal at offset (j - i) n_pix)."""
+    G = op.posterior_precision(prob)
+    Q = G - op.likelihood_term(prob)
+    k, n = prob.k, prob.n_pix
+    wbar = prob.W.mean(axis=1)
+    mbar = (prob.A.T * wbar) @ prob.A
+    Bp = np.empty((n, k, k))
+    B0 = np.empty((n, k, k))
+    for i in range(k):
+        for j in range(i, k):
+            g = G.diagonal((j - i) * n)[i * n:(i + 1) * n]
+            q = Q.diagonal((j - i) * n)[i * n:(i + 1) * n]
+            Bp[:, i, j] = Bp[:, j, i] = g
+            B0[:, i, j] = B0[:, j, i] = q + mbar[i, j]
+    return np.linalg.cholesky(B0) @ np.linalg.inv(np.linalg.cholesky(Bp))
 
 
 def diagonal_scale(prob):
@@ -128,6 +160,8 @@ def pcg(prob, b=None, x0=None, tol=1e-12, max_iter=10000, precond="block", G=Non
         Minv = fourier_preconditioner(prob)
     elif precond == "fourier_diag":
         Minv = fourier_preconditioner(prob, scaled=True)
+    elif precond == "fourier_block":
+        Minv = fourier_preconditioner(prob, scaled="block")
     else:
         Minv, _ = block_jacobi(prob, G, precond)
     bv = np.asarray(b, dtype=np.float64).reshape(k, n_pix)

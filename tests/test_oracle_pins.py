@@ -561,3 +561,64 @@ def test_scaled_fourier_pcg_matches_dense_in_fewer_iterations(boundary):
     rf = opcg.pcg(p, tol=1e-11, precond="fourier")
     assert np.linalg.norm(rs["x"] - xd) <= 1e-8 * np.linalg.norm(xd)
     assert rs["iters"] < rf["iters"], (rs["iters"], rf["iters"])
+
+
+# ---- block-scaled Fourier preconditioner T^T (Q + I (x) Mbar)^-1 T ----------------------------
+
+def _block_diag_dense(T, k, n):
+    """The [k n, k n] matrix of the per-pixel blocks T[p] in the component-major layout."""
+    D = np.zeros((k * n, k * n))
+    for p in range(n):
+        idx = np.arange(k) * n + p
+        D[np.ix_(idx, idx)] = T[p]
+    return D
+
+
+@pytest.mark.parametrize("boundary", ["periodic", "face"])
+def test_block_scaled_fourier_preconditioner_matches_pixel_blocks(boundary):
+    """The block-scaled preconditioner inverts T^-1 M0 T^-T with M0 = Q + I (x) Mbar assembled
+    without transforms and T_p lower triangular: its dense matrix P is symmetric positive
+    definite, P^-1 equals that operator, and every k x k pixel block of P^-1 equals G's."""
+    p = make_problem(6, 8, 3, 4, seed=9100, noise="hetero", mask_frac=0.15, boundary=boundary)
+    k, n = p.k, p.n_pix
+    P = _dense_columns(opcg.fourier_preconditioner(p, scaled="block"), k, n)
+    G = op.posterior_precision(p, dense=True)
+    Q = G - op.likelihood_term(p).toarray()
+    mbar = (p.A.T * p.W.mean(axis=1)) @ p.A
+    M0 = Q + np.kron(mbar, np.eye(n))
+    T = opcg.block_scale(p)
+    assert np.abs(np.triu(T, 1)).max() == 0.0
+    Tinv = np.linalg.inv(_block_diag_dense(T, k, n))
+    Pinv = np.linalg.inv(0.5 * (P + P.T))
+    assert np.abs(P - P.T).max() <= 1e-12 * np.abs(P).max()
+    assert np.linalg.eigvalsh(0.5 * (P + P.T)).min() > 0
+    assert np.abs(Pinv - Tinv @ M0 @ Tinv.T).max() <= 1e-9 * np.abs(M0).max()
+    for pix in range(n):
+        idx = np.arange(k) * n + pix
+        assert np.abs(Pinv[np.ix_(idx, idx)] - G[np.ix_(idx, idx)]).max() <= 1e-9 * np.abs(G).max()
+
+
+def test_block_scaled_fourier_preconditioner_special_cases():
+    """Pixel-independent weights: T = I and the plain preconditioner; k = 1: T = 1 / s and the
+    diagonally scaled one."""
+    p = make_problem(8, 8, 3, 5, seed=9110, noise="homo")
+    assert np.abs(opcg.block_scale(p) - np.eye(3)).max() <= 1e-13
+    R = np.random.default_rng(9111).standard_normal((p.k, p.n_pix))
+    Zb = opcg.fourier_preconditioner(p, scaled="block")(R)
+    assert np.linalg.norm(Zb - opcg.fourier_preconditioner(p)(R)) <= 1e-13 * np.linalg.norm(Zb)
+    q = make_problem(8, 8, 1, 3, seed=9112, noise="hetero", mask_frac=0.2)
+    assert np.abs(opcg.block_scale(q)[:, 0, 0] - 1.0 / opcg.diagonal_scale(q)[0]).max() <= 1e-13
+    R1 = np.random.default_rng(9113).standard_normal((1, q.n_pix))
+    Zb1 = opcg.fourier_preconditioner(q, scaled="block")(R1)
+    Zd1 = opcg.fourier_preconditioner(q, scaled=True)(R1)
+    assert np.linalg.norm(Zb1 - Zd1) <= 1e-13 * np.linalg.norm(Zd1)
+
+
+@pytest.mark.parametrize("boundary", ["periodic", "face"])
+def test_block_scaled_fourier_pcg_matches_dense(boundary):
+    p = make_problem(32, 32, 4, 6, seed=3, noise="hetero", mask_frac=0.1, boundary=boundary)
+    xd = osv.solve_dense(p)
+    rb = opcg.pcg(p, tol=1e-11, precond="fourier_block")
+    rf = opcg.pcg(p, tol=1e-11, precond="fourier")
+    assert np.linalg.norm(rb["x"] - xd) <= 1e-8 * np.linalg.norm(xd)
+    assert rb["iters"] < rf["iters"], (rb["iters"], rf["iters"])
