@@ -136,22 +136,22 @@ def cg_iteration_seconds(sy, torch, dp, Y, ws, precision, precond, n1=40, n2=140
 
 
 def cg_iteration_bytes_per_pixel(k: int, elem: int, fourier: bool = False,
-                                  nx: int = 1024, scaled: bool = False) -> float:
+                                  nx: int = 1024, scale_planes: int = 0) -> float:
     """Algorithmic bytes of one CG iteration per pixel: the fused apply reads p_old, z and the
     k(k+1)/2 mixing planes and writes p, q, and it advances x (float32: read and write x every
     iteration; float64: every second iteration, reading x and p_(i-2) and writing x, i.e. 1.5 k
     planes per iteration on average).  Block-Jacobi: the update reads r, q and the bfloat16
     factor planes and writes r, z.  Fourier: the update reads r, q and writes r; the three FFT
     passes read r and write the half spectrum, read and write it again (column pass), and read it
-    and write z: 6 k planes, the half spectrum being (nx/2 + 1) / (nx/2) planes.  scaled (the
-    diagonally scaled variant): the two row passes also read the k scale planes."""
+    and write z: 6 k planes, the half spectrum being (nx/2 + 1) / (nx/2) planes.  The scaled
+    variants' two row passes also read the scale planes (diagonal: k, block: k(k+1)/2)."""
     mk = k * (k + 1) // 2
     x_planes = 2.0 * k if elem == 4 else 1.5 * k
     apply = (4 * k + mk + x_planes) * elem
     if not fourier:
         return apply + 4 * k * elem + mk * 2
     half = (nx // 2 + 1) / (nx // 2)
-    return apply + 3 * k * elem + (2 * k + 4 * k * half) * elem + (2 * k * elem if scaled else 0)
+    return apply + 3 * k * elem + (2 * k + 4 * k * half) * elem + 2 * scale_planes * elem
 
 
 def cpu_baseline(prob, tol, precond="block"):
@@ -806,7 +806,10 @@ def main():
                 "fourier": (sy.SYLV_PC_FOURIER, "Fourier (pixel-mean weights, per-mode inverse)"),
                 "fourier_diag": (sy.SYLV_PC_FOURIER_DIAG,
                                  "Fourier with diagonal scaling (pixel-mean weights, per-mode "
-                                 "inverse, scaled per pixel to the diagonal of G)")}
+                                 "inverse, scaled per pixel to the diagonal of G)"),
+                "fourier_block": (sy.SYLV_PC_FOURIER_BLOCK,
+                                  "Fourier with block scaling (pixel-mean weights, per-mode "
+                                  "inverse, transformed per pixel to G's k x k pixel blocks)")}
     opts = {(label, pc): sy.SolveOptions(tol=tol, precision=prec, precond=preconds[pc][0])
             for pc in preconds
             for label, prec in (("mixed", sy.SYLV_PREC_MIXED), ("f64", sy.SYLV_PREC_F64))}
@@ -869,8 +872,9 @@ def main():
             # Fourier runs reach the float32 floor within ~10 iterations: time 3 against 11
             n1, n2 = (40, 140) if pc == "block" else (3, 11)
             sec = cg_iteration_seconds(sy, torch, dp, Y, ws, prec, preconds[pc][0], n1, n2)
-            nb = int(cg_iteration_bytes_per_pixel(k, elem, pc != "block", prob.nx,
-                                                  pc == "fourier_diag") * n_pix)
+            planes = {"fourier_diag": k, "fourier_block": k * (k + 1) // 2}.get(pc, 0)
+            nb = int(cg_iteration_bytes_per_pixel(k, elem, pc != "block", prob.nx, planes)
+                     * n_pix)
             cg_it[f"{label}_{pc}"] = {
                 "us": round(sec * 1e6, 2), "algorithmic_bytes": nb,
                 "achieved": round(nb / sec / 1e9, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",

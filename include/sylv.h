@@ -110,6 +110,14 @@ extern "C" {
                                    (the heteroscedastic weights enter through the scale; s = 1
                                    for pixel-independent weights).  Same grids and limits as
                                    SYLV_PC_FOURIER                                               */
+#define SYLV_PC_FOURIER_BLOCK 5 /* z = T^T (Q + I (x) Mbar)^-1 T r, T block diagonal over the
+                                   pixels with T_p = L0_p Lp^-1 (Lp, L0_p the Cholesky factors of
+                                   the k x k pixel blocks of G and of Q + I (x) Mbar): the
+                                   operator it inverts has G's pixel blocks.  Same grids as
+                                   SYLV_PC_FOURIER, and the row passes hold every component of
+                                   two grid rows and the stage table in LDS: k * nx <= 8192 in
+                                   float32, (1 + 33 k / 32) nx <= 10112 in float64 (else
+                                   SYLV_E_INVALID)                                               */
 
 /* One posterior-mean system (Section 2, Section 3).  Host struct of device pointers. */
 typedef struct sylv_problem {
@@ -132,7 +140,7 @@ typedef struct sylv_pcg_opts {
     double  inner_tol;     /* mixed: smallest relative reduction asked of one float32 inner run
                               (0 = 1e-5)                                                          */
     int32_t refine_max;    /* mixed: maximum number of float64 refinement steps (0 = 8)          */
-    int32_t precond;       /* SYLV_PC_NONE, _JACOBI, _BLOCK, _FOURIER or _FOURIER_DIAG            */
+    int32_t precond;       /* SYLV_PC_NONE, _JACOBI, _BLOCK, _FOURIER, _FOURIER_DIAG, _FOURIER_BLOCK */
     int32_t check_every;   /* iterations enqueued between host convergence checks (0 = 8)        */
     int32_t block;         /* 1: block CG over blocks of s right-hand sides of each problem
                               (s = block_size): s x s Gram matrices in float64, alpha and beta

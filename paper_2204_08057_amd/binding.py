@@ -42,6 +42,7 @@ SYLV_PC_JACOBI = 1
 SYLV_PC_BLOCK = 2
 SYLV_PC_FOURIER = 3
 SYLV_PC_FOURIER_DIAG = 4
+SYLV_PC_FOURIER_BLOCK = 5
 
 STATUS_NAMES = {
     SYLV_OK: "ok", SYLV_NOT_CONVERGED: "not converged", SYLV_BREAKDOWN: "breakdown",

@@ -104,7 +104,7 @@ int chunks_for(int n_pix) { return (n_pix + kChunk - 1) / kChunk; }
 struct ProbLayout {
     size_t coef, M64, M32, P64, P32, P16;
     size_t fsym, fpart;   // Fourier preconditioner: symbol block and the weight-mean partials
-    size_t fsc64, fsc32;  // its diagonal scale (SYLV_PC_FOURIER_DIAG), on Fourier grids only
+    size_t fsc64, fsc32;  // its diagonal or block scale, on Fourier grids only
 };
 struct InstLayout {
     size_t st, partial, b, r, z, p, p2, q, r32, z32, p32, p32b, q32, d32;
@@ -125,8 +125,10 @@ struct Layout {
 // Whether a grid can take the Fourier preconditioner in some precision (the stand-alone
 // workspace then holds its spectrum), and the spectrum's bytes (complex float64 half spectrum;
 // the cosine coefficients of face grids take less).
-// The two Fourier-basis preconditioners (plain and diagonally scaled).
-bool is_fourier(int pc) { return pc == SYLV_PC_FOURIER || pc == SYLV_PC_FOURIER_DIAG; }
+// The Fourier-basis preconditioners (plain, diagonally scaled, block scaled).
+bool is_fourier(int pc) {
+    return pc == SYLV_PC_FOURIER || pc == SYLV_PC_FOURIER_DIAG || pc == SYLV_PC_FOURIER_BLOCK;
+}
 
 bool fp_grid(const sylv_problem &p) {
     char why[160];
@@ -173,7 +175,7 @@ bool make_layout(const sylv_problem *probs, int nprob, int nrhs, bool solve, Lay
         P.fpart = off; off = align_up(off + sizeof(double) * fp_setup_partials((int)n, probs[g].f));
         P.fsc64 = P.fsc32 = 0;
         if (fp_grid(probs[g])) {
-            const size_t vk = (size_t)probs[g].k * n;
+            const size_t vk = (size_t)packed_size(probs[g].k) * n;   // block: k(k+1)/2 planes
             P.fsc64 = off; off = align_up(off + sizeof(double) * vk);
             P.fsc32 = off; off = align_up(off + sizeof(float) * vk);
         }
@@ -264,7 +266,7 @@ Inst operator_inst(const sylv_problem &p, const ProbLayout &P, char *base, int p
     I.n_pix = (int)(p.ny * p.nx);
     I.tiles_x = (I.nx + kTileX - 1) / kTileX;
     I.pc = is_fourier(pc) ? SYLV_PC_FOURIER : pc;   // the kernels tell the two apart by fsc64
-    if (pc == SYLV_PC_FOURIER_DIAG) {
+    if (pc == SYLV_PC_FOURIER_DIAG || pc == SYLV_PC_FOURIER_BLOCK) {
         I.fsc64 = reinterpret_cast<const double *>(base + P.fsc64);
         I.fsc32 = reinterpret_cast<const float *>(base + P.fsc32);
     }
@@ -293,14 +295,14 @@ int prepare_operator(const sylv_problem &p, const ProbLayout &P, char *base, int
                          reinterpret_cast<float *>(base + P.P32),
                          reinterpret_cast<unsigned short *>(base + P.P16), exact, p.k, s));
     if (is_fourier(pc)) {
-        const bool diag = pc == SYLV_PC_FOURIER_DIAG;
+        const int scale = pc == SYLV_PC_FOURIER_DIAG ? 1 : pc == SYLV_PC_FOURIER_BLOCK ? 2 : 0;
         HIP_TRY(launch_fp_setup(p.W, p.A, p.f, p.k, (int)p.nx, (int)p.ny,
                                 p.boundary == SYLV_BC_FACE ? 1 : 0, coef,
                                 reinterpret_cast<double *>(base + P.fpart),
                                 reinterpret_cast<double *>(base + P.fsym),
-                                reinterpret_cast<const double *>(base + P.M64),
-                                diag ? reinterpret_cast<double *>(base + P.fsc64) : nullptr,
-                                diag ? reinterpret_cast<float *>(base + P.fsc32) : nullptr, s));
+                                reinterpret_cast<const double *>(base + P.M64), scale,
+                                scale ? reinterpret_cast<double *>(base + P.fsc64) : nullptr,
+                                scale ? reinterpret_cast<float *>(base + P.fsc32) : nullptr, s));
     }
     return SYLV_OK;
 }
@@ -322,7 +324,7 @@ int check_opts(const sylv_pcg_opts *o) {
     if (!(o->tol > 0.0) || !(o->tol < 1.0)) { set_err("tol must be in (0, 1)"); return SYLV_E_INVALID; }
     if (o->max_iter < 1) { set_err("max_iter must be >= 1"); return SYLV_E_INVALID; }
     if (o->precision != SYLV_PREC_F64 && o->precision != SYLV_PREC_MIXED) { set_err("bad precision"); return SYLV_E_INVALID; }
-    if (o->precond < SYLV_PC_NONE || o->precond > SYLV_PC_FOURIER_DIAG) { set_err("bad precond"); return SYLV_E_INVALID; }
+    if (o->precond < SYLV_PC_NONE || o->precond > SYLV_PC_FOURIER_BLOCK) { set_err("bad precond"); return SYLV_E_INVALID; }
     if (o->inner_tol < 0.0 || o->inner_tol >= 1.0) { set_err("inner_tol must be in [0, 1)"); return SYLV_E_INVALID; }
     if (o->refine_max < 0 || o->check_every < 0) { set_err("negative refine_max/check_every"); return SYLV_E_INVALID; }
     if (o->stop_ref != SYLV_STOP_R0 && o->stop_ref != SYLV_STOP_B) { set_err("bad stop_ref"); return SYLV_E_INVALID; }
@@ -590,6 +592,14 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
                 set_err("problem %d: %s", g, why);
                 return SYLV_E_INVALID;
             }
+            if (opts->precond == SYLV_PC_FOURIER_BLOCK &&
+                !fp_rows_per_block_blk((int)probs[g].nx, (int)probs[g].ny, k, dt)) {
+                set_err("problem %d: the block-scaled Fourier preconditioner's row passes hold "
+                        "every component of two grid rows and the stage table in LDS: k * nx = "
+                        "%d does not fit (%s)", g, k * (int)probs[g].nx,
+                        dt == SYLV_F64 ? "float64" : "float32");
+                return SYLV_E_INVALID;
+            }
         }
     }
     make_layout(probs, nprob, nrhs, true, L, opts->precond);
@@ -653,13 +663,16 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
                 I.fsym = reinterpret_cast<const double *>(base + L.prob[g].fsym);
                 I.lognx = __builtin_ctz((unsigned)I.nx);
                 I.logny = __builtin_ctz((unsigned)I.ny);
-                I.frb = fp_rows_per_block(I.nx, I.ny, mixed ? SYLV_F32 : SYLV_F64);
+                const bool blk = pc == SYLV_PC_FOURIER_BLOCK;
+                I.frb = blk ? fp_rows_per_block_blk(I.nx, I.ny, k, mixed ? SYLV_F32 : SYLV_F64)
+                            : fp_rows_per_block(I.nx, I.ny, mixed ? SYLV_F32 : SYLV_F64);
                 I.nfft = I.nx / 2;
-                nfa = k * (I.ny / I.frb);
+                nfa = blk ? I.ny / I.frb : k * (I.ny / I.frb);
                 I.nrr = mixed ? nfa : I.nchunks;   // the producer of ||r||^2 (see fourier_apply)
                 nfb = I.nfft;
                 const int dt = mixed ? SYLV_F32 : SYLV_F64;
-                fp_lds_rows = std::max(fp_lds_rows, fp_lds_bytes(0, I.nx, I.frb, dt));
+                fp_lds_rows = std::max(fp_lds_rows,
+                                       fp_lds_bytes(0, I.nx, blk ? k * I.frb : I.frb, dt));
                 fp_lds_cols = std::max(fp_lds_cols, fp_lds_bytes(1, I.ny, k, dt));
                 fp_cols_gtw |= fp_cols_global_twiddles(I.ny, k, dt) ? 1 : 0;
                 fp_rmask_x |= fp_radix_bit(I.lognx);
@@ -694,6 +707,7 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
     set.any_pre = any_pre;
     set.fourier = fourier;
     set.fp_scaled = opts->precond == SYLV_PC_FOURIER_DIAG ? 1 : 0;
+    set.fp_block = opts->precond == SYLV_PC_FOURIER_BLOCK ? 1 : 0;
     set.fprefa = set.cprefix + (ninst + 1);
     set.fprefb = set.fprefa + (ninst + 1);
     set.total_fa = fpa[ninst];
@@ -1597,7 +1611,7 @@ size_t sylv_workspace_bytes(const sylv_problem *probs, int32_t nprob, int32_t nr
 int sylv_prepare(const sylv_problem *prob, int32_t precond, void *ws, size_t ws_bytes,
                  void *stream) {
     if (!check_problem(prob, 0)) return SYLV_E_INVALID;
-    if (precond < SYLV_PC_NONE || precond > SYLV_PC_FOURIER_DIAG) { set_err("bad precond"); return SYLV_E_INVALID; }
+    if (precond < SYLV_PC_NONE || precond > SYLV_PC_FOURIER_BLOCK) { set_err("bad precond"); return SYLV_E_INVALID; }
     if (is_fourier(precond) && !fp_grid(*prob)) {
         set_err("the Fourier preconditioner needs grid sides that are powers of two in [4, 4096]");
         return SYLV_E_INVALID;
@@ -1648,10 +1662,17 @@ int sylv_precond(const sylv_problem *prob, int32_t dtype, int32_t precond, const
                  void *stream) {
     if (!check_problem(prob, 0)) return SYLV_E_INVALID;
     if (dtype != SYLV_F64 && dtype != SYLV_F32) { set_err("bad dtype"); return SYLV_E_INVALID; }
-    if (precond < SYLV_PC_NONE || precond > SYLV_PC_FOURIER_DIAG) { set_err("bad precond"); return SYLV_E_INVALID; }
+    if (precond < SYLV_PC_NONE || precond > SYLV_PC_FOURIER_BLOCK) { set_err("bad precond"); return SYLV_E_INVALID; }
     if (is_fourier(precond)) {
         char why[200];
         if (!fp_supported((int)prob->ny, (int)prob->nx, prob->k, dtype, why, sizeof(why))) { set_err("%s", why); return SYLV_E_INVALID; }
+        if (precond == SYLV_PC_FOURIER_BLOCK &&
+            !fp_rows_per_block_blk((int)prob->nx, (int)prob->ny, prob->k, dtype)) {
+            set_err("the block-scaled Fourier preconditioner's row passes hold every component of "
+                    "two grid rows and the stage table in LDS: k * nx = %d does not fit (%s)",
+                    prob->k * (int)prob->nx, dtype == SYLV_F64 ? "float64" : "float32");
+            return SYLV_E_INVALID;
+        }
     }
     if (!R || !Z || nrhs < 1) { set_err("null R/Z or nrhs < 1"); return SYLV_E_INVALID; }
     Layout L;
@@ -1673,11 +1694,14 @@ int sylv_precond(const sylv_problem *prob, int32_t dtype, int32_t precond, const
         I.fsym = reinterpret_cast<const double *>(base + L.prob[0].fsym);
         I.lognx = __builtin_ctz((unsigned)I.nx);
         I.logny = __builtin_ctz((unsigned)I.ny);
-        I.frb = fp_rows_per_block(I.nx, I.ny, dtype);
+        const int k = prob->k;
+        const bool blk = precond == SYLV_PC_FOURIER_BLOCK;
+        I.frb = blk ? fp_rows_per_block_blk(I.nx, I.ny, k, dtype)
+                    : fp_rows_per_block(I.nx, I.ny, dtype);
         I.nfft = I.nx / 2;
         I.partial = nullptr;
-        const int k = prob->k;
-        int pre[kPrefixArrays * 2] = {0, 0, 0, 0, 0, 0, 0, k * (I.ny / I.frb), 0, I.nfft};
+        int pre[kPrefixArrays * 2] = {0, 0, 0, 0, 0, 0, 0, blk ? I.ny / I.frb : k * (I.ny / I.frb),
+                                      0, I.nfft};
         HIP_TRY(launch_upload(base + L.table, &I, sizeof(Inst), s));
         HIP_TRY(launch_upload(base + L.tprefix, pre, sizeof(pre), s));
         InstSet set;
@@ -1693,7 +1717,8 @@ int sylv_precond(const sylv_problem *prob, int32_t dtype, int32_t precond, const
         set.total_fb = pre[9];
         set.fourier = 1;
         set.fp_scaled = precond == SYLV_PC_FOURIER_DIAG ? 1 : 0;
-        set.fp_lds_rows = fp_lds_bytes(0, I.nx, I.frb, dtype);
+        set.fp_block = blk ? 1 : 0;
+        set.fp_lds_rows = fp_lds_bytes(0, I.nx, blk ? k * I.frb : I.frb, dtype);
         set.fp_lds_cols = fp_lds_bytes(1, I.ny, k, dtype);
         set.fp_cols_gtw = fp_cols_global_twiddles(I.ny, k, dtype) ? 1 : 0;
         set.fp_rmask_x = fp_radix_bit(I.lognx);

@@ -152,10 +152,94 @@ __global__ __launch_bounds__(kBlock) void k_fp_scale(const double *__restrict__ 
     sc32[e] = (float)v;
 }
 
+// Block scale of SYLV_PC_FOURIER_BLOCK: thread p of the grid forms pixel p's k x k blocks of G,
+// Bp = diag(dq) + M_p, and of Q + I (x) Mbar, B0 = diag(dq) + Mbar (dq_j the prior's diagonal as
+// in k_fp_scale), their Cholesky factors Lp and L0, and writes T = L0 Lp^-1 (lower triangular,
+// packed at tidx(a, b)) in float64 and float32.
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_fp_tscale(const double *__restrict__ M64,
+                                                      const double *__restrict__ fsym, int nx,
+                                                      int ny, int face, double *__restrict__ sc64,
+                                                      float *__restrict__ sc32) {
+    const int n_pix = nx * ny;
+    const int p = blockIdx.x * kBlock + threadIdx.x;
+    if (p >= n_pix) return;
+    const int y = p / nx, x = p - y * nx;
+    const double d = face ? (double)((x > 0) + (x < nx - 1) + (y > 0) + (y < ny - 1)) : 4.0;
+    double lp[K][K], l0[K][K];
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+            const double m = M64[(size_t)pidx<K>(a, b) * n_pix + p];
+            const double mb = fsym[a * kMaxK + b];
+            double dq = 0.0;
+            if (a == b) {
+                const double t = fsym[kMaxK * kMaxK + a] + d;
+                dq = fsym[kMaxK * kMaxK + kMaxK + a] * (t * t + d);
+            }
+            lp[a][b] = m + dq;
+            l0[a][b] = mb + dq;
+        }
+    }
+    // Cholesky factors in place (lower triangles)
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+#pragma unroll
+        for (int m = 0; m < j; ++m) {
+            lp[j][j] -= lp[j][m] * lp[j][m];
+            l0[j][j] -= l0[j][m] * l0[j][m];
+        }
+        lp[j][j] = sqrt(lp[j][j]);
+        l0[j][j] = sqrt(l0[j][j]);
+#pragma unroll
+        for (int i = j + 1; i < K; ++i) {
+#pragma unroll
+            for (int m = 0; m < j; ++m) {
+                lp[i][j] -= lp[i][m] * lp[j][m];
+                l0[i][j] -= l0[i][m] * l0[j][m];
+            }
+            lp[i][j] /= lp[j][j];
+            l0[i][j] /= l0[j][j];
+        }
+    }
+    // Lp^-1 by forward substitution, column by column (lower triangle)
+    double li[K][K];
+#pragma unroll
+    for (int b = 0; b < K; ++b) {
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            if (a < b) continue;
+            double v = a == b ? 1.0 : 0.0;
+#pragma unroll
+            for (int m = b; m < a; ++m) v -= lp[a][m] * li[m][b];
+            li[a][b] = v / lp[a][a];
+        }
+    }
+    // T = L0 Lp^-1
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+            double v = 0.0;
+#pragma unroll
+            for (int m = b; m <= a; ++m) v += l0[a][m] * li[m][b];
+            const size_t o = (size_t)tidx(a, b) * n_pix + p;
+            sc64[o] = v;
+            sc32[o] = (float)v;
+        }
+    }
+}
+
 }  // namespace
 
 int fp_rows_per_block(int nx, int ny, int dtype) {
     return dtype == SYLV_F64 ? rows_per_block<double>(nx, ny) : rows_per_block<float>(nx, ny);
+}
+
+int fp_rows_per_block_blk(int nx, int ny, int k, int dtype) {
+    return dtype == SYLV_F64 ? rows_per_block_blk<double>(nx, ny, k)
+                             : rows_per_block_blk<float>(nx, ny, k);
 }
 
 bool fp_supported(int ny, int nx, int k, int dtype, char *why, size_t why_len) {
@@ -187,7 +271,8 @@ size_t fp_table_bytes(int nx, int ny) { return sizeof(double) * fp_tabs(nx, ny).
 
 hipError_t launch_fp_setup(const double *W, const double *A, int f, int k, int nx, int ny,
                            int face, const double *coef, double *part, double *fsym,
-                           const double *M64, double *sc64, float *sc32, hipStream_t s) {
+                           const double *M64, int scale, double *sc64, float *sc32,
+                           hipStream_t s) {
     const int n_pix = nx * ny;
     const int nblk = (int)blocks_for(n_pix, kWChunk);
     hipLaunchKernelGGL(k_wmean_part, dim3(nblk), dim3(kBlock), 0, s, W, f, n_pix, part);
@@ -199,7 +284,14 @@ hipError_t launch_fp_setup(const double *W, const double *A, int f, int k, int n
     const int nt = nx + ny + (nx - 1) + (ny - 1) + (face ? nx + ny : 0);
     hipLaunchKernelGGL(k_fp_tables, dim3((nt + kBlock - 1) / kBlock), dim3(kBlock), 0, s, nx, ny,
                        face, fsym);
-    if ((e = hipGetLastError()) != hipSuccess || !sc64) return e;
+    if ((e = hipGetLastError()) != hipSuccess || !scale) return e;
+    if (scale == 2)
+        return dispatch_k(k, [&](auto tag) {
+            constexpr int K = decltype(tag)::value;
+            hipLaunchKernelGGL((k_fp_tscale<K>), dim3((n_pix + kBlock - 1) / kBlock), dim3(kBlock),
+                               0, s, M64, fsym, nx, ny, face, sc64, sc32);
+            return hipGetLastError();
+        });
     const int ns = k * n_pix;
     hipLaunchKernelGGL(k_fp_scale, dim3((ns + kBlock - 1) / kBlock), dim3(kBlock), 0, s, M64, fsym,
                        k, nx, ny, face, sc64, sc32);

@@ -871,6 +871,232 @@ __global__ __launch_bounds__(kFT) void k_fp_rows_inv(const Inst *__restrict__ ta
     fft_run<T, 1, FR>(buf, tw, ln, h, false, NoLoad<T>(), true, stg);
 }
 
+// Block-scaled variant (SYLV_PC_FOURIER_BLOCK): z = T^T M0^-1 T r with T_p = L0_p Lp^-1 lower
+// triangular per pixel (Lp Lp^T = G's k x k block of the pixel, L0_p L0_p^T that block of
+// M0 = Q + I (x) Mbar), stored packed at tidx(a, b), a >= b, one plane per entry.  Its row passes
+// transform all K components of rb grid rows in one workgroup (K rb / 2 complex rows: row pair qq
+// of component j is complex row j rb / 2 + qq), so that T r before the forward transforms and
+// T^T zhat after the inverse ones see every component of a pixel.  They stage the pixel products
+// through LDS (the transforms start and end there); the column pass is the same as above.
+__host__ __device__ constexpr int tidx(int a, int b) { return a * (a + 1) / 2 + b; }
+// Inverse of cos_src: the transform index of sample x.
+__device__ __forceinline__ int cos_dst(int x, int n) { return (x & 1) ? n - 1 - (x >> 1) : x >> 1; }
+
+// Pass A of the block-scaled variant: the update and ||r||^2 partials as k_fp_rows_fwd (upd), then
+// u = T_p r_p at every pixel of the band, the forward row transforms of all components, and the
+// half spectrum (or the cosine coefficients) of every component stored as k_fp_rows_fwd does.
+template <typename T, int K, int CLS, bool DCT>
+__global__ __launch_bounds__(kFT) void k_fp_rows_fwd_blk(const Inst *__restrict__ tab,
+                                                         const int *__restrict__ fpre, int ninst,
+                                                         int nb, int inner,
+                                                         const T *__restrict__ rin, int use_in,
+                                                         int upd, int it) {
+    extern __shared__ __align__(16) unsigned char fp_lds[];
+    const int L = xcd_remap(blockIdx.x, nb);
+    const int ii = find_inst(fpre, ninst, L);
+    const Inst &I = tab[ii];
+    if (fft_class(I.lognx) != CLS) return;                         // another launch's instance
+    constexpr int FR = cls_fr(CLS), LN = cls_ln(CLS);
+    const int blk = L - fpre[ii];
+    T alpha = (T)0;
+    if (inner >= 0) {                                              // inner < 0: stand-alone
+        DevState *st = inner ? I.st_in : I.st;
+        if (st->done) return;
+        if (upd == 2) {
+            const int pend = st->pend;
+            if (pend >= 0) {   // this iteration's apply stopped the run
+                if (blk == 0 && threadIdx.x == 0) {
+                    st->status = pend;
+                    st->done = 1;
+                    st->total_iter += it;
+                }
+                return;
+            }
+            const double pq = fp_consume(I.partial, I.nred, SLOT_PQ,
+                                         I.pre ? 1 : (sizeof(T) == 4 ? I.ntiles32 : I.ntiles));
+            int status = -1;
+            if (!finite_d(pq)) status = SYLV_NONFINITE;
+            else if (!(pq > 0.0)) status = SYLV_BREAKDOWN;
+            const double alpha_d = st->rho[it & 1] / pq;
+            if (blk == 0 && threadIdx.x == 0) {
+                if (status >= 0) {
+                    st->status = status;
+                    st->done = 1;
+                    st->total_iter += it;
+                } else {
+                    st->alpha[it & 1] = alpha_d;
+                }
+            }
+            if (status >= 0) return;
+            alpha = (T)alpha_d;
+        }
+    }
+    const int ln = LN ? LN : I.lognx, nx = 1 << ln;
+    const int ny = I.ny, rb = I.frb, nc = nx / 2 + 1, hb = rb / 2;
+    const int lrb = __builtin_ctz((unsigned)rb), lh = lrb - 1, y0 = blk << lrb;
+    Cx<T> *tw = reinterpret_cast<Cx<T> *>(fp_lds);
+    Cx<T> *buf = tw + nx;
+    const FpTabs tb = fp_tabs(nx, ny);
+    load_table<T>(tw, stage_table<T>(I.fsym, tb, true), nx);
+    const uint32_t np = (uint32_t)I.n_pix;
+    const size_t pl = (size_t)I.n_pix;
+    GAS T *r = use_in ? gp(const_cast<T *>(rin)) : Sel<T>::r(I);
+    const GAS T *qv = Sel<T>::q(I);
+    const GAS T *tp = gp(fscale<T>(I));
+    double rr = 0.0;
+    for (int e = threadIdx.x; e < (hb << ln); e += kFT) {
+        const int qq = e >> ln, x = e & (nx - 1);
+        T u[2][K];
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            const uint32_t o = (uint32_t)(y0 + 2 * qq + w) * (uint32_t)nx + (uint32_t)x;
+            T v[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) v[j] = bld(r + j * pl, np, o);
+            if (upd == 2) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    v[j] -= alpha * bld(qv + j * pl, np, o);
+                    bst(r + j * pl, np, o, v[j]);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < K; ++j) rr += (double)v[j] * (double)v[j];
+#pragma unroll
+            for (int a = 0; a < K; ++a) {
+                T sacc = (T)0;
+#pragma unroll
+                for (int b = 0; b <= a; ++b) sacc += bld(tp + tidx(a, b) * pl, np, o) * v[b];
+                u[w][a] = sacc;
+            }
+        }
+        const int i = DCT ? cos_dst(x, nx) : x;
+#pragma unroll
+        for (int a = 0; a < K; ++a) buf[lpad(((a * hb + qq) << ln) + i)] = {u[0][a], u[1][a]};
+    }
+    __syncthreads();
+    fft_run<T, 0, FR>(buf, tw, ln, K * hb, false, NoLoad<T>(), false, NoStore<T>());
+    if (upd) {   // the ||r||^2 partial of this workgroup's rows (all components)
+        const double tot = fp_block_sum(rr);
+        if (threadIdx.x == 0) gp(I.partial)[(size_t)SLOT_RR * I.nred + blk] = tot;
+    }
+    if (DCT) {
+        const Cx<T> *ct = cos_table<T>(I.fsym, tb, true);
+        const T hf = (T)0.5;
+        const int per = nx << lh;   // entries of one component
+        for (int e = threadIdx.x; e < K * per; e += kFT) {
+            const int j = e >> (ln + lh), e2 = e & (per - 1);
+            const int u = e2 >> lh, q = j * hb + (e2 & (hb - 1));
+            GAS T *Sr = spectrum<T>(I) + (size_t)j * nx * ny;
+            const Cx<T> U = buf[lpad((q << ln) + u)];
+            const Cx<T> M = buf[lpad((q << ln) + ((nx - u) & (nx - 1)))];
+            const Cx<T> va = {hf * (U.x + M.x), hf * (U.y - M.y)};
+            const Cx<T> vb = {hf * (U.y + M.y), hf * (M.x - U.x)};
+            const Cx<T> w = ct[u];
+            cstore(Sr, ((size_t)u * ny + y0) / 2 + (e2 & (hb - 1)),
+                   Cx<T>{w.x * va.x - w.y * va.y, w.x * vb.x - w.y * vb.y});
+        }
+        return;
+    }
+    const T half = (T)0.5;
+    const int per = rb * nc;
+    for (int e = threadIdx.x; e < K * per; e += kFT) {
+        const int j = e / per, e2 = e - j * per;
+        const int c = e2 >> lrb, yy = e2 & (rb - 1), q = j * hb + (yy >> 1);
+        GAS T *S = spectrum<T>(I) + (size_t)2 * j * nc * ny;
+        const Cx<T> U = buf[lpad((q << ln) + c)];
+        const Cx<T> V = buf[lpad((q << ln) + ((nx - c) & (nx - 1)))];   // U[-c]
+        const Cx<T> out = (yy & 1) ? Cx<T>{half * (U.y + V.y), half * (V.x - U.x)}
+                                   : Cx<T>{half * (U.x + V.x), half * (U.y - V.y)};
+        cstore(S, (size_t)c * ny + y0 + yy, out);
+    }
+}
+
+// Pass C of the block-scaled variant: the rows of every component rebuilt from the half spectrum
+// (or the cosine coefficients) as k_fp_rows_inv does, the inverse row transforms, then
+// z_p = T_p^T zhat_p / (nx ny) at every pixel of the band.
+template <typename T, int K, int CLS, bool DCT>
+__global__ __launch_bounds__(kFT) void k_fp_rows_inv_blk(const Inst *__restrict__ tab,
+                                                         const int *__restrict__ fpre, int ninst,
+                                                         int nb, int inner, T *__restrict__ zout,
+                                                         int use_out) {
+    extern __shared__ __align__(16) unsigned char fp_lds[];
+    const int L = xcd_remap(blockIdx.x, nb);
+    const int ii = find_inst(fpre, ninst, L);
+    const Inst &I = tab[ii];
+    if (inner >= 0 && (inner ? I.st_in : I.st)->done) return;   // inner < 0: stand-alone
+    if (fft_class(I.lognx) != CLS) return;                         // another launch's instance
+    constexpr int FR = cls_fr(CLS), LN = cls_ln(CLS);
+    const int blk = L - fpre[ii];
+    const int ln = LN ? LN : I.lognx, nx = 1 << ln;
+    const int ny = I.ny, rb = I.frb, nc = nx / 2 + 1, hb = rb / 2;
+    const int lrb = __builtin_ctz((unsigned)rb), lh = lrb - 1, y0 = blk << lrb;
+    Cx<T> *tw = reinterpret_cast<Cx<T> *>(fp_lds);
+    Cx<T> *buf = tw + nx;
+    const FpTabs tb = fp_tabs(nx, ny);
+    load_table<T>(tw, stage_table<T>(I.fsym, tb, true), nx);
+    if (DCT) {
+        const Cx<T> *ct = cos_table<T>(I.fsym, tb, true);
+        const int per = (nx / 2 + 1) << lh;
+        for (int e = threadIdx.x; e < K * per; e += kFT) {
+            const int j = e / per, e2 = e - j * per;
+            const int u = e2 >> lh, qq = e2 & (hb - 1), q = j * hb + qq;
+            const int um = (nx - u) & (nx - 1);
+            const GAS T *Sr = spectrum<T>(I) + (size_t)j * nx * ny;
+            const Cx<T> zu = cload(Sr, ((size_t)u * ny + y0) / 2 + qq);
+            const Cx<T> zm = u == 0 ? Cx<T>{(T)0, (T)0} : cload(Sr, ((size_t)um * ny + y0) / 2 + qq);
+            const Cx<T> t = ct[u];
+            const Cx<T> a0 = {t.x * zu.x - t.y * zm.x, -t.y * zu.x - t.x * zm.x};
+            const Cx<T> a1 = {t.x * zu.y - t.y * zm.y, -t.y * zu.y - t.x * zm.y};
+            buf[lpad((q << ln) + u)] = {a0.x - a1.y, a0.y + a1.x};
+            if (u != 0 && um != u) {
+                const Cx<T> tm = ct[um];
+                const Cx<T> b0 = {tm.x * zm.x - tm.y * zu.x, -tm.y * zm.x - tm.x * zu.x};
+                const Cx<T> b1 = {tm.x * zm.y - tm.y * zu.y, -tm.y * zm.y - tm.x * zu.y};
+                buf[lpad((q << ln) + um)] = {b0.x - b1.y, b0.y + b1.x};
+            }
+        }
+    } else {
+        // unit u = rows 2qq, 2qq + 1 of column c of component j (one 4-vector)
+        const int per = nc << lh;
+        for (int e = threadIdx.x; e < K * per; e += kFT) {
+            const int j = e / per, e2 = e - j * per;
+            const int c = e2 >> lh, qq = e2 & (hb - 1), q = j * hb + qq;
+            const GAS T *S = spectrum<T>(I) + (size_t)2 * j * nc * ny;
+            T a[4];
+            ld4(S + 2 * ((size_t)c * ny + y0 + 2 * qq), a);
+            buf[lpad((q << ln) + c)] = {a[0] - a[3], a[1] + a[2]};
+            if (c > 0 && 2 * c < nx) buf[lpad((q << ln) + nx - c)] = {a[0] + a[3], a[2] - a[1]};
+        }
+    }
+    __syncthreads();
+    fft_run<T, 1, FR>(buf, tw, ln, K * hb, false, NoLoad<T>(), false, NoStore<T>());
+    const T scale = (T)(1.0 / ((double)nx * (double)ny));
+    const uint32_t np = (uint32_t)I.n_pix;
+    const size_t pl = (size_t)I.n_pix;
+    GAS T *z = use_out ? gp(zout) : gp(Sel<T>::z(I));
+    const GAS T *tp = gp(fscale<T>(I));
+    for (int e = threadIdx.x; e < (hb << ln); e += kFT) {
+        const int qq = e >> ln, x = e & (nx - 1);
+        const int i = DCT ? cos_dst(x, nx) : x;
+        Cx<T> zh[K];
+#pragma unroll
+        for (int a = 0; a < K; ++a) zh[a] = buf[lpad(((a * hb + qq) << ln) + i)];
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            const uint32_t o = (uint32_t)(y0 + 2 * qq + w) * (uint32_t)nx + (uint32_t)x;
+#pragma unroll
+            for (int b = 0; b < K; ++b) {   // z_b = sum over a >= b of T[a][b] zhat_a
+                T sacc = (T)0;
+#pragma unroll
+                for (int a = b; a < K; ++a)
+                    sacc += bld(tp + tidx(a, b) * pl, np, o) * (w ? zh[a].y : zh[a].x);
+                bst(z + b * pl, np, o, sacc * scale);
+            }
+        }
+    }
+}
+
 // LDS bytes of a row pass over rb real rows of length nx (rb / 2 complex rows) and of the column
 // pass (k components of length ny), stage tables included.
 template <typename T>
@@ -884,6 +1110,17 @@ size_t cols_lds(int ny, int k, bool table = true) {
 
 // Static LDS of the passes (the column pass's reduction table) kept free beside the dynamic part.
 constexpr size_t kLdsMargin = 1024;
+
+// Grid rows per workgroup of the block-scaled row passes (all k components of each row): as
+// rows_per_block over k rb real rows; 0 when even two rows of every component do not fit.
+template <typename T>
+int rows_per_block_blk(int nx, int ny, int k) {
+    int rb = std::min(64 / (int)sizeof(Cx<T>), ny);
+    while (rb > 2 && (k * rb / 2 * nx > kFftCap || rows_lds<T>(nx, k * rb) > kMaxLds - kLdsMargin))
+        rb /= 2;
+    if (k * rb / 2 * nx > kFftCap || rows_lds<T>(nx, k * rb) > kMaxLds - kLdsMargin) return 0;
+    return rb;
+}
 
 template <typename T>
 int rows_per_block(int nx, int ny) {
@@ -925,7 +1162,12 @@ hipError_t fp_apply_impl(const InstSet &set, int k, int inner, const void *rin, 
         constexpr int K = decltype(tag)::value;
         hipError_t e = for_each_class(set.fp_rmask_x, [&](auto fr) -> hipError_t {
             constexpr int FR = decltype(fr)::value;   // the class
-            if (set.fp_scaled)
+            if (set.fp_block)
+                hipLaunchKernelGGL((k_fp_rows_fwd_blk<T, K, FR, DCT>), dim3(set.total_fa),
+                                   dim3(kFT), lr, s, set.table, set.fprefa, set.ninst,
+                                   set.total_fa, mixed, reinterpret_cast<const T *>(rin),
+                                   rin ? 1 : 0, inner >= 0 ? upd : 0, it);
+            else if (set.fp_scaled)
                 hipLaunchKernelGGL((k_fp_rows_fwd<T, FR, DCT, true>), dim3(set.total_fa),
                                    dim3(kFT), lr, s, set.table, set.fprefa, set.ninst,
                                    set.total_fa, mixed, reinterpret_cast<const T *>(rin),
@@ -958,7 +1200,12 @@ hipError_t fp_apply_impl(const InstSet &set, int k, int inner, const void *rin, 
         if (e != hipSuccess) return e;
         return for_each_class(set.fp_rmask_x, [&](auto fr) -> hipError_t {
             constexpr int FR = decltype(fr)::value;   // the class
-            if (set.fp_scaled)
+            if (set.fp_block)
+                hipLaunchKernelGGL((k_fp_rows_inv_blk<T, K, FR, DCT>), dim3(set.total_fa),
+                                   dim3(kFT), lr, s, set.table, set.fprefa, set.ninst,
+                                   set.total_fa, mixed, reinterpret_cast<T *>(zout),
+                                   zout ? 1 : 0);
+            else if (set.fp_scaled)
                 hipLaunchKernelGGL((k_fp_rows_inv<T, FR, DCT, true>), dim3(set.total_fa),
                                    dim3(kFT), lr, s, set.table, set.fprefa, set.ninst,
                                    set.total_fa, mixed, reinterpret_cast<T *>(zout),

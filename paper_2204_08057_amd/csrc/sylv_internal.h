@@ -109,7 +109,8 @@ struct Inst {
     const double *fsym;  // Fourier region: Mbar [kMaxK][kMaxK], kappa_j^2 [kMaxK], tau_j
                          // [kMaxK], then eigenvalue and FFT stage tables
     const double *fsc64; // SYLV_PC_FOURIER_DIAG: 1 / s [k][n_pix] (s^2 = diag(G) / diag(Q + I
-    const float *fsc32;  // (x) Mbar)) in float64 and float32; null for the plain preconditioner
+    const float *fsc32;  // (x) Mbar)); SYLV_PC_FOURIER_BLOCK: T [k(k+1)/2][n_pix] (packed lower
+                         // triangle); float64 and float32; null for the plain preconditioner
     int32_t lognx, logny;
     int32_t frb;         // grid rows per workgroup of the row passes
     int32_t nfft;        // column workgroups = nx/2 (partials of <r, z>)
@@ -142,6 +143,7 @@ struct InstSet {
     int fp_cols_gtw;      // the column pass reads its twiddles from global memory
     int fp_rmask_x, fp_rmask_y;   // final FFT radices present (fp_radix_bit) along x and y
     int fp_scaled;        // SYLV_PC_FOURIER_DIAG: the row passes apply the diagonal scale
+    int fp_block;         // SYLV_PC_FOURIER_BLOCK: the block-scaled row passes (all components)
 };
 
 inline int packed_size(int k) { return k * (k + 1) / 2; }
@@ -218,11 +220,15 @@ size_t fp_setup_partials(int n_pix, int f);
 // eigenvalues of both grid sides and the FFT stage tables.
 size_t fp_table_bytes(int nx, int ny);
 // The Fourier region of a problem, fsym (part: fp_setup_partials doubles of scratch); face grids
-// (face = 1) take the cosine basis.  sc64 / sc32 non-null (SYLV_PC_FOURIER_DIAG): also the
-// diagonal scale 1 / s [k][n_pix] from the mixing blocks M64 (packed, as k_setup writes them).
+// (face = 1) take the cosine basis.  scale = 1 (SYLV_PC_FOURIER_DIAG): also the diagonal scale
+// 1 / s [k][n_pix] into sc64 / sc32; scale = 2 (SYLV_PC_FOURIER_BLOCK): the block scale T
+// [k(k+1)/2][n_pix]; both from the mixing blocks M64 (packed, as k_setup writes them).
 hipError_t launch_fp_setup(const double *W, const double *A, int f, int k, int nx, int ny,
                            int face, const double *coef, double *part, double *fsym,
-                           const double *M64, double *sc64, float *sc32, hipStream_t s);
+                           const double *M64, int scale, double *sc64, float *sc32,
+                           hipStream_t s);
+// Grid rows per workgroup of the block-scaled row passes (0: k nx too large for them).
+int fp_rows_per_block_blk(int nx, int ny, int k, int dtype);
 // z = Fourier preconditioner of r for every instance of the set, in float32 (f32) or float64;
 // inner = 1: the float32 inner runs of the mixed path, 0: the float64 runs, -1: the stand-alone
 // preconditioner (one instance without run state: r read from rin, z written to zout).  upd

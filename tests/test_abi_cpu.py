@@ -284,3 +284,22 @@ def test_fourier_preconditioner_refusals_before_any_device_call():
     n0 = L.sylv_workspace_bytes(ctypes.byref(p), 1, 2, ctypes.byref(plain))
     n1 = L.sylv_workspace_bytes(ctypes.byref(p), 1, 2, ctypes.byref(fourier))
     assert n1 - n0 >= 2 * 16 * 3 * 33 * 64
+
+
+def test_block_scaled_fourier_refuses_wide_rows_before_any_device_call():
+    """The block-scaled Fourier preconditioner's row passes hold every component of two grid
+    rows (k nx <= 8192); wider rows are refused, by the solve and the stand-alone application,
+    before any work is enqueued."""
+    L = sy.lib()
+    opts = bd._Opts(1e-8, 10, 0, 0.0, 0, bd.SYLV_PC_FOURIER_BLOCK, 0, 0)
+    p = fake_problem(16, 4096, k=3)
+    rc = L.sylv_pcg_solve(ctypes.byref(p), 1, 1, FAKE, None, FAKE, ctypes.byref(opts), FAKE,
+                          FAKE, 1 << 40, None)
+    assert rc == bd.SYLV_E_INVALID and b"k * nx" in L.sylv_last_error()
+    rc = L.sylv_precond(ctypes.byref(p), 1, bd.SYLV_PC_FOURIER_BLOCK, FAKE, FAKE * 2, 1, 1, FAKE,
+                        1 << 40, None)
+    assert rc == bd.SYLV_E_INVALID and b"k * nx" in L.sylv_last_error()
+    bad = bd._Opts(1e-8, 10, 0, 0.0, 0, bd.SYLV_PC_FOURIER_BLOCK + 1, 0, 0)
+    rc = L.sylv_pcg_solve(ctypes.byref(fake_problem(16, 16)), 1, 1, FAKE, None, FAKE,
+                          ctypes.byref(bad), FAKE, FAKE, 1 << 40, None)
+    assert rc == bd.SYLV_E_INVALID

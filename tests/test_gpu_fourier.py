@@ -362,3 +362,132 @@ def test_diag_het_1024_whole_solution_vs_oracle(precision, tol, bound):
     assert st[0]["status"] == 0, st
     say("  iterations", st[0]["iters"], "outer", st[0]["outer"])
     assert rel(host(X).reshape(p.k, p.n_pix), ref) <= bound
+
+
+# ---- block-scaled variant (SYLV_PC_FOURIER_BLOCK): z = T^T (Q + I (x) Mbar)^-1 T r ---------------
+
+BLOCK_SHAPES = [("periodic", s) for s in [(8, 16, 3, 5), (32, 64, 4, 9), (128, 32, 8, 16),
+                                          (2048, 16, 4, 9), (16, 1024, 8, 9), (8, 4096, 1, 3),
+                                          (4096, 4, 2, 3), (64, 64, 1, 3)]] + \
+               [("face", s) for s in [(8, 16, 3, 5), (64, 32, 4, 9), (1024, 8, 8, 9)]]
+
+
+@pytest.mark.parametrize("boundary,shape", BLOCK_SHAPES)
+def test_block_application_matches_oracle(boundary, shape):
+    ny, nx, k, f = shape
+    p = make_problem(ny, nx, k, f, seed=6000 + ny + nx, noise="hetero", mask_frac=0.1,
+                     boundary=boundary)
+    dp = sy.DeviceProblem.from_numpy(p)
+    R = random_maps(p, seed=6001, nrhs=2)
+    Minv = opcg.fourier_preconditioner(p, scaled="block")
+    ref = np.stack([Minv(R[i]) for i in range(2)])
+    say("block application", boundary, shape)
+    assert rel(host(sy.precond(dp, dev(R), kind=sy.SYLV_PC_FOURIER_BLOCK)), ref) <= 1e-12
+    assert rel(host(sy.precond(dp, dev(R, torch.float32), kind=sy.SYLV_PC_FOURIER_BLOCK)),
+               ref) <= 2e-5
+
+
+def test_block_refuses_rows_wider_than_its_pass():
+    p = make_problem(16, 4096, 3, 4, seed=6050, noise="hetero")
+    dp = sy.DeviceProblem.from_numpy(p)
+    with pytest.raises(Exception):
+        sy.precond(dp, dev(random_maps(p, seed=6051)), kind=sy.SYLV_PC_FOURIER_BLOCK)
+    # the plain preconditioner takes the same grid
+    assert host(sy.precond(dp, dev(random_maps(p, seed=6051)), kind=sy.SYLV_PC_FOURIER)).size
+
+
+@pytest.mark.parametrize("precision,tol,bound", [(sy.SYLV_PREC_F64, 1e-12, 1e-8),
+                                                 (sy.SYLV_PREC_MIXED, 1e-11, 1e-7)])
+@pytest.mark.parametrize("boundary,shape", [("periodic", (32, 64, 4, 9)),
+                                            ("periodic", (16, 16, 6, 7)),
+                                            ("face", (32, 64, 4, 9)), ("face", (64, 32, 2, 3))])
+def test_block_solve_matches_dense(boundary, shape, precision, tol, bound):
+    ny, nx, k, f = shape
+    p = make_problem(ny, nx, k, f, seed=6100 + ny * nx, noise="hetero", mask_frac=0.1,
+                     boundary=boundary)
+    dp = sy.DeviceProblem.from_numpy(p)
+    say("block solve", boundary, shape, precision)
+    X, st = sy.pcg_solve(dp, Y=dev(p.Y), opts=sy.SolveOptions(
+        tol=tol, precision=precision, precond=sy.SYLV_PC_FOURIER_BLOCK))
+    assert st[0]["status"] == 0, st
+    assert rel(host(X).reshape(p.k, p.n_pix), osv.solve_dense(p)) <= bound
+
+
+@pytest.mark.parametrize("boundary,shape", [("periodic", (64, 64, 3, 6)),
+                                            ("periodic", (128, 128, 3, 9)),
+                                            ("face", (128, 128, 3, 9))])
+def test_block_iteration_count_matches_oracle(boundary, shape):
+    ny, nx, k, f = shape
+    p = make_problem(ny, nx, k, f, seed=6200 + ny, noise="hetero", boundary=boundary)
+    ref = opcg.pcg(p, tol=1e-8, max_iter=2000, precond="fourier_block")
+    say("block iterations", boundary, shape, "oracle", ref["iters"])
+    dp = sy.DeviceProblem.from_numpy(p)
+    X, st = sy.pcg_solve(dp, Y=dev(p.Y), opts=sy.SolveOptions(
+        tol=1e-8, precond=sy.SYLV_PC_FOURIER_BLOCK))
+    assert st[0]["status"] == 0, st
+    say("  gpu", st[0]["iters"])
+    assert abs(st[0]["iters"] - ref["iters"]) <= 1
+
+
+def test_block_homoscedastic_grid_solves_in_one_iteration():
+    p = make_problem(64, 32, 3, 6, seed=6300, noise="homo")
+    dp = sy.DeviceProblem.from_numpy(p)
+    X, st = sy.pcg_solve(dp, Y=dev(p.Y), opts=sy.SolveOptions(
+        tol=1e-10, precond=sy.SYLV_PC_FOURIER_BLOCK))
+    assert st[0]["status"] == 0 and st[0]["iters"] <= 2, st
+    assert rel(host(X).reshape(p.k, p.n_pix), osv.solve_fft(p)) <= 1e-9
+
+
+def test_block_fixed_schedule_equals_adaptive_and_batch():
+    """Fixed and adaptive schedules give bitwise equal solutions; a batch of two uneven grids
+    with two right-hand sides each matches dense solves."""
+    p = make_problem(64, 64, 3, 6, seed=6400, noise="hetero", mask_frac=0.1)
+    dp = sy.DeviceProblem.from_numpy(p)
+    for precision in (sy.SYLV_PREC_F64, sy.SYLV_PREC_MIXED):
+        o = sy.SolveOptions(tol=1e-9, precision=precision, precond=sy.SYLV_PC_FOURIER_BLOCK)
+        Xa, sa = sy.pcg_solve(dp, Y=dev(p.Y), opts=o)
+        of = sy.SolveOptions(tol=1e-9, precision=precision, precond=sy.SYLV_PC_FOURIER_BLOCK,
+                             schedule=sy.SYLV_SCHED_FIXED, max_iter=sa[0]["iters"] + 5)
+        Xf, sf = sy.pcg_solve(dp, Y=dev(p.Y), opts=of)
+        say("block fixed", precision, sa[0]["iters"], sf[0]["iters"])
+        assert sa[0]["status"] == 0 and sf[0]["status"] == 0, (sa, sf)
+        assert torch.equal(Xa, Xf)
+    probs = [make_problem(32, 64, 3, 5, seed=6401, noise="hetero"),
+             make_problem(16, 16, 3, 5, seed=6402, noise="hetero", mask_frac=0.1)]
+    nrhs = 2
+    rng = np.random.default_rng(6403)
+    Bx = [rng.standard_normal((nrhs, q.k, q.n_pix)) for q in probs]
+    dps = [sy.DeviceProblem.from_numpy(q) for q in probs]
+    X, st = sy.pcg_solve(dps, Y=torch.cat([dev(q.Y.ravel()) for q in probs]),
+                         Bextra=torch.cat([dev(b.ravel()) for b in Bx]), nrhs=nrhs,
+                         opts=sy.SolveOptions(tol=1e-11, precision=sy.SYLV_PREC_MIXED,
+                                              precond=sy.SYLV_PC_FOURIER_BLOCK))
+    assert all(s["status"] == 0 for s in st), st
+    from oracle import operator as op
+    x = host(X)
+    off = 0
+    for g, q in enumerate(probs):
+        for r in range(nrhs):
+            xs = osv.solve_dense(q, b=op.rhs(q) + Bx[g][r])
+            assert rel(x[off:off + q.k * q.n_pix].reshape(q.k, q.n_pix), xs) <= 1e-7
+            off += q.k * q.n_pix
+
+
+@pytest.mark.parametrize("precision,tol,bound", [(sy.SYLV_PREC_F64, 1e-12, 1e-8),
+                                                 (sy.SYLV_PREC_MIXED, 1e-11, 1e-7)])
+def test_block_het_1024_whole_solution_vs_oracle(precision, tol, bound):
+    global _HET
+    try:
+        p, ref = _HET
+    except NameError:
+        p = workload("het_1024")[0]
+        say("oracle PCG het_1024 to 1e-13 (CPU)")
+        ref = opcg.pcg(p, tol=1e-13, max_iter=5000, precond="block")["x"]
+        _HET = (p, ref)
+    say("block het_1024", precision)
+    dp = sy.DeviceProblem.from_numpy(p)
+    X, st = sy.pcg_solve(dp, Y=dev(p.Y), opts=sy.SolveOptions(
+        tol=tol, precision=precision, precond=sy.SYLV_PC_FOURIER_BLOCK))
+    assert st[0]["status"] == 0, st
+    say("  iterations", st[0]["iters"], "outer", st[0]["outer"])
+    assert rel(host(X).reshape(p.k, p.n_pix), ref) <= bound
