@@ -881,6 +881,13 @@ __global__ __launch_bounds__(kFT) void k_fp_rows_inv(const Inst *__restrict__ ta
 __host__ __device__ constexpr int tidx(int a, int b) { return a * (a + 1) / 2 + b; }
 // Inverse of cos_src: the transform index of sample x.
 __device__ __forceinline__ int cos_dst(int x, int n) { return (x & 1) ? n - 1 - (x >> 1) : x >> 1; }
+// Pixel pairs a thread of the block-scaled row passes has in flight at once: as many as about
+// 96 (float32) or 48 (float64) loaded values allow, each pair holding 2 (K + K(K+1)/2) of them.
+template <typename T, int K>
+constexpr int blk_pairs() {
+    constexpr int per = 2 * (K + K * (K + 1) / 2), cap = sizeof(T) == 8 ? 48 : 96;
+    return per >= cap ? 1 : (cap / per > 4 ? 4 : cap / per);
+}
 
 // Pass A of the block-scaled variant: the update and ||r||^2 partials as k_fp_rows_fwd (upd), then
 // u = T_p r_p at every pixel of the band, the forward row transforms of all components, and the
@@ -944,35 +951,59 @@ __global__ __launch_bounds__(kFT) void k_fp_rows_fwd_blk(const Inst *__restrict_
     const GAS T *qv = Sel<T>::q(I);
     const GAS T *tp = gp(fscale<T>(I));
     double rr = 0.0;
-    for (int e = threadIdx.x; e < (hb << ln); e += kFT) {
-        const int qq = e >> ln, x = e & (nx - 1);
-        T u[2][K];
+    constexpr int NB = blk_pairs<T, K>(), KP = K * (K + 1) / 2;
+    const int items = hb << ln;
+    for (int e0 = threadIdx.x; e0 < items; e0 += NB * kFT) {
+        // every load of NB pixel pairs first, then the products
+        T v[NB][2][K], tt[NB][2][KP];
 #pragma unroll
-        for (int w = 0; w < 2; ++w) {
-            const uint32_t o = (uint32_t)(y0 + 2 * qq + w) * (uint32_t)nx + (uint32_t)x;
-            T v[K];
+        for (int g = 0; g < NB; ++g) {
+            const int e = e0 + g * kFT;
+            if (e < items) {
+                const int qq = e >> ln, x = e & (nx - 1);
 #pragma unroll
-            for (int j = 0; j < K; ++j) v[j] = bld(r + j * pl, np, o);
-            if (upd == 2) {
+                for (int w = 0; w < 2; ++w) {
+                    const uint32_t o = (uint32_t)(y0 + 2 * qq + w) * (uint32_t)nx + (uint32_t)x;
 #pragma unroll
-                for (int j = 0; j < K; ++j) {
-                    v[j] -= alpha * bld(qv + j * pl, np, o);
-                    bst(r + j * pl, np, o, v[j]);
+                    for (int j = 0; j < K; ++j) {
+                        v[g][w][j] = bld(r + j * pl, np, o);
+                        if (upd == 2) v[g][w][j] -= alpha * bld(qv + j * pl, np, o);
+                    }
+#pragma unroll
+                    for (int t = 0; t < KP; ++t) tt[g][w][t] = bld(tp + t * pl, np, o);
                 }
             }
+        }
 #pragma unroll
-            for (int j = 0; j < K; ++j) rr += (double)v[j] * (double)v[j];
+        for (int g = 0; g < NB; ++g) {
+            const int e = e0 + g * kFT;
+            if (e < items) {
+                const int qq = e >> ln, x = e & (nx - 1);
+                T u[2][K];
 #pragma unroll
-            for (int a = 0; a < K; ++a) {
-                T sacc = (T)0;
+                for (int w = 0; w < 2; ++w) {
+                    if (upd == 2) {
+                        const uint32_t o =
+                            (uint32_t)(y0 + 2 * qq + w) * (uint32_t)nx + (uint32_t)x;
 #pragma unroll
-                for (int b = 0; b <= a; ++b) sacc += bld(tp + tidx(a, b) * pl, np, o) * v[b];
-                u[w][a] = sacc;
+                        for (int j = 0; j < K; ++j) bst(r + j * pl, np, o, v[g][w][j]);
+                    }
+#pragma unroll
+                    for (int j = 0; j < K; ++j) rr += (double)v[g][w][j] * (double)v[g][w][j];
+#pragma unroll
+                    for (int a = 0; a < K; ++a) {
+                        T sacc = (T)0;
+#pragma unroll
+                        for (int b = 0; b <= a; ++b) sacc += tt[g][w][tidx(a, b)] * v[g][w][b];
+                        u[w][a] = sacc;
+                    }
+                }
+                const int i = DCT ? cos_dst(x, nx) : x;
+#pragma unroll
+                for (int a = 0; a < K; ++a)
+                    buf[lpad(((a * hb + qq) << ln) + i)] = {u[0][a], u[1][a]};
             }
         }
-        const int i = DCT ? cos_dst(x, nx) : x;
-#pragma unroll
-        for (int a = 0; a < K; ++a) buf[lpad(((a * hb + qq) << ln) + i)] = {u[0][a], u[1][a]};
     }
     __syncthreads();
     fft_run<T, 0, FR>(buf, tw, ln, K * hb, false, NoLoad<T>(), false, NoStore<T>());
@@ -1057,16 +1088,33 @@ __global__ __launch_bounds__(kFT) void k_fp_rows_inv_blk(const Inst *__restrict_
             }
         }
     } else {
-        // unit u = rows 2qq, 2qq + 1 of column c of component j (one 4-vector)
-        const int per = nc << lh;
-        for (int e = threadIdx.x; e < K * per; e += kFT) {
-            const int j = e / per, e2 = e - j * per;
-            const int c = e2 >> lh, qq = e2 & (hb - 1), q = j * hb + qq;
-            const GAS T *S = spectrum<T>(I) + (size_t)2 * j * nc * ny;
-            T a[4];
-            ld4(S + 2 * ((size_t)c * ny + y0 + 2 * qq), a);
-            buf[lpad((q << ln) + c)] = {a[0] - a[3], a[1] + a[2]};
-            if (c > 0 && 2 * c < nx) buf[lpad((q << ln) + nx - c)] = {a[0] + a[3], a[2] - a[1]};
+        // unit u = rows 2qq, 2qq + 1 of column c of component j (one 4-vector), G units of a
+        // thread in flight at once
+        const int per = nc << lh, units = K * per;
+        constexpr int G = sizeof(T) == 8 ? 4 : 8;
+        for (int u0 = 0; u0 < units; u0 += G * kFT) {
+            T a[G][4];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int e = u0 + g * kFT + threadIdx.x;
+                if (e < units) {
+                    const int j = e / per, e2 = e - j * per;
+                    const int c = e2 >> lh, qq = e2 & (hb - 1);
+                    ld4(spectrum<T>(I) + (size_t)2 * j * nc * ny + 2 * ((size_t)c * ny + y0 + 2 * qq),
+                        a[g]);
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int e = u0 + g * kFT + threadIdx.x;
+                if (e < units) {
+                    const int j = e / per, e2 = e - j * per;
+                    const int c = e2 >> lh, q = j * hb + (e2 & (hb - 1));
+                    buf[lpad((q << ln) + c)] = {a[g][0] - a[g][3], a[g][1] + a[g][2]};
+                    if (c > 0 && 2 * c < nx)
+                        buf[lpad((q << ln) + nx - c)] = {a[g][0] + a[g][3], a[g][2] - a[g][1]};
+                }
+            }
         }
     }
     __syncthreads();
@@ -1076,22 +1124,44 @@ __global__ __launch_bounds__(kFT) void k_fp_rows_inv_blk(const Inst *__restrict_
     const size_t pl = (size_t)I.n_pix;
     GAS T *z = use_out ? gp(zout) : gp(Sel<T>::z(I));
     const GAS T *tp = gp(fscale<T>(I));
-    for (int e = threadIdx.x; e < (hb << ln); e += kFT) {
-        const int qq = e >> ln, x = e & (nx - 1);
-        const int i = DCT ? cos_dst(x, nx) : x;
-        Cx<T> zh[K];
+    constexpr int NB = blk_pairs<T, K>(), KP = K * (K + 1) / 2;
+    const int items = hb << ln;
+    for (int e0 = threadIdx.x; e0 < items; e0 += NB * kFT) {
+        T tt[NB][2][KP];
 #pragma unroll
-        for (int a = 0; a < K; ++a) zh[a] = buf[lpad(((a * hb + qq) << ln) + i)];
+        for (int g = 0; g < NB; ++g) {
+            const int e = e0 + g * kFT;
+            if (e < items) {
+                const int qq = e >> ln, x = e & (nx - 1);
 #pragma unroll
-        for (int w = 0; w < 2; ++w) {
-            const uint32_t o = (uint32_t)(y0 + 2 * qq + w) * (uint32_t)nx + (uint32_t)x;
+                for (int w = 0; w < 2; ++w) {
+                    const uint32_t o = (uint32_t)(y0 + 2 * qq + w) * (uint32_t)nx + (uint32_t)x;
 #pragma unroll
-            for (int b = 0; b < K; ++b) {   // z_b = sum over a >= b of T[a][b] zhat_a
-                T sacc = (T)0;
+                    for (int t = 0; t < KP; ++t) tt[g][w][t] = bld(tp + t * pl, np, o);
+                }
+            }
+        }
 #pragma unroll
-                for (int a = b; a < K; ++a)
-                    sacc += bld(tp + tidx(a, b) * pl, np, o) * (w ? zh[a].y : zh[a].x);
-                bst(z + b * pl, np, o, sacc * scale);
+        for (int g = 0; g < NB; ++g) {
+            const int e = e0 + g * kFT;
+            if (e < items) {
+                const int qq = e >> ln, x = e & (nx - 1);
+                const int i = DCT ? cos_dst(x, nx) : x;
+                Cx<T> zh[K];
+#pragma unroll
+                for (int a = 0; a < K; ++a) zh[a] = buf[lpad(((a * hb + qq) << ln) + i)];
+#pragma unroll
+                for (int w = 0; w < 2; ++w) {
+                    const uint32_t o = (uint32_t)(y0 + 2 * qq + w) * (uint32_t)nx + (uint32_t)x;
+#pragma unroll
+                    for (int b = 0; b < K; ++b) {   // z_b = sum over a >= b of T[a][b] zhat_a
+                        T sacc = (T)0;
+#pragma unroll
+                        for (int a = b; a < K; ++a)
+                            sacc += tt[g][w][tidx(a, b)] * (w ? zh[a].y : zh[a].x);
+                        bst(z + b * pl, np, o, sacc * scale);
+                    }
+                }
             }
         }
     }
