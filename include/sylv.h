@@ -141,7 +141,8 @@ typedef struct sylv_pcg_opts {
                               (0 = 1e-5)                                                          */
     int32_t refine_max;    /* mixed: maximum number of float64 refinement steps (0 = 8)          */
     int32_t precond;       /* SYLV_PC_NONE, _JACOBI, _BLOCK, _FOURIER, _FOURIER_DIAG, _FOURIER_BLOCK */
-    int32_t check_every;   /* iterations enqueued between host convergence checks (0 = 8)        */
+    int32_t check_every;   /* iterations enqueued between host convergence checks (0 = 8, 4 with
+                              the Fourier preconditioners)                                        */
     int32_t block;         /* 1: block CG over blocks of s right-hand sides of each problem
                               (s = block_size): s x s Gram matrices in float64, alpha and beta
                               from s x s Cholesky solves, converged columns deflated;

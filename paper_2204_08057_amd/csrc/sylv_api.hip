@@ -786,7 +786,10 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
         const Inst &I = tab[i];
         HIP_TRY(launch_rhs(I.W, I.Y, I.A, I.f, I.n_pix, I.bext, I.b, k, s));
     }
-    const int chunk = opts->check_every > 0 ? opts->check_every : 8;
+    // Fourier-preconditioned runs take about ten iterations or fewer: shorter batches leave
+    // fewer early-exit iterations queued past a run's end (het_1024, block-scaled, mixed: 1.39
+    // ms with batches of 8, 1.33 ms with 4; float64 runs are insensitive)
+    const int chunk = opts->check_every > 0 ? opts->check_every : fourier ? 4 : 8;
     HostFlags *flags = nullptr;   // stays null under the fixed schedule
     if (!fixed && (rc = host_flags(flags))) return rc;
     HIP_TRY(launch_resid(set, k, 0, s));   // r0 = b - G x0, ||b||, ||r0||
