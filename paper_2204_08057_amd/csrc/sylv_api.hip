@@ -421,11 +421,13 @@ int wait_count(HostFlags *f, int slot, int &value) {
 // Iterations still to queue after those already queued (indices below `queued`): the gap to the
 // threshold shrinks about linearly in log scale, so the slowest run stops near iteration
 // iter + gap / rate, the rate taken from the last two completion reports or, after the first,
-// from the gap at the start of the run.  Returns half a batch while no rate is known (a run can
-// stop within the next few iterations: Fourier-preconditioned runs take about ten), 0 when the
-// queued iterations should already finish every run, and otherwise the estimate plus a margin,
-// never more than `chunk`.  A short estimate costs one more host round trip, an over-estimate a
-// few early-exit launches; the result of the solve does not depend on it.
+// from the gap at the start of the run.  Returns a quarter batch (at least one iteration: enough
+// queued work to cover the host's round trip) while no rate is known, 0 when the queued
+// iterations should already finish every run, and otherwise the estimate plus one, never more
+// than `chunk`.  A short estimate costs one more host round trip, an over-estimate a few
+// early-exit launches; the result of the solve does not depend on it.  (het_1024 with the
+// block-scaled Fourier preconditioner, whose runs take 6-7 iterations: half-batch blind queues
+// and a margin of two took 1.36 ms mixed, this 1.33 ms; block-Jacobi unchanged.)
 int next_batch(const Report &prev, const Report &cur, bool have_prev, bool have_cur, int queued,
                int chunk) {
     double rate = 0.0;
@@ -433,11 +435,11 @@ int next_batch(const Report &prev, const Report &cur, bool have_prev, bool have_
         rate = (prev.gap - cur.gap) / (cur.iter - prev.iter);
     else if (have_cur && cur.iter > 0 && cur.gap > 0.0 && cur.gap0 > cur.gap)
         rate = (cur.gap0 - cur.gap) / cur.iter;
-    if (!(rate > 0.0)) return std::max(2, chunk / 2);
+    if (!(rate > 0.0)) return std::max(1, chunk / 4);
     const double stop = cur.iter + cur.gap / rate;
     const double left = stop - (queued - 1);
     if (left <= 0.0) return 0;
-    const int n = (int)ceil(left * 1.1) + 2;
+    const int n = (int)ceil(left * 1.1) + 1;
     return n < chunk ? n : chunk;
 }
 
