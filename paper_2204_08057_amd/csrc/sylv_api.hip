@@ -284,8 +284,10 @@ Inst operator_inst(const sylv_problem &p, const ProbLayout &P, char *base, int p
 
 // exact = 1 also stores the exact block inverses (float64 and float32) that the stand-alone
 // sylv_precond reads; CG runs read only the bfloat16 factor.
+// prec: which precisions of the Fourier scales to make (bit 0 float32, bit 1 float64; a solve
+// makes the one its runs read, the stand-alone set-up both).
 int prepare_operator(const sylv_problem &p, const ProbLayout &P, char *base, int pc, int exact,
-                     hipStream_t s) {
+                     hipStream_t s, int prec = 3) {
     double *coef = reinterpret_cast<double *>(base + P.coef);
     HIP_TRY(launch_coef(p.kappa, p.tau, p.k, (int)p.ny, (int)p.nx, coef, s));
     HIP_TRY(launch_setup(p.W, p.A, p.f, (int)p.ny, (int)p.nx, p.boundary, coef, pc,
@@ -301,8 +303,10 @@ int prepare_operator(const sylv_problem &p, const ProbLayout &P, char *base, int
                                 reinterpret_cast<double *>(base + P.fpart),
                                 reinterpret_cast<double *>(base + P.fsym),
                                 reinterpret_cast<const double *>(base + P.M64), scale,
-                                scale ? reinterpret_cast<double *>(base + P.fsc64) : nullptr,
-                                scale ? reinterpret_cast<float *>(base + P.fsc32) : nullptr, s));
+                                scale && (prec & 2) ? reinterpret_cast<double *>(base + P.fsc64)
+                                                    : nullptr,
+                                scale && (prec & 1) ? reinterpret_cast<float *>(base + P.fsc32)
+                                                    : nullptr, s));
     }
     return SYLV_OK;
 }
@@ -780,7 +784,8 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
 
     // operator set-up and right-hand sides
     for (int g = 0; g < nprob; ++g) {
-        rc = prepare_operator(probs[g], L.prob[g], base, pc, 0, s);
+        rc = prepare_operator(probs[g], L.prob[g], base, pc, 0, s,
+                              opts->precision == SYLV_PREC_MIXED ? 1 : 2);
         if (rc) return rc;
     }
     HIP_TRY(launch_state_init(set, opts->tol, opts->max_iter, opts->stop_ref, s));

@@ -148,14 +148,14 @@ __global__ __launch_bounds__(kBlock) void k_fp_scale(const double *__restrict__ 
     const double dg = dq + M64[(size_t)jj * n_pix + p];
     const double dm = dq + fsym[j * kMaxK + j];
     const double v = sqrt(dm / dg);
-    sc64[e] = v;
-    sc32[e] = (float)v;
+    if (sc64) sc64[e] = v;   // a solve writes the one precision its runs read
+    if (sc32) sc32[e] = (float)v;
 }
 
 // Block scale of SYLV_PC_FOURIER_BLOCK: thread p of the grid forms pixel p's k x k blocks of G,
 // Bp = diag(dq) + M_p, and of Q + I (x) Mbar, B0 = diag(dq) + Mbar (dq_j the prior's diagonal as
 // in k_fp_scale), their Cholesky factors Lp and L0, and writes T = L0 Lp^-1 (lower triangular,
-// packed at tidx(a, b)) in float64 and float32.
+// packed at tidx(a, b)) in float64 and float32 (either pointer may be null).
 template <int K>
 __global__ __launch_bounds__(kBlock) void k_fp_tscale(const double *__restrict__ M64,
                                                       const double *__restrict__ fsym, int nx,
@@ -225,8 +225,8 @@ __global__ __launch_bounds__(kBlock) void k_fp_tscale(const double *__restrict__
 #pragma unroll
             for (int m = b; m <= a; ++m) v += l0[a][m] * li[m][b];
             const size_t o = (size_t)tidx(a, b) * n_pix + p;
-            sc64[o] = v;
-            sc32[o] = (float)v;
+            if (sc64) sc64[o] = v;   // a solve writes the one precision its runs read
+            if (sc32) sc32[o] = (float)v;
         }
     }
 }

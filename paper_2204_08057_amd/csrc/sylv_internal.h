@@ -222,7 +222,8 @@ size_t fp_table_bytes(int nx, int ny);
 // The Fourier region of a problem, fsym (part: fp_setup_partials doubles of scratch); face grids
 // (face = 1) take the cosine basis.  scale = 1 (SYLV_PC_FOURIER_DIAG): also the diagonal scale
 // 1 / s [k][n_pix] into sc64 / sc32; scale = 2 (SYLV_PC_FOURIER_BLOCK): the block scale T
-// [k(k+1)/2][n_pix]; both from the mixing blocks M64 (packed, as k_setup writes them).
+// [k(k+1)/2][n_pix]; both from the mixing blocks M64 (packed, as k_setup writes them); a null
+// sc64 or sc32 skips that precision.
 hipError_t launch_fp_setup(const double *W, const double *A, int f, int k, int nx, int ny,
                            int face, const double *coef, double *part, double *fsym,
                            const double *M64, int scale, double *sc64, float *sc32,
