@@ -475,6 +475,48 @@ __device__ __forceinline__ double dot_re(const Cx<T> (&a)[K], const Cx<T> (&b)[K
     return s;
 }
 
+// Run state at the start of a forward row pass (inner < 0: the stand-alone preconditioner, no
+// state).  Returns false when the workgroup has nothing to do: the run has stopped, or, for
+// upd == 2 (the CG update of iteration `it` fused into the pass), this iteration's apply stopped
+// it (its pending status is recorded) or <p, q> from the apply's partials is not a positive
+// finite number (breakdown recorded).  Otherwise alpha = rho / <p, q> for the update, recorded by
+// workgroup 0 for the next apply.
+template <typename T>
+__device__ __forceinline__ bool fp_update_prologue(const Inst &I, int inner, int upd, int it,
+                                                   int blk, T &alpha) {
+    if (inner < 0) return true;
+    DevState *st = inner ? I.st_in : I.st;
+    if (st->done) return false;
+    if (upd != 2) return true;
+    const int pend = st->pend;
+    if (pend >= 0) {   // this iteration's apply stopped the run
+        if (blk == 0 && threadIdx.x == 0) {
+            st->status = pend;
+            st->done = 1;
+            st->total_iter += it;
+        }
+        return false;
+    }
+    const double pq = fp_consume(I.partial, I.nred, SLOT_PQ,
+                                 I.pre ? 1 : (sizeof(T) == 4 ? I.ntiles32 : I.ntiles));
+    int status = -1;
+    if (!finite_d(pq)) status = SYLV_NONFINITE;
+    else if (!(pq > 0.0)) status = SYLV_BREAKDOWN;
+    const double alpha_d = st->rho[it & 1] / pq;
+    if (blk == 0 && threadIdx.x == 0) {
+        if (status >= 0) {
+            st->status = status;
+            st->done = 1;
+            st->total_iter += it;
+        } else {
+            st->alpha[it & 1] = alpha_d;
+        }
+    }
+    if (status >= 0) return false;
+    alpha = (T)alpha_d;
+    return true;
+}
+
 // Pass A: forward FFT of rows y0 .. y0 + rb of component j of r (rb even), half spectrum stored
 // transposed: S[j][c][y], c in [0, nx/2].  Two real rows travel as one complex row, u = r_2q +
 // i r_(2q+1) (the first stage reads them from global memory); their spectra separate by
@@ -501,38 +543,7 @@ __global__ __launch_bounds__(kFT) void k_fp_rows_fwd(const Inst *__restrict__ ta
     constexpr int FR = cls_fr(CLS), LN = cls_ln(CLS);
     const int blk = L - fpre[ii];
     T alpha = (T)0;
-    if (inner >= 0) {                                              // inner < 0: stand-alone
-        DevState *st = inner ? I.st_in : I.st;
-        if (st->done) return;
-        if (upd == 2) {
-            const int pend = st->pend;
-            if (pend >= 0) {   // this iteration's apply stopped the run
-                if (blk == 0 && threadIdx.x == 0) {
-                    st->status = pend;
-                    st->done = 1;
-                    st->total_iter += it;
-                }
-                return;
-            }
-            const double pq = fp_consume(I.partial, I.nred, SLOT_PQ,
-                                         I.pre ? 1 : (sizeof(T) == 4 ? I.ntiles32 : I.ntiles));
-            int status = -1;
-            if (!finite_d(pq)) status = SYLV_NONFINITE;
-            else if (!(pq > 0.0)) status = SYLV_BREAKDOWN;
-            const double alpha_d = st->rho[it & 1] / pq;
-            if (blk == 0 && threadIdx.x == 0) {
-                if (status >= 0) {
-                    st->status = status;
-                    st->done = 1;
-                    st->total_iter += it;
-                } else {
-                    st->alpha[it & 1] = alpha_d;
-                }
-            }
-            if (status >= 0) return;
-            alpha = (T)alpha_d;
-        }
-    }
+    if (!fp_update_prologue(I, inner, upd, it, blk, alpha)) return;
     const int ln = LN ? LN : I.lognx, nx = 1 << ln;
     const int ny = I.ny, rb = I.frb, nc = nx / 2 + 1, h = rb / 2;
     const int lrb = __builtin_ctz((unsigned)rb), nrb = ny >> lrb;
@@ -906,38 +917,7 @@ __global__ __launch_bounds__(kFT) void k_fp_rows_fwd_blk(const Inst *__restrict_
     constexpr int FR = cls_fr(CLS), LN = cls_ln(CLS);
     const int blk = L - fpre[ii];
     T alpha = (T)0;
-    if (inner >= 0) {                                              // inner < 0: stand-alone
-        DevState *st = inner ? I.st_in : I.st;
-        if (st->done) return;
-        if (upd == 2) {
-            const int pend = st->pend;
-            if (pend >= 0) {   // this iteration's apply stopped the run
-                if (blk == 0 && threadIdx.x == 0) {
-                    st->status = pend;
-                    st->done = 1;
-                    st->total_iter += it;
-                }
-                return;
-            }
-            const double pq = fp_consume(I.partial, I.nred, SLOT_PQ,
-                                         I.pre ? 1 : (sizeof(T) == 4 ? I.ntiles32 : I.ntiles));
-            int status = -1;
-            if (!finite_d(pq)) status = SYLV_NONFINITE;
-            else if (!(pq > 0.0)) status = SYLV_BREAKDOWN;
-            const double alpha_d = st->rho[it & 1] / pq;
-            if (blk == 0 && threadIdx.x == 0) {
-                if (status >= 0) {
-                    st->status = status;
-                    st->done = 1;
-                    st->total_iter += it;
-                } else {
-                    st->alpha[it & 1] = alpha_d;
-                }
-            }
-            if (status >= 0) return;
-            alpha = (T)alpha_d;
-        }
-    }
+    if (!fp_update_prologue(I, inner, upd, it, blk, alpha)) return;
     const int ln = LN ? LN : I.lognx, nx = 1 << ln;
     const int ny = I.ny, rb = I.frb, nc = nx / 2 + 1, hb = rb / 2;
     const int lrb = __builtin_ctz((unsigned)rb), lh = lrb - 1, y0 = blk << lrb;
