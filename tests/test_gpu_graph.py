@@ -302,17 +302,19 @@ def test_graph_face_batch(precision, bound):
         off += n
 
 
+@pytest.mark.parametrize("kind", [sy.SYLV_PC_FOURIER, sy.SYLV_PC_FOURIER_DIAG,
+                                  sy.SYLV_PC_FOURIER_BLOCK])
 @pytest.mark.parametrize("precision,bound", PRECISIONS)
-def test_graph_fourier_preconditioner(precision, bound):
-    """Fourier-preconditioned solves: the fixed schedule equals the adaptive one bitwise, and a
-    captured solve replays bitwise equal to the eager call, also after new data in place."""
+def test_graph_fourier_preconditioner(precision, bound, kind):
+    """Fourier-preconditioned solves (plain, diagonally and block scaled): the fixed schedule
+    equals the adaptive one bitwise, and a captured solve replays bitwise equal to the eager
+    call, also after new data in place."""
     p = make_problem(64, 32, 3, 6, seed=7400, noise="hetero", mask_frac=0.1)
     dp = sy.DeviceProblem.from_numpy(p)
     Yd = dev(p.Y)
-    fixed = opts_for(precision, sy.SYLV_SCHED_FIXED, precond=sy.SYLV_PC_FOURIER, max_iter=60)
-    adaptive = opts_for(precision, sy.SYLV_SCHED_ADAPTIVE, precond=sy.SYLV_PC_FOURIER,
-                        max_iter=60)
-    say("fourier fixed vs adaptive", precision)
+    fixed = opts_for(precision, sy.SYLV_SCHED_FIXED, precond=kind, max_iter=60)
+    adaptive = opts_for(precision, sy.SYLV_SCHED_ADAPTIVE, precond=kind, max_iter=60)
+    say("fourier fixed vs adaptive", precision, kind)
     Xa, sa = sy.pcg_solve(dp, Y=Yd, opts=adaptive)
     Xf, sf = sy.pcg_solve(dp, Y=Yd, opts=fixed)
     assert sa[0]["status"] == 0, sa
@@ -334,7 +336,7 @@ def test_graph_fourier_preconditioner(precision, bound):
         X.fill_(2.0e3 + rep)
         stats.zero_()
         torch.cuda.synchronize()
-        say("fourier replay", rep)
+        say("fourier replay", kind, rep)
         g.replay()
         torch.cuda.synchronize()
         assert torch.equal(X, Xe), rep
