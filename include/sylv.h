@@ -115,9 +115,7 @@ extern "C" {
                                    the k x k pixel blocks of G and of Q + I (x) Mbar): the
                                    operator it inverts has G's pixel blocks.  Same grids as
                                    SYLV_PC_FOURIER, and the row passes hold every component of
-                                   two grid rows and the stage table in LDS: k * nx <= 8192 in
-                                   float32, (1 + 33 k / 32) nx <= 10112 in float64 (else
-                                   SYLV_E_INVALID)                                               */
+                                   two grid rows: k * nx <= 8192 (else SYLV_E_INVALID)          */
 
 /* One posterior-mean system (Section 2, Section 3).  Host struct of device pointers. */
 typedef struct sylv_problem {

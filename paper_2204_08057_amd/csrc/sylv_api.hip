@@ -589,6 +589,7 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
         return SYLV_E_INVALID;
     }
     const int fourier = is_fourier(opts->precond);
+    int blk_gtw = 0;   // block-scaled row passes with global twiddles (any problem needing them)
     if (fourier) {
         if (block) { set_err("block CG takes the per-pixel preconditioners only"); return SYLV_E_INVALID; }
         const int dt = opts->precision == SYLV_PREC_MIXED ? SYLV_F32 : SYLV_F64;
@@ -599,11 +600,13 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
                 return SYLV_E_INVALID;
             }
             if (opts->precond == SYLV_PC_FOURIER_BLOCK &&
+                fp_blk_global_twiddles((int)probs[g].nx, k, dt))
+                blk_gtw = 1;
+            if (opts->precond == SYLV_PC_FOURIER_BLOCK &&
                 !fp_rows_per_block_blk((int)probs[g].nx, (int)probs[g].ny, k, dt)) {
                 set_err("problem %d: the block-scaled Fourier preconditioner's row passes hold "
-                        "every component of two grid rows and the stage table in LDS: k * nx = "
-                        "%d does not fit (%s)", g, k * (int)probs[g].nx,
-                        dt == SYLV_F64 ? "float64" : "float32");
+                        "every component of two grid rows: k * nx = %d > 8192", g,
+                        k * (int)probs[g].nx);
                 return SYLV_E_INVALID;
             }
         }
@@ -678,7 +681,8 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
                 nfb = I.nfft;
                 const int dt = mixed ? SYLV_F32 : SYLV_F64;
                 fp_lds_rows = std::max(fp_lds_rows,
-                                       fp_lds_bytes(0, I.nx, blk ? k * I.frb : I.frb, dt));
+                                       blk ? fp_lds_bytes_blk(I.nx, k, dt, blk_gtw != 0)
+                                           : fp_lds_bytes(0, I.nx, I.frb, dt));
                 fp_lds_cols = std::max(fp_lds_cols, fp_lds_bytes(1, I.ny, k, dt));
                 fp_cols_gtw |= fp_cols_global_twiddles(I.ny, k, dt) ? 1 : 0;
                 fp_rmask_x |= fp_radix_bit(I.lognx);
@@ -714,6 +718,7 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
     set.fourier = fourier;
     set.fp_scaled = opts->precond == SYLV_PC_FOURIER_DIAG ? 1 : 0;
     set.fp_block = opts->precond == SYLV_PC_FOURIER_BLOCK ? 1 : 0;
+    set.fp_blk_gtw = blk_gtw;
     set.fprefa = set.cprefix + (ninst + 1);
     set.fprefb = set.fprefa + (ninst + 1);
     set.total_fa = fpa[ninst];
@@ -1679,8 +1684,7 @@ int sylv_precond(const sylv_problem *prob, int32_t dtype, int32_t precond, const
         if (precond == SYLV_PC_FOURIER_BLOCK &&
             !fp_rows_per_block_blk((int)prob->nx, (int)prob->ny, prob->k, dtype)) {
             set_err("the block-scaled Fourier preconditioner's row passes hold every component of "
-                    "two grid rows and the stage table in LDS: k * nx = %d does not fit (%s)",
-                    prob->k * (int)prob->nx, dtype == SYLV_F64 ? "float64" : "float32");
+                    "two grid rows: k * nx = %d > 8192", prob->k * (int)prob->nx);
             return SYLV_E_INVALID;
         }
     }
@@ -1728,7 +1732,9 @@ int sylv_precond(const sylv_problem *prob, int32_t dtype, int32_t precond, const
         set.fourier = 1;
         set.fp_scaled = precond == SYLV_PC_FOURIER_DIAG ? 1 : 0;
         set.fp_block = blk ? 1 : 0;
-        set.fp_lds_rows = fp_lds_bytes(0, I.nx, blk ? k * I.frb : I.frb, dtype);
+        set.fp_blk_gtw = blk && fp_blk_global_twiddles(I.nx, k, dtype) ? 1 : 0;
+        set.fp_lds_rows = blk ? fp_lds_bytes_blk(I.nx, k, dtype, set.fp_blk_gtw != 0)
+                              : fp_lds_bytes(0, I.nx, I.frb, dtype);
         set.fp_lds_cols = fp_lds_bytes(1, I.ny, k, dtype);
         set.fp_cols_gtw = fp_cols_global_twiddles(I.ny, k, dtype) ? 1 : 0;
         set.fp_rmask_x = fp_radix_bit(I.lognx);

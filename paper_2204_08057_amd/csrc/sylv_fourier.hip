@@ -242,6 +242,14 @@ int fp_rows_per_block_blk(int nx, int ny, int k, int dtype) {
                              : rows_per_block_blk<float>(nx, ny, k);
 }
 
+bool fp_blk_global_twiddles(int nx, int k, int dtype) {
+    return dtype == SYLV_F64 ? blk_global_twiddles<double>(nx, k) : blk_global_twiddles<float>(nx, k);
+}
+
+size_t fp_lds_bytes_blk(int nx, int k, int dtype, bool gtw) {
+    return dtype == SYLV_F64 ? rows_lds_blk<double>(nx, k, !gtw) : rows_lds_blk<float>(nx, k, !gtw);
+}
+
 bool fp_supported(int ny, int nx, int k, int dtype, char *why, size_t why_len) {
     auto pow2 = [](int v) { return v >= 4 && v <= 4096 && (v & (v - 1)) == 0; };
     if (!pow2(nx) || !pow2(ny)) {

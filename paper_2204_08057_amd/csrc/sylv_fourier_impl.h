@@ -903,7 +903,7 @@ constexpr int blk_pairs() {
 // Pass A of the block-scaled variant: the update and ||r||^2 partials as k_fp_rows_fwd (upd), then
 // u = T_p r_p at every pixel of the band, the forward row transforms of all components, and the
 // half spectrum (or the cosine coefficients) of every component stored as k_fp_rows_fwd does.
-template <typename T, int K, int CLS, bool DCT>
+template <typename T, int K, int CLS, bool DCT, bool GTW>
 __global__ __launch_bounds__(kFT) void k_fp_rows_fwd_blk(const Inst *__restrict__ tab,
                                                          const int *__restrict__ fpre, int ninst,
                                                          int nb, int inner,
@@ -921,10 +921,15 @@ __global__ __launch_bounds__(kFT) void k_fp_rows_fwd_blk(const Inst *__restrict_
     const int ln = LN ? LN : I.lognx, nx = 1 << ln;
     const int ny = I.ny, rb = I.frb, nc = nx / 2 + 1, hb = rb / 2;
     const int lrb = __builtin_ctz((unsigned)rb), lh = lrb - 1, y0 = blk << lrb;
-    Cx<T> *tw = reinterpret_cast<Cx<T> *>(fp_lds);
-    Cx<T> *buf = tw + nx;
+    // GTW: the stage twiddles read from the set-up table in global memory (float64 bands whose
+    // k complex rows and table do not both fit in LDS)
+    Cx<T> *buf = reinterpret_cast<Cx<T> *>(fp_lds) + (GTW ? 0 : nx);
     const FpTabs tb = fp_tabs(nx, ny);
-    load_table<T>(tw, stage_table<T>(I.fsym, tb, true), nx);
+    const Cx<T> *tw = stage_table<T>(I.fsym, tb, true);
+    if (!GTW) {
+        load_table<T>(reinterpret_cast<Cx<T> *>(fp_lds), tw, nx);
+        tw = reinterpret_cast<const Cx<T> *>(fp_lds);
+    }
     const uint32_t np = (uint32_t)I.n_pix;
     const size_t pl = (size_t)I.n_pix;
     GAS T *r = use_in ? gp(const_cast<T *>(rin)) : Sel<T>::r(I);
@@ -1026,7 +1031,7 @@ __global__ __launch_bounds__(kFT) void k_fp_rows_fwd_blk(const Inst *__restrict_
 // Pass C of the block-scaled variant: the rows of every component rebuilt from the half spectrum
 // (or the cosine coefficients) as k_fp_rows_inv does, the inverse row transforms, then
 // z_p = T_p^T zhat_p / (nx ny) at every pixel of the band.
-template <typename T, int K, int CLS, bool DCT>
+template <typename T, int K, int CLS, bool DCT, bool GTW>
 __global__ __launch_bounds__(kFT) void k_fp_rows_inv_blk(const Inst *__restrict__ tab,
                                                          const int *__restrict__ fpre, int ninst,
                                                          int nb, int inner, T *__restrict__ zout,
@@ -1042,10 +1047,15 @@ __global__ __launch_bounds__(kFT) void k_fp_rows_inv_blk(const Inst *__restrict_
     const int ln = LN ? LN : I.lognx, nx = 1 << ln;
     const int ny = I.ny, rb = I.frb, nc = nx / 2 + 1, hb = rb / 2;
     const int lrb = __builtin_ctz((unsigned)rb), lh = lrb - 1, y0 = blk << lrb;
-    Cx<T> *tw = reinterpret_cast<Cx<T> *>(fp_lds);
-    Cx<T> *buf = tw + nx;
+    // GTW: the stage twiddles read from the set-up table in global memory (float64 bands whose
+    // k complex rows and table do not both fit in LDS)
+    Cx<T> *buf = reinterpret_cast<Cx<T> *>(fp_lds) + (GTW ? 0 : nx);
     const FpTabs tb = fp_tabs(nx, ny);
-    load_table<T>(tw, stage_table<T>(I.fsym, tb, true), nx);
+    const Cx<T> *tw = stage_table<T>(I.fsym, tb, true);
+    if (!GTW) {
+        load_table<T>(reinterpret_cast<Cx<T> *>(fp_lds), tw, nx);
+        tw = reinterpret_cast<const Cx<T> *>(fp_lds);
+    }
     if (DCT) {
         const Cx<T> *ct = cos_table<T>(I.fsym, tb, true);
         const int per = (nx / 2 + 1) << lh;
@@ -1165,12 +1175,22 @@ constexpr size_t kLdsMargin = 1024;
 // so that a pass has twice the workgroups of four-row bands (two per CU at 1024^2, k = 3) whose
 // loads and transforms overlap; measured faster than four-row bands despite 16-byte runs in the
 // transposed spectrum (float32 1024^2, k = 3: forward 21.5 against 23.5 us, inverse 14.4 against
-// 15.6 us).  0 when the k complex rows and the stage table do not fit in LDS or kFftCap.
+// 15.6 us).  0 when the k complex rows exceed kFftCap or, without the stage table, the LDS.
+template <typename T>
+size_t rows_lds_blk(int nx, int k, bool table) {
+    return sizeof(Cx<T>) * ((table ? (size_t)nx : 0) + lds_entries(k * nx));
+}
 template <typename T>
 int rows_per_block_blk(int nx, int ny, int k) {
     (void)ny;
-    const bool fits = k * nx <= kFftCap && rows_lds<T>(nx, 2 * k) <= kMaxLds - kLdsMargin;
+    const bool fits = k * nx <= kFftCap && rows_lds_blk<T>(nx, k, false) <= kMaxLds - kLdsMargin;
     return fits ? 2 : 0;
+}
+// Whether the block-scaled row passes read their stage twiddles from global memory (the band and
+// the table do not both fit in LDS; float64 only: 2048 columns at k = 4, 4096 at k = 2).
+template <typename T>
+bool blk_global_twiddles(int nx, int k) {
+    return rows_lds_blk<T>(nx, k, true) > kMaxLds - kLdsMargin;
 }
 
 template <typename T>
@@ -1213,12 +1233,25 @@ hipError_t fp_apply_impl(const InstSet &set, int k, int inner, const void *rin, 
         constexpr int K = decltype(tag)::value;
         hipError_t e = for_each_class(set.fp_rmask_x, [&](auto fr) -> hipError_t {
             constexpr int FR = decltype(fr)::value;   // the class
-            if (set.fp_block)
-                hipLaunchKernelGGL((k_fp_rows_fwd_blk<T, K, FR, DCT>), dim3(set.total_fa),
-                                   dim3(kFT), lr, s, set.table, set.fprefa, set.ninst,
-                                   set.total_fa, mixed, reinterpret_cast<const T *>(rin),
-                                   rin ? 1 : 0, inner >= 0 ? upd : 0, it);
-            else if (set.fp_scaled)
+            if (set.fp_block) {
+                if (sizeof(T) == 8 && set.fp_blk_gtw) {
+                    // only float64 bands of k nx = 8192 with nx = 2048 (k = 4) or 4096 (k = 2)
+                    if constexpr (sizeof(T) == 8 && ((FR == 111 && K == 4) || (FR == 16 && K == 2)))
+                        hipLaunchKernelGGL((k_fp_rows_fwd_blk<T, K, FR, DCT, true>),
+                                           dim3(set.total_fa), dim3(kFT), lr, s, set.table,
+                                           set.fprefa, set.ninst, set.total_fa, mixed,
+                                           reinterpret_cast<const T *>(rin), rin ? 1 : 0,
+                                           inner >= 0 ? upd : 0, it);
+                    else
+                        return hipErrorInvalidValue;
+                } else {
+                    hipLaunchKernelGGL((k_fp_rows_fwd_blk<T, K, FR, DCT, false>),
+                                       dim3(set.total_fa), dim3(kFT), lr, s, set.table,
+                                       set.fprefa, set.ninst, set.total_fa, mixed,
+                                       reinterpret_cast<const T *>(rin), rin ? 1 : 0,
+                                       inner >= 0 ? upd : 0, it);
+                }
+            } else if (set.fp_scaled)
                 hipLaunchKernelGGL((k_fp_rows_fwd<T, FR, DCT, true>), dim3(set.total_fa),
                                    dim3(kFT), lr, s, set.table, set.fprefa, set.ninst,
                                    set.total_fa, mixed, reinterpret_cast<const T *>(rin),
@@ -1251,12 +1284,22 @@ hipError_t fp_apply_impl(const InstSet &set, int k, int inner, const void *rin, 
         if (e != hipSuccess) return e;
         return for_each_class(set.fp_rmask_x, [&](auto fr) -> hipError_t {
             constexpr int FR = decltype(fr)::value;   // the class
-            if (set.fp_block)
-                hipLaunchKernelGGL((k_fp_rows_inv_blk<T, K, FR, DCT>), dim3(set.total_fa),
-                                   dim3(kFT), lr, s, set.table, set.fprefa, set.ninst,
-                                   set.total_fa, mixed, reinterpret_cast<T *>(zout),
-                                   zout ? 1 : 0);
-            else if (set.fp_scaled)
+            if (set.fp_block) {
+                if (sizeof(T) == 8 && set.fp_blk_gtw) {
+                    if constexpr (sizeof(T) == 8 && ((FR == 111 && K == 4) || (FR == 16 && K == 2)))
+                        hipLaunchKernelGGL((k_fp_rows_inv_blk<T, K, FR, DCT, true>),
+                                           dim3(set.total_fa), dim3(kFT), lr, s, set.table,
+                                           set.fprefa, set.ninst, set.total_fa, mixed,
+                                           reinterpret_cast<T *>(zout), zout ? 1 : 0);
+                    else
+                        return hipErrorInvalidValue;
+                } else {
+                    hipLaunchKernelGGL((k_fp_rows_inv_blk<T, K, FR, DCT, false>),
+                                       dim3(set.total_fa), dim3(kFT), lr, s, set.table,
+                                       set.fprefa, set.ninst, set.total_fa, mixed,
+                                       reinterpret_cast<T *>(zout), zout ? 1 : 0);
+                }
+            } else if (set.fp_scaled)
                 hipLaunchKernelGGL((k_fp_rows_inv<T, FR, DCT, true>), dim3(set.total_fa),
                                    dim3(kFT), lr, s, set.table, set.fprefa, set.ninst,
                                    set.total_fa, mixed, reinterpret_cast<T *>(zout),

@@ -144,6 +144,7 @@ struct InstSet {
     int fp_rmask_x, fp_rmask_y;   // final FFT radices present (fp_radix_bit) along x and y
     int fp_scaled;        // SYLV_PC_FOURIER_DIAG: the row passes apply the diagonal scale
     int fp_block;         // SYLV_PC_FOURIER_BLOCK: the block-scaled row passes (all components)
+    int fp_blk_gtw;       // ... reading their twiddles from global memory (float64, wide bands)
 };
 
 inline int packed_size(int k) { return k * (k + 1) / 2; }
@@ -230,6 +231,9 @@ hipError_t launch_fp_setup(const double *W, const double *A, int f, int k, int n
                            hipStream_t s);
 // Grid rows per workgroup of the block-scaled row passes (0: k nx too large for them).
 int fp_rows_per_block_blk(int nx, int ny, int k, int dtype);
+// Whether those passes read their stage twiddles from global memory, and their dynamic LDS bytes.
+bool fp_blk_global_twiddles(int nx, int k, int dtype);
+size_t fp_lds_bytes_blk(int nx, int k, int dtype, bool gtw);
 // z = Fourier preconditioner of r for every instance of the set, in float32 (f32) or float64;
 // inner = 1: the float32 inner runs of the mixed path, 0: the float64 runs, -1: the stand-alone
 // preconditioner (one instance without run state: r read from rin, z written to zout).  upd
