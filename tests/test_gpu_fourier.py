@@ -370,9 +370,10 @@ BLOCK_SHAPES = [("periodic", s) for s in [(8, 16, 3, 5), (32, 64, 4, 9), (128, 3
                                           (2048, 16, 4, 9), (16, 1024, 8, 9), (8, 4096, 1, 3),
                                           (4096, 4, 2, 3), (64, 64, 1, 3),
                                           # float64 bands whose table goes to global memory
-                                          (16, 2048, 4, 9), (8, 4096, 2, 3)]] + \
+                                          (16, 2048, 4, 9), (8, 4096, 2, 3), (16, 1024, 4, 9),
+                                          (8, 2048, 2, 3)]] + \
                [("face", s) for s in [(8, 16, 3, 5), (64, 32, 4, 9), (1024, 8, 8, 9),
-                                      (16, 2048, 4, 9)]]
+                                      (16, 2048, 4, 9), (16, 1024, 4, 9)]]
 
 
 @pytest.mark.parametrize("boundary,shape", BLOCK_SHAPES)
