@@ -878,6 +878,14 @@ def main():
                           args.apply_reps)
     b_fp = int(6 * k * 4 * n_pix * (prob.nx // 2 + 1) / (prob.nx // 2))
     log(f"Fourier preconditioner f32 {t_fp * 1e3:.2f} us {b_fp / t_fp / 1e6:.0f} GB/s")
+    # the block-scaled one (the headline's): the row passes also read the k(k+1)/2 planes of T
+    ws_fb = sy.binding.prepare(dp, sy.SYLV_PC_FOURIER_BLOCK)
+    t_fb = timed_launches(torch, sy.precond_launcher(dp, X32, Zf, sy.SYLV_PC_FOURIER_BLOCK,
+                                                     ws_fb), args.apply_reps)
+    b_fb = b_fp + 2 * (k * (k + 1) // 2) * 4 * n_pix
+    log(f"block-scaled Fourier preconditioner f32 {t_fb * 1e3:.2f} us "
+        f"{b_fb / t_fb / 1e6:.0f} GB/s")
+    del ws_fb
 
     # the dominant loop: one CG iteration, timed live for both precisions and preconditioners
     cg_it = {}
@@ -942,6 +950,11 @@ def main():
                                 "gbs": round(b_fp / t_fp / 1e6, 1),
                                 "note": "one stand-alone call (three FFT passes and the call's "
                                         "two table uploads), HIP events over back-to-back calls"},
+        "fourier_block_precond_f32": {"us": round(t_fb * 1e3, 3), "algorithmic_bytes": b_fb,
+                                      "gbs": round(b_fb / t_fb / 1e6, 1),
+                                      "frac": round(b_fb / t_fb / 1e6 / PEAK_HBM_GBS, 4),
+                                      "note": "the headline's preconditioner, one stand-alone "
+                                              "call as above; its row passes also read T"},
         "roofline_fourier": {"bound": "hbm", "peak": PEAK_HBM_GBS, "unit": "GB/s",
                              "passes": fourier_passes_from_counters(),
                              "source": "median active launch of rocprofv3 --kernel-trace and "
