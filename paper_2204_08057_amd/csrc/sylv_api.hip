@@ -174,7 +174,10 @@ bool make_layout(const sylv_problem *probs, int nprob, int nrhs, bool solve, Lay
         P.fsym = off; off = align_up(off + fp_table_bytes((int)probs[g].nx, (int)probs[g].ny));
         P.fpart = off; off = align_up(off + sizeof(double) * fp_setup_partials((int)n, probs[g].f));
         P.fsc64 = P.fsc32 = 0;
-        if (fp_grid(probs[g])) {
+        // a solve lays out its operator for itself: the scale planes only for the scaled kinds;
+        // the stand-alone layout (one problem, any later sylv_precond kind) always on these grids
+        const bool scaled = pc == SYLV_PC_FOURIER_DIAG || pc == SYLV_PC_FOURIER_BLOCK;
+        if (fp_grid(probs[g]) && (!solve || scaled)) {
             const size_t vk = (size_t)packed_size(probs[g].k) * n;   // block: k(k+1)/2 planes
             P.fsc64 = off; off = align_up(off + sizeof(double) * vk);
             P.fsc32 = off; off = align_up(off + sizeof(float) * vk);
