@@ -592,7 +592,8 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
         return SYLV_E_INVALID;
     }
     const int fourier = is_fourier(opts->precond);
-    int blk_gtw = 0;   // block-scaled row passes with global twiddles (any problem needing them)
+    int blk_gtw = 0;   // length classes (fp_radix_bit) whose block-scaled row passes read global
+                       // twiddles
     if (fourier) {
         if (block) { set_err("block CG takes the per-pixel preconditioners only"); return SYLV_E_INVALID; }
         const int dt = opts->precision == SYLV_PREC_MIXED ? SYLV_F32 : SYLV_F64;
@@ -602,9 +603,6 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
                 set_err("problem %d: %s", g, why);
                 return SYLV_E_INVALID;
             }
-            if (opts->precond == SYLV_PC_FOURIER_BLOCK &&
-                fp_blk_global_twiddles((int)probs[g].nx, k, dt))
-                blk_gtw = 1;
             if (opts->precond == SYLV_PC_FOURIER_BLOCK &&
                 !fp_rows_per_block_blk((int)probs[g].nx, (int)probs[g].ny, k, dt)) {
                 set_err("problem %d: the block-scaled Fourier preconditioner's row passes hold "
@@ -683,11 +681,15 @@ int solve_impl(const sylv_problem *probs, int nprob, int nrhs, const double *Y,
                 I.nrr = mixed ? nfa : I.nchunks;   // the producer of ||r||^2 (see fourier_apply)
                 nfb = I.nfft;
                 const int dt = mixed ? SYLV_F32 : SYLV_F64;
-                fp_lds_rows = std::max(fp_lds_rows,
-                                       blk ? fp_lds_bytes_blk(I.nx, k, dt, blk_gtw != 0)
-                                           : fp_lds_bytes(0, I.nx, I.frb, dt));
+                // global twiddles are chosen per length class: a class with any instance that
+                // needs them reads them so for all its instances (right for every length of the
+                // class; the LDS is sized for the largest need)
+                const bool rg = blk && fp_blk_global_twiddles(I.nx, k, dt);
+                if (rg) blk_gtw |= fp_radix_bit(I.lognx);
+                fp_lds_rows = std::max(fp_lds_rows, blk ? fp_lds_bytes_blk(I.nx, k, dt, rg)
+                                                        : fp_lds_bytes(0, I.nx, I.frb, dt));
                 fp_lds_cols = std::max(fp_lds_cols, fp_lds_bytes(1, I.ny, k, dt));
-                fp_cols_gtw |= fp_cols_global_twiddles(I.ny, k, dt) ? 1 : 0;
+                if (fp_cols_global_twiddles(I.ny, k, dt)) fp_cols_gtw |= fp_radix_bit(I.logny);
                 fp_rmask_x |= fp_radix_bit(I.lognx);
                 fp_rmask_y |= fp_radix_bit(I.logny);
             }
@@ -1735,11 +1737,12 @@ int sylv_precond(const sylv_problem *prob, int32_t dtype, int32_t precond, const
         set.fourier = 1;
         set.fp_scaled = precond == SYLV_PC_FOURIER_DIAG ? 1 : 0;
         set.fp_block = blk ? 1 : 0;
-        set.fp_blk_gtw = blk && fp_blk_global_twiddles(I.nx, k, dtype) ? 1 : 0;
-        set.fp_lds_rows = blk ? fp_lds_bytes_blk(I.nx, k, dtype, set.fp_blk_gtw != 0)
+        const bool rg = blk && fp_blk_global_twiddles(I.nx, k, dtype);
+        set.fp_blk_gtw = rg ? fp_radix_bit(I.lognx) : 0;
+        set.fp_lds_rows = blk ? fp_lds_bytes_blk(I.nx, k, dtype, rg)
                               : fp_lds_bytes(0, I.nx, I.frb, dtype);
         set.fp_lds_cols = fp_lds_bytes(1, I.ny, k, dtype);
-        set.fp_cols_gtw = fp_cols_global_twiddles(I.ny, k, dtype) ? 1 : 0;
+        set.fp_cols_gtw = fp_cols_global_twiddles(I.ny, k, dtype) ? fp_radix_bit(I.logny) : 0;
         set.fp_rmask_x = fp_radix_bit(I.lognx);
         set.fp_rmask_y = fp_radix_bit(I.logny);
         set.bc = prob->boundary;

@@ -334,9 +334,6 @@ hipError_t launch_fp_apply(const InstSet &set, int k, int f32, int inner, const 
                 : fp_apply_f64_periodic(set, k, inner, rin, zout, upd, it, s);
 }
 
-int fp_radix_bit(int logn) {
-    const int c = fft_class(logn);
-    return c >= 100 ? 16 << (c - 110) : c / 2;
-}
+int fp_radix_bit(int logn) { return cls_bit(fft_class(logn)); }
 
 }  // namespace sylv

@@ -147,6 +147,8 @@ __host__ __device__ constexpr int fft_class(int logn) {
 }
 __host__ __device__ constexpr int cls_fr(int cls) { return cls >= 100 ? fft_last_radix(cls - 100) : cls; }
 __host__ __device__ constexpr int cls_ln(int cls) { return cls >= 100 ? cls - 100 : 0; }
+// The bit of a class in the set masks (the same as fp_radix_bit of its lengths).
+__host__ __device__ constexpr int cls_bit(int cls) { return cls >= 100 ? 16 << (cls - 110) : cls / 2; }
 
 // ---- DFTs of R = 2, 4, 8, 16 points in registers, natural order in and out ----------------
 // Forward: X[k] = sum_j x[j] exp(-2 pi i j k / R); INV = 1 uses exp(+2 pi i j k / R).
@@ -1234,7 +1236,7 @@ hipError_t fp_apply_impl(const InstSet &set, int k, int inner, const void *rin, 
         hipError_t e = for_each_class(set.fp_rmask_x, [&](auto fr) -> hipError_t {
             constexpr int FR = decltype(fr)::value;   // the class
             if (set.fp_block) {
-                if (sizeof(T) == 8 && set.fp_blk_gtw) {
+                if (sizeof(T) == 8 && (set.fp_blk_gtw & cls_bit(FR))) {
                     // only float64 bands of k nx = 8192 with nx = 2048 (k = 4) or 4096 (k = 2)
                     if constexpr (sizeof(T) == 8 && ((FR == 111 && K == 4) || (FR == 16 && K == 2)))
                         hipLaunchKernelGGL((k_fp_rows_fwd_blk<T, K, FR, DCT, true>),
@@ -1267,7 +1269,7 @@ hipError_t fp_apply_impl(const InstSet &set, int k, int inner, const void *rin, 
         e = for_each_class(set.fp_rmask_y, [&](auto fr) -> hipError_t {
             constexpr int FR = decltype(fr)::value;   // the class
             const dim3 g(set.total_fb), b(kFT);
-            if (sizeof(T) == 8 && set.fp_cols_gtw) {
+            if (sizeof(T) == 8 && (set.fp_cols_gtw & cls_bit(FR))) {
                 // only float64 columns of k ny = 8192 with ny = 2048 (k <= 4) or 4096 (k <= 2)
                 // exceed the LDS with their table (fp_cols_global_twiddles)
                 if constexpr (sizeof(T) == 8 && ((FR == 111 && K <= 4) || (FR == 16 && K <= 2)))
@@ -1285,7 +1287,7 @@ hipError_t fp_apply_impl(const InstSet &set, int k, int inner, const void *rin, 
         return for_each_class(set.fp_rmask_x, [&](auto fr) -> hipError_t {
             constexpr int FR = decltype(fr)::value;   // the class
             if (set.fp_block) {
-                if (sizeof(T) == 8 && set.fp_blk_gtw) {
+                if (sizeof(T) == 8 && (set.fp_blk_gtw & cls_bit(FR))) {
                     if constexpr (sizeof(T) == 8 && ((FR == 111 && K == 4) || (FR == 16 && K == 2)))
                         hipLaunchKernelGGL((k_fp_rows_inv_blk<T, K, FR, DCT, true>),
                                            dim3(set.total_fa), dim3(kFT), lr, s, set.table,

@@ -140,11 +140,13 @@ struct InstSet {
     int fourier;          // pc == SYLV_PC_FOURIER
     size_t fp_lds_rows, fp_lds_cols;  // dynamic LDS of the row and column passes (largest over
                                       // the set's instances)
-    int fp_cols_gtw;      // the column pass reads its twiddles from global memory
+    int fp_cols_gtw;      // length classes (fp_radix_bit of ny) whose column pass reads its
+                          // twiddles from global memory
     int fp_rmask_x, fp_rmask_y;   // final FFT radices present (fp_radix_bit) along x and y
     int fp_scaled;        // SYLV_PC_FOURIER_DIAG: the row passes apply the diagonal scale
     int fp_block;         // SYLV_PC_FOURIER_BLOCK: the block-scaled row passes (all components)
-    int fp_blk_gtw;       // ... reading their twiddles from global memory (float64, wide bands)
+    int fp_blk_gtw;       // ... of the length classes (fp_radix_bit of nx) reading their
+                          // twiddles from global memory (float64, wide bands)
 };
 
 inline int packed_size(int k) { return k * (k + 1) / 2; }

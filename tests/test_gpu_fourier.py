@@ -495,3 +495,25 @@ def test_block_het_1024_whole_solution_vs_oracle(precision, tol, bound):
     assert st[0]["status"] == 0, st
     say("  iterations", st[0]["iters"], "outer", st[0]["outer"])
     assert rel(host(X).reshape(p.k, p.n_pix), ref) <= bound
+
+
+def test_float64_batch_mixing_global_and_lds_twiddles():
+    """A float64 batch whose grids need the stage twiddles from global memory in some length
+    classes and not in others (rows of 2048 and of 1024 at k = 4 with the block-scaled row
+    passes, a column of 2048 at k = 4): every instance equals its solve alone, bitwise."""
+    probs = [make_problem(16, 2048, 4, 5, seed=6500, noise="hetero"),
+             make_problem(16, 1024, 4, 5, seed=6501, noise="hetero"),
+             make_problem(2048, 16, 4, 5, seed=6502, noise="hetero")]
+    dps = [sy.DeviceProblem.from_numpy(q) for q in probs]
+    for kind in (sy.SYLV_PC_FOURIER_BLOCK, sy.SYLV_PC_FOURIER):
+        o = sy.SolveOptions(tol=1e-10, precision=sy.SYLV_PREC_F64, precond=kind)
+        say("float64 mixed-twiddle batch", kind)
+        X, st = sy.pcg_solve(dps, Y=torch.cat([dev(q.Y.ravel()) for q in probs]), opts=o)
+        assert all(s["status"] == 0 for s in st), st
+        off = 0
+        for q, dq in zip(probs, dps):
+            Xq, sq = sy.pcg_solve(dq, Y=dev(q.Y), opts=o)
+            n = q.k * q.n_pix
+            assert torch.equal(X[off:off + n], Xq.reshape(-1)), (kind, q.ny, q.nx)
+            assert sq[0]["iters"] == [s for s in st][probs.index(q)]["iters"]
+            off += n
